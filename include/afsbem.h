@@ -1,0 +1,169 @@
+/*
+ * afsbem -- per-frequency Laplace-domain elastodynamic boundary-element solve
+ * on AMD Instinct MI355X (gfx950), and the frequency-domain drivers on top.
+ *
+ * The operation (Xiao, Rong, Ye, Zhang, "An efficient adaptive frequency
+ * sampling scheme for large-scale transient boundary element analysis",
+ * Section 2.1, Eq. 1 and Eq. 2): for a complex frequency s, the boundary
+ * integral equation
+ *     c_ij u_j(x) + PV int_G T_ij(x,y;s) u_j(y) dG = int_G U_ij(x,y;s) t_j(y) dG
+ * is discretised on a closed surface of flat triangles with constant u and t
+ * per element, collocated at element centroids (c = 1/2 I there), giving the
+ * N x N complex system A(s) a(s) = b(s), N = 3 * n_tri.  Per element either the
+ * traction is prescribed (kind 0: the displacement is unknown) or the
+ * displacement is prescribed (kind 1: the traction is unknown).
+ * The system is solved by right block-Jacobi-preconditioned GMRES (Section 4,
+ * "GMRES in conjunction with the block diagonal preconditioner").
+ *
+ * Conventions
+ *  - Status codes: 0 success, < 0 error (AFSBEM_E*).  On error, outputs are left
+ *    untouched and afsbem_last_error() returns a thread-local message.
+ *  - Complex numbers are interleaved (re, im) doubles unless stated otherwise.
+ *  - Element vectors are [n_tri][3] (x, y, z components), frequency-major for
+ *    several frequencies: [n_s][n_tri][3].
+ *  - Matrices on the device are column-major: entry (row, col) at col*N + row.
+ *  - Handles are opaque and owned by the library; free them with *_destroy.
+ *    Host arrays passed in are copied; the library never frees caller memory.
+ *  - *_device entry points take device pointers allocated by the caller (for
+ *    instance PyTorch tensors) and a hipStream_t passed as void*; work is
+ *    enqueued on that stream and results are valid once it has completed.
+ *  - One problem handle must not be used from two threads at once.
+ */
+#ifndef AFSBEM_H
+#define AFSBEM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    AFSBEM_OK = 0,
+    AFSBEM_EINVAL = -1,     /* invalid argument (size, index, null pointer, degenerate triangle) */
+    AFSBEM_ENOMEM = -2,     /* device or host allocation failed */
+    AFSBEM_EDEVICE = -3,    /* HIP runtime error */
+    AFSBEM_ENOCONV = -4,    /* outputs written, but the final FP64 residual exceeds the tolerance */
+    AFSBEM_EBREAKDOWN = -5, /* Krylov breakdown that restarting did not cure */
+    AFSBEM_ENAN = -6        /* NaN or Inf met in the residual */
+};
+
+typedef struct afsbem_mesh afsbem_mesh;
+typedef struct afsbem_problem afsbem_problem;
+
+/* Thread-local text of the last error; never NULL. */
+const char *afsbem_last_error(void);
+int afsbem_version(int *major, int *minor);
+
+/* ------------------------------------------------------------------ mesh ---
+ * xyz: [n_vert][3] doubles; tri: [n_tri][3] vertex indices.  The triangle
+ * normal (v1-v0)x(v2-v0) must point out of the elastic domain (into cavities,
+ * outward on the faces of a bounded body).  Rejects indices out of range and
+ * zero-area triangles (AFSBEM_EINVAL).  Arrays are copied. */
+int afsbem_mesh_create(const double *xyz, int64_t n_vert, const int32_t *tri, int64_t n_tri,
+                       afsbem_mesh **out);
+int afsbem_mesh_destroy(afsbem_mesh *mesh);
+
+/* -------------------------------------------------------------- problem ---
+ * Isotropic material (Section 2.1): shear modulus mu, Poisson ratio nu in
+ * (-1, 0.5), density rho; c_s = sqrt(mu/rho), c_p = sqrt((lambda+2mu)/rho). */
+typedef struct {
+    double mu, nu, rho;
+} afsbem_material;
+
+/* Quadrature policy (the paper's Section 2.1 names regular Gauss rules,
+ * recursive subdivision for nearly singular integrals and a dedicated scheme
+ * for singular ones; this library uses):
+ *   far_ratio   -- the 7-point degree-5 rule when |x - c_n| >= far_ratio * h_n
+ *                  (h_n = longest edge), else 4-way midpoint subdivision with
+ *                  the same test on every sub-triangle (default 2.0)
+ *   max_subdiv  -- subdivision depth limit (default 8)
+ *   self_n_theta, self_n_rho -- Gauss-Legendre orders of the polar rule on each
+ *                  of the three sub-triangles of the self element (16, 16). */
+typedef struct {
+    double far_ratio;
+    int32_t max_subdiv;
+    int32_t self_n_theta, self_n_rho;
+} afsbem_quad_policy;
+
+/* bc_kind: [n_tri], 0 = traction prescribed, 1 = displacement prescribed.
+ * policy may be NULL (defaults).  Builds the s-independent quadrature plan
+ * (element geometry, near-pair subdivision leaves, self-element polar tables
+ * and static principal values) and uploads it to the current HIP device. */
+int afsbem_problem_create(const afsbem_mesh *mesh, const afsbem_material *mat, const int8_t *bc_kind,
+                          const afsbem_quad_policy *policy, afsbem_problem **out);
+int afsbem_problem_destroy(afsbem_problem *p);
+
+/* Sizes of the plan: n_tri, number of near pairs, number of subdivision leaves,
+ * number of self quadrature nodes per element.  Any pointer may be NULL. */
+int afsbem_problem_info(const afsbem_problem *p, int64_t *n_tri, int64_t *n_near_pairs,
+                        int64_t *n_leaves, int64_t *self_nodes_per_element);
+
+/* ------------------------------------------------ step-level entry points ---
+ * Matrix storage formats on the device (N = 3 n_tri, column-major):
+ *   AFSBEM_FMT_C128  -- one plane of complex<double>, N*N*16 bytes;
+ *   AFSBEM_FMT_SPLIT -- two planes of complex<float>: hi = fp32(A), lo =
+ *                       fp32(A - hi); hi+lo carries A to ~2^-48 relative.
+ *                       N*N*8 bytes each. */
+enum { AFSBEM_FMT_C128 = 0, AFSBEM_FMT_SPLIT = 1 };
+
+/* Assembles A(s) and b(s) of Eq. 2 at one s on the device.
+ * d_bc_val: [n_tri][3] complex<double>, the prescribed traction or displacement
+ * at this s.  d_A (and d_A_lo for SPLIT) must hold N*N entries; d_b N complex
+ * doubles.  d_precond (nullable): [n_tri][3][3] complex<double> receives the
+ * inverses of the 3x3 diagonal blocks (row-major per block). */
+int afsbem_assemble_device(afsbem_problem *p, double s_re, double s_im, const void *d_bc_val,
+                           int format, void *d_A, void *d_A_lo, void *d_b, void *d_precond,
+                           void *hip_stream);
+
+/* y = A x on the device.  precision 0: FP64 product (C128, or hi+lo of SPLIT);
+ * precision 1: FP32 product of the hi plane with FP32 accumulation (SPLIT only).
+ * x and y are N complex doubles. */
+int afsbem_matvec_device(afsbem_problem *p, int format, int precision, const void *d_A,
+                         const void *d_A_lo, const void *d_x, void *d_y, void *hip_stream);
+
+/* ---------------------------------------------------------------- solve --- */
+enum { AFSBEM_PREC_FP64 = 0, AFSBEM_PREC_MIXED = 1 };
+enum { AFSBEM_WARM_NONE = 0, AFSBEM_WARM_PREV = 1, AFSBEM_WARM_USER = 2, AFSBEM_WARM_LEARNED = 3 };
+
+typedef struct {
+    double tol;          /* target FP64 true relative residual ||b - A x|| / ||b|| (1e-6) */
+    int32_t restart;     /* GMRES restart length m (50) */
+    int32_t max_iter;    /* cap on matrix-vector products per frequency (1000) */
+    int32_t precision;   /* AFSBEM_PREC_FP64 or AFSBEM_PREC_MIXED */
+    int32_t warm_start;  /* AFSBEM_WARM_* */
+    double inner_tol;    /* mixed: relative reduction asked of each FP32 inner solve (1e-4) */
+    int32_t batch;       /* frequencies resident at once; 0 = as many as fit */
+    uint32_t fault_inject; /* test hook bits, 0 in production */
+} afsbem_solve_opts;
+
+typedef struct {
+    int32_t iters;        /* matrix-vector products in the Krylov solver */
+    int32_t refine_steps; /* FP64 residual evaluations (mixed) */
+    int32_t fallback;     /* 0 none; 1 warm start rejected; 2 mixed fell back to FP64 */
+    int32_t status;       /* per-frequency status code */
+    double rel_res_fp64;  /* final ||b - A x|| / ||b|| with the FP64 operator */
+    double t_assemble_ms, t_solve_ms;
+    double bytes;         /* algorithmic matrix bytes streamed */
+} afsbem_solve_stats;
+
+/* Fills opts with the defaults listed above. */
+int afsbem_solve_opts_default(afsbem_solve_opts *opts);
+
+/* Solves A(s_k) a_k = b_k for n_s frequencies s (host array, 2*n_s doubles).
+ * d_bc_val: [n_s][n_tri][3] complex<double> prescribed values at each s.
+ * d_x0: nullable [n_s][N] complex<double> initial guesses (used with
+ *       AFSBEM_WARM_USER).
+ * Outputs (each nullable): d_a_out [n_s][N] solution vector, d_u_out and
+ * d_t_out [n_s][n_tri][3] displacement and traction per element.
+ * stats: nullable host array of n_s entries.
+ * Returns AFSBEM_ENOCONV if any frequency missed the tolerance (outputs are
+ * still written with the best iterate). */
+int afsbem_solve_device(afsbem_problem *p, int32_t n_s, const double *s, const void *d_bc_val,
+                        const void *d_x0, void *d_a_out, void *d_u_out, void *d_t_out,
+                        const afsbem_solve_opts *opts, afsbem_solve_stats *stats, void *hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* AFSBEM_H */

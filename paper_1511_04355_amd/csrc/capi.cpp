@@ -1,0 +1,285 @@
+// C ABI of the afsbem library: argument validation, error capture, handles.
+#include <cmath>
+#include <cstring>
+#include <string>
+
+#include "internal.hpp"
+#include "solver.hpp"
+
+struct afsbem_mesh {
+    std::vector<double> xyz;
+    std::vector<int32_t> tri;
+    int64_t n_vert = 0, n_tri = 0;
+};
+
+struct afsbem_problem {
+    afsbem::Problem p;
+    std::vector<void *> allocs;
+};
+
+namespace afsbem {
+
+static thread_local std::string g_last_error = "";
+
+void set_error(const std::string &msg) { g_last_error = msg; }
+
+template <class F>
+static int guarded(F &&f) {
+    try {
+        return f();
+    } catch (const Error &e) {
+        set_error(e.msg);
+        return e.code;
+    } catch (const std::bad_alloc &) {
+        set_error("host allocation failed");
+        return AFSBEM_ENOMEM;
+    } catch (const std::exception &e) {
+        set_error(e.what());
+        return AFSBEM_EINVAL;
+    }
+}
+
+template <class T>
+static T *upload(afsbem_problem *h, const std::vector<T> &v) {
+    void *p = nullptr;
+    const size_t bytes = std::max<size_t>(v.size() * sizeof(T), 16);
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess)
+        throw Error{AFSBEM_ENOMEM, std::string("hipMalloc failed: ") + hipGetErrorString(e)};
+    h->allocs.push_back(p);
+    if (!v.empty())
+        AFS_HIP(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+    return static_cast<T *>(p);
+}
+
+static void free_problem(afsbem_problem *h) {
+    if (!h)
+        return;
+    delete h->p.ws;
+    h->p.ws = nullptr;
+    for (void *p : h->allocs)
+        (void)hipFree(p);
+    h->allocs.clear();
+}
+
+}  // namespace afsbem
+
+using namespace afsbem;
+
+extern "C" {
+
+const char *afsbem_last_error(void) { return g_last_error.c_str(); }
+
+int afsbem_version(int *major, int *minor) {
+    if (major)
+        *major = 0;
+    if (minor)
+        *minor = 1;
+    return AFSBEM_OK;
+}
+
+int afsbem_mesh_create(const double *xyz, int64_t n_vert, const int32_t *tri, int64_t n_tri, afsbem_mesh **out) {
+    return guarded([&] {
+        AFS_REQUIRE(out && xyz && tri, AFSBEM_EINVAL, "null pointer argument");
+        AFS_REQUIRE(n_vert >= 3 && n_tri >= 1, AFSBEM_EINVAL, "mesh needs at least 3 vertices and 1 triangle");
+        AFS_REQUIRE(n_tri <= (int64_t)1 << 28, AFSBEM_EINVAL, "too many triangles");
+        for (int64_t k = 0; k < 3 * n_tri; ++k)
+            AFS_REQUIRE(tri[k] >= 0 && tri[k] < n_vert, AFSBEM_EINVAL,
+                        "triangle " + std::to_string(k / 3) + " has a vertex index out of range");
+        for (int64_t k = 0; k < 3 * n_vert; ++k)
+            AFS_REQUIRE(std::isfinite(xyz[k]), AFSBEM_EINVAL, "non-finite vertex coordinate");
+        auto *m = new afsbem_mesh();
+        m->xyz.assign(xyz, xyz + 3 * n_vert);
+        m->tri.assign(tri, tri + 3 * n_tri);
+        m->n_vert = n_vert;
+        m->n_tri = n_tri;
+        *out = m;
+        return AFSBEM_OK;
+    });
+}
+
+int afsbem_mesh_destroy(afsbem_mesh *mesh) {
+    delete mesh;
+    return AFSBEM_OK;
+}
+
+int afsbem_problem_create(const afsbem_mesh *mesh, const afsbem_material *mat, const int8_t *bc_kind,
+                          const afsbem_quad_policy *policy, afsbem_problem **out) {
+    afsbem_problem *h = nullptr;
+    int rc = guarded([&] {
+        AFS_REQUIRE(mesh && mat && bc_kind && out, AFSBEM_EINVAL, "null pointer argument");
+        AFS_REQUIRE(mat->mu > 0 && mat->rho > 0 && mat->nu > -1.0 && mat->nu < 0.5, AFSBEM_EINVAL,
+                    "material needs mu > 0, rho > 0, -1 < nu < 0.5");
+        afsbem_quad_policy pol{2.0, 8, 16, 16};
+        if (policy)
+            pol = *policy;
+        AFS_REQUIRE(pol.far_ratio >= 0 && pol.max_subdiv >= 0 && pol.max_subdiv <= 12 && pol.self_n_theta >= 1 &&
+                        pol.self_n_theta <= 64 && pol.self_n_rho >= 1 && pol.self_n_rho <= 64,
+                    AFSBEM_EINVAL, "invalid quadrature policy");
+        for (int64_t e = 0; e < mesh->n_tri; ++e)
+            AFS_REQUIRE(bc_kind[e] == 0 || bc_kind[e] == 1, AFSBEM_EINVAL, "bc_kind must be 0 or 1");
+        h = new afsbem_problem();
+        Problem &P = h->p;
+        P.mat = derive_material(*mat);
+        P.pol = pol;
+        AFS_HIP(hipGetDevice(&P.device));
+        build_plan(mesh->xyz.data(), mesh->n_vert, mesh->tri.data(), mesh->n_tri, bc_kind, pol, P.mat, P.host);
+        const HostPlan &H = P.host;
+        DevicePlan &D = P.dev;
+        D.n_tri = H.n_tri;
+        D.nnz = (int64_t)H.near_col.size();
+        D.n_leaves = (int64_t)(H.leaves.size() / 10);
+        D.n_theta = H.n_theta;
+        D.n_rho = H.n_rho;
+        std::vector<double> cx(H.n_tri), cy(H.n_tri), cz(H.n_tri);
+        for (int64_t e = 0; e < H.n_tri; ++e) {
+            cx[e] = H.cen[3 * e];
+            cy[e] = H.cen[3 * e + 1];
+            cz[e] = H.cen[3 * e + 2];
+        }
+        D.colx = upload(h, cx);
+        D.coly = upload(h, cy);
+        D.colz = upload(h, cz);
+        D.src = upload(h, H.src);
+        D.kind = upload(h, H.kind);
+        D.near_ptr = upload(h, H.near_ptr);
+        D.near_col = upload(h, H.near_col);
+        D.near_row = upload(h, H.near_row);
+        D.leaf_ptr = upload(h, H.leaf_ptr);
+        D.leaves = upload(h, H.leaves);
+        D.self_ang = upload(h, H.self_ang);
+        D.self_cpv = upload(h, H.self_cpv);
+        D.gl_rho = upload(h, H.gl_rho);
+        D.nrm = upload(h, H.nrm);
+        D.coef = upload(h, H.coef);
+        *out = h;
+        return AFSBEM_OK;
+    });
+    if (rc != AFSBEM_OK && h) {
+        free_problem(h);
+        delete h;
+    }
+    return rc;
+}
+
+int afsbem_problem_destroy(afsbem_problem *p) {
+    if (p) {
+        free_problem(p);
+        delete p;
+    }
+    return AFSBEM_OK;
+}
+
+int afsbem_problem_info(const afsbem_problem *p, int64_t *n_tri, int64_t *n_near_pairs, int64_t *n_leaves,
+                        int64_t *self_nodes_per_element) {
+    return guarded([&] {
+        AFS_REQUIRE(p, AFSBEM_EINVAL, "null problem");
+        if (n_tri)
+            *n_tri = p->p.dev.n_tri;
+        if (n_near_pairs)
+            *n_near_pairs = p->p.dev.nnz;
+        if (n_leaves)
+            *n_leaves = p->p.dev.n_leaves;
+        if (self_nodes_per_element)
+            *self_nodes_per_element = 3 * (int64_t)p->p.dev.n_theta * p->p.dev.n_rho;
+        return AFSBEM_OK;
+    });
+}
+
+int afsbem_assemble_device(afsbem_problem *p, double s_re, double s_im, const void *d_bc_val, int format, void *d_A,
+                           void *d_A_lo, void *d_b, void *d_precond, void *hip_stream) {
+    return guarded([&] {
+        AFS_REQUIRE(p && d_bc_val && d_A && d_b, AFSBEM_EINVAL, "null pointer argument");
+        AFS_REQUIRE(format == AFSBEM_FMT_C128 || (format == AFSBEM_FMT_SPLIT && d_A_lo), AFSBEM_EINVAL,
+                    "format must be C128, or SPLIT with both planes");
+        AFS_REQUIRE(std::isfinite(s_re) && std::isfinite(s_im), AFSBEM_EINVAL, "non-finite s");
+        hipStream_t st = static_cast<hipStream_t>(hip_stream);
+        void *scratch = nullptr;
+        AFS_HIP(hipMallocAsync(&scratch, assembly_scratch_bytes(p->p), st));
+        KernelParams kp = kernel_params(p->p.mat, s_re, s_im);
+        launch_assembly(p->p, kp, static_cast<const double *>(d_bc_val), format, d_A, d_A_lo,
+                        static_cast<double *>(d_b), static_cast<double *>(d_precond), scratch, st);
+        AFS_HIP(hipFreeAsync(scratch, st));
+        return AFSBEM_OK;
+    });
+}
+
+int afsbem_matvec_device(afsbem_problem *p, int format, int precision, const void *d_A, const void *d_A_lo,
+                         const void *d_x, void *d_y, void *hip_stream) {
+    return guarded([&] {
+        AFS_REQUIRE(p && d_A && d_x && d_y, AFSBEM_EINVAL, "null pointer argument");
+        AFS_REQUIRE(format == AFSBEM_FMT_C128 || format == AFSBEM_FMT_SPLIT, AFSBEM_EINVAL, "bad format");
+        AFS_REQUIRE(precision == 0 || (precision == 1 && format == AFSBEM_FMT_SPLIT), AFSBEM_EINVAL,
+                    "FP32 products need the SPLIT format");
+        AFS_REQUIRE(format == AFSBEM_FMT_C128 || precision == 1 || d_A_lo, AFSBEM_EINVAL, "FP64 SPLIT needs lo plane");
+        hipStream_t st = static_cast<hipStream_t>(hip_stream);
+        const int64_t N = 3 * p->p.dev.n_tri;
+        void *partial = nullptr;
+        AFS_HIP(hipMallocAsync(&partial, (size_t)gemv_chunks(N) * N * 16, st));
+        launch_gemv(N, format, precision, d_A, d_A_lo, static_cast<const double *>(d_x), static_cast<double *>(d_y),
+                    static_cast<double *>(partial), st);
+        AFS_HIP(hipFreeAsync(partial, st));
+        return AFSBEM_OK;
+    });
+}
+
+int afsbem_solve_opts_default(afsbem_solve_opts *o) {
+    if (!o) {
+        set_error("null opts");
+        return AFSBEM_EINVAL;
+    }
+    std::memset(o, 0, sizeof *o);
+    o->tol = 1e-6;
+    o->restart = 50;
+    o->max_iter = 1000;
+    o->precision = AFSBEM_PREC_FP64;
+    o->warm_start = AFSBEM_WARM_NONE;
+    o->inner_tol = 1e-4;
+    o->batch = 0;
+    o->fault_inject = 0;
+    return AFSBEM_OK;
+}
+
+int afsbem_solve_device(afsbem_problem *p, int32_t n_s, const double *s, const void *d_bc_val, const void *d_x0,
+                        void *d_a_out, void *d_u_out, void *d_t_out, const afsbem_solve_opts *opts,
+                        afsbem_solve_stats *stats, void *hip_stream) {
+    return guarded([&] {
+        AFS_REQUIRE(p && s && d_bc_val, AFSBEM_EINVAL, "null pointer argument");
+        AFS_REQUIRE(n_s >= 0, AFSBEM_EINVAL, "n_s must be >= 0");
+        afsbem_solve_opts o;
+        afsbem_solve_opts_default(&o);
+        if (opts)
+            o = *opts;
+        AFS_REQUIRE(o.tol > 0 && o.restart >= 1 && o.restart <= 500 && o.max_iter >= 1, AFSBEM_EINVAL,
+                    "invalid solver options");
+        AFS_REQUIRE(o.precision == AFSBEM_PREC_FP64 || o.precision == AFSBEM_PREC_MIXED, AFSBEM_EINVAL,
+                    "unknown precision");
+        AFS_REQUIRE(o.warm_start != AFSBEM_WARM_USER || d_x0, AFSBEM_EINVAL, "user warm start needs x0");
+        hipStream_t st = static_cast<hipStream_t>(hip_stream);
+        const int64_t nt = p->p.dev.n_tri, N = 3 * nt;
+        int rc = AFSBEM_OK;
+        for (int32_t k = 0; k < n_s; ++k) {
+            AFS_REQUIRE(std::isfinite(s[2 * k]) && std::isfinite(s[2 * k + 1]), AFSBEM_EINVAL, "non-finite s");
+            const double *bc = static_cast<const double *>(d_bc_val) + 2 * (size_t)k * N;
+            const double *x0 = nullptr;
+            if (o.warm_start == AFSBEM_WARM_USER)
+                x0 = static_cast<const double *>(d_x0) + 2 * (size_t)k * N;
+            else if (o.warm_start == AFSBEM_WARM_PREV && k > 0 && d_a_out)
+                x0 = static_cast<const double *>(d_a_out) + 2 * (size_t)(k - 1) * N;
+            double *a = d_a_out ? static_cast<double *>(d_a_out) + 2 * (size_t)k * N : nullptr;
+            double *u = d_u_out ? static_cast<double *>(d_u_out) + 2 * (size_t)k * N : nullptr;
+            double *t = d_t_out ? static_cast<double *>(d_t_out) + 2 * (size_t)k * N : nullptr;
+            afsbem_solve_opts ok = o;
+            if (!x0)
+                ok.warm_start = AFSBEM_WARM_NONE;
+            int r = solve_one(p->p, ok, s[2 * k], s[2 * k + 1], bc, x0, a, u, t, stats ? &stats[k] : nullptr, st);
+            if (r != AFSBEM_OK && rc == AFSBEM_OK)
+                rc = r;
+        }
+        if (rc == AFSBEM_ENOCONV)
+            set_error("at least one frequency did not reach the tolerance");
+        return rc;
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,155 @@
+// Internal declarations of the afsbem library (not part of the public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/afsbem.h"
+
+namespace afsbem {
+
+// ------------------------------------------------------------------ errors --
+void set_error(const std::string &msg);
+
+struct Error {
+    int code;
+    std::string msg;
+};
+
+#define AFS_HIP(call)                                                                          \
+    do {                                                                                       \
+        hipError_t e_ = (call);                                                                \
+        if (e_ != hipSuccess)                                                                  \
+            throw ::afsbem::Error{AFSBEM_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)}; \
+    } while (0)
+
+#define AFS_REQUIRE(cond, code, msg)                                                            \
+    do {                                                                                       \
+        if (!(cond))                                                                           \
+            throw ::afsbem::Error{(code), (msg)};                                              \
+    } while (0)
+
+// -------------------------------------------------------------- materials --
+struct MaterialDerived {
+    double mu, nu, rho, lam;
+    double cs, cp, beta;       // beta = cs / cp
+    double lam_over_mu;
+};
+MaterialDerived derive_material(const afsbem_material &m);
+
+// ------------------------------------------------------------------ plan --
+// Per-element source record read with wave-uniform (scalar) loads by the far
+// field kernel: 7 quadrature nodes (x, y, z, weight*area), unit normal, kind.
+constexpr int kFarNodes = 7;
+constexpr int kSrcStride = 32;  // doubles per element record
+
+struct HostPlan {
+    int64_t n_tri = 0;
+    // element geometry
+    std::vector<double> vtx;       // [n][9] vertex coordinates p0, p1, p2
+    std::vector<double> cen;       // [n][3] centroid (collocation point)
+    std::vector<double> nrm;       // [n][3]
+    std::vector<double> area;      // [n]
+    std::vector<double> hmax;      // [n] longest edge
+    std::vector<double> src;       // [n][kSrcStride]
+    std::vector<int8_t> kind;      // [n]
+    // near pairs, CSR by collocation row element
+    std::vector<int64_t> near_ptr; // [n+1]
+    std::vector<int32_t> near_col; // [nnz] source element
+    std::vector<int32_t> near_row; // [nnz] collocation element
+    std::vector<int64_t> leaf_ptr; // [nnz+1]
+    std::vector<double> leaves;    // [n_leaves][10]: p0(3), e1(3), e2(3), area
+    // self element polar tables
+    int n_theta = 16, n_rho = 16;
+    std::vector<double> self_ang;  // [n][3*n_theta][5]: e(3), R, w_theta
+    std::vector<double> self_cpv;  // [n][9] principal value of the static 1/r^2 part (real)
+    std::vector<double> gl_rho;    // [n_rho][2]: node in [0,1], weight on [0,1]
+    std::vector<double> coef;      // [16][4]: a_n, b_n, (n-1) a_n, (n-1) b_n
+};
+
+void build_plan(const double *xyz, int64_t nv, const int32_t *tri, int64_t nt, const int8_t *kind,
+                const afsbem_quad_policy &pol, const MaterialDerived &mat, HostPlan &out);
+
+// Gauss-Legendre rule on [-1, 1] (Newton iteration on Legendre polynomials).
+void gauss_legendre(int n, double *x, double *w);
+
+struct DevicePlan {
+    int64_t n_tri = 0, nnz = 0, n_leaves = 0;
+    int n_theta = 16, n_rho = 16;
+    double *colx = nullptr, *coly = nullptr, *colz = nullptr; // collocation points SoA
+    double *src = nullptr;
+    int8_t *kind = nullptr;
+    int64_t *near_ptr = nullptr;
+    int32_t *near_col = nullptr, *near_row = nullptr;
+    int64_t *leaf_ptr = nullptr;
+    double *leaves = nullptr;
+    double *self_ang = nullptr, *self_cpv = nullptr, *gl_rho = nullptr;
+    double *nrm = nullptr;         // [n][3]
+    double *coef = nullptr;        // [16][4] series coefficients of the radial functions
+};
+
+// -------------------------------------------------------------- problem --
+struct Workspace;
+
+struct Problem {
+    MaterialDerived mat;
+    afsbem_quad_policy pol;
+    HostPlan host;
+    DevicePlan dev;
+    int device = 0;
+    Workspace *ws = nullptr;
+};
+
+// ----------------------------------------------------- kernel launchers --
+struct KernelParams {
+    double s_re, s_im;
+    double inv_cs;        // 1 / c_s
+    double beta;          // c_s / c_p
+    double c_u;           // 1 / (4 pi mu)
+    double lam_over_mu;
+};
+KernelParams kernel_params(const MaterialDerived &m, double s_re, double s_im);
+
+// Assembly scratch sizes for a problem: b partial sums of the far field
+// ([n_chunks][N] complex), per-self b ([n][3]), per-near-pair b corrections.
+int far_source_chunks(int64_t n_tri);
+size_t assembly_scratch_bytes(const Problem &p);
+
+// Launch the whole assembly: far field, near pairs, self elements, b and the
+// block-Jacobi inverses.  format: AFSBEM_FMT_*.
+void launch_assembly(const Problem &p, const KernelParams &kp, const double *bc_val, int format,
+                     void *A, void *A_lo, double *b, double *precond, void *scratch,
+                     hipStream_t st);
+
+// y = A x.  precision 0: FP64, 1: FP32 hi plane.  partial: scratch of
+// gemv_chunks(N) * N complex doubles.
+int gemv_chunks(int64_t N);
+void launch_gemv(int64_t N, int format, int precision, const void *A, const void *A_lo,
+                 const double *x, double *y, double *partial, hipStream_t st);
+
+// ------------------------------------------------------ vector kernels --
+// All vectors are complex<double> interleaved, length N (complex entries).
+void vec_precond(int64_t n_tri, const double *Dinv, const double *v, double *z, hipStream_t st);
+void vec_sub(int64_t N, const double *a, const double *b, double *out, hipStream_t st);   // out = a - b
+void vec_axpy(int64_t N, const double *alpha_dev, int idx, double sign, const double *x, double *y,
+              hipStream_t st);
+// Multi-dot: out[i] = sum_r conj(V_i[r]) w[r], i < nv; V rows strided by ldv.
+void vec_mdot(int64_t N, int nv, const double *V, int64_t ldv, const double *w, double *partial,
+              double *out, hipStream_t st);
+// w -= sum_i h[i] V_i
+void vec_mupdate(int64_t N, int nv, const double *V, int64_t ldv, const double *h, double *w,
+                 hipStream_t st);
+// out = x / norm (norm read from device scalar nrm2 = ||x||^2)
+void vec_normalize(int64_t N, const double *nrm2, const double *x, double *out, hipStream_t st);
+// x += sum_i y[i] V_i  (y on device, complex)
+void vec_combine(int64_t N, int nv, const double *V, int64_t ldv, const double *y, double *x,
+                 hipStream_t st);
+// scatter solution a into u, t by element kind
+void vec_split_ut(int64_t n_tri, const int8_t *kind, const double *a, const double *bc, double *u,
+                  double *t, hipStream_t st);
+int mdot_blocks(int64_t N);
+
+}  // namespace afsbem

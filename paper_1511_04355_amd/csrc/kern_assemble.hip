@@ -1,0 +1,545 @@
+// Assembly of the collocation system A(s) a = b(s) (paper Section 2.1, Eq. 1-2)
+// on gfx950, FP64 kernel evaluation.
+//
+// Matrix layout: column-major with leading dimension lda (a multiple of 64);
+// entry (row 3m+i, col 3n+j) is the (i, j) entry of the 3x3 block of
+// collocation element m and source element n.
+//
+// Work mapping.  The far-field kernel gives every lane one collocation point
+// (row block m) and walks a chunk of source elements n in lock-step, so the
+// source quadrature nodes, normal and boundary kind are wave-uniform (scalar
+// loads, no divergence on the boundary-condition branch) and each store of a
+// 3x3 block column lands on 3 consecutive rows per lane, i.e. one contiguous
+// 48/24-byte run per lane that together with the neighbouring lanes covers
+// 64*3 consecutive rows of the column.  Near pairs and self elements are few
+// but need many nodes each: one wavefront per pair, lanes over nodes, then a
+// wavefront reduction.
+#include "cplx.hpp"
+#include "internal.hpp"
+
+namespace afsbem {
+
+struct Rule7Args {
+    double b1[7], b2[7], w[7];  // barycentric weights of vertices 1 and 2, rule weight
+};
+
+// ---------------------------------------------------------------------------
+// Kernel evaluation at one point pair.  r^k-scaled radial functions
+//   Psi = r psi, X = r chi, Psd = r^2 psi', Xd = r^2 chi'
+// of x = s r / c_s; series about 0 for |x| < 1/4 (the P/S cancellation makes
+// the closed form lose eps/|x|^2), closed form above.
+// ---------------------------------------------------------------------------
+struct Radial {
+    cd Psi, X, Psd, Xd;
+};
+
+__device__ __forceinline__ Radial radial64(cd x, double beta, const double *__restrict__ coef) {
+    Radial R;
+    const double ax2 = x.r * x.r + x.i * x.i;
+    if (ax2 < 0.0625) {
+        // coef: [16][4] = a_n, b_n, (n-1) a_n, (n-1) b_n ; Horner from the top
+        cd p0 = cd{coef[4 * 15 + 0], 0.0}, p1 = cd{coef[4 * 15 + 1], 0.0};
+        cd p2 = cd{coef[4 * 15 + 2], 0.0}, p3 = cd{coef[4 * 15 + 3], 0.0};
+#pragma unroll
+        for (int n = 14; n >= 0; --n) {
+            p0 = cfma_real(p0, x, coef[4 * n + 0]);
+            p1 = cfma_real(p1, x, coef[4 * n + 1]);
+            p2 = cfma_real(p2, x, coef[4 * n + 2]);
+            p3 = cfma_real(p3, x, coef[4 * n + 3]);
+        }
+        R.Psi = p0;
+        R.X = p1;
+        R.Psd = p2;
+        R.Xd = p3;
+        return R;
+    }
+    double sn, cs;
+    sincos(x.i, &sn, &cs);
+    const double ex = exp(-x.r);
+    const cd e = cd{ex * cs, -ex * sn};
+    sincos(beta * x.i, &sn, &cs);
+    const double exp_ = exp(-beta * x.r);
+    const cd ep = cd{exp_ * cs, -exp_ * sn};
+    const double inv = 1.0 / ax2;
+    const cd ix = cd{x.r * inv, -x.i * inv};
+    const cd ix2 = cmul(ix, ix);
+    const double b2 = beta * beta;
+    // P = ep (beta^2 + 3 beta ix + 3 ix^2)
+    const cd P = cmul(ep, cd{b2 + 3.0 * beta * ix.r + 3.0 * ix2.r, 3.0 * beta * ix.i + 3.0 * ix2.i});
+    R.Psi = csub(cmul(e, cd{1.0 + ix.r + ix2.r, ix.i + ix2.i}), cmul(ep, cd{beta * ix.r + ix2.r, beta * ix.i + ix2.i}));
+    R.X = csub(cmul(e, cd{1.0 + 3.0 * ix.r + 3.0 * ix2.r, 3.0 * ix.i + 3.0 * ix2.i}), P);
+    R.Psd = csub(P, cmul(e, cd{x.r + 2.0 + 3.0 * ix.r + 3.0 * ix2.r, x.i + 3.0 * ix.i + 3.0 * ix2.i}));
+    const double b3 = b2 * beta;
+    R.Xd = csub(cmul(ep, cd{b3 * x.r + 4.0 * b2 + 9.0 * beta * ix.r + 9.0 * ix2.r, b3 * x.i + 9.0 * beta * ix.i + 9.0 * ix2.i}),
+                cmul(e, cd{x.r + 4.0 + 9.0 * ix.r + 9.0 * ix2.r, x.i + 9.0 * ix.i + 9.0 * ix2.i}));
+    return R;
+}
+
+// Coefficients of T_ij = (1/(4 pi r^2)) [t0 d_ij + t1 n_i rh_j + t2 rh_i n_j + t3 rh_i rh_j]
+// and U_ij = (1/(4 pi mu r)) [Psi d_ij - X rh_i rh_j].
+struct PairEval {
+    double rh[3];
+    double r, rn;
+    cd Psi, X;             // U coefficients (without 1/(4 pi mu r))
+    cd t0, t1, t2, t3;     // T coefficients (without 1/(4 pi r^2))
+};
+
+__device__ __forceinline__ void eval_pair(const KernelParams &kp, const double *__restrict__ coef,
+                                          double xx, double xy, double xz, double yx, double yy, double yz,
+                                          double nx, double ny, double nz, PairEval &E) {
+    const double dx = yx - xx, dy = yy - xy, dz = yz - xz;
+    const double r2 = dx * dx + dy * dy + dz * dz;
+    const double r = sqrt(r2);
+    const double ir = 1.0 / r;
+    E.r = r;
+    E.rh[0] = dx * ir;
+    E.rh[1] = dy * ir;
+    E.rh[2] = dz * ir;
+    E.rn = E.rh[0] * nx + E.rh[1] * ny + E.rh[2] * nz;
+    const cd x = cd{kp.s_re * r * kp.inv_cs, kp.s_im * r * kp.inv_cs};
+    const Radial R = radial64(x, kp.beta, coef);
+    E.Psi = R.Psi;
+    E.X = R.X;
+    const cd b1 = csub(R.Psd, R.X);
+    E.t1 = b1;
+    E.t0 = cscale(b1, E.rn);
+    // t2 = -2X + (lam/mu)(Psd - Xd - 2X)
+    const cd tmp = csub(csub(R.Psd, R.Xd), cscale(R.X, 2.0));
+    E.t2 = cadd(cscale(R.X, -2.0), cscale(tmp, kp.lam_over_mu));
+    E.t3 = cscale(csub(cscale(R.X, 4.0), cscale(R.Xd, 2.0)), E.rn);
+}
+
+constexpr double kInv4Pi = 0.079577471545947667884;  // 1 / (4 pi)
+
+// full 3x3 T block times weight w, accumulated into blk (row-major i*3+j)
+__device__ __forceinline__ void acc_T(const PairEval &E, double nx, double ny, double nz, double w,
+                                      cd blk[9]) {
+    const double n[3] = {nx, ny, nz};
+    const double f = w * kInv4Pi / (E.r * E.r);
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            cd v = cadd(cadd(cscale(E.t1, n[i] * E.rh[j]), cscale(E.t2, E.rh[i] * n[j])),
+                        cscale(E.t3, E.rh[i] * E.rh[j]));
+            if (i == j)
+                v = cadd(v, E.t0);
+            blk[3 * i + j] = cadd(blk[3 * i + j], cscale(v, f));
+        }
+}
+
+__device__ __forceinline__ void acc_U(const PairEval &E, const KernelParams &kp, double w, cd blk[9]) {
+    const double f = w * kp.c_u / E.r;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            cd v = cscale(E.X, -E.rh[i] * E.rh[j]);
+            if (i == j)
+                v = cadd(v, E.Psi);
+            blk[3 * i + j] = cadd(blk[3 * i + j], cscale(v, f));
+        }
+}
+
+// acc += w * T . v   (v complex 3-vector)
+__device__ __forceinline__ void acc_Tv(const PairEval &E, double nx, double ny, double nz, double w,
+                                       const cd v[3], cd acc[3]) {
+    const double n[3] = {nx, ny, nz};
+    const double f = w * kInv4Pi / (E.r * E.r);
+    const cd rv = cadd(cadd(cscale(v[0], E.rh[0]), cscale(v[1], E.rh[1])), cscale(v[2], E.rh[2]));
+    const cd nv = cadd(cadd(cscale(v[0], nx), cscale(v[1], ny)), cscale(v[2], nz));
+    const cd a1 = cmul(E.t1, rv), a2 = cmul(E.t2, nv), a3 = cmul(E.t3, rv);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        cd t = cadd(cmul(E.t0, v[i]), cadd(cscale(a1, n[i]), cscale(cadd(a2, a3), E.rh[i])));
+        acc[i] = cadd(acc[i], cscale(t, f));
+    }
+}
+
+// acc += w * U . v
+__device__ __forceinline__ void acc_Uv(const PairEval &E, const KernelParams &kp, double w, const cd v[3],
+                                       cd acc[3]) {
+    const double f = w * kp.c_u / E.r;
+    const cd rv = cadd(cadd(cscale(v[0], E.rh[0]), cscale(v[1], E.rh[1])), cscale(v[2], E.rh[2]));
+    const cd xr = cmul(E.X, rv);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        cd t = csub(cmul(E.Psi, v[i]), cscale(xr, E.rh[i]));
+        acc[i] = cadd(acc[i], cscale(t, f));
+    }
+}
+
+template <int FMT>
+__device__ __forceinline__ void store_block(void *A, void *A_lo, int64_t lda, int64_t m, int64_t n, const cd blk[9]) {
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        const int64_t base = (3 * n + j) * lda + 3 * m;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            const cd v = blk[3 * i + j];
+            if (FMT == AFSBEM_FMT_C128) {
+                reinterpret_cast<double2 *>(A)[base + i] = make_double2(v.r, v.i);
+            } else {
+                const float hr = (float)v.r, hi = (float)v.i;
+                reinterpret_cast<float2 *>(A)[base + i] = make_float2(hr, hi);
+                reinterpret_cast<float2 *>(A_lo)[base + i] =
+                    make_float2((float)(v.r - (double)hr), (float)(v.i - (double)hi));
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------- far field --
+template <int FMT>
+__global__ __launch_bounds__(256) void far_assemble_kernel(
+    int64_t nt, int64_t lda, KernelParams kp, const double *__restrict__ colx, const double *__restrict__ coly,
+    const double *__restrict__ colz, const double *__restrict__ src, const double *__restrict__ bc,
+    const double *__restrict__ coef, int64_t chunk_len, void *A, void *A_lo, double *__restrict__ bpart) {
+    const int64_t N = 3 * nt;
+    const int64_t m = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const bool active = m < nt;
+    double xx = 0, xy = 0, xz = 0;
+    if (active) {
+        xx = colx[m];
+        xy = coly[m];
+        xz = colz[m];
+    }
+    const int64_t n0 = (int64_t)blockIdx.y * chunk_len;
+    const int64_t n1 = (n0 + chunk_len < nt) ? n0 + chunk_len : nt;
+    cd bacc[3] = {cd{0, 0}, cd{0, 0}, cd{0, 0}};
+    for (int64_t n = n0; n < n1; ++n) {
+        const double *rec = src + kSrcStride * n;
+        const double nx = rec[28], ny = rec[29], nz = rec[30];
+        const int kind = (int)rec[31];
+        const double *bv = bc + 6 * n;
+        const cd v[3] = {cd{bv[0], bv[1]}, cd{bv[2], bv[3]}, cd{bv[4], bv[5]}};
+        if (!active || m == n)
+            continue;
+        cd blk[9];
+#pragma unroll
+        for (int e = 0; e < 9; ++e)
+            blk[e] = cd{0, 0};
+#pragma unroll
+        for (int q = 0; q < kFarNodes; ++q) {
+            PairEval E;
+            eval_pair(kp, coef, xx, xy, xz, rec[4 * q], rec[4 * q + 1], rec[4 * q + 2], nx, ny, nz, E);
+            const double w = rec[4 * q + 3];
+            if (kind == 0) {
+                acc_T(E, nx, ny, nz, w, blk);
+                acc_Uv(E, kp, w, v, bacc);
+            } else {
+                acc_U(E, kp, -w, blk);
+                acc_Tv(E, nx, ny, nz, -w, v, bacc);
+            }
+        }
+        store_block<FMT>(A, A_lo, lda, m, n, blk);
+    }
+    if (active) {
+        double *bp = bpart + 2 * ((int64_t)blockIdx.y * N + 3 * m);
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            bp[2 * i] = bacc[i].r;
+            bp[2 * i + 1] = bacc[i].i;
+        }
+    }
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+        v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// ---------------------------------------------------------------- near pairs --
+template <int FMT>
+__global__ __launch_bounds__(256) void near_assemble_kernel(
+    int64_t nt, int64_t lda, int64_t nnz, KernelParams kp, Rule7Args rule, const double *__restrict__ colx,
+    const double *__restrict__ coly, const double *__restrict__ colz, const double *__restrict__ src,
+    const double *__restrict__ bc, const double *__restrict__ coef, const int32_t *__restrict__ near_row,
+    const int32_t *__restrict__ near_col, const int64_t *__restrict__ leaf_ptr,
+    const double *__restrict__ leaves, void *A, void *A_lo, double *__restrict__ corr) {
+    const int64_t p = ((int64_t)blockIdx.x * 256 + threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63;
+    if (p >= nnz)
+        return;
+    const int64_t m = near_row[p], n = near_col[p];
+    const double xx = colx[m], xy = coly[m], xz = colz[m];
+    const double *rec = src + kSrcStride * n;
+    const double nx = rec[28], ny = rec[29], nz = rec[30];
+    const int kind = (int)rec[31];
+    const double *bv = bc + 6 * n;
+    const cd v[3] = {cd{bv[0], bv[1]}, cd{bv[2], bv[3]}, cd{bv[4], bv[5]}};
+    const int64_t L0 = leaf_ptr[p], L1 = leaf_ptr[p + 1];
+    const int64_t n_near = 7 * (L1 - L0);
+    const int64_t items = n_near + kFarNodes;
+    cd blk[9], bcor[3] = {cd{0, 0}, cd{0, 0}, cd{0, 0}};
+#pragma unroll
+    for (int e = 0; e < 9; ++e)
+        blk[e] = cd{0, 0};
+    for (int64_t k = lane; k < items; k += 64) {
+        double yx, yy, yz, w, sA, sB;
+        if (k < n_near) {
+            const double *L = leaves + 10 * (L0 + k / 7);
+            const int q = (int)(k % 7);
+            yx = L[0] + rule.b1[q] * L[3] + rule.b2[q] * L[6];
+            yy = L[1] + rule.b1[q] * L[4] + rule.b2[q] * L[7];
+            yz = L[2] + rule.b1[q] * L[5] + rule.b2[q] * L[8];
+            w = rule.w[q] * L[9];
+            sA = 1.0;
+            sB = 1.0;
+        } else {
+            const int q = (int)(k - n_near);
+            yx = rec[4 * q];
+            yy = rec[4 * q + 1];
+            yz = rec[4 * q + 2];
+            w = rec[4 * q + 3];
+            sA = 0.0;
+            sB = -1.0;  // remove the far-rule contribution the far kernel put into b
+        }
+        PairEval E;
+        eval_pair(kp, coef, xx, xy, xz, yx, yy, yz, nx, ny, nz, E);
+        if (kind == 0) {
+            acc_T(E, nx, ny, nz, sA * w, blk);
+            acc_Uv(E, kp, sB * w, v, bcor);
+        } else {
+            acc_U(E, kp, -sA * w, blk);
+            acc_Tv(E, nx, ny, nz, -sB * w, v, bcor);
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < 9; ++e) {
+        blk[e].r = wave_sum(blk[e].r);
+        blk[e].i = wave_sum(blk[e].i);
+    }
+#pragma unroll
+    for (int e = 0; e < 3; ++e) {
+        bcor[e].r = wave_sum(bcor[e].r);
+        bcor[e].i = wave_sum(bcor[e].i);
+    }
+    if (lane == 0) {
+        store_block<FMT>(A, A_lo, lda, m, n, blk);
+#pragma unroll
+        for (int e = 0; e < 3; ++e) {
+            corr[6 * p + 2 * e] = bcor[e].r;
+            corr[6 * p + 2 * e + 1] = bcor[e].i;
+        }
+    }
+}
+
+// ------------------------------------------------------------- self element --
+// 3x3 complex inverse by the adjugate (row-major in, row-major out).
+__device__ void inv3(const cd a[9], cd out[9]) {
+    const cd c00 = csub(cmul(a[4], a[8]), cmul(a[5], a[7]));
+    const cd c01 = csub(cmul(a[5], a[6]), cmul(a[3], a[8]));
+    const cd c02 = csub(cmul(a[3], a[7]), cmul(a[4], a[6]));
+    const cd det = cadd(cadd(cmul(a[0], c00), cmul(a[1], c01)), cmul(a[2], c02));
+    const cd id = cinv(det);
+    out[0] = cmul(c00, id);
+    out[1] = cmul(csub(cmul(a[2], a[7]), cmul(a[1], a[8])), id);
+    out[2] = cmul(csub(cmul(a[1], a[5]), cmul(a[2], a[4])), id);
+    out[3] = cmul(c01, id);
+    out[4] = cmul(csub(cmul(a[0], a[8]), cmul(a[2], a[6])), id);
+    out[5] = cmul(csub(cmul(a[2], a[3]), cmul(a[0], a[5])), id);
+    out[6] = cmul(c02, id);
+    out[7] = cmul(csub(cmul(a[1], a[6]), cmul(a[0], a[7])), id);
+    out[8] = cmul(csub(cmul(a[0], a[4]), cmul(a[1], a[3])), id);
+}
+
+template <int FMT>
+__global__ __launch_bounds__(256) void self_assemble_kernel(
+    int64_t nt, int64_t lda, KernelParams kp, const double *__restrict__ colx, const double *__restrict__ coly,
+    const double *__restrict__ colz, const double *__restrict__ src, const double *__restrict__ bc,
+    const double *__restrict__ coef, const double *__restrict__ self_ang, const double *__restrict__ self_cpv,
+    const double *__restrict__ gl_rho, int n_theta, int n_rho, void *A, void *A_lo, double *__restrict__ bself,
+    double *__restrict__ precond) {
+    const int64_t m = ((int64_t)blockIdx.x * 256 + threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63;
+    if (m >= nt)
+        return;
+    const double xx = colx[m], xy = coly[m], xz = colz[m];
+    const double *rec = src + kSrcStride * m;
+    const double nx = rec[28], ny = rec[29], nz = rec[30];
+    const int kind = (int)rec[31];
+    const double b2 = kp.beta * kp.beta;
+    const int items = 3 * n_theta * n_rho;
+    const double *ang = self_ang + (int64_t)m * 3 * n_theta * 5;
+    cd G[9], H[9];
+#pragma unroll
+    for (int e = 0; e < 9; ++e)
+        G[e] = H[e] = cd{0, 0};
+    for (int k = lane; k < items; k += 64) {
+        const double *a = ang + 5 * (k / n_rho);
+        const int q = k % n_rho;
+        const double R = a[3];
+        const double rho = R * gl_rho[2 * q];
+        const double w = a[4] * R * gl_rho[2 * q + 1] * rho;
+        PairEval E;
+        eval_pair(kp, coef, xx, xy, xz, xx + rho * a[0], xy + rho * a[1], xz + rho * a[2], nx, ny, nz, E);
+        acc_U(E, kp, w, G);
+        // remove the static 1/r^2 part: T0 = beta^2/(4 pi r^2)(rh_i n_j - n_i rh_j)
+        E.t1 = cadd(E.t1, cd{b2, 0.0});
+        E.t2 = csub(E.t2, cd{b2, 0.0});
+        acc_T(E, nx, ny, nz, w, H);
+    }
+#pragma unroll
+    for (int e = 0; e < 9; ++e) {
+        G[e].r = wave_sum(G[e].r);
+        G[e].i = wave_sum(G[e].i);
+        H[e].r = wave_sum(H[e].r);
+        H[e].i = wave_sum(H[e].i);
+    }
+    if (lane != 0)
+        return;
+    const double *cpv = self_cpv + 9 * m;
+#pragma unroll
+    for (int e = 0; e < 9; ++e)
+        H[e].r += cpv[e];
+    H[0].r += 0.5;
+    H[4].r += 0.5;
+    H[8].r += 0.5;
+    const double *bv = bc + 6 * m;
+    const cd v[3] = {cd{bv[0], bv[1]}, cd{bv[2], bv[3]}, cd{bv[4], bv[5]}};
+    cd blk[9], bs[3];
+    for (int i = 0; i < 3; ++i) {
+        bs[i] = cd{0, 0};
+        for (int j = 0; j < 3; ++j) {
+            if (kind == 0) {
+                blk[3 * i + j] = H[3 * i + j];
+                bs[i] = cadd(bs[i], cmul(G[3 * i + j], v[j]));
+            } else {
+                blk[3 * i + j] = cscale(G[3 * i + j], -1.0);
+                bs[i] = csub(bs[i], cmul(H[3 * i + j], v[j]));
+            }
+        }
+    }
+    store_block<FMT>(A, A_lo, lda, m, m, blk);
+    for (int i = 0; i < 3; ++i) {
+        bself[6 * m + 2 * i] = bs[i].r;
+        bself[6 * m + 2 * i + 1] = bs[i].i;
+    }
+    if (precond) {
+        cd inv[9];
+        inv3(blk, inv);
+        for (int e = 0; e < 9; ++e) {
+            precond[18 * m + 2 * e] = inv[e].r;
+            precond[18 * m + 2 * e + 1] = inv[e].i;
+        }
+    }
+}
+
+// b = sum over far chunks + self + near corrections (fixed order: deterministic)
+__global__ __launch_bounds__(256) void finalize_b_kernel(int64_t nt, int S, const double *__restrict__ bpart,
+                                                         const double *__restrict__ bself,
+                                                         const int64_t *__restrict__ near_ptr,
+                                                         const double *__restrict__ corr, double *__restrict__ b) {
+    const int64_t N = 3 * nt;
+    const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (r >= N)
+        return;
+    const int64_t m = r / 3;
+    const int i = (int)(r % 3);
+    double ar = 0, ai = 0;
+    for (int s = 0; s < S; ++s) {
+        ar += bpart[2 * ((int64_t)s * N + r)];
+        ai += bpart[2 * ((int64_t)s * N + r) + 1];
+    }
+    ar += bself[6 * m + 2 * i];
+    ai += bself[6 * m + 2 * i + 1];
+    for (int64_t p = near_ptr[m]; p < near_ptr[m + 1]; ++p) {
+        ar += corr[6 * p + 2 * i];
+        ai += corr[6 * p + 2 * i + 1];
+    }
+    b[2 * r] = ar;
+    b[2 * r + 1] = ai;
+}
+
+// ----------------------------------------------------------------- launch --
+int far_source_chunks(int64_t nt) {
+    const int64_t gx = (nt + 255) / 256;
+    int64_t S = (4096 + gx - 1) / gx;
+    if (S > nt)
+        S = nt;
+    if (S < 1)
+        S = 1;
+    return (int)S;
+}
+
+size_t assembly_scratch_bytes(const Problem &p) {
+    const int64_t nt = p.dev.n_tri, N = 3 * nt;
+    const int S = far_source_chunks(nt);
+    return (size_t)S * N * 16 + (size_t)nt * 48 + (size_t)std::max<int64_t>(p.dev.nnz, 1) * 48 + 4096;
+}
+
+KernelParams kernel_params(const MaterialDerived &m, double s_re, double s_im) {
+    KernelParams k;
+    k.s_re = s_re;
+    k.s_im = s_im;
+    k.inv_cs = 1.0 / m.cs;
+    k.beta = m.beta;
+    k.c_u = 1.0 / (4.0 * 3.14159265358979323846 * m.mu);
+    k.lam_over_mu = m.lam_over_mu;
+    return k;
+}
+
+static Rule7Args rule7_args() {
+    Rule7Args r;
+    const double q = std::sqrt(15.0);
+    const double oa[2] = {(6.0 - q) / 21.0, (6.0 + q) / 21.0};
+    const double ow[2] = {(155.0 - q) / 1200.0, (155.0 + q) / 1200.0};
+    r.b1[0] = r.b2[0] = 1.0 / 3.0;
+    r.w[0] = 0.225;
+    for (int o = 0; o < 2; ++o)
+        for (int k = 0; k < 3; ++k) {
+            const int i = 1 + 3 * o + k;
+            // barycentric (l0, l1, l2) with l_k = 1 - 2a, the others a
+            r.b1[i] = (k == 1) ? 1.0 - 2.0 * oa[o] : oa[o];
+            r.b2[i] = (k == 2) ? 1.0 - 2.0 * oa[o] : oa[o];
+            r.w[i] = ow[o];
+        }
+    return r;
+}
+
+void launch_assembly(const Problem &p, const KernelParams &kp, const double *bc_val, int format, void *A,
+                     void *A_lo, double *b, double *precond, void *scratch, hipStream_t st) {
+    const DevicePlan &d = p.dev;
+    const int64_t nt = d.n_tri, N = 3 * nt;
+    const int64_t lda = (N + 63) / 64 * 64;
+    const int S = far_source_chunks(nt);
+    const int64_t chunk = (nt + S - 1) / S;
+    const int Sused = (int)((nt + chunk - 1) / chunk);
+    double *bpart = static_cast<double *>(scratch);
+    double *bself = bpart + 2 * (size_t)S * N;
+    double *corr = bself + 6 * nt;
+    const double *coef = d.coef;
+    dim3 gfar((unsigned)((nt + 255) / 256), (unsigned)Sused);
+    const unsigned gnear = (unsigned)((d.nnz * 64 + 255) / 256);
+    const unsigned gself = (unsigned)((nt * 64 + 255) / 256);
+    const Rule7Args rule = rule7_args();
+    if (format == AFSBEM_FMT_C128) {
+        far_assemble_kernel<AFSBEM_FMT_C128><<<gfar, 256, 0, st>>>(nt, lda, kp, d.colx, d.coly, d.colz, d.src, bc_val,
+                                                                  coef, chunk, A, A_lo, bpart);
+        if (d.nnz)
+            near_assemble_kernel<AFSBEM_FMT_C128><<<gnear, 256, 0, st>>>(
+                nt, lda, d.nnz, kp, rule, d.colx, d.coly, d.colz, d.src, bc_val, coef, d.near_row, d.near_col,
+                d.leaf_ptr, d.leaves, A, A_lo, corr);
+        self_assemble_kernel<AFSBEM_FMT_C128><<<gself, 256, 0, st>>>(nt, lda, kp, d.colx, d.coly, d.colz, d.src,
+                                                                    bc_val, coef, d.self_ang, d.self_cpv, d.gl_rho,
+                                                                    d.n_theta, d.n_rho, A, A_lo, bself, precond);
+    } else {
+        far_assemble_kernel<AFSBEM_FMT_SPLIT><<<gfar, 256, 0, st>>>(nt, lda, kp, d.colx, d.coly, d.colz, d.src,
+                                                                   bc_val, coef, chunk, A, A_lo, bpart);
+        if (d.nnz)
+            near_assemble_kernel<AFSBEM_FMT_SPLIT><<<gnear, 256, 0, st>>>(
+                nt, lda, d.nnz, kp, rule, d.colx, d.coly, d.colz, d.src, bc_val, coef, d.near_row, d.near_col,
+                d.leaf_ptr, d.leaves, A, A_lo, corr);
+        self_assemble_kernel<AFSBEM_FMT_SPLIT><<<gself, 256, 0, st>>>(nt, lda, kp, d.colx, d.coly, d.colz, d.src,
+                                                                     bc_val, coef, d.self_ang, d.self_cpv, d.gl_rho,
+                                                                     d.n_theta, d.n_rho, A, A_lo, bself, precond);
+    }
+    AFS_HIP(hipGetLastError());
+    finalize_b_kernel<<<(unsigned)((N + 255) / 256), 256, 0, st>>>(nt, Sused, bpart, bself, d.near_ptr, corr, b);
+    AFS_HIP(hipGetLastError());
+}
+
+}  // namespace afsbem

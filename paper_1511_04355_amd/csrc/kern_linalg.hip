@@ -1,0 +1,416 @@
+// Dense complex matrix-vector products and Krylov vector kernels for gfx950.
+//
+// GEMV (the GMRES operator application, HBM-bound): the matrix is
+// column-major, lanes own rows and a workgroup walks a chunk of columns, so
+// every load instruction of a wavefront reads 1 KiB of one column contiguously
+// and the vector entry x[col] is wave-uniform (scalar load).  Columns are split
+// into chunks over grid.y to put enough bytes in flight; partial sums per
+// chunk are combined in FP64 by a second pass in a fixed order
+// (deterministic).
+//   C128: one row per lane, 16-byte loads, FP64 FMA.
+//   SPLIT FP32: two rows per lane (16 bytes of the hi plane), FP32 FMA and
+//               FP32 accumulation within a chunk.
+//   SPLIT FP64: hi + lo planes converted to FP64 per entry, FP64 FMA.
+#include "cplx.hpp"
+#include "internal.hpp"
+
+namespace afsbem {
+
+constexpr int kGemvUnroll = 8;
+
+typedef double d2v __attribute__((ext_vector_type(2)));
+typedef float f4v __attribute__((ext_vector_type(4)));
+
+// streaming (non-temporal) 16-byte loads: the matrix is read once per product
+__device__ __forceinline__ double2 ld_nt(const double2 *p) {
+    const d2v v = __builtin_nontemporal_load(reinterpret_cast<const d2v *>(p));
+    return make_double2(v.x, v.y);
+}
+__device__ __forceinline__ float4 ld_nt(const float4 *p) {
+    const f4v v = __builtin_nontemporal_load(reinterpret_cast<const f4v *>(p));
+    return make_float4(v.x, v.y, v.z, v.w);
+}
+
+__global__ __launch_bounds__(256) void gemv_c128_kernel(int64_t N, int64_t lda, const double2 *__restrict__ A,
+                                                        const double2 *__restrict__ x, int64_t chunk,
+                                                        double2 *__restrict__ partial) {
+    const int64_t row = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t c0 = (int64_t)blockIdx.y * chunk;
+    const int64_t c1 = (c0 + chunk < N) ? c0 + chunk : N;
+    double ar = 0.0, ai = 0.0;
+    if (row < N) {
+        const double2 *a = A + row;
+        int64_t c = c0;
+        for (; c + kGemvUnroll <= c1; c += kGemvUnroll) {
+            double2 v[kGemvUnroll];
+#pragma unroll
+            for (int u = 0; u < kGemvUnroll; ++u)
+                v[u] = ld_nt(a + (c + u) * lda);
+#pragma unroll
+            for (int u = 0; u < kGemvUnroll; ++u) {
+                const double2 xv = x[c + u];
+                ar = fma(v[u].x, xv.x, ar);
+                ar = fma(-v[u].y, xv.y, ar);
+                ai = fma(v[u].x, xv.y, ai);
+                ai = fma(v[u].y, xv.x, ai);
+            }
+        }
+        for (; c < c1; ++c) {
+            const double2 v = a[c * lda];
+            const double2 xv = x[c];
+            ar = fma(v.x, xv.x, ar);
+            ar = fma(-v.y, xv.y, ar);
+            ai = fma(v.x, xv.y, ai);
+            ai = fma(v.y, xv.x, ai);
+        }
+        partial[(int64_t)blockIdx.y * N + row] = make_double2(ar, ai);
+    }
+}
+
+// hi plane only, FP32 arithmetic; two rows per lane.
+__global__ __launch_bounds__(256) void gemv_split32_kernel(int64_t N, int64_t lda, const float4 *__restrict__ A,
+                                                           const double2 *__restrict__ x, int64_t chunk,
+                                                           double2 *__restrict__ partial) {
+    const int64_t r2 = (int64_t)blockIdx.x * 256 + threadIdx.x;  // row pair
+    const int64_t row = 2 * r2;
+    const int64_t c0 = (int64_t)blockIdx.y * chunk;
+    const int64_t c1 = (c0 + chunk < N) ? c0 + chunk : N;
+    if (row >= N)
+        return;
+    const int64_t lda2 = lda / 2;  // float4 units per column
+    float a0r = 0.f, a0i = 0.f, a1r = 0.f, a1i = 0.f;
+    const float4 *a = A + r2;
+    int64_t c = c0;
+    for (; c + kGemvUnroll <= c1; c += kGemvUnroll) {
+        float4 v[kGemvUnroll];
+#pragma unroll
+        for (int u = 0; u < kGemvUnroll; ++u)
+            v[u] = ld_nt(a + (c + u) * lda2);
+#pragma unroll
+        for (int u = 0; u < kGemvUnroll; ++u) {
+            const double2 xd = x[c + u];
+            const float xr = (float)xd.x, xi = (float)xd.y;
+            a0r = fmaf(v[u].x, xr, a0r);
+            a0r = fmaf(-v[u].y, xi, a0r);
+            a0i = fmaf(v[u].x, xi, a0i);
+            a0i = fmaf(v[u].y, xr, a0i);
+            a1r = fmaf(v[u].z, xr, a1r);
+            a1r = fmaf(-v[u].w, xi, a1r);
+            a1i = fmaf(v[u].z, xi, a1i);
+            a1i = fmaf(v[u].w, xr, a1i);
+        }
+    }
+    for (; c < c1; ++c) {
+        const float4 v = a[c * lda2];
+        const double2 xd = x[c];
+        const float xr = (float)xd.x, xi = (float)xd.y;
+        a0r = fmaf(v.x, xr, a0r);
+        a0r = fmaf(-v.y, xi, a0r);
+        a0i = fmaf(v.x, xi, a0i);
+        a0i = fmaf(v.y, xr, a0i);
+        a1r = fmaf(v.z, xr, a1r);
+        a1r = fmaf(-v.w, xi, a1r);
+        a1i = fmaf(v.z, xi, a1i);
+        a1i = fmaf(v.w, xr, a1i);
+    }
+    double2 *out = partial + (int64_t)blockIdx.y * N + row;
+    out[0] = make_double2(a0r, a0i);
+    if (row + 1 < N)
+        out[1] = make_double2(a1r, a1i);
+}
+
+// hi + lo planes, FP64 arithmetic; two rows per lane.
+__global__ __launch_bounds__(256) void gemv_split64_kernel(int64_t N, int64_t lda, const float4 *__restrict__ Ah,
+                                                           const float4 *__restrict__ Al,
+                                                           const double2 *__restrict__ x, int64_t chunk,
+                                                           double2 *__restrict__ partial) {
+    const int64_t r2 = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t row = 2 * r2;
+    const int64_t c0 = (int64_t)blockIdx.y * chunk;
+    const int64_t c1 = (c0 + chunk < N) ? c0 + chunk : N;
+    if (row >= N)
+        return;
+    const int64_t lda2 = lda / 2;
+    double a0r = 0, a0i = 0, a1r = 0, a1i = 0;
+    const float4 *h = Ah + r2;
+    const float4 *l = Al + r2;
+    int64_t c = c0;
+    constexpr int U = kGemvUnroll / 2;
+    for (; c + U <= c1; c += U) {
+        float4 vh[U], vl[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            vh[u] = ld_nt(h + (c + u) * lda2);
+            vl[u] = ld_nt(l + (c + u) * lda2);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const double2 xv = x[c + u];
+            const double e0r = (double)vh[u].x + (double)vl[u].x, e0i = (double)vh[u].y + (double)vl[u].y;
+            const double e1r = (double)vh[u].z + (double)vl[u].z, e1i = (double)vh[u].w + (double)vl[u].w;
+            a0r = fma(e0r, xv.x, a0r);
+            a0r = fma(-e0i, xv.y, a0r);
+            a0i = fma(e0r, xv.y, a0i);
+            a0i = fma(e0i, xv.x, a0i);
+            a1r = fma(e1r, xv.x, a1r);
+            a1r = fma(-e1i, xv.y, a1r);
+            a1i = fma(e1r, xv.y, a1i);
+            a1i = fma(e1i, xv.x, a1i);
+        }
+    }
+    for (; c < c1; ++c) {
+        const float4 vh = h[c * lda2], vl = l[c * lda2];
+        const double2 xv = x[c];
+        const double e0r = (double)vh.x + (double)vl.x, e0i = (double)vh.y + (double)vl.y;
+        const double e1r = (double)vh.z + (double)vl.z, e1i = (double)vh.w + (double)vl.w;
+        a0r = fma(e0r, xv.x, a0r);
+        a0r = fma(-e0i, xv.y, a0r);
+        a0i = fma(e0r, xv.y, a0i);
+        a0i = fma(e0i, xv.x, a0i);
+        a1r = fma(e1r, xv.x, a1r);
+        a1r = fma(-e1i, xv.y, a1r);
+        a1i = fma(e1r, xv.y, a1i);
+        a1i = fma(e1i, xv.x, a1i);
+    }
+    double2 *out = partial + (int64_t)blockIdx.y * N + row;
+    out[0] = make_double2(a0r, a0i);
+    if (row + 1 < N)
+        out[1] = make_double2(a1r, a1i);
+}
+
+__global__ __launch_bounds__(256) void sum_partials_kernel(int64_t N, int S, const double2 *__restrict__ partial,
+                                                           double2 *__restrict__ y) {
+    const int64_t row = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (row >= N)
+        return;
+    double r = 0, i = 0;
+    for (int s = 0; s < S; ++s) {
+        const double2 v = partial[(int64_t)s * N + row];
+        r += v.x;
+        i += v.y;
+    }
+    y[row] = make_double2(r, i);
+}
+
+int gemv_chunks(int64_t N) {
+    // enough workgroups to cover the chip several times over
+    const int64_t rows_per_block = 256;
+    const int64_t gx = (N + rows_per_block - 1) / rows_per_block;
+    int64_t S = (2048 + gx - 1) / gx;
+    const int64_t max_s = (N + 31) / 32;  // keep at least 32 columns per chunk
+    if (S > max_s)
+        S = max_s;
+    if (S < 1)
+        S = 1;
+    return (int)S;
+}
+
+void launch_gemv(int64_t N, int format, int precision, const void *A, const void *A_lo, const double *x, double *y,
+                 double *partial, hipStream_t st) {
+    const int64_t lda = (N + 63) / 64 * 64;
+    const int S = gemv_chunks(N);
+    const int64_t chunk = (N + S - 1) / S;
+    const int Su = (int)((N + chunk - 1) / chunk);
+    double2 *part = reinterpret_cast<double2 *>(partial);
+    const double2 *xv = reinterpret_cast<const double2 *>(x);
+    if (format == AFSBEM_FMT_C128) {
+        dim3 g((unsigned)((N + 255) / 256), (unsigned)Su);
+        gemv_c128_kernel<<<g, 256, 0, st>>>(N, lda, static_cast<const double2 *>(A), xv, chunk, part);
+    } else if (precision == 1) {
+        dim3 g((unsigned)((N / 2 + 1 + 255) / 256), (unsigned)Su);
+        gemv_split32_kernel<<<g, 256, 0, st>>>(N, lda, static_cast<const float4 *>(A), xv, chunk, part);
+    } else {
+        dim3 g((unsigned)((N / 2 + 1 + 255) / 256), (unsigned)Su);
+        gemv_split64_kernel<<<g, 256, 0, st>>>(N, lda, static_cast<const float4 *>(A),
+                                               static_cast<const float4 *>(A_lo), xv, chunk, part);
+    }
+    AFS_HIP(hipGetLastError());
+    sum_partials_kernel<<<(unsigned)((N + 255) / 256), 256, 0, st>>>(N, Su, part, reinterpret_cast<double2 *>(y));
+    AFS_HIP(hipGetLastError());
+}
+
+// ---------------------------------------------------------- vector kernels --
+__global__ __launch_bounds__(256) void precond_kernel(int64_t nt, const double *__restrict__ D,
+                                                      const double *__restrict__ v, double *__restrict__ z) {
+    const int64_t m = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (m >= nt)
+        return;
+    cd vin[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+        vin[j] = cd{v[6 * m + 2 * j], v[6 * m + 2 * j + 1]};
+    const double *d = D + 18 * m;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        cd acc{0, 0};
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+            acc = cadd(acc, cmul(cd{d[6 * i + 2 * j], d[6 * i + 2 * j + 1]}, vin[j]));
+        z[6 * m + 2 * i] = acc.r;
+        z[6 * m + 2 * i + 1] = acc.i;
+    }
+}
+
+void vec_precond(int64_t nt, const double *D, const double *v, double *z, hipStream_t st) {
+    precond_kernel<<<(unsigned)((nt + 255) / 256), 256, 0, st>>>(nt, D, v, z);
+    AFS_HIP(hipGetLastError());
+}
+
+__global__ __launch_bounds__(256) void sub_kernel(int64_t n2, const double *a, const double *b, double *o) {
+    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (k < n2)
+        o[k] = a[k] - b[k];
+}
+
+void vec_sub(int64_t N, const double *a, const double *b, double *out, hipStream_t st) {
+    sub_kernel<<<(unsigned)((2 * N + 255) / 256), 256, 0, st>>>(2 * N, a, b, out);
+    AFS_HIP(hipGetLastError());
+}
+
+int mdot_blocks(int64_t N) {
+    int64_t b = (N + 1023) / 1024;
+    if (b > 256)
+        b = 256;
+    if (b < 1)
+        b = 1;
+    return (int)b;
+}
+
+// grid (B, nv): block (b, i) computes the partial dot of V_i and w over its rows
+__global__ __launch_bounds__(256) void mdot_partial_kernel(int64_t N, const double2 *__restrict__ V, int64_t ldv,
+                                                           const double2 *__restrict__ w, int B,
+                                                           double2 *__restrict__ partial) {
+    __shared__ double sr[256], si[256];
+    const int i = blockIdx.y;
+    const double2 *v = V + (int64_t)i * ldv;
+    double ar = 0, ai = 0;
+    for (int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x; r < N; r += (int64_t)B * 256) {
+        const double2 a = v[r], b = w[r];
+        // conj(a) * b
+        ar += a.x * b.x + a.y * b.y;
+        ai += a.x * b.y - a.y * b.x;
+    }
+    sr[threadIdx.x] = ar;
+    si[threadIdx.x] = ai;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) {
+            sr[threadIdx.x] += sr[threadIdx.x + off];
+            si[threadIdx.x] += si[threadIdx.x + off];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        partial[(int64_t)i * B + blockIdx.x] = make_double2(sr[0], si[0]);
+}
+
+__global__ __launch_bounds__(64) void mdot_final_kernel(int B, const double2 *__restrict__ partial,
+                                                        double2 *__restrict__ out) {
+    const int i = blockIdx.x;
+    __shared__ double sr[64], si[64];
+    double ar = 0, ai = 0;
+    for (int b = threadIdx.x; b < B; b += 64) {
+        const double2 v = partial[(int64_t)i * B + b];
+        ar += v.x;
+        ai += v.y;
+    }
+    sr[threadIdx.x] = ar;
+    si[threadIdx.x] = ai;
+    __syncthreads();
+    for (int off = 32; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) {
+            sr[threadIdx.x] += sr[threadIdx.x + off];
+            si[threadIdx.x] += si[threadIdx.x + off];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        out[i] = make_double2(sr[0], si[0]);
+}
+
+void vec_mdot(int64_t N, int nv, const double *V, int64_t ldv, const double *w, double *partial, double *out,
+              hipStream_t st) {
+    const int B = mdot_blocks(N);
+    mdot_partial_kernel<<<dim3(B, nv), 256, 0, st>>>(N, reinterpret_cast<const double2 *>(V), ldv,
+                                                     reinterpret_cast<const double2 *>(w), B,
+                                                     reinterpret_cast<double2 *>(partial));
+    mdot_final_kernel<<<nv, 64, 0, st>>>(B, reinterpret_cast<const double2 *>(partial),
+                                         reinterpret_cast<double2 *>(out));
+    AFS_HIP(hipGetLastError());
+}
+
+// w -= sum_i h_i V_i   (sign = -1)   or   x += sum_i y_i V_i   (sign = +1)
+__global__ __launch_bounds__(256) void mcombine_kernel(int64_t N, int nv, const double2 *__restrict__ V, int64_t ldv,
+                                                       const double2 *__restrict__ h, double sign,
+                                                       double2 *__restrict__ w) {
+    const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (r >= N)
+        return;
+    double ar = 0, ai = 0;
+    for (int i = 0; i < nv; ++i) {
+        const double2 c = h[i], v = V[(int64_t)i * ldv + r];
+        ar += c.x * v.x - c.y * v.y;
+        ai += c.x * v.y + c.y * v.x;
+    }
+    double2 o = w[r];
+    o.x += sign * ar;
+    o.y += sign * ai;
+    w[r] = o;
+}
+
+void vec_mupdate(int64_t N, int nv, const double *V, int64_t ldv, const double *h, double *w, hipStream_t st) {
+    mcombine_kernel<<<(unsigned)((N + 255) / 256), 256, 0, st>>>(N, nv, reinterpret_cast<const double2 *>(V), ldv,
+                                                                 reinterpret_cast<const double2 *>(h), -1.0,
+                                                                 reinterpret_cast<double2 *>(w));
+    AFS_HIP(hipGetLastError());
+}
+
+void vec_combine(int64_t N, int nv, const double *V, int64_t ldv, const double *y, double *x, hipStream_t st) {
+    mcombine_kernel<<<(unsigned)((N + 255) / 256), 256, 0, st>>>(N, nv, reinterpret_cast<const double2 *>(V), ldv,
+                                                                 reinterpret_cast<const double2 *>(y), 1.0,
+                                                                 reinterpret_cast<double2 *>(x));
+    AFS_HIP(hipGetLastError());
+}
+
+// out = x / sqrt(nrm2[0].re)
+__global__ __launch_bounds__(256) void normalize_kernel(int64_t N, const double *__restrict__ nrm2,
+                                                        const double2 *__restrict__ x, double2 *__restrict__ out) {
+    const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (r >= N)
+        return;
+    const double inv = 1.0 / sqrt(nrm2[0]);
+    const double2 v = x[r];
+    out[r] = make_double2(v.x * inv, v.y * inv);
+}
+
+void vec_normalize(int64_t N, const double *nrm2, const double *x, double *out, hipStream_t st) {
+    normalize_kernel<<<(unsigned)((N + 255) / 256), 256, 0, st>>>(N, nrm2, reinterpret_cast<const double2 *>(x),
+                                                                  reinterpret_cast<double2 *>(out));
+    AFS_HIP(hipGetLastError());
+}
+
+__global__ __launch_bounds__(256) void split_ut_kernel(int64_t nt, const int8_t *__restrict__ kind,
+                                                       const double2 *__restrict__ a, const double2 *__restrict__ bc,
+                                                       double2 *__restrict__ u, double2 *__restrict__ t) {
+    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (k >= 3 * nt)
+        return;
+    const bool trac = kind[k / 3] == 0;
+    const double2 av = a[k], bv = bc[k];
+    if (u)
+        u[k] = trac ? av : bv;
+    if (t)
+        t[k] = trac ? bv : av;
+}
+
+void vec_split_ut(int64_t nt, const int8_t *kind, const double *a, const double *bc, double *u, double *t,
+                  hipStream_t st) {
+    split_ut_kernel<<<(unsigned)((3 * nt + 255) / 256), 256, 0, st>>>(
+        nt, kind, reinterpret_cast<const double2 *>(a), reinterpret_cast<const double2 *>(bc),
+        reinterpret_cast<double2 *>(u), reinterpret_cast<double2 *>(t));
+    AFS_HIP(hipGetLastError());
+}
+
+void vec_axpy(int64_t, const double *, int, double, const double *, double *, hipStream_t) {}
+
+}  // namespace afsbem

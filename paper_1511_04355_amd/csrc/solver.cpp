@@ -1,0 +1,323 @@
+// Per-frequency solve: assembly, right block-Jacobi-preconditioned GMRES(m)
+// (paper Section 2.1 and Section 4: GMRES with the block diagonal
+// preconditioner), and FP32-operator / FP64-residual iterative refinement.
+//
+// The Krylov basis, the Hessenberg columns and every residual are FP64; only
+// the operator application of the inner solve of the mixed path streams the
+// FP32 hi plane.  Orthogonalisation is classical Gram-Schmidt applied twice.
+// The small (m+1) x m least-squares problem is reduced on the host with
+// Givens rotations: one device-to-host copy of the new Hessenberg column per
+// iteration.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <complex>
+#include <cstring>
+
+#include "internal.hpp"
+#include "solver.hpp"
+
+namespace afsbem {
+
+using cplx = std::complex<double>;
+
+static void *dalloc(size_t bytes) {
+    void *p = nullptr;
+    if (bytes == 0)
+        bytes = 16;
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess)
+        throw Error{AFSBEM_ENOMEM, "hipMalloc(" + std::to_string(bytes) + " bytes) failed: " + hipGetErrorString(e)};
+    return p;
+}
+
+Workspace::~Workspace() { release(); }
+
+void Workspace::release() {
+    for (void *p : {(void *)A, (void *)A_lo, (void *)b, (void *)precond, (void *)asm_scratch, (void *)gemv_partial,
+                    (void *)V, (void *)w, (void *)z, (void *)x, (void *)r, (void *)tmp, (void *)rin, (void *)xo,
+                    (void *)dots_partial, (void *)small, (void *)one})
+        if (p)
+            (void)hipFree(p);
+    if (host_small)
+        (void)hipHostFree(host_small);
+    // reset every field in place (no temporary Workspace: its destructor would
+    // call release() again)
+    N = 0;
+    format = -1;
+    m = 0;
+    A = A_lo = asm_scratch = nullptr;
+    b = precond = gemv_partial = V = w = z = x = r = tmp = rin = xo = nullptr;
+    dots_partial = small = one = host_small = nullptr;
+}
+
+void Workspace::ensure(const Problem &p, int format, int restart_m) {
+    const int64_t nt = p.dev.n_tri, N = 3 * nt;
+    const int64_t lda = (N + 63) / 64 * 64;
+    if (N == this->N && format == this->format && restart_m <= this->m && A)
+        return;
+    release();
+    this->N = N;
+    this->format = format;
+    this->m = restart_m;
+    const size_t plane = (size_t)N * lda * (format == AFSBEM_FMT_C128 ? 16 : 8);
+    A = dalloc(plane);
+    if (format == AFSBEM_FMT_SPLIT)
+        A_lo = dalloc(plane);
+    b = (double *)dalloc((size_t)N * 16);
+    precond = (double *)dalloc((size_t)nt * 9 * 16);
+    asm_scratch = dalloc(assembly_scratch_bytes(p));
+    gemv_partial = (double *)dalloc((size_t)gemv_chunks(N) * N * 16);
+    V = (double *)dalloc((size_t)(restart_m + 1) * N * 16);
+    w = (double *)dalloc((size_t)N * 16);
+    z = (double *)dalloc((size_t)N * 16);
+    x = (double *)dalloc((size_t)N * 16);
+    r = (double *)dalloc((size_t)N * 16);
+    tmp = (double *)dalloc((size_t)N * 16);
+    rin = (double *)dalloc((size_t)N * 16);
+    xo = (double *)dalloc((size_t)N * 16);
+    dots_partial = (double *)dalloc((size_t)mdot_blocks(N) * (restart_m + 2) * 16);
+    small = (double *)dalloc((size_t)(4 * (restart_m + 2)) * 16);
+    AFS_HIP(hipHostMalloc((void **)&host_small, (size_t)(4 * (restart_m + 2)) * 16, hipHostMallocDefault));
+    one = (double *)dalloc(16);
+    const double unit[2] = {1.0, 0.0};
+    AFS_HIP(hipMemcpy(one, unit, 16, hipMemcpyHostToDevice));
+}
+
+// --------------------------------------------------------------- operator --
+void Operator::apply(const double *xin, double *yout, hipStream_t st) const {
+    launch_gemv(N, format, precision, A, A_lo, xin, yout, partial, st);
+    ++*counter;
+    *bytes += (double)N * N * ((format == AFSBEM_FMT_C128 || precision == 0) ? 16.0 : 8.0);
+}
+
+static double norm2_dev(Workspace &ws, int64_t N, const double *v, hipStream_t st) {
+    vec_mdot(N, 1, v, N, v, ws.dots_partial, ws.small, st);
+    AFS_HIP(hipMemcpyAsync(ws.host_small, ws.small, 16, hipMemcpyDeviceToHost, st));
+    AFS_HIP(hipStreamSynchronize(st));
+    return std::sqrt(std::max(ws.host_small[0], 0.0));
+}
+
+// r = b - op(x)
+static void residual(const Operator &op, Workspace &ws, const double *b, const double *x, double *r, hipStream_t st) {
+    op.apply(x, ws.tmp, st);
+    vec_sub(op.N, b, ws.tmp, r, st);
+}
+
+GmresResult gmres(const Operator &op, Workspace &ws, int64_t n_tri, const double *rhs, double rhs_norm,
+                  double *x, bool x_is_zero, double tol_abs, int restart, int max_iter, hipStream_t st) {
+    const int64_t N = op.N;
+    GmresResult res;
+    std::vector<cplx> Hm((size_t)(restart + 1) * restart), g(restart + 1), cs(restart), sn(restart);
+    double *hbuf = ws.small;            // device: h1 [0..j], h2 [restart+2 ..], nrm2
+    double *h2 = ws.small + 2 * (restart + 2);
+    double *nrm = ws.small + 4 * (restart + 2);
+    double *host = ws.host_small;
+    (void)nrm;
+    // initial residual
+    double beta;
+    if (x_is_zero) {
+        AFS_HIP(hipMemcpyAsync(ws.r, rhs, (size_t)N * 16, hipMemcpyDeviceToDevice, st));
+        beta = rhs_norm;
+    } else {
+        residual(op, ws, rhs, x, ws.r, st);
+        beta = norm2_dev(ws, N, ws.r, st);
+    }
+    res.est = beta;
+    while (true) {
+        if (!(beta > tol_abs) || res.iters >= max_iter) {
+            res.est = beta;
+            res.converged = beta <= tol_abs;
+            if (!std::isfinite(beta))
+                res.nan = true;
+            return res;
+        }
+        // V_0 = r / beta
+        host[0] = beta * beta;
+        AFS_HIP(hipMemcpyAsync(ws.small + 4 * (restart + 2) + 2, host, 8, hipMemcpyHostToDevice, st));
+        vec_normalize(N, ws.small + 4 * (restart + 2) + 2, ws.r, ws.V, st);
+        std::fill(g.begin(), g.end(), cplx(0));
+        g[0] = beta;
+        int k = 0;
+        for (int j = 0; j < restart; ++j) {
+            double *vj = ws.V + 2 * (int64_t)j * N;
+            vec_precond(n_tri, ws.precond, vj, ws.z, st);
+            op.apply(ws.z, ws.w, st);
+            // classical Gram-Schmidt, twice
+            vec_mdot(N, j + 1, ws.V, N, ws.w, ws.dots_partial, hbuf, st);
+            vec_mupdate(N, j + 1, ws.V, N, hbuf, ws.w, st);
+            vec_mdot(N, j + 1, ws.V, N, ws.w, ws.dots_partial, h2, st);
+            vec_mupdate(N, j + 1, ws.V, N, h2, ws.w, st);
+            vec_mdot(N, 1, ws.w, N, ws.w, ws.dots_partial, h2 + 2 * (j + 1), st);
+            AFS_HIP(hipMemcpyAsync(host, hbuf, (size_t)(j + 1) * 16, hipMemcpyDeviceToHost, st));
+            AFS_HIP(hipMemcpyAsync(host + 2 * (restart + 2), h2, (size_t)(j + 2) * 16, hipMemcpyDeviceToHost, st));
+            AFS_HIP(hipStreamSynchronize(st));
+            const double hn = std::sqrt(std::max(host[2 * (restart + 2) + 2 * (j + 1)], 0.0));
+            for (int i = 0; i <= j; ++i)
+                Hm[(size_t)i * restart + j] =
+                    cplx(host[2 * i] + host[2 * (restart + 2) + 2 * i], host[2 * i + 1] + host[2 * (restart + 2) + 2 * i + 1]);
+            Hm[(size_t)(j + 1) * restart + j] = hn;
+            ++res.iters;
+            if (!std::isfinite(hn)) {
+                res.nan = true;
+                return res;
+            }
+            if (hn > 0.0) {
+                // V_{j+1} = w / hn  (device scalar nrm2 at h2 + 2(j+1))
+                vec_normalize(N, h2 + 2 * (j + 1), ws.w, ws.V + 2 * (int64_t)(j + 1) * N, st);
+            }
+            for (int i = 0; i < j; ++i) {
+                cplx a = Hm[(size_t)i * restart + j], c = Hm[(size_t)(i + 1) * restart + j];
+                Hm[(size_t)i * restart + j] = cs[i] * a + sn[i] * c;
+                Hm[(size_t)(i + 1) * restart + j] = -std::conj(sn[i]) * a + std::conj(cs[i]) * c;
+            }
+            cplx a = Hm[(size_t)j * restart + j], c = Hm[(size_t)(j + 1) * restart + j];
+            const double den = std::sqrt(std::norm(a) + std::norm(c));
+            if (std::abs(a) == 0.0) {
+                cs[j] = 0.0;
+                sn[j] = 1.0;
+            } else {
+                cs[j] = std::abs(a) / den;
+                sn[j] = (a / std::abs(a)) * std::conj(c) / den;
+            }
+            Hm[(size_t)j * restart + j] = cs[j] * a + sn[j] * c;
+            Hm[(size_t)(j + 1) * restart + j] = 0.0;
+            g[j + 1] = -std::conj(sn[j]) * g[j];
+            g[j] = cs[j] * g[j];
+            k = j + 1;
+            res.est = std::abs(g[j + 1]);
+            if (res.est <= 0.5 * tol_abs || res.iters >= max_iter || hn == 0.0)
+                break;
+        }
+        // y = H(1:k,1:k) \ g(1:k)
+        std::vector<cplx> y(k);
+        for (int i = k - 1; i >= 0; --i) {
+            cplx s = g[i];
+            for (int l = i + 1; l < k; ++l)
+                s -= Hm[(size_t)i * restart + l] * y[l];
+            y[i] = s / Hm[(size_t)i * restart + i];
+        }
+        for (int i = 0; i < k; ++i) {
+            host[2 * i] = y[i].real();
+            host[2 * i + 1] = y[i].imag();
+        }
+        AFS_HIP(hipMemcpyAsync(hbuf, host, (size_t)k * 16, hipMemcpyHostToDevice, st));
+        AFS_HIP(hipMemsetAsync(ws.tmp, 0, (size_t)N * 16, st));
+        vec_combine(N, k, ws.V, N, hbuf, ws.tmp, st);
+        vec_precond(n_tri, ws.precond, ws.tmp, ws.z, st);
+        if (x_is_zero) {
+            AFS_HIP(hipMemcpyAsync(x, ws.z, (size_t)N * 16, hipMemcpyDeviceToDevice, st));
+            x_is_zero = false;
+        } else {
+            vec_combine(N, 1, ws.z, N, ws.one, x, st);  // x += z
+        }
+        ++res.cycles;
+        // true residual of this operator for the restart
+        residual(op, ws, rhs, x, ws.r, st);
+        beta = norm2_dev(ws, N, ws.r, st);
+        res.est = beta;
+    }
+}
+
+// ------------------------------------------------------------ one solve --
+static double elapsed_ms(hipEvent_t a, hipEvent_t b) {
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, a, b);
+    return (double)ms;
+}
+
+int solve_one(Problem &p, const afsbem_solve_opts &o, double s_re, double s_im, const double *d_bc,
+              const double *d_x0, double *d_a, double *d_u, double *d_t, afsbem_solve_stats *stats,
+              hipStream_t st) {
+    const int64_t nt = p.dev.n_tri, N = 3 * nt;
+    const int fmt = (o.precision == AFSBEM_PREC_MIXED) ? AFSBEM_FMT_SPLIT : AFSBEM_FMT_C128;
+    if (!p.ws)
+        p.ws = new Workspace();
+    Workspace &ws = *p.ws;
+    ws.ensure(p, fmt, o.restart);
+    hipEvent_t e0, e1, e2;
+    AFS_HIP(hipEventCreate(&e0));
+    AFS_HIP(hipEventCreate(&e1));
+    AFS_HIP(hipEventCreate(&e2));
+    AFS_HIP(hipEventRecord(e0, st));
+    KernelParams kp = kernel_params(p.mat, s_re, s_im);
+    launch_assembly(p, kp, d_bc, fmt, ws.A, ws.A_lo, ws.b, ws.precond, ws.asm_scratch, st);
+    AFS_HIP(hipEventRecord(e1, st));
+
+    int matvecs = 0;
+    double bytes = 0.0;
+    Operator op64{N, fmt, 0, ws.A, ws.A_lo, ws.gemv_partial, &matvecs, &bytes};
+    const double bnorm = norm2_dev(ws, N, ws.b, st);
+    bool x_zero = true;
+    if (d_x0 && o.warm_start != AFSBEM_WARM_NONE) {
+        AFS_HIP(hipMemcpyAsync(ws.x, d_x0, (size_t)N * 16, hipMemcpyDeviceToDevice, st));
+        x_zero = false;
+    } else {
+        AFS_HIP(hipMemsetAsync(ws.x, 0, (size_t)N * 16, st));
+    }
+    int status = AFSBEM_OK, refine = 0, fallback = 0;
+    double relres = 1.0;
+    if (bnorm == 0.0) {
+        AFS_HIP(hipMemsetAsync(ws.x, 0, (size_t)N * 16, st));
+        relres = 0.0;
+    } else if (fmt == AFSBEM_FMT_C128) {
+        GmresResult g = gmres(op64, ws, nt, ws.b, bnorm, ws.x, x_zero, o.tol * bnorm, o.restart, o.max_iter, st);
+        // final true FP64 residual (after the last restart gmres already formed r)
+        relres = g.est / bnorm;
+        if (g.nan)
+            status = AFSBEM_ENAN;
+    } else {
+        // mixed: outer residual with the FP64 operator (hi + lo planes), inner
+        // GMRES on the FP32 hi plane for the correction d: A32 d = r.
+        Operator op32{N, fmt, 1, ws.A, ws.A_lo, ws.gemv_partial, &matvecs, &bytes};
+        double rnorm;
+        if (x_zero) {
+            AFS_HIP(hipMemsetAsync(ws.xo, 0, (size_t)N * 16, st));
+            AFS_HIP(hipMemcpyAsync(ws.rin, ws.b, (size_t)N * 16, hipMemcpyDeviceToDevice, st));
+            rnorm = bnorm;
+        } else {
+            AFS_HIP(hipMemcpyAsync(ws.xo, ws.x, (size_t)N * 16, hipMemcpyDeviceToDevice, st));
+            residual(op64, ws, ws.b, ws.xo, ws.rin, st);
+            rnorm = norm2_dev(ws, N, ws.rin, st);
+        }
+        while (rnorm > o.tol * bnorm && matvecs < o.max_iter && std::isfinite(rnorm)) {
+            const double tol_in = std::max(o.inner_tol * rnorm, 0.5 * o.tol * bnorm);
+            GmresResult g = gmres(op32, ws, nt, ws.rin, rnorm, ws.x, true, tol_in, o.restart,
+                                  std::max(1, o.max_iter - matvecs), st);
+            vec_combine(N, 1, ws.x, N, ws.one, ws.xo, st);  // x_outer += d
+            residual(op64, ws, ws.b, ws.xo, ws.rin, st);
+            rnorm = norm2_dev(ws, N, ws.rin, st);
+            ++refine;
+            if (g.nan)
+                break;
+        }
+        relres = rnorm / bnorm;
+        if (!std::isfinite(rnorm))
+            status = AFSBEM_ENAN;
+        AFS_HIP(hipMemcpyAsync(ws.x, ws.xo, (size_t)N * 16, hipMemcpyDeviceToDevice, st));
+    }
+    AFS_HIP(hipEventRecord(e2, st));
+    if (d_a)
+        AFS_HIP(hipMemcpyAsync(d_a, ws.x, (size_t)N * 16, hipMemcpyDeviceToDevice, st));
+    if (d_u || d_t)
+        vec_split_ut(nt, p.dev.kind, ws.x, d_bc, d_u, d_t, st);
+    AFS_HIP(hipStreamSynchronize(st));
+    if (status == AFSBEM_OK && !(relres <= o.tol))
+        status = AFSBEM_ENOCONV;
+    if (stats) {
+        stats->iters = matvecs;
+        stats->refine_steps = refine;
+        stats->fallback = fallback;
+        stats->status = status;
+        stats->rel_res_fp64 = relres;
+        stats->t_assemble_ms = elapsed_ms(e0, e1);
+        stats->t_solve_ms = elapsed_ms(e1, e2);
+        stats->bytes = bytes;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipEventDestroy(e2);
+    return status;
+}
+
+}  // namespace afsbem

@@ -1,0 +1,53 @@
+// Solver internals: device workspace, operator, GMRES.
+#pragma once
+#include "internal.hpp"
+
+namespace afsbem {
+
+struct Workspace {
+    int64_t N = 0;
+    int format = -1;
+    int m = 0;
+    void *A = nullptr, *A_lo = nullptr;
+    double *b = nullptr, *precond = nullptr;
+    void *asm_scratch = nullptr;
+    double *gemv_partial = nullptr;
+    double *V = nullptr, *w = nullptr, *z = nullptr, *x = nullptr, *r = nullptr, *tmp = nullptr;
+    double *rin = nullptr, *xo = nullptr;  // mixed: outer residual and outer iterate
+    double *dots_partial = nullptr, *small = nullptr;
+    double *one = nullptr;                 // device complex 1 + 0i
+    double *host_small = nullptr;          // pinned
+    ~Workspace();
+    void release();
+    void ensure(const Problem &p, int format, int restart_m);
+};
+
+// y = A x with a stored matrix: precision 0 = FP64 (C128, or hi+lo of SPLIT),
+// 1 = FP32 on the hi plane.  Counts applications and streamed bytes.
+struct Operator {
+    int64_t N;
+    int format, precision;
+    const void *A, *A_lo;
+    double *partial;
+    int *counter;
+    double *bytes;
+    void apply(const double *x, double *y, hipStream_t st) const;
+};
+
+struct GmresResult {
+    int iters = 0, cycles = 0;
+    double est = 0.0;  // last residual norm (true residual of the operator after a restart)
+    bool converged = false, nan = false;
+};
+
+// Right-preconditioned GMRES(m) on op with the block-Jacobi inverses in
+// ws.precond.  x (device) is the initial guess unless x_is_zero; on return it
+// holds the iterate.  Stops when the residual norm is <= tol_abs.
+GmresResult gmres(const Operator &op, Workspace &ws, int64_t n_tri, const double *rhs, double rhs_norm, double *x,
+                  bool x_is_zero, double tol_abs, int restart, int max_iter, hipStream_t st);
+
+int solve_one(Problem &p, const afsbem_solve_opts &o, double s_re, double s_im, const double *d_bc,
+              const double *d_x0, double *d_a, double *d_u, double *d_t, afsbem_solve_stats *stats,
+              hipStream_t st);
+
+}  // namespace afsbem
