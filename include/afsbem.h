@@ -21,7 +21,8 @@
  *  - Complex numbers are interleaved (re, im) doubles unless stated otherwise.
  *  - Element vectors are [n_tri][3] (x, y, z components), frequency-major for
  *    several frequencies: [n_s][n_tri][3].
- *  - Matrices on the device are column-major: entry (row, col) at col*N + row.
+ *  - Matrices on the device are column-major with leading dimension
+ *    lda = N rounded up to a multiple of 64: entry (row, col) at col*lda + row.
  *  - Handles are opaque and owned by the library; free them with *_destroy.
  *    Host arrays passed in are copied; the library never frees caller memory.
  *  - *_device entry points take device pointers allocated by the caller (for
@@ -109,7 +110,7 @@ enum { AFSBEM_FMT_C128 = 0, AFSBEM_FMT_SPLIT = 1 };
 
 /* Assembles A(s) and b(s) of Eq. 2 at one s on the device.
  * d_bc_val: [n_tri][3] complex<double>, the prescribed traction or displacement
- * at this s.  d_A (and d_A_lo for SPLIT) must hold N*N entries; d_b N complex
+ * at this s.  d_A (and d_A_lo for SPLIT) must hold N*lda entries; d_b N complex
  * doubles.  d_precond (nullable): [n_tri][3][3] complex<double> receives the
  * inverses of the 3x3 diagonal blocks (row-major per block). */
 int afsbem_assemble_device(afsbem_problem *p, double s_re, double s_im, const void *d_bc_val,
@@ -132,9 +133,11 @@ typedef struct {
     int32_t max_iter;    /* cap on matrix-vector products per frequency (1000) */
     int32_t precision;   /* AFSBEM_PREC_FP64 or AFSBEM_PREC_MIXED */
     int32_t warm_start;  /* AFSBEM_WARM_* */
-    double inner_tol;    /* mixed: relative reduction asked of each FP32 inner solve (1e-4) */
+    double inner_tol;    /* mixed: relative reduction asked of each FP32 inner solve; the target
+                            is max(inner_tol * ||r||, tol * ||b|| / 2) (default 0: aim at tol) */
     int32_t batch;       /* frequencies resident at once; 0 = as many as fit */
     uint32_t fault_inject; /* test hook bits, 0 in production */
+    int32_t profile;     /* 1: time every matrix-vector kernel with HIP events (stats.gemv_*) */
 } afsbem_solve_opts;
 
 typedef struct {
@@ -145,6 +148,11 @@ typedef struct {
     double rel_res_fp64;  /* final ||b - A x|| / ||b|| with the FP64 operator */
     double t_assemble_ms, t_solve_ms;
     double bytes;         /* algorithmic matrix bytes streamed */
+    /* with opts.profile: device time of the GEMV kernels (partial-sum pass
+     * excluded) of the Krylov operator (FP32 hi plane in the mixed path, FP64 in
+     * the plain path) and of the FP64 residual operator of the mixed path */
+    double gemv_ms, gemv64_ms;
+    int32_t gemv_count, gemv64_count;
 } afsbem_solve_stats;
 
 /* Fills opts with the defaults listed above. */

@@ -40,13 +40,14 @@ class _Policy(ctypes.Structure):
 class _Opts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("restart", ctypes.c_int32), ("max_iter", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("warm_start", ctypes.c_int32), ("inner_tol", ctypes.c_double),
-                ("batch", ctypes.c_int32), ("fault_inject", ctypes.c_uint32)]
+                ("batch", ctypes.c_int32), ("fault_inject", ctypes.c_uint32), ("profile", ctypes.c_int32)]
 
 
 class _Stats(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("refine_steps", ctypes.c_int32), ("fallback", ctypes.c_int32),
                 ("status", ctypes.c_int32), ("rel_res_fp64", ctypes.c_double), ("t_assemble_ms", ctypes.c_double),
-                ("t_solve_ms", ctypes.c_double), ("bytes", ctypes.c_double)]
+                ("t_solve_ms", ctypes.c_double), ("bytes", ctypes.c_double), ("gemv_ms", ctypes.c_double),
+                ("gemv64_ms", ctypes.c_double), ("gemv_count", ctypes.c_int32), ("gemv64_count", ctypes.c_int32)]
 
 
 def lib_path() -> str:
@@ -108,13 +109,14 @@ class SolveOptions:
     max_iter: int = 1000
     precision: int = PREC_FP64
     warm_start: int = WARM_NONE
-    inner_tol: float = 1e-4
+    inner_tol: float = 0.0
     batch: int = 0
     fault_inject: int = 0
+    profile: int = 0
 
     def _c(self):
         return _Opts(self.tol, self.restart, self.max_iter, self.precision, self.warm_start, self.inner_tol,
-                     self.batch, self.fault_inject)
+                     self.batch, self.fault_inject, self.profile)
 
 
 class Problem:

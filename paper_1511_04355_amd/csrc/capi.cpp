@@ -234,7 +234,7 @@ int afsbem_solve_opts_default(afsbem_solve_opts *o) {
     o->max_iter = 1000;
     o->precision = AFSBEM_PREC_FP64;
     o->warm_start = AFSBEM_WARM_NONE;
-    o->inner_tol = 1e-4;
+    o->inner_tol = 0.0;
     o->batch = 0;
     o->fault_inject = 0;
     return AFSBEM_OK;

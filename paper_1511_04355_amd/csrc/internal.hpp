@@ -128,7 +128,8 @@ void launch_assembly(const Problem &p, const KernelParams &kp, const double *bc_
 // gemv_chunks(N) * N complex doubles.
 int gemv_chunks(int64_t N);
 void launch_gemv(int64_t N, int format, int precision, const void *A, const void *A_lo,
-                 const double *x, double *y, double *partial, hipStream_t st);
+                 const double *x, double *y, double *partial, hipStream_t st,
+                 hipEvent_t ev_begin = nullptr, hipEvent_t ev_end = nullptr);
 
 // ------------------------------------------------------ vector kernels --
 // All vectors are complex<double> interleaved, length N (complex entries).

@@ -79,7 +79,7 @@ __device__ __forceinline__ Radial radial64(cd x, double beta, const double *__re
 // and U_ij = (1/(4 pi mu r)) [Psi d_ij - X rh_i rh_j].
 struct PairEval {
     double rh[3];
-    double r, rn;
+    double r, ir, rn;
     cd Psi, X;             // U coefficients (without 1/(4 pi mu r))
     cd t0, t1, t2, t3;     // T coefficients (without 1/(4 pi r^2))
 };
@@ -92,6 +92,7 @@ __device__ __forceinline__ void eval_pair(const KernelParams &kp, const double *
     const double r = sqrt(r2);
     const double ir = 1.0 / r;
     E.r = r;
+    E.ir = ir;
     E.rh[0] = dx * ir;
     E.rh[1] = dy * ir;
     E.rh[2] = dz * ir;
@@ -115,7 +116,7 @@ constexpr double kInv4Pi = 0.079577471545947667884;  // 1 / (4 pi)
 __device__ __forceinline__ void acc_T(const PairEval &E, double nx, double ny, double nz, double w,
                                       cd blk[9]) {
     const double n[3] = {nx, ny, nz};
-    const double f = w * kInv4Pi / (E.r * E.r);
+    const double f = w * kInv4Pi * E.ir * E.ir;
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
@@ -129,7 +130,7 @@ __device__ __forceinline__ void acc_T(const PairEval &E, double nx, double ny, d
 }
 
 __device__ __forceinline__ void acc_U(const PairEval &E, const KernelParams &kp, double w, cd blk[9]) {
-    const double f = w * kp.c_u / E.r;
+    const double f = w * kp.c_u * E.ir;
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
@@ -145,7 +146,7 @@ __device__ __forceinline__ void acc_U(const PairEval &E, const KernelParams &kp,
 __device__ __forceinline__ void acc_Tv(const PairEval &E, double nx, double ny, double nz, double w,
                                        const cd v[3], cd acc[3]) {
     const double n[3] = {nx, ny, nz};
-    const double f = w * kInv4Pi / (E.r * E.r);
+    const double f = w * kInv4Pi * E.ir * E.ir;
     const cd rv = cadd(cadd(cscale(v[0], E.rh[0]), cscale(v[1], E.rh[1])), cscale(v[2], E.rh[2]));
     const cd nv = cadd(cadd(cscale(v[0], nx), cscale(v[1], ny)), cscale(v[2], nz));
     const cd a1 = cmul(E.t1, rv), a2 = cmul(E.t2, nv), a3 = cmul(E.t3, rv);
@@ -159,7 +160,7 @@ __device__ __forceinline__ void acc_Tv(const PairEval &E, double nx, double ny, 
 // acc += w * U . v
 __device__ __forceinline__ void acc_Uv(const PairEval &E, const KernelParams &kp, double w, const cd v[3],
                                        cd acc[3]) {
-    const double f = w * kp.c_u / E.r;
+    const double f = w * kp.c_u * E.ir;
     const cd rv = cadd(cadd(cscale(v[0], E.rh[0]), cscale(v[1], E.rh[1])), cscale(v[2], E.rh[2]));
     const cd xr = cmul(E.X, rv);
 #pragma unroll
@@ -190,6 +191,83 @@ __device__ __forceinline__ void store_block(void *A, void *A_lo, int64_t lda, in
 }
 
 // ---------------------------------------------------------------- far field --
+// Per (collocation point, source element) the 3x3 traction block is
+//   sum_q f_q [t0 d_ij + t1 n_i rh_j + t2 rh_i n_j + t3 rh_i rh_j],  f_q = w_q/(4 pi r_q^2),
+// and n is constant over the element, so it is accumulated as the invariants
+//   E = sum f t0,  Aj = sum f t1 rh_j,  Ci = sum f t2 rh_i,  Dij = sum f t3 rh_i rh_j (symmetric)
+// and expanded to T_ij = E d_ij + n_i Aj + Ci n_j + Dij once per pair.  The
+// displacement block likewise from E = sum g Psi, Dij = sum g X rh_i rh_j,
+// g_q = w_q / (4 pi mu r_q):  U_ij = E d_ij - Dij.
+struct BlockAcc {
+    cd E, Aj[3], Ci[3], D[6];  // D: xx, yy, zz, xy, xz, yz
+    __device__ __forceinline__ void zero() {
+        E = cd{0, 0};
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+            Aj[k] = Ci[k] = cd{0, 0};
+#pragma unroll
+        for (int k = 0; k < 6; ++k)
+            D[k] = cd{0, 0};
+    }
+};
+
+__device__ __forceinline__ int sym_idx(int i, int j) {
+    return (i == j) ? i : ((i + j == 1) ? 3 : ((i + j == 2) ? 4 : 5));
+}
+
+__device__ __forceinline__ void acc_sym(cd D[6], cd c, const double rh[3]) {
+    D[0] = cadd(D[0], cscale(c, rh[0] * rh[0]));
+    D[1] = cadd(D[1], cscale(c, rh[1] * rh[1]));
+    D[2] = cadd(D[2], cscale(c, rh[2] * rh[2]));
+    D[3] = cadd(D[3], cscale(c, rh[0] * rh[1]));
+    D[4] = cadd(D[4], cscale(c, rh[0] * rh[2]));
+    D[5] = cadd(D[5], cscale(c, rh[1] * rh[2]));
+}
+
+// One quadrature node.  kind 0 (traction known): the block collects T with
+// weight wA and b collects U.v with weight wB; kind 1 (displacement known): the
+// block collects U with weight wA (negated at expansion) and b collects -T.v.
+template <int KIND>
+__device__ __forceinline__ void acc_node(const PairEval &E, const KernelParams &kp, double nx, double ny,
+                                         double nz, double wA, double wB, const cd v[3], BlockAcc &acc,
+                                         cd bacc[3]) {
+    if (KIND == 0) {
+        const double f = wA * kInv4Pi * E.ir * E.ir;
+        acc.E = cadd(acc.E, cscale(E.t0, f));
+        const cd ft1 = cscale(E.t1, f), ft2 = cscale(E.t2, f);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            acc.Aj[k] = cadd(acc.Aj[k], cscale(ft1, E.rh[k]));
+            acc.Ci[k] = cadd(acc.Ci[k], cscale(ft2, E.rh[k]));
+        }
+        acc_sym(acc.D, cscale(E.t3, f), E.rh);
+        acc_Uv(E, kp, wB, v, bacc);
+    } else {
+        const double g = wA * kp.c_u * E.ir;
+        acc.E = cadd(acc.E, cscale(E.Psi, g));
+        acc_sym(acc.D, cscale(E.X, g), E.rh);
+        acc_Tv(E, nx, ny, nz, -wB, v, bacc);
+    }
+}
+
+// A-matrix block: T (kind 0) or -U (kind 1)
+__device__ __forceinline__ void expand_block(int kind, const BlockAcc &acc, double nx, double ny, double nz,
+                                             cd blk[9]) {
+    const double nn[3] = {nx, ny, nz};
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            const cd d = acc.D[sym_idx(i, j)];
+            if (kind == 0) {
+                const cd e = cadd(cadd(cscale(acc.Aj[j], nn[i]), cscale(acc.Ci[i], nn[j])), d);
+                blk[3 * i + j] = (i == j) ? cadd(e, acc.E) : e;
+            } else {
+                blk[3 * i + j] = (i == j) ? csub(d, acc.E) : d;
+            }
+        }
+}
+
 template <int FMT>
 __global__ __launch_bounds__(256) void far_assemble_kernel(
     int64_t nt, int64_t lda, KernelParams kp, const double *__restrict__ colx, const double *__restrict__ coly,
@@ -215,23 +293,27 @@ __global__ __launch_bounds__(256) void far_assemble_kernel(
         const cd v[3] = {cd{bv[0], bv[1]}, cd{bv[2], bv[3]}, cd{bv[4], bv[5]}};
         if (!active || m == n)
             continue;
-        cd blk[9];
-#pragma unroll
-        for (int e = 0; e < 9; ++e)
-            blk[e] = cd{0, 0};
-#pragma unroll
-        for (int q = 0; q < kFarNodes; ++q) {
-            PairEval E;
-            eval_pair(kp, coef, xx, xy, xz, rec[4 * q], rec[4 * q + 1], rec[4 * q + 2], nx, ny, nz, E);
-            const double w = rec[4 * q + 3];
-            if (kind == 0) {
-                acc_T(E, nx, ny, nz, w, blk);
-                acc_Uv(E, kp, w, v, bacc);
-            } else {
-                acc_U(E, kp, -w, blk);
-                acc_Tv(E, nx, ny, nz, -w, v, bacc);
+        BlockAcc acc;
+        acc.zero();
+        if (kind == 0) {
+#pragma unroll 1
+            for (int q = 0; q < kFarNodes; ++q) {
+                PairEval E;
+                eval_pair(kp, coef, xx, xy, xz, rec[4 * q], rec[4 * q + 1], rec[4 * q + 2], nx, ny, nz, E);
+                const double w = rec[4 * q + 3];
+                acc_node<0>(E, kp, nx, ny, nz, w, w, v, acc, bacc);
+            }
+        } else {
+#pragma unroll 1
+            for (int q = 0; q < kFarNodes; ++q) {
+                PairEval E;
+                eval_pair(kp, coef, xx, xy, xz, rec[4 * q], rec[4 * q + 1], rec[4 * q + 2], nx, ny, nz, E);
+                const double w = rec[4 * q + 3];
+                acc_node<1>(E, kp, nx, ny, nz, w, w, v, acc, bacc);
             }
         }
+        cd blk[9];
+        expand_block(kind, acc, nx, ny, nz, blk);
         store_block<FMT>(A, A_lo, lda, m, n, blk);
     }
     if (active) {
@@ -249,6 +331,41 @@ __device__ __forceinline__ double wave_sum(double v) {
     for (int off = 32; off > 0; off >>= 1)
         v += __shfl_xor(v, off, 64);
     return v;
+}
+
+// Lane-strided walk over the subdivision-leaf nodes of one near pair, plus the
+// 7 far-rule nodes whose contribution to b is removed again.
+template <int KIND>
+__device__ __forceinline__ void near_items(int lane, int64_t items, int64_t n_near, int64_t L0,
+                                           const double *__restrict__ leaves, const Rule7Args &rule,
+                                           const double *__restrict__ rec, const KernelParams &kp,
+                                           const double *__restrict__ coef, double xx, double xy, double xz,
+                                           double nx, double ny, double nz, const cd v[3], BlockAcc &acc,
+                                           cd bcor[3]) {
+    for (int64_t k = lane; k < items; k += 64) {
+        double yx, yy, yz, w, sA, sB;
+        if (k < n_near) {
+            const double *L = leaves + 10 * (L0 + k / 7);
+            const int q = (int)(k % 7);
+            yx = L[0] + rule.b1[q] * L[3] + rule.b2[q] * L[6];
+            yy = L[1] + rule.b1[q] * L[4] + rule.b2[q] * L[7];
+            yz = L[2] + rule.b1[q] * L[5] + rule.b2[q] * L[8];
+            w = rule.w[q] * L[9];
+            sA = 1.0;
+            sB = 1.0;
+        } else {
+            const int q = (int)(k - n_near);
+            yx = rec[4 * q];
+            yy = rec[4 * q + 1];
+            yz = rec[4 * q + 2];
+            w = rec[4 * q + 3];
+            sA = 0.0;
+            sB = -1.0;
+        }
+        PairEval E;
+        eval_pair(kp, coef, xx, xy, xz, yx, yy, yz, nx, ny, nz, E);
+        acc_node<KIND>(E, kp, nx, ny, nz, sA * w, sB * w, v, acc, bcor);
+    }
 }
 
 // ---------------------------------------------------------------- near pairs --
@@ -273,50 +390,31 @@ __global__ __launch_bounds__(256) void near_assemble_kernel(
     const int64_t L0 = leaf_ptr[p], L1 = leaf_ptr[p + 1];
     const int64_t n_near = 7 * (L1 - L0);
     const int64_t items = n_near + kFarNodes;
-    cd blk[9], bcor[3] = {cd{0, 0}, cd{0, 0}, cd{0, 0}};
-#pragma unroll
-    for (int e = 0; e < 9; ++e)
-        blk[e] = cd{0, 0};
-    for (int64_t k = lane; k < items; k += 64) {
-        double yx, yy, yz, w, sA, sB;
-        if (k < n_near) {
-            const double *L = leaves + 10 * (L0 + k / 7);
-            const int q = (int)(k % 7);
-            yx = L[0] + rule.b1[q] * L[3] + rule.b2[q] * L[6];
-            yy = L[1] + rule.b1[q] * L[4] + rule.b2[q] * L[7];
-            yz = L[2] + rule.b1[q] * L[5] + rule.b2[q] * L[8];
-            w = rule.w[q] * L[9];
-            sA = 1.0;
-            sB = 1.0;
-        } else {
-            const int q = (int)(k - n_near);
-            yx = rec[4 * q];
-            yy = rec[4 * q + 1];
-            yz = rec[4 * q + 2];
-            w = rec[4 * q + 3];
-            sA = 0.0;
-            sB = -1.0;  // remove the far-rule contribution the far kernel put into b
-        }
-        PairEval E;
-        eval_pair(kp, coef, xx, xy, xz, yx, yy, yz, nx, ny, nz, E);
-        if (kind == 0) {
-            acc_T(E, nx, ny, nz, sA * w, blk);
-            acc_Uv(E, kp, sB * w, v, bcor);
-        } else {
-            acc_U(E, kp, -sA * w, blk);
-            acc_Tv(E, nx, ny, nz, -sB * w, v, bcor);
-        }
-    }
-#pragma unroll
-    for (int e = 0; e < 9; ++e) {
-        blk[e].r = wave_sum(blk[e].r);
-        blk[e].i = wave_sum(blk[e].i);
-    }
+    BlockAcc acc;
+    acc.zero();
+    cd bcor[3] = {cd{0, 0}, cd{0, 0}, cd{0, 0}};
+    if (kind == 0)
+        near_items<0>(lane, items, n_near, L0, leaves, rule, rec, kp, coef, xx, xy, xz, nx, ny, nz, v, acc, bcor);
+    else
+        near_items<1>(lane, items, n_near, L0, leaves, rule, rec, kp, coef, xx, xy, xz, nx, ny, nz, v, acc, bcor);
+    acc.E.r = wave_sum(acc.E.r);
+    acc.E.i = wave_sum(acc.E.i);
 #pragma unroll
     for (int e = 0; e < 3; ++e) {
+        acc.Aj[e].r = wave_sum(acc.Aj[e].r);
+        acc.Aj[e].i = wave_sum(acc.Aj[e].i);
+        acc.Ci[e].r = wave_sum(acc.Ci[e].r);
+        acc.Ci[e].i = wave_sum(acc.Ci[e].i);
         bcor[e].r = wave_sum(bcor[e].r);
         bcor[e].i = wave_sum(bcor[e].i);
     }
+#pragma unroll
+    for (int e = 0; e < 6; ++e) {
+        acc.D[e].r = wave_sum(acc.D[e].r);
+        acc.D[e].i = wave_sum(acc.D[e].i);
+    }
+    cd blk[9];
+    expand_block(kind, acc, nx, ny, nz, blk);
     if (lane == 0) {
         store_block<FMT>(A, A_lo, lda, m, n, blk);
 #pragma unroll

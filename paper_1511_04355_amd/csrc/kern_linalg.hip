@@ -206,13 +206,15 @@ int gemv_chunks(int64_t N) {
 }
 
 void launch_gemv(int64_t N, int format, int precision, const void *A, const void *A_lo, const double *x, double *y,
-                 double *partial, hipStream_t st) {
+                 double *partial, hipStream_t st, hipEvent_t ev_begin, hipEvent_t ev_end) {
     const int64_t lda = (N + 63) / 64 * 64;
     const int S = gemv_chunks(N);
     const int64_t chunk = (N + S - 1) / S;
     const int Su = (int)((N + chunk - 1) / chunk);
     double2 *part = reinterpret_cast<double2 *>(partial);
     const double2 *xv = reinterpret_cast<const double2 *>(x);
+    if (ev_begin)
+        AFS_HIP(hipEventRecord(ev_begin, st));
     if (format == AFSBEM_FMT_C128) {
         dim3 g((unsigned)((N + 255) / 256), (unsigned)Su);
         gemv_c128_kernel<<<g, 256, 0, st>>>(N, lda, static_cast<const double2 *>(A), xv, chunk, part);
@@ -225,6 +227,8 @@ void launch_gemv(int64_t N, int format, int precision, const void *A, const void
                                                static_cast<const float4 *>(A_lo), xv, chunk, part);
     }
     AFS_HIP(hipGetLastError());
+    if (ev_end)
+        AFS_HIP(hipEventRecord(ev_end, st));
     sum_partials_kernel<<<(unsigned)((N + 255) / 256), 256, 0, st>>>(N, Su, part, reinterpret_cast<double2 *>(y));
     AFS_HIP(hipGetLastError());
 }

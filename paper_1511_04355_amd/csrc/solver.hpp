@@ -17,6 +17,11 @@ struct Workspace {
     double *dots_partial = nullptr, *small = nullptr;
     double *one = nullptr;                 // device complex 1 + 0i
     double *host_small = nullptr;          // pinned
+    // GEMV timing (opts.profile): event pairs recorded around each product
+    std::vector<hipEvent_t> ev;            // 2 per slot
+    std::vector<int> ev_prec;              // precision of the product in each used slot
+    int ev_used = 0;
+    void reset_timing() { ev_used = 0; ev_prec.clear(); }
     ~Workspace();
     void release();
     void ensure(const Problem &p, int format, int restart_m);
@@ -31,6 +36,7 @@ struct Operator {
     double *partial;
     int *counter;
     double *bytes;
+    Workspace *prof = nullptr;             // non-null: record GEMV events
     void apply(const double *x, double *y, hipStream_t st) const;
 };
 
@@ -42,9 +48,11 @@ struct GmresResult {
 
 // Right-preconditioned GMRES(m) on op with the block-Jacobi inverses in
 // ws.precond.  x (device) is the initial guess unless x_is_zero; on return it
-// holds the iterate.  Stops when the residual norm is <= tol_abs.
+// holds the iterate.  Stops when the residual norm is <= tol_abs.  With
+// verify = false a cycle whose Arnoldi estimate meets the tolerance returns
+// without forming the true residual of op (an outer loop judges it).
 GmresResult gmres(const Operator &op, Workspace &ws, int64_t n_tri, const double *rhs, double rhs_norm, double *x,
-                  bool x_is_zero, double tol_abs, int restart, int max_iter, hipStream_t st);
+                  bool x_is_zero, double tol_abs, int restart, int max_iter, hipStream_t st, bool verify);
 
 int solve_one(Problem &p, const afsbem_solve_opts &o, double s_re, double s_im, const double *d_bc,
               const double *d_x0, double *d_a, double *d_u, double *d_t, afsbem_solve_stats *stats,
