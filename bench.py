@@ -42,6 +42,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain FP64 path")
     ap.add_argument("--cpu-freqs", type=int, default=1)
+    ap.add_argument("--warm", choices=["none", "prev"], default="prev",
+                    help="initial guess of the optimised path")
     return ap.parse_args()
 
 
@@ -96,7 +98,8 @@ def main():
     plan_s = time.perf_counter() - t0
     N = P.N
 
-    mixed = afs.SolveOptions(tol=args.tol, precision=afs.PREC_MIXED, warm_start=afs.WARM_PREV, profile=1)
+    warm = afs.WARM_PREV if args.warm == "prev" else afs.WARM_NONE
+    mixed = afs.SolveOptions(tol=args.tol, precision=afs.PREC_MIXED, warm_start=warm, profile=1)
     ms_mixed, out = timed(P, s, bc, mixed, args.steps, args.warmup, torch)
     st = out["stats"]
     worst = max(x["rel_res_fp64"] for x in st)
@@ -124,7 +127,8 @@ def main():
         "config": {"workload": f"pressurised spherical cavity, icosphere level {args.level} "
                                f"({P.n_tri} triangles, {N} complex unknowns), {args.nfreq} frequencies "
                                f"s_k=0.25+ik*pi/20, FP64 true rel. residual <= {args.tol}",
-                   "path": "mixed: FP32 hi-plane GMRES(50) + FP64 refinement, previous-s warm start",
+                   "path": "mixed: FP32 hi-plane GMRES(50) + FP64 refinement, "
+                           + ("previous-s warm start" if args.warm == "prev" else "zero start"),
                    "plan_s": plan_s},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,

@@ -135,8 +135,9 @@ void launch_gemv(int64_t N, int format, int precision, const void *A, const void
 // All vectors are complex<double> interleaved, length N (complex entries).
 void vec_precond(int64_t n_tri, const double *Dinv, const double *v, double *z, hipStream_t st);
 void vec_sub(int64_t N, const double *a, const double *b, double *out, hipStream_t st);   // out = a - b
-void vec_axpy(int64_t N, const double *alpha_dev, int idx, double sign, const double *x, double *y,
-              hipStream_t st);
+// out = alpha x + beta y (complex scalars passed by value; out may alias)
+void vec_axpby(int64_t N, double ar, double ai, const double *x, double br, double bi, const double *y, double *out,
+               hipStream_t st);
 // Multi-dot: out[i] = sum_r conj(V_i[r]) w[r], i < nv; V rows strided by ldv.
 void vec_mdot(int64_t N, int nv, const double *V, int64_t ldv, const double *w, double *partial,
               double *out, hipStream_t st);

@@ -336,13 +336,13 @@ __device__ __forceinline__ double wave_sum(double v) {
 // Lane-strided walk over the subdivision-leaf nodes of one near pair, plus the
 // 7 far-rule nodes whose contribution to b is removed again.
 template <int KIND>
-__device__ __forceinline__ void near_items(int lane, int64_t items, int64_t n_near, int64_t L0,
+__device__ __forceinline__ void near_items(int64_t first, int64_t stride, int64_t items, int64_t n_near, int64_t L0,
                                            const double *__restrict__ leaves, const Rule7Args &rule,
                                            const double *__restrict__ rec, const KernelParams &kp,
                                            const double *__restrict__ coef, double xx, double xy, double xz,
                                            double nx, double ny, double nz, const cd v[3], BlockAcc &acc,
                                            cd bcor[3]) {
-    for (int64_t k = lane; k < items; k += 64) {
+    for (int64_t k = first; k < items; k += stride) {
         double yx, yy, yz, w, sA, sB;
         if (k < n_near) {
             const double *L = leaves + 10 * (L0 + k / 7);
@@ -369,6 +369,19 @@ __device__ __forceinline__ void near_items(int lane, int64_t items, int64_t n_ne
 }
 
 // ---------------------------------------------------------------- near pairs --
+// kNearLanes lanes per near pair (8 pairs per wavefront): the lanes of a group
+// stride over the pair's subdivision-leaf nodes (about 8 leaves, 60 nodes on
+// average) and combine the 32 accumulated doubles in log2(kNearLanes) shuffle
+// steps; neighbouring groups hold neighbouring pairs.
+constexpr int kNearLanes = 8;
+
+__device__ __forceinline__ double group_sum(double v) {
+#pragma unroll
+    for (int off = kNearLanes / 2; off > 0; off >>= 1)
+        v += __shfl_xor(v, off, 64);
+    return v;
+}
+
 template <int FMT>
 __global__ __launch_bounds__(256) void near_assemble_kernel(
     int64_t nt, int64_t lda, int64_t nnz, KernelParams kp, Rule7Args rule, const double *__restrict__ colx,
@@ -376,8 +389,10 @@ __global__ __launch_bounds__(256) void near_assemble_kernel(
     const double *__restrict__ bc, const double *__restrict__ coef, const int32_t *__restrict__ near_row,
     const int32_t *__restrict__ near_col, const int64_t *__restrict__ leaf_ptr,
     const double *__restrict__ leaves, void *A, void *A_lo, double *__restrict__ corr) {
-    const int64_t p = ((int64_t)blockIdx.x * 256 + threadIdx.x) >> 6;
-    const int lane = threadIdx.x & 63;
+    const int64_t gid = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t p = gid / kNearLanes;
+    const int sub = (int)(gid % kNearLanes);
+    // groups are aligned inside a wavefront, so a whole group is in or out
     if (p >= nnz)
         return;
     const int64_t m = near_row[p], n = near_col[p];
@@ -394,34 +409,36 @@ __global__ __launch_bounds__(256) void near_assemble_kernel(
     acc.zero();
     cd bcor[3] = {cd{0, 0}, cd{0, 0}, cd{0, 0}};
     if (kind == 0)
-        near_items<0>(lane, items, n_near, L0, leaves, rule, rec, kp, coef, xx, xy, xz, nx, ny, nz, v, acc, bcor);
+        near_items<0>(sub, kNearLanes, items, n_near, L0, leaves, rule, rec, kp, coef, xx, xy, xz, nx, ny, nz, v,
+                      acc, bcor);
     else
-        near_items<1>(lane, items, n_near, L0, leaves, rule, rec, kp, coef, xx, xy, xz, nx, ny, nz, v, acc, bcor);
-    acc.E.r = wave_sum(acc.E.r);
-    acc.E.i = wave_sum(acc.E.i);
+        near_items<1>(sub, kNearLanes, items, n_near, L0, leaves, rule, rec, kp, coef, xx, xy, xz, nx, ny, nz, v,
+                      acc, bcor);
+    acc.E.r = group_sum(acc.E.r);
+    acc.E.i = group_sum(acc.E.i);
 #pragma unroll
     for (int e = 0; e < 3; ++e) {
-        acc.Aj[e].r = wave_sum(acc.Aj[e].r);
-        acc.Aj[e].i = wave_sum(acc.Aj[e].i);
-        acc.Ci[e].r = wave_sum(acc.Ci[e].r);
-        acc.Ci[e].i = wave_sum(acc.Ci[e].i);
-        bcor[e].r = wave_sum(bcor[e].r);
-        bcor[e].i = wave_sum(bcor[e].i);
+        acc.Aj[e].r = group_sum(acc.Aj[e].r);
+        acc.Aj[e].i = group_sum(acc.Aj[e].i);
+        acc.Ci[e].r = group_sum(acc.Ci[e].r);
+        acc.Ci[e].i = group_sum(acc.Ci[e].i);
+        bcor[e].r = group_sum(bcor[e].r);
+        bcor[e].i = group_sum(bcor[e].i);
     }
 #pragma unroll
     for (int e = 0; e < 6; ++e) {
-        acc.D[e].r = wave_sum(acc.D[e].r);
-        acc.D[e].i = wave_sum(acc.D[e].i);
+        acc.D[e].r = group_sum(acc.D[e].r);
+        acc.D[e].i = group_sum(acc.D[e].i);
     }
+    if (sub != 0)
+        return;
     cd blk[9];
     expand_block(kind, acc, nx, ny, nz, blk);
-    if (lane == 0) {
-        store_block<FMT>(A, A_lo, lda, m, n, blk);
+    store_block<FMT>(A, A_lo, lda, m, n, blk);
 #pragma unroll
-        for (int e = 0; e < 3; ++e) {
-            corr[6 * p + 2 * e] = bcor[e].r;
-            corr[6 * p + 2 * e + 1] = bcor[e].i;
-        }
+    for (int e = 0; e < 3; ++e) {
+        corr[6 * p + 2 * e] = bcor[e].r;
+        corr[6 * p + 2 * e + 1] = bcor[e].i;
     }
 }
 
@@ -611,7 +628,7 @@ void launch_assembly(const Problem &p, const KernelParams &kp, const double *bc_
     double *corr = bself + 6 * nt;
     const double *coef = d.coef;
     dim3 gfar((unsigned)((nt + 255) / 256), (unsigned)Sused);
-    const unsigned gnear = (unsigned)((d.nnz * 64 + 255) / 256);
+    const unsigned gnear = (unsigned)((d.nnz * kNearLanes + 255) / 256);
     const unsigned gself = (unsigned)((nt * 64 + 255) / 256);
     const Rule7Args rule = rule7_args();
     if (format == AFSBEM_FMT_C128) {

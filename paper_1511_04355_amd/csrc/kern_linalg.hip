@@ -415,6 +415,22 @@ void vec_split_ut(int64_t nt, const int8_t *kind, const double *a, const double 
     AFS_HIP(hipGetLastError());
 }
 
-void vec_axpy(int64_t, const double *, int, double, const double *, double *, hipStream_t) {}
+// out = alpha x + beta y  (complex scalars; out may alias x or y)
+__global__ __launch_bounds__(256) void axpby_kernel(int64_t N, double ar, double ai, const double2 *x, double br,
+                                                    double bi, const double2 *y, double2 *out) {
+    const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (r >= N)
+        return;
+    const double2 a = x[r], b = y[r];
+    out[r] = make_double2(ar * a.x - ai * a.y + br * b.x - bi * b.y, ar * a.y + ai * a.x + br * b.y + bi * b.x);
+}
+
+void vec_axpby(int64_t N, double ar, double ai, const double *x, double br, double bi, const double *y, double *out,
+               hipStream_t st) {
+    axpby_kernel<<<(unsigned)((N + 255) / 256), 256, 0, st>>>(N, ar, ai, reinterpret_cast<const double2 *>(x), br, bi,
+                                                              reinterpret_cast<const double2 *>(y),
+                                                              reinterpret_cast<double2 *>(out));
+    AFS_HIP(hipGetLastError());
+}
 
 }  // namespace afsbem

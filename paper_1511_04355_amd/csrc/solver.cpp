@@ -127,7 +127,7 @@ static void residual(const Operator &op, Workspace &ws, const double *b, const d
 
 GmresResult gmres(const Operator &op, Workspace &ws, int64_t n_tri, const double *rhs, double rhs_norm,
                   double *x, bool x_is_zero, double tol_abs, int restart, int max_iter, hipStream_t st,
-                  bool verify) {
+                  bool verify, const double *r0, double r0_norm) {
     const int64_t N = op.N;
     GmresResult res;
     std::vector<cplx> Hm((size_t)(restart + 1) * restart), g(restart + 1), cs(restart), sn(restart);
@@ -141,11 +141,17 @@ GmresResult gmres(const Operator &op, Workspace &ws, int64_t n_tri, const double
     if (x_is_zero) {
         AFS_HIP(hipMemcpyAsync(ws.r, rhs, (size_t)N * 16, hipMemcpyDeviceToDevice, st));
         beta = rhs_norm;
+    } else if (r0) {
+        if (r0 != ws.r)
+            AFS_HIP(hipMemcpyAsync(ws.r, r0, (size_t)N * 16, hipMemcpyDeviceToDevice, st));
+        beta = r0_norm;
     } else {
         residual(op, ws, rhs, x, ws.r, st);
         beta = norm2_dev(ws, N, ws.r, st);
     }
     res.est = beta;
+    if (x_is_zero && (!(beta > tol_abs) || res.iters >= max_iter))
+        AFS_HIP(hipMemsetAsync(x, 0, (size_t)N * 16, st));  // leave a valid (zero) iterate
     while (true) {
         if (!(beta > tol_abs) || res.iters >= max_iter) {
             res.est = beta;
@@ -246,6 +252,26 @@ GmresResult gmres(const Operator &op, Workspace &ws, int64_t n_tri, const double
     }
 }
 
+// Residual-optimal scaling of a warm start: y = op(x0), alpha = y^H b / y^H y,
+// x = alpha x0, r = b - alpha y.  Returns ||r||.  The scaling absorbs the
+// change of load amplitude and phase between neighbouring frequencies at no
+// extra operator application.
+static double scaled_start(const Operator &op, Workspace &ws, const double *b, const double *x0, double *x, double *r,
+                           hipStream_t st) {
+    const int64_t N = op.N;
+    op.apply(x0, ws.tmp, st);
+    vec_mdot(N, 1, ws.tmp, N, b, ws.dots_partial, ws.small, st);
+    vec_mdot(N, 1, ws.tmp, N, ws.tmp, ws.dots_partial, ws.small + 2, st);
+    AFS_HIP(hipMemcpyAsync(ws.host_small, ws.small, 32, hipMemcpyDeviceToHost, st));
+    AFS_HIP(hipStreamSynchronize(st));
+    const std::complex<double> yb(ws.host_small[0], ws.host_small[1]);
+    const double yy = ws.host_small[2];
+    const std::complex<double> alpha = (yy > 0.0 && std::isfinite(yy)) ? yb / yy : std::complex<double>(0.0);
+    vec_axpby(N, alpha.real(), alpha.imag(), x0, 0.0, 0.0, x0, x, st);
+    vec_axpby(N, 1.0, 0.0, b, -alpha.real(), -alpha.imag(), ws.tmp, r, st);
+    return norm2_dev(ws, N, r, st);
+}
+
 // ------------------------------------------------------------ one solve --
 static double elapsed_ms(hipEvent_t a, hipEvent_t b) {
     float ms = 0.f;
@@ -290,8 +316,11 @@ int solve_one(Problem &p, const afsbem_solve_opts &o, double s_re, double s_im, 
         AFS_HIP(hipMemsetAsync(ws.x, 0, (size_t)N * 16, st));
         relres = 0.0;
     } else if (fmt == AFSBEM_FMT_C128) {
+        double r0n = 0.0;
+        if (!x_zero)
+            r0n = scaled_start(op64, ws, ws.b, ws.x, ws.x, ws.r, st);
         GmresResult g = gmres(op64, ws, nt, ws.b, bnorm, ws.x, x_zero, o.tol * bnorm, o.restart, o.max_iter, st,
-                              true);
+                              true, x_zero ? nullptr : ws.r, r0n);
         // final true FP64 residual (after the last restart gmres already formed r)
         relres = g.est / bnorm;
         if (g.nan)
@@ -306,19 +335,18 @@ int solve_one(Problem &p, const afsbem_solve_opts &o, double s_re, double s_im, 
             AFS_HIP(hipMemcpyAsync(ws.rin, ws.b, (size_t)N * 16, hipMemcpyDeviceToDevice, st));
             rnorm = bnorm;
         } else {
-            AFS_HIP(hipMemcpyAsync(ws.xo, ws.x, (size_t)N * 16, hipMemcpyDeviceToDevice, st));
-            residual(op64, ws, ws.b, ws.xo, ws.rin, st);
-            rnorm = norm2_dev(ws, N, ws.rin, st);
+            // the starting residual only seeds the inner solve: FP32 operator
+            rnorm = scaled_start(op32, ws, ws.b, ws.x, ws.xo, ws.rin, st);
         }
-        while (rnorm > o.tol * bnorm && matvecs < o.max_iter && std::isfinite(rnorm)) {
+        while (std::isfinite(rnorm)) {
             const double tol_in = std::max(o.inner_tol * rnorm, 0.5 * o.tol * bnorm);
             GmresResult g = gmres(op32, ws, nt, ws.rin, rnorm, ws.x, true, tol_in, o.restart,
-                                  std::max(1, o.max_iter - matvecs), st, false);
+                                  std::max(1, o.max_iter - matvecs), st, false, nullptr, 0.0);
             vec_combine(N, 1, ws.x, N, ws.one, ws.xo, st);  // x_outer += d
-            residual(op64, ws, ws.b, ws.xo, ws.rin, st);
+            residual(op64, ws, ws.b, ws.xo, ws.rin, st);     // FP64 judge
             rnorm = norm2_dev(ws, N, ws.rin, st);
             ++refine;
-            if (g.nan)
+            if (g.nan || rnorm <= o.tol * bnorm || matvecs >= o.max_iter)
                 break;
         }
         relres = rnorm / bnorm;

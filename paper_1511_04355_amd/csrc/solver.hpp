@@ -50,9 +50,11 @@ struct GmresResult {
 // ws.precond.  x (device) is the initial guess unless x_is_zero; on return it
 // holds the iterate.  Stops when the residual norm is <= tol_abs.  With
 // verify = false a cycle whose Arnoldi estimate meets the tolerance returns
-// without forming the true residual of op (an outer loop judges it).
+// without forming the true residual of op (an outer loop judges it).  r0
+// (nullable, with x not zero): the residual of x, already formed.
 GmresResult gmres(const Operator &op, Workspace &ws, int64_t n_tri, const double *rhs, double rhs_norm, double *x,
-                  bool x_is_zero, double tol_abs, int restart, int max_iter, hipStream_t st, bool verify);
+                  bool x_is_zero, double tol_abs, int restart, int max_iter, hipStream_t st, bool verify,
+                  const double *r0 = nullptr, double r0_norm = 0.0);
 
 int solve_one(Problem &p, const afsbem_solve_opts &o, double s_re, double s_im, const double *d_bc,
               const double *d_x0, double *d_a, double *d_u, double *d_t, afsbem_solve_stats *stats,

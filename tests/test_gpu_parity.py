@@ -187,3 +187,25 @@ def test_large_cavity_sampled_rows():
         # row-sampled residual of the oracle operator, relative to the same rows of b
         rr = np.linalg.norm(bo - Ao @ x) / np.linalg.norm(bo)
         assert rr <= 20 * tol
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_solve_warm_starts(prec):
+    """Previous-frequency and user warm starts reach the same solutions."""
+    afs, bem = _afs(), _oracle()
+    mesh, s, bc = _cavity_workload(2, 16)
+    s, bc = s[:6], bc[:6]
+    P = afs.Problem.from_mesh(mesh)
+    p = afs.PREC_FP64 if prec == "fp64" else afs.PREC_MIXED
+    bcd = torch.from_numpy(bc).cuda()
+    out = P.solve(s, bcd, afs.SolveOptions(tol=1e-8, precision=p, warm_start=afs.WARM_PREV))
+    a = out["a"].cpu().numpy()
+    x0 = torch.roll(out["a"], 1, 0).contiguous()  # a neighbouring frequency's solution as a user guess
+    out2 = P.solve(s, bcd, afs.SolveOptions(tol=1e-8, precision=p, warm_start=afs.WARM_USER), x0=x0)
+    a2 = out2["a"].cpu().numpy()
+    for k, sk in enumerate(s):
+        A, b = bem.assemble(mesh, sk)
+        xo = bem.solve_dense(A, b)
+        for sol, st in ((a[k], out["stats"][k]), (a2[k], out2["stats"][k])):
+            assert st["rel_res_fp64"] <= 1e-8
+            assert np.linalg.norm(sol - xo) / np.linalg.norm(xo) <= 1e-6
