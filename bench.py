@@ -44,6 +44,9 @@ def parse():
     ap.add_argument("--cpu-freqs", type=int, default=1)
     ap.add_argument("--warm", choices=["none", "prev"], default="prev",
                     help="initial guess of the optimised path")
+    ap.add_argument("--batch", type=int, default=0,
+                    help="optimised path: 1 = one frequency at a time, 0 = assembly of the next frequency "
+                         "overlapped with the Krylov phase of the current one")
     return ap.parse_args()
 
 
@@ -99,7 +102,7 @@ def main():
     N = P.N
 
     warm = afs.WARM_PREV if args.warm == "prev" else afs.WARM_NONE
-    mixed = afs.SolveOptions(tol=args.tol, precision=afs.PREC_MIXED, warm_start=warm, profile=1)
+    mixed = afs.SolveOptions(tol=args.tol, precision=afs.PREC_MIXED, warm_start=warm, profile=1, batch=args.batch)
     ms_mixed, out = timed(P, s, bc, mixed, args.steps, args.warmup, torch)
     st = out["stats"]
     worst = max(x["rel_res_fp64"] for x in st)
@@ -128,7 +131,8 @@ def main():
                                f"({P.n_tri} triangles, {N} complex unknowns), {args.nfreq} frequencies "
                                f"s_k=0.25+ik*pi/20, FP64 true rel. residual <= {args.tol}",
                    "path": "mixed: FP32 hi-plane GMRES(50) + FP64 refinement, "
-                           + ("previous-s warm start" if args.warm == "prev" else "zero start"),
+                           + ("previous-s warm start" if args.warm == "prev" else "zero start")
+                           + (", assembly of s_k+1 overlapped with GMRES of s_k" if args.batch != 1 else ""),
                    "plan_s": plan_s},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
@@ -145,7 +149,8 @@ def main():
     }
     del out
     if not args.no_plain:
-        plain = afs.SolveOptions(tol=args.tol, precision=afs.PREC_FP64, warm_start=afs.WARM_NONE, profile=1)
+        plain = afs.SolveOptions(tol=args.tol, precision=afs.PREC_FP64, warm_start=afs.WARM_NONE, profile=1,
+                                 batch=1)
         ms_plain, out = timed(P, s, bc, plain, args.steps, args.warmup, torch)
         sp = out["stats"]
         wp = max(x["rel_res_fp64"] for x in sp)

@@ -135,7 +135,9 @@ typedef struct {
     int32_t warm_start;  /* AFSBEM_WARM_* */
     double inner_tol;    /* mixed: relative reduction asked of each FP32 inner solve; the target
                             is max(inner_tol * ||r||, tol * ||b|| / 2) (default 0: aim at tol) */
-    int32_t batch;       /* frequencies resident at once; 0 = as many as fit */
+    int32_t batch;       /* 1: one frequency at a time on the caller's stream; otherwise (default 0)
+                            two in flight: the assembly of frequency k+1 on one library stream
+                            overlaps the Krylov phase of frequency k on another */
     uint32_t fault_inject; /* test hook bits, 0 in production */
     int32_t profile;     /* 1: time every matrix-vector kernel with HIP events (stats.gemv_*) */
 } afsbem_solve_opts;

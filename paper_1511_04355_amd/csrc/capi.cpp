@@ -57,6 +57,13 @@ static void free_problem(afsbem_problem *h) {
         return;
     delete h->p.ws;
     h->p.ws = nullptr;
+    delete h->p.ws2;
+    h->p.ws2 = nullptr;
+    if (h->p.st_asm)
+        (void)hipStreamDestroy(h->p.st_asm);
+    if (h->p.st_sol)
+        (void)hipStreamDestroy(h->p.st_sol);
+    h->p.st_asm = h->p.st_sol = nullptr;
     for (void *p : h->allocs)
         (void)hipFree(p);
     h->allocs.clear();
@@ -257,24 +264,31 @@ int afsbem_solve_device(afsbem_problem *p, int32_t n_s, const double *s, const v
         AFS_REQUIRE(o.warm_start != AFSBEM_WARM_USER || d_x0, AFSBEM_EINVAL, "user warm start needs x0");
         hipStream_t st = static_cast<hipStream_t>(hip_stream);
         const int64_t nt = p->p.dev.n_tri, N = 3 * nt;
-        int rc = AFSBEM_OK;
-        for (int32_t k = 0; k < n_s; ++k) {
+        for (int32_t k = 0; k < n_s; ++k)
             AFS_REQUIRE(std::isfinite(s[2 * k]) && std::isfinite(s[2 * k + 1]), AFSBEM_EINVAL, "non-finite s");
-            const double *bc = static_cast<const double *>(d_bc_val) + 2 * (size_t)k * N;
-            const double *x0 = nullptr;
-            if (o.warm_start == AFSBEM_WARM_USER)
-                x0 = static_cast<const double *>(d_x0) + 2 * (size_t)k * N;
-            else if (o.warm_start == AFSBEM_WARM_PREV && k > 0 && d_a_out)
-                x0 = static_cast<const double *>(d_a_out) + 2 * (size_t)(k - 1) * N;
-            double *a = d_a_out ? static_cast<double *>(d_a_out) + 2 * (size_t)k * N : nullptr;
-            double *u = d_u_out ? static_cast<double *>(d_u_out) + 2 * (size_t)k * N : nullptr;
-            double *t = d_t_out ? static_cast<double *>(d_t_out) + 2 * (size_t)k * N : nullptr;
-            afsbem_solve_opts ok = o;
-            if (!x0)
-                ok.warm_start = AFSBEM_WARM_NONE;
-            int r = solve_one(p->p, ok, s[2 * k], s[2 * k + 1], bc, x0, a, u, t, stats ? &stats[k] : nullptr, st);
-            if (r != AFSBEM_OK && rc == AFSBEM_OK)
-                rc = r;
+        int rc = AFSBEM_OK;
+        const double *bcd = static_cast<const double *>(d_bc_val);
+        if (o.batch != 1 && n_s >= 2) {
+            rc = solve_pipelined(p->p, o, n_s, s, bcd, static_cast<const double *>(d_x0), static_cast<double *>(d_a_out),
+                                 static_cast<double *>(d_u_out), static_cast<double *>(d_t_out), stats, st);
+        } else {
+            for (int32_t k = 0; k < n_s; ++k) {
+                const double *bc = bcd + 2 * (size_t)k * N;
+                const double *x0 = nullptr;
+                if (o.warm_start == AFSBEM_WARM_USER)
+                    x0 = static_cast<const double *>(d_x0) + 2 * (size_t)k * N;
+                else if (o.warm_start == AFSBEM_WARM_PREV && k > 0 && d_a_out)
+                    x0 = static_cast<const double *>(d_a_out) + 2 * (size_t)(k - 1) * N;
+                double *a = d_a_out ? static_cast<double *>(d_a_out) + 2 * (size_t)k * N : nullptr;
+                double *u = d_u_out ? static_cast<double *>(d_u_out) + 2 * (size_t)k * N : nullptr;
+                double *t = d_t_out ? static_cast<double *>(d_t_out) + 2 * (size_t)k * N : nullptr;
+                afsbem_solve_opts ok = o;
+                if (!x0)
+                    ok.warm_start = AFSBEM_WARM_NONE;
+                int r = solve_one(p->p, ok, s[2 * k], s[2 * k + 1], bc, x0, a, u, t, stats ? &stats[k] : nullptr, st);
+                if (r != AFSBEM_OK && rc == AFSBEM_OK)
+                    rc = r;
+            }
         }
         if (rc == AFSBEM_ENOCONV)
             set_error("at least one frequency did not reach the tolerance");

@@ -100,7 +100,8 @@ struct Problem {
     HostPlan host;
     DevicePlan dev;
     int device = 0;
-    Workspace *ws = nullptr;
+    Workspace *ws = nullptr, *ws2 = nullptr;      // second workspace: two frequencies in flight
+    hipStream_t st_asm = nullptr, st_sol = nullptr;  // library streams (default priority)
 };
 
 // ----------------------------------------------------- kernel launchers --

@@ -279,24 +279,26 @@ static double elapsed_ms(hipEvent_t a, hipEvent_t b) {
     return (double)ms;
 }
 
-int solve_one(Problem &p, const afsbem_solve_opts &o, double s_re, double s_im, const double *d_bc,
-              const double *d_x0, double *d_a, double *d_u, double *d_t, afsbem_solve_stats *stats,
-              hipStream_t st) {
-    const int64_t nt = p.dev.n_tri, N = 3 * nt;
-    const int fmt = (o.precision == AFSBEM_PREC_MIXED) ? AFSBEM_FMT_SPLIT : AFSBEM_FMT_C128;
-    if (!p.ws)
-        p.ws = new Workspace();
-    Workspace &ws = *p.ws;
-    ws.ensure(p, fmt, o.restart);
-    hipEvent_t e0, e1, e2;
-    AFS_HIP(hipEventCreate(&e0));
-    AFS_HIP(hipEventCreate(&e1));
-    AFS_HIP(hipEventCreate(&e2));
-    AFS_HIP(hipEventRecord(e0, st));
+static void assemble_into(Problem &p, Workspace &ws, int fmt, double s_re, double s_im, const double *d_bc,
+                          hipStream_t st) {
     KernelParams kp = kernel_params(p.mat, s_re, s_im);
     launch_assembly(p, kp, d_bc, fmt, ws.A, ws.A_lo, ws.b, ws.precond, ws.asm_scratch, st);
-    AFS_HIP(hipEventRecord(e1, st));
+}
 
+// Krylov phase of one frequency on an assembled workspace (stream st); the
+// timing events bracket the assembly (ea0, ea1, possibly on another stream)
+// and this phase.
+static int krylov_phase(Problem &p, Workspace &ws, const afsbem_solve_opts &o, int fmt, const double *d_bc,
+                        const double *d_x0, double *d_a, double *d_u, double *d_t, afsbem_solve_stats *stats,
+                        hipStream_t st, hipEvent_t ea0, hipEvent_t ea1, hipEvent_t e2) {
+    const int64_t nt = p.dev.n_tri, N = 3 * nt;
+    hipEvent_t ek;  // start of this phase on st
+    AFS_HIP(hipEventCreate(&ek));
+    struct EvGuard {
+        hipEvent_t e;
+        ~EvGuard() { (void)hipEventDestroy(e); }
+    } ek_guard{ek};
+    AFS_HIP(hipEventRecord(ek, st));
     int matvecs = 0;
     double bytes = 0.0;
     Workspace *prof = o.profile ? &ws : nullptr;
@@ -368,8 +370,8 @@ int solve_one(Problem &p, const afsbem_solve_opts &o, double s_re, double s_im, 
         stats->fallback = fallback;
         stats->status = status;
         stats->rel_res_fp64 = relres;
-        stats->t_assemble_ms = elapsed_ms(e0, e1);
-        stats->t_solve_ms = elapsed_ms(e1, e2);
+        stats->t_assemble_ms = elapsed_ms(ea0, ea1);
+        stats->t_solve_ms = elapsed_ms(ek, e2);
         stats->bytes = bytes;
         stats->gemv_ms = stats->gemv64_ms = 0.0;
         stats->gemv_count = stats->gemv64_count = 0;
@@ -385,10 +387,128 @@ int solve_one(Problem &p, const afsbem_solve_opts &o, double s_re, double s_im, 
             }
         }
     }
+    return status;
+}
+
+
+int solve_one(Problem &p, const afsbem_solve_opts &o, double s_re, double s_im, const double *d_bc,
+              const double *d_x0, double *d_a, double *d_u, double *d_t, afsbem_solve_stats *stats,
+              hipStream_t st) {
+    const int fmt = (o.precision == AFSBEM_PREC_MIXED) ? AFSBEM_FMT_SPLIT : AFSBEM_FMT_C128;
+    if (!p.ws)
+        p.ws = new Workspace();
+    Workspace &ws = *p.ws;
+    ws.ensure(p, fmt, o.restart);
+    hipEvent_t e0, e1, e2;
+    AFS_HIP(hipEventCreate(&e0));
+    AFS_HIP(hipEventCreate(&e1));
+    AFS_HIP(hipEventCreate(&e2));
+    AFS_HIP(hipEventRecord(e0, st));
+    assemble_into(p, ws, fmt, s_re, s_im, d_bc, st);
+    AFS_HIP(hipEventRecord(e1, st));
+    int rc;
+    try {
+        rc = krylov_phase(p, ws, o, fmt, d_bc, d_x0, d_a, d_u, d_t, stats, st, e0, e1, e2);
+    } catch (...) {
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        (void)hipEventDestroy(e2);
+        throw;
+    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     (void)hipEventDestroy(e2);
-    return status;
+    return rc;
+}
+
+// Two frequencies in flight: the FP64 assembly of frequency k+1 (VALU-bound)
+// runs on one library stream while the Krylov phase of frequency k
+// (HBM-bound GEMVs, latency-bound Arnoldi steps with host round trips) runs on
+// another; two workspaces alternate.  Ordering with the caller's stream is
+// kept by events at entry and exit.
+int solve_pipelined(Problem &p, const afsbem_solve_opts &o, int32_t n_s, const double *s, const double *bc,
+                    const double *x0_user, double *a_out, double *u_out, double *t_out,
+                    afsbem_solve_stats *stats, hipStream_t caller) {
+    const int64_t N = 3 * p.dev.n_tri;
+    const int fmt = (o.precision == AFSBEM_PREC_MIXED) ? AFSBEM_FMT_SPLIT : AFSBEM_FMT_C128;
+    if (!p.ws)
+        p.ws = new Workspace();
+    if (!p.ws2)
+        p.ws2 = new Workspace();
+    Workspace *W[2] = {p.ws, p.ws2};
+    W[0]->ensure(p, fmt, o.restart);
+    W[1]->ensure(p, fmt, o.restart);
+    if (!p.st_asm)
+        AFS_HIP(hipStreamCreateWithFlags(&p.st_asm, hipStreamNonBlocking));
+    if (!p.st_sol)
+        AFS_HIP(hipStreamCreateWithFlags(&p.st_sol, hipStreamNonBlocking));
+    hipStream_t SA = p.st_asm, SS = p.st_sol;
+    std::vector<hipEvent_t> evs;
+    auto mk = [&]() {
+        hipEvent_t e;
+        AFS_HIP(hipEventCreate(&e));
+        evs.push_back(e);
+        return e;
+    };
+    int rc = AFSBEM_OK;
+    try {
+        hipEvent_t entry = mk();
+        AFS_HIP(hipEventRecord(entry, caller));
+        AFS_HIP(hipStreamWaitEvent(SA, entry, 0));
+        AFS_HIP(hipStreamWaitEvent(SS, entry, 0));
+        std::vector<hipEvent_t> a0(n_s), a1(n_s), sdone(n_s), e2(n_s);
+        for (int32_t k = 0; k < n_s; ++k) {
+            a0[k] = mk();
+            a1[k] = mk();
+            sdone[k] = mk();
+            e2[k] = mk();
+        }
+        auto enqueue_asm = [&](int32_t k) {
+            Workspace &w = *W[k % 2];
+            if (k >= 2)
+                AFS_HIP(hipStreamWaitEvent(SA, sdone[k - 2], 0));  // workspace free again
+            AFS_HIP(hipEventRecord(a0[k], SA));
+            assemble_into(p, w, fmt, s[2 * k], s[2 * k + 1], bc + 2 * (size_t)k * N, SA);
+            AFS_HIP(hipEventRecord(a1[k], SA));
+        };
+        enqueue_asm(0);
+        for (int32_t k = 0; k < n_s; ++k) {
+            if (k + 1 < n_s)
+                enqueue_asm(k + 1);
+            AFS_HIP(hipStreamWaitEvent(SS, a1[k], 0));
+            const double *x0 = nullptr;
+            if (o.warm_start == AFSBEM_WARM_USER)
+                x0 = x0_user + 2 * (size_t)k * N;
+            else if (o.warm_start == AFSBEM_WARM_PREV && k > 0 && a_out)
+                x0 = a_out + 2 * (size_t)(k - 1) * N;
+            afsbem_solve_opts ok = o;
+            if (!x0)
+                ok.warm_start = AFSBEM_WARM_NONE;
+            int r = krylov_phase(p, *W[k % 2], ok, fmt, bc + 2 * (size_t)k * N, x0,
+                                 a_out ? a_out + 2 * (size_t)k * N : nullptr, u_out ? u_out + 2 * (size_t)k * N : nullptr,
+                                 t_out ? t_out + 2 * (size_t)k * N : nullptr, stats ? &stats[k] : nullptr, SS, a0[k],
+                                 a1[k], e2[k]);
+            AFS_HIP(hipEventRecord(sdone[k], SS));
+            if (r != AFSBEM_OK && rc == AFSBEM_OK)
+                rc = r;
+        }
+        hipEvent_t ex_a = mk(), ex_s = mk();
+        AFS_HIP(hipEventRecord(ex_a, SA));
+        AFS_HIP(hipEventRecord(ex_s, SS));
+        AFS_HIP(hipStreamWaitEvent(caller, ex_a, 0));
+        AFS_HIP(hipStreamWaitEvent(caller, ex_s, 0));
+        AFS_HIP(hipStreamSynchronize(SS));
+        AFS_HIP(hipStreamSynchronize(SA));
+    } catch (...) {
+        (void)hipStreamSynchronize(SA);
+        (void)hipStreamSynchronize(SS);
+        for (hipEvent_t e : evs)
+            (void)hipEventDestroy(e);
+        throw;
+    }
+    for (hipEvent_t e : evs)
+        (void)hipEventDestroy(e);
+    return rc;
 }
 
 }  // namespace afsbem

@@ -56,6 +56,10 @@ GmresResult gmres(const Operator &op, Workspace &ws, int64_t n_tri, const double
                   bool x_is_zero, double tol_abs, int restart, int max_iter, hipStream_t st, bool verify,
                   const double *r0 = nullptr, double r0_norm = 0.0);
 
+int solve_pipelined(Problem &p, const afsbem_solve_opts &o, int32_t n_s, const double *s, const double *bc,
+                    const double *x0_user, double *a_out, double *u_out, double *t_out,
+                    afsbem_solve_stats *stats, hipStream_t caller);
+
 int solve_one(Problem &p, const afsbem_solve_opts &o, double s_re, double s_im, const double *d_bc,
               const double *d_x0, double *d_a, double *d_u, double *d_t, afsbem_solve_stats *stats,
               hipStream_t st);

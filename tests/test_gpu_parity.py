@@ -131,12 +131,15 @@ def test_solve_fp64_cavity_L2_all_frequencies():
         assert np.linalg.norm(b - A @ a[k]) / np.linalg.norm(b) <= 1.01e-8
 
 
-def test_solve_mixed_cavity_L2():
+@pytest.mark.parametrize("batch", [1, 0])
+def test_solve_mixed_cavity_L2(batch):
+    """batch 1: one frequency at a time; 0: assembly of the next frequency
+    overlapped with the Krylov phase of the current one (two workspaces)."""
     afs, bem = _afs(), _oracle()
     mesh, s, bc = _cavity_workload(2, 16)
     s, bc = s[::5], bc[::5]
     P = afs.Problem.from_mesh(mesh)
-    out = P.solve(s, torch.from_numpy(bc).cuda(), afs.SolveOptions(tol=1e-6, precision=afs.PREC_MIXED))
+    out = P.solve(s, torch.from_numpy(bc).cuda(), afs.SolveOptions(tol=1e-6, precision=afs.PREC_MIXED, batch=batch))
     a = out["a"].cpu().numpy()
     for k, sk in enumerate(s):
         A, b = bem.assemble(mesh, sk)
