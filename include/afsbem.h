@@ -173,6 +173,96 @@ int afsbem_solve_device(afsbem_problem *p, int32_t n_s, const double *s, const v
                         const void *d_x0, void *d_a_out, void *d_u_out, void *d_t_out,
                         const afsbem_solve_opts *opts, afsbem_solve_stats *stats, void *hip_stream);
 
+
+/* ===================================================================== drivers
+ * Host-side frequency-domain drivers on top of the solve.  Complex arrays are
+ * interleaved (re, im) doubles; all arrays are caller-owned host memory. */
+
+/* Fourier-series method (Section 2.2, Eq. 3-4): s_k = eta + i 2 pi k / P,
+ * k = 0..Ns/2 (Ns even); s_out holds Ns/2 + 1 complex values. */
+int afsbem_fsm_grid(double P, double eta, int32_t Ns, double *s_out);
+
+/* Inverse Laplace transform by the trapezoidal rule on the Bromwich line
+ * evaluated with an FFT:  h(t_n) = (e^{eta t_n} / P) Re sum_{k=0}^{Ns-1} W_k H_k
+ * e^{2 pi i k n / Ns},  t_n = n P / Ns, with H_{Ns-k} = conj(H_k) and the
+ * Nyquist term at half weight (trapezoid end points).  H: [n_sig][Ns/2+1]
+ * complex samples at afsbem_fsm_grid; window 0 = none, 1 = Hann
+ * W_k = (1 + cos(2 pi k / Ns)) / 2.  h_out: [n_sig][Ns] real.  The factor
+ * 1/P that Eq. 4 omits is included. */
+int afsbem_fsm_invert(double P, double eta, int32_t Ns, int window, int64_t n_sig, const double *H,
+                      double *h_out);
+
+/* Vector fitting with common poles (Section 2.3, Eq. 5): f_k(s) = sum_m r_km /
+ * (s - a_m), strictly proper, real-coefficient structure (conjugate pairs).
+ * s: [J] complex samples, F: [K][J] complex data, M poles.  init_poles
+ * (nullable, [M] complex): default pairs -b/100 +- i b, b equally spaced in
+ * (0, omega_max] (omega_max <= 0: the largest Im s), plus one real pole for odd M.
+ * n_iter pole-identification passes (stops early when the poles settle);
+ * unstable poles are kept.  Outputs: poles_out [M], residues_out [K][M]
+ * complex, rms_out (nullable) the root-mean-square misfit on the samples. */
+int afsbem_vf_fit(int32_t J, const double *s, int32_t K, const double *F, int32_t M,
+                  const double *init_poles, int32_t n_iter, double omega_max, double *poles_out,
+                  double *residues_out, double *rms_out);
+/* Residue identification for n_fun functions with fixed poles (conjugate
+ * pairs must be complete); residues_out [n_fun][M] in the given pole order. */
+int afsbem_vf_residues(int32_t J, const double *s, int64_t n_fun, const double *F, int32_t M,
+                       const double *poles, double *residues_out);
+/* f_out [n_fun][n_s] complex: the model at the points s. */
+int afsbem_vf_eval(int32_t M, const double *poles, int64_t n_fun, const double *residues, int32_t n_s,
+                   const double *s, double *f_out);
+/* f_out [n_fun][n_t] real: the time response sum_m r_km e^{a_m t} (the exact
+ * inverse transform of the model; Eq. 6 prints the exponent's sign the other
+ * way, which would contradict Eq. 5). */
+int afsbem_vf_eval_time(int32_t M, const double *poles, int64_t n_fun, const double *residues, int32_t n_t,
+                        const double *t, double *f_out);
+
+/* Adaptive frequency sampling (Section 3, Eq. 7-14, the Algorithm of 3.4).
+ * T: period, eta: abscissa, Ns: FSM resolution (Omega = pi Ns / T), J0 initial
+ * Chebyshev-type frequencies w_j = Omega [1 - cos(j pi / (2 (J0-1)))] (the
+ * printed formula lacks the pi), fitting orders floor(J/alpha_H), floor(J/alpha_L),
+ * thresholds E1_bar, E2_bar, Jc validation steps, max_Nc cap (0 = Ns/2 + 1),
+ * grid_pts points of the uniform grid on which maxima over [0, Omega] are
+ * taken, n_iter pole-identification passes per fit. */
+typedef struct {
+    double T, eta;
+    int32_t Ns, J0;
+    double alpha_H, alpha_L, E1_bar, E2_bar;
+    int32_t Jc, max_Nc, grid_pts, n_iter;
+} afsbem_afs_params;
+
+typedef struct afsbem_afs_result afsbem_afs_result;
+
+/* Response callback: fills f_out [n_s][Kt] complex with the responses at the
+ * n_s complex frequencies s; columns 0..K-1 are the observation response
+ * functions used for pole identification, K..Kt-1 further test functions.
+ * Returns 0 on success. */
+typedef int (*afsbem_response_fn)(int32_t n_s, const double *s, int32_t Kt, double *f_out, void *user);
+
+/* Defaults: alpha_H 2.0, alpha_L 2.3, E1_bar 1e-4, E2_bar 2e-3, Jc 3, J0 16
+ * (Section 3.4), grid_pts 2048, n_iter 10, max_Nc 0; T, eta, Ns placeholders. */
+int afsbem_afs_params_default(afsbem_afs_params *p);
+/* Runs AFS with any response (a mock, or afsbem_afs_run_problem's BEM solve). */
+int afsbem_afs_run(const afsbem_afs_params *p, int32_t K, int32_t Kt, afsbem_response_fn fn, void *user,
+                   afsbem_afs_result **out);
+/* AFS driving the GPU solve of a problem: at each requested s the boundary
+ * values are bc_shape * load(s) (load_kind 0: Heaviside, load = 1/s; 1:
+ * constant 1), bc_shape [n_tri][3] real; the Kt responses are the solution-vector
+ * entries dof_idx[0..Kt-1] (the first K are the observation functions).  The
+ * initial frequencies are solved in one call (assembly overlapped with the
+ * Krylov phases); each new frequency is warm-started from the solution at the
+ * nearest sampled frequency.  opts may be NULL. */
+int afsbem_afs_run_problem(afsbem_problem *p, const afsbem_afs_params *params, const double *bc_shape,
+                           int load_kind, const int64_t *dof_idx, int32_t K, int32_t Kt,
+                           const afsbem_solve_opts *opts, afsbem_afs_result **out);
+int afsbem_afs_result_info(const afsbem_afs_result *r, int32_t *Nc, int32_t *M, int32_t *n_steps,
+                           int32_t *converged);
+/* Copies (each pointer nullable): s_out [Nc] complex samples in the order
+ * taken, F_out [Nc][Kt] complex responses, poles_out [M] and residues_out
+ * [Kt][M] of the final order-M_H model, E1_out and E2_out [n_steps]. */
+int afsbem_afs_result_get(const afsbem_afs_result *r, double *s_out, double *F_out, double *poles_out,
+                          double *residues_out, double *E1_out, double *E2_out);
+int afsbem_afs_result_destroy(afsbem_afs_result *r);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1,0 +1,128 @@
+"""Oracle: adaptive frequency sampling (paper Section 3, Eq. 7-14 and the
+Algorithm of Section 3.4).  Test infrastructure; drives any response
+function (a real BEM solve or a synthetic rational mock).
+
+Readings of the paper used here:
+ * initial frequencies (Section 3.4): w_j = Omega [1 - cos(j pi / (2 (J0 - 1)))],
+   j = 0..J0-1 (the printed formula lacks the pi and would span only
+   [0, 0.12 Omega]); s_j = eta + i w_j; Omega = pi Ns / T;
+ * fitting orders (Eq. 10): M_H = floor(J / alpha_H), M_L = floor(J / alpha_L);
+ * "s in [0, Omega]" (Eq. 7-9) means w in [0, Omega] on Re s = eta; maxima
+   are taken over a uniform grid of G points; grid points within dw/4 of an
+   existing sample are excluded for s_new; ties go to the smallest w;
+ * e_k (Eq. 8) is evaluated for every test function; k_max ranges over the
+   ORFs I_o (Eq. 9) and E2 over the test set I_t, which contains I_o (Eq. 13);
+   the test functions use the ORF poles of each order (residue identification);
+ * E1 (Eq. 12) compares the order-M_H time responses (Eq. 11) of consecutive
+   steps; E1 at step 0 is +infinity; the integrals over [0, T] use composite
+   Simpson on 4 Ns + 1 points;
+ * convergence (Eq. 14): E1 < E1_bar and E2 < E2_bar, then Jc further steps
+   that must all pass, otherwise sampling resumes (stage 3 of the Algorithm);
+ * safety cap: at most Ns/2 + 1 samples (the cost of the FSM).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import vf
+
+
+def initial_frequencies(eta, omega, J0):
+    j = np.arange(J0)
+    return eta + 1j * omega * (1 - np.cos(j * np.pi / (2 * (J0 - 1))))
+
+
+def orders(J, alpha_H=2.0, alpha_L=2.3):
+    return int(np.floor(J / alpha_H)), int(np.floor(J / alpha_L))
+
+
+def simpson(y, t):
+    """Composite Simpson rule on a uniform grid with an even number of intervals."""
+    h = t[1] - t[0]
+    return h / 3 * (y[..., 0] + y[..., -1] + 4 * y[..., 1:-1:2].sum(-1) + 2 * y[..., 2:-1:2].sum(-1))
+
+
+def _fit_pair(S, F, K, J, omega, alpha_H, alpha_L, n_iter):
+    MH, ML = orders(J, alpha_H, alpha_L)
+    out = []
+    for M in (MH, ML):
+        p, _, _ = vf.fit(S, F[:, :K].T, M, n_iter=n_iter, omega_max=omega)
+        p, r = vf.identify_residues(S, F.T, p)
+        out.append((p, r))
+    return out, (MH, ML)
+
+
+def run(response, K, Kt, T, eta, Ns, J0=16, alpha_H=2.0, alpha_L=2.3, E1_bar=1e-4, E2_bar=2e-3, Jc=3,
+        max_Nc=None, grid_pts=2048, n_iter=10):
+    """response(s) -> array [len(s), Kt] of complex values (columns < K are the ORFs).
+    Returns a dict with the samples, the final order-M_H model and the histories."""
+    omega = np.pi * Ns / T
+    dw = 2 * np.pi / T
+    max_Nc = (Ns // 2 + 1) if max_Nc is None else max_Nc
+    wgrid = np.linspace(0.0, omega, grid_pts)
+    sgrid = eta + 1j * wgrid
+    tgrid = np.linspace(0.0, T, 4 * Ns + 1)
+    S = list(initial_frequencies(eta, omega, J0))
+    F = np.asarray(response(np.array(S)), np.complex128).reshape(len(S), Kt)
+    hist = {"E1": [], "E2": [], "J": [], "s_new": [], "MH": [], "ML": []}
+    prev_td = None
+
+    def analyse():
+        nonlocal prev_td
+        Sa = np.array(S)
+        J = len(S)
+        ((pH, rH), (pL, rL)), (MH, ML) = _fit_pair(Sa, F, K, J, omega, alpha_H, alpha_L, n_iter)
+        fH = vf.evaluate(sgrid, pH, rH)
+        fL = vf.evaluate(sgrid, pL, rL)
+        diff = np.abs(fH - fL)
+        e = diff.max(axis=1) / np.abs(fH).max(axis=1)
+        E2 = float(e.max())
+        td = vf.time_response(tgrid, pH, rH)
+        if prev_td is None:
+            E1 = np.inf
+        else:
+            num = simpson((td - prev_td) ** 2, tgrid)
+            den = simpson(td ** 2, tgrid)
+            E1 = float(np.max(num / den))
+        prev_td = td
+        kmax = int(np.argmax(e[:K]))
+        d = diff[kmax].copy()
+        taken = np.abs(wgrid[:, None] - Sa.imag[None, :]).min(axis=1) < dw / 4
+        d[taken] = -1.0
+        s_new = sgrid[int(np.argmax(d))]
+        hist["E1"].append(E1)
+        hist["E2"].append(E2)
+        hist["J"].append(J)
+        hist["s_new"].append(s_new)
+        hist["MH"].append(MH)
+        hist["ML"].append(ML)
+        return E1, E2, s_new, (pH, rH)
+
+    def add(s_new):
+        nonlocal F
+        S.append(s_new)
+        F = np.concatenate([F, np.asarray(response(np.array([s_new])), np.complex128).reshape(1, Kt)])
+
+    E1, E2, s_new, model = analyse()
+    converged = False
+    while True:
+        if E1 < E1_bar and E2 < E2_bar:
+            ok = True
+            for _ in range(Jc):
+                if len(S) >= max_Nc:
+                    break
+                add(s_new)
+                E1, E2, s_new, model = analyse()
+                if not (E1 < E1_bar and E2 < E2_bar):
+                    ok = False
+                    break
+            if ok:
+                converged = True
+                break
+            continue
+        if len(S) >= max_Nc:
+            break
+        add(s_new)
+        E1, E2, s_new, model = analyse()
+    return {"s": np.array(S), "F": F, "poles": model[0], "residues": model[1], "converged": converged,
+            "Nc": len(S), "history": hist}

@@ -20,4 +20,12 @@ from ._lib import (  # noqa: F401
     lib,
     lib_path,
     version,
+    fsm_grid,
+    fsm_invert,
+    vf_fit,
+    vf_residues,
+    vf_eval,
+    vf_eval_time,
+    afs_params,
+    afs_run,
 )

@@ -50,6 +50,17 @@ class _Stats(ctypes.Structure):
                 ("gemv64_ms", ctypes.c_double), ("gemv_count", ctypes.c_int32), ("gemv64_count", ctypes.c_int32)]
 
 
+class _AfsParams(ctypes.Structure):
+    _fields_ = [("T", ctypes.c_double), ("eta", ctypes.c_double), ("Ns", ctypes.c_int32), ("J0", ctypes.c_int32),
+                ("alpha_H", ctypes.c_double), ("alpha_L", ctypes.c_double), ("E1_bar", ctypes.c_double),
+                ("E2_bar", ctypes.c_double), ("Jc", ctypes.c_int32), ("max_Nc", ctypes.c_int32),
+                ("grid_pts", ctypes.c_int32), ("n_iter", ctypes.c_int32)]
+
+
+_RESPONSE_FN = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_int32, ctypes.POINTER(ctypes.c_double), ctypes.c_int32,
+                                ctypes.POINTER(ctypes.c_double), ctypes.c_void_p)
+
+
 def lib_path() -> str:
     return _LIBPATH
 
@@ -73,6 +84,18 @@ def lib():
         L.afsbem_matvec_device.argtypes = [P, ctypes.c_int, ctypes.c_int, P, P, P, P, P]
         L.afsbem_solve_opts_default.argtypes = [P]
         L.afsbem_solve_device.argtypes = [P, i32, P, P, P, P, P, P, P, P, P]
+        L.afsbem_fsm_grid.argtypes = [d, d, i32, P]
+        L.afsbem_fsm_invert.argtypes = [d, d, i32, ctypes.c_int, i64, P, P]
+        L.afsbem_vf_fit.argtypes = [i32, P, i32, P, i32, P, i32, d, P, P, P]
+        L.afsbem_vf_residues.argtypes = [i32, P, i64, P, i32, P, P]
+        L.afsbem_vf_eval.argtypes = [i32, P, i64, P, i32, P, P]
+        L.afsbem_vf_eval_time.argtypes = [i32, P, i64, P, i32, P, P]
+        L.afsbem_afs_params_default.argtypes = [P]
+        L.afsbem_afs_run.argtypes = [P, i32, i32, _RESPONSE_FN, P, P]
+        L.afsbem_afs_run_problem.argtypes = [P, P, P, ctypes.c_int, P, i32, i32, P, P]
+        L.afsbem_afs_result_info.argtypes = [P, P, P, P, P]
+        L.afsbem_afs_result_get.argtypes = [P, P, P, P, P, P, P]
+        L.afsbem_afs_result_destroy.argtypes = [P]
         _lib = L
     return _lib
 
@@ -160,6 +183,17 @@ class Problem:
         except Exception:
             pass
 
+    def afs(self, params, bc_shape, dof_idx, K, load_kind=0, opts: "SolveOptions | None" = None):
+        """Adaptive frequency sampling driving this problem's GPU solve."""
+        bc = np.ascontiguousarray(bc_shape, np.float64)
+        idx = np.ascontiguousarray(dof_idx, np.int64)
+        c = (opts or SolveOptions())._c()
+        r = ctypes.c_void_p()
+        _check(lib().afsbem_afs_run_problem(self._h, ctypes.byref(params), bc.ctypes.data, int(load_kind),
+                                            idx.ctypes.data, int(K), int(idx.shape[0]), ctypes.byref(c),
+                                            ctypes.byref(r)))
+        return _afs_result(r, int(idx.shape[0]))
+
     def info(self):
         v = [ctypes.c_int64() for _ in range(4)]
         _check(lib().afsbem_problem_info(self._h, *[ctypes.byref(x) for x in v]))
@@ -221,3 +255,111 @@ class Problem:
         out["status"] = rc
         out["stats"] = [{f: getattr(stats[k], f) for f, _ in _Stats._fields_} for k in range(ns)]
         return out
+
+
+# ------------------------------------------------------------------- drivers
+def _c128(a):
+    return np.ascontiguousarray(np.asarray(a, np.complex128))
+
+
+def fsm_grid(P, eta, Ns):
+    out = np.zeros(Ns // 2 + 1, np.complex128)
+    _check(lib().afsbem_fsm_grid(float(P), float(eta), int(Ns), out.ctypes.data))
+    return out
+
+
+def fsm_invert(P, eta, Ns, H, window=False):
+    """H: [n_sig, Ns/2+1] complex -> h: [n_sig, Ns] real at t_n = n P / Ns."""
+    H = _c128(np.atleast_2d(H))
+    assert H.shape[1] == Ns // 2 + 1
+    out = np.zeros((H.shape[0], Ns))
+    _check(lib().afsbem_fsm_invert(float(P), float(eta), int(Ns), int(bool(window)), H.shape[0], H.ctypes.data,
+                                   out.ctypes.data))
+    return out
+
+
+def vf_fit(s, F, M, n_iter=10, init_poles=None, omega_max=0.0):
+    s = _c128(s)
+    F = _c128(np.atleast_2d(F))
+    K, J = F.shape
+    poles = np.zeros(M, np.complex128)
+    res = np.zeros((K, M), np.complex128)
+    rms = ctypes.c_double()
+    ip = None if init_poles is None else _c128(init_poles)
+    _check(lib().afsbem_vf_fit(J, s.ctypes.data, K, F.ctypes.data, M, None if ip is None else ip.ctypes.data,
+                               int(n_iter), float(omega_max), poles.ctypes.data, res.ctypes.data, ctypes.byref(rms)))
+    return poles, res, rms.value
+
+
+def vf_residues(s, F, poles):
+    s, F, poles = _c128(s), _c128(np.atleast_2d(F)), _c128(poles)
+    res = np.zeros((F.shape[0], poles.shape[0]), np.complex128)
+    _check(lib().afsbem_vf_residues(s.shape[0], s.ctypes.data, F.shape[0], F.ctypes.data, poles.shape[0],
+                                    poles.ctypes.data, res.ctypes.data))
+    return res
+
+
+def vf_eval(poles, res, s):
+    poles, res, s = _c128(poles), _c128(np.atleast_2d(res)), _c128(s)
+    out = np.zeros((res.shape[0], s.shape[0]), np.complex128)
+    _check(lib().afsbem_vf_eval(poles.shape[0], poles.ctypes.data, res.shape[0], res.ctypes.data, s.shape[0],
+                                s.ctypes.data, out.ctypes.data))
+    return out
+
+
+def vf_eval_time(poles, res, t):
+    poles, res = _c128(poles), _c128(np.atleast_2d(res))
+    t = np.ascontiguousarray(t, np.float64)
+    out = np.zeros((res.shape[0], t.shape[0]))
+    _check(lib().afsbem_vf_eval_time(poles.shape[0], poles.ctypes.data, res.shape[0], res.ctypes.data, t.shape[0],
+                                     t.ctypes.data, out.ctypes.data))
+    return out
+
+
+def afs_params(T, eta, Ns, **kw):
+    p = _AfsParams()
+    _check(lib().afsbem_afs_params_default(ctypes.byref(p)))
+    p.T, p.eta, p.Ns = float(T), float(eta), int(Ns)
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+def _afs_result(r, Kt):
+    L = lib()
+    nc, m, ns, conv = (ctypes.c_int32() for _ in range(4))
+    _check(L.afsbem_afs_result_info(r, ctypes.byref(nc), ctypes.byref(m), ctypes.byref(ns), ctypes.byref(conv)))
+    s = np.zeros(nc.value, np.complex128)
+    F = np.zeros((nc.value, Kt), np.complex128)
+    poles = np.zeros(m.value, np.complex128)
+    res = np.zeros((Kt, m.value), np.complex128)
+    E1 = np.zeros(ns.value)
+    E2 = np.zeros(ns.value)
+    _check(L.afsbem_afs_result_get(r, s.ctypes.data, F.ctypes.data, poles.ctypes.data, res.ctypes.data,
+                                   E1.ctypes.data, E2.ctypes.data))
+    L.afsbem_afs_result_destroy(r)
+    return {"s": s, "F": F, "poles": poles, "residues": res, "E1": E1, "E2": E2, "Nc": nc.value,
+            "converged": bool(conv.value)}
+
+
+def afs_run(response, K, Kt, params):
+    """AFS with a Python response(s: complex array) -> [len(s), Kt] complex."""
+    err = []
+
+    def cb(n, sp, kt, fp, user):
+        try:
+            sv = np.ctypeslib.as_array(sp, shape=(2 * n,)).view(np.complex128)
+            f = np.asarray(response(sv.copy()), np.complex128).reshape(n, kt)
+            np.ctypeslib.as_array(fp, shape=(2 * n * kt,))[:] = f.reshape(-1).view(np.float64)
+            return 0
+        except Exception as e:  # reported through the status code
+            err.append(e)
+            return 1
+
+    fn = _RESPONSE_FN(cb)
+    r = ctypes.c_void_p()
+    rc = lib().afsbem_afs_run(ctypes.byref(params), int(K), int(Kt), fn, None, ctypes.byref(r))
+    if err:
+        raise err[0]
+    _check(rc)
+    return _afs_result(r, Kt)

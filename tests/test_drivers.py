@@ -1,0 +1,223 @@
+"""Frequency-domain drivers (paper Sections 2.2, 2.3, 3): oracle pins against
+known transform pairs and rational functions, and the library's C++
+implementations (FFT inversion, vector fitting, AFS) against the oracle.
+All on the CPU (the drivers are host code)."""
+import numpy as np
+import pytest
+
+from oracle import afs as oafs
+from oracle import fsm, vf
+from tests import analytic
+
+
+def _lib():
+    import paper_1511_04355_amd as afs
+    return afs
+
+
+# --------------------------------------------------------------------- FSM
+def test_fsm_frequency_counts_of_the_paper():
+    """Nc = Ns/2 + 1 (Section 2.2) for the three examples: 218 -> 110,
+    160 -> 81, 478 -> 240."""
+    afs = _lib()
+    for Ns, Nc in [(218, 110), (160, 81), (478, 240)]:
+        assert len(fsm.grid(1.0, 0.1, Ns)) == Nc
+        assert len(afs.fsm_grid(1.0, 0.1, Ns)) == Nc
+
+
+@pytest.mark.parametrize("Ns,bound", [(512, 2e-6), (2048, 5e-8)])
+def test_fsm_oracle_known_pair(Ns, bound):
+    """(s+1)^-4 <-> t^3 e^-t / 6, period 40, kappa = 3, no window."""
+    P = 40.0
+    eta = 3 * np.log(10) / P
+    s = fsm.grid(P, eta, Ns)
+    t = np.linspace(0.05, P / 2, 300)
+    h = fsm.invert_direct(P, eta, Ns, (s + 1.0) ** -4, t)
+    assert np.max(np.abs(h - t ** 3 * np.exp(-t) / 6)) < bound
+
+
+def test_fsm_oracle_hann_bias_shrinks():
+    P = 40.0
+    eta = 3 * np.log(10) / P
+    t = np.linspace(0.05, P / 2, 300)
+    errs = []
+    for Ns in (512, 2048):
+        s = fsm.grid(P, eta, Ns)
+        h = fsm.invert_direct(P, eta, Ns, (s + 1.0) ** -4, t, window=True)
+        errs.append(np.max(np.abs(h - t ** 3 * np.exp(-t) / 6)))
+    assert errs[1] < errs[0] / 10 and errs[1] < 3e-5
+
+
+def test_fsm_oracle_cavity_transform():
+    """The pressurised-cavity transform inverts to its closed-form time signal."""
+    P, eta, Ns = 40.0, 0.25, 4096
+    s = fsm.grid(P, eta, Ns)
+    H = np.array([analytic.cavity_ur(x) for x in s])
+    t = np.linspace(0.2, 15, 200)
+    assert np.max(np.abs(fsm.invert_direct(P, eta, Ns, H, t) - analytic.cavity_ur_time(t))) < 3e-5
+
+
+@pytest.mark.parametrize("Ns", [256, 218])
+@pytest.mark.parametrize("window", [False, True])
+def test_fsm_library_matches_oracle(Ns, window):
+    afs = _lib()
+    P = 30.0
+    eta = 3 * np.log(10) / P
+    s = afs.fsm_grid(P, eta, Ns)
+    assert np.max(np.abs(s - fsm.grid(P, eta, Ns))) < 1e-12
+    rng = np.random.default_rng(Ns)
+    H = np.stack([(s + 1.0) ** -3, rng.standard_normal(len(s)) + 1j * rng.standard_normal(len(s))])
+    h = afs.fsm_invert(P, eta, Ns, H, window)
+    t = np.arange(Ns) * P / Ns
+    ho = fsm.invert_direct(P, eta, Ns, H, t, window)
+    assert np.max(np.abs(h - ho)) <= 1e-11 * np.max(np.abs(ho))
+
+
+# ---------------------------------------------------------------------- VF
+def _rational(seed, n_pairs=3, K=3, real_pole=True):
+    rng = np.random.default_rng(seed)
+    poles = []
+    for i in range(n_pairs):
+        a = complex(-0.05 - 0.1 * rng.random(), 0.8 + 1.1 * i + 0.3 * rng.random())
+        poles += [a, np.conj(a)]
+    if real_pole:
+        poles.append(complex(-0.5, 0.0))
+    poles = np.array(poles)
+    res = np.zeros((K, len(poles)), complex)
+    for k in range(K):
+        for i in range(n_pairs):
+            r = complex(rng.normal(), rng.normal())
+            res[k, 2 * i], res[k, 2 * i + 1] = r, np.conj(r)
+        if real_pole:
+            res[k, -1] = rng.normal()
+    return poles, res
+
+
+@pytest.mark.parametrize("impl", ["oracle", "library"])
+@pytest.mark.parametrize("seed,real_pole", [(0, True), (1, False), (2, True)])
+def test_vf_recovers_known_rational_functions(impl, seed, real_pole):
+    poles, res = _rational(seed, real_pole=real_pole)
+    s = 0.2 + 1j * np.linspace(0, 5, 50)
+    F = vf.evaluate(s, poles, res)
+    M = len(poles)
+    if impl == "oracle":
+        p, r, rms = vf.fit(s, F, M, n_iter=20, omega_max=5.0)
+    else:
+        p, r, rms = _lib().vf_fit(s, F, M, n_iter=20, omega_max=5.0)
+    assert rms < 1e-10
+    # poles up to ordering; conjugate structure
+    for a in poles:
+        assert np.min(np.abs(p - a)) < 1e-8
+    for a in p:
+        assert np.min(np.abs(p - np.conj(a))) < 1e-12 * max(1, abs(a))
+    # the model reproduces the data off the samples too
+    s2 = 0.2 + 1j * np.linspace(0.05, 4.9, 37)
+    assert np.max(np.abs(vf.evaluate(s2, p, r) - vf.evaluate(s2, poles, res))) < 1e-8
+    # the time response is the inverse transform: sum r e^{a t}
+    t = np.linspace(0, 10, 50)
+    assert np.max(np.abs(vf.time_response(t, p, r) - vf.time_response(t, poles, res))) < 1e-8
+
+
+def test_vf_library_residues_and_evaluation_match_oracle():
+    afs = _lib()
+    poles, res = _rational(3)
+    s = 0.1 + 1j * np.linspace(0, 4, 40)
+    F = vf.evaluate(s, poles, res) + 1e-3 * np.sin(np.arange(40))  # not exactly rational
+    _, ro = vf.identify_residues(s, F, poles)
+    rl = afs.vf_residues(s, F, poles)
+    assert np.max(np.abs(rl - ro)) < 1e-10 * np.max(np.abs(ro))
+    s2 = 0.1 + 1j * np.linspace(0, 4, 9)
+    assert np.max(np.abs(afs.vf_eval(poles, rl, s2) - vf.evaluate(s2, poles, ro))) < 1e-10
+    t = np.linspace(0, 5, 11)
+    assert np.max(np.abs(afs.vf_eval_time(poles, rl, t) - vf.time_response(t, poles, ro))) < 1e-10
+
+
+def test_vf_fit_error_metric():
+    """E_vf of Section 4.1 is the relative discrete L2 misfit."""
+    f = np.array([1.0, 2.0, -1.0])
+    assert abs(vf.fit_error(f * 1.01, f) - 0.01) < 1e-15
+
+
+# --------------------------------------------------------------------- AFS
+def test_afs_rule_arithmetic():
+    assert oafs.orders(16) == (8, 6)        # Eq. 10 at the paper's J0 = 16
+    assert oafs.orders(8) == (4, 3)
+    s0 = oafs.initial_frequencies(0.1, 5.0, 16)
+    assert abs(s0[0] - 0.1) < 1e-15 and abs(s0[-1] - (0.1 + 5j)) < 1e-12
+    assert np.all(np.diff(s0.imag) > 0)
+    # clustered toward w = 0: the first gap is the smallest (Chebyshev-type)
+    assert np.argmin(np.diff(s0.imag)) == 0
+
+
+def _mock(seed=1, n_modes=8, Kt=7):
+    rng = np.random.default_rng(seed)
+    modes = [complex(-0.02 * (i + 1), 0.5 + 0.6 * i) for i in range(n_modes)]
+    poles = []
+    for a in modes:
+        poles += [a, np.conj(a)]
+    poles.append(complex(-0.01, 0))
+    poles = np.array(poles)
+    res = np.zeros((Kt, len(poles)), complex)
+    for k in range(Kt):
+        for i in range(n_modes):
+            r = complex(rng.normal(), rng.normal()) / (1 + i)
+            res[k, 2 * i], res[k, 2 * i + 1] = r, np.conj(r)
+        res[k, -1] = rng.normal()
+    return poles, res
+
+
+def test_afs_oracle_on_rational_mock():
+    """AFS needs fewer solves than the FSM and recovers the time response."""
+    poles, res = _mock()
+    T, Ns = 60.0, 256
+    eta = 3 * np.log(10) / T
+    calls = []
+
+    def resp(s):
+        calls.append(len(s))
+        return vf.evaluate(np.asarray(s), poles, res).T
+
+    out = oafs.run(resp, 5, 7, T, eta, Ns)
+    assert out["converged"]
+    assert out["Nc"] == sum(calls) and calls[0] == 16
+    assert out["Nc"] < Ns // 2 + 1
+    t = np.linspace(0, T, 300)
+    ex = vf.time_response(t, poles, res)
+    assert np.max(np.abs(vf.time_response(t, out["poles"], out["residues"]) - ex)) < 1e-6 * np.max(np.abs(ex))
+    h = out["history"]
+    assert np.isinf(h["E1"][0])
+    assert h["E1"][-1] < 1e-4 and h["E2"][-1] < 2e-3
+    # the last Jc + 1 analyses all passed (convergence validation)
+    assert all(e1 < 1e-4 and e2 < 2e-3 for e1, e2 in zip(h["E1"][-4:], h["E2"][-4:]))
+
+
+def test_afs_library_matches_oracle_on_mock():
+    afs = _lib()
+    poles, res = _mock()
+    T, Ns = 60.0, 256
+    eta = 3 * np.log(10) / T
+
+    def resp(s):
+        return vf.evaluate(np.asarray(s), poles, res).T
+
+    o = oafs.run(resp, 5, 7, T, eta, Ns)
+    p = afs.afs_run(resp, 5, 7, afs.afs_params(T, eta, Ns))
+    assert p["converged"] and o["converged"]
+    assert abs(p["Nc"] - o["Nc"]) <= 2
+    # identical sample sequence until the fits become degenerate (exact model reached)
+    assert np.max(np.abs(p["s"][:30] - o["s"][:30])) < 1e-9
+    # the fits at J = 33 (16 poles for 17-pole data) are ill-conditioned: 1e-4
+    np.testing.assert_allclose(p["E2"][:20], o["history"]["E2"][:20], rtol=1e-4)
+    t = np.linspace(0, T, 300)
+    ex = vf.time_response(t, poles, res)
+    assert np.max(np.abs(afs.vf_eval_time(p["poles"], p["residues"], t) - ex)) < 1e-6 * np.max(np.abs(ex))
+
+
+def test_afs_library_reports_callback_failure():
+    afs = _lib()
+
+    def bad(s):
+        raise ValueError("boom")
+
+    with pytest.raises(ValueError):
+        afs.afs_run(bad, 2, 2, afs.afs_params(10.0, 0.5, 64))

@@ -1,0 +1,54 @@
+"""AFS driving the GPU solve (afsbem_afs_run_problem) on the small cavity,
+against the oracle AFS driven by the oracle's LU solves."""
+import numpy as np
+import pytest
+
+from synth import meshgen as mg
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _needs_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+
+
+def test_afs_on_gpu_solve_matches_oracle_afs():
+    import paper_1511_04355_amd as afs
+    from oracle import afs as oafs
+    from oracle import bem, vf
+
+    mesh = mg.cavity(2)
+    T, Ns, eta = 20.0, 64, 0.25
+    rng = np.random.default_rng(5)
+    dofs = np.sort(rng.choice(3 * mesh.n_tri, 6, replace=False))
+    K = 4
+    P = afs.Problem.from_mesh(mesh)
+    params = afs.afs_params(T, eta, Ns)
+    out = P.afs(params, mesh.bc_shape, dofs, K, load_kind=0, opts=afs.SolveOptions(tol=1e-10))
+    assert out["converged"]
+    assert out["Nc"] <= Ns // 2 + 1
+    # every sampled response equals the oracle's discrete solution at that s
+    for k in range(0, out["Nc"], 7):
+        sk = out["s"][k]
+        A, b = bem.assemble(mesh, sk)
+        x = bem.solve_dense(A, b)
+        assert np.max(np.abs(out["F"][k] - x[dofs])) <= 1e-7 * np.max(np.abs(x[dofs]))
+
+    # the oracle AFS on the oracle BEM
+    def resp(svals):
+        rows = []
+        for sk in svals:
+            A, b = bem.assemble(mesh, sk)
+            rows.append(bem.solve_dense(A, b)[dofs])
+        return np.array(rows)
+
+    o = oafs.run(resp, K, len(dofs), T, eta, Ns)
+    assert o["converged"]
+    assert abs(o["Nc"] - out["Nc"]) <= 3
+    t = np.linspace(0, T, 200)
+    ho = vf.time_response(t, o["poles"], o["residues"])
+    hg = afs.vf_eval_time(out["poles"], out["residues"], t)
+    assert np.max(np.abs(hg - ho)) <= 1e-3 * np.max(np.abs(ho))
