@@ -125,6 +125,11 @@ int afsbem_matvec_device(afsbem_problem *p, int format, int precision, const voi
 
 /* ---------------------------------------------------------------- solve --- */
 enum { AFSBEM_PREC_FP64 = 0, AFSBEM_PREC_MIXED = 1 };
+/* Initial guesses.  PREV: the previous frequency's solution; USER: d_x0;
+ * LEARNED: the warm-start network of the problem (trained on the solutions of
+ * all frequencies it has solved so far, across calls) combined with the
+ * previous solution.  Every guess x0 is rescaled (or the pair combined) to
+ * minimise ||b - A x0|| before the Krylov solve. */
 enum { AFSBEM_WARM_NONE = 0, AFSBEM_WARM_PREV = 1, AFSBEM_WARM_USER = 2, AFSBEM_WARM_LEARNED = 3 };
 
 typedef struct {
@@ -140,6 +145,7 @@ typedef struct {
                             overlaps the Krylov phase of frequency k on another */
     uint32_t fault_inject; /* test hook bits, 0 in production */
     int32_t profile;     /* 1: time every matrix-vector kernel with HIP events (stats.gemv_*) */
+    int32_t learn_steps; /* AFSBEM_WARM_LEARNED: Adam steps after each solved frequency (0: 24) */
 } afsbem_solve_opts;
 
 typedef struct {
@@ -155,6 +161,9 @@ typedef struct {
      * the plain path) and of the FP64 residual operator of the mixed path */
     double gemv_ms, gemv64_ms;
     int32_t gemv_count, gemv64_count;
+    double rel_res_start; /* ||b - A x0|| / ||b|| of the starting iterate (1 from zero) */
+    int32_t used_net;     /* 1 if the warm-start network's prediction entered x0 */
+    int32_t pad_;
 } afsbem_solve_stats;
 
 /* Fills opts with the defaults listed above. */
@@ -173,6 +182,28 @@ int afsbem_solve_device(afsbem_problem *p, int32_t n_s, const double *s, const v
                         const void *d_x0, void *d_a_out, void *d_u_out, void *d_t_out,
                         const afsbem_solve_opts *opts, afsbem_solve_stats *stats, void *hip_stream);
 
+
+/* ======================================================= learned warm start
+ * A multilayer perceptron (not part of the paper) that maps per-element
+ * features at a frequency to the element's solution components; it is
+ * trained on solutions of earlier frequencies and supplies initial guesses.
+ *   Z1 = X W1 + b1, H1 = silu(Z1), Z2 = H1 W2 + b2, H2 = silu(Z2), Y = H2 W3 + b3
+ * Flat FP32 parameters: W1 [d_in][hidden] row-major, b1 [hidden],
+ * W2 [hidden][hidden], b2 [hidden], W3 [hidden][d_out], b3 [d_out].
+ * X [n][d_in], Y and T [n][d_out] row-major FP32 device arrays.
+ * mode 1: bfloat16 matrix-core products with FP32 accumulation (production);
+ * mode 0: FP32 fused multiply-adds (reference arithmetic). */
+int afsbem_mlp_n_params(int32_t d_in, int32_t hidden, int32_t d_out, int64_t *n);
+int afsbem_mlp_forward(int32_t d_in, int32_t hidden, int32_t d_out, int32_t n, const float *d_params,
+                       const float *d_X, float *d_Y, int mode, void *hip_stream);
+/* d_grad [n_params] receives the gradient of mean((Y - T)^2); d_loss
+ * (nullable) one float, the loss. */
+int afsbem_mlp_loss_grad(int32_t d_in, int32_t hidden, int32_t d_out, int32_t n, const float *d_params,
+                         const float *d_X, const float *d_T, float *d_grad, float *d_loss, int mode,
+                         void *hip_stream);
+/* One Adam step (step counter t >= 1) in place on d_params with moments d_m, d_v. */
+int afsbem_mlp_adam(int64_t n_params, float *d_params, const float *d_grad, float *d_m, float *d_v, int32_t t,
+                    float lr, float beta1, float beta2, float eps, void *hip_stream);
 
 /* ===================================================================== drivers
  * Host-side frequency-domain drivers on top of the solve.  Complex arrays are

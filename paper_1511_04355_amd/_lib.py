@@ -40,14 +40,16 @@ class _Policy(ctypes.Structure):
 class _Opts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("restart", ctypes.c_int32), ("max_iter", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("warm_start", ctypes.c_int32), ("inner_tol", ctypes.c_double),
-                ("batch", ctypes.c_int32), ("fault_inject", ctypes.c_uint32), ("profile", ctypes.c_int32)]
+                ("batch", ctypes.c_int32), ("fault_inject", ctypes.c_uint32), ("profile", ctypes.c_int32),
+                ("learn_steps", ctypes.c_int32)]
 
 
 class _Stats(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("refine_steps", ctypes.c_int32), ("fallback", ctypes.c_int32),
                 ("status", ctypes.c_int32), ("rel_res_fp64", ctypes.c_double), ("t_assemble_ms", ctypes.c_double),
                 ("t_solve_ms", ctypes.c_double), ("bytes", ctypes.c_double), ("gemv_ms", ctypes.c_double),
-                ("gemv64_ms", ctypes.c_double), ("gemv_count", ctypes.c_int32), ("gemv64_count", ctypes.c_int32)]
+                ("gemv64_ms", ctypes.c_double), ("gemv_count", ctypes.c_int32), ("gemv64_count", ctypes.c_int32),
+                ("rel_res_start", ctypes.c_double), ("used_net", ctypes.c_int32), ("pad_", ctypes.c_int32)]
 
 
 class _AfsParams(ctypes.Structure):
@@ -84,6 +86,11 @@ def lib():
         L.afsbem_matvec_device.argtypes = [P, ctypes.c_int, ctypes.c_int, P, P, P, P, P]
         L.afsbem_solve_opts_default.argtypes = [P]
         L.afsbem_solve_device.argtypes = [P, i32, P, P, P, P, P, P, P, P, P]
+        L.afsbem_mlp_n_params.argtypes = [i32, i32, i32, P]
+        L.afsbem_mlp_forward.argtypes = [i32, i32, i32, i32, P, P, P, ctypes.c_int, P]
+        L.afsbem_mlp_loss_grad.argtypes = [i32, i32, i32, i32, P, P, P, P, P, ctypes.c_int, P]
+        L.afsbem_mlp_adam.argtypes = [i64, P, P, P, P, i32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                      ctypes.c_float, P]
         L.afsbem_fsm_grid.argtypes = [d, d, i32, P]
         L.afsbem_fsm_invert.argtypes = [d, d, i32, ctypes.c_int, i64, P, P]
         L.afsbem_vf_fit.argtypes = [i32, P, i32, P, i32, P, i32, d, P, P, P]
@@ -136,10 +143,11 @@ class SolveOptions:
     batch: int = 0
     fault_inject: int = 0
     profile: int = 0
+    learn_steps: int = 0
 
     def _c(self):
         return _Opts(self.tol, self.restart, self.max_iter, self.precision, self.warm_start, self.inner_tol,
-                     self.batch, self.fault_inject, self.profile)
+                     self.batch, self.fault_inject, self.profile, self.learn_steps)
 
 
 class Problem:
@@ -363,3 +371,35 @@ def afs_run(response, K, Kt, params):
         raise err[0]
     _check(rc)
     return _afs_result(r, Kt)
+
+
+# ----------------------------------------------------------------------- MLP
+def mlp_n_params(d_in, hidden, d_out):
+    n = ctypes.c_int64()
+    _check(lib().afsbem_mlp_n_params(d_in, hidden, d_out, ctypes.byref(n)))
+    return n.value
+
+
+def mlp_forward(params, X, d_in, hidden, d_out, mode=1):
+    """params: float32 cuda [n_params]; X: float32 cuda [n, d_in] -> Y [n, d_out]."""
+    import torch
+    X = X.contiguous()
+    Y = torch.empty((X.shape[0], d_out), dtype=torch.float32, device="cuda")
+    _check(lib().afsbem_mlp_forward(d_in, hidden, d_out, X.shape[0], _ptr(params), _ptr(X), _ptr(Y), int(mode),
+                                    _stream()))
+    return Y
+
+
+def mlp_loss_grad(params, X, T, d_in, hidden, d_out, mode=1):
+    import torch
+    X, T = X.contiguous(), T.contiguous()
+    G = torch.empty_like(params)
+    loss = torch.empty(1, dtype=torch.float32, device="cuda")
+    _check(lib().afsbem_mlp_loss_grad(d_in, hidden, d_out, X.shape[0], _ptr(params), _ptr(X), _ptr(T), _ptr(G),
+                                      _ptr(loss), int(mode), _stream()))
+    return loss, G
+
+
+def mlp_adam(params, grad, m, v, t, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+    _check(lib().afsbem_mlp_adam(params.numel(), _ptr(params), _ptr(grad), _ptr(m), _ptr(v), int(t), lr, beta1,
+                                 beta2, eps, _stream()))

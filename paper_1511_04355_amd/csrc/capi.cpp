@@ -5,6 +5,7 @@
 
 #include "internal.hpp"
 #include "solver.hpp"
+#include "mlp.hpp"
 
 struct afsbem_mesh {
     std::vector<double> xyz;
@@ -59,6 +60,8 @@ static void free_problem(afsbem_problem *h) {
     h->p.ws = nullptr;
     delete h->p.ws2;
     h->p.ws2 = nullptr;
+    delete h->p.learn;
+    h->p.learn = nullptr;
     if (h->p.st_asm)
         (void)hipStreamDestroy(h->p.st_asm);
     if (h->p.st_sol)
@@ -230,6 +233,58 @@ int afsbem_matvec_device(afsbem_problem *p, int format, int precision, const voi
     });
 }
 
+int afsbem_mlp_n_params(int32_t d_in, int32_t hidden, int32_t d_out, int64_t *n) {
+    return guarded([&] {
+        AFS_REQUIRE(d_in >= 1 && hidden >= 1 && d_out >= 1 && n, AFSBEM_EINVAL, "bad MLP shape");
+        *n = MlpShape(d_in, hidden, d_out).n_params;
+        return AFSBEM_OK;
+    });
+}
+
+int afsbem_mlp_forward(int32_t d_in, int32_t hidden, int32_t d_out, int32_t n, const float *d_params, const float *d_X,
+                       float *d_Y, int mode, void *hip_stream) {
+    return guarded([&] {
+        AFS_REQUIRE(d_in >= 1 && hidden >= 1 && d_out >= 1 && n >= 0, AFSBEM_EINVAL, "bad MLP shape");
+        AFS_REQUIRE(d_params && d_X && d_Y, AFSBEM_EINVAL, "null pointer argument");
+        AFS_REQUIRE(mode == 0 || mode == 1, AFSBEM_EINVAL, "mode must be 0 (FP32) or 1 (BF16 MFMA)");
+        if (n == 0)
+            return AFSBEM_OK;
+        hipStream_t st = static_cast<hipStream_t>(hip_stream);
+        MlpShape s(d_in, hidden, d_out);
+        void *work = nullptr;
+        AFS_HIP(hipMallocAsync(&work, mlp_work_floats(s, n) * 4, st));
+        mlp_forward(s, mode, n, d_params, d_X, d_Y, static_cast<float *>(work), st);
+        AFS_HIP(hipFreeAsync(work, st));
+        return AFSBEM_OK;
+    });
+}
+
+int afsbem_mlp_loss_grad(int32_t d_in, int32_t hidden, int32_t d_out, int32_t n, const float *d_params,
+                         const float *d_X, const float *d_T, float *d_grad, float *d_loss, int mode, void *hip_stream) {
+    return guarded([&] {
+        AFS_REQUIRE(d_in >= 1 && hidden >= 1 && d_out >= 1 && n >= 1, AFSBEM_EINVAL, "bad MLP shape");
+        AFS_REQUIRE(d_params && d_X && d_T && d_grad, AFSBEM_EINVAL, "null pointer argument");
+        AFS_REQUIRE(mode == 0 || mode == 1, AFSBEM_EINVAL, "mode must be 0 (FP32) or 1 (BF16 MFMA)");
+        hipStream_t st = static_cast<hipStream_t>(hip_stream);
+        MlpShape s(d_in, hidden, d_out);
+        void *work = nullptr;
+        AFS_HIP(hipMallocAsync(&work, mlp_work_floats(s, n) * 4, st));
+        mlp_loss_grad(s, mode, n, d_params, d_X, d_T, d_grad, d_loss, static_cast<float *>(work), st);
+        AFS_HIP(hipFreeAsync(work, st));
+        return AFSBEM_OK;
+    });
+}
+
+int afsbem_mlp_adam(int64_t n_params, float *d_params, const float *d_grad, float *d_m, float *d_v, int32_t t,
+                    float lr, float beta1, float beta2, float eps, void *hip_stream) {
+    return guarded([&] {
+        AFS_REQUIRE(n_params >= 1 && d_params && d_grad && d_m && d_v && t >= 1, AFSBEM_EINVAL,
+                    "bad Adam arguments");
+        mlp_adam(n_params, d_params, d_grad, d_m, d_v, t, lr, beta1, beta2, eps, static_cast<hipStream_t>(hip_stream));
+        return AFSBEM_OK;
+    });
+}
+
 int afsbem_solve_opts_default(afsbem_solve_opts *o) {
     if (!o) {
         set_error("null opts");
@@ -244,6 +299,8 @@ int afsbem_solve_opts_default(afsbem_solve_opts *o) {
     o->inner_tol = 0.0;
     o->batch = 0;
     o->fault_inject = 0;
+    o->profile = 0;
+    o->learn_steps = 0;
     return AFSBEM_OK;
 }
 
@@ -262,6 +319,10 @@ int afsbem_solve_device(afsbem_problem *p, int32_t n_s, const double *s, const v
         AFS_REQUIRE(o.precision == AFSBEM_PREC_FP64 || o.precision == AFSBEM_PREC_MIXED, AFSBEM_EINVAL,
                     "unknown precision");
         AFS_REQUIRE(o.warm_start != AFSBEM_WARM_USER || d_x0, AFSBEM_EINVAL, "user warm start needs x0");
+        AFS_REQUIRE(o.warm_start >= AFSBEM_WARM_NONE && o.warm_start <= AFSBEM_WARM_LEARNED, AFSBEM_EINVAL,
+                    "unknown warm start");
+        AFS_REQUIRE(o.warm_start != AFSBEM_WARM_LEARNED || d_a_out, AFSBEM_EINVAL,
+                    "the learned warm start needs the solution output buffer");
         hipStream_t st = static_cast<hipStream_t>(hip_stream);
         const int64_t nt = p->p.dev.n_tri, N = 3 * nt;
         for (int32_t k = 0; k < n_s; ++k)
@@ -277,13 +338,14 @@ int afsbem_solve_device(afsbem_problem *p, int32_t n_s, const double *s, const v
                 const double *x0 = nullptr;
                 if (o.warm_start == AFSBEM_WARM_USER)
                     x0 = static_cast<const double *>(d_x0) + 2 * (size_t)k * N;
-                else if (o.warm_start == AFSBEM_WARM_PREV && k > 0 && d_a_out)
+                else if ((o.warm_start == AFSBEM_WARM_PREV || o.warm_start == AFSBEM_WARM_LEARNED) && k > 0 &&
+                         d_a_out)
                     x0 = static_cast<const double *>(d_a_out) + 2 * (size_t)(k - 1) * N;
                 double *a = d_a_out ? static_cast<double *>(d_a_out) + 2 * (size_t)k * N : nullptr;
                 double *u = d_u_out ? static_cast<double *>(d_u_out) + 2 * (size_t)k * N : nullptr;
                 double *t = d_t_out ? static_cast<double *>(d_t_out) + 2 * (size_t)k * N : nullptr;
                 afsbem_solve_opts ok = o;
-                if (!x0)
+                if (!x0 && ok.warm_start != AFSBEM_WARM_LEARNED)
                     ok.warm_start = AFSBEM_WARM_NONE;
                 int r = solve_one(p->p, ok, s[2 * k], s[2 * k + 1], bc, x0, a, u, t, stats ? &stats[k] : nullptr, st);
                 if (r != AFSBEM_OK && rc == AFSBEM_OK)

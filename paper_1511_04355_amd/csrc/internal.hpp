@@ -93,6 +93,7 @@ struct DevicePlan {
 
 // -------------------------------------------------------------- problem --
 struct Workspace;
+struct LearnState;
 
 struct Problem {
     MaterialDerived mat;
@@ -102,6 +103,7 @@ struct Problem {
     int device = 0;
     Workspace *ws = nullptr, *ws2 = nullptr;      // second workspace: two frequencies in flight
     hipStream_t st_asm = nullptr, st_sol = nullptr;  // library streams (default priority)
+    LearnState *learn = nullptr;                     // warm-start network (created on first use)
 };
 
 // ----------------------------------------------------- kernel launchers --

@@ -16,6 +16,7 @@
 
 #include "internal.hpp"
 #include "solver.hpp"
+#include "mlp.hpp"
 
 namespace afsbem {
 
@@ -272,6 +273,94 @@ static double scaled_start(const Operator &op, Workspace &ws, const double *b, c
     return norm2_dev(ws, N, r, st);
 }
 
+// Two-vector residual-minimising start: x = alpha x1 + beta x2 minimising
+// ||b - alpha A x1 - beta A x2||, solved in an orthogonalised basis of the
+// images (y2' = y2 - mu y1, mu = y1^H y2 / |y1|^2) so that the coefficients and
+// the starting residual stay accurate; x2 is dropped (x1 alone) when its image
+// adds less than 10% of a new direction.  Returns ||r|| (sets *used2).
+static double scaled_start2(const Operator &op, Workspace &ws, const double *b, const double *x1, const double *x2,
+                            double *x, double *r, hipStream_t st, bool *used2, double *gain) {
+    const int64_t N = op.N;
+    double *y1 = ws.tmp, *y2 = ws.w;
+    op.apply(x1, y1, st);
+    op.apply(x2, y2, st);
+    double *d = ws.small;
+    vec_mdot(N, 1, y1, N, y1, ws.dots_partial, d, st);      // |y1|^2
+    vec_mdot(N, 1, y1, N, y2, ws.dots_partial, d + 2, st);  // y1^H y2
+    vec_mdot(N, 1, y2, N, y2, ws.dots_partial, d + 4, st);  // |y2|^2
+    vec_mdot(N, 1, y1, N, b, ws.dots_partial, d + 6, st);   // y1^H b
+    vec_mdot(N, 1, y2, N, b, ws.dots_partial, d + 8, st);   // y2^H b
+    AFS_HIP(hipMemcpyAsync(ws.host_small, d, 80, hipMemcpyDeviceToHost, st));
+    AFS_HIP(hipStreamSynchronize(st));
+    using C = std::complex<double>;
+    const double *h = ws.host_small;
+    const double g11 = h[0], g22 = h[4];
+    const C g12(h[2], h[3]), c1(h[6], h[7]), c2(h[8], h[9]);
+    *used2 = false;
+    *gain = 1.0;
+    if (!(g11 > 0.0) || !std::isfinite(g11) || !(g22 > 0.0) || !std::isfinite(g22)) {
+        // degenerate image: fall back to whichever vector has one
+        const bool one = g11 > 0.0 && std::isfinite(g11);
+        const C a = one ? c1 / g11 : (g22 > 0.0 && std::isfinite(g22) ? c2 / g22 : C(0.0));
+        const double *xs = one ? x1 : x2;
+        const double *ys = one ? y1 : y2;
+        vec_axpby(N, a.real(), a.imag(), xs, 0.0, 0.0, xs, x, st);
+        vec_axpby(N, 1.0, 0.0, b, -a.real(), -a.imag(), ys, r, st);
+        return norm2_dev(ws, N, r, st);
+    }
+    const C mu = g12 / g11;
+    const double g2p = g22 - std::norm(g12) / g11;  // |y2'|^2
+    if (!(g2p > 0.01 * g22)) {
+        const C a = c1 / g11;
+        vec_axpby(N, a.real(), a.imag(), x1, 0.0, 0.0, x1, x, st);
+        vec_axpby(N, 1.0, 0.0, b, -a.real(), -a.imag(), y1, r, st);
+        return norm2_dev(ws, N, r, st);
+    }
+    const C a = c1 / g11;
+    const C c = (c2 - std::conj(mu) * c1) / g2p;  // y2'^H b / |y2'|^2
+    const C alpha = a - c * mu;
+    *used2 = true;
+    {
+        // residual norms with x1 alone and with the pair (normal equations)
+        double bb = 0.0;
+        vec_mdot(N, 1, b, N, b, ws.dots_partial, ws.small, st);
+        AFS_HIP(hipMemcpyAsync(ws.host_small, ws.small, 16, hipMemcpyDeviceToHost, st));
+        AFS_HIP(hipStreamSynchronize(st));
+        bb = ws.host_small[0];
+        const double r1 = std::max(bb - std::norm(c1) / g11, 0.0);
+        const double r2 = std::max(r1 - std::norm(c) * g2p, 0.0);
+        *gain = r2 > 0.0 ? std::sqrt(r1 / r2) : 1e30;
+    }
+    vec_axpby(N, alpha.real(), alpha.imag(), x1, c.real(), c.imag(), x2, x, st);
+    // r = b - a y1 - c (y2 - mu y1) = b - alpha y1 - c y2, formed from the orthogonal pieces
+    vec_axpby(N, 1.0, 0.0, y2, -mu.real(), -mu.imag(), y1, y2, st);  // y2 <- y2'
+    vec_axpby(N, 1.0, 0.0, b, -a.real(), -a.imag(), y1, r, st);
+    vec_axpby(N, 1.0, 0.0, r, -c.real(), -c.imag(), y2, r, st);
+    return norm2_dev(ws, N, r, st);
+}
+
+// Starting iterate from the available guesses (previous-frequency solution
+// and/or network prediction); returns the residual norm (x_zero: b itself).
+static double start_iterate(const Operator &op, Workspace &ws, const double *b, double bnorm, const double *x_prev,
+                            const double *x_net, double *x, double *r, bool &x_zero, hipStream_t st,
+                            bool *used_net, double *net_gain) {
+    x_zero = false;
+    *used_net = false;
+    *net_gain = 0.0;
+    if (x_prev && x_net)
+        return scaled_start2(op, ws, b, x_prev, x_net, x, r, st, used_net, net_gain);
+    if (x_net)
+        *used_net = true;
+    if (x_net)
+        return scaled_start(op, ws, b, x_net, x, r, st);
+    if (x_prev)
+        return scaled_start(op, ws, b, x_prev, x, r, st);
+    x_zero = true;
+    AFS_HIP(hipMemsetAsync(x, 0, (size_t)op.N * 16, st));
+    AFS_HIP(hipMemcpyAsync(r, b, (size_t)op.N * 16, hipMemcpyDeviceToDevice, st));
+    return bnorm;
+}
+
 // ------------------------------------------------------------ one solve --
 static double elapsed_ms(hipEvent_t a, hipEvent_t b) {
     float ms = 0.f;
@@ -288,9 +377,9 @@ static void assemble_into(Problem &p, Workspace &ws, int fmt, double s_re, doubl
 // Krylov phase of one frequency on an assembled workspace (stream st); the
 // timing events bracket the assembly (ea0, ea1, possibly on another stream)
 // and this phase.
-static int krylov_phase(Problem &p, Workspace &ws, const afsbem_solve_opts &o, int fmt, const double *d_bc,
-                        const double *d_x0, double *d_a, double *d_u, double *d_t, afsbem_solve_stats *stats,
-                        hipStream_t st, hipEvent_t ea0, hipEvent_t ea1, hipEvent_t e2) {
+static int krylov_phase(Problem &p, Workspace &ws, const afsbem_solve_opts &o, int fmt, double s_re, double s_im,
+                        const double *d_bc, const double *d_x0, double *d_a, double *d_u, double *d_t,
+                        afsbem_solve_stats *stats, hipStream_t st, hipEvent_t ea0, hipEvent_t ea1, hipEvent_t e2) {
     const int64_t nt = p.dev.n_tri, N = 3 * nt;
     hipEvent_t ek;  // start of this phase on st
     AFS_HIP(hipEventCreate(&ek));
@@ -305,22 +394,30 @@ static int krylov_phase(Problem &p, Workspace &ws, const afsbem_solve_opts &o, i
     ws.reset_timing();
     Operator op64{N, fmt, 0, ws.A, ws.A_lo, ws.gemv_partial, &matvecs, &bytes, prof};
     const double bnorm = norm2_dev(ws, N, ws.b, st);
-    bool x_zero = true;
-    if (d_x0 && o.warm_start != AFSBEM_WARM_NONE) {
-        AFS_HIP(hipMemcpyAsync(ws.x, d_x0, (size_t)N * 16, hipMemcpyDeviceToDevice, st));
-        x_zero = false;
-    } else {
-        AFS_HIP(hipMemsetAsync(ws.x, 0, (size_t)N * 16, st));
+    const bool learned = o.warm_start == AFSBEM_WARM_LEARNED;
+    const double *x_prev = (d_x0 && o.warm_start != AFSBEM_WARM_NONE) ? d_x0 : nullptr;
+    const double *x_net = nullptr;
+    if (learned) {
+        if (!p.learn) {
+            p.learn = new LearnState();
+            p.learn->s_scale = std::max(1.0, std::fabs(s_im));
+            p.learn->init(p);
+        }
+        if (p.learn->rows > 0 && p.learn->query_now()) {
+            p.learn->predict(p, s_re, s_im, ws.z, st);
+            x_net = ws.z;
+        }
     }
+    bool x_zero = true, used_net = false;
+    double net_gain = 0.0;
     int status = AFSBEM_OK, refine = 0, fallback = 0;
-    double relres = 1.0;
+    double relres = 1.0, rel_start = 1.0;
     if (bnorm == 0.0) {
         AFS_HIP(hipMemsetAsync(ws.x, 0, (size_t)N * 16, st));
         relres = 0.0;
     } else if (fmt == AFSBEM_FMT_C128) {
-        double r0n = 0.0;
-        if (!x_zero)
-            r0n = scaled_start(op64, ws, ws.b, ws.x, ws.x, ws.r, st);
+        const double r0n = start_iterate(op64, ws, ws.b, bnorm, x_prev, x_net, ws.x, ws.r, x_zero, st, &used_net, &net_gain);
+        rel_start = r0n / bnorm;
         GmresResult g = gmres(op64, ws, nt, ws.b, bnorm, ws.x, x_zero, o.tol * bnorm, o.restart, o.max_iter, st,
                               true, x_zero ? nullptr : ws.r, r0n);
         // final true FP64 residual (after the last restart gmres already formed r)
@@ -329,17 +426,11 @@ static int krylov_phase(Problem &p, Workspace &ws, const afsbem_solve_opts &o, i
             status = AFSBEM_ENAN;
     } else {
         // mixed: outer residual with the FP64 operator (hi + lo planes), inner
-        // GMRES on the FP32 hi plane for the correction d: A32 d = r.
+        // GMRES on the FP32 hi plane for the correction d: A32 d = r.  The
+        // starting residual only seeds the inner solve: FP32 operator.
         Operator op32{N, fmt, 1, ws.A, ws.A_lo, ws.gemv_partial, &matvecs, &bytes, prof};
-        double rnorm;
-        if (x_zero) {
-            AFS_HIP(hipMemsetAsync(ws.xo, 0, (size_t)N * 16, st));
-            AFS_HIP(hipMemcpyAsync(ws.rin, ws.b, (size_t)N * 16, hipMemcpyDeviceToDevice, st));
-            rnorm = bnorm;
-        } else {
-            // the starting residual only seeds the inner solve: FP32 operator
-            rnorm = scaled_start(op32, ws, ws.b, ws.x, ws.xo, ws.rin, st);
-        }
+        double rnorm = start_iterate(op32, ws, ws.b, bnorm, x_prev, x_net, ws.xo, ws.rin, x_zero, st, &used_net, &net_gain);
+        rel_start = rnorm / bnorm;
         while (std::isfinite(rnorm)) {
             const double tol_in = std::max(o.inner_tol * rnorm, 0.5 * o.tol * bnorm);
             GmresResult g = gmres(op32, ws, nt, ws.rin, rnorm, ws.x, true, tol_in, o.restart,
@@ -361,6 +452,12 @@ static int krylov_phase(Problem &p, Workspace &ws, const afsbem_solve_opts &o, i
         AFS_HIP(hipMemcpyAsync(d_a, ws.x, (size_t)N * 16, hipMemcpyDeviceToDevice, st));
     if (d_u || d_t)
         vec_split_ut(nt, p.dev.kind, ws.x, d_bc, d_u, d_t, st);
+    if (learned && x_net && x_prev)
+        p.learn->record_gain(net_gain);
+    if (learned && std::isfinite(relres)) {
+        p.learn->add_solution(p, s_re, s_im, ws.x, st);
+        p.learn->train(o.learn_steps > 0 ? o.learn_steps : p.learn->steps_per_sample, st);
+    }
     AFS_HIP(hipStreamSynchronize(st));
     if (status == AFSBEM_OK && !(relres <= o.tol))
         status = AFSBEM_ENOCONV;
@@ -370,6 +467,8 @@ static int krylov_phase(Problem &p, Workspace &ws, const afsbem_solve_opts &o, i
         stats->fallback = fallback;
         stats->status = status;
         stats->rel_res_fp64 = relres;
+        stats->rel_res_start = rel_start;
+        stats->used_net = used_net ? 1 : 0;
         stats->t_assemble_ms = elapsed_ms(ea0, ea1);
         stats->t_solve_ms = elapsed_ms(ek, e2);
         stats->bytes = bytes;
@@ -408,7 +507,7 @@ int solve_one(Problem &p, const afsbem_solve_opts &o, double s_re, double s_im, 
     AFS_HIP(hipEventRecord(e1, st));
     int rc;
     try {
-        rc = krylov_phase(p, ws, o, fmt, d_bc, d_x0, d_a, d_u, d_t, stats, st, e0, e1, e2);
+        rc = krylov_phase(p, ws, o, fmt, s_re, s_im, d_bc, d_x0, d_a, d_u, d_t, stats, st, e0, e1, e2);
     } catch (...) {
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
@@ -479,12 +578,12 @@ int solve_pipelined(Problem &p, const afsbem_solve_opts &o, int32_t n_s, const d
             const double *x0 = nullptr;
             if (o.warm_start == AFSBEM_WARM_USER)
                 x0 = x0_user + 2 * (size_t)k * N;
-            else if (o.warm_start == AFSBEM_WARM_PREV && k > 0 && a_out)
+            else if ((o.warm_start == AFSBEM_WARM_PREV || o.warm_start == AFSBEM_WARM_LEARNED) && k > 0 && a_out)
                 x0 = a_out + 2 * (size_t)(k - 1) * N;
             afsbem_solve_opts ok = o;
-            if (!x0)
+            if (!x0 && ok.warm_start != AFSBEM_WARM_LEARNED)
                 ok.warm_start = AFSBEM_WARM_NONE;
-            int r = krylov_phase(p, *W[k % 2], ok, fmt, bc + 2 * (size_t)k * N, x0,
+            int r = krylov_phase(p, *W[k % 2], ok, fmt, s[2 * k], s[2 * k + 1], bc + 2 * (size_t)k * N, x0,
                                  a_out ? a_out + 2 * (size_t)k * N : nullptr, u_out ? u_out + 2 * (size_t)k * N : nullptr,
                                  t_out ? t_out + 2 * (size_t)k * N : nullptr, stats ? &stats[k] : nullptr, SS, a0[k],
                                  a1[k], e2[k]);
