@@ -123,6 +123,16 @@ int afsbem_assemble_device(afsbem_problem *p, double s_re, double s_im, const vo
 int afsbem_matvec_device(afsbem_problem *p, int format, int precision, const void *d_A,
                          const void *d_A_lo, const void *d_x, void *d_y, void *hip_stream);
 
+/* Preconditioner clusters of the plan: n_clusters, ptr_out [n_clusters+1]
+ * offsets into elem_out [n_tri] (element indices grouped by cluster); the
+ * arrays are nullable (query the count first). */
+int afsbem_problem_clusters(const afsbem_problem *p, int64_t *n_clusters, int64_t *ptr_out, int32_t *elem_out);
+
+/* z = M^-1 v with M the block diagonal of A over the clusters (FP32
+ * inverses built from d_A on the device, FP64 application). */
+int afsbem_precond_apply_device(afsbem_problem *p, int format, const void *d_A, const void *d_A_lo,
+                                const void *d_v, void *d_z, void *hip_stream);
+
 /* ---------------------------------------------------------------- solve --- */
 enum { AFSBEM_PREC_FP64 = 0, AFSBEM_PREC_MIXED = 1 };
 /* Initial guesses.  PREV: the previous frequency's solution; USER: d_x0;
@@ -146,6 +156,9 @@ typedef struct {
     uint32_t fault_inject; /* test hook bits, 0 in production */
     int32_t profile;     /* 1: time every matrix-vector kernel with HIP events (stats.gemv_*) */
     int32_t learn_steps; /* AFSBEM_WARM_LEARNED: Adam steps after each solved frequency (0: 24) */
+    int32_t precond;     /* block-diagonal preconditioner: 0 = one 3x3 block per collocation point;
+                            1 = blocks over spatial clusters of up to 24 elements (recursive
+                            coordinate bisection), inverted in FP32 on the device */
 } afsbem_solve_opts;
 
 typedef struct {

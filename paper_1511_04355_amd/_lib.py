@@ -41,7 +41,7 @@ class _Opts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("restart", ctypes.c_int32), ("max_iter", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("warm_start", ctypes.c_int32), ("inner_tol", ctypes.c_double),
                 ("batch", ctypes.c_int32), ("fault_inject", ctypes.c_uint32), ("profile", ctypes.c_int32),
-                ("learn_steps", ctypes.c_int32)]
+                ("learn_steps", ctypes.c_int32), ("precond", ctypes.c_int32)]
 
 
 class _Stats(ctypes.Structure):
@@ -85,6 +85,8 @@ def lib():
         L.afsbem_assemble_device.argtypes = [P, d, d, P, ctypes.c_int, P, P, P, P, P]
         L.afsbem_matvec_device.argtypes = [P, ctypes.c_int, ctypes.c_int, P, P, P, P, P]
         L.afsbem_solve_opts_default.argtypes = [P]
+        L.afsbem_problem_clusters.argtypes = [P, P, P, P]
+        L.afsbem_precond_apply_device.argtypes = [P, ctypes.c_int, P, P, P, P, P]
         L.afsbem_solve_device.argtypes = [P, i32, P, P, P, P, P, P, P, P, P]
         L.afsbem_mlp_n_params.argtypes = [i32, i32, i32, P]
         L.afsbem_mlp_forward.argtypes = [i32, i32, i32, i32, P, P, P, ctypes.c_int, P]
@@ -144,10 +146,11 @@ class SolveOptions:
     fault_inject: int = 0
     profile: int = 0
     learn_steps: int = 0
+    precond: int = 0
 
     def _c(self):
         return _Opts(self.tol, self.restart, self.max_iter, self.precision, self.warm_start, self.inner_tol,
-                     self.batch, self.fault_inject, self.profile, self.learn_steps)
+                     self.batch, self.fault_inject, self.profile, self.learn_steps, self.precond)
 
 
 class Problem:
@@ -239,6 +242,21 @@ class Problem:
         _check(lib().afsbem_matvec_device(self._h, int(fmt), int(precision), _ptr(A), _ptr(A_lo), _ptr(x), _ptr(y),
                                           _stream()))
         return y
+
+    def clusters(self):
+        n = ctypes.c_int64()
+        _check(lib().afsbem_problem_clusters(self._h, ctypes.byref(n), None, None))
+        ptr = np.zeros(n.value + 1, np.int64)
+        elem = np.zeros(self.n_tri, np.int32)
+        _check(lib().afsbem_problem_clusters(self._h, ctypes.byref(n), ptr.ctypes.data, elem.ctypes.data))
+        return ptr, elem
+
+    def precond_apply(self, A, A_lo, v, fmt=FMT_C128):
+        import torch
+        v = v.contiguous()
+        z = torch.empty_like(v)
+        _check(lib().afsbem_precond_apply_device(self._h, int(fmt), _ptr(A), _ptr(A_lo), _ptr(v), _ptr(z), _stream()))
+        return z
 
     # --------------------------------------------------------------- solve
     def solve(self, s_list, bc_val, opts: SolveOptions | None = None, x0=None, want_ut=True, out=None):

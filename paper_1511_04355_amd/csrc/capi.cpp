@@ -162,6 +162,9 @@ int afsbem_problem_create(const afsbem_mesh *mesh, const afsbem_material *mat, c
         D.gl_rho = upload(h, H.gl_rho);
         D.nrm = upload(h, H.nrm);
         D.coef = upload(h, H.coef);
+        D.n_clusters = (int64_t)H.clus_ptr.size() - 1;
+        D.clus_ptr = upload(h, H.clus_ptr);
+        D.clus_elem = upload(h, H.clus_elem);
         *out = h;
         return AFSBEM_OK;
     });
@@ -285,6 +288,36 @@ int afsbem_mlp_adam(int64_t n_params, float *d_params, const float *d_grad, floa
     });
 }
 
+int afsbem_problem_clusters(const afsbem_problem *p, int64_t *n_clusters, int64_t *ptr_out, int32_t *elem_out) {
+    return guarded([&] {
+        AFS_REQUIRE(p && n_clusters, AFSBEM_EINVAL, "null pointer argument");
+        const HostPlan &H = p->p.host;
+        *n_clusters = (int64_t)H.clus_ptr.size() - 1;
+        if (ptr_out)
+            std::memcpy(ptr_out, H.clus_ptr.data(), H.clus_ptr.size() * sizeof(int64_t));
+        if (elem_out)
+            std::memcpy(elem_out, H.clus_elem.data(), H.clus_elem.size() * sizeof(int32_t));
+        return AFSBEM_OK;
+    });
+}
+
+int afsbem_precond_apply_device(afsbem_problem *p, int format, const void *d_A, const void *d_A_lo, const void *d_v,
+                                void *d_z, void *hip_stream) {
+    return guarded([&] {
+        AFS_REQUIRE(p && d_A && d_v && d_z, AFSBEM_EINVAL, "null pointer argument");
+        AFS_REQUIRE(format == AFSBEM_FMT_C128 || format == AFSBEM_FMT_SPLIT, AFSBEM_EINVAL, "bad format");
+        hipStream_t st = static_cast<hipStream_t>(hip_stream);
+        void *inv = nullptr;
+        AFS_HIP(hipMallocAsync(&inv, (size_t)std::max<int64_t>(p->p.dev.n_clusters, 1) * kClusterDim * kClusterDim * 8,
+                               st));
+        cluster_inverse(p->p.dev, format, d_A, d_A_lo, static_cast<float *>(inv), st);
+        cluster_apply(p->p.dev, static_cast<float *>(inv), static_cast<const double *>(d_v), static_cast<double *>(d_z),
+                      st);
+        AFS_HIP(hipFreeAsync(inv, st));
+        return AFSBEM_OK;
+    });
+}
+
 int afsbem_solve_opts_default(afsbem_solve_opts *o) {
     if (!o) {
         set_error("null opts");
@@ -301,6 +334,7 @@ int afsbem_solve_opts_default(afsbem_solve_opts *o) {
     o->fault_inject = 0;
     o->profile = 0;
     o->learn_steps = 0;
+    o->precond = 0;
     return AFSBEM_OK;
 }
 
@@ -321,6 +355,7 @@ int afsbem_solve_device(afsbem_problem *p, int32_t n_s, const double *s, const v
         AFS_REQUIRE(o.warm_start != AFSBEM_WARM_USER || d_x0, AFSBEM_EINVAL, "user warm start needs x0");
         AFS_REQUIRE(o.warm_start >= AFSBEM_WARM_NONE && o.warm_start <= AFSBEM_WARM_LEARNED, AFSBEM_EINVAL,
                     "unknown warm start");
+        AFS_REQUIRE(o.precond == 0 || o.precond == 1, AFSBEM_EINVAL, "precond must be 0 or 1");
         AFS_REQUIRE(o.warm_start != AFSBEM_WARM_LEARNED || d_a_out, AFSBEM_EINVAL,
                     "the learned warm start needs the solution output buffer");
         hipStream_t st = static_cast<hipStream_t>(hip_stream);

@@ -44,6 +44,8 @@ MaterialDerived derive_material(const afsbem_material &m);
 // Per-element source record read with wave-uniform (scalar) loads by the far
 // field kernel: 7 quadrature nodes (x, y, z, weight*area), unit normal, kind.
 constexpr int kFarNodes = 7;
+constexpr int kClusterElems = 24;                  // elements per preconditioner cluster (at most)
+constexpr int kClusterDim = 3 * kClusterElems;      // unknowns per cluster block (at most)
 constexpr int kSrcStride = 32;  // doubles per element record
 
 struct HostPlan {
@@ -68,6 +70,9 @@ struct HostPlan {
     std::vector<double> self_cpv;  // [n][9] principal value of the static 1/r^2 part (real)
     std::vector<double> gl_rho;    // [n_rho][2]: node in [0,1], weight on [0,1]
     std::vector<double> coef;      // [16][4]: a_n, b_n, (n-1) a_n, (n-1) b_n
+    // preconditioner clusters (recursive coordinate bisection of the centroids)
+    std::vector<int64_t> clus_ptr; // [n_clusters+1]
+    std::vector<int32_t> clus_elem;// [n] elements grouped by cluster
 };
 
 void build_plan(const double *xyz, int64_t nv, const int32_t *tri, int64_t nt, const int8_t *kind,
@@ -89,6 +94,9 @@ struct DevicePlan {
     double *self_ang = nullptr, *self_cpv = nullptr, *gl_rho = nullptr;
     double *nrm = nullptr;         // [n][3]
     double *coef = nullptr;        // [16][4] series coefficients of the radial functions
+    int64_t n_clusters = 0;
+    int64_t *clus_ptr = nullptr;
+    int32_t *clus_elem = nullptr;
 };
 
 // -------------------------------------------------------------- problem --
@@ -156,5 +164,10 @@ void vec_combine(int64_t N, int nv, const double *V, int64_t ldv, const double *
 void vec_split_ut(int64_t n_tri, const int8_t *kind, const double *a, const double *bc, double *u,
                   double *t, hipStream_t st);
 int mdot_blocks(int64_t N);
+
+// cluster block-Jacobi preconditioner: inverses [n_clusters][kClusterDim^2]
+// complex<float>; z = M^-1 v
+void cluster_inverse(const DevicePlan &d, int format, const void *A, const void *A_lo, float *inv, hipStream_t st);
+void cluster_apply(const DevicePlan &d, const float *inv, const double *v, double *z, hipStream_t st);
 
 }  // namespace afsbem

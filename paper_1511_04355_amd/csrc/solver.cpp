@@ -37,7 +37,7 @@ Workspace::~Workspace() { release(); }
 void Workspace::release() {
     for (void *p : {(void *)A, (void *)A_lo, (void *)b, (void *)precond, (void *)asm_scratch, (void *)gemv_partial,
                     (void *)V, (void *)w, (void *)z, (void *)x, (void *)r, (void *)tmp, (void *)rin, (void *)xo,
-                    (void *)dots_partial, (void *)small, (void *)one})
+                    (void *)dots_partial, (void *)small, (void *)one, (void *)clinv})
         if (p)
             (void)hipFree(p);
     if (host_small)
@@ -55,14 +55,33 @@ void Workspace::release() {
     A = A_lo = asm_scratch = nullptr;
     b = precond = gemv_partial = V = w = z = x = r = tmp = rin = xo = nullptr;
     dots_partial = small = one = host_small = nullptr;
+    clinv = nullptr;
+    prec_kind = 0;
+    plan = nullptr;
 }
 
-void Workspace::ensure(const Problem &p, int format, int restart_m) {
+void Workspace::apply_precond(const double *v, double *z, hipStream_t st) const {
+    if (prec_kind == 1)
+        cluster_apply(*plan, clinv, v, z, st);
+    else
+        vec_precond(plan->n_tri, precond, v, z, st);
+}
+
+void Workspace::ensure(const Problem &p, int format, int restart_m, int prec) {
     const int64_t nt = p.dev.n_tri, N = 3 * nt;
     const int64_t lda = (N + 63) / 64 * 64;
-    if (N == this->N && format == this->format && restart_m <= this->m && A)
+    plan = &p.dev;
+    if (N == this->N && format == this->format && restart_m <= this->m && A) {
+        if (prec == 1 && !clinv)
+            clinv = (float *)dalloc((size_t)std::max<int64_t>(p.dev.n_clusters, 1) * kClusterDim * kClusterDim * 8);
+        prec_kind = prec;
         return;
+    }
     release();
+    plan = &p.dev;
+    prec_kind = prec;
+    if (prec == 1)
+        clinv = (float *)dalloc((size_t)std::max<int64_t>(p.dev.n_clusters, 1) * kClusterDim * kClusterDim * 8);
     this->N = N;
     this->format = format;
     this->m = restart_m;
@@ -170,7 +189,7 @@ GmresResult gmres(const Operator &op, Workspace &ws, int64_t n_tri, const double
         int k = 0;
         for (int j = 0; j < restart; ++j) {
             double *vj = ws.V + 2 * (int64_t)j * N;
-            vec_precond(n_tri, ws.precond, vj, ws.z, st);
+            ws.apply_precond(vj, ws.z, st);
             op.apply(ws.z, ws.w, st);
             // classical Gram-Schmidt, twice
             vec_mdot(N, j + 1, ws.V, N, ws.w, ws.dots_partial, hbuf, st);
@@ -233,7 +252,7 @@ GmresResult gmres(const Operator &op, Workspace &ws, int64_t n_tri, const double
         AFS_HIP(hipMemcpyAsync(hbuf, host, (size_t)k * 16, hipMemcpyHostToDevice, st));
         AFS_HIP(hipMemsetAsync(ws.tmp, 0, (size_t)N * 16, st));
         vec_combine(N, k, ws.V, N, hbuf, ws.tmp, st);
-        vec_precond(n_tri, ws.precond, ws.tmp, ws.z, st);
+        ws.apply_precond(ws.tmp, ws.z, st);
         if (x_is_zero) {
             AFS_HIP(hipMemcpyAsync(x, ws.z, (size_t)N * 16, hipMemcpyDeviceToDevice, st));
             x_is_zero = false;
@@ -372,6 +391,8 @@ static void assemble_into(Problem &p, Workspace &ws, int fmt, double s_re, doubl
                           hipStream_t st) {
     KernelParams kp = kernel_params(p.mat, s_re, s_im);
     launch_assembly(p, kp, d_bc, fmt, ws.A, ws.A_lo, ws.b, ws.precond, ws.asm_scratch, st);
+    if (ws.prec_kind == 1)
+        cluster_inverse(p.dev, fmt, ws.A, ws.A_lo, ws.clinv, st);
 }
 
 // Krylov phase of one frequency on an assembled workspace (stream st); the
@@ -497,7 +518,7 @@ int solve_one(Problem &p, const afsbem_solve_opts &o, double s_re, double s_im, 
     if (!p.ws)
         p.ws = new Workspace();
     Workspace &ws = *p.ws;
-    ws.ensure(p, fmt, o.restart);
+    ws.ensure(p, fmt, o.restart, o.precond);
     hipEvent_t e0, e1, e2;
     AFS_HIP(hipEventCreate(&e0));
     AFS_HIP(hipEventCreate(&e1));
@@ -535,8 +556,8 @@ int solve_pipelined(Problem &p, const afsbem_solve_opts &o, int32_t n_s, const d
     if (!p.ws2)
         p.ws2 = new Workspace();
     Workspace *W[2] = {p.ws, p.ws2};
-    W[0]->ensure(p, fmt, o.restart);
-    W[1]->ensure(p, fmt, o.restart);
+    W[0]->ensure(p, fmt, o.restart, o.precond);
+    W[1]->ensure(p, fmt, o.restart, o.precond);
     if (!p.st_asm)
         AFS_HIP(hipStreamCreateWithFlags(&p.st_asm, hipStreamNonBlocking));
     if (!p.st_sol)

@@ -16,6 +16,11 @@ struct Workspace {
     double *rin = nullptr, *xo = nullptr;  // mixed: outer residual and outer iterate
     double *dots_partial = nullptr, *small = nullptr;
     double *one = nullptr;                 // device complex 1 + 0i
+    // preconditioner: 0 = 3x3 blocks (precond), 1 = element clusters (clinv)
+    int prec_kind = 0;
+    float *clinv = nullptr;
+    const DevicePlan *plan = nullptr;
+    void apply_precond(const double *v, double *z, hipStream_t st) const;
     double *host_small = nullptr;          // pinned
     // GEMV timing (opts.profile): event pairs recorded around each product
     std::vector<hipEvent_t> ev;            // 2 per slot
@@ -24,7 +29,7 @@ struct Workspace {
     void reset_timing() { ev_used = 0; ev_prec.clear(); }
     ~Workspace();
     void release();
-    void ensure(const Problem &p, int format, int restart_m);
+    void ensure(const Problem &p, int format, int restart_m, int prec_kind = 0);
 };
 
 // y = A x with a stored matrix: precision 0 = FP64 (C128, or hi+lo of SPLIT),

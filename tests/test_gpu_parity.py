@@ -212,3 +212,49 @@ def test_solve_warm_starts(prec):
         for sol, st in ((a[k], out["stats"][k]), (a2[k], out2["stats"][k])):
             assert st["rel_res_fp64"] <= 1e-8
             assert np.linalg.norm(sol - xo) / np.linalg.norm(xo) <= 1e-6
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("mesh_name", ["cavity_L2", "rod"])
+def test_solve_cluster_preconditioner(prec, mesh_name):
+    """Block-diagonal preconditioning over element clusters reaches the same
+    discrete solutions (mixed boundary conditions included)."""
+    afs, bem = _afs(), _oracle()
+    mesh = MESHES[mesh_name]()
+    mat = (1.0, 0.0, 1.0) if mesh_name == "rod" else (1.0, 0.25, 1.0)
+    s = np.array([0.25 + 0.4j, 0.3 + 2.2j, 0.25 + 4.0j])
+    bc = np.stack([np.asarray(mesh.bc_shape, np.complex128) / sk for sk in s])
+    P = afs.Problem.from_mesh(mesh, material=mat)
+    p = afs.PREC_FP64 if prec == "fp64" else afs.PREC_MIXED
+    out = P.solve(s, torch.from_numpy(bc).cuda(), afs.SolveOptions(tol=1e-8, precision=p, precond=1))
+    base = P.solve(s, torch.from_numpy(bc).cuda(), afs.SolveOptions(tol=1e-8, precision=p, precond=0))
+    a = out["a"].cpu().numpy()
+    for k, sk in enumerate(s):
+        A, b = bem.assemble(mesh, sk, bc[k], mat=mat)
+        xo = bem.solve_dense(A, b)
+        assert out["stats"][k]["rel_res_fp64"] <= 1e-8
+        assert np.linalg.norm(a[k] - xo) / np.linalg.norm(xo) <= 1e-6
+    print("cluster vs point preconditioner iterations:", sum(x["iters"] for x in out["stats"]),
+          sum(x["iters"] for x in base["stats"]), flush=True)
+
+
+def test_cluster_preconditioner_blocks():
+    """The clusters partition the elements (at most 24 each) and M^-1 v equals
+    the block-diagonal inverse over them (FP32 inverses: 1e-5)."""
+    afs, bem = _afs(), _oracle()
+    mesh = mg.cavity(2)
+    s = 0.25 + 1.5j
+    P = afs.Problem.from_mesh(mesh)
+    ptr, elem = P.clusters()
+    assert np.array_equal(np.sort(elem), np.arange(mesh.n_tri))
+    assert np.all(np.diff(ptr) >= 1) and np.all(np.diff(ptr) <= 24)
+    A, _, _, _ = P.assemble(s, _bc_dev(mesh, s), fmt=afs.FMT_C128)
+    Ao = _dense_from_colmajor(A, P.N)
+    rng = np.random.default_rng(1)
+    v = rng.standard_normal(P.N) + 1j * rng.standard_normal(P.N)
+    z = P.precond_apply(A, None, torch.from_numpy(v).cuda()).cpu().numpy()
+    zr = np.zeros_like(v)
+    for c in range(len(ptr) - 1):
+        idx = (3 * elem[ptr[c]:ptr[c + 1]][:, None] + np.arange(3)[None]).reshape(-1)
+        zr[idx] = np.linalg.solve(Ao[np.ix_(idx, idx)], v[idx])
+    assert np.linalg.norm(z - zr) / np.linalg.norm(zr) < 1e-5
