@@ -195,6 +195,31 @@ int afsbem_solve_device(afsbem_problem *p, int32_t n_s, const double *s, const v
                         const void *d_x0, void *d_a_out, void *d_u_out, void *d_t_out,
                         const afsbem_solve_opts *opts, afsbem_solve_stats *stats, void *hip_stream);
 
+/* Batched solve of many independent systems: every frequency of every problem
+ * in the call (several meshes of uneven size allowed, all on the current
+ * device).  The per-frequency operation is the one of afsbem_solve_device
+ * (collocation system of Sec. 2 at each Laplace parameter); here the systems
+ * advance in lockstep, one kernel launch per Krylov step serving all of them,
+ * which keeps the device full when single systems are small.
+ *   probs[p], n_s[p]: problem handles and their frequency counts.
+ *   s: host array, 2 * sum(n_s) doubles, the frequencies of problem 0, then
+ *      of problem 1, ...
+ *   d_bc_val[p]: [n_s[p]][n_tri_p][3] complex<double> device array.
+ *   d_a_out[p], d_u_out[p], d_t_out[p]: nullable device outputs, layouts as
+ *      in afsbem_solve_device; the pointer arrays themselves may be null.
+ *   stats: nullable host array of sum(n_s) entries, same order as s.
+ * Options: tol, restart, max_iter, precision (FP64, or MIXED: FP32 hi-plane
+ * inner cycles with FP64 residuals); opts.batch > 1 caps the systems solved
+ * together (default: as many as fit in 60 % of free device memory, at most
+ * 64).  Warm starts and the cluster preconditioner are not available here
+ * (AFSBEM_EINVAL).  Work is ordered on hip_stream; the call returns after
+ * the outputs are written.  Returns AFSBEM_ENOCONV if any system missed the
+ * tolerance. */
+int afsbem_solve_batched_device(int32_t n_prob, afsbem_problem *const *probs, const int32_t *n_s,
+                                const double *s, const void *const *d_bc_val, void *const *d_a_out,
+                                void *const *d_u_out, void *const *d_t_out, const afsbem_solve_opts *opts,
+                                afsbem_solve_stats *stats, void *hip_stream);
+
 
 /* ======================================================= learned warm start
  * A multilayer perceptron (not part of the paper) that maps per-element

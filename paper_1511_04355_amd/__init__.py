@@ -17,6 +17,7 @@ from ._lib import (  # noqa: F401
     WARM_LEARNED,
     Problem,
     SolveOptions,
+    solve_batched,
     lib,
     lib_path,
     version,

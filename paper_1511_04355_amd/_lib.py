@@ -88,6 +88,7 @@ def lib():
         L.afsbem_problem_clusters.argtypes = [P, P, P, P]
         L.afsbem_precond_apply_device.argtypes = [P, ctypes.c_int, P, P, P, P, P]
         L.afsbem_solve_device.argtypes = [P, i32, P, P, P, P, P, P, P, P, P]
+        L.afsbem_solve_batched_device.argtypes = [i32, P, P, P, P, P, P, P, P, P, P]
         L.afsbem_mlp_n_params.argtypes = [i32, i32, i32, P]
         L.afsbem_mlp_forward.argtypes = [i32, i32, i32, i32, P, P, P, ctypes.c_int, P]
         L.afsbem_mlp_loss_grad.argtypes = [i32, i32, i32, i32, P, P, P, P, P, ctypes.c_int, P]
@@ -281,6 +282,46 @@ class Problem:
         out["status"] = rc
         out["stats"] = [{f: getattr(stats[k], f) for f, _ in _Stats._fields_} for k in range(ns)]
         return out
+
+
+def solve_batched(problems, s_lists, bc_vals, opts: SolveOptions | None = None, want_ut=False):
+    """Lockstep solve of every frequency of every problem (meshes may differ
+    in size).  problems: list of Problem; s_lists[p]: its frequencies;
+    bc_vals[p]: complex128 cuda [n_s_p, n_tri_p, 3].  Returns a list of dicts
+    (a, u, t, stats) per problem and the return code."""
+    import torch
+    opts = opts or SolveOptions()
+    n = len(problems)
+    handles = (ctypes.c_void_p * max(n, 1))(*[p._h for p in problems])
+    ns = np.array([len(s) for s in s_lists], np.int32)
+    s_all = np.concatenate([np.asarray(s, np.complex128).reshape(-1) for s in s_lists]) if n else np.zeros(0)
+    s_arr = np.ascontiguousarray(np.stack([s_all.real, s_all.imag], axis=1), np.float64)
+    outs, keep = [], []
+    for p, s, bc in zip(problems, s_lists, bc_vals):
+        bc = bc.contiguous()
+        assert bc.dtype == torch.complex128 and bc.numel() == len(s) * p.N and bc.is_cuda
+        o = {"a": torch.empty((len(s), p.N), dtype=torch.complex128, device="cuda"), "bc": bc}
+        if want_ut:
+            o["u"] = torch.empty((len(s), p.n_tri, 3), dtype=torch.complex128, device="cuda")
+            o["t"] = torch.empty((len(s), p.n_tri, 3), dtype=torch.complex128, device="cuda")
+        outs.append(o)
+
+    def arr(key):
+        return (ctypes.c_void_p * max(n, 1))(*[_ptr(o.get(key)) for o in outs])
+
+    total = int(ns.sum())
+    stats = (_Stats * max(total, 1))()
+    c = opts._c()
+    rc = lib().afsbem_solve_batched_device(n, handles, ns.ctypes.data, s_arr.ctypes.data, arr("bc"), arr("a"),
+                                           arr("u") if want_ut else None, arr("t") if want_ut else None,
+                                           ctypes.byref(c), stats, _stream())
+    _check(rc, allow=(ENOCONV,))
+    k = 0
+    for o, m in zip(outs, ns):
+        o.pop("bc")
+        o["stats"] = [{f: getattr(stats[k + q], f) for f, _ in _Stats._fields_} for q in range(int(m))]
+        k += int(m)
+    return outs, rc
 
 
 # ------------------------------------------------------------------- drivers

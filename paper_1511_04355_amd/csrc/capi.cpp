@@ -6,6 +6,7 @@
 #include "internal.hpp"
 #include "solver.hpp"
 #include "mlp.hpp"
+#include "batched.hpp"
 
 struct afsbem_mesh {
     std::vector<double> xyz;
@@ -389,6 +390,56 @@ int afsbem_solve_device(afsbem_problem *p, int32_t n_s, const double *s, const v
         }
         if (rc == AFSBEM_ENOCONV)
             set_error("at least one frequency did not reach the tolerance");
+        return rc;
+    });
+}
+
+int afsbem_solve_batched_device(int32_t n_prob, afsbem_problem *const *probs, const int32_t *n_s,
+                                const double *s, const void *const *d_bc_val, void *const *d_a_out,
+                                void *const *d_u_out, void *const *d_t_out, const afsbem_solve_opts *opts,
+                                afsbem_solve_stats *stats, void *hip_stream) {
+    return guarded([&] {
+        AFS_REQUIRE(n_prob >= 0, AFSBEM_EINVAL, "n_prob must be >= 0");
+        AFS_REQUIRE(n_prob == 0 || (probs && n_s && d_bc_val), AFSBEM_EINVAL, "null pointer argument");
+        afsbem_solve_opts o;
+        afsbem_solve_opts_default(&o);
+        if (opts)
+            o = *opts;
+        AFS_REQUIRE(o.tol > 0 && o.restart >= 1 && o.restart <= 500 && o.max_iter >= 1, AFSBEM_EINVAL,
+                    "invalid solver options");
+        AFS_REQUIRE(o.precision == AFSBEM_PREC_FP64 || o.precision == AFSBEM_PREC_MIXED, AFSBEM_EINVAL,
+                    "unknown precision");
+        AFS_REQUIRE(o.warm_start == AFSBEM_WARM_NONE, AFSBEM_EINVAL, "the batched solve takes no warm start");
+        AFS_REQUIRE(o.precond == 0, AFSBEM_EINVAL, "the batched solve uses the point block-Jacobi preconditioner");
+        int dev = 0;
+        AFS_HIP(hipGetDevice(&dev));
+        std::vector<Problem *> pp(n_prob);
+        std::vector<const double *> bc(n_prob);
+        std::vector<double *> a(n_prob, nullptr), u(n_prob, nullptr), t(n_prob, nullptr);
+        int64_t total = 0;
+        for (int32_t q = 0; q < n_prob; ++q) {
+            AFS_REQUIRE(probs[q] && n_s[q] >= 0, AFSBEM_EINVAL, "null problem or negative n_s");
+            AFS_REQUIRE(probs[q]->p.device == dev, AFSBEM_EINVAL, "all problems must live on the current device");
+            AFS_REQUIRE(n_s[q] == 0 || d_bc_val[q], AFSBEM_EINVAL, "null d_bc_val entry");
+            pp[q] = &probs[q]->p;
+            bc[q] = static_cast<const double *>(d_bc_val[q]);
+            if (d_a_out)
+                a[q] = static_cast<double *>(d_a_out[q]);
+            if (d_u_out)
+                u[q] = static_cast<double *>(d_u_out[q]);
+            if (d_t_out)
+                t[q] = static_cast<double *>(d_t_out[q]);
+            total += n_s[q];
+        }
+        AFS_REQUIRE(total == 0 || s, AFSBEM_EINVAL, "null s");
+        for (int64_t k = 0; k < total; ++k)
+            AFS_REQUIRE(std::isfinite(s[2 * k]) && std::isfinite(s[2 * k + 1]), AFSBEM_EINVAL, "non-finite s");
+        if (total == 0)
+            return (int)AFSBEM_OK;
+        const int rc = solve_batched(n_prob, pp.data(), n_s, s, bc.data(), a.data(), u.data(), t.data(), o, stats,
+                                     static_cast<hipStream_t>(hip_stream));
+        if (rc == AFSBEM_ENOCONV)
+            set_error("at least one system did not reach the tolerance");
         return rc;
     });
 }
