@@ -1,12 +1,15 @@
 // Batched solve: all (problem, frequency) systems of a call are packed into
-// waves that fit in device memory; each wave is assembled (four library
-// streams, systems round-robin) and then solved in lockstep.  Outer step for
-// every system: r = b - A x with the FP64 operator, stop when ||r|| <= tol ||b||;
-// otherwise one right-preconditioned GMRES cycle (up to m steps, classical
-// Gram-Schmidt twice) on r with the inner operator (FP64, or the FP32 hi plane
-// in the mixed path) gives the correction added to x.  One launch per step
-// serves every system; converged systems are masked out; the host checks the
-// number of systems still iterating every four steps.
+// waves; a wave is assembled on four library streams (systems round-robin)
+// and then solved in lockstep on a fifth.  Two wave slots alternate, so the
+// assembly of wave w+1 (ALU-bound) runs while wave w is solved (HBM-bound).
+//
+// Lockstep solve, for every system of the wave: r = b - A x with the FP64
+// operator; stop when ||r|| <= tol ||b||; otherwise one right-preconditioned
+// GMRES cycle (up to m steps, classical Gram-Schmidt twice) on r with the
+// inner operator (FP64, or the FP32 hi plane in the mixed path) gives the
+// correction added to x.  One launch per step serves every system; finished
+// systems are masked out; the host polls the number of systems still in the
+// cycle every four steps.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -16,36 +19,187 @@
 
 namespace afsbem {
 
+BatchArena::~BatchArena() {
+    if (base)
+        (void)hipFree(base);
+    for (auto &q : st_asm)
+        if (q)
+            (void)hipStreamDestroy(q);
+    if (st_sol)
+        (void)hipStreamDestroy(st_sol);
+}
+
+void BatchArena::reserve(size_t bytes) {
+    if (!st_sol) {
+        for (auto &q : st_asm)
+            AFS_HIP(hipStreamCreateWithFlags(&q, hipStreamNonBlocking));
+        AFS_HIP(hipStreamCreateWithFlags(&st_sol, hipStreamNonBlocking));
+    }
+    if (bytes <= cap)
+        return;
+    if (base) {
+        AFS_HIP(hipDeviceSynchronize());
+        (void)hipFree(base);
+        base = nullptr;
+        cap = 0;
+    }
+    hipError_t e = hipMalloc(&base, bytes);
+    if (e != hipSuccess) {
+        base = nullptr;
+        throw Error{AFSBEM_ENOMEM, "hipMalloc(" + std::to_string(bytes) + ") failed: " + hipGetErrorString(e)};
+    }
+    cap = bytes;
+}
+
 namespace {
 
-struct Pool {
-    std::vector<void *> ptrs;
-    ~Pool() {
-        for (void *p : ptrs)
-            (void)hipFree(p);
-    }
+struct SysRef {
+    int prob, k;
+    int64_t nt, N, lda;
+};
+
+// Sub-allocation of one slot: regions aligned to 256 bytes.
+struct Carve {
+    char *base;
+    size_t off = 0;
     template <class T>
     T *get(size_t count) {
-        void *p = nullptr;
-        const size_t bytes = std::max<size_t>(count * sizeof(T), 16);
-        hipError_t e = hipMalloc(&p, bytes);
-        if (e != hipSuccess)
-            throw Error{AFSBEM_ENOMEM, "hipMalloc(" + std::to_string(bytes) + ") failed: " + hipGetErrorString(e)};
-        ptrs.push_back(p);
-        return static_cast<T *>(p);
+        off = (off + 255) / 256 * 256;
+        T *p = reinterpret_cast<T *>(base + off);
+        off += std::max<size_t>(count * sizeof(T), 16);
+        return p;
     }
 };
+
+// Everything one wave needs on the device, carved from a slot.
+struct Wave {
+    int first = 0, B = 0;
+    BatchDev bd;
+    std::vector<void *> A, Alo;
+    std::vector<int64_t> elem_off;
+    double *b = nullptr, *x = nullptr, *r = nullptr, *w = nullptr, *z = nullptr, *tmp = nullptr, *V = nullptr;
+    double *h1 = nullptr, *h2 = nullptr, *nrm = nullptr, *yv = nullptr, *ones = nullptr, *tolv = nullptr;
+    int *active = nullptr, *cyc = nullptr, *cnt = nullptr;
+    void *scr[4] = {nullptr, nullptr, nullptr, nullptr};
+    // host copies of the metadata (kept until the wave is done)
+    std::vector<BSys> hs;
+    std::vector<int32_t> sor, chunk_ptr;
+    std::vector<int4> it128, it64, chunks;
+    std::vector<double> onesh;
+    hipEvent_t asm_begin = nullptr, asm_end = nullptr;
+    float t_asm = 0.f;
+};
+
+// Lays out a wave of systems all[first, first + B) in a slot starting at
+// base (nullptr: only measure); returns the bytes used.
+size_t layout(Wave &W, const std::vector<SysRef> &all, Problem *const *probs, int first, int B, int m, bool mixed,
+              char *base) {
+    W.first = first;
+    W.B = B;
+    BatchDev &bd = W.bd;
+    bd = BatchDev();
+    bd.B = B;
+    bd.nvmax = m + 2;
+    W.hs.assign(B, BSys{});
+    W.elem_off.assign(B + 1, 0);
+    W.it128.clear();
+    W.it64.clear();
+    W.chunks.clear();
+    W.chunk_ptr.assign(B + 1, 0);
+    int64_t Ntot = 0, part = 0;
+    size_t scratch_max = 0;
+    for (int j = 0; j < B; ++j) {
+        const SysRef &r = all[first + j];
+        BSys &q = W.hs[j];
+        q.N = r.N;
+        q.off = Ntot;
+        q.lda = r.lda;
+        const int64_t rb128 = (r.N + 255) / 256, rb64 = ((r.N + 1) / 2 + 255) / 256;
+        // split the columns so that the wave offers about 4096 work-groups
+        int64_t S = (4096 + (int64_t)B * rb128 - 1) / ((int64_t)B * rb128);
+        S = std::max<int64_t>(1, std::min<int64_t>(S, std::max<int64_t>(1, r.N / 64)));
+        q.chunk = (r.N + S - 1) / S;
+        q.S = (int)((r.N + q.chunk - 1) / q.chunk);
+        q.part_off = part;
+        part += (int64_t)q.S * r.N;
+        for (int64_t rb = 0; rb < rb128; ++rb)
+            for (int c = 0; c < q.S; ++c)
+                W.it128.push_back(make_int4(j, (int)rb, c, 0));
+        for (int64_t rb = 0; rb < rb64; ++rb)
+            for (int c = 0; c < q.S; ++c)
+                W.it64.push_back(make_int4(j, (int)rb, c, 0));
+        W.chunk_ptr[j] = (int32_t)W.chunks.size();
+        for (int64_t r0 = 0; r0 < r.N; r0 += 2048)
+            W.chunks.push_back(
+                make_int4(j, (int)(Ntot + r0), (int)(Ntot + std::min<int64_t>(r0 + 2048, r.N)), 0));
+        Ntot += r.N;
+        W.elem_off[j + 1] = W.elem_off[j] + r.nt;
+        scratch_max = std::max(scratch_max, assembly_scratch_bytes(*probs[r.prob]));
+    }
+    W.chunk_ptr[B] = (int32_t)W.chunks.size();
+    AFS_REQUIRE(Ntot < ((int64_t)1 << 31), AFSBEM_EINVAL, "batched wave too large");
+    bd.Ntot = Ntot;
+    Carve c{base};
+    W.A.assign(B, nullptr);
+    W.Alo.assign(B, nullptr);
+    for (int j = 0; j < B; ++j) {
+        const size_t plane = (size_t)W.hs[j].N * W.hs[j].lda * (mixed ? 8 : 16);
+        W.A[j] = c.get<char>(plane);
+        if (mixed)
+            W.Alo[j] = c.get<char>(plane);
+        W.hs[j].A = W.A[j];
+        W.hs[j].A_lo = W.Alo[j];
+    }
+    const int ldh = bd.nvmax;
+    W.b = c.get<double>(2 * Ntot);
+    W.x = c.get<double>(2 * Ntot);
+    W.r = c.get<double>(2 * Ntot);
+    W.w = c.get<double>(2 * Ntot);
+    W.z = c.get<double>(2 * Ntot);
+    W.tmp = c.get<double>(2 * Ntot);
+    W.V = c.get<double>((size_t)2 * Ntot * (m + 1));
+    bd.precond = c.get<double>((size_t)18 * W.elem_off[B]);
+    bd.partial = c.get<double>((size_t)2 * part);
+    bd.dot_partial = c.get<double>((size_t)2 * W.chunks.size() * bd.nvmax);
+    bd.sys = c.get<BSys>(B);
+    bd.sys_of_row = c.get<int32_t>(Ntot);
+    bd.items128 = c.get<int4>(W.it128.size());
+    bd.items64 = c.get<int4>(W.it64.size());
+    bd.n_items128 = (int64_t)W.it128.size();
+    bd.n_items64 = (int64_t)W.it64.size();
+    bd.chunks = c.get<int4>(W.chunks.size());
+    bd.n_chunks = (int64_t)W.chunks.size();
+    bd.chunk_ptr = c.get<int32_t>(B + 1);
+    bd.H = c.get<double>((size_t)2 * B * (m + 1) * m);
+    bd.g = c.get<double>((size_t)2 * B * (m + 1));
+    bd.cs = c.get<double>((size_t)B * m);
+    bd.sn = c.get<double>((size_t)2 * B * m);
+    bd.est = c.get<double>(B);
+    bd.kdone = c.get<int>(B);
+    W.h1 = c.get<double>((size_t)2 * B * ldh);
+    W.h2 = c.get<double>((size_t)2 * B * ldh);
+    W.nrm = c.get<double>((size_t)2 * B);
+    W.yv = c.get<double>((size_t)2 * B * ldh);
+    W.ones = c.get<double>((size_t)2 * B);
+    W.tolv = c.get<double>(B);
+    W.active = c.get<int>(B);
+    W.cyc = c.get<int>(B);
+    W.cnt = c.get<int>(1);
+    for (auto &s : W.scr)
+        s = c.get<char>(scratch_max);
+    return c.off + 256;
+}
+
+size_t system_bytes(const SysRef &r, int m, bool mixed) {
+    (void)mixed;
+    return (size_t)r.N * r.lda * 16 + (size_t)r.N * (m + 8) * 16 + (size_t)r.nt * 144;
+}
 
 template <class T>
 void up(T *d, const std::vector<T> &h, hipStream_t st) {
     if (!h.empty())
         AFS_HIP(hipMemcpyAsync(d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, st));
 }
-
-struct SysRef {
-    int prob, k;
-    int64_t nt, N, lda;
-};
 
 }  // namespace
 
@@ -64,163 +218,129 @@ int solve_batched(int n_prob, Problem *const *probs, const int32_t *n_s, const d
             all.push_back({p, k, nt, N, (N + 63) / 64 * 64});
         }
     }
+    if (all.empty())
+        return AFSBEM_OK;
+    Problem &owner = *probs[0];
+    if (!owner.barena)
+        owner.barena = new BatchArena();
+    BatchArena &ar = *owner.barena;
+    // slot budget: a few GiB keep the HBM busy; never more than a share of
+    // the free memory; at least the largest single system
     size_t free_b = 0, total_b = 0;
     AFS_HIP(hipMemGetInfo(&free_b, &total_b));
-    const double budget = 0.6 * (double)free_b;
+    const double avail = (double)free_b + (double)ar.cap;
+    double slot_budget = std::min(0.3 * avail, 16.0 * (1 << 30));
     const int max_b = o.batch > 1 ? o.batch : 64;
-    hipStream_t as[4];
-    for (auto &q : as)
-        AFS_HIP(hipStreamCreateWithFlags(&q, hipStreamNonBlocking));
-    struct StreamGuard {
-        hipStream_t *q;
-        ~StreamGuard() {
-            for (int i = 0; i < 4; ++i)
-                (void)hipStreamDestroy(q[i]);
-        }
-    } sg{as};
-    hipEvent_t entry;
-    AFS_HIP(hipEventCreate(&entry));
-    AFS_HIP(hipEventRecord(entry, caller));
-    int rc_all = AFSBEM_OK;
-    size_t first = 0;
-    while (first < all.size()) {
-        // ---- pack a wave
-        size_t last = first;
+    // ---- pack the waves
+    std::vector<std::pair<int, int>> waves;
+    for (size_t f = 0; f < all.size();) {
+        size_t l = f;
         double bytes = 0.0;
-        while (last < all.size() && (int)(last - first) < max_b) {
-            const SysRef &r = all[last];
-            const double need = (double)r.N * r.lda * 16.0 + (double)r.N * (m + 12) * 16.0 +
-                                (double)assembly_scratch_bytes(*probs[r.prob]) / 4.0;
-            if (last > first && bytes + need > budget)
+        while (l < all.size() && (int)(l - f) < max_b) {
+            const double need = (double)system_bytes(all[l], m, mixed);
+            if (l > f && bytes + need > slot_budget)
                 break;
             bytes += need;
-            ++last;
+            ++l;
         }
-        const int B = (int)(last - first);
-        Pool pool;
-        BatchDev bd;
-        bd.B = B;
-        bd.nvmax = m + 2;
-        std::vector<BSys> hs(B);
-        std::vector<int64_t> elem_off(B + 1, 0);
-        int64_t Ntot = 0, part = 0;
-        std::vector<int4> it128, it64, chunks;
-        std::vector<int32_t> chunk_ptr(B + 1, 0);
-        for (int j = 0; j < B; ++j) {
-            const SysRef &r = all[first + j];
-            BSys &q = hs[j];
-            q.N = r.N;
-            q.off = Ntot;
-            q.lda = r.lda;
-            const int64_t rb128 = (r.N + 255) / 256, rb64 = ((r.N + 1) / 2 + 255) / 256;
-            int64_t S = (4096 + (int64_t)B * rb128 - 1) / ((int64_t)B * rb128);
-            S = std::max<int64_t>(1, std::min<int64_t>(S, std::max<int64_t>(1, r.N / 32)));
-            q.chunk = (r.N + S - 1) / S;
-            q.S = (int)((r.N + q.chunk - 1) / q.chunk);
-            q.part_off = part;
-            part += (int64_t)q.S * r.N;
-            for (int64_t rb = 0; rb < rb128; ++rb)
-                for (int c = 0; c < q.S; ++c)
-                    it128.push_back(make_int4(j, (int)rb, c, 0));
-            for (int64_t rb = 0; rb < rb64; ++rb)
-                for (int c = 0; c < q.S; ++c)
-                    it64.push_back(make_int4(j, (int)rb, c, 0));
-            chunk_ptr[j] = (int32_t)chunks.size();
-            for (int64_t r0 = 0; r0 < r.N; r0 += 2048)
-                chunks.push_back(make_int4(j, (int)(Ntot + r0), (int)(Ntot + std::min<int64_t>(r0 + 2048, r.N)), 0));
-            Ntot += r.N;
-            elem_off[j + 1] = elem_off[j] + r.nt;
+        waves.push_back({(int)f, (int)(l - f)});
+        f = l;
+    }
+    const int n_waves = (int)waves.size();
+    Wave slots[2];
+    size_t slot_bytes = 0;
+    for (auto &wv : waves)
+        slot_bytes = std::max(slot_bytes, layout(slots[0], all, probs, wv.first, wv.second, m, mixed, nullptr));
+    slot_bytes = (slot_bytes + 4095) / 4096 * 4096;
+    ar.reserve(slot_bytes * (n_waves > 1 ? 2 : 1));
+    char *slot_base[2] = {static_cast<char *>(ar.base), static_cast<char *>(ar.base) + (n_waves > 1 ? slot_bytes : 0)};
+    hipStream_t st = ar.st_sol;
+    hipEvent_t entry, fin;
+    AFS_HIP(hipEventCreate(&entry));
+    AFS_HIP(hipEventCreateWithFlags(&fin, hipEventDisableTiming));
+    for (auto &W : slots) {
+        AFS_HIP(hipEventCreate(&W.asm_begin));
+        AFS_HIP(hipEventCreate(&W.asm_end));
+    }
+    struct EvGuard {
+        hipEvent_t *e0, *e1;
+        Wave *w;
+        ~EvGuard() {
+            (void)hipEventDestroy(*e0);
+            (void)hipEventDestroy(*e1);
+            for (int i = 0; i < 2; ++i) {
+                (void)hipEventDestroy(w[i].asm_begin);
+                (void)hipEventDestroy(w[i].asm_end);
+            }
         }
-        chunk_ptr[B] = (int32_t)chunks.size();
-        AFS_REQUIRE(Ntot < (int64_t)1 << 31, AFSBEM_EINVAL, "batched wave too large");
-        bd.Ntot = Ntot;
-        // ---- device memory of the wave
-        std::vector<void *> Ap(B), Alo(B, nullptr);
-        for (int j = 0; j < B; ++j) {
-            const size_t plane = (size_t)hs[j].N * hs[j].lda * (mixed ? 8 : 16);
-            Ap[j] = pool.get<char>(plane);
-            if (mixed)
-                Alo[j] = pool.get<char>(plane);
-            hs[j].A = Ap[j];
-            hs[j].A_lo = Alo[j];
-        }
-        double *b = pool.get<double>(2 * Ntot), *x = pool.get<double>(2 * Ntot), *r = pool.get<double>(2 * Ntot);
-        double *w = pool.get<double>(2 * Ntot), *z = pool.get<double>(2 * Ntot), *tmp = pool.get<double>(2 * Ntot);
-        double *V = pool.get<double>((size_t)2 * Ntot * (m + 1));
-        bd.precond = pool.get<double>((size_t)18 * elem_off[B]);
-        bd.partial = pool.get<double>((size_t)2 * part);
-        bd.dot_partial = pool.get<double>((size_t)2 * chunks.size() * bd.nvmax);
-        bd.sys = pool.get<BSys>(B);
-        bd.sys_of_row = pool.get<int32_t>(Ntot);
-        bd.items128 = pool.get<int4>(it128.size());
-        bd.items64 = pool.get<int4>(it64.size());
-        bd.n_items128 = (int64_t)it128.size();
-        bd.n_items64 = (int64_t)it64.size();
-        bd.chunks = pool.get<int4>(chunks.size());
-        bd.n_chunks = (int64_t)chunks.size();
-        bd.chunk_ptr = pool.get<int32_t>(B + 1);
-        bd.H = pool.get<double>((size_t)2 * B * (m + 1) * m);
-        bd.g = pool.get<double>((size_t)2 * B * (m + 1));
-        bd.cs = pool.get<double>((size_t)B * m);
-        bd.sn = pool.get<double>((size_t)2 * B * m);
-        bd.est = pool.get<double>(B);
-        bd.kdone = pool.get<int>(B);
-        const int ldh = bd.nvmax;
-        double *h1 = pool.get<double>((size_t)2 * B * ldh), *h2 = pool.get<double>((size_t)2 * B * ldh);
-        double *nrm = pool.get<double>((size_t)2 * B), *yv = pool.get<double>((size_t)2 * B * ldh);
-        double *ones = pool.get<double>((size_t)2 * B), *tolv = pool.get<double>(B);
-        int *active = pool.get<int>(B), *cyc = pool.get<int>(B), *cnt = pool.get<int>(1);
-        std::vector<int32_t> sor(Ntot);
-        for (int j = 0; j < B; ++j)
-            std::fill(sor.begin() + hs[j].off, sor.begin() + hs[j].off + hs[j].N, j);
-        up(bd.sys, hs, caller);
-        up(bd.sys_of_row, sor, caller);
-        up(bd.items128, it128, caller);
-        up(bd.items64, it64, caller);
-        up(bd.chunks, chunks, caller);
-        up(bd.chunk_ptr, chunk_ptr, caller);
-        std::vector<double> onesh(2 * B, 0.0);
-        for (int j = 0; j < B; ++j)
-            onesh[2 * j] = 1.0;
-        up(ones, onesh, caller);
-        // ---- assembly, round-robin on four streams
-        hipEvent_t ea0, ea1, es1;
-        AFS_HIP(hipEventCreate(&ea0));
-        AFS_HIP(hipEventCreate(&ea1));
-        AFS_HIP(hipEventCreate(&es1));
-        AFS_HIP(hipEventRecord(ea0, caller));
-        size_t scratch_max = 0;
-        for (int j = 0; j < B; ++j)
-            scratch_max = std::max(scratch_max, assembly_scratch_bytes(*probs[all[first + j].prob]));
-        void *scr[4];
-        for (int q = 0; q < 4; ++q)
-            scr[q] = pool.get<char>(scratch_max);
-        std::vector<hipEvent_t> done(4);
-        for (int q = 0; q < 4; ++q) {
-            AFS_HIP(hipEventCreate(&done[q]));
-            AFS_HIP(hipStreamWaitEvent(as[q], ea0, 0));
-        }
-        for (int j = 0; j < B; ++j) {
-            const SysRef &rf = all[first + j];
+    } eg{&entry, &fin, slots};
+    AFS_HIP(hipEventRecord(entry, caller));
+    for (auto q : ar.st_asm)
+        AFS_HIP(hipStreamWaitEvent(q, entry, 0));
+    AFS_HIP(hipStreamWaitEvent(st, entry, 0));
+
+    // launches the assembly of wave wi into its slot
+    auto assemble = [&](int wi) {
+        Wave &W = slots[wi & 1];
+        layout(W, all, probs, waves[wi].first, waves[wi].second, m, mixed, slot_base[wi & 1]);
+        // every assembly stream must be past the previous use of this slot:
+        // the host only gets here after that wave's solve has completed
+        AFS_HIP(hipEventRecord(W.asm_begin, ar.st_asm[0]));
+        for (int q = 1; q < 4; ++q)
+            AFS_HIP(hipStreamWaitEvent(ar.st_asm[q], W.asm_begin, 0));
+        for (int j = 0; j < W.B; ++j) {
+            const SysRef &rf = all[W.first + j];
             const Problem &P = *probs[rf.prob];
             const size_t sidx = (size_t)(s_off[rf.prob] + rf.k);
             const KernelParams kp = kernel_params(P.mat, s[2 * sidx], s[2 * sidx + 1]);
-            launch_assembly(P, kp, bc[rf.prob] + 2 * (size_t)rf.k * rf.N, fmt, Ap[j], Alo[j], b + 2 * hs[j].off,
-                            bd.precond + 18 * elem_off[j], scr[j % 4], as[j % 4]);
+            launch_assembly(P, kp, bc[rf.prob] + 2 * (size_t)rf.k * rf.N, fmt, W.A[j], W.Alo[j],
+                            W.b + 2 * W.hs[j].off, W.bd.precond + 18 * W.elem_off[j], W.scr[j % 4],
+                            ar.st_asm[j % 4]);
         }
-        for (int q = 0; q < 4; ++q) {
-            AFS_HIP(hipEventRecord(done[q], as[q]));
-            AFS_HIP(hipStreamWaitEvent(caller, done[q], 0));
+        for (int q = 1; q < 4; ++q) {
+            hipEvent_t e;
+            AFS_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+            AFS_HIP(hipEventRecord(e, ar.st_asm[q]));
+            AFS_HIP(hipStreamWaitEvent(ar.st_asm[0], e, 0));
+            (void)hipEventDestroy(e);
         }
-        AFS_HIP(hipEventRecord(ea1, caller));
-        hipStream_t st = caller;
-        // ---- lockstep solve
-        const int kin = mixed ? 1 : 0, kout = mixed ? 2 : 0;
-        std::vector<int> act(B, 1), iters(B, 0), outer(B, 0);
-        up(active, act, st);
-        bmdot(bd, active, 1, b, b, nrm, 1, st);
+        AFS_HIP(hipEventRecord(W.asm_end, ar.st_asm[0]));
+    };
+
+    int rc_all = AFSBEM_OK;
+    const int kin = mixed ? 1 : 0, kout = mixed ? 2 : 0;
+    assemble(0);
+    for (int wi = 0; wi < n_waves; ++wi) {
+        Wave &W = slots[wi & 1];
+        if (wi + 1 < n_waves)
+            assemble(wi + 1);  // overlaps the solve below
+        const int B = W.B;
+        BatchDev &bd = W.bd;
+        const int ldh = bd.nvmax;
+        hipEvent_t s0, s1;
+        AFS_HIP(hipEventCreate(&s0));
+        AFS_HIP(hipEventCreate(&s1));
+        // metadata, then wait for the wave's assembly
+        W.sor.resize(bd.Ntot);
+        for (int j = 0; j < B; ++j)
+            std::fill(W.sor.begin() + W.hs[j].off, W.sor.begin() + W.hs[j].off + W.hs[j].N, j);
+        W.onesh.assign(2 * B, 0.0);
+        for (int j = 0; j < B; ++j)
+            W.onesh[2 * j] = 1.0;
+        up(bd.sys, W.hs, st);
+        up(bd.sys_of_row, W.sor, st);
+        up(bd.items128, W.it128, st);
+        up(bd.items64, W.it64, st);
+        up(bd.chunks, W.chunks, st);
+        up(bd.chunk_ptr, W.chunk_ptr, st);
+        up(W.ones, W.onesh, st);
+        AFS_HIP(hipStreamWaitEvent(st, W.asm_end, 0));
+        AFS_HIP(hipEventRecord(s0, st));
+        std::vector<int> act(B, 1), iters(B, 0), outer(B, 0), kd(B);
+        up(W.active, act, st);
+        bmdot(bd, W.active, 1, W.b, W.b, W.nrm, 1, st);
         std::vector<double> hn(2 * B);
-        AFS_HIP(hipMemcpyAsync(hn.data(), nrm, 16 * B, hipMemcpyDeviceToHost, st));
+        AFS_HIP(hipMemcpyAsync(hn.data(), W.nrm, 16 * B, hipMemcpyDeviceToHost, st));
         AFS_HIP(hipStreamSynchronize(st));
         std::vector<double> bnorm(B), rnorm(B), tolh(B);
         for (int j = 0; j < B; ++j) {
@@ -228,55 +348,55 @@ int solve_batched(int n_prob, Problem *const *probs, const int32_t *n_s, const d
             rnorm[j] = bnorm[j];
             tolh[j] = o.tol * bnorm[j];
         }
-        up(tolv, tolh, st);
-        AFS_HIP(hipMemsetAsync(x, 0, (size_t)16 * Ntot, st));
-        AFS_HIP(hipMemcpyAsync(r, b, (size_t)16 * Ntot, hipMemcpyDeviceToDevice, st));
-        std::vector<int> kd(B);
+        up(W.tolv, tolh, st);
+        AFS_HIP(hipMemsetAsync(W.x, 0, (size_t)16 * bd.Ntot, st));
+        AFS_HIP(hipMemcpyAsync(W.r, W.b, (size_t)16 * bd.Ntot, hipMemcpyDeviceToDevice, st));
         for (int step = 0;; ++step) {
             int n_act = 0;
             for (int j = 0; j < B; ++j) {
-                act[j] = (bnorm[j] > 0.0 && rnorm[j] > tolh[j] && std::isfinite(rnorm[j]) && iters[j] < o.max_iter) ? 1 : 0;
+                act[j] = (bnorm[j] > 0.0 && rnorm[j] > tolh[j] && std::isfinite(rnorm[j]) && iters[j] < o.max_iter)
+                             ? 1
+                             : 0;
                 n_act += act[j];
             }
             if (n_act == 0 || step > o.max_iter)
                 break;
-            up(active, act, st);
-            // the cycle: V0 = r / ||r||
-            bcycle_init(bd, m, active, nrm, tolv, cyc, st);
-            bnormalize(bd, active, nrm, 1, r, V, st);
+            up(W.active, act, st);
+            bcycle_init(bd, m, W.active, W.nrm, W.tolv, W.cyc, st);
+            bnormalize(bd, W.active, W.nrm, 1, W.r, W.V, st);
             for (int k = 0; k < m; ++k) {
-                double *vk = V + 2 * (size_t)k * Ntot;
-                bprecond(bd, cyc, vk, z, st);
-                bgemv(bd, kin, cyc, z, w, st);
-                bmdot(bd, cyc, k + 1, V, w, h1, ldh, st);
-                bcombine(bd, cyc, k + 1, nullptr, V, h1, ldh, -1.0, w, st);
-                bmdot(bd, cyc, k + 1, V, w, h2, ldh, st);
-                bcombine(bd, cyc, k + 1, nullptr, V, h2, ldh, -1.0, w, st);
-                bmdot(bd, cyc, 1, w, w, nrm, 1, st);
-                bgivens(bd, m, k, cyc, h1, h2, ldh, nrm, tolv, st);
+                double *vk = W.V + 2 * (size_t)k * bd.Ntot;
+                bprecond(bd, W.cyc, vk, W.z, st);
+                bgemv(bd, kin, W.cyc, W.z, W.w, st);
+                bmdot(bd, W.cyc, k + 1, W.V, W.w, W.h1, ldh, st);
+                bcombine(bd, W.cyc, k + 1, nullptr, W.V, W.h1, ldh, -1.0, W.w, st);
+                bmdot(bd, W.cyc, k + 1, W.V, W.w, W.h2, ldh, st);
+                bcombine(bd, W.cyc, k + 1, nullptr, W.V, W.h2, ldh, -1.0, W.w, st);
+                bmdot(bd, W.cyc, 1, W.w, W.w, W.nrm, 1, st);
+                bgivens(bd, m, k, W.cyc, W.h1, W.h2, ldh, W.nrm, W.tolv, st);
                 if (k + 1 < m)
-                    bnormalize(bd, cyc, nrm, 1, w, V + 2 * (size_t)(k + 1) * Ntot, st);
+                    bnormalize(bd, W.cyc, W.nrm, 1, W.w, W.V + 2 * (size_t)(k + 1) * bd.Ntot, st);
                 if ((k % 4) == 3) {
-                    int c = 0;
-                    bcount(bd, cyc, cnt, st);
-                    AFS_HIP(hipMemcpyAsync(&c, cnt, 4, hipMemcpyDeviceToHost, st));
+                    int cnum = 0;
+                    bcount(bd, W.cyc, W.cnt, st);
+                    AFS_HIP(hipMemcpyAsync(&cnum, W.cnt, 4, hipMemcpyDeviceToHost, st));
                     AFS_HIP(hipStreamSynchronize(st));
-                    if (c == 0)
+                    if (cnum == 0)
                         break;
                 }
             }
             // x += M^-1 V y
-            bbacksolve(bd, m, active, yv, ldh, st);
+            bbacksolve(bd, m, W.active, W.yv, ldh, st);
             AFS_HIP(hipMemcpyAsync(kd.data(), bd.kdone, 4 * B, hipMemcpyDeviceToHost, st));
-            AFS_HIP(hipMemsetAsync(tmp, 0, (size_t)16 * Ntot, st));
-            bcombine(bd, active, m, bd.kdone, V, yv, ldh, 1.0, tmp, st);
-            bprecond(bd, active, tmp, z, st);
-            bcombine(bd, active, 1, nullptr, z, ones, 1, 1.0, x, st);
-            // outer residual with the FP64 operator
-            bgemv(bd, kout, active, x, tmp, st);
-            bsub(bd, active, b, tmp, r, st);
-            bmdot(bd, active, 1, r, r, nrm, 1, st);
-            AFS_HIP(hipMemcpyAsync(hn.data(), nrm, 16 * B, hipMemcpyDeviceToHost, st));
+            AFS_HIP(hipMemsetAsync(W.tmp, 0, (size_t)16 * bd.Ntot, st));
+            bcombine(bd, W.active, m, bd.kdone, W.V, W.yv, ldh, 1.0, W.tmp, st);
+            bprecond(bd, W.active, W.tmp, W.z, st);
+            bcombine(bd, W.active, 1, nullptr, W.z, W.ones, 1, 1.0, W.x, st);
+            // the true residual with the FP64 operator
+            bgemv(bd, kout, W.active, W.x, W.tmp, st);
+            bsub(bd, W.active, W.b, W.tmp, W.r, st);
+            bmdot(bd, W.active, 1, W.r, W.r, W.nrm, 1, st);
+            AFS_HIP(hipMemcpyAsync(hn.data(), W.nrm, 16 * B, hipMemcpyDeviceToHost, st));
             AFS_HIP(hipStreamSynchronize(st));
             for (int j = 0; j < B; ++j)
                 if (act[j]) {
@@ -285,27 +405,29 @@ int solve_batched(int n_prob, Problem *const *probs, const int32_t *n_s, const d
                     ++outer[j];
                 }
         }
-        AFS_HIP(hipEventRecord(es1, st));
         // ---- outputs
         for (int j = 0; j < B; ++j) {
-            const SysRef &rf = all[first + j];
+            const SysRef &rf = all[W.first + j];
             const size_t o2 = 2 * (size_t)rf.k * rf.N;
+            const double *xj = W.x + 2 * W.hs[j].off;
             if (a_out && a_out[rf.prob])
-                AFS_HIP(hipMemcpyAsync(a_out[rf.prob] + o2, x + 2 * hs[j].off, (size_t)16 * rf.N,
-                                       hipMemcpyDeviceToDevice, st));
+                AFS_HIP(hipMemcpyAsync(a_out[rf.prob] + o2, xj, (size_t)16 * rf.N, hipMemcpyDeviceToDevice, st));
             double *u = u_out && u_out[rf.prob] ? u_out[rf.prob] + o2 : nullptr;
             double *tt = t_out && t_out[rf.prob] ? t_out[rf.prob] + o2 : nullptr;
             if (u || tt)
-                vec_split_ut(rf.nt, probs[rf.prob]->dev.kind, x + 2 * hs[j].off, bc[rf.prob] + o2, u, tt, st);
+                vec_split_ut(rf.nt, probs[rf.prob]->dev.kind, xj, bc[rf.prob] + o2, u, tt, st);
         }
+        AFS_HIP(hipEventRecord(s1, st));
         AFS_HIP(hipStreamSynchronize(st));
         float ta = 0.f, ts = 0.f;
-        (void)hipEventElapsedTime(&ta, ea0, ea1);
-        (void)hipEventElapsedTime(&ts, ea1, es1);
+        (void)hipEventElapsedTime(&ta, W.asm_begin, W.asm_end);
+        (void)hipEventElapsedTime(&ts, s0, s1);
+        (void)hipEventDestroy(s0);
+        (void)hipEventDestroy(s1);
         for (int j = 0; j < B; ++j) {
-            const SysRef &rf = all[first + j];
+            const SysRef &rf = all[W.first + j];
             const double rel = bnorm[j] > 0 ? rnorm[j] / bnorm[j] : 0.0;
-            int status = std::isfinite(rel) ? (rel <= o.tol ? AFSBEM_OK : AFSBEM_ENOCONV) : AFSBEM_ENAN;
+            const int status = std::isfinite(rel) ? (rel <= o.tol ? AFSBEM_OK : AFSBEM_ENOCONV) : AFSBEM_ENAN;
             if (status != AFSBEM_OK && rc_all == AFSBEM_OK)
                 rc_all = status;
             if (stats) {
@@ -320,14 +442,9 @@ int solve_batched(int n_prob, Problem *const *probs, const int32_t *n_s, const d
                 S.rel_res_start = 1.0;
             }
         }
-        (void)hipEventDestroy(ea0);
-        (void)hipEventDestroy(ea1);
-        (void)hipEventDestroy(es1);
-        for (auto e : done)
-            (void)hipEventDestroy(e);
-        first = last;
     }
-    (void)hipEventDestroy(entry);
+    AFS_HIP(hipEventRecord(fin, st));
+    AFS_HIP(hipStreamWaitEvent(caller, fin, 0));
     return rc_all;
 }
 

@@ -27,6 +27,17 @@ struct BatchDev {
     int *kdone = nullptr;
 };
 
+// Device memory and streams of the batched solve, kept between calls (owned
+// by the first problem of a call, released with it).
+struct BatchArena {
+    void *base = nullptr;
+    size_t cap = 0;
+    hipStream_t st_asm[4] = {nullptr, nullptr, nullptr, nullptr};
+    hipStream_t st_sol = nullptr;
+    ~BatchArena();
+    void reserve(size_t bytes);
+};
+
 // kind 0: C128 FP64; 1: split hi plane FP32; 2: split hi+lo FP64
 void bgemv(const BatchDev &b, int kind, const int *active, const double *x, double *y, hipStream_t st);
 void bmdot(const BatchDev &b, const int *active, int nv, const double *V, const double *w, double *out, int ldo,

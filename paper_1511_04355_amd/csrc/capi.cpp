@@ -63,6 +63,8 @@ static void free_problem(afsbem_problem *h) {
     h->p.ws2 = nullptr;
     delete h->p.learn;
     h->p.learn = nullptr;
+    delete h->p.barena;
+    h->p.barena = nullptr;
     if (h->p.st_asm)
         (void)hipStreamDestroy(h->p.st_asm);
     if (h->p.st_sol)

@@ -102,6 +102,7 @@ struct DevicePlan {
 // -------------------------------------------------------------- problem --
 struct Workspace;
 struct LearnState;
+struct BatchArena;
 
 struct Problem {
     MaterialDerived mat;
@@ -112,6 +113,7 @@ struct Problem {
     Workspace *ws = nullptr, *ws2 = nullptr;      // second workspace: two frequencies in flight
     hipStream_t st_asm = nullptr, st_sol = nullptr;  // library streams (default priority)
     LearnState *learn = nullptr;                     // warm-start network (created on first use)
+    BatchArena *barena = nullptr;                    // batched-solve memory (created on first use)
 };
 
 // ----------------------------------------------------- kernel launchers --

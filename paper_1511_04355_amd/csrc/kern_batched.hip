@@ -75,7 +75,53 @@ __global__ __launch_bounds__(256) void bgemv_kernel(const BSys *__restrict__ sys
         const float4 *l = static_cast<const float4 *>(S.A_lo) + r2;
         double a0r = 0, a0i = 0, a1r = 0, a1i = 0;
         float f0r = 0, f0i = 0, f1r = 0, f1i = 0;
-        for (int64_t c = c0; c < c1; ++c) {
+        int64_t c = c0;
+        if (KIND == 1) {
+            // eight columns in flight per lane
+            for (; c + 8 <= c1; c += 8) {
+                float4 v[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+                    v[u] = ldnt(h + (c + u) * lda2);
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const double2 xv = xs[c + u];
+                    const float xr = (float)xv.x, xi = (float)xv.y;
+                    f0r = fmaf(v[u].x, xr, f0r);
+                    f0r = fmaf(-v[u].y, xi, f0r);
+                    f0i = fmaf(v[u].x, xi, f0i);
+                    f0i = fmaf(v[u].y, xr, f0i);
+                    f1r = fmaf(v[u].z, xr, f1r);
+                    f1r = fmaf(-v[u].w, xi, f1r);
+                    f1i = fmaf(v[u].z, xi, f1i);
+                    f1i = fmaf(v[u].w, xr, f1i);
+                }
+            }
+        } else {
+            for (; c + 4 <= c1; c += 4) {
+                float4 vh[4], vl[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    vh[u] = ldnt(h + (c + u) * lda2);
+                    vl[u] = ldnt(l + (c + u) * lda2);
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const double2 xv = xs[c + u];
+                    const double e0r = (double)vh[u].x + (double)vl[u].x, e0i = (double)vh[u].y + (double)vl[u].y;
+                    const double e1r = (double)vh[u].z + (double)vl[u].z, e1i = (double)vh[u].w + (double)vl[u].w;
+                    a0r = fma(e0r, xv.x, a0r);
+                    a0r = fma(-e0i, xv.y, a0r);
+                    a0i = fma(e0r, xv.y, a0i);
+                    a0i = fma(e0i, xv.x, a0i);
+                    a1r = fma(e1r, xv.x, a1r);
+                    a1r = fma(-e1i, xv.y, a1r);
+                    a1i = fma(e1r, xv.y, a1i);
+                    a1i = fma(e1i, xv.x, a1i);
+                }
+            }
+        }
+        for (; c < c1; ++c) {
             const float4 vh = ldnt(h + c * lda2);
             const double2 xv = xs[c];
             if (KIND == 1) {

@@ -279,3 +279,15 @@ def fsm_parameters(T: float, kappa: float, Ns: int):
 def cavity_frequencies(n: int, T: float = 20.0):
     """Laplace parameters of the cavity workloads: s_k = 5/T + i k pi/T."""
     return (5.0 / T) + 1j * np.arange(n) * np.pi / T
+
+
+def block_frequencies(n: int = 24, T: float = 300.0, kappa: float = 3.0, Ns: int = 512, seed: int = 0):
+    """Laplace parameters of the porous-block workloads: n points on the line
+    Re s = eta of the band omega in [0, Omega_s], Omega_s = (Ns/2) 2pi/T:
+    omega = 0 plus n-1 seeded uniform draws, sorted (the mix of low and high
+    frequencies that an adaptive sampling round asks for)."""
+    eta, dw = fsm_parameters(T, kappa, Ns)
+    om_max = (Ns // 2) * dw
+    rng = np.random.default_rng(seed)
+    om = np.sort(np.concatenate([[0.0], rng.uniform(0.0, om_max, n - 1)]))
+    return eta + 1j * om
