@@ -123,6 +123,18 @@ int afsbem_assemble_device(afsbem_problem *p, double s_re, double s_im, const vo
 int afsbem_matvec_device(afsbem_problem *p, int format, int precision, const void *d_A,
                          const void *d_A_lo, const void *d_x, void *d_y, void *hip_stream);
 
+/* Matrix-free product at one s (Eq. 2 without a stored matrix): the far-field
+ * rule is evaluated on the fly for every pair m != n (precision 0: FP64;
+ * 1: FP32 evaluation with FP64 sums over sources) and the near-pair
+ * corrections and self blocks (FP64, formed here) are added.  d_x, d_y
+ * (nullable together): N complex doubles, y = A(s) x.  d_b (nullable): N
+ * complex doubles, b(s) from d_bc_val ([n_tri][3] complex, nullable when no b
+ * is asked for).  Temporary device memory O(N + near pairs) is taken from the
+ * stream-ordered allocator. */
+int afsbem_matvec_free_device(afsbem_problem *p, double s_re, double s_im, int precision,
+                              const void *d_bc_val, const void *d_x, void *d_y, void *d_b,
+                              void *hip_stream);
+
 /* Preconditioner clusters of the plan: n_clusters, ptr_out [n_clusters+1]
  * offsets into elem_out [n_tri] (element indices grouped by cluster); the
  * arrays are nullable (query the count first). */
@@ -159,6 +171,10 @@ typedef struct {
     int32_t precond;     /* block-diagonal preconditioner: 0 = one 3x3 block per collocation point;
                             1 = blocks over spatial clusters of up to 24 elements (recursive
                             coordinate bisection), inverted in FP32 on the device */
+    int32_t matrix_free; /* 1: no stored matrix; every product evaluates the far-field rule on the
+                            fly (FP64, or FP32 for the inner products of the mixed path) and adds
+                            the near/self blocks formed once per frequency in FP64 (needs
+                            precond 0); memory O(N + near pairs) instead of O(N^2) */
 } afsbem_solve_opts;
 
 typedef struct {

@@ -41,7 +41,7 @@ class _Opts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("restart", ctypes.c_int32), ("max_iter", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("warm_start", ctypes.c_int32), ("inner_tol", ctypes.c_double),
                 ("batch", ctypes.c_int32), ("fault_inject", ctypes.c_uint32), ("profile", ctypes.c_int32),
-                ("learn_steps", ctypes.c_int32), ("precond", ctypes.c_int32)]
+                ("learn_steps", ctypes.c_int32), ("precond", ctypes.c_int32), ("matrix_free", ctypes.c_int32)]
 
 
 class _Stats(ctypes.Structure):
@@ -84,6 +84,7 @@ def lib():
         L.afsbem_problem_info.argtypes = [P, P, P, P, P]
         L.afsbem_assemble_device.argtypes = [P, d, d, P, ctypes.c_int, P, P, P, P, P]
         L.afsbem_matvec_device.argtypes = [P, ctypes.c_int, ctypes.c_int, P, P, P, P, P]
+        L.afsbem_matvec_free_device.argtypes = [P, d, d, ctypes.c_int, P, P, P, P, P]
         L.afsbem_solve_opts_default.argtypes = [P]
         L.afsbem_problem_clusters.argtypes = [P, P, P, P]
         L.afsbem_precond_apply_device.argtypes = [P, ctypes.c_int, P, P, P, P, P]
@@ -148,10 +149,11 @@ class SolveOptions:
     profile: int = 0
     learn_steps: int = 0
     precond: int = 0
+    matrix_free: int = 0
 
     def _c(self):
         return _Opts(self.tol, self.restart, self.max_iter, self.precision, self.warm_start, self.inner_tol,
-                     self.batch, self.fault_inject, self.profile, self.learn_steps, self.precond)
+                     self.batch, self.fault_inject, self.profile, self.learn_steps, self.precond, self.matrix_free)
 
 
 class Problem:
@@ -243,6 +245,23 @@ class Problem:
         _check(lib().afsbem_matvec_device(self._h, int(fmt), int(precision), _ptr(A), _ptr(A_lo), _ptr(x), _ptr(y),
                                           _stream()))
         return y
+
+    def matvec_free(self, s, x=None, bc_val=None, precision=0):
+        """Matrix-free product y = A(s) x and/or b(s) (bc_val given).  Returns (y, b)."""
+        import torch
+        y = b = None
+        if x is not None:
+            x = x.contiguous()
+            assert x.dtype == torch.complex128 and x.numel() == self.N and x.is_cuda
+            y = torch.empty(self.N, dtype=torch.complex128, device="cuda")
+        if bc_val is not None:
+            bc_val = bc_val.contiguous()
+            assert bc_val.dtype == torch.complex128 and bc_val.numel() == self.N and bc_val.is_cuda
+            b = torch.empty(self.N, dtype=torch.complex128, device="cuda")
+        s = complex(s)
+        _check(lib().afsbem_matvec_free_device(self._h, s.real, s.imag, int(precision), _ptr(bc_val), _ptr(x),
+                                               _ptr(y), _ptr(b), _stream()))
+        return y, b
 
     def clusters(self):
         n = ctypes.c_int64()

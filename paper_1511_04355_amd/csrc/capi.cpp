@@ -165,6 +165,22 @@ int afsbem_problem_create(const afsbem_mesh *mesh, const afsbem_material *mat, c
         D.gl_rho = upload(h, H.gl_rho);
         D.nrm = upload(h, H.nrm);
         D.coef = upload(h, H.coef);
+        // on-the-fly far field: collocation points as [n][4], FP32 copies
+        std::vector<double> c4(4 * H.n_tri, 0.0);
+        std::vector<float> c4f(4 * H.n_tri, 0.f), srcf(H.src.size()), coeff(H.coef.size());
+        for (int64_t e = 0; e < H.n_tri; ++e)
+            for (int d = 0; d < 3; ++d) {
+                c4[4 * e + d] = H.cen[3 * e + d];
+                c4f[4 * e + d] = (float)H.cen[3 * e + d];
+            }
+        for (size_t k = 0; k < H.src.size(); ++k)
+            srcf[k] = (float)H.src[k];
+        for (size_t k = 0; k < H.coef.size(); ++k)
+            coeff[k] = (float)H.coef[k];
+        D.col64 = upload(h, c4);
+        D.col32 = upload(h, c4f);
+        D.src32 = upload(h, srcf);
+        D.coef32 = upload(h, coeff);
         D.n_clusters = (int64_t)H.clus_ptr.size() - 1;
         D.clus_ptr = upload(h, H.clus_ptr);
         D.clus_elem = upload(h, H.clus_elem);
@@ -235,6 +251,45 @@ int afsbem_matvec_device(afsbem_problem *p, int format, int precision, const voi
         launch_gemv(N, format, precision, d_A, d_A_lo, static_cast<const double *>(d_x), static_cast<double *>(d_y),
                     static_cast<double *>(partial), st);
         AFS_HIP(hipFreeAsync(partial, st));
+        return AFSBEM_OK;
+    });
+}
+
+int afsbem_matvec_free_device(afsbem_problem *p, double s_re, double s_im, int precision, const void *d_bc_val,
+                              const void *d_x, void *d_y, void *d_b, void *hip_stream) {
+    return guarded([&] {
+        AFS_REQUIRE(p, AFSBEM_EINVAL, "null problem");
+        AFS_REQUIRE(precision == 0 || precision == 1, AFSBEM_EINVAL, "precision must be 0 or 1");
+        AFS_REQUIRE((d_x == nullptr) == (d_y == nullptr), AFSBEM_EINVAL, "x and y go together");
+        AFS_REQUIRE(!d_b || d_bc_val, AFSBEM_EINVAL, "b needs the boundary values");
+        AFS_REQUIRE(std::isfinite(s_re) && std::isfinite(s_im), AFSBEM_EINVAL, "non-finite s");
+        hipStream_t st = static_cast<hipStream_t>(hip_stream);
+        const Problem &P = p->p;
+        const int64_t nt = P.dev.n_tri, N = 3 * nt;
+        char *mem = nullptr;
+        const size_t blk = ((size_t)std::max<int64_t>(P.dev.nnz, 1) * 144 + 255) / 256 * 256;
+        const size_t sblk = ((size_t)nt * 144 + 255) / 256 * 256;
+        const size_t zb = d_bc_val ? 0 : ((size_t)N * 16 + 255) / 256 * 256;
+        const size_t scr = assembly_scratch_bytes(P);
+        AFS_HIP(hipMallocAsync((void **)&mem, blk + sblk + zb + scr, st));
+        double *nearblk = reinterpret_cast<double *>(mem), *selfblk = reinterpret_cast<double *>(mem + blk);
+        const double *bc = static_cast<const double *>(d_bc_val);
+        if (!bc) {
+            AFS_HIP(hipMemsetAsync(mem + blk + sblk, 0, (size_t)N * 16, st));
+            bc = reinterpret_cast<const double *>(mem + blk + sblk);
+        }
+        void *scratch = mem + blk + sblk + zb;
+        KernelParams kp = kernel_params(P.mat, s_re, s_im);
+        launch_block_setup(P, kp, bc, nearblk, selfblk, nullptr, scratch, st);
+        double *part = static_cast<double *>(scratch);  // far partial sums (b first, then y)
+        if (d_b) {
+            mf_apply(P, kp, 0, 1, nullptr, nullptr, bc, nullptr, part, st);
+            launch_finalize_b(P, mf_chunks(nt), part, scratch, static_cast<double *>(d_b), st);
+        }
+        if (d_x)
+            mf_apply(P, kp, precision, 0, nearblk, selfblk, static_cast<const double *>(d_x),
+                     static_cast<double *>(d_y), part, st);
+        AFS_HIP(hipFreeAsync(mem, st));
         return AFSBEM_OK;
     });
 }
@@ -338,6 +393,7 @@ int afsbem_solve_opts_default(afsbem_solve_opts *o) {
     o->profile = 0;
     o->learn_steps = 0;
     o->precond = 0;
+    o->matrix_free = 0;
     return AFSBEM_OK;
 }
 
@@ -359,6 +415,9 @@ int afsbem_solve_device(afsbem_problem *p, int32_t n_s, const double *s, const v
         AFS_REQUIRE(o.warm_start >= AFSBEM_WARM_NONE && o.warm_start <= AFSBEM_WARM_LEARNED, AFSBEM_EINVAL,
                     "unknown warm start");
         AFS_REQUIRE(o.precond == 0 || o.precond == 1, AFSBEM_EINVAL, "precond must be 0 or 1");
+        AFS_REQUIRE(o.matrix_free == 0 || o.matrix_free == 1, AFSBEM_EINVAL, "matrix_free must be 0 or 1");
+        AFS_REQUIRE(!(o.matrix_free && o.precond == 1), AFSBEM_EINVAL,
+                    "the cluster preconditioner needs the stored matrix");
         AFS_REQUIRE(o.warm_start != AFSBEM_WARM_LEARNED || d_a_out, AFSBEM_EINVAL,
                     "the learned warm start needs the solution output buffer");
         hipStream_t st = static_cast<hipStream_t>(hip_stream);
@@ -413,6 +472,7 @@ int afsbem_solve_batched_device(int32_t n_prob, afsbem_problem *const *probs, co
                     "unknown precision");
         AFS_REQUIRE(o.warm_start == AFSBEM_WARM_NONE, AFSBEM_EINVAL, "the batched solve takes no warm start");
         AFS_REQUIRE(o.precond == 0, AFSBEM_EINVAL, "the batched solve uses the point block-Jacobi preconditioner");
+        AFS_REQUIRE(o.matrix_free == 0, AFSBEM_EINVAL, "the batched solve stores its matrices");
         int dev = 0;
         AFS_HIP(hipGetDevice(&dev));
         std::vector<Problem *> pp(n_prob);

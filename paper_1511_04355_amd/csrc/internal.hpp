@@ -94,6 +94,8 @@ struct DevicePlan {
     double *self_ang = nullptr, *self_cpv = nullptr, *gl_rho = nullptr;
     double *nrm = nullptr;         // [n][3]
     double *coef = nullptr;        // [16][4] series coefficients of the radial functions
+    double *col64 = nullptr;       // [n][4] collocation points (x, y, z, 0)
+    float *col32 = nullptr, *src32 = nullptr, *coef32 = nullptr;  // FP32 copies for on-the-fly evaluation
     int64_t n_clusters = 0;
     int64_t *clus_ptr = nullptr;
     int32_t *clus_elem = nullptr;
@@ -136,6 +138,24 @@ size_t assembly_scratch_bytes(const Problem &p);
 void launch_assembly(const Problem &p, const KernelParams &kp, const double *bc_val, int format,
                      void *A, void *A_lo, double *b, double *precond, void *scratch,
                      hipStream_t st);
+
+// Matrix-free operator (no stored dense matrix).  Per frequency: the near-pair
+// correction blocks (exact minus the far rule) [nnz][9] and the self blocks
+// [nt][9] (complex, row-major 3x3), b's near/self parts in scratch, and the
+// block-Jacobi inverses; per application the far rule is evaluated on the fly.
+constexpr int kFmtBlocks = 2;
+void launch_block_setup(const Problem &p, const KernelParams &kp, const double *bc_val, double *nearblk,
+                        double *selfblk, double *precond, void *scratch, hipStream_t st);
+// b = sum of S far partials [S][N] (bpart) + the near/self parts held in scratch
+void launch_finalize_b(const Problem &p, int S, const double *bpart, const void *scratch, double *b,
+                       hipStream_t st);
+// source chunks of the on-the-fly far field and its partial-sum scratch
+int mf_chunks(int64_t n_tri);
+// y = A x (comp = 0) or the right-hand-side operator applied to the boundary
+// values (comp = 1, y = b's far part; use launch_finalize_b for b).
+// precision 0: FP64 evaluation, 1: FP32 evaluation (FP64 sums over sources).
+void mf_apply(const Problem &p, const KernelParams &kp, int precision, int comp, const double *nearblk,
+              const double *selfblk, const double *x, double *y, double *partial, hipStream_t st);
 
 // y = A x.  precision 0: FP64, 1: FP32 hi plane.  partial: scratch of
 // gemv_chunks(N) * N complex doubles.

@@ -190,6 +190,15 @@ __device__ __forceinline__ void store_block(void *A, void *A_lo, int64_t lda, in
     }
 }
 
+// 3x3 complex block, row-major, to 18 consecutive doubles
+__device__ __forceinline__ void store_blk9(double *out, const cd blk[9]) {
+#pragma unroll
+    for (int e = 0; e < 9; ++e) {
+        out[2 * e] = blk[e].r;
+        out[2 * e + 1] = blk[e].i;
+    }
+}
+
 // ---------------------------------------------------------------- far field --
 // Per (collocation point, source element) the 3x3 traction block is
 //   sum_q f_q [t0 d_ij + t1 n_i rh_j + t2 rh_i n_j + t3 rh_i rh_j],  f_q = w_q/(4 pi r_q^2),
@@ -340,8 +349,8 @@ __device__ __forceinline__ void near_items(int64_t first, int64_t stride, int64_
                                            const double *__restrict__ leaves, const Rule7Args &rule,
                                            const double *__restrict__ rec, const KernelParams &kp,
                                            const double *__restrict__ coef, double xx, double xy, double xz,
-                                           double nx, double ny, double nz, const cd v[3], BlockAcc &acc,
-                                           cd bcor[3]) {
+                                           double nx, double ny, double nz, const cd v[3], double far_sA,
+                                           BlockAcc &acc, cd bcor[3]) {
     for (int64_t k = first; k < items; k += stride) {
         double yx, yy, yz, w, sA, sB;
         if (k < n_near) {
@@ -359,7 +368,7 @@ __device__ __forceinline__ void near_items(int64_t first, int64_t stride, int64_
             yy = rec[4 * q + 1];
             yz = rec[4 * q + 2];
             w = rec[4 * q + 3];
-            sA = 0.0;
+            sA = far_sA;
             sB = -1.0;
         }
         PairEval E;
@@ -389,6 +398,8 @@ __global__ __launch_bounds__(256) void near_assemble_kernel(
     const double *__restrict__ bc, const double *__restrict__ coef, const int32_t *__restrict__ near_row,
     const int32_t *__restrict__ near_col, const int64_t *__restrict__ leaf_ptr,
     const double *__restrict__ leaves, void *A, void *A_lo, double *__restrict__ corr) {
+    // FMT == kFmtBlocks: A receives the correction block (exact - far rule) of
+    // pair p at [p][9] complex, row-major (the far rule stays in the operator)
     const int64_t gid = (int64_t)blockIdx.x * 256 + threadIdx.x;
     const int64_t p = gid / kNearLanes;
     const int sub = (int)(gid % kNearLanes);
@@ -408,12 +419,13 @@ __global__ __launch_bounds__(256) void near_assemble_kernel(
     BlockAcc acc;
     acc.zero();
     cd bcor[3] = {cd{0, 0}, cd{0, 0}, cd{0, 0}};
+    const double far_sA = (FMT == kFmtBlocks) ? -1.0 : 0.0;
     if (kind == 0)
         near_items<0>(sub, kNearLanes, items, n_near, L0, leaves, rule, rec, kp, coef, xx, xy, xz, nx, ny, nz, v,
-                      acc, bcor);
+                      far_sA, acc, bcor);
     else
         near_items<1>(sub, kNearLanes, items, n_near, L0, leaves, rule, rec, kp, coef, xx, xy, xz, nx, ny, nz, v,
-                      acc, bcor);
+                      far_sA, acc, bcor);
     acc.E.r = group_sum(acc.E.r);
     acc.E.i = group_sum(acc.E.i);
 #pragma unroll
@@ -434,7 +446,10 @@ __global__ __launch_bounds__(256) void near_assemble_kernel(
         return;
     cd blk[9];
     expand_block(kind, acc, nx, ny, nz, blk);
-    store_block<FMT>(A, A_lo, lda, m, n, blk);
+    if (FMT == kFmtBlocks)
+        store_blk9(static_cast<double *>(A) + 18 * p, blk);
+    else
+        store_block<FMT>(A, A_lo, lda, m, n, blk);
 #pragma unroll
     for (int e = 0; e < 3; ++e) {
         corr[6 * p + 2 * e] = bcor[e].r;
@@ -528,7 +543,10 @@ __global__ __launch_bounds__(256) void self_assemble_kernel(
             }
         }
     }
-    store_block<FMT>(A, A_lo, lda, m, m, blk);
+    if (FMT == kFmtBlocks)
+        store_blk9(static_cast<double *>(A) + 18 * m, blk);
+    else
+        store_block<FMT>(A, A_lo, lda, m, m, blk);
     for (int i = 0; i < 3; ++i) {
         bself[6 * m + 2 * i] = bs[i].r;
         bself[6 * m + 2 * i + 1] = bs[i].i;
@@ -654,6 +672,39 @@ void launch_assembly(const Problem &p, const KernelParams &kp, const double *bc_
     }
     AFS_HIP(hipGetLastError());
     finalize_b_kernel<<<(unsigned)((N + 255) / 256), 256, 0, st>>>(nt, Sused, bpart, bself, d.near_ptr, corr, b);
+    AFS_HIP(hipGetLastError());
+}
+
+void launch_block_setup(const Problem &p, const KernelParams &kp, const double *bc_val, double *nearblk,
+                        double *selfblk, double *precond, void *scratch, hipStream_t st) {
+    const DevicePlan &d = p.dev;
+    const int64_t nt = d.n_tri;
+    const int S = far_source_chunks(nt);
+    const int64_t N = 3 * nt;
+    double *bpart = static_cast<double *>(scratch);
+    double *bself = bpart + 2 * (size_t)S * N;
+    double *corr = bself + 6 * nt;
+    const unsigned gnear = (unsigned)((d.nnz * kNearLanes + 255) / 256);
+    const unsigned gself = (unsigned)((nt * 64 + 255) / 256);
+    const Rule7Args rule = rule7_args();
+    if (d.nnz)
+        near_assemble_kernel<kFmtBlocks><<<gnear, 256, 0, st>>>(nt, 0, d.nnz, kp, rule, d.colx, d.coly, d.colz, d.src,
+                                                                bc_val, d.coef, d.near_row, d.near_col, d.leaf_ptr,
+                                                                d.leaves, nearblk, nullptr, corr);
+    self_assemble_kernel<kFmtBlocks><<<gself, 256, 0, st>>>(nt, 0, kp, d.colx, d.coly, d.colz, d.src, bc_val, d.coef,
+                                                            d.self_ang, d.self_cpv, d.gl_rho, d.n_theta, d.n_rho,
+                                                            selfblk, nullptr, bself, precond);
+    AFS_HIP(hipGetLastError());
+}
+
+void launch_finalize_b(const Problem &p, int S, const double *bpart, const void *scratch, double *b,
+                       hipStream_t st) {
+    const DevicePlan &d = p.dev;
+    const int64_t nt = d.n_tri, N = 3 * nt;
+    const int Smax = far_source_chunks(nt);
+    const double *bself = static_cast<const double *>(scratch) + 2 * (size_t)Smax * N;
+    const double *corr = bself + 6 * nt;
+    finalize_b_kernel<<<(unsigned)((N + 255) / 256), 256, 0, st>>>(nt, S, bpart, bself, d.near_ptr, corr, b);
     AFS_HIP(hipGetLastError());
 }
 

@@ -35,7 +35,7 @@ static void *dalloc(size_t bytes) {
 Workspace::~Workspace() { release(); }
 
 void Workspace::release() {
-    for (void *p : {(void *)A, (void *)A_lo, (void *)b, (void *)precond, (void *)asm_scratch, (void *)gemv_partial,
+    for (void *p : {(void *)A, (void *)A_lo, (void *)nearblk, (void *)selfblk, (void *)b, (void *)precond, (void *)asm_scratch, (void *)gemv_partial,
                     (void *)V, (void *)w, (void *)z, (void *)x, (void *)r, (void *)tmp, (void *)rin, (void *)xo,
                     (void *)dots_partial, (void *)small, (void *)one, (void *)clinv})
         if (p)
@@ -53,6 +53,7 @@ void Workspace::release() {
     format = -1;
     m = 0;
     A = A_lo = asm_scratch = nullptr;
+    nearblk = selfblk = nullptr;
     b = precond = gemv_partial = V = w = z = x = r = tmp = rin = xo = nullptr;
     dots_partial = small = one = host_small = nullptr;
     clinv = nullptr;
@@ -71,7 +72,7 @@ void Workspace::ensure(const Problem &p, int format, int restart_m, int prec) {
     const int64_t nt = p.dev.n_tri, N = 3 * nt;
     const int64_t lda = (N + 63) / 64 * 64;
     plan = &p.dev;
-    if (N == this->N && format == this->format && restart_m <= this->m && A) {
+    if (N == this->N && format == this->format && restart_m <= this->m && b) {
         if (prec == 1 && !clinv)
             clinv = (float *)dalloc((size_t)std::max<int64_t>(p.dev.n_clusters, 1) * kClusterDim * kClusterDim * 8);
         prec_kind = prec;
@@ -85,14 +86,19 @@ void Workspace::ensure(const Problem &p, int format, int restart_m, int prec) {
     this->N = N;
     this->format = format;
     this->m = restart_m;
-    const size_t plane = (size_t)N * lda * (format == AFSBEM_FMT_C128 ? 16 : 8);
-    A = dalloc(plane);
-    if (format == AFSBEM_FMT_SPLIT)
-        A_lo = dalloc(plane);
+    if (format == kFmtBlocks) {
+        nearblk = (double *)dalloc((size_t)std::max<int64_t>(p.dev.nnz, 1) * 144);
+        selfblk = (double *)dalloc((size_t)nt * 144);
+    } else {
+        const size_t plane = (size_t)N * lda * (format == AFSBEM_FMT_C128 ? 16 : 8);
+        A = dalloc(plane);
+        if (format == AFSBEM_FMT_SPLIT)
+            A_lo = dalloc(plane);
+    }
     b = (double *)dalloc((size_t)N * 16);
     precond = (double *)dalloc((size_t)nt * 9 * 16);
     asm_scratch = dalloc(assembly_scratch_bytes(p));
-    gemv_partial = (double *)dalloc((size_t)gemv_chunks(N) * N * 16);
+    gemv_partial = (double *)dalloc((size_t)(format == kFmtBlocks ? mf_chunks(nt) : gemv_chunks(N)) * N * 16);
     V = (double *)dalloc((size_t)(restart_m + 1) * N * 16);
     w = (double *)dalloc((size_t)N * 16);
     z = (double *)dalloc((size_t)N * 16);
@@ -126,6 +132,16 @@ void Operator::apply(const double *xin, double *yout, hipStream_t st) const {
             w.ev_prec.push_back(format == AFSBEM_FMT_C128 ? 2 : precision);
             ++w.ev_used;
         }
+    }
+    if (format == kFmtBlocks) {
+        if (eb)
+            AFS_HIP(hipEventRecord(eb, st));
+        mf_apply(*prob, kp, precision, 0, nearblk, selfblk, xin, yout, partial, st);
+        if (ee)
+            AFS_HIP(hipEventRecord(ee, st));
+        ++*counter;
+        *bytes += (double)(prob->dev.nnz + prob->dev.n_tri) * 144.0;
+        return;
     }
     launch_gemv(N, format, precision, A, A_lo, xin, yout, partial, st, eb, ee);
     ++*counter;
@@ -390,6 +406,14 @@ static double elapsed_ms(hipEvent_t a, hipEvent_t b) {
 static void assemble_into(Problem &p, Workspace &ws, int fmt, double s_re, double s_im, const double *d_bc,
                           hipStream_t st) {
     KernelParams kp = kernel_params(p.mat, s_re, s_im);
+    if (fmt == kFmtBlocks) {
+        // near/self blocks and b (far part evaluated on the fly in FP64)
+        launch_block_setup(p, kp, d_bc, ws.nearblk, ws.selfblk, ws.precond, ws.asm_scratch, st);
+        double *bpart = static_cast<double *>(ws.asm_scratch);
+        mf_apply(p, kp, 0, 1, nullptr, nullptr, d_bc, nullptr, bpart, st);
+        launch_finalize_b(p, mf_chunks(p.dev.n_tri), bpart, ws.asm_scratch, ws.b, st);
+        return;
+    }
     launch_assembly(p, kp, d_bc, fmt, ws.A, ws.A_lo, ws.b, ws.precond, ws.asm_scratch, st);
     if (ws.prec_kind == 1)
         cluster_inverse(p.dev, fmt, ws.A, ws.A_lo, ws.clinv, st);
@@ -414,6 +438,12 @@ static int krylov_phase(Problem &p, Workspace &ws, const afsbem_solve_opts &o, i
     Workspace *prof = o.profile ? &ws : nullptr;
     ws.reset_timing();
     Operator op64{N, fmt, 0, ws.A, ws.A_lo, ws.gemv_partial, &matvecs, &bytes, prof};
+    const KernelParams kp = kernel_params(p.mat, s_re, s_im);
+    op64.prob = &p;
+    op64.kp = kp;
+    op64.nearblk = ws.nearblk;
+    op64.selfblk = ws.selfblk;
+    const bool mixed = o.precision == AFSBEM_PREC_MIXED;
     const double bnorm = norm2_dev(ws, N, ws.b, st);
     const bool learned = o.warm_start == AFSBEM_WARM_LEARNED;
     const double *x_prev = (d_x0 && o.warm_start != AFSBEM_WARM_NONE) ? d_x0 : nullptr;
@@ -436,7 +466,7 @@ static int krylov_phase(Problem &p, Workspace &ws, const afsbem_solve_opts &o, i
     if (bnorm == 0.0) {
         AFS_HIP(hipMemsetAsync(ws.x, 0, (size_t)N * 16, st));
         relres = 0.0;
-    } else if (fmt == AFSBEM_FMT_C128) {
+    } else if (!mixed) {
         const double r0n = start_iterate(op64, ws, ws.b, bnorm, x_prev, x_net, ws.x, ws.r, x_zero, st, &used_net, &net_gain);
         rel_start = r0n / bnorm;
         GmresResult g = gmres(op64, ws, nt, ws.b, bnorm, ws.x, x_zero, o.tol * bnorm, o.restart, o.max_iter, st,
@@ -449,7 +479,8 @@ static int krylov_phase(Problem &p, Workspace &ws, const afsbem_solve_opts &o, i
         // mixed: outer residual with the FP64 operator (hi + lo planes), inner
         // GMRES on the FP32 hi plane for the correction d: A32 d = r.  The
         // starting residual only seeds the inner solve: FP32 operator.
-        Operator op32{N, fmt, 1, ws.A, ws.A_lo, ws.gemv_partial, &matvecs, &bytes, prof};
+        Operator op32 = op64;
+        op32.precision = 1;
         double rnorm = start_iterate(op32, ws, ws.b, bnorm, x_prev, x_net, ws.xo, ws.rin, x_zero, st, &used_net, &net_gain);
         rel_start = rnorm / bnorm;
         while (std::isfinite(rnorm)) {
@@ -514,7 +545,8 @@ static int krylov_phase(Problem &p, Workspace &ws, const afsbem_solve_opts &o, i
 int solve_one(Problem &p, const afsbem_solve_opts &o, double s_re, double s_im, const double *d_bc,
               const double *d_x0, double *d_a, double *d_u, double *d_t, afsbem_solve_stats *stats,
               hipStream_t st) {
-    const int fmt = (o.precision == AFSBEM_PREC_MIXED) ? AFSBEM_FMT_SPLIT : AFSBEM_FMT_C128;
+    const int fmt = o.matrix_free ? kFmtBlocks
+                                  : ((o.precision == AFSBEM_PREC_MIXED) ? AFSBEM_FMT_SPLIT : AFSBEM_FMT_C128);
     if (!p.ws)
         p.ws = new Workspace();
     Workspace &ws = *p.ws;
@@ -550,7 +582,8 @@ int solve_pipelined(Problem &p, const afsbem_solve_opts &o, int32_t n_s, const d
                     const double *x0_user, double *a_out, double *u_out, double *t_out,
                     afsbem_solve_stats *stats, hipStream_t caller) {
     const int64_t N = 3 * p.dev.n_tri;
-    const int fmt = (o.precision == AFSBEM_PREC_MIXED) ? AFSBEM_FMT_SPLIT : AFSBEM_FMT_C128;
+    const int fmt = o.matrix_free ? kFmtBlocks
+                                  : ((o.precision == AFSBEM_PREC_MIXED) ? AFSBEM_FMT_SPLIT : AFSBEM_FMT_C128);
     if (!p.ws)
         p.ws = new Workspace();
     if (!p.ws2)

@@ -9,6 +9,7 @@ struct Workspace {
     int format = -1;
     int m = 0;
     void *A = nullptr, *A_lo = nullptr;
+    double *nearblk = nullptr, *selfblk = nullptr;  // matrix-free format: per-frequency blocks
     double *b = nullptr, *precond = nullptr;
     void *asm_scratch = nullptr;
     double *gemv_partial = nullptr;
@@ -33,7 +34,9 @@ struct Workspace {
 };
 
 // y = A x with a stored matrix: precision 0 = FP64 (C128, or hi+lo of SPLIT),
-// 1 = FP32 on the hi plane.  Counts applications and streamed bytes.
+// 1 = FP32 on the hi plane; format kFmtBlocks: matrix-free (far field
+// evaluated on the fly in FP64 or FP32, near/self blocks of the workspace).
+// Counts applications and streamed matrix bytes.
 struct Operator {
     int64_t N;
     int format, precision;
@@ -42,6 +45,9 @@ struct Operator {
     int *counter;
     double *bytes;
     Workspace *prof = nullptr;             // non-null: record GEMV events
+    const Problem *prob = nullptr;         // matrix-free: plan, frequency, blocks
+    KernelParams kp{};
+    const double *nearblk = nullptr, *selfblk = nullptr;
     void apply(const double *x, double *y, hipStream_t st) const;
 };
 

@@ -1,0 +1,120 @@
+"""GPU parity of the matrix-free operator (far-field rule evaluated on the fly,
+near/self blocks per frequency) against the oracle's dense rows.
+
+Tolerances: the FP64 product and b agree with the oracle's A x and b to 1e-11
+of their norms (same quadrature, different summation order); the FP32
+evaluation to 2e-5 (FP32 positions give r to ~1e-7 of the box size, the
+closed-form radial functions lose eps32/|x|^2 above the series threshold
+|x| = 1); solves as for the stored operators: FP64 1e-6, mixed 1e-5.
+"""
+import numpy as np
+import pytest
+
+from synth import meshgen as mg
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _needs_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+
+
+def _tetra():
+    return mg.Mesh(np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1.0]]),
+                   np.array([[0, 2, 1], [0, 1, 3], [0, 3, 2], [1, 2, 3]], np.int32),
+                   np.array([0, 0, 1, 0], np.int8),
+                   np.array([[0, 0, 1.0], [0.3, 0, 0], [0, 0, 0], [1, 1, 1.0]]))
+
+
+MESHES = {
+    "tetra": _tetra,
+    "cavity_L1": lambda: mg.cavity(1),
+    "rod": lambda: mg.rod(2.0, 1.0, 3, 6),
+    "cavity_L2": lambda: mg.cavity(2),
+    "random_block_7": lambda: mg.random_block(7),
+}
+
+
+def _rand_x(n, seed):
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal(n) + 1j * rng.standard_normal(n)
+
+
+@pytest.mark.parametrize("name", list(MESHES))
+@pytest.mark.parametrize("s", [0.25 + 0.0j, 0.25 + 3.1j])
+def test_matvec_free_matches_oracle(name, s):
+    import paper_1511_04355_amd as afs
+    from oracle import bem
+    mesh = MESHES[name]()
+    N = 3 * mesh.n_tri
+    bc = np.asarray(mesh.bc_shape, np.complex128) / s
+    x = _rand_x(N, 11)
+    P = afs.Problem.from_mesh(mesh)
+    print(f"[matfree] {name} s={s} N={N}", flush=True)
+    if N > 3000:
+        rows = np.sort(np.random.default_rng(3).choice(mesh.n_tri, 24, replace=False))
+    else:
+        rows = np.arange(mesh.n_tri)
+    A, b = bem.assemble(mesh, s, bc, rows=rows)
+    ridx = (3 * rows[:, None] + np.arange(3)).reshape(-1)
+    y_ref = A @ x
+    y64, b64 = P.matvec_free(s, torch.from_numpy(x).cuda(), torch.from_numpy(bc.reshape(-1)).cuda(), precision=0)
+    y32, _ = P.matvec_free(s, torch.from_numpy(x).cuda(), precision=1)
+    y64, b64, y32 = y64.cpu().numpy()[ridx], b64.cpu().numpy()[ridx], y32.cpu().numpy()[ridx]
+    e64 = np.linalg.norm(y64 - y_ref) / np.linalg.norm(y_ref)
+    eb = np.linalg.norm(b64 - b) / np.linalg.norm(b)
+    e32 = np.linalg.norm(y32 - y_ref) / np.linalg.norm(y_ref)
+    print(f"  fp64 {e64:.2e}  b {eb:.2e}  fp32 {e32:.2e}", flush=True)
+    assert e64 <= 1e-11
+    assert eb <= 1e-11
+    assert e32 <= 2e-5
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_solve_matrix_free_cavity_L2(prec):
+    import paper_1511_04355_amd as afs
+    from oracle import bem
+    mesh = mg.cavity(2)
+    s = mg.cavity_frequencies(6)[::2]
+    bc = np.stack([np.asarray(mesh.bc_shape, np.complex128) / sk for sk in s])
+    P = afs.Problem.from_mesh(mesh)
+    tol, err = (1e-9, 1e-6) if prec == "fp64" else (1e-6, 1e-5)
+    for batch in (1, 0):
+        opts = afs.SolveOptions(tol=tol, precision=afs.PREC_FP64 if prec == "fp64" else afs.PREC_MIXED,
+                                matrix_free=1, batch=batch, warm_start=afs.WARM_PREV)
+        out = P.solve(s, torch.from_numpy(bc).cuda(), opts)
+        assert out["status"] == 0
+        a = out["a"].cpu().numpy()
+        for k, sk in enumerate(s):
+            A, b = bem.assemble(mesh, sk, bc[k])
+            xo = bem.solve_dense(A, b)
+            assert np.linalg.norm(b - A @ a[k]) / np.linalg.norm(b) <= 1.5 * tol
+            assert np.linalg.norm(a[k] - xo) / np.linalg.norm(xo) <= err
+
+
+def test_solve_matrix_free_rod_u_t():
+    import paper_1511_04355_amd as afs
+    from oracle import bem
+    mesh = mg.rod(2.0, 1.0, 3, 6)
+    mat = (1.0, 0.0, 1.0)
+    s = np.array([0.5 + 0.3j, 0.3 + 1.2j])
+    bc = np.stack([np.asarray(mesh.bc_shape, np.complex128) / sk for sk in s])
+    P = afs.Problem.from_mesh(mesh, material=mat)
+    out = P.solve(s, torch.from_numpy(bc).cuda(), afs.SolveOptions(tol=1e-10, matrix_free=1))
+    for k, sk in enumerate(s):
+        _, uo, to = bem.solve(mesh, sk, bc[k], mat=mat)
+        assert np.linalg.norm(out["u"][k].cpu().numpy() - uo) / np.linalg.norm(uo) < 1e-8
+        assert np.linalg.norm(out["t"][k].cpu().numpy() - to) / np.linalg.norm(to) < 1e-8
+
+
+def test_matrix_free_rejects_cluster_preconditioner():
+    import paper_1511_04355_amd as afs
+    mesh = mg.cavity(1)
+    s = mg.cavity_frequencies(1)
+    P = afs.Problem.from_mesh(mesh)
+    bc = torch.from_numpy(np.asarray(mesh.bc_shape, np.complex128)[None] / s[0]).cuda()
+    with pytest.raises(afs.AfsbemError):
+        P.solve(s, bc, afs.SolveOptions(matrix_free=1, precond=1))
