@@ -211,6 +211,15 @@ int afsbem_solve_device(afsbem_problem *p, int32_t n_s, const double *s, const v
                         const void *d_x0, void *d_a_out, void *d_u_out, void *d_t_out,
                         const afsbem_solve_opts *opts, afsbem_solve_stats *stats, void *hip_stream);
 
+/* Host-pointer variant of afsbem_solve_device: s, bc_val [n_s][n_tri][3],
+ * x0 (nullable), a_out [n_s][N], u_out and t_out [n_s][n_tri][3] (each
+ * nullable) are host arrays owned by the caller; the library copies them to
+ * and from device buffers of its own (freed before return) and works on the
+ * null stream.  Same options, statistics and return codes. */
+int afsbem_solve(afsbem_problem *p, int32_t n_s, const double *s, const double *bc_val, const double *x0,
+                 double *a_out, double *u_out, double *t_out, const afsbem_solve_opts *opts,
+                 afsbem_solve_stats *stats);
+
 /* Batched solve of many independent systems: every frequency of every problem
  * in the call (several meshes of uneven size allowed, all on the current
  * device).  The per-frequency operation is the one of afsbem_solve_device

@@ -89,6 +89,7 @@ def lib():
         L.afsbem_problem_clusters.argtypes = [P, P, P, P]
         L.afsbem_precond_apply_device.argtypes = [P, ctypes.c_int, P, P, P, P, P]
         L.afsbem_solve_device.argtypes = [P, i32, P, P, P, P, P, P, P, P, P]
+        L.afsbem_solve.argtypes = [P, i32, P, P, P, P, P, P, P, P]
         L.afsbem_solve_batched_device.argtypes = [i32, P, P, P, P, P, P, P, P, P, P]
         L.afsbem_mlp_n_params.argtypes = [i32, i32, i32, P]
         L.afsbem_mlp_forward.argtypes = [i32, i32, i32, i32, P, P, P, ctypes.c_int, P]
@@ -245,6 +246,25 @@ class Problem:
         _check(lib().afsbem_matvec_device(self._h, int(fmt), int(precision), _ptr(A), _ptr(A_lo), _ptr(x), _ptr(y),
                                           _stream()))
         return y
+
+    def solve_host(self, s_list, bc_val, opts: SolveOptions | None = None, x0=None):
+        """Host-array solve (numpy in, numpy out) through afsbem_solve."""
+        opts = opts or SolveOptions()
+        s_arr = np.ascontiguousarray(np.stack([np.real(s_list), np.imag(s_list)], axis=1), np.float64)
+        ns = s_arr.shape[0]
+        bc = np.ascontiguousarray(np.asarray(bc_val, np.complex128).reshape(ns, self.n_tri, 3))
+        x0a = None if x0 is None else np.ascontiguousarray(np.asarray(x0, np.complex128).reshape(ns, self.N))
+        a = np.zeros((ns, self.N), np.complex128)
+        u = np.zeros((ns, self.n_tri, 3), np.complex128)
+        t = np.zeros((ns, self.n_tri, 3), np.complex128)
+        stats = (_Stats * max(ns, 1))()
+        c = opts._c()
+        rc = lib().afsbem_solve(self._h, ns, s_arr.ctypes.data, bc.ctypes.data,
+                                None if x0a is None else x0a.ctypes.data, a.ctypes.data, u.ctypes.data,
+                                t.ctypes.data, ctypes.byref(c), stats)
+        _check(rc, allow=(ENOCONV,))
+        return {"a": a, "u": u, "t": t, "status": rc,
+                "stats": [{f: getattr(stats[k], f) for f, _ in _Stats._fields_} for k in range(ns)]}
 
     def matvec_free(self, s, x=None, bc_val=None, precision=0):
         """Matrix-free product y = A(s) x and/or b(s) (bc_val given).  Returns (y, b)."""

@@ -455,6 +455,56 @@ int afsbem_solve_device(afsbem_problem *p, int32_t n_s, const double *s, const v
     });
 }
 
+int afsbem_solve(afsbem_problem *p, int32_t n_s, const double *s, const double *bc_val, const double *x0,
+                 double *a_out, double *u_out, double *t_out, const afsbem_solve_opts *opts,
+                 afsbem_solve_stats *stats) {
+    return guarded([&] {
+        AFS_REQUIRE(p && s && bc_val, AFSBEM_EINVAL, "null pointer argument");
+        AFS_REQUIRE(n_s >= 0, AFSBEM_EINVAL, "n_s must be >= 0");
+        if (n_s == 0)
+            return (int)AFSBEM_OK;
+        const size_t bytes = (size_t)n_s * 3 * p->p.dev.n_tri * 16;
+        const bool need_a = a_out || (opts && opts->warm_start == AFSBEM_WARM_LEARNED);
+        std::vector<void *> bufs;
+        struct Free {
+            std::vector<void *> &b;
+            ~Free() {
+                for (void *q : b)
+                    (void)hipFree(q);
+            }
+        } fr{bufs};
+        auto dev = [&](bool want) -> void * {
+            if (!want)
+                return nullptr;
+            void *q = nullptr;
+            hipError_t e = hipMalloc(&q, bytes);
+            if (e != hipSuccess)
+                throw Error{AFSBEM_ENOMEM, std::string("hipMalloc failed: ") + hipGetErrorString(e)};
+            bufs.push_back(q);
+            return q;
+        };
+        void *d_bc = dev(true), *d_x0 = dev(x0 != nullptr), *d_a = dev(need_a), *d_u = dev(u_out != nullptr),
+             *d_t = dev(t_out != nullptr);
+        AFS_HIP(hipMemcpy(d_bc, bc_val, bytes, hipMemcpyHostToDevice));
+        if (x0)
+            AFS_HIP(hipMemcpy(d_x0, x0, bytes, hipMemcpyHostToDevice));
+        const int rc = afsbem_solve_device(p, n_s, s, d_bc, d_x0, d_a, d_u, d_t, opts, stats, nullptr);
+        if (rc != AFSBEM_OK && rc != AFSBEM_ENOCONV)
+            return rc;
+        const std::string msg = afsbem_last_error();
+        AFS_HIP(hipDeviceSynchronize());
+        if (a_out)
+            AFS_HIP(hipMemcpy(a_out, d_a, bytes, hipMemcpyDeviceToHost));
+        if (u_out)
+            AFS_HIP(hipMemcpy(u_out, d_u, bytes, hipMemcpyDeviceToHost));
+        if (t_out)
+            AFS_HIP(hipMemcpy(t_out, d_t, bytes, hipMemcpyDeviceToHost));
+        if (rc == AFSBEM_ENOCONV)
+            set_error(msg);
+        return rc;
+    });
+}
+
 int afsbem_solve_batched_device(int32_t n_prob, afsbem_problem *const *probs, const int32_t *n_s,
                                 const double *s, const void *const *d_bc_val, void *const *d_a_out,
                                 void *const *d_u_out, void *const *d_t_out, const afsbem_solve_opts *opts,

@@ -52,14 +52,15 @@ __device__ __forceinline__ void exp_sincos(double a, double b, double &e, double
 __device__ __forceinline__ float inv_sqrt(float a) { return rsqrtf(a); }
 __device__ __forceinline__ double inv_sqrt(double a) { return 1.0 / sqrt(a); }
 
-// Series about 0 below |x|^2 < thr2 (FP32: |x| < 1 with 12 terms, truncation
-// below 1e-8; FP64: |x| < 1/4 with 16 terms), closed form above.
+// Series about 0 below |x|^2 < thr2, closed form above.  FP32: |x| < 1/2 with
+// 9 terms (truncation ~1e-9; the closed form loses eps32/|x|^2 <= 5e-7 above);
+// FP64: |x| < 1/4 with 16 terms.
 template <class R>
 struct MfTraits;
 template <>
 struct MfTraits<float> {
-    static constexpr float thr2 = 1.0f;
-    static constexpr int nser = 12;
+    static constexpr float thr2 = 0.25f;
+    static constexpr int nser = 9;
 };
 template <>
 struct MfTraits<double> {

@@ -258,3 +258,18 @@ def test_cluster_preconditioner_blocks():
         idx = (3 * elem[ptr[c]:ptr[c + 1]][:, None] + np.arange(3)[None]).reshape(-1)
         zr[idx] = np.linalg.solve(Ao[np.ix_(idx, idx)], v[idx])
     assert np.linalg.norm(z - zr) / np.linalg.norm(zr) < 1e-5
+
+
+def test_solve_host_pointer_entry():
+    """afsbem_solve (host arrays in and out) on the small cavity and the rod."""
+    afs, bem = _afs(), _oracle()
+    for mesh, s in ((mg.cavity(1), mg.cavity_frequencies(3)), (mg.rod(2.0, 1.0, 3, 6), np.array([0.5 + 0.3j]))):
+        bc = np.stack([np.asarray(mesh.bc_shape, np.complex128) / sk for sk in s])
+        P = afs.Problem.from_mesh(mesh)
+        out = P.solve_host(s, bc, afs.SolveOptions(tol=1e-10, precision=afs.PREC_MIXED))
+        assert out["status"] == 0
+        for k, sk in enumerate(s):
+            x, uo, to = bem.solve(mesh, sk, bc[k])
+            assert np.linalg.norm(out["a"][k] - x) / np.linalg.norm(x) <= 1e-7
+            assert np.linalg.norm(out["u"][k] - uo) / np.linalg.norm(uo) <= 1e-7
+            assert np.linalg.norm(out["t"][k] - to) / np.linalg.norm(to) <= 1e-7
