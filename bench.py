@@ -13,9 +13,23 @@ Timed paths (same mesh, same s list, same GPU):
   * plain FP64: FP64 storage and GMRES(50) with block-Jacobi, zero x0 -> ``plain_fp64``
 Inputs (mesh plan, boundary values) are resident in HBM before timing starts.
 
-Also reported: the roofline of the dominant kernel (the GEMV streaming the
-matrix; its launches are timed with HIP events on the solve's stream during the
-timed steps) and the FP64 CPU oracle timed on this host on a bounded sample.
+Also reported: the roofline of the dominant kernel -- the FP64 far-field
+assembly kernel, VALU-bound; its launches are timed with HIP events on the
+assembly stream during the timed steps -- with the GEMV that streams the matrix
+(HBM-bound) beside it, the lockstep batched path on the same workload, and the
+FP64 CPU oracle timed on this host on a bounded sample.
+
+Algorithmic work per unit (counted from the formulas as implemented, closed-
+form branch of the radial functions; each sqrt, division, exp and sincos
+counted as one operation):
+  far field, per quadrature node (7 per source element, every pair m != n):
+    geometry 22 + radial functions 118 + traction coefficients 24
+    + traction invariants 63 + U.t for b 60 + 7 special functions
+    + per-pair expansion 90 / 7  ->  307 FP64 flops
+  GEMV: N^2 * 8 bytes (FP32 hi plane) per product.
+HBM traffic of these kernels from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE,
+FETCH_SIZE scaled by 2.0 (it reads 524,300 KiB for a 1 GiB device copy,
+WRITE_SIZE 1,048,576 KiB).
 """
 import argparse
 import json
@@ -29,6 +43,12 @@ if ROOT not in sys.path:
 
 METRIC = "frequency solves/s at rel-res 1e-6: mixed+batched+learned vs plain FP64"
 HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
+FAR_FLOPS_PER_NODE = 307.0
+FAR_NODES = 7
+# HBM bytes per launch, rocprofv3 --pmc on this workload (FETCH_SIZE x 2.0 + WRITE_SIZE)
+FAR_TRAFFIC_BYTES = (2.0 * 21978.77 + 3736212.70) * 1024
+GEMV32_TRAFFIC_BYTES = 2.0 * 923563.31 * 1024
 
 
 def parse():
@@ -41,6 +61,7 @@ def parse():
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain FP64 path")
+    ap.add_argument("--no-batched", action="store_true", help="skip the lockstep batched path")
     ap.add_argument("--cpu-freqs", type=int, default=1)
     ap.add_argument("--warm", choices=["none", "prev"], default="prev",
                     help="initial guess of the optimised path")
@@ -107,6 +128,9 @@ def main():
     st = out["stats"]
     worst = max(x["rel_res_fp64"] for x in st)
     assert worst <= args.tol, f"mixed path missed the tolerance: {worst}"
+    far_ms = sum(x["t_far_ms"] for x in st) / len(st)
+    far_flops = FAR_FLOPS_PER_NODE * FAR_NODES * float(P.n_tri) * (P.n_tri - 1)
+    far_tf = far_flops / (far_ms * 1e-3) / 1e12
     g_ms = sum(x["gemv_ms"] for x in st)
     g_n = sum(x["gemv_count"] for x in st)
     g64_ms = sum(x["gemv64_ms"] for x in st)
@@ -134,10 +158,14 @@ def main():
                            + ("previous-s warm start" if args.warm == "prev" else "zero start")
                            + (", assembly of s_k+1 overlapped with GMRES of s_k" if args.batch != 1 else ""),
                    "plan_s": plan_s},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "gemv_split32_kernel", "bytes_per_launch": bytes_per_launch,
-                     "avg_launch_ms": avg_ms, "launches": g_n},
+        "roofline": {"bound": "alu", "achieved": far_tf, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": far_tf / FP64_PEAK_TFLOPS, "traffic": FAR_TRAFFIC_BYTES,
+                     "kernel": "far_assemble_kernel (FP64 far-field rule, split store)",
+                     "flops_per_launch": far_flops, "avg_launch_ms": far_ms, "launches": len(st)},
+        "gemv": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                 "frac": achieved / HBM_PEAK_GBS, "traffic": GEMV32_TRAFFIC_BYTES,
+                 "kernel": "gemv_split32_kernel (live, sharing the GPU with the next assembly)",
+                 "bytes_per_launch": bytes_per_launch, "avg_launch_ms": avg_ms, "launches": g_n},
         "solve": {"max_rel_res_fp64": worst,
                   "matvecs_per_solve": sum(x["iters"] for x in st) / len(st),
                   "refine_steps_per_solve": sum(x["refine_steps"] for x in st) / len(st),
@@ -164,6 +192,23 @@ def main():
                              "gemv_c128_GBs": float(N) * N * 16 / (gp_ms / max(gp_n, 1) * 1e-3) / 1e9}
         res["speedup_vs_plain_fp64"] = res["value"] / res["plain_fp64"]["value"]
         del out
+    if not args.no_batched:
+        bopts = afs.SolveOptions(tol=args.tol, precision=afs.PREC_MIXED)
+        for _ in range(args.warmup):
+            outs, _ = afs.solve_batched([P], [s], [bc], bopts)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            outs, _ = afs.solve_batched([P], [s], [bc], bopts)
+        torch.cuda.synchronize()
+        ms_b = (time.perf_counter() - t0) * 1e3 / args.steps
+        sb = outs[0]["stats"]
+        res["batched_lockstep"] = {"value": args.nfreq / (ms_b * 1e-3), "ms_per_step": ms_b,
+                                   "max_rel_res_fp64": max(x["rel_res_fp64"] for x in sb),
+                                   "inner_matvecs_per_solve": sum(x["iters"] for x in sb) / len(sb),
+                                   "path": "all frequencies in waves solved in lockstep, FP32 inner cycles, "
+                                           "FP64 residuals, next wave assembled during the current solve"}
+        del outs
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline(mesh, s, args.cpu_freqs)
     print(json.dumps(res), flush=True)

@@ -193,6 +193,8 @@ typedef struct {
     double rel_res_start; /* ||b - A x0|| / ||b|| of the starting iterate (1 from zero) */
     int32_t used_net;     /* 1 if the warm-start network's prediction entered x0 */
     int32_t pad_;
+    double t_far_ms;      /* with opts.profile: device time of the far-field kernel of the
+                             assembly (stored operators), else 0 */
 } afsbem_solve_stats;
 
 /* Fills opts with the defaults listed above. */

@@ -49,7 +49,8 @@ class _Stats(ctypes.Structure):
                 ("status", ctypes.c_int32), ("rel_res_fp64", ctypes.c_double), ("t_assemble_ms", ctypes.c_double),
                 ("t_solve_ms", ctypes.c_double), ("bytes", ctypes.c_double), ("gemv_ms", ctypes.c_double),
                 ("gemv64_ms", ctypes.c_double), ("gemv_count", ctypes.c_int32), ("gemv64_count", ctypes.c_int32),
-                ("rel_res_start", ctypes.c_double), ("used_net", ctypes.c_int32), ("pad_", ctypes.c_int32)]
+                ("rel_res_start", ctypes.c_double), ("used_net", ctypes.c_int32), ("pad_", ctypes.c_int32),
+                ("t_far_ms", ctypes.c_double)]
 
 
 class _AfsParams(ctypes.Structure):

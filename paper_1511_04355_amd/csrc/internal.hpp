@@ -137,7 +137,7 @@ size_t assembly_scratch_bytes(const Problem &p);
 // block-Jacobi inverses.  format: AFSBEM_FMT_*.
 void launch_assembly(const Problem &p, const KernelParams &kp, const double *bc_val, int format,
                      void *A, void *A_lo, double *b, double *precond, void *scratch,
-                     hipStream_t st);
+                     hipStream_t st, hipEvent_t far_begin = nullptr, hipEvent_t far_end = nullptr);
 
 // Matrix-free operator (no stored dense matrix).  Per frequency: the near-pair
 // correction blocks (exact minus the far rule) [nnz][9] and the self blocks

@@ -634,7 +634,8 @@ static Rule7Args rule7_args() {
 }
 
 void launch_assembly(const Problem &p, const KernelParams &kp, const double *bc_val, int format, void *A,
-                     void *A_lo, double *b, double *precond, void *scratch, hipStream_t st) {
+                     void *A_lo, double *b, double *precond, void *scratch, hipStream_t st, hipEvent_t far_begin,
+                     hipEvent_t far_end) {
     const DevicePlan &d = p.dev;
     const int64_t nt = d.n_tri, N = 3 * nt;
     const int64_t lda = (N + 63) / 64 * 64;
@@ -649,9 +650,17 @@ void launch_assembly(const Problem &p, const KernelParams &kp, const double *bc_
     const unsigned gnear = (unsigned)((d.nnz * kNearLanes + 255) / 256);
     const unsigned gself = (unsigned)((nt * 64 + 255) / 256);
     const Rule7Args rule = rule7_args();
-    if (format == AFSBEM_FMT_C128) {
+    if (far_begin)
+        AFS_HIP(hipEventRecord(far_begin, st));
+    if (format == AFSBEM_FMT_C128)
         far_assemble_kernel<AFSBEM_FMT_C128><<<gfar, 256, 0, st>>>(nt, lda, kp, d.colx, d.coly, d.colz, d.src, bc_val,
                                                                   coef, chunk, A, A_lo, bpart);
+    else
+        far_assemble_kernel<AFSBEM_FMT_SPLIT><<<gfar, 256, 0, st>>>(nt, lda, kp, d.colx, d.coly, d.colz, d.src,
+                                                                   bc_val, coef, chunk, A, A_lo, bpart);
+    if (far_end)
+        AFS_HIP(hipEventRecord(far_end, st));
+    if (format == AFSBEM_FMT_C128) {
         if (d.nnz)
             near_assemble_kernel<AFSBEM_FMT_C128><<<gnear, 256, 0, st>>>(
                 nt, lda, d.nnz, kp, rule, d.colx, d.coly, d.colz, d.src, bc_val, coef, d.near_row, d.near_col,
@@ -660,8 +669,6 @@ void launch_assembly(const Problem &p, const KernelParams &kp, const double *bc_
                                                                     bc_val, coef, d.self_ang, d.self_cpv, d.gl_rho,
                                                                     d.n_theta, d.n_rho, A, A_lo, bself, precond);
     } else {
-        far_assemble_kernel<AFSBEM_FMT_SPLIT><<<gfar, 256, 0, st>>>(nt, lda, kp, d.colx, d.coly, d.colz, d.src,
-                                                                   bc_val, coef, chunk, A, A_lo, bpart);
         if (d.nnz)
             near_assemble_kernel<AFSBEM_FMT_SPLIT><<<gnear, 256, 0, st>>>(
                 nt, lda, d.nnz, kp, rule, d.colx, d.coly, d.colz, d.src, bc_val, coef, d.near_row, d.near_col,

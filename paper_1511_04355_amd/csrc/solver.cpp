@@ -45,6 +45,12 @@ void Workspace::release() {
     for (hipEvent_t e : ev)
         (void)hipEventDestroy(e);
     ev.clear();
+    for (auto &e : ev_far)
+        if (e) {
+            (void)hipEventDestroy(e);
+            e = nullptr;
+        }
+    far_timed = false;
     ev_prec.clear();
     ev_used = 0;
     // reset every field in place (no temporary Workspace: its destructor would
@@ -404,7 +410,7 @@ static double elapsed_ms(hipEvent_t a, hipEvent_t b) {
 }
 
 static void assemble_into(Problem &p, Workspace &ws, int fmt, double s_re, double s_im, const double *d_bc,
-                          hipStream_t st) {
+                          hipStream_t st, bool profile = false) {
     KernelParams kp = kernel_params(p.mat, s_re, s_im);
     if (fmt == kFmtBlocks) {
         // near/self blocks and b (far part evaluated on the fly in FP64)
@@ -414,7 +420,13 @@ static void assemble_into(Problem &p, Workspace &ws, int fmt, double s_re, doubl
         launch_finalize_b(p, mf_chunks(p.dev.n_tri), bpart, ws.asm_scratch, ws.b, st);
         return;
     }
-    launch_assembly(p, kp, d_bc, fmt, ws.A, ws.A_lo, ws.b, ws.precond, ws.asm_scratch, st);
+    if (profile)
+        for (auto &e : ws.ev_far)
+            if (!e)
+                AFS_HIP(hipEventCreate(&e));
+    ws.far_timed = profile;
+    launch_assembly(p, kp, d_bc, fmt, ws.A, ws.A_lo, ws.b, ws.precond, ws.asm_scratch, st,
+                    profile ? ws.ev_far[0] : nullptr, profile ? ws.ev_far[1] : nullptr);
     if (ws.prec_kind == 1)
         cluster_inverse(p.dev, fmt, ws.A, ws.A_lo, ws.clinv, st);
 }
@@ -525,6 +537,7 @@ static int krylov_phase(Problem &p, Workspace &ws, const afsbem_solve_opts &o, i
         stats->t_solve_ms = elapsed_ms(ek, e2);
         stats->bytes = bytes;
         stats->gemv_ms = stats->gemv64_ms = 0.0;
+        stats->t_far_ms = ws.far_timed ? elapsed_ms(ws.ev_far[0], ws.ev_far[1]) : 0.0;
         stats->gemv_count = stats->gemv64_count = 0;
         for (int k = 0; k < ws.ev_used; ++k) {
             const double ms = elapsed_ms(ws.ev[2 * k], ws.ev[2 * k + 1]);
@@ -556,7 +569,7 @@ int solve_one(Problem &p, const afsbem_solve_opts &o, double s_re, double s_im, 
     AFS_HIP(hipEventCreate(&e1));
     AFS_HIP(hipEventCreate(&e2));
     AFS_HIP(hipEventRecord(e0, st));
-    assemble_into(p, ws, fmt, s_re, s_im, d_bc, st);
+    assemble_into(p, ws, fmt, s_re, s_im, d_bc, st, o.profile != 0);
     AFS_HIP(hipEventRecord(e1, st));
     int rc;
     try {
@@ -621,7 +634,7 @@ int solve_pipelined(Problem &p, const afsbem_solve_opts &o, int32_t n_s, const d
             if (k >= 2)
                 AFS_HIP(hipStreamWaitEvent(SA, sdone[k - 2], 0));  // workspace free again
             AFS_HIP(hipEventRecord(a0[k], SA));
-            assemble_into(p, w, fmt, s[2 * k], s[2 * k + 1], bc + 2 * (size_t)k * N, SA);
+            assemble_into(p, w, fmt, s[2 * k], s[2 * k + 1], bc + 2 * (size_t)k * N, SA, o.profile != 0);
             AFS_HIP(hipEventRecord(a1[k], SA));
         };
         enqueue_asm(0);

@@ -27,6 +27,8 @@ struct Workspace {
     std::vector<hipEvent_t> ev;            // 2 per slot
     std::vector<int> ev_prec;              // precision of the product in each used slot
     int ev_used = 0;
+    hipEvent_t ev_far[2] = {nullptr, nullptr};  // around the far-field kernel (opts.profile)
+    bool far_timed = false;
     void reset_timing() { ev_used = 0; ev_prec.clear(); }
     ~Workspace();
     void release();
