@@ -46,9 +46,10 @@ HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
 FAR_FLOPS_PER_NODE = 307.0
 FAR_NODES = 7
-# HBM bytes per launch, rocprofv3 --pmc on this workload (FETCH_SIZE x 2.0 + WRITE_SIZE)
-FAR_TRAFFIC_BYTES = (2.0 * 21978.77 + 3736212.70) * 1024
-GEMV32_TRAFFIC_BYTES = 2.0 * 923563.31 * 1024
+# HBM bytes per launch from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE over --workload pmc_probe
+# (FETCH_SIZE x 2.0, its reading for a 1 GiB device copy being half the true bytes)
+FAR_TRAFFIC_BYTES = (2.0 * 22011.25 + 3736702.23) * 1024
+GEMV32_TRAFFIC_BYTES = 2.0 * 923563.16 * 1024
 
 
 def parse():
@@ -65,6 +66,14 @@ def parse():
     ap.add_argument("--cpu-freqs", type=int, default=1)
     ap.add_argument("--warm", choices=["none", "prev"], default="prev",
                     help="initial guess of the optimised path")
+    ap.add_argument("--workload", default="cavity_L4",
+                    choices=["cavity_L4", "pmc_probe", "cavity_L2_batched", "blocks_batched", "porous_learned",
+                             "porous_matrix_free"],
+                    help="cavity_L4: the contract line (default).  The others print their own JSON line: "
+                         "pmc_probe (1 GiB copies + 4 mixed solves, for counter runs), cavity_L2_batched "
+                         "(320 triangles, 16 frequencies), blocks_batched (16 seeded porous blocks x 24 "
+                         "frequencies), porous_learned (27-void block, 40,320 unknowns: warm-start A/B on an "
+                         "AFS frequency sequence), porous_matrix_free (64-void block, 300,516 unknowns)")
     ap.add_argument("--batch", type=int, default=0,
                     help="optimised path: 1 = one frequency at a time, 0 = assembly of the next frequency "
                          "overlapped with the Krylov phase of the current one")
@@ -100,6 +109,178 @@ def cpu_baseline(mesh, s_list, nfreq):
                       f"+ LAPACK LU solve, {dt:.1f} s"}
 
 
+def _bcs(mesh, s, torch, np):
+    return torch.from_numpy(np.stack([np.asarray(mesh.bc_shape, np.complex128) / sk for sk in s])).cuda()
+
+
+def _clock(fn, steps, warmup, torch):
+    out = None
+    for _ in range(warmup):
+        out = fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        out = fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3 / max(steps, 1), out
+
+
+def run_pmc_probe(afs, mg, np, torch):
+    """Short fixed program for counter runs: 3 device copies of 1 GiB (the
+    calibration of FETCH_SIZE / WRITE_SIZE), then 4 mixed pipelined solves of
+    the level-4 cavity (s_8 .. s_11) with event timing."""
+    x = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    del x, y
+    mesh = mg.cavity(4)
+    s = mg.cavity_frequencies(64)[8:12]
+    P = afs.Problem.from_mesh(mesh)
+    o = P.solve(s, _bcs(mesh, s, torch, np),
+                afs.SolveOptions(tol=1e-6, precision=afs.PREC_MIXED, warm_start=afs.WARM_PREV, profile=1),
+                want_ut=False)
+    torch.cuda.synchronize()
+    return {"workload": "pmc_probe", "far_ms": [st["t_far_ms"] for st in o["stats"]]}
+
+
+def run_cavity_L2_batched(args, afs, mg, np, torch):
+    """320-triangle cavity, 16 frequencies, FP64 tol 1e-8: one frequency at a
+    time vs all 16 in one lockstep call (FP64 and mixed)."""
+    mesh = mg.cavity(2)
+    s = mg.cavity_frequencies(16)
+    bc = _bcs(mesh, s, torch, np)
+    P = afs.Problem.from_mesh(mesh)
+    res = {"workload": "cavity_L2_batched: icosphere level 2 (320 triangles, 960 unknowns), 16 frequencies, "
+                       "FP64 true rel. residual <= 1e-8", "unit": "frequency solves/s"}
+    legs = {
+        "sequential_fp64": lambda: P.solve(s, bc, afs.SolveOptions(tol=1e-8, batch=1), want_ut=False)["stats"],
+        "batched_fp64": lambda: afs.solve_batched([P], [s], [bc], afs.SolveOptions(tol=1e-8))[0][0]["stats"],
+        "batched_mixed": lambda: afs.solve_batched([P], [s], [bc],
+                                                   afs.SolveOptions(tol=1e-8, precision=afs.PREC_MIXED))[0][0]["stats"],
+    }
+    for name, fn in legs.items():
+        ms, st = _clock(fn, args.steps * 10, args.warmup, torch)
+        res[name] = {"value": 16 / (ms * 1e-3), "ms_per_step": ms,
+                     "max_rel_res_fp64": max(x["rel_res_fp64"] for x in st),
+                     "matvecs_per_solve": sum(x["iters"] for x in st) / len(st)}
+    res["speedup_batched_fp64"] = res["batched_fp64"]["value"] / res["sequential_fp64"]["value"]
+    return res
+
+
+def run_blocks_batched(args, afs, mg, np, torch):
+    """16 seeded porous blocks (2.8k-20k unknowns), 24 frequencies each on the
+    line Re s = 0.023 over [0, 5.36]: each block's frequencies pipelined one
+    block after another vs all 384 systems through the lockstep batched call."""
+    meshes = [mg.random_block(seed) for seed in range(16)]
+    s = mg.block_frequencies(24)
+    probs = [afs.Problem.from_mesh(m) for m in meshes]
+    bcs = [_bcs(m, s, torch, np) for m in meshes]
+    opts = afs.SolveOptions(tol=args.tol, precision=afs.PREC_MIXED, restart=150, max_iter=6000)
+    res = {"workload": "blocks_batched: 16 porous blocks (seeds 0-15), unknowns "
+                       + ",".join(str(3 * m.n_tri) for m in meshes) + f"; 24 frequencies each; mixed, "
+                       f"GMRES(150), FP64 true rel. residual <= {args.tol}", "unit": "frequency solves/s"}
+
+    def seq():
+        st = []
+        for P, b in zip(probs, bcs):
+            o = P.solve(s, b, afs.SolveOptions(tol=args.tol, precision=afs.PREC_MIXED, restart=150, max_iter=6000,
+                                               warm_start=afs.WARM_PREV), want_ut=False)
+            st += o["stats"]
+        return st
+
+    def bat():
+        outs, _ = afs.solve_batched(probs, [s] * 16, bcs, opts)
+        return [x for o in outs for x in o["stats"]]
+
+    for name, fn in (("per_block_pipelined", seq), ("batched_lockstep", bat)):
+        ms, st = _clock(fn, 1, 0, torch)
+        res[name] = {"value": 384 / (ms * 1e-3), "seconds": ms * 1e-3,
+                     "max_rel_res_fp64": max(x["rel_res_fp64"] for x in st),
+                     "not_converged": sum(1 for x in st if x["status"] != 0),
+                     "inner_matvecs_mean": sum(x["iters"] for x in st) / len(st),
+                     "inner_matvecs_max": max(x["iters"] for x in st)}
+    res["speedup_batched"] = res["batched_lockstep"]["value"] / res["per_block_pipelined"]["value"]
+    return res
+
+
+def run_porous_learned(args, afs, mg, np, torch):
+    """27-void porous block (13,440 elements, 40,320 unknowns): the frequency
+    sequence of an AFS run (J0 = 16 Chebyshev points, then adaptive, at most 24
+    samples) without learning, replayed in the same order with zero, previous-s
+    and learned (network trained on the GPU after each solve) initial guesses."""
+    mesh = mg.lattice_block(3, 20, 2, 1000)
+    P = afs.Problem.from_mesh(mesh)
+    T, kappa, Ns = 300.0, 3.0, 512
+    eta = kappa * np.log(10.0) / T
+    rng = np.random.default_rng(1000)
+    loaded = np.nonzero(np.abs(np.asarray(mesh.bc_shape)).sum(1) > 0)[0]
+    dofs = np.sort(3 * rng.choice(loaded, 6, replace=False) + 2)
+    params = afs.afs_params(T, eta, Ns, max_Nc=24)
+    base = afs.SolveOptions(tol=args.tol, precision=afs.PREC_MIXED, restart=100, max_iter=8000)
+    t0 = time.perf_counter()
+    r = P.afs(params, np.asarray(mesh.bc_shape, np.float64).reshape(-1), dofs, 4, load_kind=0, opts=base)
+    afs_s = time.perf_counter() - t0
+    s = np.asarray(r["s"])
+    P.close()
+    res = {"workload": f"porous_learned: 27-void block ({mesh.n_tri} elements, {3 * mesh.n_tri} unknowns), "
+                       f"{len(s)} AFS frequencies (T=300, eta={eta:.4f}), mixed GMRES(100), "
+                       f"FP64 true rel. residual <= {args.tol}", "afs_seconds": afs_s, "n_freq": len(s)}
+    bc = _bcs(mesh, s, torch, np)
+    for name, warm in (("zero", afs.WARM_NONE), ("previous", afs.WARM_PREV), ("learned", afs.WARM_LEARNED)):
+        Q = afs.Problem.from_mesh(mesh)  # fresh network for the learned leg
+        o = afs.SolveOptions(tol=args.tol, precision=afs.PREC_MIXED, restart=100, max_iter=8000, warm_start=warm,
+                             batch=1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = Q.solve(s, bc, o, want_ut=False)
+        torch.cuda.synchronize()
+        st = out["stats"]
+        res[name] = {"seconds": time.perf_counter() - t0, "value": len(s) / (time.perf_counter() - t0),
+                     "matvecs_total": sum(x["iters"] for x in st),
+                     "rel_res_start_median": float(np.median([x["rel_res_start"] for x in st])),
+                     "used_net": sum(x["used_net"] for x in st),
+                     "max_rel_res_fp64": max(x["rel_res_fp64"] for x in st)}
+        Q.close()
+    return res
+
+
+def run_porous_matrix_free(args, afs, mg, np, torch):
+    """64-void porous block (100,172 elements, 300,516 unknowns; the dense
+    matrix would need 1.4 TB): matrix-free products in both precisions, and one
+    mixed solve at the lowest frequency s = eta."""
+    mesh = mg.lattice_block(4, 39, 3, 2000, rmax=0.45)
+    t0 = time.perf_counter()
+    P = afs.Problem.from_mesh(mesh)
+    torch.cuda.synchronize()
+    res = {"workload": f"porous_matrix_free: 64-void block ({mesh.n_tri} elements, {3 * mesh.n_tri} unknowns)",
+           "plan_s": time.perf_counter() - t0, "info": P.info()}
+    N = 3 * mesh.n_tri
+    rng = np.random.default_rng(0)
+    x = torch.from_numpy(rng.standard_normal(N) + 1j * rng.standard_normal(N)).cuda()
+    s0 = 0.023 + 1.0j
+    pairs = float(mesh.n_tri) * (mesh.n_tri - 1)
+    for prec, name in ((1, "product_fp32"), (0, "product_fp64")):
+        ms, _ = _clock(lambda: P.matvec_free(s0, x, precision=prec), 2, 1, torch)
+        res[name] = {"ms_incl_block_setup": ms, "node_evals_per_s": pairs * 7 / (ms * 1e-3)}
+    eta = 3.0 * np.log(10.0) / 300.0
+    s = np.array([eta + 0.0j])
+    o = afs.SolveOptions(tol=args.tol, precision=afs.PREC_MIXED, matrix_free=1, restart=100, max_iter=2000,
+                         profile=1, batch=1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = P.solve(s, _bcs(mesh, s, torch, np), o, want_ut=False)
+    torch.cuda.synchronize()
+    st = out["stats"][0]
+    res["solve_mixed_s_eta"] = {"seconds": time.perf_counter() - t0, "inner_products": st["gemv_count"],
+                                "inner_ms_avg": st["gemv_ms"] / max(st["gemv_count"], 1),
+                                "fp64_products": st["gemv64_count"],
+                                "fp64_ms_avg": st["gemv64_ms"] / max(st["gemv64_count"], 1),
+                                "rel_res_fp64": st["rel_res_fp64"], "setup_ms": st["t_assemble_ms"]}
+    return res
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -113,6 +294,14 @@ def main():
     from synth import meshgen as mg
 
     torch.cuda.set_device(0)
+    if args.workload != "cavity_L4":
+        fn = {"pmc_probe": lambda: run_pmc_probe(afs, mg, np, torch),
+              "cavity_L2_batched": lambda: run_cavity_L2_batched(args, afs, mg, np, torch),
+              "blocks_batched": lambda: run_blocks_batched(args, afs, mg, np, torch),
+              "porous_learned": lambda: run_porous_learned(args, afs, mg, np, torch),
+              "porous_matrix_free": lambda: run_porous_matrix_free(args, afs, mg, np, torch)}[args.workload]
+        print(json.dumps(fn()), flush=True)
+        return
     mesh = mg.cavity(args.level)
     s = mg.cavity_frequencies(args.nfreq)
     bc = torch.from_numpy(np.stack([np.asarray(mesh.bc_shape, np.complex128) / sk for sk in s])).cuda()
