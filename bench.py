@@ -74,6 +74,7 @@ def parse():
                          "(320 triangles, 16 frequencies), blocks_batched (16 seeded porous blocks x 24 "
                          "frequencies), porous_learned (27-void block, 40,320 unknowns: warm-start A/B on an "
                          "AFS frequency sequence), porous_matrix_free (64-void block, 300,516 unknowns)")
+    ap.add_argument("--afs-max", type=int, default=24, help="porous_learned: cap on AFS samples")
     ap.add_argument("--batch", type=int, default=0,
                     help="optimised path: 1 = one frequency at a time, 0 = assembly of the next frequency "
                          "overlapped with the Krylov phase of the current one")
@@ -157,6 +158,8 @@ def run_cavity_L2_batched(args, afs, mg, np, torch):
     legs = {
         "sequential_fp64": lambda: P.solve(s, bc, afs.SolveOptions(tol=1e-8, batch=1), want_ut=False)["stats"],
         "batched_fp64": lambda: afs.solve_batched([P], [s], [bc], afs.SolveOptions(tol=1e-8))[0][0]["stats"],
+        "batched_fp64_no_graph": lambda: afs.solve_batched([P], [s], [bc],
+                                                           afs.SolveOptions(tol=1e-8, no_graph=1))[0][0]["stats"],
         "batched_mixed": lambda: afs.solve_batched([P], [s], [bc],
                                                    afs.SolveOptions(tol=1e-8, precision=afs.PREC_MIXED))[0][0]["stats"],
     }
@@ -184,13 +187,15 @@ def run_blocks_batched(args, afs, mg, np, torch):
 
     def seq():
         st = []
-        for P, b in zip(probs, bcs):
+        for j, (P, b) in enumerate(zip(probs, bcs)):
             o = P.solve(s, b, afs.SolveOptions(tol=args.tol, precision=afs.PREC_MIXED, restart=150, max_iter=6000,
                                                warm_start=afs.WARM_PREV), want_ut=False)
             st += o["stats"]
+            print(f"[blocks] block {j} done", file=sys.stderr, flush=True)
         return st
 
     def bat():
+        print("[blocks] batched call", file=sys.stderr, flush=True)
         outs, _ = afs.solve_batched(probs, [s] * 16, bcs, opts)
         return [x for o in outs for x in o["stats"]]
 
@@ -207,9 +212,10 @@ def run_blocks_batched(args, afs, mg, np, torch):
 
 def run_porous_learned(args, afs, mg, np, torch):
     """27-void porous block (13,440 elements, 40,320 unknowns): the frequency
-    sequence of an AFS run (J0 = 16 Chebyshev points, then adaptive, at most 24
-    samples) without learning, replayed in the same order with zero, previous-s
-    and learned (network trained on the GPU after each solve) initial guesses."""
+    sequence of an AFS run (J0 = 16 Chebyshev points, then adaptive, at most
+    args.afs_max samples) without learning, replayed in the same order with
+    zero, previous-s and learned (network trained on the GPU after each solve)
+    initial guesses.  Prints a progress line per solve batch on stderr."""
     mesh = mg.lattice_block(3, 20, 2, 1000)
     P = afs.Problem.from_mesh(mesh)
     T, kappa, Ns = 300.0, 3.0, 512
@@ -217,31 +223,59 @@ def run_porous_learned(args, afs, mg, np, torch):
     rng = np.random.default_rng(1000)
     loaded = np.nonzero(np.abs(np.asarray(mesh.bc_shape)).sum(1) > 0)[0]
     dofs = np.sort(3 * rng.choice(loaded, 6, replace=False) + 2)
-    params = afs.afs_params(T, eta, Ns, max_Nc=24)
-    base = afs.SolveOptions(tol=args.tol, precision=afs.PREC_MIXED, restart=100, max_iter=8000)
+    shape = np.asarray(mesh.bc_shape, np.complex128)
+    base = dict(tol=args.tol, precision=afs.PREC_MIXED, restart=100, max_iter=8000)
+    prev = {}
+
+    def response(sv):
+        # GPU solves of the requested frequencies, each warm-started from the
+        # nearest frequency solved so far (the AFS loop's own policy)
+        rows = []
+        for sk in sv:
+            x0 = None
+            o = afs.SolveOptions(**base)
+            if prev:
+                near = min(prev, key=lambda q: abs(q - sk))
+                x0 = prev[near][None]
+                o.warm_start = afs.WARM_USER
+            bc = torch.from_numpy((shape / sk)[None]).cuda()
+            out = P.solve(np.array([sk]), bc, o, x0=x0, want_ut=False)
+            prev[complex(sk)] = out["a"][0].clone()
+            rows.append(out["a"][0].cpu().numpy()[dofs])
+            st = out["stats"][0]
+            print(f"[afs] s={sk.real:.4f}{sk.imag:+.4f}i matvecs={st['iters']} rel={st['rel_res_fp64']:.1e}",
+                  file=sys.stderr, flush=True)
+        return np.array(rows)
+
+    params = afs.afs_params(T, eta, Ns, max_Nc=args.afs_max)
     t0 = time.perf_counter()
-    r = P.afs(params, np.asarray(mesh.bc_shape, np.float64).reshape(-1), dofs, 4, load_kind=0, opts=base)
+    r = afs.afs_run(response, 4, len(dofs), params)
     afs_s = time.perf_counter() - t0
     s = np.asarray(r["s"])
     P.close()
     res = {"workload": f"porous_learned: 27-void block ({mesh.n_tri} elements, {3 * mesh.n_tri} unknowns), "
-                       f"{len(s)} AFS frequencies (T=300, eta={eta:.4f}), mixed GMRES(100), "
-                       f"FP64 true rel. residual <= {args.tol}", "afs_seconds": afs_s, "n_freq": len(s)}
+                       f"{len(s)} AFS frequencies (T=300, eta={eta:.4f}, Ns=512), mixed GMRES(100), "
+                       f"FP64 true rel. residual <= {args.tol}", "afs_seconds": afs_s, "n_freq": len(s),
+           "afs_converged": bool(r["converged"])}
     bc = _bcs(mesh, s, torch, np)
     for name, warm in (("zero", afs.WARM_NONE), ("previous", afs.WARM_PREV), ("learned", afs.WARM_LEARNED)):
         Q = afs.Problem.from_mesh(mesh)  # fresh network for the learned leg
-        o = afs.SolveOptions(tol=args.tol, precision=afs.PREC_MIXED, restart=100, max_iter=8000, warm_start=warm,
-                             batch=1)
+        o = afs.SolveOptions(warm_start=warm, batch=1, **base)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        out = Q.solve(s, bc, o, want_ut=False)
+        stats = []
+        for k in range(len(s)):  # one call per frequency: same state as one call, with progress
+            out = Q.solve(s[k:k + 1], bc[k:k + 1], o, want_ut=False,
+                          x0=None if (warm == afs.WARM_NONE or k == 0) else a_prev[None])
+            a_prev = out["a"][0].clone()
+            stats += out["stats"]
+            print(f"[{name}] k={k} matvecs={out['stats'][0]['iters']}", file=sys.stderr, flush=True)
         torch.cuda.synchronize()
-        st = out["stats"]
-        res[name] = {"seconds": time.perf_counter() - t0, "value": len(s) / (time.perf_counter() - t0),
-                     "matvecs_total": sum(x["iters"] for x in st),
-                     "rel_res_start_median": float(np.median([x["rel_res_start"] for x in st])),
-                     "used_net": sum(x["used_net"] for x in st),
-                     "max_rel_res_fp64": max(x["rel_res_fp64"] for x in st)}
+        dt = time.perf_counter() - t0
+        res[name] = {"seconds": dt, "value": len(s) / dt, "matvecs_total": sum(x["iters"] for x in stats),
+                     "rel_res_start_median": float(np.median([x["rel_res_start"] for x in stats])),
+                     "used_net": sum(x["used_net"] for x in stats),
+                     "max_rel_res_fp64": max(x["rel_res_fp64"] for x in stats)}
         Q.close()
     return res
 

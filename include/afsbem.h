@@ -147,7 +147,8 @@ int afsbem_precond_apply_device(afsbem_problem *p, int format, const void *d_A, 
 
 /* ---------------------------------------------------------------- solve --- */
 enum { AFSBEM_PREC_FP64 = 0, AFSBEM_PREC_MIXED = 1 };
-/* Initial guesses.  PREV: the previous frequency's solution; USER: d_x0;
+/* Initial guesses.  PREV: the previous frequency's solution (for the first
+ * frequency of a call: d_x0 when given, one [N] vector); USER: d_x0;
  * LEARNED: the warm-start network of the problem (trained on the solutions of
  * all frequencies it has solved so far, across calls) combined with the
  * previous solution.  Every guess x0 is rescaled (or the pair combined) to
@@ -175,6 +176,8 @@ typedef struct {
                             fly (FP64, or FP32 for the inner products of the mixed path) and adds
                             the near/self blocks formed once per frequency in FP64 (needs
                             precond 0); memory O(N + near pairs) instead of O(N^2) */
+    int32_t no_graph;    /* batched solve: 1 = launch every kernel directly instead of replaying
+                            the captured graphs of four Arnoldi steps (default 0) */
 } afsbem_solve_opts;
 
 typedef struct {
@@ -203,7 +206,8 @@ int afsbem_solve_opts_default(afsbem_solve_opts *opts);
 /* Solves A(s_k) a_k = b_k for n_s frequencies s (host array, 2*n_s doubles).
  * d_bc_val: [n_s][n_tri][3] complex<double> prescribed values at each s.
  * d_x0: nullable [n_s][N] complex<double> initial guesses (used with
- *       AFSBEM_WARM_USER).
+ *       AFSBEM_WARM_USER; with PREV or LEARNED its first N entries stand for
+ *       the solution preceding the first frequency).
  * Outputs (each nullable): d_a_out [n_s][N] solution vector, d_u_out and
  * d_t_out [n_s][n_tri][3] displacement and traction per element.
  * stats: nullable host array of n_s entries.

@@ -41,7 +41,8 @@ class _Opts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("restart", ctypes.c_int32), ("max_iter", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("warm_start", ctypes.c_int32), ("inner_tol", ctypes.c_double),
                 ("batch", ctypes.c_int32), ("fault_inject", ctypes.c_uint32), ("profile", ctypes.c_int32),
-                ("learn_steps", ctypes.c_int32), ("precond", ctypes.c_int32), ("matrix_free", ctypes.c_int32)]
+                ("learn_steps", ctypes.c_int32), ("precond", ctypes.c_int32), ("matrix_free", ctypes.c_int32),
+                ("no_graph", ctypes.c_int32)]
 
 
 class _Stats(ctypes.Structure):
@@ -152,10 +153,12 @@ class SolveOptions:
     learn_steps: int = 0
     precond: int = 0
     matrix_free: int = 0
+    no_graph: int = 0
 
     def _c(self):
         return _Opts(self.tol, self.restart, self.max_iter, self.precision, self.warm_start, self.inner_tol,
-                     self.batch, self.fault_inject, self.profile, self.learn_steps, self.precond, self.matrix_free)
+                     self.batch, self.fault_inject, self.profile, self.learn_steps, self.precond, self.matrix_free,
+                     self.no_graph)
 
 
 class Problem:

@@ -9,7 +9,9 @@
 // inner operator (FP64, or the FP32 hi plane in the mixed path) gives the
 // correction added to x.  One launch per step serves every system; finished
 // systems are masked out; the host polls the number of systems still in the
-// cycle every four steps.
+// cycle every four steps.  Each block of four steps is captured once per wave
+// as a HIP graph and replayed (the launches of a block are ~50 small kernels
+// when the systems are small).
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -19,7 +21,16 @@
 
 namespace afsbem {
 
+void BatchArena::drop_graphs() {
+    for (auto &kv : graphs)
+        for (auto e : kv.second)
+            if (e)
+                (void)hipGraphExecDestroy(e);
+    graphs.clear();
+}
+
 BatchArena::~BatchArena() {
+    drop_graphs();
     if (base)
         (void)hipFree(base);
     for (auto &q : st_asm)
@@ -39,6 +50,7 @@ void BatchArena::reserve(size_t bytes) {
         return;
     if (base) {
         AFS_HIP(hipDeviceSynchronize());
+        drop_graphs();
         (void)hipFree(base);
         base = nullptr;
         cap = 0;
@@ -52,6 +64,8 @@ void BatchArena::reserve(size_t bytes) {
 }
 
 namespace {
+
+constexpr int kStepsPerCheck = 4;  // Arnoldi steps between host checks (one graph)
 
 struct SysRef {
     int prob, k;
@@ -309,6 +323,7 @@ int solve_batched(int n_prob, Problem *const *probs, const int32_t *n_s, const d
 
     int rc_all = AFSBEM_OK;
     const int kin = mixed ? 1 : 0, kout = mixed ? 2 : 0;
+    const bool use_graphs = o.no_graph == 0;
     assemble(0);
     for (int wi = 0; wi < n_waves; ++wi) {
         Wave &W = slots[wi & 1];
@@ -336,6 +351,39 @@ int solve_batched(int n_prob, Problem *const *probs, const int32_t *n_s, const d
         up(W.ones, W.onesh, st);
         AFS_HIP(hipStreamWaitEvent(st, W.asm_end, 0));
         AFS_HIP(hipEventRecord(s0, st));
+        // Arnoldi steps k0 .. k0+3 of the current cycle for every system still
+        // in it, then the count of those systems (W.cnt).  With graphs on, each
+        // such block is captured once per wave and replayed: its kernel
+        // arguments depend only on the wave's buffers and k.
+        auto arnoldi_steps = [&](int k0) {
+            const int k1 = std::min(m, k0 + kStepsPerCheck);
+            for (int k = k0; k < k1; ++k) {
+                double *vk = W.V + 2 * (size_t)k * bd.Ntot;
+                bprecond(bd, W.cyc, vk, W.z, st);
+                bgemv(bd, kin, W.cyc, W.z, W.w, st);
+                bmdot(bd, W.cyc, k + 1, W.V, W.w, W.h1, ldh, st);
+                bcombine(bd, W.cyc, k + 1, nullptr, W.V, W.h1, ldh, -1.0, W.w, st);
+                bmdot(bd, W.cyc, k + 1, W.V, W.w, W.h2, ldh, st);
+                bcombine(bd, W.cyc, k + 1, nullptr, W.V, W.h2, ldh, -1.0, W.w, st);
+                bmdot(bd, W.cyc, 1, W.w, W.w, W.nrm, 1, st);
+                bgivens(bd, m, k, W.cyc, W.h1, W.h2, ldh, W.nrm, W.tolv, st);
+                if (k + 1 < m)
+                    bnormalize(bd, W.cyc, W.nrm, 1, W.w, W.V + 2 * (size_t)(k + 1) * bd.Ntot, st);
+            }
+            bcount(bd, W.cyc, W.cnt, st);
+        };
+        // graph cache key: everything the captured kernel arguments depend on
+        std::vector<int64_t> gkey = {(int64_t)(wi & 1), (int64_t)(intptr_t)slot_base[wi & 1], B, bd.Ntot, m, kin,
+                                     bd.n_items128, bd.n_items64, bd.n_chunks};
+        for (int j = 0; j < B; ++j) {
+            gkey.push_back(W.hs[j].N);
+            gkey.push_back(W.hs[j].S);
+        }
+        if (ar.graphs.size() >= 64 && !ar.graphs.count(gkey))
+            ar.drop_graphs();  // bound the cache; layouts rarely repeat beyond a few
+        std::vector<hipGraphExec_t> &graphs = ar.graphs[gkey];
+        if (graphs.empty())
+            graphs.assign((m + kStepsPerCheck - 1) / kStepsPerCheck, nullptr);
         std::vector<int> act(B, 1), iters(B, 0), outer(B, 0), kd(B);
         up(W.active, act, st);
         bmdot(bd, W.active, 1, W.b, W.b, W.nrm, 1, st);
@@ -364,26 +412,36 @@ int solve_batched(int n_prob, Problem *const *probs, const int32_t *n_s, const d
             up(W.active, act, st);
             bcycle_init(bd, m, W.active, W.nrm, W.tolv, W.cyc, st);
             bnormalize(bd, W.active, W.nrm, 1, W.r, W.V, st);
-            for (int k = 0; k < m; ++k) {
-                double *vk = W.V + 2 * (size_t)k * bd.Ntot;
-                bprecond(bd, W.cyc, vk, W.z, st);
-                bgemv(bd, kin, W.cyc, W.z, W.w, st);
-                bmdot(bd, W.cyc, k + 1, W.V, W.w, W.h1, ldh, st);
-                bcombine(bd, W.cyc, k + 1, nullptr, W.V, W.h1, ldh, -1.0, W.w, st);
-                bmdot(bd, W.cyc, k + 1, W.V, W.w, W.h2, ldh, st);
-                bcombine(bd, W.cyc, k + 1, nullptr, W.V, W.h2, ldh, -1.0, W.w, st);
-                bmdot(bd, W.cyc, 1, W.w, W.w, W.nrm, 1, st);
-                bgivens(bd, m, k, W.cyc, W.h1, W.h2, ldh, W.nrm, W.tolv, st);
-                if (k + 1 < m)
-                    bnormalize(bd, W.cyc, W.nrm, 1, W.w, W.V + 2 * (size_t)(k + 1) * bd.Ntot, st);
-                if ((k % 4) == 3) {
-                    int cnum = 0;
-                    bcount(bd, W.cyc, W.cnt, st);
-                    AFS_HIP(hipMemcpyAsync(&cnum, W.cnt, 4, hipMemcpyDeviceToHost, st));
-                    AFS_HIP(hipStreamSynchronize(st));
-                    if (cnum == 0)
-                        break;
+            for (int k0 = 0; k0 < m; k0 += kStepsPerCheck) {
+                const int blk = k0 / kStepsPerCheck;
+                if (use_graphs) {
+                    if (!graphs[blk]) {
+                        hipGraph_t g = nullptr;
+                        AFS_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+                        try {
+                            arnoldi_steps(k0);
+                        } catch (...) {
+                            (void)hipStreamEndCapture(st, &g);
+                            if (g)
+                                (void)hipGraphDestroy(g);
+                            throw;
+                        }
+                        AFS_HIP(hipStreamEndCapture(st, &g));
+                        hipGraphExec_t ex = nullptr;
+                        const hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+                        (void)hipGraphDestroy(g);
+                        AFS_HIP(e);
+                        graphs[blk] = ex;
+                    }
+                    AFS_HIP(hipGraphLaunch(graphs[blk], st));
+                } else {
+                    arnoldi_steps(k0);
                 }
+                int cnum = 0;
+                AFS_HIP(hipMemcpyAsync(&cnum, W.cnt, 4, hipMemcpyDeviceToHost, st));
+                AFS_HIP(hipStreamSynchronize(st));
+                if (cnum == 0)
+                    break;
             }
             // x += M^-1 V y
             bbacksolve(bd, m, W.active, W.yv, ldh, st);

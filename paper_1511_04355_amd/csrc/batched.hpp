@@ -1,5 +1,8 @@
 // Batched (lockstep) solve of many systems: layout and kernel launchers.
 #pragma once
+#include <map>
+#include <vector>
+
 #include "internal.hpp"
 
 namespace afsbem {
@@ -34,8 +37,13 @@ struct BatchArena {
     size_t cap = 0;
     hipStream_t st_asm[4] = {nullptr, nullptr, nullptr, nullptr};
     hipStream_t st_sol = nullptr;
+    // Instantiated graphs of Arnoldi-step blocks, kept while the arena is not
+    // reallocated: a later wave with the same layout in the same slot has
+    // identical kernel arguments and replays them.
+    std::map<std::vector<int64_t>, std::vector<hipGraphExec_t>> graphs;
     ~BatchArena();
     void reserve(size_t bytes);
+    void drop_graphs();
 };
 
 // kind 0: C128 FP64; 1: split hi plane FP32; 2: split hi+lo FP64

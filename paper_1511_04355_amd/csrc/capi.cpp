@@ -394,6 +394,7 @@ int afsbem_solve_opts_default(afsbem_solve_opts *o) {
     o->learn_steps = 0;
     o->precond = 0;
     o->matrix_free = 0;
+    o->no_graph = 0;
     return AFSBEM_OK;
 }
 
@@ -438,6 +439,8 @@ int afsbem_solve_device(afsbem_problem *p, int32_t n_s, const double *s, const v
                 else if ((o.warm_start == AFSBEM_WARM_PREV || o.warm_start == AFSBEM_WARM_LEARNED) && k > 0 &&
                          d_a_out)
                     x0 = static_cast<const double *>(d_a_out) + 2 * (size_t)(k - 1) * N;
+                else if ((o.warm_start == AFSBEM_WARM_PREV || o.warm_start == AFSBEM_WARM_LEARNED) && k == 0)
+                    x0 = static_cast<const double *>(d_x0);  // the caller's previous solution (nullable)
                 double *a = d_a_out ? static_cast<double *>(d_a_out) + 2 * (size_t)k * N : nullptr;
                 double *u = d_u_out ? static_cast<double *>(d_u_out) + 2 * (size_t)k * N : nullptr;
                 double *t = d_t_out ? static_cast<double *>(d_t_out) + 2 * (size_t)k * N : nullptr;

@@ -647,6 +647,8 @@ int solve_pipelined(Problem &p, const afsbem_solve_opts &o, int32_t n_s, const d
                 x0 = x0_user + 2 * (size_t)k * N;
             else if ((o.warm_start == AFSBEM_WARM_PREV || o.warm_start == AFSBEM_WARM_LEARNED) && k > 0 && a_out)
                 x0 = a_out + 2 * (size_t)(k - 1) * N;
+            else if ((o.warm_start == AFSBEM_WARM_PREV || o.warm_start == AFSBEM_WARM_LEARNED) && k == 0)
+                x0 = x0_user;  // the caller's previous solution (nullable)
             afsbem_solve_opts ok = o;
             if (!x0 && ok.warm_start != AFSBEM_WARM_LEARNED)
                 ok.warm_start = AFSBEM_WARM_NONE;

@@ -111,3 +111,26 @@ def test_batched_rejects_warm_start_and_cluster_precond():
     for o in (afs.SolveOptions(warm_start=afs.WARM_PREV), afs.SolveOptions(precond=1)):
         with pytest.raises(afs.AfsbemError):
             afs.solve_batched([P], [s], [bc], o)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_batched_graph_replay_matches_eager(prec):
+    """The captured 4-step graphs are replayed many times per call (every
+    cycle of every outer step, with eager kernels, copies and host waits in
+    between); the results must equal the eagerly launched solve exactly
+    (same kernels, fixed-order reductions), on two calls in a row."""
+    import paper_1511_04355_amd as afs
+    meshes = [mg.cavity(1), mg.rod(2.0, 1.0, 3, 6), mg.cavity(2)]
+    s_lists = [mg.cavity_frequencies(4), np.array([0.5 + 0.3j, 0.3 + 1.2j]), mg.cavity_frequencies(3)]
+    bcs = [torch.from_numpy(_bcs(m, s)).cuda() for m, s in zip(meshes, s_lists)]
+    probs = [afs.Problem.from_mesh(m) for m in meshes]
+    kw = dict(tol=1e-9 if prec == "fp64" else 1e-7, precision=afs.PREC_FP64 if prec == "fp64" else afs.PREC_MIXED,
+              restart=10)
+    eager, rc = afs.solve_batched(probs, s_lists, bcs, afs.SolveOptions(no_graph=1, **kw))
+    assert rc == 0
+    for rep in range(2):
+        outs, rc = afs.solve_batched(probs, s_lists, bcs, afs.SolveOptions(**kw))
+        assert rc == 0
+        for o, e in zip(outs, eager):
+            assert torch.equal(o["a"], e["a"]), f"replay {rep}"
+            assert [x["iters"] for x in o["stats"]] == [x["iters"] for x in e["stats"]]
