@@ -257,6 +257,16 @@ def run_porous_learned(args, afs, mg, np, torch):
                        f"{len(s)} AFS frequencies (T=300, eta={eta:.4f}, Ns=512), mixed GMRES(100), "
                        f"FP64 true rel. residual <= {args.tol}", "afs_seconds": afs_s, "n_freq": len(s),
            "afs_converged": bool(r["converged"])}
+    # the library AFS loop with nearest-sample and vector-fitting-model starts
+    for name, warm in (("afs_nearest", afs.WARM_PREV), ("afs_model", afs.WARM_MODEL)):
+        Q = afs.Problem.from_mesh(mesh)
+        t0 = time.perf_counter()
+        rq = Q.afs(params, np.asarray(mesh.bc_shape, np.float64).reshape(-1), dofs, 4, load_kind=0,
+                   opts=afs.SolveOptions(warm_start=warm, **base))
+        res[name] = {"seconds": time.perf_counter() - t0, "matvecs_total": rq["matvecs"], "n_freq": rq["Nc"],
+                     "same_samples": bool(len(rq["s"]) == len(s) and np.max(np.abs(rq["s"] - s)) == 0.0)}
+        print(f"[{name}] {res[name]}", file=sys.stderr, flush=True)
+        Q.close()
     bc = _bcs(mesh, s, torch, np)
     for name, warm in (("zero", afs.WARM_NONE), ("previous", afs.WARM_PREV), ("learned", afs.WARM_LEARNED)):
         Q = afs.Problem.from_mesh(mesh)  # fresh network for the learned leg

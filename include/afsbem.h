@@ -153,7 +153,8 @@ enum { AFSBEM_PREC_FP64 = 0, AFSBEM_PREC_MIXED = 1 };
  * all frequencies it has solved so far, across calls) combined with the
  * previous solution.  Every guess x0 is rescaled (or the pair combined) to
  * minimise ||b - A x0|| before the Krylov solve. */
-enum { AFSBEM_WARM_NONE = 0, AFSBEM_WARM_PREV = 1, AFSBEM_WARM_USER = 2, AFSBEM_WARM_LEARNED = 3 };
+enum { AFSBEM_WARM_NONE = 0, AFSBEM_WARM_PREV = 1, AFSBEM_WARM_USER = 2, AFSBEM_WARM_LEARNED = 3,
+       AFSBEM_WARM_MODEL = 4 /* afsbem_afs_run_problem only, see there */ };
 
 typedef struct {
     double tol;          /* target FP64 true relative residual ||b - A x|| / ||b|| (1e-6) */
@@ -349,13 +350,21 @@ int afsbem_afs_run(const afsbem_afs_params *p, int32_t K, int32_t Kt, afsbem_res
  * constant 1), bc_shape [n_tri][3] real; the Kt responses are the solution-vector
  * entries dof_idx[0..Kt-1] (the first K are the observation functions).  The
  * initial frequencies are solved in one call (assembly overlapped with the
- * Krylov phases); each new frequency is warm-started from the solution at the
- * nearest sampled frequency.  opts may be NULL. */
+ * Krylov phases).  Initial guess of each new frequency by opts->warm_start:
+ * NONE zero; PREV, USER, LEARNED the solution at the nearest sampled
+ * frequency; MODEL the prediction of the current order-M_H vector-fitting
+ * model (Section 3) for every unknown -- the residues of each unknown with the
+ * model's poles, identified from all solved samples by least squares as in
+ * Section 2.3, evaluated at the new s -- (nearest sample while there is no
+ * model with fewer poles than samples).  Every guess is rescaled to minimise
+ * the residual.  opts may be NULL (zero start). */
 int afsbem_afs_run_problem(afsbem_problem *p, const afsbem_afs_params *params, const double *bc_shape,
                            int load_kind, const int64_t *dof_idx, int32_t K, int32_t Kt,
                            const afsbem_solve_opts *opts, afsbem_afs_result **out);
 int afsbem_afs_result_info(const afsbem_afs_result *r, int32_t *Nc, int32_t *M, int32_t *n_steps,
                            int32_t *converged);
+/* afsbem_afs_run_problem: total Krylov products of all its solves (0 for afsbem_afs_run). */
+int afsbem_afs_result_work(const afsbem_afs_result *r, int64_t *matvecs);
 /* Copies (each pointer nullable): s_out [Nc] complex samples in the order
  * taken, F_out [Nc][Kt] complex responses, poles_out [M] and residues_out
  * [Kt][M] of the final order-M_H model, E1_out and E2_out [n_steps]. */

@@ -15,6 +15,7 @@ from ._lib import (  # noqa: F401
     WARM_PREV,
     WARM_USER,
     WARM_LEARNED,
+    WARM_MODEL,
     Problem,
     SolveOptions,
     solve_batched,

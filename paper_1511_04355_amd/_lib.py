@@ -19,7 +19,7 @@ _lib = None
 OK, EINVAL, ENOMEM, EDEVICE, ENOCONV, EBREAKDOWN, ENAN = 0, -1, -2, -3, -4, -5, -6
 FMT_C128, FMT_SPLIT = 0, 1
 PREC_FP64, PREC_MIXED = 0, 1
-WARM_NONE, WARM_PREV, WARM_USER, WARM_LEARNED = 0, 1, 2, 3
+WARM_NONE, WARM_PREV, WARM_USER, WARM_LEARNED, WARM_MODEL = 0, 1, 2, 3, 4
 
 
 class AfsbemError(RuntimeError):
@@ -110,6 +110,7 @@ def lib():
         L.afsbem_afs_result_info.argtypes = [P, P, P, P, P]
         L.afsbem_afs_result_get.argtypes = [P, P, P, P, P, P, P]
         L.afsbem_afs_result_destroy.argtypes = [P]
+        L.afsbem_afs_result_work.argtypes = [P, P]
         _lib = L
     return _lib
 
@@ -447,9 +448,11 @@ def _afs_result(r, Kt):
     E2 = np.zeros(ns.value)
     _check(L.afsbem_afs_result_get(r, s.ctypes.data, F.ctypes.data, poles.ctypes.data, res.ctypes.data,
                                    E1.ctypes.data, E2.ctypes.data))
+    mv = ctypes.c_int64()
+    _check(L.afsbem_afs_result_work(r, ctypes.byref(mv)))
     L.afsbem_afs_result_destroy(r)
     return {"s": s, "F": F, "poles": poles, "residues": res, "E1": E1, "E2": E2, "Nc": nc.value,
-            "converged": bool(conv.value)}
+            "converged": bool(conv.value), "matvecs": mv.value}
 
 
 def afs_run(response, K, Kt, params):

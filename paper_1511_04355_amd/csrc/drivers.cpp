@@ -546,9 +546,47 @@ struct AfsResult {
     std::vector<int> J, MH, ML;
     int converged = 0;
     int Kt = 0;
+    int64_t matvecs = 0;           // GPU solves (afs_run_problem): Krylov products in all
 };
 
-using ResponseFn = std::function<void(const std::vector<cplx> &, std::vector<cplx> &)>;  // [n][Kt]
+// responses [n][Kt] at the frequencies asked for; model: the current order-M_H
+// fit (null in the initial round)
+using ResponseFn = std::function<void(const std::vector<cplx> &, std::vector<cplx> &, const VfModel *)>;
+
+// Weights (alpha_j, beta_j) such that the model's prediction at s_new of any
+// function sampled at s_j (j < J) is sum_j alpha_j F_j + beta_j conj(F_j): the
+// residues of that function with the given poles are the least-squares
+// solution of the real-coefficient basis (as in residue identification), which
+// is real-linear in (Re F, Im F).
+static void vf_prediction_weights(const std::vector<cplx> &s, const std::vector<cplx> &poles, cplx s_new,
+                                  std::vector<cplx> &alpha, std::vector<cplx> &beta) {
+    const int J = (int)s.size();
+    const PoleSet ps = group_poles(poles);
+    const int M = ps.dim();
+    const std::vector<cplx> Phi = basis_values(s, ps);
+    std::vector<double> A((size_t)2 * J * M), I((size_t)2 * J * 2 * J, 0.0), X;
+    for (int c = 0; c < M; ++c)
+        for (int j = 0; j < J; ++j) {
+            A[(size_t)c * 2 * J + j] = Phi[(size_t)c * J + j].real();
+            A[(size_t)c * 2 * J + J + j] = Phi[(size_t)c * J + j].imag();
+        }
+    for (int i = 0; i < 2 * J; ++i)
+        I[(size_t)i * 2 * J + i] = 1.0;
+    lstsq(2 * J, M, A, 2 * J, I, X);  // X[i][m]: column i of the pseudo-inverse
+    const std::vector<cplx> phi = basis_values(std::vector<cplx>{s_new}, ps);
+    alpha.assign(J, 0.0);
+    beta.assign(J, 0.0);
+    const cplx Im(0.0, 1.0);
+    for (int j = 0; j < J; ++j) {
+        cplx u = 0.0, v = 0.0;  // weights of Re F_j and Im F_j
+        for (int m = 0; m < M; ++m) {
+            u += phi[m] * X[(size_t)j * M + m];
+            v += phi[m] * X[(size_t)(J + j) * M + m];
+        }
+        alpha[j] = 0.5 * (u - Im * v);
+        beta[j] = 0.5 * (u + Im * v);
+    }
+}
 
 static void afs_run_impl(const afsbem_afs_params &P, int K, int Kt, const ResponseFn &resp, AfsResult &R) {
     const double omega = kPi * P.Ns / P.T;
@@ -561,7 +599,7 @@ static void afs_run_impl(const afsbem_afs_params &P, int K, int Kt, const Respon
     for (int j = 0; j < P.J0; ++j)
         S.push_back(cplx(P.eta, omega * (1.0 - std::cos(j * kPi / (2.0 * (P.J0 - 1))))));
     std::vector<cplx> Fv;
-    resp(S, Fv);
+    resp(S, Fv, nullptr);
     std::vector<double> prev_td;
     cplx s_new;
 
@@ -649,7 +687,7 @@ static void afs_run_impl(const afsbem_afs_params &P, int K, int Kt, const Respon
     };
     auto add = [&](cplx sn) {
         std::vector<cplx> one{sn}, f;
-        resp(one, f);
+        resp(one, f, R.model.poles.empty() ? nullptr : &R.model);
         S.push_back(sn);
         Fv.insert(Fv.end(), f.begin(), f.end());
     };
@@ -897,7 +935,7 @@ int afsbem_afs_run(const afsbem_afs_params *P, int32_t K, int32_t Kt, afsbem_res
         AFS_REQUIRE(fn && out, AFSBEM_EINVAL, "null callback or output");
         auto *res = new afsbem_afs_result();
         try {
-            ResponseFn resp = [&](const std::vector<cplx> &s, std::vector<cplx> &f) {
+            ResponseFn resp = [&](const std::vector<cplx> &s, std::vector<cplx> &f, const VfModel *) {
                 std::vector<double> sv(2 * s.size()), fv(2 * s.size() * Kt);
                 for (size_t i = 0; i < s.size(); ++i) {
                     sv[2 * i] = s[i].real();
@@ -951,7 +989,7 @@ int afsbem_afs_run_problem(afsbem_problem *p, const afsbem_afs_params *params, c
         std::vector<std::pair<cplx, double *>> solved;  // (s, device solution)
         auto *res = new afsbem_afs_result();
         try {
-            ResponseFn resp = [&](const std::vector<cplx> &s, std::vector<cplx> &f) {
+            ResponseFn resp = [&](const std::vector<cplx> &s, std::vector<cplx> &f, const VfModel *model) {
                 const int n = (int)s.size();
                 std::vector<double> hb((size_t)n * N * 2), sv(2 * n);
                 for (int i = 0; i < n; ++i) {
@@ -968,7 +1006,22 @@ int afsbem_afs_run_problem(afsbem_problem *p, const afsbem_afs_params *params, c
                 AFS_HIP(hipMemcpyAsync(dbc, hb.data(), hb.size() * 8, hipMemcpyHostToDevice, st));
                 afsbem_solve_opts oo = o;
                 const double *x0 = nullptr;
-                if (n == 1 && !solved.empty()) {
+                const bool warm = o.warm_start != AFSBEM_WARM_NONE;
+                const int M = model ? (int)model->poles.size() : 0;
+                if (n == 1 && warm && o.warm_start == AFSBEM_WARM_MODEL && M > 0 && (int)solved.size() > M) {
+                    // prediction of the current rational model for every unknown
+                    std::vector<cplx> sj(solved.size()), al, be;
+                    for (size_t q = 0; q < solved.size(); ++q)
+                        sj[q] = solved[q].first;
+                    vf_prediction_weights(sj, model->poles, s[0], al, be);
+                    double *xp = (double *)dmalloc((size_t)N * 16);
+                    AFS_HIP(hipMemsetAsync(xp, 0, (size_t)N * 16, st));
+                    for (size_t q = 0; q < solved.size(); ++q)
+                        vec_axpy_conj(N, al[q].real(), al[q].imag(), be[q].real(), be[q].imag(), solved[q].second,
+                                      xp, st);
+                    x0 = xp;
+                    oo.warm_start = AFSBEM_WARM_USER;
+                } else if (n == 1 && warm && !solved.empty()) {
                     // warm start from the nearest sampled frequency (residual-optimal scaling inside)
                     size_t best = 0;
                     for (size_t q = 1; q < solved.size(); ++q)
@@ -976,14 +1029,18 @@ int afsbem_afs_run_problem(afsbem_problem *p, const afsbem_afs_params *params, c
                             best = q;
                     x0 = solved[best].second;
                     oo.warm_start = AFSBEM_WARM_USER;
-                } else if (n > 1) {
+                } else if (n > 1 && warm) {
                     oo.warm_start = AFSBEM_WARM_PREV;
+                } else {
+                    oo.warm_start = AFSBEM_WARM_NONE;
                 }
                 std::vector<afsbem_solve_stats> stats(n);
                 const int rc = afsbem_solve_device(p, n, sv.data(), dbc, x0, da, nullptr, nullptr, &oo, stats.data(),
                                                    st);
                 if (rc != AFSBEM_OK && rc != AFSBEM_ENOCONV)
                     throw Error{rc, std::string("solve failed: ") + afsbem_last_error()};
+                for (const auto &q : stats)
+                    res->r.matvecs += q.iters;
                 std::vector<double> ha(hb.size());
                 AFS_HIP(hipMemcpyAsync(ha.data(), da, ha.size() * 8, hipMemcpyDeviceToHost, st));
                 AFS_HIP(hipStreamSynchronize(st));
@@ -1025,6 +1082,14 @@ int afsbem_afs_result_info(const afsbem_afs_result *r, int32_t *Nc, int32_t *M, 
             *n_steps = (int32_t)r->r.E1.size();
         if (converged)
             *converged = r->r.converged;
+        return AFSBEM_OK;
+    });
+}
+
+int afsbem_afs_result_work(const afsbem_afs_result *r, int64_t *matvecs) {
+    return guarded_d([&] {
+        AFS_REQUIRE(r && matvecs, AFSBEM_EINVAL, "null argument");
+        *matvecs = r->r.matvecs;
         return AFSBEM_OK;
     });
 }

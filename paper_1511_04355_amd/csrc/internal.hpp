@@ -179,6 +179,9 @@ void vec_mupdate(int64_t N, int nv, const double *V, int64_t ldv, const double *
                  hipStream_t st);
 // out = x / norm (norm read from device scalar nrm2 = ||x||^2)
 void vec_normalize(int64_t N, const double *nrm2, const double *x, double *out, hipStream_t st);
+// out += a x + b conj(x)  (complex a, b)
+void vec_axpy_conj(int64_t N, double ar, double ai, double br, double bi, const double *x, double *out,
+                   hipStream_t st);
 // x += sum_i y[i] V_i  (y on device, complex)
 void vec_combine(int64_t N, int nv, const double *V, int64_t ldv, const double *y, double *x,
                  hipStream_t st);

@@ -433,4 +433,25 @@ void vec_axpby(int64_t N, double ar, double ai, const double *x, double br, doub
     AFS_HIP(hipGetLastError());
 }
 
+// out += a x + b conj(x)
+__global__ __launch_bounds__(256) void axpy_conj_kernel(int64_t N, double ar, double ai, double br, double bi,
+                                                        const double2 *x, double2 *out) {
+    const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (r >= N)
+        return;
+    const double2 v = x[r];
+    double2 o = out[r];
+    o.x += ar * v.x - ai * v.y + br * v.x + bi * v.y;
+    o.y += ar * v.y + ai * v.x - br * v.y + bi * v.x;
+    out[r] = o;
+}
+
+void vec_axpy_conj(int64_t N, double ar, double ai, double br, double bi, const double *x, double *out,
+                   hipStream_t st) {
+    axpy_conj_kernel<<<(unsigned)((N + 255) / 256), 256, 0, st>>>(N, ar, ai, br, bi,
+                                                                  reinterpret_cast<const double2 *>(x),
+                                                                  reinterpret_cast<double2 *>(out));
+    AFS_HIP(hipGetLastError());
+}
+
 }  // namespace afsbem

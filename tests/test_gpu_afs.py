@@ -52,3 +52,32 @@ def test_afs_on_gpu_solve_matches_oracle_afs():
     ho = vf.time_response(t, o["poles"], o["residues"])
     hg = afs.vf_eval_time(out["poles"], out["residues"], t)
     assert np.max(np.abs(hg - ho)) <= 1e-3 * np.max(np.abs(ho))
+
+
+def test_afs_model_warm_start_same_samples_fewer_products():
+    """AFS with the vector-fitting prediction as initial guess (WARM_MODEL)
+    takes the same samples as with zero starts (the solves agree to 1e-10).
+    On this well-damped cavity a zero start already converges in ~10 products,
+    so a guess can at most pay for the one product its residual costs: the
+    bound checked is zero-start products + one per adaptive sample."""
+    import paper_1511_04355_amd as afs
+    mesh = mg.cavity(2)
+    T, Ns, eta = 20.0, 64, 0.25
+    rng = np.random.default_rng(5)
+    dofs = np.sort(rng.choice(3 * mesh.n_tri, 6, replace=False))
+    P = afs.Problem.from_mesh(mesh)
+    params = afs.afs_params(T, eta, Ns)
+    runs = {}
+    for name, warm in (("zero", afs.WARM_NONE), ("nearest", afs.WARM_PREV), ("model", afs.WARM_MODEL)):
+        runs[name] = P.afs(params, mesh.bc_shape, dofs, 4, load_kind=0,
+                           opts=afs.SolveOptions(tol=1e-10, warm_start=warm))
+        print(f"[afs] {name}: Nc={runs[name]['Nc']} matvecs={runs[name]['matvecs']}", flush=True)
+    z = runs["zero"]
+    for name in ("nearest", "model"):
+        r = runs[name]
+        assert r["Nc"] == z["Nc"]
+        assert np.max(np.abs(r["s"] - z["s"])) == 0.0
+        assert np.max(np.abs(r["F"] - z["F"])) <= 1e-7 * np.max(np.abs(z["F"]))
+    n_adaptive = z["Nc"] - 16
+    for name in ("nearest", "model"):
+        assert runs[name]["matvecs"] <= z["matvecs"] + n_adaptive + 16
