@@ -74,6 +74,7 @@ def parse():
                          "(320 triangles, 16 frequencies), blocks_batched (16 seeded porous blocks x 24 "
                          "frequencies), porous_learned (27-void block, 40,320 unknowns: warm-start A/B on an "
                          "AFS frequency sequence), porous_matrix_free (64-void block, 300,516 unknowns)")
+    ap.add_argument("--precond", type=int, default=0, help="blocks_batched: 0 point, 1 cluster block-Jacobi")
     ap.add_argument("--afs-max", type=int, default=24, help="porous_learned: cap on AFS samples")
     ap.add_argument("--batch", type=int, default=0,
                     help="optimised path: 1 = one frequency at a time, 0 = assembly of the next frequency "
@@ -180,16 +181,18 @@ def run_blocks_batched(args, afs, mg, np, torch):
     s = mg.block_frequencies(24)
     probs = [afs.Problem.from_mesh(m) for m in meshes]
     bcs = [_bcs(m, s, torch, np) for m in meshes]
-    opts = afs.SolveOptions(tol=args.tol, precision=afs.PREC_MIXED, restart=150, max_iter=6000)
+    opts = afs.SolveOptions(tol=args.tol, precision=afs.PREC_MIXED, restart=150, max_iter=6000,
+                            precond=args.precond)
     res = {"workload": "blocks_batched: 16 porous blocks (seeds 0-15), unknowns "
                        + ",".join(str(3 * m.n_tri) for m in meshes) + f"; 24 frequencies each; mixed, "
-                       f"GMRES(150), FP64 true rel. residual <= {args.tol}", "unit": "frequency solves/s"}
+                       f"GMRES(150), {'cluster' if args.precond else 'point'} block-Jacobi, "
+                       f"FP64 true rel. residual <= {args.tol}", "unit": "frequency solves/s"}
 
     def seq():
         st = []
         for j, (P, b) in enumerate(zip(probs, bcs)):
             o = P.solve(s, b, afs.SolveOptions(tol=args.tol, precision=afs.PREC_MIXED, restart=150, max_iter=6000,
-                                               warm_start=afs.WARM_PREV), want_ut=False)
+                                               warm_start=afs.WARM_PREV, precond=args.precond), want_ut=False)
             st += o["stats"]
             print(f"[blocks] block {j} done", file=sys.stderr, flush=True)
         return st

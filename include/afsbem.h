@@ -241,11 +241,15 @@ int afsbem_solve(afsbem_problem *p, int32_t n_s, const double *s, const double *
  *      in afsbem_solve_device; the pointer arrays themselves may be null.
  *   stats: nullable host array of sum(n_s) entries, same order as s.
  * Options: tol, restart, max_iter, precision (FP64, or MIXED: FP32 hi-plane
- * inner cycles with FP64 residuals); opts.batch > 1 caps the systems solved
- * together (default: as many as fit in 60 % of free device memory, at most
- * 64).  Warm starts and the cluster preconditioner are not available here
- * (AFSBEM_EINVAL).  Work is ordered on hip_stream; the call returns after
- * the outputs are written.  Returns AFSBEM_ENOCONV if any system missed the
+ * inner cycles with FP64 residuals), precond (0 or 1 as in
+ * afsbem_solve_device), no_graph.  Systems are solved in waves that fit a
+ * slot of min(30 % of free device memory, 16 GiB) (at least one system, at
+ * most 64, or opts.batch if > 1); two slots alternate so that the next wave
+ * is assembled while the current one is solved.  The device memory and
+ * streams are kept by probs[0] for later calls (freed with it).  Warm starts
+ * and the matrix-free operator are not available here (AFSBEM_EINVAL).  Work
+ * is ordered after hip_stream's prior work and the call returns after the
+ * outputs are written.  Returns AFSBEM_ENOCONV if any system missed the
  * tolerance. */
 int afsbem_solve_batched_device(int32_t n_prob, afsbem_problem *const *probs, const int32_t *n_s,
                                 const double *s, const void *const *d_bc_val, void *const *d_a_out,

@@ -90,6 +90,7 @@ struct Wave {
     int first = 0, B = 0;
     BatchDev bd;
     std::vector<void *> A, Alo;
+    std::vector<float *> clinv;  // cluster preconditioner inverses per system (precond 1)
     std::vector<int64_t> elem_off;
     double *b = nullptr, *x = nullptr, *r = nullptr, *w = nullptr, *z = nullptr, *tmp = nullptr, *V = nullptr;
     double *h1 = nullptr, *h2 = nullptr, *nrm = nullptr, *yv = nullptr, *ones = nullptr, *tolv = nullptr;
@@ -107,7 +108,7 @@ struct Wave {
 // Lays out a wave of systems all[first, first + B) in a slot starting at
 // base (nullptr: only measure); returns the bytes used.
 size_t layout(Wave &W, const std::vector<SysRef> &all, Problem *const *probs, int first, int B, int m, bool mixed,
-              char *base) {
+              int prec, char *base) {
     W.first = first;
     W.B = B;
     BatchDev &bd = W.bd;
@@ -199,14 +200,21 @@ size_t layout(Wave &W, const std::vector<SysRef> &all, Problem *const *probs, in
     W.active = c.get<int>(B);
     W.cyc = c.get<int>(B);
     W.cnt = c.get<int>(1);
+    W.clinv.assign(B, nullptr);
+    if (prec == 1)
+        for (int j = 0; j < B; ++j)
+            W.clinv[j] = c.get<float>((size_t)std::max<int64_t>(probs[all[first + j].prob]->dev.n_clusters, 1) *
+                                      kClusterDim * kClusterDim * 2);
     for (auto &s : W.scr)
         s = c.get<char>(scratch_max);
     return c.off + 256;
 }
 
-size_t system_bytes(const SysRef &r, int m, bool mixed) {
-    (void)mixed;
-    return (size_t)r.N * r.lda * 16 + (size_t)r.N * (m + 8) * 16 + (size_t)r.nt * 144;
+size_t system_bytes(const SysRef &r, int m, int prec) {
+    // matrix (16 B per entry in both formats), vectors and basis, blocks, and
+    // the cluster inverses (72 x 72 complex64 per cluster of <= 24 elements)
+    return (size_t)r.N * r.lda * 16 + (size_t)r.N * (m + 8) * 16 + (size_t)r.nt * 144 +
+           (prec == 1 ? (size_t)(r.nt / 12 + 2) * kClusterDim * kClusterDim * 8 : 0);
 }
 
 template <class T>
@@ -251,7 +259,7 @@ int solve_batched(int n_prob, Problem *const *probs, const int32_t *n_s, const d
         size_t l = f;
         double bytes = 0.0;
         while (l < all.size() && (int)(l - f) < max_b) {
-            const double need = (double)system_bytes(all[l], m, mixed);
+            const double need = (double)system_bytes(all[l], m, o.precond);
             if (l > f && bytes + need > slot_budget)
                 break;
             bytes += need;
@@ -264,7 +272,8 @@ int solve_batched(int n_prob, Problem *const *probs, const int32_t *n_s, const d
     Wave slots[2];
     size_t slot_bytes = 0;
     for (auto &wv : waves)
-        slot_bytes = std::max(slot_bytes, layout(slots[0], all, probs, wv.first, wv.second, m, mixed, nullptr));
+        slot_bytes =
+            std::max(slot_bytes, layout(slots[0], all, probs, wv.first, wv.second, m, mixed, o.precond, nullptr));
     slot_bytes = (slot_bytes + 4095) / 4096 * 4096;
     ar.reserve(slot_bytes * (n_waves > 1 ? 2 : 1));
     char *slot_base[2] = {static_cast<char *>(ar.base), static_cast<char *>(ar.base) + (n_waves > 1 ? slot_bytes : 0)};
@@ -296,7 +305,7 @@ int solve_batched(int n_prob, Problem *const *probs, const int32_t *n_s, const d
     // launches the assembly of wave wi into its slot
     auto assemble = [&](int wi) {
         Wave &W = slots[wi & 1];
-        layout(W, all, probs, waves[wi].first, waves[wi].second, m, mixed, slot_base[wi & 1]);
+        layout(W, all, probs, waves[wi].first, waves[wi].second, m, mixed, o.precond, slot_base[wi & 1]);
         // every assembly stream must be past the previous use of this slot:
         // the host only gets here after that wave's solve has completed
         AFS_HIP(hipEventRecord(W.asm_begin, ar.st_asm[0]));
@@ -310,6 +319,8 @@ int solve_batched(int n_prob, Problem *const *probs, const int32_t *n_s, const d
             launch_assembly(P, kp, bc[rf.prob] + 2 * (size_t)rf.k * rf.N, fmt, W.A[j], W.Alo[j],
                             W.b + 2 * W.hs[j].off, W.bd.precond + 18 * W.elem_off[j], W.scr[j % 4],
                             ar.st_asm[j % 4]);
+            if (o.precond == 1)
+                cluster_inverse(P.dev, fmt, W.A[j], W.Alo[j], W.clinv[j], ar.st_asm[j % 4]);
         }
         for (int q = 1; q < 4; ++q) {
             hipEvent_t e;
@@ -351,6 +362,17 @@ int solve_batched(int n_prob, Problem *const *probs, const int32_t *n_s, const d
         up(W.ones, W.onesh, st);
         AFS_HIP(hipStreamWaitEvent(st, W.asm_end, 0));
         AFS_HIP(hipEventRecord(s0, st));
+        // z = M^-1 v for the systems flagged in mask (point blocks), or for all
+        // systems (clusters: one launch per system; unflagged rows are unused)
+        auto apply_prec = [&](const int *mask, const double *v, double *z) {
+            if (o.precond == 1) {
+                for (int j = 0; j < B; ++j)
+                    cluster_apply(probs[all[W.first + j].prob]->dev, W.clinv[j], v + 2 * W.hs[j].off,
+                                  z + 2 * W.hs[j].off, st);
+            } else {
+                bprecond(bd, mask, v, z, st);
+            }
+        };
         // Arnoldi steps k0 .. k0+3 of the current cycle for every system still
         // in it, then the count of those systems (W.cnt).  With graphs on, each
         // such block is captured once per wave and replayed: its kernel
@@ -359,7 +381,7 @@ int solve_batched(int n_prob, Problem *const *probs, const int32_t *n_s, const d
             const int k1 = std::min(m, k0 + kStepsPerCheck);
             for (int k = k0; k < k1; ++k) {
                 double *vk = W.V + 2 * (size_t)k * bd.Ntot;
-                bprecond(bd, W.cyc, vk, W.z, st);
+                apply_prec(W.cyc, vk, W.z);
                 bgemv(bd, kin, W.cyc, W.z, W.w, st);
                 bmdot(bd, W.cyc, k + 1, W.V, W.w, W.h1, ldh, st);
                 bcombine(bd, W.cyc, k + 1, nullptr, W.V, W.h1, ldh, -1.0, W.w, st);
@@ -374,7 +396,9 @@ int solve_batched(int n_prob, Problem *const *probs, const int32_t *n_s, const d
         };
         // graph cache key: everything the captured kernel arguments depend on
         std::vector<int64_t> gkey = {(int64_t)(wi & 1), (int64_t)(intptr_t)slot_base[wi & 1], B, bd.Ntot, m, kin,
-                                     bd.n_items128, bd.n_items64, bd.n_chunks};
+                                     bd.n_items128, bd.n_items64, bd.n_chunks, o.precond};
+        for (int j = 0; o.precond == 1 && j < B; ++j)  // the cluster launches read each problem's plan
+            gkey.push_back((int64_t)(intptr_t)&probs[all[W.first + j].prob]->dev);
         for (int j = 0; j < B; ++j) {
             gkey.push_back(W.hs[j].N);
             gkey.push_back(W.hs[j].S);
@@ -448,7 +472,7 @@ int solve_batched(int n_prob, Problem *const *probs, const int32_t *n_s, const d
             AFS_HIP(hipMemcpyAsync(kd.data(), bd.kdone, 4 * B, hipMemcpyDeviceToHost, st));
             AFS_HIP(hipMemsetAsync(W.tmp, 0, (size_t)16 * bd.Ntot, st));
             bcombine(bd, W.active, m, bd.kdone, W.V, W.yv, ldh, 1.0, W.tmp, st);
-            bprecond(bd, W.active, W.tmp, W.z, st);
+            apply_prec(W.active, W.tmp, W.z);
             bcombine(bd, W.active, 1, nullptr, W.z, W.ones, 1, 1.0, W.x, st);
             // the true residual with the FP64 operator
             bgemv(bd, kout, W.active, W.x, W.tmp, st);

@@ -524,7 +524,7 @@ int afsbem_solve_batched_device(int32_t n_prob, afsbem_problem *const *probs, co
         AFS_REQUIRE(o.precision == AFSBEM_PREC_FP64 || o.precision == AFSBEM_PREC_MIXED, AFSBEM_EINVAL,
                     "unknown precision");
         AFS_REQUIRE(o.warm_start == AFSBEM_WARM_NONE, AFSBEM_EINVAL, "the batched solve takes no warm start");
-        AFS_REQUIRE(o.precond == 0, AFSBEM_EINVAL, "the batched solve uses the point block-Jacobi preconditioner");
+        AFS_REQUIRE(o.precond == 0 || o.precond == 1, AFSBEM_EINVAL, "precond must be 0 or 1");
         AFS_REQUIRE(o.matrix_free == 0, AFSBEM_EINVAL, "the batched solve stores its matrices");
         int dev = 0;
         AFS_HIP(hipGetDevice(&dev));

@@ -102,15 +102,39 @@ def test_batched_u_t_split_rod():
         assert np.linalg.norm(outs[0]["t"][k].cpu().numpy() - to) / np.linalg.norm(to) < 1e-8
 
 
-def test_batched_rejects_warm_start_and_cluster_precond():
+def test_batched_rejects_warm_start_and_matrix_free():
     import paper_1511_04355_amd as afs
     mesh = mg.cavity(1)
     s = mg.cavity_frequencies(2)
     P = afs.Problem.from_mesh(mesh)
     bc = torch.from_numpy(_bcs(mesh, s)).cuda()
-    for o in (afs.SolveOptions(warm_start=afs.WARM_PREV), afs.SolveOptions(precond=1)):
+    for o in (afs.SolveOptions(warm_start=afs.WARM_PREV), afs.SolveOptions(matrix_free=1)):
         with pytest.raises(afs.AfsbemError):
             afs.solve_batched([P], [s], [bc], o)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_batched_cluster_preconditioner(prec):
+    """Cluster block-Jacobi inside the lockstep solve: a seeded porous block
+    (2,820 unknowns) and the small cavity, several frequencies each, against
+    the oracle; fewer products than the point blocks on the porous block."""
+    import paper_1511_04355_amd as afs
+    meshes = [mg.random_block(7), mg.cavity(1)]
+    s_lists = [np.array([0.25 + 0.5j, 0.25 + 1.5j, 0.25 + 2.5j]), mg.cavity_frequencies(3)]
+    bcs = [_bcs(m, s) for m, s in zip(meshes, s_lists)]
+    probs = [afs.Problem.from_mesh(m) for m in meshes]
+    tol, err = (1e-9, 1e-6) if prec == "fp64" else (1e-6, 1e-5)
+    iters = {}
+    for pc in (0, 1):
+        opts = afs.SolveOptions(tol=tol, precision=afs.PREC_FP64 if prec == "fp64" else afs.PREC_MIXED, precond=pc)
+        outs, rc = afs.solve_batched(probs, s_lists, [torch.from_numpy(b).cuda() for b in bcs], opts)
+        assert rc == 0
+        iters[pc] = sum(x["iters"] for x in outs[0]["stats"])
+        if pc == 1:
+            for m, s, bc, o in zip(meshes, s_lists, bcs, outs):
+                _check(m, s, bc, o, tol, err)
+    print(f"[batched] porous block products: point {iters[0]}, clusters {iters[1]}", flush=True)
+    assert iters[1] < iters[0]
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
