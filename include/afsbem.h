@@ -135,6 +135,16 @@ int afsbem_matvec_free_device(afsbem_problem *p, double s_re, double s_im, int p
                               const void *d_bc_val, const void *d_x, void *d_y, void *d_b,
                               void *hip_stream);
 
+/* Autotuning of launch parameters (on by default): the first product of a
+ * given size and format on a device measures the candidate column splits of
+ * the dense GEMV (1/4x to 4x of the default) on the live operands with HIP
+ * events and keeps the fastest for the rest of the process.  enabled = 0
+ * uses the defaults for sizes not yet tuned. */
+int afsbem_autotune_set(int enabled);
+/* Text table of the tuned choices and the measured times; len receives the
+ * full length, buf (nullable, cap bytes) a NUL-terminated copy. */
+int afsbem_autotune_report(char *buf, int64_t cap, int64_t *len);
+
 /* Preconditioner clusters of the plan: n_clusters, ptr_out [n_clusters+1]
  * offsets into elem_out [n_tri] (element indices grouped by cluster); the
  * arrays are nullable (query the count first). */

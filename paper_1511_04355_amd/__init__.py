@@ -19,6 +19,8 @@ from ._lib import (  # noqa: F401
     Problem,
     SolveOptions,
     solve_batched,
+    autotune_set,
+    autotune_report,
     lib,
     lib_path,
     version,

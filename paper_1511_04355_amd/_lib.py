@@ -86,6 +86,8 @@ def lib():
         L.afsbem_problem_info.argtypes = [P, P, P, P, P]
         L.afsbem_assemble_device.argtypes = [P, d, d, P, ctypes.c_int, P, P, P, P, P]
         L.afsbem_matvec_device.argtypes = [P, ctypes.c_int, ctypes.c_int, P, P, P, P, P]
+        L.afsbem_autotune_set.argtypes = [ctypes.c_int]
+        L.afsbem_autotune_report.argtypes = [P, i64, P]
         L.afsbem_matvec_free_device.argtypes = [P, d, d, ctypes.c_int, P, P, P, P, P]
         L.afsbem_solve_opts_default.argtypes = [P]
         L.afsbem_problem_clusters.argtypes = [P, P, P, P]
@@ -366,6 +368,18 @@ def solve_batched(problems, s_lists, bc_vals, opts: SolveOptions | None = None, 
         o["stats"] = [{f: getattr(stats[k + q], f) for f, _ in _Stats._fields_} for q in range(int(m))]
         k += int(m)
     return outs, rc
+
+
+def autotune_set(enabled: bool):
+    _check(lib().afsbem_autotune_set(int(bool(enabled))))
+
+
+def autotune_report() -> str:
+    n = ctypes.c_int64()
+    _check(lib().afsbem_autotune_report(None, 0, ctypes.byref(n)))
+    buf = ctypes.create_string_buffer(n.value + 1)
+    _check(lib().afsbem_autotune_report(buf, n.value + 1, ctypes.byref(n)))
+    return buf.value.decode()
 
 
 # ------------------------------------------------------------------- drivers

@@ -7,6 +7,7 @@
 #include "solver.hpp"
 #include "mlp.hpp"
 #include "batched.hpp"
+#include "tune.hpp"
 
 struct afsbem_mesh {
     std::vector<double> xyz;
@@ -291,6 +292,25 @@ int afsbem_matvec_free_device(afsbem_problem *p, double s_re, double s_im, int p
                      static_cast<double *>(d_y), part, st);
         AFS_HIP(hipFreeAsync(mem, st));
         return AFSBEM_OK;
+    });
+}
+
+int afsbem_autotune_set(int enabled) {
+    autotune_set_enabled(enabled != 0);
+    return AFSBEM_OK;
+}
+
+int afsbem_autotune_report(char *buf, int64_t cap, int64_t *len) {
+    return guarded([&] {
+        const std::string r = autotune_report();
+        if (len)
+            *len = (int64_t)r.size();
+        if (buf && cap > 0) {
+            const size_t n = std::min<size_t>((size_t)cap - 1, r.size());
+            std::memcpy(buf, r.data(), n);
+            buf[n] = 0;
+        }
+        return (int)AFSBEM_OK;
     });
 }
 

@@ -11,7 +11,11 @@
 //   SPLIT FP32: two rows per lane (16 bytes of the hi plane), FP32 FMA and
 //               FP32 accumulation within a chunk.
 //   SPLIT FP64: hi + lo planes converted to FP64 per entry, FP64 FMA.
+#include <algorithm>
+#include <vector>
+
 #include "cplx.hpp"
+#include "tune.hpp"
 #include "internal.hpp"
 
 namespace afsbem {
@@ -192,12 +196,13 @@ __global__ __launch_bounds__(256) void sum_partials_kernel(int64_t N, int S, con
     y[row] = make_double2(r, i);
 }
 
-int gemv_chunks(int64_t N) {
-    // enough workgroups to cover the chip several times over
-    const int64_t rows_per_block = 256;
-    const int64_t gx = (N + rows_per_block - 1) / rows_per_block;
+// Column split of the GEMV: the default gives about 2048 work-groups (enough
+// to cover the chip several times over, at least 32 columns per chunk); the
+// autotuner measures 1/4x .. 4x of it.
+static int gemv_chunks_default(int64_t N) {
+    const int64_t gx = (N + 255) / 256;
     int64_t S = (2048 + gx - 1) / gx;
-    const int64_t max_s = (N + 31) / 32;  // keep at least 32 columns per chunk
+    const int64_t max_s = (N + 31) / 32;
     if (S > max_s)
         S = max_s;
     if (S < 1)
@@ -205,10 +210,27 @@ int gemv_chunks(int64_t N) {
     return (int)S;
 }
 
-void launch_gemv(int64_t N, int format, int precision, const void *A, const void *A_lo, const double *x, double *y,
-                 double *partial, hipStream_t st, hipEvent_t ev_begin, hipEvent_t ev_end) {
+static std::vector<int> gemv_chunk_candidates(int64_t N) {
+    const int s0 = gemv_chunks_default(N);
+    const int64_t max_s = std::max<int64_t>(1, (N + 31) / 32);
+    std::vector<int> c;
+    for (int f : {-4, -2, 1, 2, 4}) {
+        int64_t s = f < 0 ? (s0 + (-f) - 1) / (-f) : (int64_t)s0 * f;
+        s = std::max<int64_t>(1, std::min<int64_t>(s, max_s));
+        if (std::find(c.begin(), c.end(), (int)s) == c.end())
+            c.push_back((int)s);
+    }
+    return c;
+}
+
+int gemv_chunks(int64_t N) {
+    const std::vector<int> c = gemv_chunk_candidates(N);
+    return *std::max_element(c.begin(), c.end());
+}
+
+static void gemv_enqueue(int64_t N, int format, int precision, const void *A, const void *A_lo, const double *x,
+                         double *y, double *partial, int S, hipStream_t st, hipEvent_t ev_begin, hipEvent_t ev_end) {
     const int64_t lda = (N + 63) / 64 * 64;
-    const int S = gemv_chunks(N);
     const int64_t chunk = (N + S - 1) / S;
     const int Su = (int)((N + chunk - 1) / chunk);
     double2 *part = reinterpret_cast<double2 *>(partial);
@@ -231,6 +253,18 @@ void launch_gemv(int64_t N, int format, int precision, const void *A, const void
         AFS_HIP(hipEventRecord(ev_end, st));
     sum_partials_kernel<<<(unsigned)((N + 255) / 256), 256, 0, st>>>(N, Su, part, reinterpret_cast<double2 *>(y));
     AFS_HIP(hipGetLastError());
+}
+
+void launch_gemv(int64_t N, int format, int precision, const void *A, const void *A_lo, const double *x, double *y,
+                 double *partial, hipStream_t st, hipEvent_t ev_begin, hipEvent_t ev_end) {
+    // the split is tuned once per (device, N, format/precision) on the live
+    // operands (products and partial sums together); y is overwritten below
+    const int variant = format == AFSBEM_FMT_C128 ? 0 : (precision == 1 ? 1 : 2);
+    const int S = autotune(
+        "gemv_column_split", N, variant, gemv_chunk_candidates(N), st,
+        [&](int c) { gemv_enqueue(N, format, precision, A, A_lo, x, y, partial, c, st, nullptr, nullptr); },
+        gemv_chunks_default(N));
+    gemv_enqueue(N, format, precision, A, A_lo, x, y, partial, S, st, ev_begin, ev_end);
 }
 
 // ---------------------------------------------------------- vector kernels --

@@ -273,3 +273,24 @@ def test_solve_host_pointer_entry():
             assert np.linalg.norm(out["a"][k] - x) / np.linalg.norm(x) <= 1e-7
             assert np.linalg.norm(out["u"][k] - uo) / np.linalg.norm(uo) <= 1e-7
             assert np.linalg.norm(out["t"][k] - to) / np.linalg.norm(to) <= 1e-7
+
+
+def test_autotuned_gemv_split():
+    """The tuned column split changes only the summation order: products with
+    and without tuning agree to rounding, and the report lists the choice."""
+    afs = _afs()
+    mesh = mg.cavity(3)
+    P = afs.Problem.from_mesh(mesh)
+    s = 0.25 + 1.1j
+    A, A_lo, b, _ = P.assemble(s, _bc_dev(mesh, s), fmt=afs.FMT_SPLIT)
+    rng = np.random.default_rng(4)
+    x = torch.from_numpy(rng.standard_normal(P.N) + 1j * rng.standard_normal(P.N)).cuda()
+    afs.autotune_set(False)
+    y_def = [P.matvec(A, A_lo, x, fmt=afs.FMT_SPLIT, precision=p).cpu().numpy() for p in (0, 1)]
+    afs.autotune_set(True)
+    y_tun = [P.matvec(A, A_lo, x, fmt=afs.FMT_SPLIT, precision=p).cpu().numpy() for p in (0, 1)]
+    rep = afs.autotune_report()
+    print(rep, flush=True)
+    assert f"gemv_column_split n={P.N} variant=1" in rep and f"gemv_column_split n={P.N} variant=2" in rep
+    for yd, yt, tol in zip(y_def, y_tun, (1e-13, 1e-6)):
+        assert np.linalg.norm(yt - yd) / np.linalg.norm(yd) <= tol
