@@ -61,11 +61,13 @@ template <>
 struct MfTraits<float> {
     static constexpr float thr2 = 0.25f;
     static constexpr int nser = 9;
+    static constexpr int unroll = 8;  // the whole Horner loop
 };
 template <>
 struct MfTraits<double> {
     static constexpr double thr2 = 0.0625;
     static constexpr int nser = 16;
+    static constexpr int unroll = 4;  // a full unroll keeps all 60 coefficients live (240 VGPRs)
 };
 
 template <class R>
@@ -80,7 +82,7 @@ __device__ __forceinline__ MfRad<R> mf_radial(cx<R> x, R beta, const R *__restri
     if (ax2 < MfTraits<R>::thr2) {
         constexpr int top = MfTraits<R>::nser - 1;
         cx<R> p0{coef[4 * top], 0}, p1{coef[4 * top + 1], 0}, p2{coef[4 * top + 2], 0}, p3{coef[4 * top + 3], 0};
-#pragma unroll
+#pragma unroll MfTraits<R>::unroll
         for (int n = top - 1; n >= 0; --n) {
             p0 = cx<R>{p0.r * x.r - p0.i * x.i + coef[4 * n], p0.r * x.i + p0.i * x.r};
             p1 = cx<R>{p1.r * x.r - p1.i * x.i + coef[4 * n + 1], p1.r * x.i + p1.i * x.r};
