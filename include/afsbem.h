@@ -163,6 +163,15 @@ enum { AFSBEM_PREC_FP64 = 0, AFSBEM_PREC_MIXED = 1 };
  * all frequencies it has solved so far, across calls) combined with the
  * previous solution.  Every guess x0 is rescaled (or the pair combined) to
  * minimise ||b - A x0|| before the Krylov solve. */
+/* Failure handling of afsbem_solve_device / afsbem_solve (stats.fallback):
+ * a starting guess whose residual is not finite or not below ||b|| is
+ * replaced by the zero start (fallback 1); mixed refinement whose outer FP64
+ * residual is not finite, or fails twice in a row to drop below 0.9 of its
+ * previous value, continues as FP64 GMRES from the best iterate (fallback 2).
+ * The fault_inject bits force these conditions from the host (the kernels
+ * run as usual): NAN_START replaces the starting guess by NaNs, STALL_INNER
+ * discards every inner correction. */
+enum { AFSBEM_FAULT_NAN_START = 1, AFSBEM_FAULT_STALL_INNER = 2 };
 enum { AFSBEM_WARM_NONE = 0, AFSBEM_WARM_PREV = 1, AFSBEM_WARM_USER = 2, AFSBEM_WARM_LEARNED = 3,
        AFSBEM_WARM_MODEL = 4 /* afsbem_afs_run_problem only, see there */ };
 
@@ -177,7 +186,7 @@ typedef struct {
     int32_t batch;       /* 1: one frequency at a time on the caller's stream; otherwise (default 0)
                             two in flight: the assembly of frequency k+1 on one library stream
                             overlaps the Krylov phase of frequency k on another */
-    uint32_t fault_inject; /* test hook bits, 0 in production */
+    uint32_t fault_inject; /* test hooks (AFSBEM_FAULT_* bits), 0 in production */
     int32_t profile;     /* 1: time every matrix-vector kernel with HIP events (stats.gemv_*) */
     int32_t learn_steps; /* AFSBEM_WARM_LEARNED: Adam steps after each solved frequency (0: 24) */
     int32_t precond;     /* block-diagonal preconditioner: 0 = one 3x3 block per collocation point;

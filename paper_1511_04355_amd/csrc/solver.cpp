@@ -478,38 +478,84 @@ static int krylov_phase(Problem &p, Workspace &ws, const afsbem_solve_opts &o, i
     if (bnorm == 0.0) {
         AFS_HIP(hipMemsetAsync(ws.x, 0, (size_t)N * 16, st));
         relres = 0.0;
-    } else if (!mixed) {
-        const double r0n = start_iterate(op64, ws, ws.b, bnorm, x_prev, x_net, ws.x, ws.r, x_zero, st, &used_net, &net_gain);
-        rel_start = r0n / bnorm;
-        GmresResult g = gmres(op64, ws, nt, ws.b, bnorm, ws.x, x_zero, o.tol * bnorm, o.restart, o.max_iter, st,
-                              true, x_zero ? nullptr : ws.r, r0n);
-        // final true FP64 residual (after the last restart gmres already formed r)
-        relres = g.est / bnorm;
-        if (g.nan)
-            status = AFSBEM_ENAN;
     } else {
-        // mixed: outer residual with the FP64 operator (hi + lo planes), inner
-        // GMRES on the FP32 hi plane for the correction d: A32 d = r.  The
-        // starting residual only seeds the inner solve: FP32 operator.
+        // Starting iterate.  A guess whose residual is not finite or not below
+        // ||b|| is rejected for the zero start (stats.fallback = 1).  The mixed
+        // path seeds its inner solve with the FP32 operator's residual.
         Operator op32 = op64;
         op32.precision = 1;
-        double rnorm = start_iterate(op32, ws, ws.b, bnorm, x_prev, x_net, ws.xo, ws.rin, x_zero, st, &used_net, &net_gain);
-        rel_start = rnorm / bnorm;
-        while (std::isfinite(rnorm)) {
-            const double tol_in = std::max(o.inner_tol * rnorm, 0.5 * o.tol * bnorm);
-            GmresResult g = gmres(op32, ws, nt, ws.rin, rnorm, ws.x, true, tol_in, o.restart,
-                                  std::max(1, o.max_iter - matvecs), st, false, nullptr, 0.0);
-            vec_combine(N, 1, ws.x, N, ws.one, ws.xo, st);  // x_outer += d
-            residual(op64, ws, ws.b, ws.xo, ws.rin, st);     // FP64 judge
-            rnorm = norm2_dev(ws, N, ws.rin, st);
-            ++refine;
-            if (g.nan || rnorm <= o.tol * bnorm || matvecs >= o.max_iter)
-                break;
+        double *xs = mixed ? ws.xo : ws.x, *rs = mixed ? ws.rin : ws.r;
+        double r0n = start_iterate(mixed ? op32 : op64, ws, ws.b, bnorm, x_prev, x_net, xs, rs, x_zero, st, &used_net,
+                                   &net_gain);
+        if (!x_zero && (o.fault_inject & AFSBEM_FAULT_NAN_START)) {
+            // test hook: the guess turned out non-finite
+            AFS_HIP(hipMemsetAsync(xs, 0xff, (size_t)N * 16, st));
+            residual(mixed ? op32 : op64, ws, ws.b, xs, rs, st);
+            r0n = norm2_dev(ws, N, rs, st);
         }
-        relres = rnorm / bnorm;
-        if (!std::isfinite(rnorm))
+        if (!x_zero && !(r0n < bnorm)) {
+            AFS_HIP(hipMemsetAsync(xs, 0, (size_t)N * 16, st));
+            AFS_HIP(hipMemcpyAsync(rs, ws.b, (size_t)N * 16, hipMemcpyDeviceToDevice, st));
+            r0n = bnorm;
+            x_zero = true;
+            used_net = false;
+            fallback = 1;
+        }
+        rel_start = r0n / bnorm;
+        bool plain = !mixed;
+        if (mixed) {
+            // outer residual with the FP64 operator (hi + lo planes, or FP64
+            // evaluation), inner GMRES on the FP32 operator for the correction
+            // d: A32 d = r.  Two outer steps that do not reduce the residual
+            // to 0.9 of its value, or a non-finite residual, hand the solve
+            // to FP64 GMRES from the best iterate (stats.fallback = 2).
+            double rnorm = r0n;
+            int stalls = 0;
+            bool from_zero = false;
+            while (true) {
+                const double tol_in = std::max(o.inner_tol * rnorm, 0.5 * o.tol * bnorm);
+                GmresResult g = gmres(op32, ws, nt, ws.rin, rnorm, ws.x, true, tol_in, o.restart,
+                                      std::max(1, o.max_iter - matvecs), st, false, nullptr, 0.0);
+                if (!(o.fault_inject & AFSBEM_FAULT_STALL_INNER))  // test hook: the correction is lost
+                    vec_combine(N, 1, ws.x, N, ws.one, ws.xo, st);  // x_outer += d
+                residual(op64, ws, ws.b, ws.xo, ws.rin, st);         // FP64 judge
+                const double rn = norm2_dev(ws, N, ws.rin, st);
+                ++refine;
+                if (!std::isfinite(rn) || g.nan) {
+                    AFS_HIP(hipMemsetAsync(ws.xo, 0, (size_t)N * 16, st));
+                    rnorm = bnorm;
+                    plain = from_zero = true;
+                    break;
+                }
+                stalls = rn > 0.9 * rnorm ? stalls + 1 : 0;
+                rnorm = rn;
+                if (rnorm <= o.tol * bnorm || matvecs >= o.max_iter)
+                    break;
+                if (stalls >= 2) {
+                    plain = true;
+                    break;
+                }
+            }
+            relres = rnorm / bnorm;
+            AFS_HIP(hipMemcpyAsync(ws.x, ws.xo, (size_t)N * 16, hipMemcpyDeviceToDevice, st));
+            if (plain) {
+                fallback = 2;
+                x_zero = from_zero;  // after a non-finite residual: from zero
+                r0n = rnorm;
+                AFS_HIP(hipMemcpyAsync(ws.r, from_zero ? ws.b : ws.rin, (size_t)N * 16, hipMemcpyDeviceToDevice,
+                                       st));
+            }
+        }
+        if (plain) {
+            GmresResult g = gmres(op64, ws, nt, ws.b, bnorm, ws.x, x_zero, o.tol * bnorm, o.restart,
+                                  std::max(1, o.max_iter - matvecs), st, true, x_zero ? nullptr : ws.r, r0n);
+            // final true FP64 residual (after the last restart gmres already formed r)
+            relres = g.est / bnorm;
+            if (g.nan)
+                status = AFSBEM_ENAN;
+        }
+        if (!std::isfinite(relres))
             status = AFSBEM_ENAN;
-        AFS_HIP(hipMemcpyAsync(ws.x, ws.xo, (size_t)N * 16, hipMemcpyDeviceToDevice, st));
     }
     AFS_HIP(hipEventRecord(e2, st));
     if (d_a)

@@ -294,3 +294,58 @@ def test_autotuned_gemv_split():
     assert f"gemv_column_split n={P.N} variant=1" in rep and f"gemv_column_split n={P.N} variant=2" in rep
     for yd, yt, tol in zip(y_def, y_tun, (1e-13, 1e-6)):
         assert np.linalg.norm(yt - yd) / np.linalg.norm(yd) <= tol
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_failure_handling_nan_start(prec):
+    """A non-finite starting guess (forced from the host) is replaced by the
+    zero start (stats.fallback = 1) and the solve still meets the tolerance
+    and matches the oracle."""
+    afs, bem = _afs(), _oracle()
+    mesh, s, bc = _cavity_workload(1, 3)
+    P = afs.Problem.from_mesh(mesh)
+    tol = 1e-9 if prec == "fp64" else 1e-6
+    o = afs.SolveOptions(tol=tol, precision=afs.PREC_FP64 if prec == "fp64" else afs.PREC_MIXED,
+                         warm_start=afs.WARM_PREV, fault_inject=1, batch=1)
+    out = P.solve(s, torch.from_numpy(bc).cuda(), o)
+    assert out["status"] == 0
+    assert [x["fallback"] for x in out["stats"]] == [0, 1, 1]
+    for k, sk in enumerate(s):
+        A, b = bem.assemble(mesh, sk)
+        x = out["a"][k].cpu().numpy()
+        assert np.linalg.norm(b - A @ x) / np.linalg.norm(b) <= 1.5 * tol
+
+
+def test_failure_handling_stalled_refinement():
+    """Mixed refinement whose inner corrections are lost (forced) hands over
+    to FP64 GMRES (stats.fallback = 2) and still converges."""
+    afs, bem = _afs(), _oracle()
+    mesh, s, bc = _cavity_workload(1, 2)
+    P = afs.Problem.from_mesh(mesh)
+    for batch in (1, 0):
+        o = afs.SolveOptions(tol=1e-8, precision=afs.PREC_MIXED, fault_inject=2, batch=batch)
+        out = P.solve(s, torch.from_numpy(bc).cuda(), o)
+        assert out["status"] == 0
+        for k, sk in enumerate(s):
+            st = out["stats"][k]
+            assert st["fallback"] == 2 and st["refine_steps"] == 2
+            A, b = bem.assemble(mesh, sk)
+            x = out["a"][k].cpu().numpy()
+            assert np.linalg.norm(b - A @ x) / np.linalg.norm(b) <= 1.5e-8
+
+
+def test_failure_handling_iteration_cap_and_bad_arguments():
+    afs = _afs()
+    mesh, s, bc = _cavity_workload(1, 1)
+    P = afs.Problem.from_mesh(mesh)
+    bcd = torch.from_numpy(bc).cuda()
+    out = P.solve(s, bcd, afs.SolveOptions(tol=1e-12, max_iter=2, restart=2))
+    assert out["status"] == afs._lib.ENOCONV
+    assert out["stats"][0]["status"] == afs._lib.ENOCONV and out["stats"][0]["rel_res_fp64"] > 1e-12
+    assert torch.isfinite(out["a"]).all()
+    for bad in (afs.SolveOptions(restart=0), afs.SolveOptions(tol=-1.0), afs.SolveOptions(precision=7),
+                afs.SolveOptions(warm_start=afs.WARM_MODEL)):
+        with pytest.raises(afs.AfsbemError):
+            P.solve(s, bcd, bad)
+    with pytest.raises(afs.AfsbemError):
+        P.solve(np.array([np.nan + 0j]), bcd, afs.SolveOptions())
