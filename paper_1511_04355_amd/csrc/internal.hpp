@@ -125,6 +125,7 @@ struct KernelParams {
     double beta;          // c_s / c_p
     double c_u;           // 1 / (4 pi mu)
     double lam_over_mu;
+    double inv_ks2;       // c_s^2 / |s|^2: 1/|x|^2 = inv_ks2 / r^2 (0 at s = 0)
 };
 KernelParams kernel_params(const MaterialDerived &m, double s_re, double s_im);
 

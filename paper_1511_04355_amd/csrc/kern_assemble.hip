@@ -15,6 +15,7 @@
 // but need many nodes each: one wavefront per pair, lanes over nodes, then a
 // wavefront reduction.
 #include "cplx.hpp"
+#include "fastmath64.hpp"
 #include "internal.hpp"
 
 namespace afsbem {
@@ -33,7 +34,8 @@ struct Radial {
     cd Psi, X, Psd, Xd;
 };
 
-__device__ __forceinline__ Radial radial64(cd x, double beta, const double *__restrict__ coef) {
+// inv_ax2 = 1 / |x|^2, supplied by the caller (from 1/r, without a division)
+__device__ __forceinline__ Radial radial64(cd x, double beta, const double *__restrict__ coef, double inv_ax2) {
     Radial R;
     const double ax2 = x.r * x.r + x.i * x.i;
     if (ax2 < 0.0625) {
@@ -54,13 +56,13 @@ __device__ __forceinline__ Radial radial64(cd x, double beta, const double *__re
         return R;
     }
     double sn, cs;
-    sincos(x.i, &sn, &cs);
-    const double ex = exp(-x.r);
+    sincos_cw(x.i, &sn, &cs);
+    const double ex = exp_cw(-x.r);
     const cd e = cd{ex * cs, -ex * sn};
-    sincos(beta * x.i, &sn, &cs);
-    const double exp_ = exp(-beta * x.r);
+    sincos_cw(beta * x.i, &sn, &cs);
+    const double exp_ = exp_cw(-beta * x.r);
     const cd ep = cd{exp_ * cs, -exp_ * sn};
-    const double inv = 1.0 / ax2;
+    const double inv = inv_ax2;
     const cd ix = cd{x.r * inv, -x.i * inv};
     const cd ix2 = cmul(ix, ix);
     const double b2 = beta * beta;
@@ -89,8 +91,8 @@ __device__ __forceinline__ void eval_pair(const KernelParams &kp, const double *
                                           double nx, double ny, double nz, PairEval &E) {
     const double dx = yx - xx, dy = yy - xy, dz = yz - xz;
     const double r2 = dx * dx + dy * dy + dz * dz;
-    const double r = sqrt(r2);
-    const double ir = 1.0 / r;
+    const double ir = rsqrt_nr(r2);
+    const double r = r2 * ir;
     E.r = r;
     E.ir = ir;
     E.rh[0] = dx * ir;
@@ -98,7 +100,7 @@ __device__ __forceinline__ void eval_pair(const KernelParams &kp, const double *
     E.rh[2] = dz * ir;
     E.rn = E.rh[0] * nx + E.rh[1] * ny + E.rh[2] * nz;
     const cd x = cd{kp.s_re * r * kp.inv_cs, kp.s_im * r * kp.inv_cs};
-    const Radial R = radial64(x, kp.beta, coef);
+    const Radial R = radial64(x, kp.beta, coef, ir * ir * kp.inv_ks2);
     E.Psi = R.Psi;
     E.X = R.X;
     const cd b1 = csub(R.Psd, R.X);
@@ -612,6 +614,8 @@ KernelParams kernel_params(const MaterialDerived &m, double s_re, double s_im) {
     k.beta = m.beta;
     k.c_u = 1.0 / (4.0 * 3.14159265358979323846 * m.mu);
     k.lam_over_mu = m.lam_over_mu;
+    const double s2 = s_re * s_re + s_im * s_im;
+    k.inv_ks2 = s2 > 0.0 ? m.cs * m.cs / s2 : 0.0;  // only the closed form (|x| >= 1/4) uses it
     return k;
 }
 

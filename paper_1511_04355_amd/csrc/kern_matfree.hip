@@ -16,6 +16,7 @@
 // accumulators, which then hold one partial sum per source chunk.
 #include <hip/hip_runtime.h>
 
+#include "fastmath64.hpp"
 #include "internal.hpp"
 
 namespace afsbem {
@@ -46,11 +47,11 @@ __device__ __forceinline__ void exp_sincos(float a, float b, float &e, float &sn
     __sincosf(b, &sn, &cs);
 }
 __device__ __forceinline__ void exp_sincos(double a, double b, double &e, double &sn, double &cs) {
-    e = exp(a);
-    sincos(b, &sn, &cs);
+    e = exp_cw(a);
+    sincos_cw(b, &sn, &cs);
 }
 __device__ __forceinline__ float inv_sqrt(float a) { return rsqrtf(a); }
-__device__ __forceinline__ double inv_sqrt(double a) { return 1.0 / sqrt(a); }
+__device__ __forceinline__ double inv_sqrt(double a) { return rsqrt_nr(a); }
 
 // Series about 0 below |x|^2 < thr2, closed form above.  FP32: |x| < 1/2 with
 // 9 terms (truncation ~1e-9; the closed form loses eps32/|x|^2 <= 5e-7 above);
@@ -75,8 +76,9 @@ struct MfRad {
     cx<R> Psi, X, Psd, Xd;
 };
 
+// inv_ax2 = 1 / |x|^2, supplied by the caller from 1/r (no division)
 template <class R>
-__device__ __forceinline__ MfRad<R> mf_radial(cx<R> x, R beta, const R *__restrict__ coef) {
+__device__ __forceinline__ MfRad<R> mf_radial(cx<R> x, R beta, const R *__restrict__ coef, R inv_ax2) {
     MfRad<R> o;
     const R ax2 = x.r * x.r + x.i * x.i;
     if (ax2 < MfTraits<R>::thr2) {
@@ -100,7 +102,7 @@ __device__ __forceinline__ MfRad<R> mf_radial(cx<R> x, R beta, const R *__restri
     exp_sincos(-beta * x.r, beta * x.i, exq, snq, csq);
     const cx<R> e{ex * cs, -ex * sn};      // e^{-x}
     const cx<R> ep{exq * csq, -exq * snq};  // e^{-beta x}
-    const R inv = R(1) / ax2;
+    const R inv = inv_ax2;
     const cx<R> ix{x.r * inv, -x.i * inv};
     const cx<R> ix2 = cxmul(ix, ix);
     const R b2 = beta * beta, b3 = b2 * beta;
@@ -118,6 +120,7 @@ __device__ __forceinline__ MfRad<R> mf_radial(cx<R> x, R beta, const R *__restri
 struct MfArgs {
     double sr, si;  // s / c_s
     double beta, lam_over_mu, c_u;
+    double inv_ks2;  // 1 / |s / c_s|^2 (0 at s = 0)
 };
 
 // One far source chunk per blockIdx.y.  COMP = 0: y = A x (T for kind-0
@@ -144,6 +147,7 @@ __global__ __launch_bounds__(256) void mf_far_kernel(int64_t nt, MfArgs a, const
     const R sr = (R)a.sr, si = (R)a.si, beta = (R)a.beta, lam = (R)a.lam_over_mu;
     const R cT = (R)0.079577471545947667884;  // 1 / (4 pi)
     const R cU = (R)a.c_u;
+    const R iks2 = (R)a.inv_ks2;
     const int64_t n0 = (int64_t)blockIdx.y * chunk_len;
     const int64_t n1 = (n0 + chunk_len < nt) ? n0 + chunk_len : nt;
     double acc[6] = {0, 0, 0, 0, 0, 0};
@@ -167,7 +171,7 @@ __global__ __launch_bounds__(256) void mf_far_kernel(int64_t nt, MfArgs a, const
                 const R r = r2 * ir;
                 const R hx = dx * ir, hy = dy * ir, hz = dz * ir;
                 const R rn = hx * nx + hy * ny + hz * nz;
-                const MfRad<R> Rd = mf_radial<R>(cx<R>{sr * r, si * r}, beta, coef);
+                const MfRad<R> Rd = mf_radial<R>(cx<R>{sr * r, si * r}, beta, coef, ir * ir * iks2);
                 const R f = rec[4 * q + 3] * cT * ir * ir;
                 const cx<R> t1 = cxsub(Rd.Psd, Rd.X);
                 const cx<R> t2 = cxadd(cxs(Rd.X, R(-2)), cxs(cxsub(cxsub(Rd.Psd, Rd.Xd), cxs(Rd.X, R(2))), lam));
@@ -189,7 +193,7 @@ __global__ __launch_bounds__(256) void mf_far_kernel(int64_t nt, MfArgs a, const
                 const R ir = inv_sqrt(r2);
                 const R r = r2 * ir;
                 const R hx = dx * ir, hy = dy * ir, hz = dz * ir;
-                const MfRad<R> Rd = mf_radial<R>(cx<R>{sr * r, si * r}, beta, coef);
+                const MfRad<R> Rd = mf_radial<R>(cx<R>{sr * r, si * r}, beta, coef, ir * ir * iks2);
                 const R f = rec[4 * q + 3] * cU * ir;
                 const cx<R> rv = cxadd(cxadd(cxs(v0, hx), cxs(v1, hy)), cxs(v2, hz));
                 c0 = cxadd(c0, cxs(Rd.Psi, f));
@@ -279,6 +283,8 @@ void mf_apply(const Problem &p, const KernelParams &kp, int precision, int comp,
     a.beta = kp.beta;
     a.lam_over_mu = kp.lam_over_mu;
     a.c_u = kp.c_u;
+    const double ks2 = a.sr * a.sr + a.si * a.si;
+    a.inv_ks2 = ks2 > 0.0 ? 1.0 / ks2 : 0.0;
     const dim3 g((unsigned)((nt + 255) / 256), (unsigned)Sused);
     double2 *part = reinterpret_cast<double2 *>(partial);
     if (precision == 1) {
