@@ -159,6 +159,7 @@ int afsbem_problem_create(const afsbem_mesh *mesh, const afsbem_material *mat, c
         D.near_ptr = upload(h, H.near_ptr);
         D.near_col = upload(h, H.near_col);
         D.near_row = upload(h, H.near_row);
+        D.near_order = upload(h, H.near_order);
         D.leaf_ptr = upload(h, H.leaf_ptr);
         D.leaves = upload(h, H.leaves);
         D.self_ang = upload(h, H.self_ang);

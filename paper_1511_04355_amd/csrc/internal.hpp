@@ -64,6 +64,7 @@ struct HostPlan {
     std::vector<int32_t> near_row; // [nnz] collocation element
     std::vector<int64_t> leaf_ptr; // [nnz+1]
     std::vector<double> leaves;    // [n_leaves][10]: p0(3), e1(3), e2(3), area
+    std::vector<int32_t> near_order; // [nnz] pairs by decreasing leaf count (work order of the near kernel)
     // self element polar tables
     int n_theta = 16, n_rho = 16;
     std::vector<double> self_ang;  // [n][3*n_theta][5]: e(3), R, w_theta
@@ -88,7 +89,7 @@ struct DevicePlan {
     double *src = nullptr;
     int8_t *kind = nullptr;
     int64_t *near_ptr = nullptr;
-    int32_t *near_col = nullptr, *near_row = nullptr;
+    int32_t *near_col = nullptr, *near_row = nullptr, *near_order = nullptr;
     int64_t *leaf_ptr = nullptr;
     double *leaves = nullptr;
     double *self_ang = nullptr, *self_cpv = nullptr, *gl_rho = nullptr;

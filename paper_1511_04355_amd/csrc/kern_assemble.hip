@@ -398,16 +398,17 @@ __global__ __launch_bounds__(256) void near_assemble_kernel(
     int64_t nt, int64_t lda, int64_t nnz, KernelParams kp, Rule7Args rule, const double *__restrict__ colx,
     const double *__restrict__ coly, const double *__restrict__ colz, const double *__restrict__ src,
     const double *__restrict__ bc, const double *__restrict__ coef, const int32_t *__restrict__ near_row,
-    const int32_t *__restrict__ near_col, const int64_t *__restrict__ leaf_ptr,
+    const int32_t *__restrict__ near_col, const int32_t *__restrict__ near_order, const int64_t *__restrict__ leaf_ptr,
     const double *__restrict__ leaves, void *A, void *A_lo, double *__restrict__ corr) {
     // FMT == kFmtBlocks: A receives the correction block (exact - far rule) of
     // pair p at [p][9] complex, row-major (the far rule stays in the operator)
     const int64_t gid = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    const int64_t p = gid / kNearLanes;
+    const int64_t g = gid / kNearLanes;
     const int sub = (int)(gid % kNearLanes);
     // groups are aligned inside a wavefront, so a whole group is in or out
-    if (p >= nnz)
+    if (g >= nnz)
         return;
+    const int64_t p = near_order[g];
     const int64_t m = near_row[p], n = near_col[p];
     const double xx = colx[m], xy = coly[m], xz = colz[m];
     const double *rec = src + kSrcStride * n;
@@ -667,7 +668,7 @@ void launch_assembly(const Problem &p, const KernelParams &kp, const double *bc_
     if (format == AFSBEM_FMT_C128) {
         if (d.nnz)
             near_assemble_kernel<AFSBEM_FMT_C128><<<gnear, 256, 0, st>>>(
-                nt, lda, d.nnz, kp, rule, d.colx, d.coly, d.colz, d.src, bc_val, coef, d.near_row, d.near_col,
+                nt, lda, d.nnz, kp, rule, d.colx, d.coly, d.colz, d.src, bc_val, coef, d.near_row, d.near_col, d.near_order,
                 d.leaf_ptr, d.leaves, A, A_lo, corr);
         self_assemble_kernel<AFSBEM_FMT_C128><<<gself, 256, 0, st>>>(nt, lda, kp, d.colx, d.coly, d.colz, d.src,
                                                                     bc_val, coef, d.self_ang, d.self_cpv, d.gl_rho,
@@ -675,7 +676,7 @@ void launch_assembly(const Problem &p, const KernelParams &kp, const double *bc_
     } else {
         if (d.nnz)
             near_assemble_kernel<AFSBEM_FMT_SPLIT><<<gnear, 256, 0, st>>>(
-                nt, lda, d.nnz, kp, rule, d.colx, d.coly, d.colz, d.src, bc_val, coef, d.near_row, d.near_col,
+                nt, lda, d.nnz, kp, rule, d.colx, d.coly, d.colz, d.src, bc_val, coef, d.near_row, d.near_col, d.near_order,
                 d.leaf_ptr, d.leaves, A, A_lo, corr);
         self_assemble_kernel<AFSBEM_FMT_SPLIT><<<gself, 256, 0, st>>>(nt, lda, kp, d.colx, d.coly, d.colz, d.src,
                                                                      bc_val, coef, d.self_ang, d.self_cpv, d.gl_rho,
@@ -700,7 +701,7 @@ void launch_block_setup(const Problem &p, const KernelParams &kp, const double *
     const Rule7Args rule = rule7_args();
     if (d.nnz)
         near_assemble_kernel<kFmtBlocks><<<gnear, 256, 0, st>>>(nt, 0, d.nnz, kp, rule, d.colx, d.coly, d.colz, d.src,
-                                                                bc_val, d.coef, d.near_row, d.near_col, d.leaf_ptr,
+                                                                bc_val, d.coef, d.near_row, d.near_col, d.near_order, d.leaf_ptr,
                                                                 d.leaves, nearblk, nullptr, corr);
     self_assemble_kernel<kFmtBlocks><<<gself, 256, 0, st>>>(nt, 0, kp, d.colx, d.coly, d.colz, d.src, bc_val, d.coef,
                                                             d.self_ang, d.self_cpv, d.gl_rho, d.n_theta, d.n_rho,

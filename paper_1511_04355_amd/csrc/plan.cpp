@@ -256,6 +256,16 @@ void build_plan(const double *xyz, int64_t nv, const int32_t *tri, int64_t nt, c
             ++k;
         }
     }
+    // The near kernel gives each pair a fixed group of lanes and a wave holds
+    // several pairs: taking the pairs in decreasing order of their leaf count
+    // keeps the pairs of a wave alike (edge neighbours of a collocation point
+    // have ~10x the median leaf count; in row order nearly every wave holds one).
+    P.near_order.resize(nnz);
+    for (int64_t q = 0; q < nnz; ++q)
+        P.near_order[q] = (int32_t)q;
+    std::stable_sort(P.near_order.begin(), P.near_order.end(), [&](int32_t a, int32_t b) {
+        return P.leaf_ptr[a + 1] - P.leaf_ptr[a] > P.leaf_ptr[b + 1] - P.leaf_ptr[b];
+    });
 
     // ---- self element polar tables
     const int nth = pol.self_n_theta, nrh = pol.self_n_rho;
