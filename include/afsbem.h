@@ -263,7 +263,7 @@ int afsbem_solve(afsbem_problem *p, int32_t n_s, const double *s, const double *
  * inner cycles with FP64 residuals), precond (0 or 1 as in
  * afsbem_solve_device), no_graph.  Systems are solved in waves that fit a
  * slot of min(30 % of free device memory, 16 GiB) (at least one system, at
- * most 64, or opts.batch if > 1); two slots alternate so that the next wave
+ * most 64, or opts.batch if >= 1); two slots alternate so that the next wave
  * is assembled while the current one is solved.  The device memory and
  * streams are kept by probs[0] for later calls (freed with it).  Warm starts
  * and the matrix-free operator are not available here (AFSBEM_EINVAL).  Work

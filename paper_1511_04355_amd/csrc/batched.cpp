@@ -252,7 +252,7 @@ int solve_batched(int n_prob, Problem *const *probs, const int32_t *n_s, const d
     AFS_HIP(hipMemGetInfo(&free_b, &total_b));
     const double avail = (double)free_b + (double)ar.cap;
     double slot_budget = std::min(0.3 * avail, 16.0 * (1 << 30));
-    const int max_b = o.batch > 1 ? o.batch : 64;
+    const int max_b = o.batch >= 1 ? o.batch : 64;
     // ---- pack the waves
     std::vector<std::pair<int, int>> waves;
     for (size_t f = 0; f < all.size();) {
