@@ -48,8 +48,8 @@ FAR_FLOPS_PER_NODE = 307.0
 FAR_NODES = 7
 # HBM bytes per launch from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE over --workload pmc_probe
 # (FETCH_SIZE x 2.0, its reading for a 1 GiB device copy being half the true bytes)
-FAR_TRAFFIC_BYTES = (2.0 * 22011.25 + 3736702.23) * 1024
-GEMV32_TRAFFIC_BYTES = 2.0 * 923563.16 * 1024
+FAR_TRAFFIC_BYTES = (2.0 * 23885.20 + 3736479.73) * 1024
+GEMV32_TRAFFIC_BYTES = 2.0 * 923559.66 * 1024
 
 
 def parse():

@@ -575,10 +575,31 @@ __global__ __launch_bounds__(256) void finalize_b_kernel(int64_t nt, int S, cons
         return;
     const int64_t m = r / 3;
     const int i = (int)(r % 3);
+    // eight partial sums in flight per lane, combined in a fixed order
+    const double2 *bp = reinterpret_cast<const double2 *>(bpart);
+    double pr[8] = {0, 0, 0, 0, 0, 0, 0, 0}, pi[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int s = 0;
+    for (; s + 8 <= S; s += 8) {
+        double2 v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            v[u] = bp[(int64_t)(s + u) * N + r];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            pr[u] += v[u].x;
+            pi[u] += v[u].y;
+        }
+    }
+    for (; s < S; ++s) {
+        const double2 v = bp[(int64_t)s * N + r];
+        pr[0] += v.x;
+        pi[0] += v.y;
+    }
     double ar = 0, ai = 0;
-    for (int s = 0; s < S; ++s) {
-        ar += bpart[2 * ((int64_t)s * N + r)];
-        ai += bpart[2 * ((int64_t)s * N + r) + 1];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+        ar += pr[u];
+        ai += pi[u];
     }
     ar += bself[6 * m + 2 * i];
     ai += bself[6 * m + 2 * i + 1];

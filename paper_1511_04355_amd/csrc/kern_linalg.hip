@@ -187,11 +187,31 @@ __global__ __launch_bounds__(256) void sum_partials_kernel(int64_t N, int S, con
     const int64_t row = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (row >= N)
         return;
-    double r = 0, i = 0;
-    for (int s = 0; s < S; ++s) {
+    // eight partial sums in flight per lane (the loop is latency-bound), then
+    // combined in a fixed order
+    double rr[8] = {0, 0, 0, 0, 0, 0, 0, 0}, ii[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int s = 0;
+    for (; s + 8 <= S; s += 8) {
+        double2 v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            v[u] = partial[(int64_t)(s + u) * N + row];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            rr[u] += v[u].x;
+            ii[u] += v[u].y;
+        }
+    }
+    for (; s < S; ++s) {
         const double2 v = partial[(int64_t)s * N + row];
-        r += v.x;
-        i += v.y;
+        rr[0] += v.x;
+        ii[0] += v.y;
+    }
+    double r = 0, i = 0;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+        r += rr[u];
+        i += ii[u];
     }
     y[row] = make_double2(r, i);
 }
@@ -314,66 +334,78 @@ int mdot_blocks(int64_t N) {
     return (int)b;
 }
 
-// grid (B, nv): block (b, i) computes the partial dot of V_i and w over its rows
-__global__ __launch_bounds__(256) void mdot_partial_kernel(int64_t N, const double2 *__restrict__ V, int64_t ldv,
-                                                           const double2 *__restrict__ w, int B,
-                                                           double2 *__restrict__ partial) {
-    __shared__ double sr[256], si[256];
+// Multi-dot in one launch, grid (B, nv): block (b, i) reduces conj(V_i) . w
+// over its rows (wave shuffles, then the four waves through LDS) and stores
+// its partial; the last block to finish vector i (a per-vector arrival
+// counter) adds the B partials in block order, writes out[i] and re-arms the
+// counter.  The counters live at the head of the partial buffer (zeroed when
+// the buffer is allocated).
+__device__ __forceinline__ double wave_sum64(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+        v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__global__ __launch_bounds__(256) void mdot_kernel(int64_t N, const double2 *__restrict__ V, int64_t ldv,
+                                                   const double2 *__restrict__ w, int B,
+                                                   double2 *__restrict__ partial, unsigned *__restrict__ counter,
+                                                   double2 *__restrict__ out) {
+    __shared__ double sr[4], si[4];
+    __shared__ bool last;
     const int i = blockIdx.y;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const double2 *v = V + (int64_t)i * ldv;
     double ar = 0, ai = 0;
     for (int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x; r < N; r += (int64_t)B * 256) {
         const double2 a = v[r], b = w[r];
-        // conj(a) * b
-        ar += a.x * b.x + a.y * b.y;
+        ar += a.x * b.x + a.y * b.y;  // conj(a) * b
         ai += a.x * b.y - a.y * b.x;
     }
-    sr[threadIdx.x] = ar;
-    si[threadIdx.x] = ai;
-    __syncthreads();
-    for (int off = 128; off > 0; off >>= 1) {
-        if ((int)threadIdx.x < off) {
-            sr[threadIdx.x] += sr[threadIdx.x + off];
-            si[threadIdx.x] += si[threadIdx.x + off];
-        }
-        __syncthreads();
+    ar = wave_sum64(ar);
+    ai = wave_sum64(ai);
+    if (lane == 0) {
+        sr[wv] = ar;
+        si[wv] = ai;
     }
-    if (threadIdx.x == 0)
-        partial[(int64_t)i * B + blockIdx.x] = make_double2(sr[0], si[0]);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        partial[(int64_t)i * B + blockIdx.x] = make_double2((sr[0] + sr[1]) + (sr[2] + sr[3]),
+                                                            (si[0] + si[1]) + (si[2] + si[3]));
+        __threadfence();
+        last = atomicAdd(&counter[i], 1u) == (unsigned)(B - 1);
+    }
+    __syncthreads();
+    if (!last || wv != 0)
+        return;
+    __threadfence();
+    double br = 0, bi = 0;
+    for (int b = lane; b < B; b += 64) {
+        const double2 q = partial[(int64_t)i * B + b];
+        br += q.x;
+        bi += q.y;
+    }
+    br = wave_sum64(br);
+    bi = wave_sum64(bi);
+    if (lane == 0) {
+        out[i] = make_double2(br, bi);
+        counter[i] = 0u;
+    }
 }
 
-__global__ __launch_bounds__(64) void mdot_final_kernel(int B, const double2 *__restrict__ partial,
-                                                        double2 *__restrict__ out) {
-    const int i = blockIdx.x;
-    __shared__ double sr[64], si[64];
-    double ar = 0, ai = 0;
-    for (int b = threadIdx.x; b < B; b += 64) {
-        const double2 v = partial[(int64_t)i * B + b];
-        ar += v.x;
-        ai += v.y;
-    }
-    sr[threadIdx.x] = ar;
-    si[threadIdx.x] = ai;
-    __syncthreads();
-    for (int off = 32; off > 0; off >>= 1) {
-        if ((int)threadIdx.x < off) {
-            sr[threadIdx.x] += sr[threadIdx.x + off];
-            si[threadIdx.x] += si[threadIdx.x + off];
-        }
-        __syncthreads();
-    }
-    if (threadIdx.x == 0)
-        out[i] = make_double2(sr[0], si[0]);
+size_t mdot_scratch_bytes(int64_t N, int nv_max) {
+    return (size_t)kMdotCounterBytes + (size_t)mdot_blocks(N) * nv_max * 16;
 }
 
 void vec_mdot(int64_t N, int nv, const double *V, int64_t ldv, const double *w, double *partial, double *out,
               hipStream_t st) {
     const int B = mdot_blocks(N);
-    mdot_partial_kernel<<<dim3(B, nv), 256, 0, st>>>(N, reinterpret_cast<const double2 *>(V), ldv,
-                                                     reinterpret_cast<const double2 *>(w), B,
-                                                     reinterpret_cast<double2 *>(partial));
-    mdot_final_kernel<<<nv, 64, 0, st>>>(B, reinterpret_cast<const double2 *>(partial),
-                                         reinterpret_cast<double2 *>(out));
+    AFS_REQUIRE(nv >= 1 && nv <= kMdotMaxVectors, AFSBEM_EINVAL, "multi-dot: too many vectors");
+    unsigned *counter = reinterpret_cast<unsigned *>(partial);
+    double2 *part = reinterpret_cast<double2 *>(reinterpret_cast<char *>(partial) + kMdotCounterBytes);
+    mdot_kernel<<<dim3(B, nv), 256, 0, st>>>(N, reinterpret_cast<const double2 *>(V), ldv,
+                                             reinterpret_cast<const double2 *>(w), B, part, counter,
+                                             reinterpret_cast<double2 *>(out));
     AFS_HIP(hipGetLastError());
 }
 

@@ -113,7 +113,8 @@ void Workspace::ensure(const Problem &p, int format, int restart_m, int prec) {
     tmp = (double *)dalloc((size_t)N * 16);
     rin = (double *)dalloc((size_t)N * 16);
     xo = (double *)dalloc((size_t)N * 16);
-    dots_partial = (double *)dalloc((size_t)mdot_blocks(N) * (restart_m + 2) * 16);
+    dots_partial = (double *)dalloc(mdot_scratch_bytes(N, restart_m + 2));
+    AFS_HIP(hipMemset(dots_partial, 0, kMdotCounterBytes));  // arrival counters
     small = (double *)dalloc((size_t)(4 * (restart_m + 2)) * 16);
     AFS_HIP(hipHostMalloc((void **)&host_small, (size_t)(4 * (restart_m + 2)) * 16, hipHostMallocDefault));
     one = (double *)dalloc(16);
