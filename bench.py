@@ -348,8 +348,8 @@ def run_porous_matrix_free(args, afs, mg, np, torch):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              "(frequencies shard across GPUs with no communication, see DESIGN.md)", file=sys.stderr)
+        print(f"bench.py: the benchmark runs on one GPU; --gpus {args.gpus} is not supported "
+              "(the frequencies would shard across GPUs with no communication beyond returning the observed values)", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
