@@ -69,13 +69,15 @@ def parse():
                     help="initial guess of the optimised path")
     ap.add_argument("--workload", default="cavity_L4",
                     choices=["cavity_L4", "pmc_probe", "cavity_L2_batched", "blocks_batched", "porous_learned",
-                             "porous_matrix_free"],
+                             "porous_matrix_free", "porous_afs_matrix_free"],
                     help="cavity_L4: the contract line (default).  The others print their own JSON line: "
                          "pmc_probe (1 GiB copies + 4 mixed solves, for counter runs), cavity_L2_batched "
                          "(320 triangles, 16 frequencies), blocks_batched (16 seeded porous blocks x 24 "
                          "frequencies), porous_learned (27-void block, 40,320 unknowns: warm-start A/B on an "
-                         "AFS frequency sequence), porous_matrix_free (64-void block, 300,516 unknowns)")
+                         "AFS frequency sequence), porous_matrix_free (64-void block, 300,516 unknowns), "
+                         "porous_afs_matrix_free (AFS + matrix-free solves + time synthesis at 300,516 unknowns)")
     ap.add_argument("--precond", type=int, default=0, help="blocks_batched: 0 point, 1 cluster block-Jacobi")
+    ap.add_argument("--afs-ns", type=int, default=64, help="porous_afs_matrix_free: FSM size Ns of the band")
     ap.add_argument("--afs-max", type=int, default=24, help="porous_learned: cap on AFS samples")
     ap.add_argument("--batch", type=int, default=0,
                     help="optimised path: 1 = one frequency at a time, 0 = assembly of the next frequency "
@@ -345,6 +347,77 @@ def run_porous_matrix_free(args, afs, mg, np, torch):
     return res
 
 
+
+def run_porous_afs_matrix_free(args, afs, mg, np, torch):
+    """The whole pipeline at 300,516 unknowns: adaptive frequency sampling from
+    J0 = 8 Chebyshev frequencies (band of Ns = 64: Omega = 0.67 at T = 300,
+    eta = 0.023) driving mixed matrix-free solves (FP32 on-the-fly inner
+    products, FP64 residuals, each new frequency started from the nearest
+    sampled solution), the vector-fitting model's time response at 512 steps
+    (Eq. 6), and the Fourier-series inversion (Eq. 4, FFT) of the same model
+    sampled on the FSM grid as a cross-check.  Prints a line per solve."""
+    mesh = mg.lattice_block(4, 39, 3, 2000, rmax=0.45)
+    t0 = time.perf_counter()
+    P = afs.Problem.from_mesh(mesh)
+    plan_s = time.perf_counter() - t0
+    T, kappa, Ns = 300.0, 3.0, args.afs_ns
+    eta = kappa * np.log(10.0) / T
+    rng = np.random.default_rng(2000)
+    loaded = np.nonzero(np.abs(np.asarray(mesh.bc_shape)).sum(1) > 0)[0]
+    dofs = np.sort(3 * rng.choice(loaded, 6, replace=False) + 2)
+    shape = np.asarray(mesh.bc_shape, np.complex128)
+    base = dict(tol=args.tol, precision=afs.PREC_MIXED, matrix_free=1, restart=100, max_iter=4000, batch=1)
+    solved, log = {}, []
+
+    def response(sv):
+        rows = []
+        for sk in sv:
+            o = afs.SolveOptions(**base)
+            x0 = None
+            if solved:
+                near = min(solved, key=lambda q: abs(q - sk))
+                x0 = solved[near][None]
+                o.warm_start = afs.WARM_USER
+            bc = torch.from_numpy((shape / sk)[None]).cuda()
+            ts = time.perf_counter()
+            out = P.solve(np.array([sk]), bc, o, x0=x0, want_ut=False)
+            torch.cuda.synchronize()
+            st = out["stats"][0]
+            solved[complex(sk)] = out["a"][0].clone()
+            rows.append(out["a"][0].cpu().numpy()[dofs])
+            log.append({"s": [sk.real, sk.imag], "seconds": time.perf_counter() - ts, "inner": st["gemv_count"],
+                        "fp64": st["gemv64_count"], "rel_res_fp64": st["rel_res_fp64"]})
+            print(f"[afs-300k] s={sk.real:.4f}{sk.imag:+.4f}i {log[-1]['seconds']:.1f}s inner={st['iters']} "
+                  f"rel={st['rel_res_fp64']:.1e}", file=sys.stderr, flush=True)
+        return np.array(rows)
+
+    params = afs.afs_params(T, eta, Ns, J0=8, max_Nc=args.afs_max)
+    t0 = time.perf_counter()
+    r = afs.afs_run(response, 4, len(dofs), params)
+    afs_s = time.perf_counter() - t0
+    # time domain: Eq. 6 at 512 steps, and the FSM inversion of the model on its grid
+    t512 = np.arange(512) * T / 512
+    h512 = afs.vf_eval_time(r["poles"], r["residues"], t512)
+    sg = afs.fsm_grid(T, eta, Ns)
+    Hs = afs.vf_eval(r["poles"], r["residues"], sg)
+    h_fsm = afs.fsm_invert(T, eta, Ns, Hs)
+    t_fsm = np.arange(Ns) * T / Ns
+    h_direct = afs.vf_eval_time(r["poles"], r["residues"], t_fsm)
+    half = Ns // 2  # compare away from the period end, where the FSM wraps around
+    fsm_gap = float(np.max(np.abs(h_fsm[:, :half] - h_direct[:, :half])) / np.max(np.abs(h_direct[:, :half])))
+    # the model at the sampled frequencies against the solves
+    fit = afs.vf_eval(r["poles"], r["residues"], r["s"])
+    fit_err = float(np.max(np.abs(fit.T - r["F"])) / np.max(np.abs(r["F"])))
+    return {"workload": f"porous_afs_matrix_free: 64-void block ({mesh.n_tri} elements, {3 * mesh.n_tri} unknowns), "
+                        f"AFS from J0=8, T={T}, eta={eta:.4f}, Ns={Ns} (Omega={np.pi * Ns / T:.3f}), mixed "
+                        f"matrix-free GMRES(100), FP64 true rel. residual <= {args.tol}",
+            "plan_s": plan_s, "afs_seconds": afs_s, "n_solves": r["Nc"], "fsm_solves_avoided": Ns // 2 + 1 - r["Nc"],
+            "converged": bool(r["converged"]), "model_order": len(r["poles"]),
+            "E1": [float(x) for x in r["E1"][-3:]], "E2": [float(x) for x in r["E2"][-3:]],
+            "model_vs_samples_max_rel": fit_err, "fsm_vs_eq6_max_rel": fsm_gap,
+            "time_response_512_peak": float(np.max(np.abs(h512))), "solves": log}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -363,7 +436,8 @@ def main():
               "cavity_L2_batched": lambda: run_cavity_L2_batched(args, afs, mg, np, torch),
               "blocks_batched": lambda: run_blocks_batched(args, afs, mg, np, torch),
               "porous_learned": lambda: run_porous_learned(args, afs, mg, np, torch),
-              "porous_matrix_free": lambda: run_porous_matrix_free(args, afs, mg, np, torch)}[args.workload]
+              "porous_matrix_free": lambda: run_porous_matrix_free(args, afs, mg, np, torch),
+              "porous_afs_matrix_free": lambda: run_porous_afs_matrix_free(args, afs, mg, np, torch)}[args.workload]
         print(json.dumps(fn()), flush=True)
         return
     mesh = mg.cavity(args.level)
