@@ -161,7 +161,10 @@ enum { AFSBEM_PREC_FP64 = 0, AFSBEM_PREC_MIXED = 1 };
  * frequency of a call: d_x0 when given, one [N] vector); USER: d_x0;
  * LEARNED: the warm-start network of the problem (trained on the solutions of
  * all frequencies it has solved so far, across calls) combined with the
- * previous solution.  Every guess x0 is rescaled (or the pair combined) to
+ * previous solution; the network is skipped for 8 frequencies after three
+ * gains below 1.3 over the previous solution alone, and retired for the
+ * problem (no queries, no training: PREV behaviour) after three such closures
+ * with no better gain in between.  Every guess x0 is rescaled (or the pair combined) to
  * minimise ||b - A x0|| before the Krylov solve. */
 /* Failure handling of afsbem_solve_device / afsbem_solve (stats.fallback):
  * a starting guess whose residual is not finite or not below ||b|| is

@@ -35,7 +35,7 @@ static uint64_t splitmix(uint64_t &s) {
 
 LearnState::~LearnState() {
     for (void *q : {(void *)P, (void *)m, (void *)v, (void *)G, (void *)work, (void *)Xtr, (void *)Ttr, (void *)Xb,
-                    (void *)Tb, (void *)Y, (void *)loss, (void *)idx})
+                    (void *)Tb, (void *)Y, (void *)loss, (void *)idx, (void *)ref_dev, (void *)dots, (void *)dot_out})
         if (q)
             (void)hipFree(q);
     if (idx_host)
@@ -56,6 +56,10 @@ void LearnState::init(const Problem &p) {
     Y = (float *)learn_alloc((size_t)nt * kLearnOut * 4);
     loss = (float *)learn_alloc(16);
     idx = (int32_t *)learn_alloc((size_t)steps_per_sample * batch * 4);
+    ref_dev = (double *)learn_alloc((size_t)nt * 3 * 16);
+    dots = (double *)learn_alloc(mdot_scratch_bytes(3 * nt, 1));
+    AFS_HIP(hipMemset(dots, 0, kMdotCounterBytes));  // multi-dot arrival counters
+    dot_out = (double *)learn_alloc(64);
     AFS_HIP(hipHostMalloc((void **)&idx_host, (size_t)steps_per_sample * batch * 4, hipHostMallocDefault));
     // uniform(-1/sqrt(fan_in), 1/sqrt(fan_in)) weights and biases
     std::vector<float> hp(np);
@@ -92,19 +96,21 @@ void LearnState::features(const Problem &p, double sr, double si, float *X, hipS
 
 void LearnState::add_solution(const Problem &p, double sr, double si, const double *a, hipStream_t st) {
     const int64_t N = 3 * nt;
-    std::vector<double> h(2 * N);
-    AFS_HIP(hipMemcpyAsync(h.data(), a, (size_t)N * 16, hipMemcpyDeviceToHost, st));
+    // ||a||^2 and <a, a_ref> on the device; only the two numbers come back
+    const bool first = ref_norm == 0.0;
+    if (first)
+        AFS_HIP(hipMemcpyAsync(ref_dev, a, (size_t)N * 16, hipMemcpyDeviceToDevice, st));
+    vec_mdot(N, 1, a, N, a, dots, dot_out, st);
+    vec_mdot(N, 1, ref_dev, N, a, dots, dot_out + 2, st);
+    double hd[4];
+    AFS_HIP(hipMemcpyAsync(hd, dot_out, 32, hipMemcpyDeviceToHost, st));
     AFS_HIP(hipStreamSynchronize(st));
-    double nrm2 = 0.0;
-    for (int64_t k = 0; k < 2 * N; ++k)
-        nrm2 += h[k] * h[k];
+    const double nrm2 = hd[0];
     if (!(nrm2 > 0.0) || !std::isfinite(nrm2))
-        return;  // nothing to learn from
-    if (ref.empty())
-        ref = h;
-    std::complex<double> dot = 0.0;  // <a, a_ref>
-    for (int64_t k = 0; k < N; ++k)
-        dot += std::complex<double>(h[2 * k], h[2 * k + 1]) * std::complex<double>(ref[2 * k], -ref[2 * k + 1]);
+        return;  // nothing to learn from (a first reference is taken again next time)
+    if (first)
+        ref_norm = std::sqrt(nrm2);
+    const std::complex<double> dot(hd[2], hd[3]);  // sum a conj(a_ref)
     const std::complex<double> ph = std::abs(dot) > 0 ? dot / std::abs(dot) : std::complex<double>(1.0, 0.0);
     const std::complex<double> c = ph * std::sqrt(nrm2 / (double)nt);
     if (rows + nt > cap) {

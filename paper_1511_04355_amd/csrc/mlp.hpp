@@ -45,15 +45,21 @@ struct LearnState {
     int steps_per_sample = 24;
     double box[4] = {0, 0, 0, 1};
     double s_scale = 1.0;
-    double ref_norm = 0.0;
-    std::vector<double> ref;  // reference solution (host) fixing the phase of the targets
+    double ref_norm = 0.0;    // norm of the reference solution (ref_dev) fixing the phase of the targets
     uint64_t rng = 0x9e3779b97f4a7c15ull;
     // Gate on the network query: the gain of the prediction is the factor by
     // which it lowers the starting residual of the previous solution alone;
     // after three consecutive gains below 1.3 the network is not queried for
-    // the next 8 frequencies (training continues), then probed again.
-    int low_gains = 0, skip = 0;
+    // the next 8 frequencies (training continues), then probed again.  After
+    // kRetireAfter such closures with no gain >= 1.3 in between, the network
+    // is retired for this problem: no more queries, samples or training (its
+    // cost would exceed its gain on the problem's frequencies).
+    static constexpr int kRetireAfter = 3;
+    int low_gains = 0, skip = 0, closures = 0;
+    bool retired = false;
     bool query_now() {
+        if (retired)
+            return false;
         if (skip > 0) {
             --skip;
             return false;
@@ -61,12 +67,20 @@ struct LearnState {
         return true;
     }
     void record_gain(double g) {
-        low_gains = (g < 1.3) ? low_gains + 1 : 0;
-        if (low_gains >= 3) {
+        if (g >= 1.3) {
+            low_gains = 0;
+            closures = 0;
+            return;
+        }
+        if (++low_gains >= 3) {
             skip = 8;
             low_gains = 0;
+            if (++closures >= kRetireAfter)
+                retired = true;
         }
     }
+    // device scratch for the target scale (two dots of N complex entries)
+    double *ref_dev = nullptr, *dots = nullptr, *dot_out = nullptr;
     ~LearnState();
     void init(const Problem &p);
     void features(const Problem &p, double sr, double si, float *X, hipStream_t st);

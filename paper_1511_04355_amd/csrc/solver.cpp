@@ -565,7 +565,7 @@ static int krylov_phase(Problem &p, Workspace &ws, const afsbem_solve_opts &o, i
         vec_split_ut(nt, p.dev.kind, ws.x, d_bc, d_u, d_t, st);
     if (learned && x_net && x_prev)
         p.learn->record_gain(net_gain);
-    if (learned && std::isfinite(relres)) {
+    if (learned && !p.learn->retired && std::isfinite(relres)) {
         p.learn->add_solution(p, s_re, s_im, ws.x, st);
         p.learn->train(o.learn_steps > 0 ? o.learn_steps : p.learn->steps_per_sample, st);
     }
