@@ -367,6 +367,18 @@ typedef struct afsbem_afs_result afsbem_afs_result;
  * Returns 0 on success. */
 typedef int (*afsbem_response_fn)(int32_t n_s, const double *s, int32_t Kt, double *f_out, void *user);
 
+/* All-DOF time synthesis: the time responses (Eq. 6) of every unknown from
+ * its samples, with the common poles of a vector-fitting model.  For each n
+ * the residues with these poles are identified by least squares from the
+ * samples X[j][n] at s_j (as in Section 2.3, real-coefficient basis), and
+ * h[n][k] = sum_m r_nm e^{a_m t_k} (real part).  Computed as one FP64
+ * matrix-core contraction over 2 J terms per output.
+ * poles [M], s [J] (complex, host); d_X [J][N] complex<double> (device);
+ * t [Nt] (host); d_h [N][Nt] double (device, written).  Needs the number of
+ * real basis functions (M, counting a conjugate pair as two) <= 2 J. */
+int afsbem_time_synthesis_device(int32_t M, const double *poles, int32_t J, const double *s, int64_t N,
+                                 const void *d_X, int32_t Nt, const double *t, void *d_h, void *hip_stream);
+
 /* Defaults: alpha_H 2.0, alpha_L 2.3, E1_bar 1e-4, E2_bar 2e-3, Jc 3, J0 16
  * (Section 3.4), grid_pts 2048, n_iter 10, max_Nc 0; T, eta, Ns placeholders. */
 int afsbem_afs_params_default(afsbem_afs_params *p);

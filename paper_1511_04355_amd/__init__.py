@@ -31,5 +31,6 @@ from ._lib import (  # noqa: F401
     vf_eval,
     vf_eval_time,
     afs_params,
+    time_synthesis,
     afs_run,
 )

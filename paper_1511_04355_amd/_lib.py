@@ -113,6 +113,7 @@ def lib():
         L.afsbem_afs_result_get.argtypes = [P, P, P, P, P, P, P]
         L.afsbem_afs_result_destroy.argtypes = [P]
         L.afsbem_afs_result_work.argtypes = [P, P]
+        L.afsbem_time_synthesis_device.argtypes = [i32, P, i32, P, i64, P, i32, P, P, P]
         _lib = L
     return _lib
 
@@ -439,6 +440,21 @@ def vf_eval_time(poles, res, t):
     _check(lib().afsbem_vf_eval_time(poles.shape[0], poles.ctypes.data, res.shape[0], res.ctypes.data, t.shape[0],
                                      t.ctypes.data, out.ctypes.data))
     return out
+
+
+def time_synthesis(poles, s, X, t):
+    """Time responses h [N, Nt] (float64 cuda) of every column of X [J, N]
+    (complex128 cuda samples at s) with the given common poles."""
+    import torch
+    poles, s = _c128(poles), _c128(s)
+    t = np.ascontiguousarray(t, np.float64)
+    X = X.contiguous()
+    assert X.dtype == torch.complex128 and X.is_cuda and X.shape[0] == s.shape[0]
+    N = X.shape[1]
+    h = torch.empty((N, t.shape[0]), dtype=torch.float64, device="cuda")
+    _check(lib().afsbem_time_synthesis_device(poles.shape[0], poles.ctypes.data, s.shape[0], s.ctypes.data, N,
+                                              _ptr(X), t.shape[0], t.ctypes.data, _ptr(h), _stream()))
+    return h
 
 
 def afs_params(T, eta, Ns, **kw):

@@ -537,6 +537,53 @@ static double vf_time1(const VfModel &m, int64_t k, double t) {
     return acc.real();
 }
 
+// ====================================================== all-DOF synthesis
+// K [Kpad][Nt] with h(t) = sum_i B_i K[i][t] for any function sampled as
+// F_j at s_j (B = [Re F; Im F]): its residues with the given poles are the
+// least-squares coefficients x = A^+ B of the real-coefficient basis (as in
+// residue identification, Section 2.3), and the basis functions' time
+// responses (Eq. 6) are 2 Re e^{a t} and -2 Im e^{a t} for a conjugate pair,
+// e^{a t} for a real pole, so K[i][t] = sum_c A^+[c][i] phi_c(t).
+static std::vector<double> synthesis_matrix(const std::vector<cplx> &s, const std::vector<cplx> &poles,
+                                            const double *t, int Nt, int Kpad) {
+    const int J = (int)s.size();
+    const PoleSet ps = group_poles(poles);
+    const int M = ps.dim();
+    const std::vector<cplx> Phi = basis_values(s, ps);
+    std::vector<double> A((size_t)2 * J * M), I((size_t)2 * J * 2 * J, 0.0), X;
+    for (int c = 0; c < M; ++c)
+        for (int j = 0; j < J; ++j) {
+            A[(size_t)c * 2 * J + j] = Phi[(size_t)c * J + j].real();
+            A[(size_t)c * 2 * J + J + j] = Phi[(size_t)c * J + j].imag();
+        }
+    for (int i = 0; i < 2 * J; ++i)
+        I[(size_t)i * 2 * J + i] = 1.0;
+    lstsq(2 * J, M, A, 2 * J, I, X);  // X[i][c] = A^+[c][i]
+    std::vector<double> phi((size_t)M * Nt);
+    int c = 0;
+    for (size_t q = 0; q < ps.rep.size(); ++q) {
+        const cplx a = ps.rep[q];
+        for (int n = 0; n < Nt; ++n) {
+            const cplx e = std::exp(a * t[n]);
+            if (ps.pair[q]) {
+                phi[(size_t)c * Nt + n] = 2.0 * e.real();
+                phi[(size_t)(c + 1) * Nt + n] = -2.0 * e.imag();
+            } else {
+                phi[(size_t)c * Nt + n] = e.real();
+            }
+        }
+        c += ps.pair[q] ? 2 : 1;
+    }
+    std::vector<double> K((size_t)Kpad * Nt, 0.0);
+    for (int i = 0; i < 2 * J; ++i)
+        for (int cc = 0; cc < M; ++cc) {
+            const double w = X[(size_t)i * M + cc];
+            for (int n = 0; n < Nt; ++n)
+                K[(size_t)i * Nt + n] += w * phi[(size_t)cc * Nt + n];
+        }
+    return K;
+}
+
 // =================================================================== AFS
 struct AfsResult {
     std::vector<cplx> s;           // samples
@@ -897,6 +944,33 @@ int afsbem_vf_eval_time(int32_t M, const double *poles, int64_t n_fun, const dou
                 f_out[(size_t)k * n_t + i] = acc.real();
             }
         return AFSBEM_OK;
+    });
+}
+
+int afsbem_time_synthesis_device(int32_t M, const double *poles, int32_t J, const double *s, int64_t N,
+                                 const void *d_X, int32_t Nt, const double *t, void *d_h, void *hip_stream) {
+    return guarded_d([&] {
+        AFS_REQUIRE(M >= 1 && J >= 1 && N >= 0 && Nt >= 0, AFSBEM_EINVAL, "bad sizes");
+        AFS_REQUIRE(poles && s && (N == 0 || d_X) && (Nt == 0 || t) && (N == 0 || Nt == 0 || d_h), AFSBEM_EINVAL,
+                    "null pointer argument");
+        if (N == 0 || Nt == 0)
+            return (int)AFSBEM_OK;
+        std::vector<cplx> sv(J), pv(M);
+        for (int j = 0; j < J; ++j)
+            sv[j] = cplx(s[2 * j], s[2 * j + 1]);
+        for (int m = 0; m < M; ++m)
+            pv[m] = cplx(poles[2 * m], poles[2 * m + 1]);
+        AFS_REQUIRE(group_poles(pv).dim() <= 2 * J, AFSBEM_EINVAL, "more poles than real samples (2 J)");
+        const int Kpad = (2 * J + 3) / 4 * 4;
+        const std::vector<double> K = synthesis_matrix(sv, pv, t, Nt, Kpad);
+        hipStream_t st = static_cast<hipStream_t>(hip_stream);
+        double *dK = nullptr;
+        AFS_HIP(hipMallocAsync((void **)&dK, K.size() * 8, st));
+        AFS_HIP(hipMemcpyAsync(dK, K.data(), K.size() * 8, hipMemcpyHostToDevice, st));
+        launch_synthesis(N, J, Kpad, Nt, static_cast<const double *>(d_X), dK, static_cast<double *>(d_h), st);
+        AFS_HIP(hipFreeAsync(dK, st));
+        AFS_HIP(hipStreamSynchronize(st));  // K lives on this host frame until the copy has run
+        return (int)AFSBEM_OK;
     });
 }
 

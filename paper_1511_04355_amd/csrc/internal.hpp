@@ -193,6 +193,10 @@ void vec_axpy_conj(int64_t N, double ar, double ai, double br, double bi, const 
 // x += sum_i y[i] V_i  (y on device, complex)
 void vec_combine(int64_t N, int nv, const double *V, int64_t ldv, const double *y, double *x,
                  hipStream_t st);
+// h[n][t] = sum_i B[n][i] Km[i][t] with B[n][i] = Re X[i][n] (i < J), Im X[i-J][n];
+// X [J][N] complex, Km [Kpad][Nt] (Kpad = 2J rounded up to 4, zero rows), h [N][Nt]
+void launch_synthesis(int64_t N, int J, int Kpad, int Nt, const double *X, const double *Km, double *h,
+                      hipStream_t st);
 // scatter solution a into u, t by element kind
 void vec_split_ut(int64_t n_tri, const int8_t *kind, const double *a, const double *bc, double *u,
                   double *t, hipStream_t st);
