@@ -374,8 +374,10 @@ typedef int (*afsbem_response_fn)(int32_t n_s, const double *s, int32_t Kt, doub
  * h[n][k] = sum_m r_nm e^{a_m t_k} (real part).  Computed as one FP64
  * matrix-core contraction over 2 J terms per output.
  * poles [M], s [J] (complex, host); d_X [J][N] complex<double> (device);
- * t [Nt] (host); d_h [N][Nt] double (device, written).  Needs the number of
- * real basis functions (M, counting a conjugate pair as two) <= 2 J. */
+ * t [Nt] (host); d_h [N][Nt] double (device, written); d_X 16-byte and d_h
+ * 8-byte aligned.  Needs the number of real basis functions (M, counting a
+ * conjugate pair as two) <= 2 J.  Synchronises the stream; AFSBEM_EINVAL on
+ * bad sizes, null pointers, alignment or too many poles. */
 int afsbem_time_synthesis_device(int32_t M, const double *poles, int32_t J, const double *s, int64_t N,
                                  const void *d_X, int32_t Nt, const double *t, void *d_h, void *hip_stream);
 

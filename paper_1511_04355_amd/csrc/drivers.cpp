@@ -955,6 +955,8 @@ int afsbem_time_synthesis_device(int32_t M, const double *poles, int32_t J, cons
                     "null pointer argument");
         if (N == 0 || Nt == 0)
             return (int)AFSBEM_OK;
+        AFS_REQUIRE((reinterpret_cast<uintptr_t>(d_X) & 15) == 0 && (reinterpret_cast<uintptr_t>(d_h) & 7) == 0,
+                    AFSBEM_EINVAL, "d_X must be 16-byte aligned and d_h 8-byte aligned");
         std::vector<cplx> sv(J), pv(M);
         for (int j = 0; j < J; ++j)
             sv[j] = cplx(s[2 * j], s[2 * j + 1]);

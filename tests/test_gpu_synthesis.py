@@ -50,6 +50,26 @@ def test_synthesis_matches_oracle(real_pole, N, Nt):
     assert np.max(np.abs(h - ho)) <= 1e-10 * np.max(np.abs(ho))
 
 
+@pytest.mark.parametrize("J,n_pairs,real_pole,N,Nt", [(1, 0, True, 333, 77), (7, 3, False, 333, 77),
+                                                      (64, 5, True, 333, 77), (65, 5, False, 333, 77),
+                                                      (24, 5, False, 1, 300)])
+def test_synthesis_sample_counts(J, n_pairs, real_pole, N, Nt):
+    """One sample (one matrix-core pair step), a ragged pair (J = 7), the most
+    samples of the register-resident path (J = 64), the general path beyond it
+    (J = 65), and a single unknown; ragged N and Nt throughout."""
+    import paper_1511_04355_amd as afs
+    from oracle import vf
+    rng = np.random.default_rng(J * 1000 + N)
+    poles = _poles(n_pairs, real_pole)
+    s = 0.05 + 1j * np.linspace(0.0, 3.5, J)
+    X = rng.standard_normal((J, N)) + 1j * rng.standard_normal((J, N))
+    t = np.linspace(0.0, 40.0, Nt)
+    h = afs.time_synthesis(poles, s, torch.from_numpy(X).cuda(), t).cpu().numpy()
+    po, res = vf.identify_residues(s, X.T, poles)
+    ho = vf.time_response(t, po, res)
+    assert np.max(np.abs(h - ho)) <= 1e-10 * np.max(np.abs(ho))
+
+
 def test_synthesis_exact_for_rational_samples():
     """Samples of sum_m r_nm / (s - a_m) with conjugate-symmetric residues:
     the synthesis returns the exact inverse transform sum_m r_nm e^{a_m t}."""
