@@ -381,6 +381,30 @@ typedef int (*afsbem_response_fn)(int32_t n_s, const double *s, int32_t Kt, doub
 int afsbem_time_synthesis_device(int32_t M, const double *poles, int32_t J, const double *s, int64_t N,
                                  const void *d_X, int32_t Nt, const double *t, void *d_h, void *hip_stream);
 
+/* The same per-unknown models (residues identified from the samples X[j][n]
+ * at s_j with the common poles, Section 2.3) evaluated at n_z complex
+ * frequencies z (Eq. 5): H[n][k] = sum_m r_nm / (z_k - a_m).  The same FP64
+ * matrix-core contraction, with the basis functions' values at z_k in place of
+ * their time responses.  poles [M], s [J], z [n_z] (complex, host); d_X [J][N]
+ * complex<double> (device, 16-byte aligned); d_H [N][n_z] complex<double>
+ * (device, written).  Synchronises the stream; AFSBEM_EINVAL on bad sizes,
+ * null pointers, alignment or too many poles.  With z = the FSM grid this
+ * feeds afsbem_fsm_invert_device (the model's Fourier-series inversion for
+ * every unknown). */
+int afsbem_model_sample_device(int32_t M, const double *poles, int32_t J, const double *s, int64_t N,
+                               const void *d_X, int32_t n_z, const double *z, void *d_H, void *hip_stream);
+
+/* Fourier-series inversion (Section 2.2, Eq. 4 with its 1/P factor) of n_sig
+ * signals at once on the GPU; the definition of afsbem_fsm_invert (trapezoid
+ * end points at +-Omega with half weight, optional Hann window), computed by a
+ * batched FFT.  d_H [n_sig][Ns/2+1] complex<double> (device, 16-byte aligned):
+ * the samples at s_k = eta + 2 pi i k / P; d_h [n_sig][Ns] double (device,
+ * written): h(t_n), t_n = n P / Ns.  Ns a power of two in [2, 4096].
+ * Synchronises the stream; AFSBEM_EINVAL on bad sizes, null pointers or
+ * alignment. */
+int afsbem_fsm_invert_device(double P, double eta, int32_t Ns, int window, int64_t n_sig, const void *d_H,
+                             void *d_h, void *hip_stream);
+
 /* Defaults: alpha_H 2.0, alpha_L 2.3, E1_bar 1e-4, E2_bar 2e-3, Jc 3, J0 16
  * (Section 3.4), grid_pts 2048, n_iter 10, max_Nc 0; T, eta, Ns placeholders. */
 int afsbem_afs_params_default(afsbem_afs_params *p);

@@ -32,5 +32,7 @@ from ._lib import (  # noqa: F401
     vf_eval_time,
     afs_params,
     time_synthesis,
+    model_sample,
+    fsm_invert_device,
     afs_run,
 )

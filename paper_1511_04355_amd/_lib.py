@@ -114,6 +114,8 @@ def lib():
         L.afsbem_afs_result_destroy.argtypes = [P]
         L.afsbem_afs_result_work.argtypes = [P, P]
         L.afsbem_time_synthesis_device.argtypes = [i32, P, i32, P, i64, P, i32, P, P, P]
+        L.afsbem_model_sample_device.argtypes = [i32, P, i32, P, i64, P, i32, P, P, P]
+        L.afsbem_fsm_invert_device.argtypes = [d, d, i32, ctypes.c_int, i64, P, P, P]
         _lib = L
     return _lib
 
@@ -454,6 +456,33 @@ def time_synthesis(poles, s, X, t):
     h = torch.empty((N, t.shape[0]), dtype=torch.float64, device="cuda")
     _check(lib().afsbem_time_synthesis_device(poles.shape[0], poles.ctypes.data, s.shape[0], s.ctypes.data, N,
                                               _ptr(X), t.shape[0], t.ctypes.data, _ptr(h), _stream()))
+    return h
+
+
+def model_sample(poles, s, X, z):
+    """Values H [N, n_z] (complex128 cuda) at the complex frequencies z of the
+    model of every column of X [J, N] (complex128 cuda samples at s) with the
+    given common poles."""
+    import torch
+    poles, s, z = _c128(poles), _c128(s), _c128(z)
+    X = X.contiguous()
+    assert X.dtype == torch.complex128 and X.is_cuda and X.shape[0] == s.shape[0]
+    N = X.shape[1]
+    H = torch.empty((N, z.shape[0]), dtype=torch.complex128, device="cuda")
+    _check(lib().afsbem_model_sample_device(poles.shape[0], poles.ctypes.data, s.shape[0], s.ctypes.data, N,
+                                            _ptr(X), z.shape[0], z.ctypes.data, _ptr(H), _stream()))
+    return H
+
+
+def fsm_invert_device(P, eta, Ns, H, window=False):
+    """H: [n_sig, Ns/2+1] complex128 cuda -> h: [n_sig, Ns] float64 cuda at
+    t_n = n P / Ns (the same inversion as fsm_invert, on the GPU)."""
+    import torch
+    H = H.contiguous()
+    assert H.dtype == torch.complex128 and H.is_cuda and H.dim() == 2 and H.shape[1] == Ns // 2 + 1
+    h = torch.empty((H.shape[0], Ns), dtype=torch.float64, device="cuda")
+    _check(lib().afsbem_fsm_invert_device(float(P), float(eta), int(Ns), int(bool(window)), H.shape[0], _ptr(H),
+                                          _ptr(h), _stream()))
     return h
 
 

@@ -538,16 +538,14 @@ static double vf_time1(const VfModel &m, int64_t k, double t) {
 }
 
 // ====================================================== all-DOF synthesis
-// K [Kpad][Nt] with h(t) = sum_i B_i K[i][t] for any function sampled as
-// F_j at s_j (B = [Re F; Im F]): its residues with the given poles are the
-// least-squares coefficients x = A^+ B of the real-coefficient basis (as in
-// residue identification, Section 2.3), and the basis functions' time
-// responses (Eq. 6) are 2 Re e^{a t} and -2 Im e^{a t} for a conjugate pair,
-// e^{a t} for a real pole, so K[i][t] = sum_c A^+[c][i] phi_c(t).
-static std::vector<double> synthesis_matrix(const std::vector<cplx> &s, const std::vector<cplx> &poles,
-                                            const double *t, int Nt, int Kpad) {
+// For any function sampled as F_j at s_j (B = [Re F; Im F], 2J reals), its
+// residues with the given poles are the least-squares coefficients x = A^+ B
+// of the real-coefficient basis (as in residue identification, Section 2.3).
+// Any linear functional of the model -- its time response at t (Eq. 6), its
+// value at a complex frequency z -- is then sum_c x_c phi_c = sum_i B_i K_i
+// with K_i = sum_c A^+[c][i] phi_c.  synthesis_pinv returns A^+ as X[i][c].
+static std::vector<double> synthesis_pinv(const std::vector<cplx> &s, const PoleSet &ps) {
     const int J = (int)s.size();
-    const PoleSet ps = group_poles(poles);
     const int M = ps.dim();
     const std::vector<cplx> Phi = basis_values(s, ps);
     std::vector<double> A((size_t)2 * J * M), I((size_t)2 * J * 2 * J, 0.0), X;
@@ -559,6 +557,29 @@ static std::vector<double> synthesis_matrix(const std::vector<cplx> &s, const st
     for (int i = 0; i < 2 * J; ++i)
         I[(size_t)i * 2 * J + i] = 1.0;
     lstsq(2 * J, M, A, 2 * J, I, X);  // X[i][c] = A^+[c][i]
+    return X;
+}
+
+// K [Kpad][ncol]: K[i][n] = sum_c X[i][c] phi[c][n] (rows 2J..Kpad-1 zero)
+static std::vector<double> synthesis_contract(const std::vector<double> &X, int J, int M,
+                                              const std::vector<double> &phi, int ncol, int Kpad) {
+    std::vector<double> K((size_t)Kpad * ncol, 0.0);
+    for (int i = 0; i < 2 * J; ++i)
+        for (int cc = 0; cc < M; ++cc) {
+            const double w = X[(size_t)i * M + cc];
+            for (int n = 0; n < ncol; ++n)
+                K[(size_t)i * ncol + n] += w * phi[(size_t)cc * ncol + n];
+        }
+    return K;
+}
+
+// Time responses of the basis functions (Eq. 6): 2 Re e^{a t} and -2 Im e^{a t}
+// for a conjugate pair, e^{a t} for a real pole.
+static std::vector<double> synthesis_matrix(const std::vector<cplx> &s, const std::vector<cplx> &poles,
+                                            const double *t, int Nt, int Kpad) {
+    const PoleSet ps = group_poles(poles);
+    const int M = ps.dim();
+    const std::vector<double> X = synthesis_pinv(s, ps);
     std::vector<double> phi((size_t)M * Nt);
     int c = 0;
     for (size_t q = 0; q < ps.rep.size(); ++q) {
@@ -574,14 +595,31 @@ static std::vector<double> synthesis_matrix(const std::vector<cplx> &s, const st
         }
         c += ps.pair[q] ? 2 : 1;
     }
-    std::vector<double> K((size_t)Kpad * Nt, 0.0);
-    for (int i = 0; i < 2 * J; ++i)
-        for (int cc = 0; cc < M; ++cc) {
-            const double w = X[(size_t)i * M + cc];
-            for (int n = 0; n < Nt; ++n)
-                K[(size_t)i * Nt + n] += w * phi[(size_t)cc * Nt + n];
+    return synthesis_contract(X, (int)s.size(), M, phi, Nt, Kpad);
+}
+
+// Values of the basis functions at complex frequencies z (Eq. 5), as
+// interleaved (Re, Im) columns: K [Kpad][2 n_z].
+static std::vector<double> sampling_matrix(const std::vector<cplx> &s, const std::vector<cplx> &poles,
+                                           const std::vector<cplx> &z, int Kpad) {
+    const PoleSet ps = group_poles(poles);
+    const int M = ps.dim(), nz = (int)z.size();
+    const std::vector<double> X = synthesis_pinv(s, ps);
+    const std::vector<cplx> Pz = basis_values(z, ps);  // [M][nz]
+    std::vector<double> phi((size_t)M * 2 * nz);
+    for (int c = 0; c < M; ++c)
+        for (int k = 0; k < nz; ++k) {
+            phi[(size_t)c * 2 * nz + 2 * k] = Pz[(size_t)c * nz + k].real();
+            phi[(size_t)c * 2 * nz + 2 * k + 1] = Pz[(size_t)c * nz + k].imag();
         }
-    return K;
+    return synthesis_contract(X, (int)s.size(), M, phi, 2 * nz, Kpad);
+}
+
+// e^{2 pi i m / N}, angle formed and evaluated in extended precision
+static cplx unit_root(int64_t m, int64_t N) {
+    const long double pi_l = 3.14159265358979323846264338327950288L;
+    const long double a = 2.0L * pi_l * (long double)m / (long double)N;
+    return cplx((double)std::cos(a), (double)std::sin(a));
 }
 
 // =================================================================== AFS
@@ -972,6 +1010,73 @@ int afsbem_time_synthesis_device(int32_t M, const double *poles, int32_t J, cons
         launch_synthesis(N, J, Kpad, Nt, static_cast<const double *>(d_X), dK, static_cast<double *>(d_h), st);
         AFS_HIP(hipFreeAsync(dK, st));
         AFS_HIP(hipStreamSynchronize(st));  // K lives on this host frame until the copy has run
+        return (int)AFSBEM_OK;
+    });
+}
+
+int afsbem_model_sample_device(int32_t M, const double *poles, int32_t J, const double *s, int64_t N,
+                               const void *d_X, int32_t n_z, const double *z, void *d_H, void *hip_stream) {
+    return guarded_d([&] {
+        AFS_REQUIRE(M >= 1 && J >= 1 && N >= 0 && n_z >= 0, AFSBEM_EINVAL, "bad sizes");
+        AFS_REQUIRE(poles && s && (N == 0 || d_X) && (n_z == 0 || z) && (N == 0 || n_z == 0 || d_H), AFSBEM_EINVAL,
+                    "null pointer argument");
+        AFS_REQUIRE(n_z <= (1 << 30), AFSBEM_EINVAL, "too many frequencies");
+        if (N == 0 || n_z == 0)
+            return (int)AFSBEM_OK;
+        AFS_REQUIRE((reinterpret_cast<uintptr_t>(d_X) & 15) == 0 && (reinterpret_cast<uintptr_t>(d_H) & 7) == 0,
+                    AFSBEM_EINVAL, "d_X must be 16-byte aligned and d_H 8-byte aligned");
+        std::vector<cplx> sv(J), pv(M), zv(n_z);
+        for (int j = 0; j < J; ++j)
+            sv[j] = cplx(s[2 * j], s[2 * j + 1]);
+        for (int m = 0; m < M; ++m)
+            pv[m] = cplx(poles[2 * m], poles[2 * m + 1]);
+        for (int k = 0; k < n_z; ++k)
+            zv[k] = cplx(z[2 * k], z[2 * k + 1]);
+        AFS_REQUIRE(group_poles(pv).dim() <= 2 * J, AFSBEM_EINVAL, "more poles than real samples (2 J)");
+        const int Kpad = (2 * J + 3) / 4 * 4;
+        const std::vector<double> K = sampling_matrix(sv, pv, zv, Kpad);
+        hipStream_t st = static_cast<hipStream_t>(hip_stream);
+        double *dK = nullptr;
+        AFS_HIP(hipMallocAsync((void **)&dK, K.size() * 8, st));
+        AFS_HIP(hipMemcpyAsync(dK, K.data(), K.size() * 8, hipMemcpyHostToDevice, st));
+        launch_synthesis(N, J, Kpad, 2 * n_z, static_cast<const double *>(d_X), dK, static_cast<double *>(d_H), st);
+        AFS_HIP(hipFreeAsync(dK, st));
+        AFS_HIP(hipStreamSynchronize(st));  // K lives on this host frame until the copy has run
+        return (int)AFSBEM_OK;
+    });
+}
+
+int afsbem_fsm_invert_device(double P, double eta, int32_t Ns, int window, int64_t n_sig, const void *d_H,
+                             void *d_h, void *hip_stream) {
+    return guarded_d([&] {
+        AFS_REQUIRE(P > 0 && std::isfinite(P) && std::isfinite(eta) && n_sig >= 0, AFSBEM_EINVAL,
+                    "fsm_invert_device needs P > 0 and n_sig >= 0");
+        AFS_REQUIRE(Ns >= 2 && Ns <= (1 << kFsmMaxLog2) && (Ns & (Ns - 1)) == 0, AFSBEM_EINVAL,
+                    "fsm_invert_device: Ns must be a power of two in [2, 4096]");
+        AFS_REQUIRE(window == 0 || window == 1, AFSBEM_EINVAL, "window must be 0 (none) or 1 (Hann)");
+        AFS_REQUIRE(n_sig == 0 || (d_H && d_h), AFSBEM_EINVAL, "null pointer argument");
+        if (n_sig == 0)
+            return (int)AFSBEM_OK;
+        AFS_REQUIRE((reinterpret_cast<uintptr_t>(d_H) & 15) == 0 && (reinterpret_cast<uintptr_t>(d_h) & 7) == 0,
+                    AFSBEM_EINVAL, "d_H must be 16-byte aligned and d_h 8-byte aligned");
+        int L = 0;
+        while ((1 << L) < Ns)
+            ++L;
+        // tables: W[m] = e^{2 pi i m / Ns}; E[n] = e^{eta t_n} / P, t_n = n P / Ns
+        std::vector<double> tab((size_t)3 * Ns);
+        for (int m = 0; m < Ns; ++m) {
+            const cplx w = unit_root(m, Ns);
+            tab[2 * m] = w.real();
+            tab[2 * m + 1] = w.imag();
+            tab[(size_t)2 * Ns + m] = std::exp(eta * (m * P / Ns)) / P;
+        }
+        hipStream_t st = static_cast<hipStream_t>(hip_stream);
+        double *dT = nullptr;
+        AFS_HIP(hipMallocAsync((void **)&dT, tab.size() * 8, st));
+        AFS_HIP(hipMemcpyAsync(dT, tab.data(), tab.size() * 8, hipMemcpyHostToDevice, st));
+        launch_fsm(L, n_sig, window, static_cast<const double *>(d_H), dT, dT + 2 * Ns, static_cast<double *>(d_h), st);
+        AFS_HIP(hipFreeAsync(dT, st));
+        AFS_HIP(hipStreamSynchronize(st));  // the tables live on this host frame until the copy has run
         return (int)AFSBEM_OK;
     });
 }

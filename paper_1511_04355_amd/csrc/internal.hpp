@@ -195,6 +195,9 @@ void vec_combine(int64_t N, int nv, const double *V, int64_t ldv, const double *
                  hipStream_t st);
 // h[n][t] = sum_i B[n][i] Km[i][t] with B[n][i] = Re X[i][n] (i < J), Im X[i-J][n];
 // X [J][N] complex, Km [Kpad][Nt] (Kpad = 2J rounded up to 4, zero rows), h [N][Nt]
+constexpr int kFsmMaxLog2 = 12;
+void launch_fsm(int log2_ns, int64_t n_sig, int window, const double *H, const double *W, const double *E, double *h,
+                hipStream_t st);
 void launch_synthesis(int64_t N, int J, int Kpad, int Nt, const double *X, const double *Km, double *h,
                       hipStream_t st);
 // scatter solution a into u, t by element kind
