@@ -7,17 +7,24 @@
 // truncated integral at +-Omega with half weight each); w_k = 1, or the Hann
 // weight (1 + cos(2 pi k / Ns)) / 2.
 //
-// One work-group of 256 threads transforms 256 / TPS signals at once in LDS,
-// TPS = Ns / 8 threads per signal (at most 256), by a Stockham
+// A work-group of 256 threads transforms a group of 256 / TPS signals at a
+// time in LDS, TPS = Ns / 8 threads per signal (at most 256), by a Stockham
 // self-sorting FFT: radix-8 passes, then one radix-2 or radix-4 pass when
 // log2 Ns is not a multiple of 3.  Pass with radix R after a span NS (the
 // product of the earlier radices): butterfly j < Ns / R reads the R values
 // j + r Ns / R, multiplies value r by W^{r (j mod NS) Ns / (NS R)} (W =
 // e^{2 pi i / Ns}), takes their R-point transform and writes value r to
 // (j / NS) NS R + (j mod NS) + r NS.  The data stay in one LDS array (all
-// reads of a pass complete before its writes); the last pass writes the real
-// parts, scaled by e^{eta t_n} / P, straight to HBM.  Twiddles and scale
-// factors come from host-computed tables (read through the caches).
+// reads of a pass complete before its writes), one pad slot per 8 entries
+// against bank conflicts; the last pass writes the real parts, scaled by
+// e^{eta t_n} / P, straight to HBM.  Twiddles and scale factors come from
+// host-computed tables, staged in LDS up to Ns = 1024.  The work-groups are
+// persistent (as many as fit on the device) and load the next group's
+// samples into registers while the current group is transformed; the loop
+// has no divergent branch (clamped loads, the Nyquist sample broadcast to
+// every lane and written by the lane holding k = 0, stores through a buffer
+// descriptor spanning exactly the group's signals, so the hardware drops
+// those of the spare signals of the last group).
 #include <hip/hip_runtime.h>
 
 #include <utility>
@@ -76,9 +83,14 @@ __device__ __forceinline__ void dft_r(double2 *v) {
         dft8(v);
 }
 
+typedef unsigned fsm_v2u_t __attribute__((ext_vector_type(2)));
+
+template <int N>
+__device__ __forceinline__ int fsm_px(int p) { return p + (p >> 3); }  // padded LDS index
+
 template <int N, int TPS, int R, int NS>
-__device__ __forceinline__ void fsm_pass(double2 *X, const double2 *__restrict__ W, int tl, bool live, int64_t sig,
-                                         const double *__restrict__ E, double *__restrict__ h) {
+__device__ __forceinline__ void fsm_pass(double2 *X, const double2 *W, int tl, const double *E,
+                                         __amdgpu_buffer_rsrc_t rs, int obase) {
     constexpr int EPT = N / TPS, NB = EPT / R;
     constexpr bool LAST = NS * R == N;
     double2 v[EPT];
@@ -87,7 +99,7 @@ __device__ __forceinline__ void fsm_pass(double2 *X, const double2 *__restrict__
         const int j = tl + b * TPS;
 #pragma unroll
         for (int r = 0; r < R; ++r)
-            v[b * R + r] = X[j + r * (N / R)];
+            v[b * R + r] = X[fsm_px<N>(j + r * (N / R))];
     }
     if constexpr (!LAST)
         __syncthreads();  // every read of this pass before any write
@@ -105,10 +117,11 @@ __device__ __forceinline__ void fsm_pass(double2 *X, const double2 *__restrict__
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             if constexpr (LAST) {
-                if (live)
-                    __builtin_nontemporal_store(E[d + r * NS] * v[b * R + r].x, h + sig * N + d + r * NS);
+                const double val = E[d + r * NS] * v[b * R + r].x;
+                __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(fsm_v2u_t, val), rs, (obase + d + r * NS) * 8,
+                                                      0, 2 /* nt */);
             } else {
-                X[d + r * NS] = v[b * R + r];
+                X[fsm_px<N>(d + r * NS)] = v[b * R + r];
             }
         }
     }
@@ -117,51 +130,101 @@ __device__ __forceinline__ void fsm_pass(double2 *X, const double2 *__restrict__
 }
 
 template <int N, int TPS, int NS>
-__device__ __forceinline__ void fsm_passes(double2 *X, const double2 *__restrict__ W, int tl, bool live, int64_t sig,
-                                           const double *__restrict__ E, double *__restrict__ h) {
+__device__ __forceinline__ void fsm_passes(double2 *X, const double2 *W, int tl, const double *E,
+                                           __amdgpu_buffer_rsrc_t rs, int obase) {
     if constexpr (NS < N) {
         constexpr int R = N / NS >= 8 ? 8 : N / NS;
-        fsm_pass<N, TPS, R, NS>(X, W, tl, live, sig, E, h);
-        fsm_passes<N, TPS, NS * R>(X, W, tl, live, sig, E, h);
+        fsm_pass<N, TPS, R, NS>(X, W, tl, E, rs, obase);
+        fsm_passes<N, TPS, NS * R>(X, W, tl, E, rs, obase);
     }
 }
 
 template <int L>
-__global__ __launch_bounds__(256) void fsm_kernel(int64_t n_sig, int window, const double2 *__restrict__ H,
-                                                  const double2 *__restrict__ W, const double *__restrict__ E,
-                                                  double *__restrict__ h) {
-    constexpr int N = 1 << L, HALF = N / 2;
-    constexpr int TPS = N / 8 < 1 ? 1 : (N / 8 > 256 ? 256 : N / 8);
-    constexpr int SPB = 256 / TPS;
-    __shared__ double2 buf[SPB * N];
-    const int sl = threadIdx.x / TPS, tl = threadIdx.x % TPS;
-    const int64_t sig = (int64_t)blockIdx.x * SPB + sl;
-    const bool live = sig < n_sig;  // the last block's spare signals transform zeros and store nothing
-    double2 *X = buf + sl * N;
-    for (int k = tl; k <= HALF; k += TPS) {
-        const double2 hk = live ? H[sig * (HALF + 1) + k] : double2{0.0, 0.0};
-        const double w = window ? 0.5 * (1.0 + W[k].x) : 1.0;
-        if (k == HALF) {
-            X[HALF] = double2{w * hk.x, 0.0};
-        } else {
-            X[k] = double2{w * hk.x, w * hk.y};
-            if (k > 0)
-                X[N - k] = double2{w * hk.x, -w * hk.y};
+struct FsmShape {
+    static constexpr int N = 1 << L, HALF = N / 2;
+    static constexpr int TPS = N / 8 < 1 ? 1 : (N / 8 > 256 ? 256 : N / 8);
+    static constexpr int SPB = 256 / TPS;          // signals per group
+    static constexpr int KPT = HALF / TPS;         // samples k < Ns/2 per thread
+    static constexpr int NP = N + (N >> 3);        // padded signal length in LDS
+    static constexpr bool TLDS = N <= 1024;        // tables staged in LDS
+    static_assert(KPT * TPS == HALF, "Ns/2 must be a multiple of the threads per signal");
+};
+
+template <int L>
+__global__ __launch_bounds__(256) void fsm_kernel(int64_t n_sig, int64_t n_groups, int window,
+                                                  const double2 *__restrict__ H, const double2 *__restrict__ Wg,
+                                                  const double *__restrict__ Eg, double *__restrict__ h) {
+    using S = FsmShape<L>;
+    constexpr int N = S::N, HALF = S::HALF, TPS = S::TPS, SPB = S::SPB, KPT = S::KPT, NP = S::NP;
+    __shared__ double2 buf[SPB * NP];
+    __shared__ double2 wl[S::TLDS ? N : 1];
+    __shared__ double el[S::TLDS ? N : 1];
+    const double2 *W = Wg;
+    const double *E = Eg;
+    if constexpr (S::TLDS) {
+        for (int m = threadIdx.x; m < N; m += 256) {
+            wl[m] = Wg[m];
+            el[m] = Eg[m];
         }
+        W = wl;
+        E = el;
     }
-    __syncthreads();
-    fsm_passes<N, TPS, 1>(X, W, tl, live, sig, E, h);
+    const int sl = threadIdx.x / TPS, tl = threadIdx.x % TPS;
+    double2 *X = buf + sl * NP;
+    double2 pre[KPT], preh;
+    auto fetch = [&](int64_t grp) {  // clamped: always KPT + 1 loads
+        const int64_t gc = grp < n_groups ? grp : n_groups - 1;
+        const int64_t sig = gc * SPB + sl;
+        const double2 *row = H + (sig < n_sig ? sig : n_sig - 1) * (HALF + 1);
+#pragma unroll
+        for (int i = 0; i < KPT; ++i)
+            pre[i] = row[tl + i * TPS];
+        preh = row[HALF];
+    };
+    int64_t grp = blockIdx.x;
+    fetch(grp);
+    __syncthreads();  // tables
+    for (; grp < n_groups; grp += gridDim.x) {
+        const bool live = grp * SPB + sl < n_sig;
+        const double wh = window ? 0.5 * (1.0 + W[HALF].x) : 1.0;
+        const double2 nyq = double2{live ? wh * preh.x : 0.0, 0.0};
+#pragma unroll
+        for (int i = 0; i < KPT; ++i) {
+            const int k = tl + i * TPS;
+            const double2 hk = live ? pre[i] : double2{0.0, 0.0};
+            const double w = window ? 0.5 * (1.0 + W[k].x) : 1.0;
+            X[fsm_px<N>(k)] = double2{w * hk.x, w * hk.y};
+            const bool mirror = k > 0;  // k = 0 has no mirror: that lane writes the Nyquist entry
+            X[fsm_px<N>(mirror ? N - k : HALF)] = mirror ? double2{w * hk.x, -w * hk.y} : nyq;
+        }
+        __syncthreads();
+        fetch(grp + gridDim.x);
+        const int64_t s0 = grp * SPB;
+        const int64_t ns = n_sig - s0 < SPB ? n_sig - s0 : SPB;
+        const __amdgpu_buffer_rsrc_t rs =
+            __builtin_amdgcn_make_buffer_rsrc(h + s0 * N, 0, (int)(ns * N * 8), 0x00020000);
+        fsm_passes<N, TPS, 1>(X, W, tl, E, rs, sl * N);
+        __syncthreads();  // the last pass's reads of X before the next group's writes
+    }
 }
 
 template <int L>
 static void fsm_launch_l(int64_t n_sig, int window, const double *H, const double *W, const double *E, double *h,
                          hipStream_t st) {
-    constexpr int N = 1 << L;
-    constexpr int TPS = N / 8 < 1 ? 1 : (N / 8 > 256 ? 256 : N / 8);
-    constexpr int SPB = 256 / TPS;
-    const int64_t blocks = (n_sig + SPB - 1) / SPB;
-    fsm_kernel<L><<<(unsigned)blocks, 256, 0, st>>>(n_sig, window, reinterpret_cast<const double2 *>(H),
-                                                    reinterpret_cast<const double2 *>(W), E, h);
+    using S = FsmShape<L>;
+    const int64_t n_groups = (n_sig + S::SPB - 1) / S::SPB;
+    static int resident = 0;  // work-groups that fit on the device at once (per instantiation)
+    if (resident == 0) {
+        int dev = 0, per_cu = 0;
+        hipDeviceProp_t prop;
+        AFS_HIP(hipGetDevice(&dev));
+        AFS_HIP(hipGetDeviceProperties(&prop, dev));
+        AFS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fsm_kernel<L>, 256, 0));
+        resident = (per_cu > 0 ? per_cu : 1) * prop.multiProcessorCount;
+    }
+    const int64_t grid = n_groups < resident ? n_groups : resident;
+    fsm_kernel<L><<<(unsigned)grid, 256, 0, st>>>(n_sig, n_groups, window, reinterpret_cast<const double2 *>(H),
+                                                  reinterpret_cast<const double2 *>(W), E, h);
 }
 
 template <int... Ls>
