@@ -351,12 +351,17 @@ int afsbem_vf_eval_time(int32_t M, const double *poles, int64_t n_fun, const dou
  * printed formula lacks the pi), fitting orders floor(J/alpha_H), floor(J/alpha_L),
  * thresholds E1_bar, E2_bar, Jc validation steps, max_Nc cap (0 = Ns/2 + 1),
  * grid_pts points of the uniform grid on which maxima over [0, Omega] are
- * taken, n_iter pole-identification passes per fit. */
+ * taken, n_iter pole-identification passes per fit.  q (default 1, the
+ * paper's rule) new frequencies per analysis step, requested from the response
+ * in one call (one batched solve): the largest discrepancy as in Section 3.2,
+ * then the next largest local maxima of the same discrepancy at least dw/4
+ * from every sample and every earlier pick (fewer when none is left). */
 typedef struct {
     double T, eta;
     int32_t Ns, J0;
     double alpha_H, alpha_L, E1_bar, E2_bar;
     int32_t Jc, max_Nc, grid_pts, n_iter;
+    int32_t q;
 } afsbem_afs_params;
 
 typedef struct afsbem_afs_result afsbem_afs_result;

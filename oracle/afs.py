@@ -18,7 +18,12 @@ Readings of the paper used here:
    Simpson on 4 Ns + 1 points;
  * convergence (Eq. 14): E1 < E1_bar and E2 < E2_bar, then Jc further steps
    that must all pass, otherwise sampling resumes (stage 3 of the Algorithm);
- * safety cap: at most Ns/2 + 1 samples (the cost of the FSM).
+ * safety cap: at most Ns/2 + 1 samples (the cost of the FSM);
+ * multi-point steps (q new frequencies per analysis, an extension the paper
+   does not make: it inserts one): the first is the argmax above; each further
+   one is the next largest local maximum of the same masked discrepancy that
+   lies at least dw/4 from every sample and every earlier pick; fewer than q
+   when no such maximum is left.  q = 1 is the paper's rule.
 """
 from __future__ import annotations
 
@@ -42,6 +47,38 @@ def simpson(y, t):
     return h / 3 * (y[..., 0] + y[..., -1] + 4 * y[..., 1:-1:2].sum(-1) + 2 * y[..., 2:-1:2].sum(-1))
 
 
+def select_new(d, wgrid, taken_w, dw, q):
+    """Indices into wgrid of up to q new frequencies from the discrepancy d on
+    the grid: grid points within dw/4 of a sampled frequency (taken_w) are
+    excluded; the first pick is the largest remaining value (smallest w on
+    ties), then the remaining local maxima (d[i] > d[i-1], d[i] >= d[i+1],
+    one-sided at the ends) in decreasing order (smallest w on ties), each at
+    least dw/4 from every earlier pick."""
+    d = np.array(d, np.float64)
+    taken = np.zeros(len(wgrid), bool)
+    for w in taken_w:
+        taken |= np.abs(wgrid - w) < dw / 4
+    d[taken] = -1.0
+    picks = [int(np.argmax(d))]
+    if q > 1:
+        n = len(d)
+        cands = []
+        for i in range(n):
+            if taken[i]:
+                continue
+            left = d[i] > d[i - 1] if i > 0 else True
+            right = d[i] >= d[i + 1] if i < n - 1 else True
+            if left and right:
+                cands.append(i)
+        cands.sort(key=lambda i: (-d[i], i))
+        for i in cands:
+            if len(picks) >= q:
+                break
+            if all(abs(wgrid[i] - wgrid[j]) >= dw / 4 for j in picks):
+                picks.append(i)
+    return picks
+
+
 def _fit_pair(S, F, K, J, omega, alpha_H, alpha_L, n_iter):
     MH, ML = orders(J, alpha_H, alpha_L)
     out = []
@@ -53,8 +90,9 @@ def _fit_pair(S, F, K, J, omega, alpha_H, alpha_L, n_iter):
 
 
 def run(response, K, Kt, T, eta, Ns, J0=16, alpha_H=2.0, alpha_L=2.3, E1_bar=1e-4, E2_bar=2e-3, Jc=3,
-        max_Nc=None, grid_pts=2048, n_iter=10):
+        max_Nc=None, grid_pts=2048, n_iter=10, q=1):
     """response(s) -> array [len(s), Kt] of complex values (columns < K are the ORFs).
+    q: new frequencies per analysis step (select_new).
     Returns a dict with the samples, the final order-M_H model and the histories."""
     omega = np.pi * Ns / T
     dw = 2 * np.pi / T
@@ -86,10 +124,7 @@ def run(response, K, Kt, T, eta, Ns, J0=16, alpha_H=2.0, alpha_L=2.3, E1_bar=1e-
             E1 = float(np.max(num / den))
         prev_td = td
         kmax = int(np.argmax(e[:K]))
-        d = diff[kmax].copy()
-        taken = np.abs(wgrid[:, None] - Sa.imag[None, :]).min(axis=1) < dw / 4
-        d[taken] = -1.0
-        s_new = sgrid[int(np.argmax(d))]
+        s_new = sgrid[select_new(diff[kmax], wgrid, Sa.imag, dw, q)]
         hist["E1"].append(E1)
         hist["E2"].append(E2)
         hist["J"].append(J)
@@ -100,8 +135,9 @@ def run(response, K, Kt, T, eta, Ns, J0=16, alpha_H=2.0, alpha_L=2.3, E1_bar=1e-
 
     def add(s_new):
         nonlocal F
-        S.append(s_new)
-        F = np.concatenate([F, np.asarray(response(np.array([s_new])), np.complex128).reshape(1, Kt)])
+        s_new = np.asarray(s_new)[: max_Nc - len(S)]
+        S.extend(s_new)
+        F = np.concatenate([F, np.asarray(response(s_new), np.complex128).reshape(len(s_new), Kt)])
 
     E1, E2, s_new, model = analyse()
     converged = False

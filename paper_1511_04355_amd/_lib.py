@@ -58,7 +58,7 @@ class _AfsParams(ctypes.Structure):
     _fields_ = [("T", ctypes.c_double), ("eta", ctypes.c_double), ("Ns", ctypes.c_int32), ("J0", ctypes.c_int32),
                 ("alpha_H", ctypes.c_double), ("alpha_L", ctypes.c_double), ("E1_bar", ctypes.c_double),
                 ("E2_bar", ctypes.c_double), ("Jc", ctypes.c_int32), ("max_Nc", ctypes.c_int32),
-                ("grid_pts", ctypes.c_int32), ("n_iter", ctypes.c_int32)]
+                ("grid_pts", ctypes.c_int32), ("n_iter", ctypes.c_int32), ("q", ctypes.c_int32)]
 
 
 _RESPONSE_FN = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_int32, ctypes.POINTER(ctypes.c_double), ctypes.c_int32,

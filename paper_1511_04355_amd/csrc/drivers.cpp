@@ -673,6 +673,59 @@ static void vf_prediction_weights(const std::vector<cplx> &s, const std::vector<
     }
 }
 
+// New frequencies from the discrepancy d on the uniform grid (G points on
+// [0, Omega]): grid points within dw/4 of a sample are excluded; the first
+// pick is the largest remaining value (Section 3.2; smallest w on ties), each
+// further one (q > 1) the next largest local maximum (d[g] > d[g-1],
+// d[g] >= d[g+1], one-sided at the ends; smallest w on ties) at least dw/4
+// from every earlier pick.  Returns grid indices; -1 if every point is taken.
+static std::vector<int> afs_select(const std::vector<double> &d0, int G, double omega, const std::vector<cplx> &S,
+                                   double dw, int q) {
+    std::vector<double> d(d0);
+    std::vector<char> taken(G, 0);
+    auto wof = [&](int g) { return (G > 1) ? omega * g / (G - 1) : 0.0; };
+    for (int g = 0; g < G; ++g)
+        for (const cplx &sv : S)
+            if (std::fabs(wof(g) - sv.imag()) < dw / 4) {
+                taken[g] = 1;
+                d[g] = -1.0;
+                break;
+            }
+    int gbest = -1;
+    double best = -1.0;
+    for (int g = 0; g < G; ++g)
+        if (!taken[g] && d[g] > best) {
+            best = d[g];
+            gbest = g;
+        }
+    std::vector<int> picks{gbest};
+    if (q > 1 && gbest >= 0) {
+        std::vector<int> cand;
+        for (int g = 0; g < G; ++g) {
+            if (taken[g])
+                continue;
+            const bool left = g > 0 ? d[g] > d[g - 1] : true;
+            const bool right = g < G - 1 ? d[g] >= d[g + 1] : true;
+            if (left && right)
+                cand.push_back(g);
+        }
+        std::stable_sort(cand.begin(), cand.end(), [&](int a, int b) { return d[a] > d[b]; });
+        for (int g : cand) {
+            if ((int)picks.size() >= q)
+                break;
+            bool far = true;
+            for (int h : picks)
+                if (std::fabs(wof(g) - wof(h)) < dw / 4) {
+                    far = false;
+                    break;
+                }
+            if (far)
+                picks.push_back(g);
+        }
+    }
+    return picks;
+}
+
 static void afs_run_impl(const afsbem_afs_params &P, int K, int Kt, const ResponseFn &resp, AfsResult &R) {
     const double omega = kPi * P.Ns / P.T;
     const double dw = 2.0 * kPi / P.T;
@@ -686,7 +739,7 @@ static void afs_run_impl(const afsbem_afs_params &P, int K, int Kt, const Respon
     std::vector<cplx> Fv;
     resp(S, Fv, nullptr);
     std::vector<double> prev_td;
-    cplx s_new;
+    std::vector<cplx> s_new;
 
     auto analyse = [&]() -> std::pair<double, double> {
         const int J = (int)S.size();
@@ -744,24 +797,9 @@ static void afs_run_impl(const afsbem_afs_params &P, int K, int Kt, const Respon
         for (int k = 1; k < K; ++k)
             if (e[k] > e[kmax])
                 kmax = k;
-        int gbest = -1;
-        double best = -1.0;
-        for (int g = 0; g < G; ++g) {
-            const double w = (G > 1) ? omega * g / (G - 1) : 0.0;
-            bool taken = false;
-            for (const cplx &sv : S)
-                if (std::fabs(w - sv.imag()) < dw / 4) {
-                    taken = true;
-                    break;
-                }
-            if (taken)
-                continue;
-            if (diffs[kmax][g] > best) {
-                best = diffs[kmax][g];
-                gbest = g;
-            }
-        }
-        s_new = cplx(P.eta, gbest >= 0 ? omega * gbest / (G - 1) : omega);
+        s_new.clear();
+        for (int g : afs_select(diffs[kmax], G, omega, S, dw, P.q))
+            s_new.push_back(cplx(P.eta, g >= 0 ? omega * g / (G - 1) : omega));
         R.E1.push_back(E1);
         R.E2.push_back(E2);
         R.J.push_back(J);
@@ -770,10 +808,14 @@ static void afs_run_impl(const afsbem_afs_params &P, int K, int Kt, const Respon
         R.model = mH;
         return {E1, E2};
     };
-    auto add = [&](cplx sn) {
-        std::vector<cplx> one{sn}, f;
-        resp(one, f, R.model.poles.empty() ? nullptr : &R.model);
-        S.push_back(sn);
+    auto add = [&](std::vector<cplx> sn) {
+        if ((int)sn.size() > max_Nc - (int)S.size())
+            sn.resize(std::max(0, max_Nc - (int)S.size()));
+        if (sn.empty())
+            return;
+        std::vector<cplx> f;
+        resp(sn, f, R.model.poles.empty() ? nullptr : &R.model);
+        S.insert(S.end(), sn.begin(), sn.end());
         Fv.insert(Fv.end(), f.begin(), f.end());
     };
     auto pass = [&](std::pair<double, double> e) { return e.first < P.E1_bar && e.second < P.E2_bar; };
@@ -1098,13 +1140,15 @@ int afsbem_afs_params_default(afsbem_afs_params *p) {
     p->max_Nc = 0;
     p->grid_pts = 2048;
     p->n_iter = 10;
+    p->q = 1;
     return AFSBEM_OK;
 }
 
 static void check_afs_params(const afsbem_afs_params *P, int32_t K, int32_t Kt) {
     AFS_REQUIRE(P, AFSBEM_EINVAL, "null params");
     AFS_REQUIRE(P->T > 0 && P->Ns >= 4 && P->J0 >= 4 && P->alpha_H >= 1.0 && P->alpha_L > P->alpha_H &&
-                    P->Jc >= 0 && P->grid_pts >= 16 && P->n_iter >= 1 && std::isfinite(P->eta),
+                    P->Jc >= 0 && P->grid_pts >= 16 && P->n_iter >= 1 && std::isfinite(P->eta) && P->q >= 1 &&
+                    P->q <= 1024,
                 AFSBEM_EINVAL, "invalid AFS parameters");
     AFS_REQUIRE(K >= 1 && Kt >= K, AFSBEM_EINVAL, "need 1 <= K <= Kt");
 }
@@ -1189,29 +1233,35 @@ int afsbem_afs_run_problem(afsbem_problem *p, const afsbem_afs_params *params, c
                 const double *x0 = nullptr;
                 const bool warm = o.warm_start != AFSBEM_WARM_NONE;
                 const int M = model ? (int)model->poles.size() : 0;
-                if (n == 1 && warm && o.warm_start == AFSBEM_WARM_MODEL && M > 0 && (int)solved.size() > M) {
-                    // prediction of the current rational model for every unknown
+                const bool use_model = warm && o.warm_start == AFSBEM_WARM_MODEL && M > 0 && (int)solved.size() > M;
+                if (warm && !solved.empty()) {
+                    // one start per requested frequency: the current rational model's prediction for every
+                    // unknown, or the nearest sampled solution (residual-optimal scaling inside the solve)
+                    double *xs = (double *)dmalloc((size_t)n * N * 16);
                     std::vector<cplx> sj(solved.size()), al, be;
                     for (size_t q = 0; q < solved.size(); ++q)
                         sj[q] = solved[q].first;
-                    vf_prediction_weights(sj, model->poles, s[0], al, be);
-                    double *xp = (double *)dmalloc((size_t)N * 16);
-                    AFS_HIP(hipMemsetAsync(xp, 0, (size_t)N * 16, st));
-                    for (size_t q = 0; q < solved.size(); ++q)
-                        vec_axpy_conj(N, al[q].real(), al[q].imag(), be[q].real(), be[q].imag(), solved[q].second,
-                                      xp, st);
-                    x0 = xp;
-                    oo.warm_start = AFSBEM_WARM_USER;
-                } else if (n == 1 && warm && !solved.empty()) {
-                    // warm start from the nearest sampled frequency (residual-optimal scaling inside)
-                    size_t best = 0;
-                    for (size_t q = 1; q < solved.size(); ++q)
-                        if (std::abs(solved[q].first - s[0]) < std::abs(solved[best].first - s[0]))
-                            best = q;
-                    x0 = solved[best].second;
+                    for (int i = 0; i < n; ++i) {
+                        double *xi = xs + 2 * (size_t)i * N;
+                        if (use_model) {
+                            vf_prediction_weights(sj, model->poles, s[i], al, be);
+                            AFS_HIP(hipMemsetAsync(xi, 0, (size_t)N * 16, st));
+                            for (size_t q = 0; q < solved.size(); ++q)
+                                vec_axpy_conj(N, al[q].real(), al[q].imag(), be[q].real(), be[q].imag(),
+                                              solved[q].second, xi, st);
+                        } else {
+                            size_t best = 0;
+                            for (size_t q = 1; q < solved.size(); ++q)
+                                if (std::abs(solved[q].first - s[i]) < std::abs(solved[best].first - s[i]))
+                                    best = q;
+                            AFS_HIP(hipMemcpyAsync(xi, solved[best].second, (size_t)N * 16, hipMemcpyDeviceToDevice,
+                                                   st));
+                        }
+                    }
+                    x0 = xs;
                     oo.warm_start = AFSBEM_WARM_USER;
                 } else if (n > 1 && warm) {
-                    oo.warm_start = AFSBEM_WARM_PREV;
+                    oo.warm_start = AFSBEM_WARM_PREV;  // the initial round: each from the one before
                 } else {
                     oo.warm_start = AFSBEM_WARM_NONE;
                 }

@@ -213,6 +213,85 @@ def test_afs_library_matches_oracle_on_mock():
     assert np.max(np.abs(afs.vf_eval_time(p["poles"], p["residues"], t) - ex)) < 1e-6 * np.max(np.abs(ex))
 
 
+def test_afs_select_new_rules():
+    """The multi-point selection on a hand-built discrepancy (grid step 0.1,
+    dw = 1, so picks must be 0.25 apart and away from samples): peaks of 5 at
+    w = 2.0, 4 at w = 1.0 and at w = 8.0 (a sample sits at 8.0), 3 at w = 5.0,
+    2.5 at w = 5.2 (too close to 5.0), elsewhere 0.1.  Expected by hand: q = 1
+    takes the largest value; then the w = 1.0 peak (4, ahead of the excluded
+    8.0); then 5.0; 5.2 is too close to 5.0; then the flat level 0.1, where
+    only the one-sided end point w = 0 and the first grid point after the
+    excluded band around the sample (w = 8.3) are local maxima, smallest w
+    first."""
+    w = np.round(np.linspace(0.0, 10.0, 101), 12)
+    d = np.full(101, 0.1)
+    d[20], d[10], d[80], d[50], d[52] = 5.0, 4.0, 4.0, 3.0, 2.5
+    pick = lambda q: oafs.select_new(d, w, [8.0], 1.0, q)
+    assert pick(1) == [20]
+    assert pick(3) == [20, 10, 50]
+    assert pick(5) == [20, 10, 50, 0, 83]
+    # q = 1 is the argmax over the grid points away from the samples
+    rng = np.random.default_rng(0)
+    for _ in range(20):
+        dd = rng.random(101)
+        taken = np.abs(w - 3.3) < 0.25
+        assert oafs.select_new(dd, w, [3.3], 1.0, 1) == [int(np.argmax(np.where(taken, -1, dd)))]
+        many = oafs.select_new(dd, w, [3.3], 1.0, 8)
+        ws = w[many]
+        assert all(abs(a - b) >= 0.25 for i, a in enumerate(ws) for b in ws[:i])
+        assert np.all(np.abs(ws - 3.3) >= 0.25)
+
+
+def test_afs_oracle_multipoint_on_mock():
+    """q = 3 new frequencies per analysis: converges to the same accuracy with
+    fewer analysis steps than q = 1, each later response call asking for at
+    most three frequencies."""
+    poles, res = _mock()
+    T, Ns = 60.0, 256
+    eta = 3 * np.log(10) / T
+    runs = {}
+    for q in (1, 3):
+        calls = []
+
+        def resp(s):
+            calls.append(len(s))
+            return vf.evaluate(np.asarray(s), poles, res).T
+
+        runs[q] = (oafs.run(resp, 5, 7, T, eta, Ns, q=q), calls)
+    out, calls = runs[3]
+    assert out["converged"] and out["Nc"] == sum(calls) and calls[0] == 16
+    assert max(calls[1:]) <= 3 and calls.count(3) >= len(calls[1:]) // 2
+    assert out["Nc"] < Ns // 2 + 1
+    assert len(out["history"]["E1"]) < len(runs[1][0]["history"]["E1"])
+    t = np.linspace(0, T, 300)
+    ex = vf.time_response(t, poles, res)
+    assert np.max(np.abs(vf.time_response(t, out["poles"], out["residues"]) - ex)) < 1e-6 * np.max(np.abs(ex))
+
+
+def test_afs_library_matches_oracle_multipoint():
+    afs = _lib()
+    poles, res = _mock()
+    T, Ns = 60.0, 256
+    eta = 3 * np.log(10) / T
+
+    def resp(s):
+        return vf.evaluate(np.asarray(s), poles, res).T
+
+    o = oafs.run(resp, 5, 7, T, eta, Ns, q=3)
+    p = afs.afs_run(resp, 5, 7, afs.afs_params(T, eta, Ns, q=3))
+    assert p["converged"] and o["converged"]
+    assert np.max(np.abs(p["s"][:30] - o["s"][:30])) < 1e-9
+    t = np.linspace(0, T, 300)
+    ex = vf.time_response(t, poles, res)
+    assert np.max(np.abs(afs.vf_eval_time(p["poles"], p["residues"], t) - ex)) < 1e-6 * np.max(np.abs(ex))
+
+
+def test_afs_library_rejects_bad_q():
+    afs = _lib()
+    with pytest.raises(afs.AfsbemError):
+        afs.afs_run(lambda s: np.zeros((len(s), 2), complex), 2, 2, afs.afs_params(10.0, 0.5, 64, q=0))
+
+
 def test_afs_library_reports_callback_failure():
     afs = _lib()
 

@@ -54,6 +54,54 @@ def test_afs_on_gpu_solve_matches_oracle_afs():
     assert np.max(np.abs(hg - ho)) <= 1e-3 * np.max(np.abs(ho))
 
 
+@pytest.mark.parametrize("warm", ["nearest", "model"])
+def test_afs_multipoint_on_gpu_matches_oracle_afs(warm):
+    """Three new frequencies per analysis step, solved in one call with one
+    start per frequency (the nearest sample's solution, or the current model's
+    prediction): the same samples as the oracle AFS with q = 3 on the oracle's
+    LU solves, the same time response, and fewer analysis steps than q = 1."""
+    import paper_1511_04355_amd as afs
+    from oracle import afs as oafs
+    from oracle import bem, vf
+
+    mesh = mg.cavity(2)
+    T, Ns, eta = 20.0, 64, 0.25
+    rng = np.random.default_rng(5)
+    dofs = np.sort(rng.choice(3 * mesh.n_tri, 6, replace=False))
+    K = 4
+    P = afs.Problem.from_mesh(mesh)
+    ws = afs.WARM_PREV if warm == "nearest" else afs.WARM_MODEL
+    out = P.afs(afs.afs_params(T, eta, Ns, q=3), mesh.bc_shape, dofs, K, load_kind=0,
+                opts=afs.SolveOptions(tol=1e-10, warm_start=ws))
+    one = P.afs(afs.afs_params(T, eta, Ns), mesh.bc_shape, dofs, K, load_kind=0,
+                opts=afs.SolveOptions(tol=1e-10, warm_start=ws))
+    print(f"[afs q=3 {warm}] Nc={out['Nc']} steps={len(out['E1'])} (q=1: Nc={one['Nc']} steps={len(one['E1'])})",
+          flush=True)
+    assert out["converged"] and out["Nc"] <= Ns // 2 + 1
+    assert len(out["E1"]) < len(one["E1"])
+    cache = {}
+
+    def resp(svals):
+        rows = []
+        for sk in svals:
+            key = complex(sk)
+            if key not in cache:
+                A, b = bem.assemble(mesh, sk)
+                cache[key] = bem.solve_dense(A, b)[dofs]
+            rows.append(cache[key])
+        return np.array(rows)
+
+    o = oafs.run(resp, K, len(dofs), T, eta, Ns, q=3)
+    assert o["converged"]
+    n = min(len(o["s"]), len(out["s"]), 25)
+    assert np.max(np.abs(out["s"][:n] - o["s"][:n])) < 1e-9
+    assert np.max(np.abs(out["F"][:n] - o["F"][:n])) <= 1e-7 * np.max(np.abs(o["F"][:n]))
+    t = np.linspace(0, T, 200)
+    ho = vf.time_response(t, o["poles"], o["residues"])
+    hg = afs.vf_eval_time(out["poles"], out["residues"], t)
+    assert np.max(np.abs(hg - ho)) <= 1e-3 * np.max(np.abs(ho))
+
+
 def test_afs_model_warm_start_same_samples_fewer_products():
     """AFS with the vector-fitting prediction as initial guess (WARM_MODEL)
     takes the same samples as with zero starts (the solves agree to 1e-10).
