@@ -69,13 +69,16 @@ def parse():
                     help="initial guess of the optimised path")
     ap.add_argument("--workload", default="cavity_L4",
                     choices=["cavity_L4", "pmc_probe", "cavity_L2_batched", "blocks_batched", "porous_learned",
-                             "porous_matrix_free", "porous_afs_matrix_free"],
+                             "porous_matrix_free", "porous_afs_matrix_free", "cavity_L4_afs"],
                     help="cavity_L4: the contract line (default).  The others print their own JSON line: "
                          "pmc_probe (1 GiB copies + 4 mixed solves, for counter runs), cavity_L2_batched "
                          "(320 triangles, 16 frequencies), blocks_batched (16 seeded porous blocks x 24 "
                          "frequencies), porous_learned (27-void block, 40,320 unknowns: warm-start A/B on an "
                          "AFS frequency sequence), porous_matrix_free (64-void block, 300,516 unknowns), "
-                         "porous_afs_matrix_free (AFS + matrix-free solves + time synthesis at 300,516 unknowns)")
+                         "porous_afs_matrix_free (AFS + matrix-free solves + time synthesis at 300,516 unknowns), "
+                         "cavity_L4_afs (AFS on the 15,360-unknown cavity with 1 and --afs-q new frequencies per "
+                         "step, then the all-unknown time history by Eq. 6 and by the batched FSM inversion)")
+    ap.add_argument("--afs-q", type=int, default=4, help="cavity_L4_afs: new frequencies per AFS step")
     ap.add_argument("--precond", type=int, default=0, help="blocks_batched: 0 point, 1 cluster block-Jacobi")
     ap.add_argument("--afs-ns", type=int, default=64, help="porous_afs_matrix_free: FSM size Ns of the band")
     ap.add_argument("--afs-max", type=int, default=24, help="porous_learned: cap on AFS samples")
@@ -418,6 +421,59 @@ def run_porous_afs_matrix_free(args, afs, mg, np, torch):
             "time_response_512_peak": float(np.max(np.abs(h512))), "solves": log}
 
 
+def run_cavity_L4_afs(args, afs, mg, np, torch):
+    """Adaptive frequency sampling on the level-4 cavity (15,360 unknowns,
+    Heaviside pressure, T = 20, eta = 0.25, Ns = 64: the band [0, 10] of the
+    64-frequency list), mixed dense solves with the nearest sample's solution
+    as start, once with one new frequency per analysis step (the paper's rule)
+    and once with --afs-q (solved together, assembly of one overlapped with
+    the Krylov phase of another).  Then, from the q-run's samples of every
+    unknown (kept on the device): the time history of all unknowns at Ns steps
+    by Eq. 6 and by the batched FSM inversion of the model on the FSM grid."""
+    mesh = mg.cavity(args.level)
+    P = afs.Problem.from_mesh(mesh)
+    N = P.N
+    T, eta, Ns = 20.0, 0.25, 64
+    rng = np.random.default_rng(4)
+    dofs = np.sort(rng.choice(N, 8, replace=False))
+    shape = np.ascontiguousarray(np.asarray(mesh.bc_shape, np.float64).reshape(-1))
+    opts = afs.SolveOptions(tol=args.tol, precision=afs.PREC_MIXED, warm_start=afs.WARM_PREV)
+    res = {}
+    for q in (1, args.afs_q):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = P.afs(afs.afs_params(T, eta, Ns, q=q), shape, dofs, 4, load_kind=0, opts=opts)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        res[q] = {"seconds": dt, "n_solves": r["Nc"], "analysis_steps": len(r["E1"]), "converged": bool(r["converged"]),
+                  "krylov_products": int(r["matvecs"]), "solves_per_s": r["Nc"] / dt}
+        print(f"[afs-L4] q={q}: {r['Nc']} solves in {len(r['E1'])} steps, {dt:.2f} s", file=sys.stderr, flush=True)
+    # all-unknown time history from the q-run's samples: re-solve them in one batched call
+    s = r["s"]
+    bc = torch.from_numpy(np.stack([np.asarray(mesh.bc_shape, np.complex128) / sk for sk in s])).cuda()
+    out = P.solve(s, bc, afs.SolveOptions(tol=args.tol, precision=afs.PREC_MIXED, warm_start=afs.WARM_PREV),
+                  want_ut=False)
+    X = out["a"].contiguous()
+    t = np.arange(Ns) * T / Ns
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    h6 = afs.time_synthesis(r["poles"], s, X, t)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    Hs = afs.model_sample(r["poles"], s, X, afs.fsm_grid(T, eta, Ns))
+    hf = afs.fsm_invert_device(T, eta, Ns, Hs)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    scale = torch.max(torch.abs(h6)).item()
+    gap = torch.max(torch.abs(hf[:, 2:Ns // 2] - h6[:, 2:Ns // 2])).item() / scale
+    return {"workload": f"cavity_L4_afs: icosphere level {args.level} ({mesh.n_tri} elements, {N} unknowns), "
+                        f"AFS T={T}, eta={eta}, Ns={Ns}, mixed dense GMRES, FP64 true rel. residual <= {args.tol}, "
+                        f"starts from the nearest sample",
+            "q1": res[1], f"q{args.afs_q}": res[args.afs_q],
+            "all_unknowns_eq6_ms": 1e3 * (t1 - t0), "all_unknowns_fsm_ms": 1e3 * (t2 - t1),
+            "fsm_vs_eq6_max_rel_steps_2_to_31": gap}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -437,7 +493,8 @@ def main():
               "blocks_batched": lambda: run_blocks_batched(args, afs, mg, np, torch),
               "porous_learned": lambda: run_porous_learned(args, afs, mg, np, torch),
               "porous_matrix_free": lambda: run_porous_matrix_free(args, afs, mg, np, torch),
-              "porous_afs_matrix_free": lambda: run_porous_afs_matrix_free(args, afs, mg, np, torch)}[args.workload]
+              "porous_afs_matrix_free": lambda: run_porous_afs_matrix_free(args, afs, mg, np, torch),
+              "cavity_L4_afs": lambda: run_cavity_L4_afs(args, afs, mg, np, torch)}[args.workload]
         print(json.dumps(fn()), flush=True)
         return
     mesh = mg.cavity(args.level)

@@ -355,7 +355,8 @@ int afsbem_vf_eval_time(int32_t M, const double *poles, int64_t n_fun, const dou
  * paper's rule) new frequencies per analysis step, requested from the response
  * in one call (one batched solve): the largest discrepancy as in Section 3.2,
  * then the next largest local maxima of the same discrepancy at least dw/4
- * from every sample and every earlier pick (fewer when none is left). */
+ * from every sample and every earlier pick (fewer when none is left); the Jc
+ * validation steps add one frequency each, as in the paper. */
 typedef struct {
     double T, eta;
     int32_t Ns, J0;

@@ -23,7 +23,9 @@ Readings of the paper used here:
    does not make: it inserts one): the first is the argmax above; each further
    one is the next largest local maximum of the same masked discrepancy that
    lies at least dw/4 from every sample and every earlier pick; fewer than q
-   when no such maximum is left.  q = 1 is the paper's rule.
+   when no such maximum is left.  The Jc validation steps still add one
+   frequency each (the paper's convergence check unchanged).  q = 1 is the
+   paper's rule.
 """
 from __future__ import annotations
 
@@ -147,7 +149,7 @@ def run(response, K, Kt, T, eta, Ns, J0=16, alpha_H=2.0, alpha_L=2.3, E1_bar=1e-
             for _ in range(Jc):
                 if len(S) >= max_Nc:
                     break
-                add(s_new)
+                add(s_new[:1])
                 E1, E2, s_new, model = analyse()
                 if not (E1 < E1_bar and E2 < E2_bar):
                     ok = False

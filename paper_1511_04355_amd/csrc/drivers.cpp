@@ -827,7 +827,7 @@ static void afs_run_impl(const afsbem_afs_params &P, int K, int Kt, const Respon
             for (int v = 0; v < P.Jc; ++v) {
                 if ((int)S.size() >= max_Nc)
                     break;
-                add(s_new);
+                add(std::vector<cplx>(s_new.begin(), s_new.begin() + 1));  // validation: one at a time
                 err = analyse();
                 if (!pass(err)) {
                     ok = false;
