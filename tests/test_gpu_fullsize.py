@@ -1,0 +1,127 @@
+"""Full-size parity in the launch configurations the benchmarks time: the 16
+seeded porous blocks (2.8k-20k unknowns) through one lockstep batched call,
+the 27-void block (40,320 unknowns) and the 64-void block (300,516 unknowns,
+matrix-free) through the single-problem solve.
+
+The oracle cannot solve these systems, but it can assemble any row of A and
+b.  The checks use that: sampled rows of b (and, where the matrix is stored, of
+A) against the oracle's rows, and the solution's residual on sampled rows of
+the oracle's operator.  ||b - A x||_2 <= tol ||b||_2 bounds every component,
+so |b_i - A_i x| <= tol ||b||_2 must hold on each sampled row (||b|| from the
+GPU's own b -- assembled, or the matrix-free operator's -- checked against the
+oracle's rows first; 1 % slack for the two operators' rounding).
+"""
+import numpy as np
+import pytest
+
+from synth import meshgen as mg
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _needs_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+
+
+def _bcs(mesh, s):
+    shape = np.asarray(mesh.bc_shape, np.complex128)
+    return np.stack([shape / sk for sk in s])
+
+
+def _check_rows(afs, bem, P, mesh, sk, bc, x, tol, n_rows, seed, check_A):
+    """Oracle rows of b (and A) against the GPU's, and the residual bound on them."""
+    rows = np.sort(np.random.default_rng(seed).choice(mesh.n_tri, n_rows, replace=False))
+    Ao, bo = bem.assemble(mesh, sk, bc, rows=rows)
+    idx = (3 * rows[:, None] + np.arange(3)[None]).reshape(-1)
+    bct = torch.from_numpy(np.ascontiguousarray(bc.reshape(-1))).cuda()
+    if check_A:
+        A, _, b, _ = P.assemble(sk, bct, fmt=afs.FMT_C128)
+        Ag = A[:, :P.N].T[torch.from_numpy(idx).cuda()].cpu().numpy()
+        assert np.max(np.abs(Ag - Ao)) <= 1e-11 * np.max(np.abs(Ao))
+        del A
+    else:  # b of the matrix-free operator (FP64), no stored matrix
+        _, b = P.matvec_free(sk, bc_val=bct, precision=0)
+    bg = b.cpu().numpy()
+    assert np.max(np.abs(bg[idx] - bo)) <= 1e-11 * np.max(np.abs(bo))
+    r = np.max(np.abs(bo - Ao @ x))
+    assert r <= 1.01 * tol * np.linalg.norm(bg), (r, tol * np.linalg.norm(bg))
+    return r / np.linalg.norm(bg)
+
+
+@pytest.mark.timeout(300)
+def test_blocks_batched_full_size_sampled_rows():
+    """All 16 seeded blocks in one lockstep batched call with the benchmark's
+    options (mixed, GMRES(150), point block-Jacobi, tol 1e-6), two
+    frequencies each (the first and a mid-band one of the 24)."""
+    import paper_1511_04355_amd as afs
+    from oracle import bem
+    meshes = [mg.random_block(seed) for seed in range(16)]
+    s = mg.block_frequencies(24)[[0, 13]]
+    probs = [afs.Problem.from_mesh(m) for m in meshes]
+    bcs = [_bcs(m, s) for m in meshes]
+    tol = 1e-6
+    opts = afs.SolveOptions(tol=tol, precision=afs.PREC_MIXED, restart=150, max_iter=6000)
+    print(f"[full] 16 blocks x 2, unknowns {[3 * m.n_tri for m in meshes]}", flush=True)
+    outs, rc = afs.solve_batched(probs, [s] * 16, [torch.from_numpy(b).cuda() for b in bcs], opts)
+    assert rc == 0
+    worst = 0.0
+    for j, (m, P, bc, o) in enumerate(zip(meshes, probs, bcs, outs)):
+        for k, sk in enumerate(s):
+            st = o["stats"][k]
+            assert st["status"] == 0 and st["rel_res_fp64"] <= tol, (j, k, st)
+            x = o["a"][k].cpu().numpy()
+            worst = max(worst, _check_rows(afs, bem, P, m, sk, bc[k], x, tol, 3, 100 * j + k, check_A=(j < 4)))
+    print(f"[full] blocks: largest sampled-row residual {worst:.2e} of ||b||", flush=True)
+
+
+@pytest.mark.timeout(300)
+def test_porous_27_voids_full_size_sampled_rows():
+    """The 27-void block (13,440 elements, 40,320 unknowns) at a mid-band
+    frequency of its AFS line, mixed GMRES(100) as the benchmark runs it:
+    sampled rows of the stored A (26 GB in C128 here) and b, and the residual
+    bound on them."""
+    import paper_1511_04355_amd as afs
+    from oracle import bem
+    mesh = mg.lattice_block(3, 20, 2, 1000)
+    P = afs.Problem.from_mesh(mesh)
+    eta = 3.0 * np.log(10.0) / 300.0
+    sk = complex(eta, 0.31)
+    bc = _bcs(mesh, [sk])
+    tol = 1e-6
+    print(f"[full] 27-void block, N = {3 * mesh.n_tri}", flush=True)
+    out = P.solve([sk], torch.from_numpy(bc).cuda(),
+                  afs.SolveOptions(tol=tol, precision=afs.PREC_MIXED, restart=100, max_iter=8000), want_ut=False)
+    st = out["stats"][0]
+    assert st["status"] == 0 and st["rel_res_fp64"] <= tol, st
+    x = out["a"][0].cpu().numpy()
+    r = _check_rows(afs, bem, P, mesh, sk, bc[0], x, tol, 8, 7, check_A=True)
+    print(f"[full] 27 voids: {st['iters']} products, sampled-row residual {r:.2e} of ||b||", flush=True)
+
+
+@pytest.mark.timeout(300)
+def test_porous_64_voids_matrix_free_solve_sampled_rows():
+    """The 64-void block (100,172 elements, 300,516 unknowns) solved
+    matrix-free (FP32 on-the-fly inner products, FP64 residuals) at s = eta,
+    the configuration of the full AFS workload: sampled rows of b (the
+    matrix-free operator's own b) and the residual bound on the oracle's
+    rows."""
+    import paper_1511_04355_amd as afs
+    from oracle import bem
+    mesh = mg.lattice_block(4, 39, 3, 2000, rmax=0.45)
+    P = afs.Problem.from_mesh(mesh)
+    eta = 3.0 * np.log(10.0) / 300.0
+    sk = complex(eta, 0.0)
+    bc = _bcs(mesh, [sk])
+    tol = 1e-6
+    print(f"[full] 64-void block, N = {3 * mesh.n_tri}, matrix-free", flush=True)
+    out = P.solve([sk], torch.from_numpy(bc).cuda(),
+                  afs.SolveOptions(tol=tol, precision=afs.PREC_MIXED, matrix_free=1, restart=100, max_iter=4000,
+                                   batch=1), want_ut=False)
+    st = out["stats"][0]
+    assert st["status"] == 0 and st["rel_res_fp64"] <= tol, st
+    x = out["a"][0].cpu().numpy()
+    r = _check_rows(afs, bem, P, mesh, sk, bc[0], x, tol, 4, 11, check_A=False)
+    print(f"[full] 64 voids: {st['iters']} products, sampled-row residual {r:.2e} of ||b||", flush=True)
