@@ -79,7 +79,8 @@ def parse():
                          "cavity_L4_afs (AFS on the 15,360-unknown cavity with 1 and --afs-q new frequencies per "
                          "step, then the all-unknown time history by Eq. 6 and by the batched FSM inversion)")
     ap.add_argument("--afs-q", type=int, default=4, help="cavity_L4_afs: new frequencies per AFS step")
-    ap.add_argument("--precond", type=int, default=0, help="blocks_batched: 0 point, 1 cluster block-Jacobi")
+    ap.add_argument("--precond", type=int, default=0,
+                    help="blocks_batched, porous_afs_matrix_free: 0 point, 1 cluster block-Jacobi")
     ap.add_argument("--afs-ns", type=int, default=64, help="porous_afs_matrix_free: FSM size Ns of the band")
     ap.add_argument("--afs-max", type=int, default=24, help="porous_learned: cap on AFS samples")
     ap.add_argument("--batch", type=int, default=0,
@@ -317,8 +318,9 @@ def run_porous_learned(args, afs, mg, np, torch):
 
 def run_porous_matrix_free(args, afs, mg, np, torch):
     """64-void porous block (100,172 elements, 300,516 unknowns; the dense
-    matrix would need 1.4 TB): matrix-free products in both precisions, and one
-    mixed solve at the lowest frequency s = eta."""
+    matrix would need 1.4 TB): matrix-free products in both precisions, and
+    mixed solves at s = eta and at a mid-band frequency with point and with
+    cluster block-Jacobi preconditioning (one progress line per solve)."""
     mesh = mg.lattice_block(4, 39, 3, 2000, rmax=0.45)
     t0 = time.perf_counter()
     P = afs.Problem.from_mesh(mesh)
@@ -334,19 +336,24 @@ def run_porous_matrix_free(args, afs, mg, np, torch):
         ms, _ = _clock(lambda: P.matvec_free(s0, x, precision=prec), 2, 1, torch)
         res[name] = {"ms_incl_block_setup": ms, "node_evals_per_s": pairs * 7 / (ms * 1e-3)}
     eta = 3.0 * np.log(10.0) / 300.0
-    s = np.array([eta + 0.0j])
-    o = afs.SolveOptions(tol=args.tol, precision=afs.PREC_MIXED, matrix_free=1, restart=100, max_iter=2000,
-                         profile=1, batch=1)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    out = P.solve(s, _bcs(mesh, s, torch, np), o, want_ut=False)
-    torch.cuda.synchronize()
-    st = out["stats"][0]
-    res["solve_mixed_s_eta"] = {"seconds": time.perf_counter() - t0, "inner_products": st["gemv_count"],
-                                "inner_ms_avg": st["gemv_ms"] / max(st["gemv_count"], 1),
-                                "fp64_products": st["gemv64_count"],
-                                "fp64_ms_avg": st["gemv64_ms"] / max(st["gemv64_count"], 1),
-                                "rel_res_fp64": st["rel_res_fp64"], "setup_ms": st["t_assemble_ms"]}
+    for name, sk in (("s_eta", eta + 0.0j), ("s_mid_band", eta + 0.4j)):
+        for pc in (0, 1):
+            s = np.array([sk])
+            o = afs.SolveOptions(tol=args.tol, precision=afs.PREC_MIXED, matrix_free=1, restart=100, max_iter=4000,
+                                 profile=1, batch=1, precond=pc)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            out = P.solve(s, _bcs(mesh, s, torch, np), o, want_ut=False)
+            torch.cuda.synchronize()
+            st = out["stats"][0]
+            key = f"solve_mixed_{name}_{'clusters' if pc else 'points'}"
+            res[key] = {"seconds": time.perf_counter() - t0, "inner_products": st["gemv_count"],
+                        "inner_ms_avg": st["gemv_ms"] / max(st["gemv_count"], 1),
+                        "fp64_products": st["gemv64_count"],
+                        "fp64_ms_avg": st["gemv64_ms"] / max(st["gemv64_count"], 1),
+                        "rel_res_fp64": st["rel_res_fp64"], "setup_ms": st["t_assemble_ms"]}
+            print(f"[mf-300k] {key}: {res[key]['seconds']:.1f} s, {st['gemv_count']} FP32 + {st['gemv64_count']} "
+                  f"FP64 products, rel res {st['rel_res_fp64']:.1e}", file=sys.stderr, flush=True)
     return res
 
 
@@ -369,7 +376,8 @@ def run_porous_afs_matrix_free(args, afs, mg, np, torch):
     loaded = np.nonzero(np.abs(np.asarray(mesh.bc_shape)).sum(1) > 0)[0]
     dofs = np.sort(3 * rng.choice(loaded, 6, replace=False) + 2)
     shape = np.asarray(mesh.bc_shape, np.complex128)
-    base = dict(tol=args.tol, precision=afs.PREC_MIXED, matrix_free=1, restart=100, max_iter=4000, batch=1)
+    base = dict(tol=args.tol, precision=afs.PREC_MIXED, matrix_free=1, restart=100, max_iter=4000, batch=1,
+                precond=args.precond)
     solved, log = {}, []
 
     def response(sv):
@@ -413,7 +421,8 @@ def run_porous_afs_matrix_free(args, afs, mg, np, torch):
     fit_err = float(np.max(np.abs(fit.T - r["F"])) / np.max(np.abs(r["F"])))
     return {"workload": f"porous_afs_matrix_free: 64-void block ({mesh.n_tri} elements, {3 * mesh.n_tri} unknowns), "
                         f"AFS from J0=8, T={T}, eta={eta:.4f}, Ns={Ns} (Omega={np.pi * Ns / T:.3f}), mixed "
-                        f"matrix-free GMRES(100), FP64 true rel. residual <= {args.tol}",
+                        f"matrix-free GMRES(100), {'cluster' if args.precond else 'point'} block-Jacobi, "
+                        f"FP64 true rel. residual <= {args.tol}",
             "plan_s": plan_s, "afs_seconds": afs_s, "n_solves": r["Nc"], "fsm_solves_avoided": Ns // 2 + 1 - r["Nc"],
             "converged": bool(r["converged"]), "model_order": len(r["poles"]),
             "E1": [float(x) for x in r["E1"][-3:]], "E2": [float(x) for x in r["E2"][-3:]],

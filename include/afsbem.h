@@ -196,11 +196,12 @@ typedef struct {
     int32_t learn_steps; /* AFSBEM_WARM_LEARNED: Adam steps after each solved frequency (0: 24) */
     int32_t precond;     /* block-diagonal preconditioner: 0 = one 3x3 block per collocation point;
                             1 = blocks over spatial clusters of up to 24 elements (recursive
-                            coordinate bisection), inverted in FP32 on the device */
+                            coordinate bisection), inverted in FP32 on the device (with
+                            matrix_free: the blocks are evaluated, far rule + near/self blocks) */
     int32_t matrix_free; /* 1: no stored matrix; every product evaluates the far-field rule on the
                             fly (FP64, or FP32 for the inner products of the mixed path) and adds
-                            the near/self blocks formed once per frequency in FP64 (needs
-                            precond 0); memory O(N + near pairs) instead of O(N^2) */
+                            the near/self blocks formed once per frequency in FP64; memory
+                            O(N + near pairs) instead of O(N^2) */
     int32_t no_graph;    /* batched solve: 1 = launch every kernel directly instead of replaying
                             the captured graphs of four Arnoldi steps (default 0) */
 } afsbem_solve_opts;

@@ -438,8 +438,6 @@ int afsbem_solve_device(afsbem_problem *p, int32_t n_s, const double *s, const v
                     "unknown warm start");
         AFS_REQUIRE(o.precond == 0 || o.precond == 1, AFSBEM_EINVAL, "precond must be 0 or 1");
         AFS_REQUIRE(o.matrix_free == 0 || o.matrix_free == 1, AFSBEM_EINVAL, "matrix_free must be 0 or 1");
-        AFS_REQUIRE(!(o.matrix_free && o.precond == 1), AFSBEM_EINVAL,
-                    "the cluster preconditioner needs the stored matrix");
         AFS_REQUIRE(o.warm_start != AFSBEM_WARM_LEARNED || d_a_out, AFSBEM_EINVAL,
                     "the learned warm start needs the solution output buffer");
         hipStream_t st = static_cast<hipStream_t>(hip_stream);

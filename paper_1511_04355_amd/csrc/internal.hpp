@@ -207,7 +207,11 @@ int mdot_blocks(int64_t N);
 
 // cluster block-Jacobi preconditioner: inverses [n_clusters][kClusterDim^2]
 // complex<float>; z = M^-1 v
+// format kFmtBlocks: A holds the blocks gathered by cluster_gather_mf
 void cluster_inverse(const DevicePlan &d, int format, const void *A, const void *A_lo, float *inv, hipStream_t st);
+// the cluster blocks of the matrix-free operator (self, far rule + near corrections)
+void cluster_gather_mf(const Problem &p, const KernelParams &kp, const double *nearblk, const double *selfblk,
+                       float *out, hipStream_t st);
 void cluster_apply(const DevicePlan &d, const float *inv, const double *v, double *z, hipStream_t st);
 
 }  // namespace afsbem

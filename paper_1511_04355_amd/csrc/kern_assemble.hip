@@ -708,6 +708,81 @@ void launch_assembly(const Problem &p, const KernelParams &kp, const double *bc_
     AFS_HIP(hipGetLastError());
 }
 
+// Diagonal blocks of the cluster preconditioner for the matrix-free operator
+// (no stored matrix to read them from): the operator's block (m, n) is the
+// self block for m = n, else the far rule's block plus the pair's near
+// correction (exact - far rule) when (m, n) is a near pair -- the same sum a
+// matrix-free product forms.  One thread per element pair of the cluster,
+// FP64 evaluation; output FP32 complex, row-major with the cluster's own
+// dimension d = 3 ne as stride, at the cluster's slot of kClusterDim^2 entries.
+__global__ __launch_bounds__(256) void cluster_gather_mf_kernel(
+    KernelParams kp, const double *__restrict__ colx, const double *__restrict__ coly,
+    const double *__restrict__ colz, const double *__restrict__ src, const double *__restrict__ coef,
+    const int64_t *__restrict__ near_ptr, const int32_t *__restrict__ near_col, const double *__restrict__ nearblk,
+    const double *__restrict__ selfblk, const int64_t *__restrict__ cptr, const int32_t *__restrict__ celem,
+    float2 *__restrict__ out) {
+    const int c = blockIdx.x;
+    const int64_t e0 = cptr[c];
+    const int ne = (int)(cptr[c + 1] - e0);
+    const int d = 3 * ne;
+    float2 *blkout = out + (int64_t)c * kClusterDim * kClusterDim;
+    for (int q = threadIdx.x; q < ne * ne; q += 256) {
+        const int r = q / ne, k = q % ne;
+        const int64_t m = celem[e0 + r], n = celem[e0 + k];
+        cd blk[9];
+        if (m == n) {
+            const double *sb = selfblk + 18 * m;
+#pragma unroll
+            for (int e = 0; e < 9; ++e)
+                blk[e] = cd{sb[2 * e], sb[2 * e + 1]};
+        } else {
+            const double *rec = src + kSrcStride * n;
+            const double nx = rec[28], ny = rec[29], nz = rec[30];
+            const int kind = (int)rec[31];
+            const cd v0[3] = {cd{0, 0}, cd{0, 0}, cd{0, 0}};
+            cd bdummy[3] = {cd{0, 0}, cd{0, 0}, cd{0, 0}};
+            BlockAcc acc;
+            acc.zero();
+            const double xx = colx[m], xy = coly[m], xz = colz[m];
+#pragma unroll 1
+            for (int qn = 0; qn < kFarNodes; ++qn) {
+                PairEval E;
+                eval_pair(kp, coef, xx, xy, xz, rec[4 * qn], rec[4 * qn + 1], rec[4 * qn + 2], nx, ny, nz, E);
+                const double w = rec[4 * qn + 3];
+                if (kind == 0)
+                    acc_node<0>(E, kp, nx, ny, nz, w, 0.0, v0, acc, bdummy);
+                else
+                    acc_node<1>(E, kp, nx, ny, nz, w, 0.0, v0, acc, bdummy);
+            }
+            expand_block(kind, acc, nx, ny, nz, blk);
+            for (int64_t pp = near_ptr[m]; pp < near_ptr[m + 1]; ++pp)
+                if (near_col[pp] == n) {
+                    const double *nb = nearblk + 18 * pp;
+#pragma unroll
+                    for (int e = 0; e < 9; ++e)
+                        blk[e] = cadd(blk[e], cd{nb[2 * e], nb[2 * e + 1]});
+                    break;
+                }
+        }
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int b = 0; b < 3; ++b)
+                blkout[(3 * r + a) * d + 3 * k + b] = make_float2((float)blk[3 * a + b].r, (float)blk[3 * a + b].i);
+    }
+}
+
+void cluster_gather_mf(const Problem &p, const KernelParams &kp, const double *nearblk, const double *selfblk,
+                       float *out, hipStream_t st) {
+    const DevicePlan &d = p.dev;
+    if (d.n_clusters == 0)
+        return;
+    cluster_gather_mf_kernel<<<(unsigned)d.n_clusters, 256, 0, st>>>(
+        kp, d.colx, d.coly, d.colz, d.src, d.coef, d.near_ptr, d.near_col, nearblk, selfblk, d.clus_ptr, d.clus_elem,
+        reinterpret_cast<float2 *>(out));
+    AFS_HIP(hipGetLastError());
+}
+
 void launch_block_setup(const Problem &p, const KernelParams &kp, const double *bc_val, double *nearblk,
                         double *selfblk, double *precond, void *scratch, hipStream_t st) {
     const DevicePlan &d = p.dev;

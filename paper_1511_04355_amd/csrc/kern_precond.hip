@@ -44,8 +44,13 @@ __global__ __launch_bounds__(256) void cluster_inverse_kernel(int64_t lda, const
     const int tid = threadIdx.x;
     for (int q = tid; q < d * d; q += 256) {
         const int r = q / d, k = q % d;
-        const int64_t er = celem[e0 + r / 3], ek = celem[e0 + k / 3];
-        M[r][k] = load_entry<FMT>(A, A_lo, lda, 3 * er + r % 3, 3 * ek + k % 3);
+        if (FMT == kFmtBlocks) {  // blocks gathered for the matrix-free operator, stride d
+            const float2 g = static_cast<const float2 *>(A)[(int64_t)c * D * D + q];
+            M[r][k] = cf{g.x, g.y};
+        } else {
+            const int64_t er = celem[e0 + r / 3], ek = celem[e0 + k / 3];
+            M[r][k] = load_entry<FMT>(A, A_lo, lda, 3 * er + r % 3, 3 * ek + k % 3);
+        }
     }
     __syncthreads();
     for (int k = 0; k < d; ++k) {
@@ -156,6 +161,9 @@ void cluster_inverse(const DevicePlan &d, int format, const void *A, const void 
         return;
     if (format == AFSBEM_FMT_C128)
         cluster_inverse_kernel<AFSBEM_FMT_C128><<<(unsigned)d.n_clusters, 256, 0, st>>>(
+            lda, d.clus_ptr, d.clus_elem, A, A_lo, reinterpret_cast<float2 *>(inv));
+    else if (format == kFmtBlocks)
+        cluster_inverse_kernel<kFmtBlocks><<<(unsigned)d.n_clusters, 256, 0, st>>>(
             lda, d.clus_ptr, d.clus_elem, A, A_lo, reinterpret_cast<float2 *>(inv));
     else
         cluster_inverse_kernel<AFSBEM_FMT_SPLIT><<<(unsigned)d.n_clusters, 256, 0, st>>>(

@@ -37,7 +37,7 @@ Workspace::~Workspace() { release(); }
 void Workspace::release() {
     for (void *p : {(void *)A, (void *)A_lo, (void *)nearblk, (void *)selfblk, (void *)b, (void *)precond, (void *)asm_scratch, (void *)gemv_partial,
                     (void *)V, (void *)w, (void *)z, (void *)x, (void *)r, (void *)tmp, (void *)rin, (void *)xo,
-                    (void *)dots_partial, (void *)small, (void *)one, (void *)clinv})
+                    (void *)dots_partial, (void *)small, (void *)one, (void *)clinv, (void *)clgath})
         if (p)
             (void)hipFree(p);
     if (host_small)
@@ -62,7 +62,7 @@ void Workspace::release() {
     nearblk = selfblk = nullptr;
     b = precond = gemv_partial = V = w = z = x = r = tmp = rin = xo = nullptr;
     dots_partial = small = one = host_small = nullptr;
-    clinv = nullptr;
+    clinv = clgath = nullptr;
     prec_kind = 0;
     plan = nullptr;
 }
@@ -78,9 +78,12 @@ void Workspace::ensure(const Problem &p, int format, int restart_m, int prec) {
     const int64_t nt = p.dev.n_tri, N = 3 * nt;
     const int64_t lda = (N + 63) / 64 * 64;
     plan = &p.dev;
+    const size_t clbytes = (size_t)std::max<int64_t>(p.dev.n_clusters, 1) * kClusterDim * kClusterDim * 8;
     if (N == this->N && format == this->format && restart_m <= this->m && b) {
         if (prec == 1 && !clinv)
-            clinv = (float *)dalloc((size_t)std::max<int64_t>(p.dev.n_clusters, 1) * kClusterDim * kClusterDim * 8);
+            clinv = (float *)dalloc(clbytes);
+        if (prec == 1 && format == kFmtBlocks && !clgath)
+            clgath = (float *)dalloc(clbytes);
         prec_kind = prec;
         return;
     }
@@ -88,7 +91,9 @@ void Workspace::ensure(const Problem &p, int format, int restart_m, int prec) {
     plan = &p.dev;
     prec_kind = prec;
     if (prec == 1)
-        clinv = (float *)dalloc((size_t)std::max<int64_t>(p.dev.n_clusters, 1) * kClusterDim * kClusterDim * 8);
+        clinv = (float *)dalloc(clbytes);
+    if (prec == 1 && format == kFmtBlocks)
+        clgath = (float *)dalloc(clbytes);
     this->N = N;
     this->format = format;
     this->m = restart_m;
@@ -419,6 +424,10 @@ static void assemble_into(Problem &p, Workspace &ws, int fmt, double s_re, doubl
         double *bpart = static_cast<double *>(ws.asm_scratch);
         mf_apply(p, kp, 0, 1, nullptr, nullptr, d_bc, nullptr, bpart, st);
         launch_finalize_b(p, mf_chunks(p.dev.n_tri), bpart, ws.asm_scratch, ws.b, st);
+        if (ws.prec_kind == 1) {
+            cluster_gather_mf(p, kp, ws.nearblk, ws.selfblk, ws.clgath, st);
+            cluster_inverse(p.dev, kFmtBlocks, ws.clgath, nullptr, ws.clinv, st);
+        }
         return;
     }
     if (profile)

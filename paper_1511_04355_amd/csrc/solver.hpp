@@ -20,6 +20,7 @@ struct Workspace {
     // preconditioner: 0 = 3x3 blocks (precond), 1 = element clusters (clinv)
     int prec_kind = 0;
     float *clinv = nullptr;
+    float *clgath = nullptr;  // matrix-free: the gathered cluster blocks before inversion
     const DevicePlan *plan = nullptr;
     void apply_precond(const double *v, double *z, hipStream_t st) const;
     double *host_small = nullptr;          // pinned
