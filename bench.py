@@ -66,7 +66,8 @@ def parse():
     ap.add_argument("--no-batched", action="store_true", help="skip the lockstep batched path")
     ap.add_argument("--cpu-freqs", type=int, default=1)
     ap.add_argument("--warm", choices=["none", "prev", "learned"], default="prev",
-                    help="initial guess of the optimised path")
+                    help="initial guess of the optimised path (porous_afs_matrix_free: learned = the network "
+                         "combined with the nearest sample's solution)")
     ap.add_argument("--workload", default="cavity_L4",
                     choices=["cavity_L4", "pmc_probe", "cavity_L2_batched", "blocks_batched", "porous_learned",
                              "porous_matrix_free", "porous_afs_matrix_free", "cavity_L4_afs"],
@@ -389,6 +390,9 @@ def run_porous_afs_matrix_free(args, afs, mg, np, torch):
                 near = min(solved, key=lambda q: abs(q - sk))
                 x0 = solved[near][None]
                 o.warm_start = afs.WARM_USER
+            if args.warm == "learned":
+                # the network's prediction combined with the nearest solution (trained after every solve)
+                o.warm_start = afs.WARM_LEARNED
             bc = torch.from_numpy((shape / sk)[None]).cuda()
             ts = time.perf_counter()
             out = P.solve(np.array([sk]), bc, o, x0=x0, want_ut=False)

@@ -424,8 +424,9 @@ int afsbem_afs_run(const afsbem_afs_params *p, int32_t K, int32_t Kt, afsbem_res
  * entries dof_idx[0..Kt-1] (the first K are the observation functions).  The
  * initial frequencies are solved in one call (assembly overlapped with the
  * Krylov phases).  Initial guess of each new frequency by opts->warm_start:
- * NONE zero; PREV, USER, LEARNED the solution at the nearest sampled
- * frequency; MODEL the prediction of the current order-M_H vector-fitting
+ * NONE zero; PREV, USER the solution at the nearest sampled frequency;
+ * LEARNED the warm-start network's prediction (trained after every solve of
+ * the run) combined with that nearest solution; MODEL the prediction of the current order-M_H vector-fitting
  * model (Section 3) for every unknown -- the residues of each unknown with the
  * model's poles, identified from all solved samples by least squares as in
  * Section 2.3, evaluated at the new s -- (nearest sample while there is no

@@ -1259,11 +1259,14 @@ int afsbem_afs_run_problem(afsbem_problem *p, const afsbem_afs_params *params, c
                         }
                     }
                     x0 = xs;
-                    oo.warm_start = AFSBEM_WARM_USER;
+                    // learned: the network's prediction combined with the nearest solution (the first
+                    // frequency's "previous" vector; later ones in the call follow their predecessor)
+                    oo.warm_start = o.warm_start == AFSBEM_WARM_LEARNED ? AFSBEM_WARM_LEARNED : AFSBEM_WARM_USER;
                 } else if (n > 1 && warm) {
-                    oo.warm_start = AFSBEM_WARM_PREV;  // the initial round: each from the one before
+                    // the initial round: each from the one before (learned: trained as the round goes)
+                    oo.warm_start = o.warm_start == AFSBEM_WARM_LEARNED ? AFSBEM_WARM_LEARNED : AFSBEM_WARM_PREV;
                 } else {
-                    oo.warm_start = AFSBEM_WARM_NONE;
+                    oo.warm_start = o.warm_start == AFSBEM_WARM_LEARNED ? AFSBEM_WARM_LEARNED : AFSBEM_WARM_NONE;
                 }
                 std::vector<afsbem_solve_stats> stats(n);
                 const int rc = afsbem_solve_device(p, n, sv.data(), dbc, x0, da, nullptr, nullptr, &oo, stats.data(),

@@ -103,8 +103,10 @@ def test_afs_multipoint_on_gpu_matches_oracle_afs(warm):
 
 
 def test_afs_model_warm_start_same_samples_fewer_products():
-    """AFS with the vector-fitting prediction as initial guess (WARM_MODEL)
-    takes the same samples as with zero starts (the solves agree to 1e-10).
+    """AFS with the vector-fitting prediction as initial guess (WARM_MODEL),
+    the nearest solution, or the learned network's start combined with it
+    (WARM_LEARNED, trained on the GPU after every solve of the run) takes the
+    same samples as with zero starts (the solves agree to 1e-10).
     On this well-damped cavity a zero start already converges in ~10 products,
     so a guess can at most pay for the one product its residual costs: the
     bound checked is zero-start products + one per adaptive sample."""
@@ -116,12 +118,13 @@ def test_afs_model_warm_start_same_samples_fewer_products():
     P = afs.Problem.from_mesh(mesh)
     params = afs.afs_params(T, eta, Ns)
     runs = {}
-    for name, warm in (("zero", afs.WARM_NONE), ("nearest", afs.WARM_PREV), ("model", afs.WARM_MODEL)):
+    for name, warm in (("zero", afs.WARM_NONE), ("nearest", afs.WARM_PREV), ("model", afs.WARM_MODEL),
+                       ("learned", afs.WARM_LEARNED)):
         runs[name] = P.afs(params, mesh.bc_shape, dofs, 4, load_kind=0,
                            opts=afs.SolveOptions(tol=1e-10, warm_start=warm))
         print(f"[afs] {name}: Nc={runs[name]['Nc']} matvecs={runs[name]['matvecs']}", flush=True)
     z = runs["zero"]
-    for name in ("nearest", "model"):
+    for name in ("nearest", "model", "learned"):
         r = runs[name]
         assert r["Nc"] == z["Nc"]
         assert np.max(np.abs(r["s"] - z["s"])) == 0.0
