@@ -394,8 +394,8 @@ int afsbem_time_synthesis_device(int32_t M, const double *poles, int32_t J, cons
  * matrix-core contraction, with the basis functions' values at z_k in place of
  * their time responses.  poles [M], s [J], z [n_z] (complex, host); d_X [J][N]
  * complex<double> (device, 16-byte aligned); d_H [N][n_z] complex<double>
- * (device, written).  Synchronises the stream; AFSBEM_EINVAL on bad sizes,
- * null pointers, alignment or too many poles.  With z = the FSM grid this
+ * (device, written); n_z <= 2^24.  Synchronises the stream; AFSBEM_EINVAL on
+ * bad sizes, null pointers, alignment or too many poles.  With z = the FSM grid this
  * feeds afsbem_fsm_invert_device (the model's Fourier-series inversion for
  * every unknown). */
 int afsbem_model_sample_device(int32_t M, const double *poles, int32_t J, const double *s, int64_t N,

@@ -1062,7 +1062,7 @@ int afsbem_model_sample_device(int32_t M, const double *poles, int32_t J, const 
         AFS_REQUIRE(M >= 1 && J >= 1 && N >= 0 && n_z >= 0, AFSBEM_EINVAL, "bad sizes");
         AFS_REQUIRE(poles && s && (N == 0 || d_X) && (n_z == 0 || z) && (N == 0 || n_z == 0 || d_H), AFSBEM_EINVAL,
                     "null pointer argument");
-        AFS_REQUIRE(n_z <= (1 << 30), AFSBEM_EINVAL, "too many frequencies");
+        AFS_REQUIRE(n_z <= (1 << 24), AFSBEM_EINVAL, "too many frequencies (at most 2^24)");  // 2 n_z columns
         if (N == 0 || n_z == 0)
             return (int)AFSBEM_OK;
         AFS_REQUIRE((reinterpret_cast<uintptr_t>(d_X) & 15) == 0 && (reinterpret_cast<uintptr_t>(d_H) & 7) == 0,
