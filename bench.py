@@ -65,7 +65,7 @@ def parse():
     ap.add_argument("--no-plain", action="store_true", help="skip the plain FP64 path")
     ap.add_argument("--no-batched", action="store_true", help="skip the lockstep batched path")
     ap.add_argument("--cpu-freqs", type=int, default=1)
-    ap.add_argument("--warm", choices=["none", "prev", "learned"], default="prev",
+    ap.add_argument("--warm", choices=["none", "prev", "extrap", "learned"], default="extrap",
                     help="initial guess of the optimised path (porous_afs_matrix_free: learned = the network "
                          "combined with the nearest sample's solution)")
     ap.add_argument("--workload", default="cavity_L4",
@@ -519,7 +519,8 @@ def main():
     plan_s = time.perf_counter() - t0
     N = P.N
 
-    warm = {"prev": afs.WARM_PREV, "none": afs.WARM_NONE, "learned": afs.WARM_LEARNED}[args.warm]
+    warm = {"prev": afs.WARM_PREV, "none": afs.WARM_NONE, "learned": afs.WARM_LEARNED,
+            "extrap": afs.WARM_EXTRAP}[args.warm]
     mixed = afs.SolveOptions(tol=args.tol, precision=afs.PREC_MIXED, warm_start=warm, profile=1, batch=args.batch)
     ms_mixed, out = timed(P, s, bc, mixed, args.steps, args.warmup, torch)
     st = out["stats"]
@@ -553,7 +554,8 @@ def main():
                                f"s_k=0.25+ik*pi/20, FP64 true rel. residual <= {args.tol}",
                    "path": "mixed: FP32 hi-plane GMRES(50) + FP64 refinement, "
                            + {"prev": "previous-s warm start", "none": "zero start",
-                              "learned": "learned + previous-s warm start"}[args.warm]
+                              "learned": "learned + previous-s warm start",
+                              "extrap": "warm start extrapolated linearly in s from the two previous s"}[args.warm]
                            + (", assembly of s_k+1 overlapped with GMRES of s_k" if args.batch != 1 else ""),
                    "plan_s": plan_s},
         # the dominant kernel (largest share of GPU time in the timed step) is

@@ -164,7 +164,9 @@ enum { AFSBEM_PREC_FP64 = 0, AFSBEM_PREC_MIXED = 1 };
  * previous solution; the network is skipped for 8 frequencies after three
  * gains below 1.3 over the previous solution alone, and retired for the
  * problem (no queries, no training: PREV behaviour) after three such closures
- * with no better gain in between.  Every guess x0 is rescaled (or the pair combined) to
+ * with no better gain in between.  EXTRAP: the linear extrapolation in s of
+ * s*a from the two preceding frequencies of the call (needs d_a_out; PREV for
+ * the second frequency, d_x0 for the first).  Every guess x0 is rescaled (or the pair combined) to
  * minimise ||b - A x0|| before the Krylov solve. */
 /* Failure handling of afsbem_solve_device / afsbem_solve (stats.fallback):
  * a starting guess whose residual is not finite or not below ||b|| is
@@ -176,7 +178,7 @@ enum { AFSBEM_PREC_FP64 = 0, AFSBEM_PREC_MIXED = 1 };
  * discards every inner correction. */
 enum { AFSBEM_FAULT_NAN_START = 1, AFSBEM_FAULT_STALL_INNER = 2 };
 enum { AFSBEM_WARM_NONE = 0, AFSBEM_WARM_PREV = 1, AFSBEM_WARM_USER = 2, AFSBEM_WARM_LEARNED = 3,
-       AFSBEM_WARM_MODEL = 4 /* afsbem_afs_run_problem only, see there */ };
+       AFSBEM_WARM_MODEL = 4 /* afsbem_afs_run_problem only, see there */, AFSBEM_WARM_EXTRAP = 5 };
 
 typedef struct {
     double tol;          /* target FP64 true relative residual ||b - A x|| / ||b|| (1e-6) */

@@ -16,6 +16,7 @@ from ._lib import (  # noqa: F401
     WARM_USER,
     WARM_LEARNED,
     WARM_MODEL,
+    WARM_EXTRAP,
     Problem,
     SolveOptions,
     solve_batched,

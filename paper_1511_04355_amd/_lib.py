@@ -19,7 +19,7 @@ _lib = None
 OK, EINVAL, ENOMEM, EDEVICE, ENOCONV, EBREAKDOWN, ENAN = 0, -1, -2, -3, -4, -5, -6
 FMT_C128, FMT_SPLIT = 0, 1
 PREC_FP64, PREC_MIXED = 0, 1
-WARM_NONE, WARM_PREV, WARM_USER, WARM_LEARNED, WARM_MODEL = 0, 1, 2, 3, 4
+WARM_NONE, WARM_PREV, WARM_USER, WARM_LEARNED, WARM_MODEL, WARM_EXTRAP = 0, 1, 2, 3, 4, 5
 
 
 class AfsbemError(RuntimeError):

@@ -434,8 +434,9 @@ int afsbem_solve_device(afsbem_problem *p, int32_t n_s, const double *s, const v
         AFS_REQUIRE(o.precision == AFSBEM_PREC_FP64 || o.precision == AFSBEM_PREC_MIXED, AFSBEM_EINVAL,
                     "unknown precision");
         AFS_REQUIRE(o.warm_start != AFSBEM_WARM_USER || d_x0, AFSBEM_EINVAL, "user warm start needs x0");
-        AFS_REQUIRE(o.warm_start >= AFSBEM_WARM_NONE && o.warm_start <= AFSBEM_WARM_LEARNED, AFSBEM_EINVAL,
-                    "unknown warm start");
+        AFS_REQUIRE((o.warm_start >= AFSBEM_WARM_NONE && o.warm_start <= AFSBEM_WARM_LEARNED) ||
+                        o.warm_start == AFSBEM_WARM_EXTRAP,
+                    AFSBEM_EINVAL, "unknown warm start");
         AFS_REQUIRE(o.precond == 0 || o.precond == 1, AFSBEM_EINVAL, "precond must be 0 or 1");
         AFS_REQUIRE(o.matrix_free == 0 || o.matrix_free == 1, AFSBEM_EINVAL, "matrix_free must be 0 or 1");
         AFS_REQUIRE(o.warm_start != AFSBEM_WARM_LEARNED || d_a_out, AFSBEM_EINVAL,
@@ -450,26 +451,34 @@ int afsbem_solve_device(afsbem_problem *p, int32_t n_s, const double *s, const v
             rc = solve_pipelined(p->p, o, n_s, s, bcd, static_cast<const double *>(d_x0), static_cast<double *>(d_a_out),
                                  static_cast<double *>(d_u_out), static_cast<double *>(d_t_out), stats, st);
         } else {
+            void *xbuf = nullptr;  // EXTRAP guesses
             for (int32_t k = 0; k < n_s; ++k) {
                 const double *bc = bcd + 2 * (size_t)k * N;
-                const double *x0 = nullptr;
-                if (o.warm_start == AFSBEM_WARM_USER)
-                    x0 = static_cast<const double *>(d_x0) + 2 * (size_t)k * N;
-                else if ((o.warm_start == AFSBEM_WARM_PREV || o.warm_start == AFSBEM_WARM_LEARNED) && k > 0 &&
-                         d_a_out)
-                    x0 = static_cast<const double *>(d_a_out) + 2 * (size_t)(k - 1) * N;
-                else if ((o.warm_start == AFSBEM_WARM_PREV || o.warm_start == AFSBEM_WARM_LEARNED) && k == 0)
-                    x0 = static_cast<const double *>(d_x0);  // the caller's previous solution (nullable)
+                if (o.warm_start == AFSBEM_WARM_EXTRAP && k >= 2 && !xbuf)
+                    AFS_HIP(hipMallocAsync(&xbuf, (size_t)N * 16, st));
+                const double *x0 = start_guess(o, k, N, s, static_cast<const double *>(d_x0),
+                                               static_cast<const double *>(d_a_out), static_cast<double *>(xbuf), st);
                 double *a = d_a_out ? static_cast<double *>(d_a_out) + 2 * (size_t)k * N : nullptr;
                 double *u = d_u_out ? static_cast<double *>(d_u_out) + 2 * (size_t)k * N : nullptr;
                 double *t = d_t_out ? static_cast<double *>(d_t_out) + 2 * (size_t)k * N : nullptr;
                 afsbem_solve_opts ok = o;
+                if (ok.warm_start == AFSBEM_WARM_EXTRAP)
+                    ok.warm_start = AFSBEM_WARM_PREV;
                 if (!x0 && ok.warm_start != AFSBEM_WARM_LEARNED)
                     ok.warm_start = AFSBEM_WARM_NONE;
-                int r = solve_one(p->p, ok, s[2 * k], s[2 * k + 1], bc, x0, a, u, t, stats ? &stats[k] : nullptr, st);
+                int r;
+                try {
+                    r = solve_one(p->p, ok, s[2 * k], s[2 * k + 1], bc, x0, a, u, t, stats ? &stats[k] : nullptr, st);
+                } catch (...) {
+                    if (xbuf)
+                        (void)hipFreeAsync(xbuf, st);
+                    throw;
+                }
                 if (r != AFSBEM_OK && rc == AFSBEM_OK)
                     rc = r;
             }
+            if (xbuf)
+                AFS_HIP(hipFreeAsync(xbuf, st));
         }
         if (rc == AFSBEM_ENOCONV)
             set_error("at least one frequency did not reach the tolerance");

@@ -1,6 +1,7 @@
 // Internal declarations of the afsbem library (not part of the public ABI).
 #pragma once
 
+#include <complex>
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -165,6 +166,12 @@ int gemv_chunks(int64_t N);
 void launch_gemv(int64_t N, int format, int precision, const void *A, const void *A_lo,
                  const double *x, double *y, double *partial, hipStream_t st,
                  hipEvent_t ev_begin = nullptr, hipEvent_t ev_end = nullptr);
+
+// starting guesses of a multi-frequency call (solver.cpp)
+bool extrap_coeffs(std::complex<double> s0, std::complex<double> s1, std::complex<double> s2,
+                   std::complex<double> &c1, std::complex<double> &c2);
+const double *start_guess(const afsbem_solve_opts &o, int32_t k, int64_t N, const double *s, const double *x0_user,
+                          const double *a_out, double *xbuf, hipStream_t st);
 
 // ------------------------------------------------------ vector kernels --
 // All vectors are complex<double> interleaved, length N (complex entries).

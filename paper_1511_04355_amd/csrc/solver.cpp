@@ -37,6 +37,7 @@ Workspace::~Workspace() { release(); }
 void Workspace::release() {
     for (void *p : {(void *)A, (void *)A_lo, (void *)nearblk, (void *)selfblk, (void *)b, (void *)precond, (void *)asm_scratch, (void *)gemv_partial,
                     (void *)V, (void *)w, (void *)z, (void *)x, (void *)r, (void *)tmp, (void *)rin, (void *)xo,
+                    (void *)xstart,
                     (void *)dots_partial, (void *)small, (void *)one, (void *)clinv, (void *)clgath})
         if (p)
             (void)hipFree(p);
@@ -60,7 +61,7 @@ void Workspace::release() {
     m = 0;
     A = A_lo = asm_scratch = nullptr;
     nearblk = selfblk = nullptr;
-    b = precond = gemv_partial = V = w = z = x = r = tmp = rin = xo = nullptr;
+    b = precond = gemv_partial = V = w = z = x = r = tmp = rin = xo = xstart = nullptr;
     dots_partial = small = one = host_small = nullptr;
     clinv = clgath = nullptr;
     prec_kind = 0;
@@ -118,6 +119,7 @@ void Workspace::ensure(const Problem &p, int format, int restart_m, int prec) {
     tmp = (double *)dalloc((size_t)N * 16);
     rin = (double *)dalloc((size_t)N * 16);
     xo = (double *)dalloc((size_t)N * 16);
+    xstart = (double *)dalloc((size_t)N * 16);
     dots_partial = (double *)dalloc(mdot_scratch_bytes(N, restart_m + 2));
     AFS_HIP(hipMemset(dots_partial, 0, kMdotCounterBytes));  // arrival counters
     small = (double *)dalloc((size_t)(4 * (restart_m + 2)) * 16);
@@ -642,6 +644,46 @@ int solve_one(Problem &p, const afsbem_solve_opts &o, double s_re, double s_im, 
     return rc;
 }
 
+// Linear extrapolation in s of y(s) = s a(s) from the solutions at s0 and s1
+// to s2: a(s2) ~ c1 a(s1) + c2 a(s0).  False when s0 = s1 or s2 = 0.
+bool extrap_coeffs(std::complex<double> s0, std::complex<double> s1, std::complex<double> s2,
+                   std::complex<double> &c1, std::complex<double> &c2) {
+    const std::complex<double> d = s1 - s0;
+    if (std::abs(d) == 0.0 || std::abs(s2) == 0.0)
+        return false;
+    const std::complex<double> al = (s2 - s1) / d;
+    c1 = s1 * (1.0 + al) / s2;
+    c2 = -al * s0 / s2;
+    return std::isfinite(c1.real()) && std::isfinite(c1.imag()) && std::isfinite(c2.real()) &&
+           std::isfinite(c2.imag());
+}
+
+// Starting guess of frequency k of a call for PREV / LEARNED / EXTRAP / USER
+// (nullptr: zero start); EXTRAP forms its vector in xbuf on stream st.
+const double *start_guess(const afsbem_solve_opts &o, int32_t k, int64_t N, const double *s, const double *x0_user,
+                          const double *a_out, double *xbuf, hipStream_t st) {
+    using C = std::complex<double>;
+    if (o.warm_start == AFSBEM_WARM_USER)
+        return x0_user + 2 * (size_t)k * N;
+    const bool prev_like = o.warm_start == AFSBEM_WARM_PREV || o.warm_start == AFSBEM_WARM_LEARNED ||
+                           o.warm_start == AFSBEM_WARM_EXTRAP;
+    if (!prev_like)
+        return nullptr;
+    if (k == 0)
+        return x0_user;  // the caller's previous solution (nullable)
+    if (!a_out)
+        return nullptr;
+    const double *a1 = a_out + 2 * (size_t)(k - 1) * N;
+    C c1, c2;
+    if (o.warm_start == AFSBEM_WARM_EXTRAP && k >= 2 && xbuf &&
+        extrap_coeffs(C(s[2 * (k - 2)], s[2 * (k - 2) + 1]), C(s[2 * (k - 1)], s[2 * (k - 1) + 1]),
+                      C(s[2 * k], s[2 * k + 1]), c1, c2)) {
+        vec_axpby(N, c1.real(), c1.imag(), a1, c2.real(), c2.imag(), a_out + 2 * (size_t)(k - 2) * N, xbuf, st);
+        return xbuf;
+    }
+    return a1;
+}
+
 // Two frequencies in flight: the FP64 assembly of frequency k+1 (VALU-bound)
 // runs on one library stream while the Krylov phase of frequency k
 // (HBM-bound GEMVs, latency-bound Arnoldi steps with host round trips) runs on
@@ -698,14 +740,10 @@ int solve_pipelined(Problem &p, const afsbem_solve_opts &o, int32_t n_s, const d
             if (k + 1 < n_s)
                 enqueue_asm(k + 1);
             AFS_HIP(hipStreamWaitEvent(SS, a1[k], 0));
-            const double *x0 = nullptr;
-            if (o.warm_start == AFSBEM_WARM_USER)
-                x0 = x0_user + 2 * (size_t)k * N;
-            else if ((o.warm_start == AFSBEM_WARM_PREV || o.warm_start == AFSBEM_WARM_LEARNED) && k > 0 && a_out)
-                x0 = a_out + 2 * (size_t)(k - 1) * N;
-            else if ((o.warm_start == AFSBEM_WARM_PREV || o.warm_start == AFSBEM_WARM_LEARNED) && k == 0)
-                x0 = x0_user;  // the caller's previous solution (nullable)
+            const double *x0 = start_guess(o, k, N, s, x0_user, a_out, W[k % 2]->xstart, SS);
             afsbem_solve_opts ok = o;
+            if (ok.warm_start == AFSBEM_WARM_EXTRAP)
+                ok.warm_start = AFSBEM_WARM_PREV;  // the guess is formed; the solve treats it as any other
             if (!x0 && ok.warm_start != AFSBEM_WARM_LEARNED)
                 ok.warm_start = AFSBEM_WARM_NONE;
             int r = krylov_phase(p, *W[k % 2], ok, fmt, s[2 * k], s[2 * k + 1], bc + 2 * (size_t)k * N, x0,

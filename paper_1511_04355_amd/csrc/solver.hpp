@@ -15,6 +15,7 @@ struct Workspace {
     double *gemv_partial = nullptr;
     double *V = nullptr, *w = nullptr, *z = nullptr, *x = nullptr, *r = nullptr, *tmp = nullptr;
     double *rin = nullptr, *xo = nullptr;  // mixed: outer residual and outer iterate
+    double *xstart = nullptr;              // extrapolated starting guess
     double *dots_partial = nullptr, *small = nullptr;
     double *one = nullptr;                 // device complex 1 + 0i
     // preconditioner: 0 = 3x3 blocks (precond), 1 = element clusters (clinv)

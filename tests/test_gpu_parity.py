@@ -194,7 +194,8 @@ def test_large_cavity_sampled_rows():
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_solve_warm_starts(prec):
-    """Previous-frequency and user warm starts reach the same solutions."""
+    """Previous-frequency, user and extrapolated warm starts reach the same
+    solutions, pipelined and one frequency at a time."""
     afs, bem = _afs(), _oracle()
     mesh, s, bc = _cavity_workload(2, 16)
     s, bc = s[:6], bc[:6]
@@ -205,13 +206,16 @@ def test_solve_warm_starts(prec):
     a = out["a"].cpu().numpy()
     x0 = torch.roll(out["a"], 1, 0).contiguous()  # a neighbouring frequency's solution as a user guess
     out2 = P.solve(s, bcd, afs.SolveOptions(tol=1e-8, precision=p, warm_start=afs.WARM_USER), x0=x0)
-    a2 = out2["a"].cpu().numpy()
+    runs = [(a, out["stats"]), (out2["a"].cpu().numpy(), out2["stats"])]
+    for batch in (0, 1):
+        o3 = P.solve(s, bcd, afs.SolveOptions(tol=1e-8, precision=p, warm_start=afs.WARM_EXTRAP, batch=batch))
+        runs.append((o3["a"].cpu().numpy(), o3["stats"]))
     for k, sk in enumerate(s):
         A, b = bem.assemble(mesh, sk)
         xo = bem.solve_dense(A, b)
-        for sol, st in ((a[k], out["stats"][k]), (a2[k], out2["stats"][k])):
-            assert st["rel_res_fp64"] <= 1e-8
-            assert np.linalg.norm(sol - xo) / np.linalg.norm(xo) <= 1e-6
+        for sols, sts in runs:
+            assert sts[k]["rel_res_fp64"] <= 1e-8
+            assert np.linalg.norm(sols[k] - xo) / np.linalg.norm(xo) <= 1e-6
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
