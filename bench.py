@@ -35,6 +35,7 @@ WRITE_SIZE 1,048,576 KiB).
 import argparse
 import json
 import os
+import subprocess
 import sys
 import time
 
@@ -114,9 +115,26 @@ def cpu_baseline(mesh, s_list, nfreq):
         bem.solve_dense(A, b)
         del A
     dt = time.perf_counter() - t0
+    # the oracle's assembly rate on a bounded sample of rows (160 elements, all
+    # columns), measured on all cores here and on one core in a child process
+    rows = np.arange(0, mesh.n_tri, max(1, mesh.n_tri // 160))[:160]
+    ta = time.perf_counter()
+    bem.assemble(mesh, s_list[1], rows=rows)
+    t_all = time.perf_counter() - ta
+    code = ("import sys, time, numpy as np; sys.path.insert(0, %r); from oracle import bem; "
+            "from synth import meshgen as mg; m = mg.cavity(%d); r = np.arange(0, m.n_tri, max(1, m.n_tri // 160))[:160]; "
+            "t = time.perf_counter(); bem.assemble(m, %r, rows=r); print(time.perf_counter() - t)"
+            % (os.path.dirname(os.path.abspath(__file__)), int(round(np.log(mesh.n_tri / 20) / np.log(4))),
+               complex(s_list[1])))
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
+    t_one = float(subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True,
+                                 check=True).stdout.strip().splitlines()[-1])
+    n_rows = 3 * len(rows)
     return {"value": nfreq / dt, "unit": "frequency solves/s", "cores": threads, "kind": "oracle",
             "sample": f"{nfreq} frequency of the same workload (s_1): FP64 oracle assembly (C, OpenMP) "
-                      f"+ LAPACK LU solve, {dt:.1f} s"}
+                      f"+ LAPACK LU solve, {dt:.1f} s",
+            "assembly_rows_per_s": {"cores_all": n_rows / t_all, "cores_1": n_rows / t_one,
+                                    "sample": f"{n_rows} rows x {3 * mesh.n_tri} columns at s_1"}}
 
 
 def _bcs(mesh, s, torch, np):
