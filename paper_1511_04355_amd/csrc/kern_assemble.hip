@@ -395,7 +395,7 @@ __device__ __forceinline__ double group_sum(double v) {
 
 template <int FMT>
 __global__ __launch_bounds__(256) void near_assemble_kernel(
-    int64_t nt, int64_t lda, int64_t nnz, KernelParams kp, Rule7Args rule, const double *__restrict__ colx,
+    int64_t /*nt*/, int64_t lda, int64_t nnz, KernelParams kp, Rule7Args rule, const double *__restrict__ colx,
     const double *__restrict__ coly, const double *__restrict__ colz, const double *__restrict__ src,
     const double *__restrict__ bc, const double *__restrict__ coef, const int32_t *__restrict__ near_row,
     const int32_t *__restrict__ near_col, const int32_t *__restrict__ near_order, const int64_t *__restrict__ leaf_ptr,

@@ -17,7 +17,7 @@ struct cf {
 };
 
 template <int FMT>
-__device__ __forceinline__ cf load_entry(const void *A, const void *A_lo, int64_t lda, int64_t row, int64_t col) {
+__device__ __forceinline__ cf load_entry(const void *A, const void * /*A_lo*/, int64_t lda, int64_t row, int64_t col) {
     const int64_t o = col * lda + row;
     if (FMT == AFSBEM_FMT_C128) {
         const double2 v = static_cast<const double2 *>(A)[o];

@@ -175,7 +175,7 @@ static void residual(const Operator &op, Workspace &ws, const double *b, const d
     vec_sub(op.N, b, ws.tmp, r, st);
 }
 
-GmresResult gmres(const Operator &op, Workspace &ws, int64_t n_tri, const double *rhs, double rhs_norm,
+GmresResult gmres(const Operator &op, Workspace &ws, int64_t /*n_tri*/, const double *rhs, double rhs_norm,
                   double *x, bool x_is_zero, double tol_abs, int restart, int max_iter, hipStream_t st,
                   bool verify, const double *r0, double r0_norm) {
     const int64_t N = op.N;
