@@ -40,5 +40,12 @@ def lib():
         L.orc_blocks.argtypes = [P, i64, P, d, d, P, P, i64, P, P, P]
         L.orc_assemble_rows.argtypes = [P, i64, P, P, P, d, d, P, P, i64, P, P, P]
         L.orc_rowsum_H_static.argtypes = [P, i64, P, P, P, P]
+        L.orc_gauss6.argtypes = [P, P]
+        L.orc_lagrange6.argtypes = [P]
+        L.orc_q6_map.argtypes = [P, i64, P, P]
+        L.orc_nys_nodes.argtypes = [P, i64, P, P]
+        L.orc_nys_element.argtypes = [P, P, ctypes.c_int, d, d, P, P, P, P]
+        L.orc_nys_assemble_rows.argtypes = [P, i64, P, P, P, d, d, P, P, i64, P, P, P]
+        L.orc_nys_rowsum_H_static.argtypes = [P, i64, P, P, P, P]
         _lib = L
     return _lib

@@ -33,6 +33,9 @@
  *    coordinates about the centroid (three sub-triangles, Gauss-Legendre
  *    n_theta x n_rho) with the static 1/r^2 part of T taken as a Cauchy
  *    principal value over a circular exclusion.
+ *
+ * A second discretisation, the paper's own (curved six-node triangles and
+ * the locally-corrected Nystrom method), is at the end of this file.
  */
 #include <complex.h>
 #include <math.h>
@@ -616,5 +619,481 @@ int orc_rowsum_H_static(const double *xyz, int64_t nt, const int32_t *tri, const
         memcpy(out9 + 9 * me, acc, sizeof acc);
     }
     free(t);
+    return 0;
+}
+
+/* ========================================================================= */
+/* Curved quadratic triangles, locally-corrected Nystrom discretisation      */
+/* (paper Section 2.1: six-node elements; the unknowns sit at the points of  */
+/* the 6-point Gauss rule, n_k = 6 n_e; nearly singular integrals by         */
+/* recursive subdivision, singular ones in polar coordinates).               */
+/*                                                                           */
+/* Element map x(xi, eta) = sum_k N_k(xi, eta) P_k on the reference triangle */
+/* {xi, eta >= 0, xi + eta <= 1}; P0, P1, P2 corners, P3 on edge 01, P4 on   */
+/* edge 12, P5 on edge 20; normal (x_xi x x_eta) / J, J = |x_xi x x_eta|.    */
+/* Unknown q of element e (index 6 e + q) sits at rule point q.  Block of    */
+/* target node i (point x_i on element e_i) and node q of element e:         */
+/*   far  (|x_i - x_e(1/3, 1/3)| >= far_ratio h_e, h_e the longest corner    */
+/*         chord): w_q J_q K(x_i, y_q) (the rule itself);                    */
+/*   near: int_e K(x_i, y) L_q dG, recursive 4-way subdivision of the        */
+/*         parameter triangle with the same test on each piece's image, the  */
+/*         7-point rule on the leaves (locally corrected weights);           */
+/*   self (e = e_i): polar coordinates about the node in the parameter plane */
+/*         (three sub-triangles, each split at the foot of the perpendicular */
+/*         to its edge, Gauss-Legendre n_theta x n_rho per half); for T the  */
+/*         leading rho^-1 term of the node's own basis function is removed   */
+/*         and restored as a principal value over a circular exclusion;      */
+/*         1/2 I added to the node's own block.                              */
+/* L_q: the quadratic interpolant through the six rule points.               */
+/* ========================================================================= */
+
+/* 6-point degree-4 rule on the triangle, closed forms of its two orbits.
+ * Point q: orbit g = q / 3 (a, then b); barycentric (l0, l1, l2) all equal to
+ * the orbit's value except l_{q % 3} = 1 - 2 * value; (xi, eta) = (l1, l2);
+ * weights include the reference area 1/2. */
+static void gauss6(double pt[6][2], double w[6])
+{
+    double s10 = sqrt(10.0);
+    double r = sqrt(38.0 - 44.0 * sqrt(0.4));
+    double q = sqrt(213125.0 - 53320.0 * s10);
+    double val[2] = {(8.0 - s10 + r) / 18.0, (8.0 - s10 - r) / 18.0};
+    double wt[2] = {(620.0 + q) / 3720.0, (620.0 - q) / 3720.0};
+    for (int g = 0; g < 2; ++g)
+        for (int k = 0; k < 3; ++k) {
+            double l[3] = {val[g], val[g], val[g]};
+            l[k] = 1.0 - 2.0 * val[g];
+            pt[3 * g + k][0] = l[1];
+            pt[3 * g + k][1] = l[2];
+            w[3 * g + k] = 0.5 * wt[g];
+        }
+}
+
+static void mono6(double xi, double eta, double m[6])
+{
+    m[0] = 1.0;
+    m[1] = xi;
+    m[2] = eta;
+    m[3] = xi * xi;
+    m[4] = xi * eta;
+    m[5] = eta * eta;
+}
+
+/* Lagrange basis on the rule points: L_b = sum_k C[b][k] m_k with
+ * L_b(pt_c) = delta_bc, i.e. C = (V^-1)^T, V[c][k] = m_k(pt_c); Gauss-Jordan
+ * elimination with partial pivoting. */
+static void lagrange6(const double pt[6][2], double C[6][6])
+{
+    double M[6][12];
+    for (int c = 0; c < 6; ++c) {
+        mono6(pt[c][0], pt[c][1], M[c]);
+        for (int k = 0; k < 6; ++k)
+            M[c][6 + k] = (c == k) ? 1.0 : 0.0;
+    }
+    for (int col = 0; col < 6; ++col) {
+        int piv = col;
+        for (int r = col + 1; r < 6; ++r)
+            if (fabs(M[r][col]) > fabs(M[piv][col]))
+                piv = r;
+        for (int k = 0; k < 12; ++k) {
+            double t = M[col][k];
+            M[col][k] = M[piv][k];
+            M[piv][k] = t;
+        }
+        double d = M[col][col];
+        for (int k = 0; k < 12; ++k)
+            M[col][k] /= d;
+        for (int r = 0; r < 6; ++r) {
+            if (r == col)
+                continue;
+            double f = M[r][col];
+            for (int k = 0; k < 12; ++k)
+                M[r][k] -= f * M[col][k];
+        }
+    }
+    /* M[:, 6:] = V^-1 */
+    for (int b = 0; b < 6; ++b)
+        for (int k = 0; k < 6; ++k)
+            C[b][k] = M[k][6 + b];
+}
+
+static void lag_eval(const double C[6][6], double xi, double eta, double L[6])
+{
+    double m[6];
+    mono6(xi, eta, m);
+    for (int b = 0; b < 6; ++b) {
+        L[b] = 0.0;
+        for (int k = 0; k < 6; ++k)
+            L[b] += C[b][k] * m[k];
+    }
+}
+
+/* quadratic map: point, unit normal, Jacobian, tangent vectors */
+static void q6_map(const double P[6][3], double xi, double eta, double y[3], double n[3], double *J,
+                   double dxi[3], double deta[3])
+{
+    double l0 = 1.0 - xi - eta, l1 = xi, l2 = eta;
+    double N[6] = {l0 * (2.0 * l0 - 1.0), l1 * (2.0 * l1 - 1.0), l2 * (2.0 * l2 - 1.0),
+                   4.0 * l0 * l1, 4.0 * l1 * l2, 4.0 * l2 * l0};
+    double Nx[6] = {-(4.0 * l0 - 1.0), 4.0 * l1 - 1.0, 0.0, 4.0 * (l0 - l1), 4.0 * l2, -4.0 * l2};
+    double Ne[6] = {-(4.0 * l0 - 1.0), 0.0, 4.0 * l2 - 1.0, -4.0 * l1, 4.0 * l1, 4.0 * (l0 - l2)};
+    for (int k = 0; k < 3; ++k) {
+        y[k] = dxi[k] = deta[k] = 0.0;
+        for (int a = 0; a < 6; ++a) {
+            y[k] += N[a] * P[a][k];
+            dxi[k] += Nx[a] * P[a][k];
+            deta[k] += Ne[a] * P[a][k];
+        }
+    }
+    double cr[3] = {dxi[1] * deta[2] - dxi[2] * deta[1], dxi[2] * deta[0] - dxi[0] * deta[2],
+                    dxi[0] * deta[1] - dxi[1] * deta[0]};
+    *J = sqrt(cr[0] * cr[0] + cr[1] * cr[1] + cr[2] * cr[2]);
+    for (int k = 0; k < 3; ++k)
+        n[k] = cr[k] / *J;
+}
+
+typedef struct {
+    double P[6][3];
+    double c[3];   /* x(1/3, 1/3) */
+    double h;      /* longest chord between the corners */
+} q6_t;
+
+static void q6_make(q6_t *e, const double *xyz, const int32_t *t6)
+{
+    for (int a = 0; a < 6; ++a)
+        for (int k = 0; k < 3; ++k)
+            e->P[a][k] = xyz[3 * t6[a] + k];
+    double n[3], J, d1[3], d2[3];
+    q6_map(e->P, 1.0 / 3.0, 1.0 / 3.0, e->c, n, &J, d1, d2);
+    double h = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        const double *u = e->P[a], *v = e->P[(a + 1) % 3];
+        double d = sqrt((u[0] - v[0]) * (u[0] - v[0]) + (u[1] - v[1]) * (u[1] - v[1]) + (u[2] - v[2]) * (u[2] - v[2]));
+        if (d > h)
+            h = d;
+    }
+    e->h = h;
+}
+
+static q6_t *build_q6(const double *xyz, int64_t nt, const int32_t *tri6)
+{
+    q6_t *e = malloc(sizeof(q6_t) * (size_t)nt);
+    for (int64_t k = 0; k < nt; ++k)
+        q6_make(&e[k], xyz, tri6 + 6 * k);
+    return e;
+}
+
+static double dist3(const double a[3], const double b[3])
+{
+    return sqrt((a[0] - b[0]) * (a[0] - b[0]) + (a[1] - b[1]) * (a[1] - b[1]) + (a[2] - b[2]) * (a[2] - b[2]));
+}
+
+/* int over the parameter sub-triangle q of K(x, y) L_b J, b = 0..5 */
+static void nys_regular(const q6_t *e, const double C[6][6], const double x[3], const double q[3][2], cplx s,
+                        const material_t *m, const policy_t *pol, int depth, cplx G[6][9], cplx H[6][9])
+{
+    double Y[3][3], yc[3], nn[3], J, d1[3], d2[3];
+    for (int k = 0; k < 3; ++k)
+        q6_map(e->P, q[k][0], q[k][1], Y[k], nn, &J, d1, d2);
+    q6_map(e->P, (q[0][0] + q[1][0] + q[2][0]) / 3.0, (q[0][1] + q[1][1] + q[2][1]) / 3.0, yc, nn, &J, d1, d2);
+    double h = 0.0;
+    for (int k = 0; k < 3; ++k) {
+        double d = dist3(Y[k], Y[(k + 1) % 3]);
+        if (d > h)
+            h = d;
+    }
+    if (dist3(x, yc) < pol->far_ratio * h && depth < pol->max_subdiv) {
+        double m01[2] = {0.5 * (q[0][0] + q[1][0]), 0.5 * (q[0][1] + q[1][1])};
+        double m12[2] = {0.5 * (q[1][0] + q[2][0]), 0.5 * (q[1][1] + q[2][1])};
+        double m20[2] = {0.5 * (q[2][0] + q[0][0]), 0.5 * (q[2][1] + q[0][1])};
+        double ch[4][3][2] = {{{q[0][0], q[0][1]}, {m01[0], m01[1]}, {m20[0], m20[1]}},
+                              {{m01[0], m01[1]}, {q[1][0], q[1][1]}, {m12[0], m12[1]}},
+                              {{m20[0], m20[1]}, {m12[0], m12[1]}, {q[2][0], q[2][1]}},
+                              {{m01[0], m01[1]}, {m12[0], m12[1]}, {m20[0], m20[1]}}};
+        for (int c = 0; c < 4; ++c)
+            nys_regular(e, C, x, (const double(*)[2])ch[c], s, m, pol, depth + 1, G, H);
+        return;
+    }
+    double bary[7][3], w7[7];
+    radon7(bary, w7);
+    double area = 0.5 * fabs((q[1][0] - q[0][0]) * (q[2][1] - q[0][1]) - (q[2][0] - q[0][0]) * (q[1][1] - q[0][1]));
+    for (int p = 0; p < 7; ++p) {
+        double xi = bary[p][0] * q[0][0] + bary[p][1] * q[1][0] + bary[p][2] * q[2][0];
+        double eta = bary[p][0] * q[0][1] + bary[p][1] * q[1][1] + bary[p][2] * q[2][1];
+        double y[3], n[3], Jy, a1[3], a2[3], L[6];
+        q6_map(e->P, xi, eta, y, n, &Jy, a1, a2);
+        lag_eval(C, xi, eta, L);
+        cplx U[9], T[9];
+        kernel_UT(s, m, x, y, n, 0, U, T);
+        double w = w7[p] * area * Jy;
+        for (int b = 0; b < 6; ++b)
+            for (int k = 0; k < 9; ++k) {
+                G[b][k] += w * L[b] * U[k];
+                H[b][k] += w * L[b] * T[k];
+            }
+    }
+}
+
+/* self element, target at rule point b0 of the element */
+static void nys_self(const q6_t *e, const double C[6][6], const double pt[6][2], int b0, cplx s, const material_t *m,
+                     const policy_t *pol, cplx G[6][9], cplx H[6][9])
+{
+    double xi0 = pt[b0][0], eta0 = pt[b0][1];
+    double x[3], n0[3], J0, a1[3], a2[3];
+    q6_map(e->P, xi0, eta0, x, n0, &J0, a1, a2);
+    double *gt = malloc(sizeof(double) * 2 * pol->n_theta);
+    double *gr = malloc(sizeof(double) * 2 * pol->n_rho);
+    gauss_legendre(pol->n_theta, gt, gt + pol->n_theta);
+    gauss_legendre(pol->n_rho, gr, gr + pol->n_rho);
+    const double V[3][2] = {{0.0, 0.0}, {1.0, 0.0}, {0.0, 1.0}};
+    for (int k = 0; k < 3; ++k) {
+        double va[2] = {V[k][0] - xi0, V[k][1] - eta0};
+        double vb[2] = {V[(k + 1) % 3][0] - xi0, V[(k + 1) % 3][1] - eta0};
+        double ta = atan2(va[1], va[0]), tb = atan2(vb[1], vb[0]);
+        if (tb < ta)
+            tb += 2.0 * ORC_PI;
+        double ed[2] = {vb[0] - va[0], vb[1] - va[1]};
+        double tt = -(va[0] * ed[0] + va[1] * ed[1]) / (ed[0] * ed[0] + ed[1] * ed[1]);
+        double foot[2] = {va[0] + tt * ed[0], va[1] + tt * ed[1]};
+        double p = sqrt(foot[0] * foot[0] + foot[1] * foot[1]);
+        double phi = atan2(foot[1], foot[0]);
+        while (phi < ta)
+            phi += 2.0 * ORC_PI;
+        double lim[3] = {ta, phi, tb};
+        for (int half = 0; half < 2; ++half) {
+            double t0 = lim[half], t1 = lim[half + 1];
+            for (int it = 0; it < pol->n_theta; ++it) {
+                double th = t0 + 0.5 * (t1 - t0) * (1.0 + gt[it]);
+                double wth = 0.5 * (t1 - t0) * gt[pol->n_theta + it];
+                double R = p / cos(th - phi);
+                double c = cos(th), sn = sin(th);
+                double A[3], xa[3];
+                for (int d = 0; d < 3; ++d) {
+                    A[d] = a1[d] * c + a2[d] * sn;
+                    xa[d] = x[d] + A[d];
+                }
+                double Alen = sqrt(A[0] * A[0] + A[1] * A[1] + A[2] * A[2]);
+                cplx F1[9];
+                static_T0(m, x, xa, n0, F1);
+                for (int q = 0; q < 9; ++q)
+                    F1[q] *= J0;
+                for (int ir = 0; ir < pol->n_rho; ++ir) {
+                    double rho = 0.5 * R * (1.0 + gr[ir]);
+                    double wr = 0.5 * R * gr[pol->n_rho + ir];
+                    double xi = xi0 + rho * c, eta = eta0 + rho * sn;
+                    double y[3], n[3], Jy, d1[3], d2[3], L[6];
+                    q6_map(e->P, xi, eta, y, n, &Jy, d1, d2);
+                    lag_eval(C, xi, eta, L);
+                    cplx U[9], T[9];
+                    kernel_UT(s, m, x, y, n, 0, U, T);
+                    double w = wth * wr * rho * Jy;
+                    for (int b = 0; b < 6; ++b)
+                        for (int q = 0; q < 9; ++q) {
+                            G[b][q] += w * L[b] * U[q];
+                            H[b][q] += w * L[b] * T[q];
+                        }
+                    for (int q = 0; q < 9; ++q)
+                        H[b0][q] -= wth * wr / rho * F1[q];
+                }
+                double lr = log(R * Alen);
+                for (int q = 0; q < 9; ++q)
+                    H[b0][q] += wth * F1[q] * lr;
+            }
+        }
+    }
+    H[b0][0] += 0.5;
+    H[b0][4] += 0.5;
+    H[b0][8] += 0.5;
+    free(gt);
+    free(gr);
+}
+
+/* G, H blocks of target node i against the six nodes of element e */
+static void nys_blocks(const q6_t *els, const double pt[6][2], const double w6[6], const double C[6][6], int64_t i,
+                       int64_t e, cplx s, const material_t *m, const policy_t *pol, cplx G[6][9], cplx H[6][9])
+{
+    for (int b = 0; b < 6; ++b)
+        for (int q = 0; q < 9; ++q)
+            G[b][q] = H[b][q] = 0.0;
+    int64_t ei = i / 6;
+    int bi = (int)(i % 6);
+    if (e == ei) {
+        nys_self(&els[e], C, pt, bi, s, m, pol, G, H);
+        return;
+    }
+    double x[3], nx[3], Jx, d1[3], d2[3];
+    q6_map(els[ei].P, pt[bi][0], pt[bi][1], x, nx, &Jx, d1, d2);
+    if (dist3(x, els[e].c) < pol->far_ratio * els[e].h) {
+        const double ref[3][2] = {{0.0, 0.0}, {1.0, 0.0}, {0.0, 1.0}};
+        nys_regular(&els[e], C, x, ref, s, m, pol, 0, G, H);
+        return;
+    }
+    for (int q = 0; q < 6; ++q) {
+        double y[3], n[3], Jy;
+        q6_map(els[e].P, pt[q][0], pt[q][1], y, n, &Jy, d1, d2);
+        cplx U[9], T[9];
+        kernel_UT(s, m, x, y, n, 0, U, T);
+        for (int k = 0; k < 9; ++k) {
+            G[q][k] = w6[q] * Jy * U[k];
+            H[q][k] = w6[q] * Jy * T[k];
+        }
+    }
+}
+
+int orc_gauss6(double pt[12], double w[6])
+{
+    gauss6((double(*)[2])pt, w);
+    return 0;
+}
+
+/* C[b][k]: coefficients of L_b on (1, xi, eta, xi^2, xi eta, eta^2) */
+int orc_lagrange6(double C[36])
+{
+    double pt[6][2], w[6];
+    gauss6(pt, w);
+    lagrange6(pt, (double(*)[6])C);
+    return 0;
+}
+
+/* out8 per parameter point: y(3), n(3), J, 0 */
+int orc_q6_map(const double P18[18], int64_t n_pts, const double *xieta, double *out8)
+{
+    for (int64_t k = 0; k < n_pts; ++k) {
+        double d1[3], d2[3];
+        q6_map((const double(*)[3])P18, xieta[2 * k], xieta[2 * k + 1], out8 + 8 * k, out8 + 8 * k + 3,
+               out8 + 8 * k + 6, d1, d2);
+        out8[8 * k + 7] = 0.0;
+    }
+    return 0;
+}
+
+/* Nystrom nodes: out8[6 e + q] = y(3), n(3), w_q J_q, 0 */
+int orc_nys_nodes(const double *xyz, int64_t nt, const int32_t *tri6, double *out8)
+{
+    double pt[6][2], w6[6];
+    gauss6(pt, w6);
+    q6_t *els = build_q6(xyz, nt, tri6);
+    for (int64_t e = 0; e < nt; ++e)
+        for (int q = 0; q < 6; ++q) {
+            double *o = out8 + 8 * (6 * e + q), d1[3], d2[3], J;
+            q6_map(els[e].P, pt[q][0], pt[q][1], o, o + 3, &J, d1, d2);
+            o[6] = w6[q] * J;
+            o[7] = 0.0;
+        }
+    free(els);
+    return 0;
+}
+
+/* one element's six G, H blocks seen from an arbitrary point x: the self
+ * rule about rule point b0 when b0 >= 0, else the subdivision rule (which
+ * takes the 7-point rule on the whole element when x is far) */
+int orc_nys_element(const double P18[18], const double x[3], int b0, double sr, double si, const double mat[3],
+                    const double pol[4], double *G_out, double *H_out)
+{
+    q6_t e;
+    memcpy(e.P, P18, sizeof e.P);
+    material_t m = make_material(mat);
+    policy_t p = make_policy(pol);
+    double pt[6][2], w6[6], C[6][6];
+    gauss6(pt, w6);
+    lagrange6(pt, C);
+    cplx G[6][9], H[6][9];
+    for (int b = 0; b < 6; ++b)
+        for (int q = 0; q < 9; ++q)
+            G[b][q] = H[b][q] = 0.0;
+    if (b0 >= 0) {
+        nys_self(&e, C, pt, b0, sr + I * si, &m, &p, G, H);
+    } else {
+        const double ref[3][2] = {{0.0, 0.0}, {1.0, 0.0}, {0.0, 1.0}};
+        nys_regular(&e, C, x, ref, sr + I * si, &m, &p, 0, G, H);
+    }
+    for (int b = 0; b < 6; ++b)
+        for (int q = 0; q < 9; ++q) {
+            G_out[18 * b + 2 * q] = creal(G[b][q]);
+            G_out[18 * b + 2 * q + 1] = cimag(G[b][q]);
+            H_out[18 * b + 2 * q] = creal(H[b][q]);
+            H_out[18 * b + 2 * q + 1] = cimag(H[b][q]);
+        }
+    return 0;
+}
+
+/* Rows of the Nystrom system for the listed target nodes (all when rows is
+ * NULL): A_out [3 nrows][3 n_k] complex row-major, b_out [3 nrows];
+ * bc_val [n_k][3] complex, the prescribed value at each node (kind per
+ * element: 0 traction prescribed, 1 displacement prescribed). */
+int orc_nys_assemble_rows(const double *xyz, int64_t nt, const int32_t *tri6, const int8_t *bc_kind,
+                          const double *bc_val, double sr, double si, const double mat[3], const double pol[4],
+                          int64_t nrows, const int64_t *rows, double *A_out, double *b_out)
+{
+    q6_t *els = build_q6(xyz, nt, tri6);
+    material_t m = make_material(mat);
+    policy_t p = make_policy(pol);
+    double pt[6][2], w6[6], C[6][6];
+    gauss6(pt, w6);
+    lagrange6(pt, C);
+    cplx s = sr + I * si;
+    int64_t nk = 6 * nt, N = 3 * nk;
+    if (!rows)
+        nrows = nk;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t r = 0; r < nrows; ++r) {
+        int64_t i = rows ? rows[r] : r;
+        cplx b[3] = {0, 0, 0};
+        for (int64_t e = 0; e < nt; ++e) {
+            cplx G[6][9], H[6][9];
+            nys_blocks(els, pt, w6, C, i, e, s, &m, &p, G, H);
+            for (int q = 0; q < 6; ++q) {
+                int64_t j = 6 * e + q;
+                const double *v = bc_val + 6 * j;
+                cplx val[3] = {v[0] + I * v[1], v[2] + I * v[3], v[4] + I * v[5]};
+                for (int a = 0; a < 3; ++a)
+                    for (int c = 0; c < 3; ++c) {
+                        cplx av, rhs;
+                        if (bc_kind[e] == 0) {
+                            av = H[q][3 * a + c];
+                            rhs = G[q][3 * a + c] * val[c];
+                        } else {
+                            av = -G[q][3 * a + c];
+                            rhs = -H[q][3 * a + c] * val[c];
+                        }
+                        b[a] += rhs;
+                        double *dst = A_out + 2 * ((3 * r + a) * N + 3 * j + c);
+                        dst[0] = creal(av);
+                        dst[1] = cimag(av);
+                    }
+            }
+        }
+        for (int a = 0; a < 3; ++a) {
+            b_out[2 * (3 * r + a)] = creal(b[a]);
+            b_out[2 * (3 * r + a) + 1] = cimag(b[a]);
+        }
+    }
+    free(els);
+    return 0;
+}
+
+/* static (s = 0) row sums of H over all nodes for every target node */
+int orc_nys_rowsum_H_static(const double *xyz, int64_t nt, const int32_t *tri6, const double mat[3],
+                            const double pol[4], double *out9)
+{
+    q6_t *els = build_q6(xyz, nt, tri6);
+    material_t m = make_material(mat);
+    policy_t p = make_policy(pol);
+    double pt[6][2], w6[6], C[6][6];
+    gauss6(pt, w6);
+    lagrange6(pt, C);
+    int64_t nk = 6 * nt;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t i = 0; i < nk; ++i) {
+        double acc[9] = {0};
+        for (int64_t e = 0; e < nt; ++e) {
+            cplx G[6][9], H[6][9];
+            nys_blocks(els, pt, w6, C, i, e, 0.0, &m, &p, G, H);
+            for (int q = 0; q < 6; ++q)
+                for (int k = 0; k < 9; ++k)
+                    acc[k] += creal(H[q][k]);
+        }
+        memcpy(out9 + 9 * i, acc, sizeof acc);
+    }
+    free(els);
     return 0;
 }

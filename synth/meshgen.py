@@ -167,6 +167,63 @@ def cavity(level: int, radius: float = 1.0) -> Mesh:
                 meta={"level": level, "radius": radius})
 
 
+@dataclass
+class QuadMesh:
+    """Six-node (curved quadratic) triangles: corners v0 v1 v2, then the
+    mid-edge nodes of edges 01, 12, 20; the corner order follows the same
+    orientation rule as ``Mesh.tri``.  Loads are given as a pressure per element
+    (traction -p n on the surface, n out of the solid), since the normal varies
+    over a curved element."""
+    xyz: np.ndarray            # (nv, 3) float64
+    tri6: np.ndarray           # (nt, 6) int32
+    bc_kind: np.ndarray        # (nt,) int8
+    pressure: np.ndarray       # (nt,) float64
+    name: str = ""
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def n_tri(self) -> int:
+        return int(self.tri6.shape[0])
+
+    @property
+    def n_nodes(self) -> int:
+        """Unknown-carrying points: six per element."""
+        return 6 * self.n_tri
+
+    @property
+    def n_unknowns(self) -> int:
+        return 18 * self.n_tri
+
+
+def quadratic_sphere(level: int, radius: float = 1.0, center=(0.0, 0.0, 0.0), inward: bool = True):
+    """The icosphere of ``level`` with a node at each edge midpoint projected
+    onto the sphere: (xyz, tri6)."""
+    xyz, tri = icosphere(level, radius, center, inward)
+    c = np.asarray(center, dtype=np.float64)
+    pts = [p for p in xyz]
+    cache = {}
+
+    def mid(a, b):
+        key = (a, b) if a < b else (b, a)
+        if key not in cache:
+            m = 0.5 * (xyz[a] + xyz[b]) - c
+            pts.append(c + radius * m / np.linalg.norm(m))
+            cache[key] = len(pts) - 1
+        return cache[key]
+
+    tri6 = np.array([(a, b, cc, mid(a, b), mid(b, cc), mid(cc, a)) for a, b, cc in tri], dtype=np.int32)
+    return np.array(pts), tri6
+
+
+def cavity_quadratic(level: int, radius: float = 1.0) -> QuadMesh:
+    """The spherical cavity under unit internal pressure on six-node elements
+    (20 * 4**level elements, 120 * 4**level unknown-carrying points)."""
+    xyz, tri6 = quadratic_sphere(level, radius, inward=True)
+    nt = tri6.shape[0]
+    return QuadMesh(xyz, tri6, np.zeros(nt, np.int8), np.ones(nt), name=f"cavity_q{level}",
+                    meta={"level": level, "radius": radius})
+
+
 def rod(length: float, width: float, n_w: int, n_l: int) -> Mesh:
     """Prismatic rod [0,w]^2 x [0,L]: fixed at z=0 (u=0), unit axial traction
     +e_z on z=L, lateral faces traction free (the paper's first example, in
