@@ -65,6 +65,28 @@ int afsbem_mesh_create(const double *xyz, int64_t n_vert, const int32_t *tri, in
                        afsbem_mesh **out);
 int afsbem_mesh_destroy(afsbem_mesh *mesh);
 
+/* Six-node (curved quadratic) triangles, the paper's own discretisation
+ * (Section 2.1): tri6 [n_tri][6] holds the corners v0 v1 v2, then the
+ * mid-edge nodes of edges 01, 12, 20; the element map is the quadratic
+ * interpolant of the six nodes and its normal (x_xi x x_eta) must point out of
+ * the elastic domain.  A problem built on such a mesh is discretised by the
+ * locally-corrected Nystrom method: the unknowns sit at the six points of the
+ * 6-point Gauss rule of every element (point 6 e + q is rule point q of
+ * element e, q = 0..2 the orbit (a, a, 1-2a), q = 3..5 the orbit (b, b, 1-2b),
+ * the odd barycentric coordinate at position q % 3), so n_k = 6 n_tri points
+ * with three unknowns each.  Far elements use the rule itself; near elements
+ * locally corrected weights (recursive subdivision of the parameter triangle,
+ * same far_ratio/max_subdiv test as the flat elements, applied to each piece's
+ * image); the element holding the target point polar coordinates about it in
+ * the parameter plane (self_n_theta x self_n_rho per half of each of the three
+ * sub-triangles) with the strongly singular part as a principal value.  Every
+ * per-point array of the problem (boundary values, solutions, bc_kind expanded
+ * per element) then has n_k entries.  Matrix-free application is not
+ * available for these problems.  Rejects indices out of range
+ * (AFSBEM_EINVAL); arrays are copied. */
+int afsbem_mesh_create_quadratic(const double *xyz, int64_t n_vert, const int32_t *tri6, int64_t n_tri,
+                                 afsbem_mesh **out);
+
 /* -------------------------------------------------------------- problem ---
  * Isotropic material (Section 2.1): shear modulus mu, Poisson ratio nu in
  * (-1, 0.5), density rho; c_s = sqrt(mu/rho), c_p = sqrt((lambda+2mu)/rho). */
@@ -87,7 +109,7 @@ typedef struct {
     int32_t self_n_theta, self_n_rho;
 } afsbem_quad_policy;
 
-/* bc_kind: [n_tri], 0 = traction prescribed, 1 = displacement prescribed.
+/* bc_kind: [n_tri] (per element of the mesh), 0 = traction prescribed, 1 = displacement prescribed.
  * policy may be NULL (defaults).  Builds the s-independent quadrature plan
  * (element geometry, near-pair subdivision leaves, self-element polar tables
  * and static principal values) and uploads it to the current HIP device. */
@@ -95,10 +117,18 @@ int afsbem_problem_create(const afsbem_mesh *mesh, const afsbem_material *mat, c
                           const afsbem_quad_policy *policy, afsbem_problem **out);
 int afsbem_problem_destroy(afsbem_problem *p);
 
-/* Sizes of the plan: n_tri, number of near pairs, number of subdivision leaves,
- * number of self quadrature nodes per element.  Any pointer may be NULL. */
+/* Sizes of the plan: n_tri (collocation points: elements of a flat mesh, six
+ * per element of a six-node mesh; the system has 3 n_tri unknowns), number of
+ * near pairs, number of subdivision leaves, number of self quadrature nodes per
+ * collocation point.  Any pointer may be NULL. */
 int afsbem_problem_info(const afsbem_problem *p, int64_t *n_tri, int64_t *n_near_pairs,
                         int64_t *n_leaves, int64_t *self_nodes_per_element);
+
+/* Host copy of the collocation points (one per flat element, six per six-node
+ * element): out8 [n][8] = point (3), unit normal (3), weight (the element area
+ * for flat elements, w_q J_q for the Nystrom points), boundary kind.  n is the
+ * n_tri of afsbem_problem_info. */
+int afsbem_problem_points(const afsbem_problem *p, double *out8);
 
 /* ------------------------------------------------ step-level entry points ---
  * Matrix storage formats on the device (N = 3 n_tri, column-major):

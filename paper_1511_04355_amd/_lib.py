@@ -81,6 +81,8 @@ def lib():
         L.afsbem_version.argtypes = [P, P]
         L.afsbem_mesh_create.argtypes = [P, i64, P, i64, P]
         L.afsbem_mesh_destroy.argtypes = [P]
+        L.afsbem_mesh_create_quadratic.argtypes = [P, i64, P, i64, P]
+        L.afsbem_problem_points.argtypes = [P, P]
         L.afsbem_problem_create.argtypes = [P, P, P, P, P]
         L.afsbem_problem_destroy.argtypes = [P]
         L.afsbem_problem_info.argtypes = [P, P, P, P, P]
@@ -176,12 +178,15 @@ class Problem:
         xyz = np.ascontiguousarray(xyz, np.float64)
         tri = np.ascontiguousarray(tri, np.int32)
         kind = np.ascontiguousarray(bc_kind, np.int8)
-        self.n_tri = int(tri.shape[0])
+        # six nodes per element: the Nystrom discretisation, six collocation points per element
+        self.quadratic = tri.shape[1] == 6
+        self.n_el = int(tri.shape[0])
+        self.n_tri = 6 * self.n_el if self.quadratic else self.n_el
         self.N = 3 * self.n_tri
         self.lda = lda_of(self.N)
         mesh = ctypes.c_void_p()
-        _check(L.afsbem_mesh_create(xyz.ctypes.data, xyz.shape[0], tri.ctypes.data, tri.shape[0],
-                                    ctypes.byref(mesh)))
+        create = L.afsbem_mesh_create_quadratic if self.quadratic else L.afsbem_mesh_create
+        _check(create(xyz.ctypes.data, xyz.shape[0], tri.ctypes.data, tri.shape[0], ctypes.byref(mesh)))
         try:
             mat = _Material(*material)
             pol = None if policy is None else _Policy(float(policy[0]), int(policy[1]), int(policy[2]),
@@ -195,7 +200,15 @@ class Problem:
 
     @classmethod
     def from_mesh(cls, mesh, material=(1.0, 0.25, 1.0), policy=(2.0, 8, 16, 16)):
-        return cls(mesh.xyz, mesh.tri, mesh.bc_kind, material, policy)
+        tri = mesh.tri6 if hasattr(mesh, "tri6") else mesh.tri
+        return cls(mesh.xyz, tri, mesh.bc_kind, material, policy)
+
+    def points(self):
+        """Collocation points (n_tri, 3), unit normals (n_tri, 3), weights (n_tri,)
+        (element areas, or w_q J_q of the Nystrom points) and kinds (n_tri,)."""
+        out = np.zeros((self.n_tri, 8))
+        _check(lib().afsbem_problem_points(self._h, out.ctypes.data))
+        return out[:, 0:3], out[:, 3:6], out[:, 6], out[:, 7].astype(np.int8)
 
     def close(self):
         if getattr(self, "_h", None):

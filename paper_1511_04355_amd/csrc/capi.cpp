@@ -11,8 +11,9 @@
 
 struct afsbem_mesh {
     std::vector<double> xyz;
-    std::vector<int32_t> tri;
+    std::vector<int32_t> tri;      // [n_tri][3], or [n_tri][6] when order == 2
     int64_t n_vert = 0, n_tri = 0;
+    int order = 1;                 // 1: flat triangles, 2: six-node (curved quadratic) triangles
 };
 
 struct afsbem_problem {
@@ -112,6 +113,28 @@ int afsbem_mesh_create(const double *xyz, int64_t n_vert, const int32_t *tri, in
     });
 }
 
+int afsbem_mesh_create_quadratic(const double *xyz, int64_t n_vert, const int32_t *tri6, int64_t n_tri,
+                                 afsbem_mesh **out) {
+    return guarded([&] {
+        AFS_REQUIRE(out && xyz && tri6, AFSBEM_EINVAL, "null pointer argument");
+        AFS_REQUIRE(n_vert >= 6 && n_tri >= 1, AFSBEM_EINVAL, "mesh needs at least 6 nodes and 1 element");
+        AFS_REQUIRE(n_tri <= (int64_t)1 << 24, AFSBEM_EINVAL, "too many elements");
+        for (int64_t k = 0; k < 6 * n_tri; ++k)
+            AFS_REQUIRE(tri6[k] >= 0 && tri6[k] < n_vert, AFSBEM_EINVAL,
+                        "element " + std::to_string(k / 6) + " has a node index out of range");
+        for (int64_t k = 0; k < 3 * n_vert; ++k)
+            AFS_REQUIRE(std::isfinite(xyz[k]), AFSBEM_EINVAL, "non-finite node coordinate");
+        auto *m = new afsbem_mesh();
+        m->xyz.assign(xyz, xyz + 3 * n_vert);
+        m->tri.assign(tri6, tri6 + 6 * n_tri);
+        m->n_vert = n_vert;
+        m->n_tri = n_tri;
+        m->order = 2;
+        *out = m;
+        return AFSBEM_OK;
+    });
+}
+
 int afsbem_mesh_destroy(afsbem_mesh *mesh) {
     delete mesh;
     return AFSBEM_OK;
@@ -137,12 +160,26 @@ int afsbem_problem_create(const afsbem_mesh *mesh, const afsbem_material *mat, c
         P.mat = derive_material(*mat);
         P.pol = pol;
         AFS_HIP(hipGetDevice(&P.device));
-        build_plan(mesh->xyz.data(), mesh->n_vert, mesh->tri.data(), mesh->n_tri, bc_kind, pol, P.mat, P.host);
+        if (mesh->order == 2)
+            build_plan_nystrom(mesh->xyz.data(), mesh->n_vert, mesh->tri.data(), mesh->n_tri, bc_kind, pol, P.mat,
+                               P.host);
+        else
+            build_plan(mesh->xyz.data(), mesh->n_vert, mesh->tri.data(), mesh->n_tri, bc_kind, pol, P.mat, P.host);
         const HostPlan &H = P.host;
         DevicePlan &D = P.dev;
         D.n_tri = H.n_tri;
         D.nnz = (int64_t)H.near_col.size();
-        D.n_leaves = (int64_t)(H.leaves.size() / 10);
+        D.n_leaves = (int64_t)(H.disc == 1 ? H.nys_leaves.size() / 6 : H.leaves.size() / 10);
+        D.disc = H.disc;
+        D.n_el = H.disc == 1 ? H.n_el : H.n_tri;
+        if (H.disc == 1) {
+            D.nys_geom = upload(h, H.nys_geom);
+            D.nys_leaves = upload(h, H.nys_leaves);
+            D.nys_self = upload(h, H.nys_self);
+            std::vector<double> tab(H.nys_pt, H.nys_pt + 12);
+            tab.insert(tab.end(), H.nys_lag, H.nys_lag + 36);
+            D.nys_tab = upload(h, tab);
+        }
         D.n_theta = H.n_theta;
         D.n_rho = H.n_rho;
         std::vector<double> cx(H.n_tri), cy(H.n_tri), cz(H.n_tri);
@@ -215,7 +252,24 @@ int afsbem_problem_info(const afsbem_problem *p, int64_t *n_tri, int64_t *n_near
         if (n_leaves)
             *n_leaves = p->p.dev.n_leaves;
         if (self_nodes_per_element)
-            *self_nodes_per_element = 3 * (int64_t)p->p.dev.n_theta * p->p.dev.n_rho;
+            *self_nodes_per_element = (p->p.dev.disc == 1 ? 6 : 3) * (int64_t)p->p.dev.n_theta * p->p.dev.n_rho;
+        return AFSBEM_OK;
+    });
+}
+
+int afsbem_problem_points(const afsbem_problem *p, double *out8) {
+    return guarded([&] {
+        AFS_REQUIRE(p && out8, AFSBEM_EINVAL, "null pointer argument");
+        const HostPlan &H = p->p.host;
+        for (int64_t i = 0; i < H.n_tri; ++i) {
+            double *o = out8 + 8 * i;
+            for (int k = 0; k < 3; ++k) {
+                o[k] = H.cen[3 * i + k];
+                o[3 + k] = H.nrm[3 * i + k];
+            }
+            o[6] = H.disc == 1 ? H.src[kSrcStride * i + 3] : H.area[i];
+            o[7] = (double)H.kind[i];
+        }
         return AFSBEM_OK;
     });
 }
@@ -265,6 +319,8 @@ int afsbem_matvec_free_device(afsbem_problem *p, double s_re, double s_im, int p
         AFS_REQUIRE((d_x == nullptr) == (d_y == nullptr), AFSBEM_EINVAL, "x and y go together");
         AFS_REQUIRE(!d_b || d_bc_val, AFSBEM_EINVAL, "b needs the boundary values");
         AFS_REQUIRE(std::isfinite(s_re) && std::isfinite(s_im), AFSBEM_EINVAL, "non-finite s");
+        AFS_REQUIRE(p->p.dev.disc == 0, AFSBEM_EINVAL,
+                    "matrix-free application is not available for six-node (Nystrom) problems");
         hipStream_t st = static_cast<hipStream_t>(hip_stream);
         const Problem &P = p->p;
         const int64_t nt = P.dev.n_tri, N = 3 * nt;

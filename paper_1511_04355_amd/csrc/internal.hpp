@@ -75,7 +75,26 @@ struct HostPlan {
     // preconditioner clusters (recursive coordinate bisection of the centroids)
     std::vector<int64_t> clus_ptr; // [n_clusters+1]
     std::vector<int32_t> clus_elem;// [n] elements grouped by cluster
+    // Nystrom discretisation of six-node elements (disc = 1).  Every field
+    // above then describes the n_tri = 6 n_el unknown-carrying points (node
+    // 6 e + q at rule point q of element e): cen/nrm the points and normals,
+    // src one record per point (y, w J, normal, kind), the near CSR pairs
+    // (target point, source element) with leaves = parameter-plane triangles.
+    int disc = 0;
+    int64_t n_el = 0;
+    std::vector<double> nys_geom;  // [n_el][18] the six nodes of each element
+    std::vector<double> nys_leaves;// [n_leaves][6] (xi, eta) of three corners
+    std::vector<double> nys_self;  // [6][6 * n_theta][4] cos, sin, w_theta, R per angle
+    double nys_pt[12];             // rule points (xi, eta)
+    double nys_lag[36];            // Lagrange basis: L_b = sum_k lag[6b+k] m_k(xi, eta)
 };
+
+// six-node elements: xyz [nv][3], tri6 [n_el][6] (corners, then mid-edge
+// nodes of edges 01, 12, 20), kind per element
+void build_plan_nystrom(const double *xyz, int64_t nv, const int32_t *tri6, int64_t n_el, const int8_t *kind,
+                        const afsbem_quad_policy &pol, const MaterialDerived &mat, HostPlan &out);
+void plan_clusters(HostPlan &P);
+void plan_series(const MaterialDerived &mat, HostPlan &P);
 
 void build_plan(const double *xyz, int64_t nv, const int32_t *tri, int64_t nt, const int8_t *kind,
                 const afsbem_quad_policy &pol, const MaterialDerived &mat, HostPlan &out);
@@ -101,6 +120,10 @@ struct DevicePlan {
     int64_t n_clusters = 0;
     int64_t *clus_ptr = nullptr;
     int32_t *clus_elem = nullptr;
+    int disc = 0;                  // 1: Nystrom points of six-node elements
+    int64_t n_el = 0;
+    double *nys_geom = nullptr, *nys_leaves = nullptr, *nys_self = nullptr;
+    double *nys_tab = nullptr;     // [48]: rule points (12), then the Lagrange basis (36)
 };
 
 // -------------------------------------------------------------- problem --
@@ -141,6 +164,11 @@ size_t assembly_scratch_bytes(const Problem &p);
 void launch_assembly(const Problem &p, const KernelParams &kp, const double *bc_val, int format,
                      void *A, void *A_lo, double *b, double *precond, void *scratch,
                      hipStream_t st, hipEvent_t far_begin = nullptr, hipEvent_t far_end = nullptr);
+
+// Nystrom assembly (disc = 1): near-pair and self-element kernels; the far
+// field runs through the collocation far kernel with one node per source.
+void launch_nystrom_near_self(const Problem &p, const KernelParams &kp, const double *bc_val, int format, void *A,
+                              void *A_lo, double *bself, double *corr, double *precond, hipStream_t st);
 
 // Matrix-free operator (no stored dense matrix).  Per frequency: the near-pair
 // correction blocks (exact minus the far rule) [nnz][9] and the self blocks

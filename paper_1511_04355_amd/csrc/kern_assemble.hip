@@ -279,7 +279,10 @@ __device__ __forceinline__ void expand_block(int kind, const BlockAcc &acc, doub
         }
 }
 
-template <int FMT>
+// NQ nodes per source record: kFarNodes (flat elements, the record of element
+// n; skips n == m, the self element) or 1 (Nystrom points, the record of
+// point n; skips the six points of the target point's own element).
+template <int FMT, int NQ>
 __global__ __launch_bounds__(256) void far_assemble_kernel(
     int64_t nt, int64_t lda, KernelParams kp, const double *__restrict__ colx, const double *__restrict__ coly,
     const double *__restrict__ colz, const double *__restrict__ src, const double *__restrict__ bc,
@@ -302,13 +305,13 @@ __global__ __launch_bounds__(256) void far_assemble_kernel(
         const int kind = (int)rec[31];
         const double *bv = bc + 6 * n;
         const cd v[3] = {cd{bv[0], bv[1]}, cd{bv[2], bv[3]}, cd{bv[4], bv[5]}};
-        if (!active || m == n)
+        if (!active || (NQ == kFarNodes ? m == n : m / 6 == n / 6))
             continue;
         BlockAcc acc;
         acc.zero();
         if (kind == 0) {
 #pragma unroll 1
-            for (int q = 0; q < kFarNodes; ++q) {
+            for (int q = 0; q < NQ; ++q) {
                 PairEval E;
                 eval_pair(kp, coef, xx, xy, xz, rec[4 * q], rec[4 * q + 1], rec[4 * q + 2], nx, ny, nz, E);
                 const double w = rec[4 * q + 3];
@@ -316,7 +319,7 @@ __global__ __launch_bounds__(256) void far_assemble_kernel(
             }
         } else {
 #pragma unroll 1
-            for (int q = 0; q < kFarNodes; ++q) {
+            for (int q = 0; q < NQ; ++q) {
                 PairEval E;
                 eval_pair(kp, coef, xx, xy, xz, rec[4 * q], rec[4 * q + 1], rec[4 * q + 2], nx, ny, nz, E);
                 const double w = rec[4 * q + 3];
@@ -678,12 +681,27 @@ void launch_assembly(const Problem &p, const KernelParams &kp, const double *bc_
     const Rule7Args rule = rule7_args();
     if (far_begin)
         AFS_HIP(hipEventRecord(far_begin, st));
+    if (d.disc == 1) {
+        if (format == AFSBEM_FMT_C128)
+            far_assemble_kernel<AFSBEM_FMT_C128, 1><<<gfar, 256, 0, st>>>(nt, lda, kp, d.colx, d.coly, d.colz, d.src,
+                                                                         bc_val, coef, chunk, A, A_lo, bpart);
+        else
+            far_assemble_kernel<AFSBEM_FMT_SPLIT, 1><<<gfar, 256, 0, st>>>(nt, lda, kp, d.colx, d.coly, d.colz, d.src,
+                                                                          bc_val, coef, chunk, A, A_lo, bpart);
+        if (far_end)
+            AFS_HIP(hipEventRecord(far_end, st));
+        AFS_HIP(hipGetLastError());
+        launch_nystrom_near_self(p, kp, bc_val, format, A, A_lo, bself, corr, precond, st);
+        finalize_b_kernel<<<(unsigned)((N + 255) / 256), 256, 0, st>>>(nt, Sused, bpart, bself, d.near_ptr, corr, b);
+        AFS_HIP(hipGetLastError());
+        return;
+    }
     if (format == AFSBEM_FMT_C128)
-        far_assemble_kernel<AFSBEM_FMT_C128><<<gfar, 256, 0, st>>>(nt, lda, kp, d.colx, d.coly, d.colz, d.src, bc_val,
-                                                                  coef, chunk, A, A_lo, bpart);
+        far_assemble_kernel<AFSBEM_FMT_C128, kFarNodes><<<gfar, 256, 0, st>>>(
+            nt, lda, kp, d.colx, d.coly, d.colz, d.src, bc_val, coef, chunk, A, A_lo, bpart);
     else
-        far_assemble_kernel<AFSBEM_FMT_SPLIT><<<gfar, 256, 0, st>>>(nt, lda, kp, d.colx, d.coly, d.colz, d.src,
-                                                                   bc_val, coef, chunk, A, A_lo, bpart);
+        far_assemble_kernel<AFSBEM_FMT_SPLIT, kFarNodes><<<gfar, 256, 0, st>>>(
+            nt, lda, kp, d.colx, d.coly, d.colz, d.src, bc_val, coef, chunk, A, A_lo, bpart);
     if (far_end)
         AFS_HIP(hipEventRecord(far_end, st));
     if (format == AFSBEM_FMT_C128) {
@@ -813,6 +831,364 @@ void launch_finalize_b(const Problem &p, int S, const double *bpart, const void 
     const double *bself = static_cast<const double *>(scratch) + 2 * (size_t)Smax * N;
     const double *corr = bself + 6 * nt;
     finalize_b_kernel<<<(unsigned)((N + 255) / 256), 256, 0, st>>>(nt, S, bpart, bself, d.near_ptr, corr, b);
+    AFS_HIP(hipGetLastError());
+}
+
+// ---------------------------------------------------------------------------
+// Nystrom discretisation of six-node elements (paper Section 2.1): the near
+// pairs (target point, element) and the self elements.  Both sum a kernel
+// times the six Lagrange basis functions over many quadrature points; one
+// wavefront per pair (or per target point), lanes over points, and the
+// 6 x 36 weighted sums formed through LDS in chunks of 64 points (point data
+// staged once, then each lane forms 3-4 of the 216 sums), so no lane carries
+// 216 accumulators.
+// ---------------------------------------------------------------------------
+// rule table in device memory: [0, 12) rule points (xi, eta); [12, 48) the
+// Lagrange basis, L_b = sum_k tab[12 + 6 b + k] m_k, m = 1, xi, eta, xi^2, xi eta, eta^2
+constexpr int kNysTab = 48;
+
+struct QGeo {
+    double y[3], n[3], J, tx[3], te[3];
+};
+
+// quadratic element map: point, unit normal, Jacobian, tangents
+__device__ __forceinline__ void q6_geo(const double *P, double xi, double eta, QGeo &g) {
+    const double l0 = 1.0 - xi - eta, l1 = xi, l2 = eta;
+    const double N[6] = {l0 * (2.0 * l0 - 1.0), l1 * (2.0 * l1 - 1.0), l2 * (2.0 * l2 - 1.0),
+                         4.0 * l0 * l1,         4.0 * l1 * l2,         4.0 * l2 * l0};
+    const double Nx[6] = {-(4.0 * l0 - 1.0), 4.0 * l1 - 1.0, 0.0, 4.0 * (l0 - l1), 4.0 * l2, -4.0 * l2};
+    const double Ne[6] = {-(4.0 * l0 - 1.0), 0.0, 4.0 * l2 - 1.0, -4.0 * l1, 4.0 * l1, 4.0 * (l0 - l2)};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        double y = 0.0, tx = 0.0, te = 0.0;
+#pragma unroll
+        for (int a = 0; a < 6; ++a) {
+            y += N[a] * P[3 * a + k];
+            tx += Nx[a] * P[3 * a + k];
+            te += Ne[a] * P[3 * a + k];
+        }
+        g.y[k] = y;
+        g.tx[k] = tx;
+        g.te[k] = te;
+    }
+    const double c0 = g.tx[1] * g.te[2] - g.tx[2] * g.te[1];
+    const double c1 = g.tx[2] * g.te[0] - g.tx[0] * g.te[2];
+    const double c2 = g.tx[0] * g.te[1] - g.tx[1] * g.te[0];
+    g.J = sqrt(c0 * c0 + c1 * c1 + c2 * c2);
+    g.n[0] = c0 / g.J;
+    g.n[1] = c1 / g.J;
+    g.n[2] = c2 / g.J;
+}
+
+__device__ __forceinline__ void lag6(const double *__restrict__ tab, double xi, double eta, double L[6]) {
+    const double m[6] = {1.0, xi, eta, xi * xi, xi * eta, eta * eta};
+#pragma unroll
+    for (int b = 0; b < 6; ++b) {
+        double v = 0.0;
+#pragma unroll
+        for (int k = 0; k < 6; ++k)
+            v += tab[12 + 6 * b + k] * m[k];
+        L[b] = v;
+    }
+}
+
+constexpr int kNysOut = 216;    // 6 basis functions x (U, T) x 9 complex
+constexpr int kNysKStride = 37; // LDS row of one point's 36 weighted kernel values (+1 against bank conflicts)
+
+struct NysLds {
+    double K[64 * kNysKStride];
+    double L[64 * 6];
+    double out[kNysOut];
+    double bv[6 * 6];
+};
+
+// stage one point (or zeros) and add its contribution to the lane's sums
+__device__ __forceinline__ void nys_stage(NysLds &sh, int lane, bool live, const PairEval &E, const KernelParams &kp,
+                                          const double n[3], double w, const double L[6]) {
+    cd U[9], T[9];
+#pragma unroll
+    for (int e = 0; e < 9; ++e)
+        U[e] = T[e] = cd{0, 0};
+    if (live) {
+        acc_U(E, kp, w, U);
+        acc_T(E, n[0], n[1], n[2], w, T);
+    }
+    double *k = &sh.K[lane * kNysKStride];
+#pragma unroll
+    for (int e = 0; e < 9; ++e) {
+        k[2 * e] = U[e].r;
+        k[2 * e + 1] = U[e].i;
+        k[18 + 2 * e] = T[e].r;
+        k[18 + 2 * e + 1] = T[e].i;
+    }
+#pragma unroll
+    for (int b = 0; b < 6; ++b)
+        sh.L[lane * 6 + b] = live ? L[b] : 0.0;
+}
+
+__device__ __forceinline__ void nys_contract(const NysLds &sh, int lane, double acc[4]) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int o = lane + 64 * r;
+        if (o < kNysOut) {
+            const int b = o / 36, c = o % 36;
+            double v = acc[r];
+#pragma unroll 4
+            for (int p = 0; p < 64; ++p)
+                v += sh.L[p * 6 + b] * sh.K[p * kNysKStride + c];
+            acc[r] = v;
+        }
+    }
+}
+
+// near pair p = (target point i, element e): the six corrected column blocks
+// of row i (overwriting the rule's blocks written by the far kernel) and b's
+// correction (corrected minus the rule's blocks) times the prescribed values
+template <int FMT>
+__global__ __launch_bounds__(64) void nys_near_kernel(
+    int64_t lda, KernelParams kp, Rule7Args rule, const double *__restrict__ ntab, const double *__restrict__ colx,
+    const double *__restrict__ coly, const double *__restrict__ colz, const double *__restrict__ src,
+    const double *__restrict__ bc, const double *__restrict__ coef, const int32_t *__restrict__ near_row,
+    const int32_t *__restrict__ near_col, const int32_t *__restrict__ near_order, const int64_t *__restrict__ leaf_ptr,
+    const double *__restrict__ leaves, const double *__restrict__ geom, void *A, void *A_lo, double *__restrict__ corr) {
+    __shared__ NysLds sh;
+    const int lane = threadIdx.x;
+    const int64_t p = near_order[blockIdx.x];
+    const int64_t i = near_row[p], e = near_col[p];
+    const double xx = colx[i], xy = coly[i], xz = colz[i];
+    double P[18];
+#pragma unroll
+    for (int k = 0; k < 18; ++k)
+        P[k] = geom[18 * e + k];
+    const int64_t l0 = leaf_ptr[p];
+    const int64_t items = 7 * (leaf_ptr[p + 1] - l0);
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int64_t c0 = 0; c0 < items; c0 += 64) {
+        const int64_t it = c0 + lane;
+        const bool live = it < items;
+        PairEval E;
+        QGeo g;
+        double L[6], w = 0.0;
+        if (live) {
+            const double *q = leaves + 6 * (l0 + it / 7);
+            const int r = (int)(it % 7);
+            const double b1 = rule.b1[r], b2 = rule.b2[r], b0 = 1.0 - b1 - b2;
+            const double xi = b0 * q[0] + b1 * q[2] + b2 * q[4];
+            const double eta = b0 * q[1] + b1 * q[3] + b2 * q[5];
+            const double area = 0.5 * fabs((q[2] - q[0]) * (q[5] - q[1]) - (q[4] - q[0]) * (q[3] - q[1]));
+            q6_geo(P, xi, eta, g);
+            lag6(ntab, xi, eta, L);
+            eval_pair(kp, coef, xx, xy, xz, g.y[0], g.y[1], g.y[2], g.n[0], g.n[1], g.n[2], E);
+            w = rule.w[r] * area * g.J;
+        }
+        nys_stage(sh, lane, live, E, kp, g.n, w, L);
+        __syncthreads();
+        nys_contract(sh, lane, acc);
+        __syncthreads();
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+        if (lane + 64 * r < kNysOut)
+            sh.out[lane + 64 * r] = acc[r];
+    __syncthreads();
+    if (lane < 6) {
+        const int64_t j = 6 * e + lane;
+        const double *rec = src + kSrcStride * j;
+        const int kind = (int)rec[31];
+        // the block of column j: H (u unknown) or -G (t unknown)
+        const double *mat = &sh.out[36 * lane + (kind == 0 ? 18 : 0)];
+        const double sg = kind == 0 ? 1.0 : -1.0;
+        cd blk[9];
+#pragma unroll
+        for (int k = 0; k < 9; ++k)
+            blk[k] = cd{sg * mat[2 * k], sg * mat[2 * k + 1]};
+        store_block<FMT>(A, A_lo, lda, i, j, blk);
+        // b correction: (corrected - rule) block of the prescribed side times v
+        const double *known = &sh.out[36 * lane + (kind == 0 ? 0 : 18)];
+        const double *bv = bc + 6 * j;
+        const cd v[3] = {cd{bv[0], bv[1]}, cd{bv[2], bv[3]}, cd{bv[4], bv[5]}};
+        cd far[3] = {cd{0, 0}, cd{0, 0}, cd{0, 0}};
+        PairEval E;
+        eval_pair(kp, coef, xx, xy, xz, rec[0], rec[1], rec[2], rec[28], rec[29], rec[30], E);
+        if (kind == 0)
+            acc_Uv(E, kp, rec[3], v, far);
+        else
+            acc_Tv(E, rec[28], rec[29], rec[30], rec[3], v, far);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            cd d = cscale(far[a], -1.0);
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                d = cadd(d, cmul(cd{known[2 * (3 * a + c)], known[2 * (3 * a + c) + 1]}, v[c]));
+            sh.bv[6 * lane + 2 * a] = sg * d.r;
+            sh.bv[6 * lane + 2 * a + 1] = sg * d.i;
+        }
+    }
+    __syncthreads();
+    if (lane < 6) {
+        double v = 0.0;
+        for (int q = 0; q < 6; ++q)
+            v += sh.bv[6 * q + lane];
+        corr[6 * p + lane] = v;
+    }
+}
+
+// self element of target point i (rule point b0 of element e): polar rule in
+// the parameter plane about the point.  For the node's own basis function the
+// leading rho^-1 term of T, J0 T0(A(theta)) / rho with A = x_xi cos + x_eta sin
+// and T0(r) = beta^2/(4 pi |r|^2)(rh_i n0_j - rh_j n0_i), is subtracted point by
+// point and restored as its principal value over a circular exclusion,
+// int J0 T0(A) ln(R |A|) dtheta; both are antisymmetric, carried as the
+// vector of (rh x n0).  Then 1/2 I, the six blocks of row i, b's self part and
+// the inverse of the diagonal block (block-Jacobi).
+template <int FMT>
+__global__ __launch_bounds__(64) void nys_self_kernel(
+    int64_t lda, KernelParams kp, const double *__restrict__ ntab, const double *__restrict__ colx, const double *__restrict__ coly,
+    const double *__restrict__ colz, const double *__restrict__ src, const double *__restrict__ bc,
+    const double *__restrict__ coef, const double *__restrict__ geom, const double *__restrict__ table,
+    const double *__restrict__ gl_rho, int n_theta, int n_rho, void *A, void *A_lo, double *__restrict__ bself,
+    double *__restrict__ precond) {
+    __shared__ NysLds sh;
+    const int lane = threadIdx.x;
+    const int64_t i = blockIdx.x;
+    const int64_t e = i / 6;
+    const int b0 = (int)(i % 6);
+    const double xx = colx[i], xy = coly[i], xz = colz[i];
+    double P[18];
+#pragma unroll
+    for (int k = 0; k < 18; ++k)
+        P[k] = geom[18 * e + k];
+    const double xi0 = ntab[2 * b0], eta0 = ntab[2 * b0 + 1];
+    QGeo g0;
+    q6_geo(P, xi0, eta0, g0);
+    const double cT0 = g0.J * kp.beta * kp.beta * kInv4Pi;
+    const double *tab = table + (size_t)b0 * 6 * n_theta * 4;
+    const int64_t items = (int64_t)6 * n_theta * n_rho;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    double sv[3] = {0.0, 0.0, 0.0};
+    for (int64_t c0 = 0; c0 < items; c0 += 64) {
+        const int64_t it = c0 + lane;
+        const bool live = it < items;
+        PairEval E;
+        QGeo g;
+        double L[6], w = 0.0;
+        if (live) {
+            const double *t = tab + 4 * (it / n_rho);
+            const int r = (int)(it % n_rho);
+            const double cs = t[0], sn = t[1], wth = t[2], R = t[3];
+            const double rho = R * gl_rho[2 * r], wr = R * gl_rho[2 * r + 1];
+            const double xi = xi0 + rho * cs, eta = eta0 + rho * sn;
+            q6_geo(P, xi, eta, g);
+            lag6(ntab, xi, eta, L);
+            eval_pair(kp, coef, xx, xy, xz, g.y[0], g.y[1], g.y[2], g.n[0], g.n[1], g.n[2], E);
+            w = wth * wr * rho * g.J;
+            // leading term: c(theta) (rh x n0), rh = A / |A|, c = J0 beta^2 / (4 pi |A|^2)
+            double Av[3];
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+                Av[k] = g0.tx[k] * cs + g0.te[k] * sn;
+            const double A2 = Av[0] * Av[0] + Av[1] * Av[1] + Av[2] * Av[2];
+            const double Al = sqrt(A2);
+            const double cx[3] = {(Av[1] * g0.n[2] - Av[2] * g0.n[1]) / Al, (Av[2] * g0.n[0] - Av[0] * g0.n[2]) / Al,
+                                  (Av[0] * g0.n[1] - Av[1] * g0.n[0]) / Al};
+            double f = -wth * wr / rho * (cT0 / A2);
+            if (r == 0)
+                f += wth * (cT0 / A2) * log(R * Al);
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+                sv[k] += f * cx[k];
+        }
+        nys_stage(sh, lane, live, E, kp, g.n, w, L);
+        __syncthreads();
+        nys_contract(sh, lane, acc);
+        __syncthreads();
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+        sv[k] = wave_sum(sv[k]);
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+        if (lane + 64 * r < kNysOut)
+            sh.out[lane + 64 * r] = acc[r];
+    __syncthreads();
+    if (lane == 0) {
+        // H_b0 += (antisymmetric matrix of sv) + 1/2 I  (real parts)
+        double *H = &sh.out[36 * b0 + 18];
+        H[2 * 1] += sv[2];
+        H[2 * 3] -= sv[2];
+        H[2 * 5] += sv[0];
+        H[2 * 7] -= sv[0];
+        H[2 * 6] += sv[1];
+        H[2 * 2] -= sv[1];
+        H[0] += 0.5;
+        H[2 * 4] += 0.5;
+        H[2 * 8] += 0.5;
+    }
+    __syncthreads();
+    if (lane < 6) {
+        const int64_t j = 6 * e + lane;
+        const int kind = (int)src[kSrcStride * j + 31];
+        const double *mat = &sh.out[36 * lane + (kind == 0 ? 18 : 0)];
+        const double sg = kind == 0 ? 1.0 : -1.0;
+        cd blk[9];
+#pragma unroll
+        for (int k = 0; k < 9; ++k)
+            blk[k] = cd{sg * mat[2 * k], sg * mat[2 * k + 1]};
+        store_block<FMT>(A, A_lo, lda, i, j, blk);
+        const double *known = &sh.out[36 * lane + (kind == 0 ? 0 : 18)];
+        const double *bv = bc + 6 * j;
+        const cd v[3] = {cd{bv[0], bv[1]}, cd{bv[2], bv[3]}, cd{bv[4], bv[5]}};
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            cd d = cd{0, 0};
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                d = cadd(d, cmul(cd{known[2 * (3 * a + c)], known[2 * (3 * a + c) + 1]}, v[c]));
+            sh.bv[6 * lane + 2 * a] = sg * d.r;
+            sh.bv[6 * lane + 2 * a + 1] = sg * d.i;
+        }
+        if (lane == b0 && precond) {
+            cd inv[9];
+            inv3(blk, inv);
+            for (int k = 0; k < 9; ++k) {
+                precond[18 * i + 2 * k] = inv[k].r;
+                precond[18 * i + 2 * k + 1] = inv[k].i;
+            }
+        }
+    }
+    __syncthreads();
+    if (lane < 6) {
+        double v = 0.0;
+        for (int q = 0; q < 6; ++q)
+            v += sh.bv[6 * q + lane];
+        bself[6 * i + lane] = v;
+    }
+}
+
+void launch_nystrom_near_self(const Problem &p, const KernelParams &kp, const double *bc_val, int format, void *A,
+                              void *A_lo, double *bself, double *corr, double *precond, hipStream_t st) {
+    const DevicePlan &d = p.dev;
+    const int64_t lda = (3 * d.n_tri + 63) / 64 * 64;
+    const double *na = d.nys_tab;
+    const Rule7Args rule = rule7_args();
+    AFS_REQUIRE(d.nnz < (int64_t)1 << 31 && d.n_tri < (int64_t)1 << 31, AFSBEM_EINVAL, "Nystrom plan too large");
+    if (format == AFSBEM_FMT_C128) {
+        if (d.nnz)
+            nys_near_kernel<AFSBEM_FMT_C128><<<(unsigned)d.nnz, 64, 0, st>>>(
+                lda, kp, rule, na, d.colx, d.coly, d.colz, d.src, bc_val, d.coef, d.near_row, d.near_col,
+                d.near_order, d.leaf_ptr, d.nys_leaves, d.nys_geom, A, A_lo, corr);
+        nys_self_kernel<AFSBEM_FMT_C128><<<(unsigned)d.n_tri, 64, 0, st>>>(
+            lda, kp, na, d.colx, d.coly, d.colz, d.src, bc_val, d.coef, d.nys_geom, d.nys_self, d.gl_rho, d.n_theta,
+            d.n_rho, A, A_lo, bself, precond);
+    } else {
+        if (d.nnz)
+            nys_near_kernel<AFSBEM_FMT_SPLIT><<<(unsigned)d.nnz, 64, 0, st>>>(
+                lda, kp, rule, na, d.colx, d.coly, d.colz, d.src, bc_val, d.coef, d.near_row, d.near_col,
+                d.near_order, d.leaf_ptr, d.nys_leaves, d.nys_geom, A, A_lo, corr);
+        nys_self_kernel<AFSBEM_FMT_SPLIT><<<(unsigned)d.n_tri, 64, 0, st>>>(
+            lda, kp, na, d.colx, d.coly, d.colz, d.src, bc_val, d.coef, d.nys_geom, d.nys_self, d.gl_rho, d.n_theta,
+            d.n_rho, A, A_lo, bself, precond);
+    }
     AFS_HIP(hipGetLastError());
 }
 

@@ -135,6 +135,72 @@ MaterialDerived derive_material(const afsbem_material &m) {
     return d;
 }
 
+// Preconditioner clusters: recursive coordinate bisection of the collocation
+// points P.cen (split at the median of the longest box side) until a cell holds
+// at most kClusterElems points.
+void plan_clusters(HostPlan &P) {
+    const int64_t nt = P.n_tri;
+    {
+        std::vector<int32_t> ids(nt);
+        for (int64_t e = 0; e < nt; ++e)
+            ids[e] = (int32_t)e;
+        P.clus_ptr.assign(1, 0);
+        P.clus_elem.clear();
+        std::vector<std::pair<int64_t, int64_t>> stack{{0, nt}};
+        while (!stack.empty()) {
+            auto [b, e] = stack.back();
+            stack.pop_back();
+            if (e - b <= kClusterElems) {
+                for (int64_t q = b; q < e; ++q)
+                    P.clus_elem.push_back(ids[q]);
+                P.clus_ptr.push_back((int64_t)P.clus_elem.size());
+                continue;
+            }
+            double lo3[3] = {1e300, 1e300, 1e300}, hi3[3] = {-1e300, -1e300, -1e300};
+            for (int64_t q = b; q < e; ++q) {
+                const double *cc = &P.cen[3 * (size_t)ids[q]];
+                for (int dd = 0; dd < 3; ++dd) {
+                    lo3[dd] = std::min(lo3[dd], cc[dd]);
+                    hi3[dd] = std::max(hi3[dd], cc[dd]);
+                }
+            }
+            int ax = 0;
+            for (int dd = 1; dd < 3; ++dd)
+                if (hi3[dd] - lo3[dd] > hi3[ax] - lo3[ax])
+                    ax = dd;
+            const int64_t mid = b + (e - b) / 2;
+            auto key = [&](int32_t id) { return P.cen[3 * (size_t)id + ax]; };
+            std::nth_element(ids.begin() + b, ids.begin() + mid, ids.begin() + e,
+                             [&](int32_t u, int32_t w) { return key(u) < key(w) || (key(u) == key(w) && u < w); });
+            stack.push_back({mid, e});
+            stack.push_back({b, mid});
+        }
+    }
+}
+
+// Taylor coefficients of r psi and r chi in x = s r / c_s (and of r^2 psi',
+// r^2 chi', whose n-th coefficient is (n-1) times the former): expanding
+// e^{-x} and e^{-beta x} in the closed forms, the negative powers cancel and
+// the x^n coefficient is
+//   r psi: (-1)^n [(n+1)^2 + (n+1) beta^(n+2)] / (n+2)!
+//   r chi: (-1)^n (n^2 - 1)(1 - beta^(n+2)) / (n+2)!
+void plan_series(const MaterialDerived &mat, HostPlan &P) {
+    P.coef.assign(64, 0.0);
+    for (int n = 0; n < 16; ++n) {
+        double inv_fact = 1.0;
+        for (int k = 2; k <= n + 2; ++k)
+            inv_fact /= k;
+        const double sgn = (n % 2) ? -1.0 : 1.0;
+        const double bpow = std::pow(mat.beta, n + 2);
+        const double a = sgn * ((n + 1.0) * (n + 1.0) + (n + 1.0) * bpow) * inv_fact;
+        const double b = sgn * ((double)n * n - 1.0) * (1.0 - bpow) * inv_fact;
+        P.coef[4 * n + 0] = a;
+        P.coef[4 * n + 1] = b;
+        P.coef[4 * n + 2] = (n - 1.0) * a;
+        P.coef[4 * n + 3] = (n - 1.0) * b;
+    }
+}
+
 void build_plan(const double *xyz, int64_t nv, const int32_t *tri, int64_t nt, const int8_t *kind,
                 const afsbem_quad_policy &pol, const MaterialDerived &mat, HostPlan &P) {
     (void)nv;
@@ -326,70 +392,8 @@ void build_plan(const double *xyz, int64_t nv, const int32_t *tri, int64_t nt, c
             P.self_cpv[9 * e + q] = cpv_scale * cpv[q];
     }
 
-    // ---- preconditioner clusters: recursive coordinate bisection of the
-    // centroids (split at the median of the longest box side) until a cell
-    // holds at most kClusterElems elements
-    {
-        std::vector<int32_t> ids(nt);
-        for (int64_t e = 0; e < nt; ++e)
-            ids[e] = (int32_t)e;
-        P.clus_ptr.assign(1, 0);
-        P.clus_elem.clear();
-        std::vector<std::pair<int64_t, int64_t>> stack{{0, nt}};
-        while (!stack.empty()) {
-            auto [b, e] = stack.back();
-            stack.pop_back();
-            if (e - b <= kClusterElems) {
-                for (int64_t q = b; q < e; ++q)
-                    P.clus_elem.push_back(ids[q]);
-                P.clus_ptr.push_back((int64_t)P.clus_elem.size());
-                continue;
-            }
-            double lo3[3] = {1e300, 1e300, 1e300}, hi3[3] = {-1e300, -1e300, -1e300};
-            for (int64_t q = b; q < e; ++q) {
-                const V3 c = tris[ids[q]].c;
-                const double cc[3] = {c.x, c.y, c.z};
-                for (int dd = 0; dd < 3; ++dd) {
-                    lo3[dd] = std::min(lo3[dd], cc[dd]);
-                    hi3[dd] = std::max(hi3[dd], cc[dd]);
-                }
-            }
-            int ax = 0;
-            for (int dd = 1; dd < 3; ++dd)
-                if (hi3[dd] - lo3[dd] > hi3[ax] - lo3[ax])
-                    ax = dd;
-            const int64_t mid = b + (e - b) / 2;
-            auto key = [&](int32_t id) {
-                const V3 c = tris[id].c;
-                return ax == 0 ? c.x : (ax == 1 ? c.y : c.z);
-            };
-            std::nth_element(ids.begin() + b, ids.begin() + mid, ids.begin() + e,
-                             [&](int32_t u, int32_t w) { return key(u) < key(w) || (key(u) == key(w) && u < w); });
-            stack.push_back({mid, e});
-            stack.push_back({b, mid});
-        }
-    }
-
-    // ---- Taylor coefficients of r psi and r chi in x = s r / c_s (and of
-    // r^2 psi', r^2 chi', whose n-th coefficient is (n-1) times the former):
-    // expanding e^{-x} and e^{-beta x} in the closed forms, the negative powers
-    // cancel and the x^n coefficient is
-    //   r psi: (-1)^n [(n+1)^2 + (n+1) beta^(n+2)] / (n+2)!
-    //   r chi: (-1)^n (n^2 - 1)(1 - beta^(n+2)) / (n+2)!
-    P.coef.assign(64, 0.0);
-    for (int n = 0; n < 16; ++n) {
-        double inv_fact = 1.0;
-        for (int k = 2; k <= n + 2; ++k)
-            inv_fact /= k;
-        const double sgn = (n % 2) ? -1.0 : 1.0;
-        const double bpow = std::pow(mat.beta, n + 2);
-        const double a = sgn * ((n + 1.0) * (n + 1.0) + (n + 1.0) * bpow) * inv_fact;
-        const double b = sgn * ((double)n * n - 1.0) * (1.0 - bpow) * inv_fact;
-        P.coef[4 * n + 0] = a;
-        P.coef[4 * n + 1] = b;
-        P.coef[4 * n + 2] = (n - 1.0) * a;
-        P.coef[4 * n + 3] = (n - 1.0) * b;
-    }
+    plan_clusters(P);
+    plan_series(mat, P);
 }
 
 }  // namespace afsbem

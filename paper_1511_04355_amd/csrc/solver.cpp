@@ -616,6 +616,8 @@ static int krylov_phase(Problem &p, Workspace &ws, const afsbem_solve_opts &o, i
 int solve_one(Problem &p, const afsbem_solve_opts &o, double s_re, double s_im, const double *d_bc,
               const double *d_x0, double *d_a, double *d_u, double *d_t, afsbem_solve_stats *stats,
               hipStream_t st) {
+    AFS_REQUIRE(!(o.matrix_free && p.dev.disc == 1), AFSBEM_EINVAL,
+                "matrix-free application is not available for six-node (Nystrom) problems");
     const int fmt = o.matrix_free ? kFmtBlocks
                                   : ((o.precision == AFSBEM_PREC_MIXED) ? AFSBEM_FMT_SPLIT : AFSBEM_FMT_C128);
     if (!p.ws)
@@ -693,6 +695,8 @@ int solve_pipelined(Problem &p, const afsbem_solve_opts &o, int32_t n_s, const d
                     const double *x0_user, double *a_out, double *u_out, double *t_out,
                     afsbem_solve_stats *stats, hipStream_t caller) {
     const int64_t N = 3 * p.dev.n_tri;
+    AFS_REQUIRE(!(o.matrix_free && p.dev.disc == 1), AFSBEM_EINVAL,
+                "matrix-free application is not available for six-node (Nystrom) problems");
     const int fmt = o.matrix_free ? kFmtBlocks
                                   : ((o.precision == AFSBEM_PREC_MIXED) ? AFSBEM_FMT_SPLIT : AFSBEM_FMT_C128);
     if (!p.ws)

@@ -63,3 +63,16 @@ def test_product_package_never_imports_oracle():
                 text = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in text and "from oracle" not in text, f
                 assert "bem_oracle" not in text, f
+
+
+def test_quadratic_mesh_validation_errors():
+    import paper_1511_04355_amd as afs
+    L = afs.lib()
+    xyz = np.zeros((6, 3))
+    tri6 = np.array([[0, 1, 2, 3, 4, 9]], np.int32)
+    out = ctypes.c_void_p()
+    rc = L.afsbem_mesh_create_quadratic(xyz.ctypes.data, 6, tri6.ctypes.data, 1, ctypes.byref(out))
+    assert rc == afs._lib.EINVAL
+    assert b"out of range" in L.afsbem_last_error()
+    rc = L.afsbem_mesh_create_quadratic(xyz.ctypes.data, 5, tri6.ctypes.data, 1, ctypes.byref(out))
+    assert rc == afs._lib.EINVAL
