@@ -71,7 +71,7 @@ def parse():
                          "combined with the nearest sample's solution)")
     ap.add_argument("--workload", default="cavity_L4",
                     choices=["cavity_L4", "pmc_probe", "cavity_L2_batched", "blocks_batched", "porous_learned",
-                             "porous_matrix_free", "porous_afs_matrix_free", "cavity_L4_afs"],
+                             "porous_matrix_free", "porous_afs_matrix_free", "cavity_L4_afs", "cavity_nystrom"],
                     help="cavity_L4: the contract line (default).  The others print their own JSON line: "
                          "pmc_probe (1 GiB copies + 4 mixed solves, for counter runs), cavity_L2_batched "
                          "(320 triangles, 16 frequencies), blocks_batched (16 seeded porous blocks x 24 "
@@ -79,7 +79,9 @@ def parse():
                          "AFS frequency sequence), porous_matrix_free (64-void block, 300,516 unknowns), "
                          "porous_afs_matrix_free (AFS + matrix-free solves + time synthesis at 300,516 unknowns), "
                          "cavity_L4_afs (AFS on the 15,360-unknown cavity with 1 and --afs-q new frequencies per "
-                         "step, then the all-unknown time history by Eq. 6 and by the batched FSM inversion)")
+                         "step, then the all-unknown time history by Eq. 6 and by the batched FSM inversion), "
+                         "cavity_nystrom (the six-node Nystrom discretisation at --level 3: 23,040 unknowns, accuracy "
+                         "against the closed form beside the flat cavity one level finer)")
     ap.add_argument("--afs-q", type=int, default=4, help="cavity_L4_afs: new frequencies per AFS step")
     ap.add_argument("--precond", type=int, default=0,
                     help="blocks_batched, porous_afs_matrix_free: 0 point, 1 cluster block-Jacobi")
@@ -525,6 +527,46 @@ def run_cavity_L4_afs(args, afs, mg, np, torch):
             "afs_eq6_vs_fsm_all_solves_steps_2_to_31": fsm_cmp}
 
 
+def run_cavity_nystrom(args, afs, mg, np, torch):
+    """The paper's own discretisation (six-node curved triangles, locally
+    corrected Nystrom) on the cavity: level 3, 1,280 elements, 7,680 points,
+    23,040 unknowns, the 64 frequencies of the cavity workload, FP64 true
+    residual <= tol.  Plain FP64 vs mixed + pipelined + extrapolated starts, and
+    the error of the radial wall displacement against the closed form beside
+    the flat level-4 cavity (5,120 triangles, 15,360 unknowns) on the same
+    frequencies."""
+    from tests import analytic
+    s = mg.cavity_frequencies(args.nfreq)
+    ur = np.array([analytic.cavity_ur(sk) for sk in s])
+    res = {"workload": f"cavity_nystrom: six-node icosphere level {args.level} (Nystrom points of the 6-point rule), "
+                       f"{args.nfreq} frequencies, FP64 true rel. residual <= {args.tol}",
+           "unit": "frequency solves/s"}
+    legs = {}
+    for disc, mesh in (("nystrom", mg.cavity_quadratic(args.level)), ("flat", mg.cavity(args.level + 1))):
+        P = afs.Problem.from_mesh(mesh)
+        _, nrm, _, _ = P.points()
+        bc = torch.from_numpy(np.stack([-nrm / sk for sk in s])).cuda()
+        plain = afs.SolveOptions(tol=args.tol, precision=afs.PREC_FP64, batch=1)
+        opt = afs.SolveOptions(tol=args.tol, precision=afs.PREC_MIXED, warm_start=afs.WARM_EXTRAP, batch=0)
+        for leg, o in (("plain_fp64", plain), ("mixed_extrap", opt)):
+            if disc == "flat" and leg == "plain_fp64":
+                continue
+            ms, out = timed(P, s, bc, o, args.steps, args.warmup, torch)
+            a = out["a"].cpu().numpy().reshape(len(s), -1, 3)
+            un = np.einsum("kij,ij->ki", a, -nrm)
+            err = np.max(np.abs(un - ur[:, None]) / np.abs(ur)[:, None])
+            st = out["stats"]
+            legs[f"{disc}_{leg}"] = {"unknowns": P.N, "value": len(s) / (ms * 1e-3), "ms_per_step": ms,
+                                     "max_rel_res_fp64": max(x["rel_res_fp64"] for x in st),
+                                     "matvecs_per_solve": sum(x["iters"] for x in st) / len(st),
+                                     "max_rel_error_vs_closed_form": float(err)}
+        del P
+        torch.cuda.empty_cache()
+    res.update(legs)
+    res["speedup_mixed_vs_plain"] = legs["nystrom_mixed_extrap"]["value"] / legs["nystrom_plain_fp64"]["value"]
+    return res
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -545,7 +587,8 @@ def main():
               "porous_learned": lambda: run_porous_learned(args, afs, mg, np, torch),
               "porous_matrix_free": lambda: run_porous_matrix_free(args, afs, mg, np, torch),
               "porous_afs_matrix_free": lambda: run_porous_afs_matrix_free(args, afs, mg, np, torch),
-              "cavity_L4_afs": lambda: run_cavity_L4_afs(args, afs, mg, np, torch)}[args.workload]
+              "cavity_L4_afs": lambda: run_cavity_L4_afs(args, afs, mg, np, torch),
+              "cavity_nystrom": lambda: run_cavity_nystrom(args, afs, mg, np, torch)}[args.workload]
         print(json.dumps(fn()), flush=True)
         return
     mesh = mg.cavity(args.level)

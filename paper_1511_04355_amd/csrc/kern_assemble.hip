@@ -926,7 +926,8 @@ __device__ __forceinline__ void nys_stage(NysLds &sh, int lane, bool live, const
         sh.L[lane * 6 + b] = live ? L[b] : 0.0;
 }
 
-__device__ __forceinline__ void nys_contract(const NysLds &sh, int lane, double acc[4]) {
+// n_live: points staged in this chunk (wave-uniform, <= 64)
+__device__ __forceinline__ void nys_contract(const NysLds &sh, int lane, int n_live, double acc[4]) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         const int o = lane + 64 * r;
@@ -934,7 +935,7 @@ __device__ __forceinline__ void nys_contract(const NysLds &sh, int lane, double 
             const int b = o / 36, c = o % 36;
             double v = acc[r];
 #pragma unroll 4
-            for (int p = 0; p < 64; ++p)
+            for (int p = 0; p < n_live; ++p)
                 v += sh.L[p * 6 + b] * sh.K[p * kNysKStride + c];
             acc[r] = v;
         }
@@ -983,7 +984,7 @@ __global__ __launch_bounds__(64) void nys_near_kernel(
         }
         nys_stage(sh, lane, live, E, kp, g.n, w, L);
         __syncthreads();
-        nys_contract(sh, lane, acc);
+        nys_contract(sh, lane, (int)(items - c0 < 64 ? items - c0 : 64), acc);
         __syncthreads();
     }
 #pragma unroll
@@ -1100,7 +1101,7 @@ __global__ __launch_bounds__(64) void nys_self_kernel(
         }
         nys_stage(sh, lane, live, E, kp, g.n, w, L);
         __syncthreads();
-        nys_contract(sh, lane, acc);
+        nys_contract(sh, lane, (int)(items - c0 < 64 ? items - c0 : 64), acc);
         __syncthreads();
     }
 #pragma unroll

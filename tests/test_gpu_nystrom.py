@@ -199,3 +199,44 @@ def test_full_size_level3_sampled_rows_and_residual():
     r = np.max(np.abs(bo - Ao @ x))
     assert r <= 1.01 * tol * np.linalg.norm(bg)
     print(f"[nystrom] level 3: {st['iters']} products, sampled-row residual {r / np.linalg.norm(bg):.2e}", flush=True)
+
+
+def test_batched_solve_of_two_nystrom_problems():
+    """Two six-node problems of different sizes and kinds through one
+    lockstep batched call, each frequency against the oracle's LU solution."""
+    import paper_1511_04355_amd as afs
+    from oracle import nystrom as ny
+    m0, m1 = _mixed_cavity(0), mg.cavity_quadratic(1)
+    s0 = np.array([0.25 + 0.5j, 0.25 + 1.3j])
+    s1 = np.array([0.3 + 0.2j, 0.3 + 2.0j, 0.3 + 1.0j])
+    bc0 = np.stack([_point_force_bc(m0, sk)[0] for sk in s0])
+    _, nrm1, _ = ny.nodes(m1)
+    bc1 = np.stack([ny.pressure_bc(m1, sk, nrm1) for sk in s1])
+    probs = [afs.Problem.from_mesh(m0), afs.Problem.from_mesh(m1)]
+    outs, rc = afs.solve_batched(probs, [s0, s1], [torch.from_numpy(bc0).cuda(), torch.from_numpy(bc1).cuda()],
+                                 afs.SolveOptions(tol=1e-8, precision=afs.PREC_FP64))
+    assert rc == 0
+    for m, s, bc, o in ((m0, s0, bc0, outs[0]), (m1, s1, bc1, outs[1])):
+        for k, sk in enumerate(s):
+            assert o["stats"][k]["status"] == 0 and o["stats"][k]["rel_res_fp64"] <= 1e-8
+            xo = ny.solve(m, sk, bc[k])
+            a = o["a"][k].cpu().numpy()
+            assert np.linalg.norm(a - xo) / np.linalg.norm(xo) <= 1e-6
+
+
+def test_afs_driver_on_a_nystrom_problem():
+    """Adaptive frequency sampling driving the six-node solve: every sampled
+    response equals the oracle's discrete solution at that frequency."""
+    import paper_1511_04355_amd as afs
+    from oracle import nystrom as ny
+    m = mg.cavity_quadratic(1)
+    P = afs.Problem.from_mesh(m)
+    _, nrm, _, _ = P.points()
+    shape = -nrm
+    dofs = np.sort(np.random.default_rng(8).choice(P.N, 6, replace=False))
+    out = P.afs(afs.afs_params(20.0, 0.25, 64), shape, dofs, 4, load_kind=0, opts=afs.SolveOptions(tol=1e-10))
+    assert out["converged"] and out["Nc"] <= 33
+    for k in range(0, out["Nc"], 9):
+        sk = out["s"][k]
+        x = ny.solve(m, sk, shape / sk)
+        assert np.max(np.abs(out["F"][k] - x[dofs])) <= 1e-7 * np.max(np.abs(x[dofs]))
