@@ -71,7 +71,8 @@ def parse():
                          "combined with the nearest sample's solution)")
     ap.add_argument("--workload", default="cavity_L4",
                     choices=["cavity_L4", "pmc_probe", "cavity_L2_batched", "blocks_batched", "porous_learned",
-                             "porous_matrix_free", "porous_afs_matrix_free", "cavity_L4_afs", "cavity_nystrom"],
+                             "porous_matrix_free", "porous_afs_matrix_free", "cavity_L4_afs", "cavity_nystrom",
+                             "porous_hmat"],
                     help="cavity_L4: the contract line (default).  The others print their own JSON line: "
                          "pmc_probe (1 GiB copies + 4 mixed solves, for counter runs), cavity_L2_batched "
                          "(320 triangles, 16 frequencies), blocks_batched (16 seeded porous blocks x 24 "
@@ -81,8 +82,10 @@ def parse():
                          "cavity_L4_afs (AFS on the 15,360-unknown cavity with 1 and --afs-q new frequencies per "
                          "step, then the all-unknown time history by Eq. 6 and by the batched FSM inversion), "
                          "cavity_nystrom (the six-node Nystrom discretisation at --level 3: 23,040 unknowns, accuracy "
-                         "against the closed form beside the flat cavity one level finer)")
+                         "against the closed form beside the flat cavity one level finer), porous_hmat (300,516 "
+                         "unknowns: hierarchical vs on-the-fly inner operator of the matrix-free solve)")
     ap.add_argument("--afs-q", type=int, default=4, help="cavity_L4_afs: new frequencies per AFS step")
+    ap.add_argument("--hmat-eps", type=float, default=1e-5, help="porous_hmat: accuracy of the low-rank blocks")
     ap.add_argument("--precond", type=int, default=0,
                     help="blocks_batched, porous_afs_matrix_free: 0 point, 1 cluster block-Jacobi")
     ap.add_argument("--afs-ns", type=int, default=64, help="porous_afs_matrix_free: FSM size Ns of the band")
@@ -379,6 +382,52 @@ def run_porous_matrix_free(args, afs, mg, np, torch):
 
 
 
+def run_porous_hmat(args, afs, mg, np, torch):
+    """64-void porous block (300,516 unknowns): the hierarchical inner operator
+    (matrix_free = 2: low-rank cross-approximation blocks + dense near blocks,
+    built per frequency) against the on-the-fly FP32 inner operator
+    (matrix_free = 1); accuracy of one hierarchical product against the FP64
+    on-the-fly product, then mixed solves at s = eta and mid-band with cluster
+    block-Jacobi preconditioning (one progress line per solve)."""
+    mesh = mg.lattice_block(4, 39, 3, 2000, rmax=0.45)
+    P = afs.Problem.from_mesh(mesh)
+    N = 3 * mesh.n_tri
+    eta = 3.0 * np.log(10.0) / 300.0
+    res = {"workload": f"porous_hmat: 64-void block ({mesh.n_tri} elements, {N} unknowns), hmat_eps {args.hmat_eps}"}
+    rng = np.random.default_rng(0)
+    x = torch.from_numpy(rng.standard_normal(N) + 1j * rng.standard_normal(N)).cuda()
+    s_mid = eta + 0.4j
+    y_ref, _ = P.matvec_free(s_mid, x, precision=0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    y, info = P.hmat_matvec(s_mid, x, eps=args.hmat_eps)
+    torch.cuda.synchronize()
+    res["product_mid_band"] = {"build_and_apply_s": time.perf_counter() - t0,
+                               "rel_err_vs_fp64_on_the_fly": (torch.linalg.norm(y - y_ref) /
+                                                              torch.linalg.norm(y_ref)).item(), **info}
+    print(f"[hmat-300k] product: {res['product_mid_band']}", file=sys.stderr, flush=True)
+    del y, y_ref
+    for name, sk in (("s_eta", eta + 0.0j), ("s_mid_band", s_mid)):
+        for mf in (2, 1):
+            s = np.array([sk])
+            o = afs.SolveOptions(tol=args.tol, precision=afs.PREC_MIXED, matrix_free=mf, restart=100, max_iter=4000,
+                                 profile=1, batch=1, precond=1, hmat_eps=args.hmat_eps)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            out = P.solve(s, _bcs(mesh, s, torch, np), o, want_ut=False)
+            torch.cuda.synchronize()
+            st = out["stats"][0]
+            key = f"solve_{name}_{'hmat' if mf == 2 else 'on_the_fly'}"
+            res[key] = {"seconds": time.perf_counter() - t0, "inner_products": st["gemv_count"],
+                        "inner_ms_avg": st["gemv_ms"] / max(st["gemv_count"], 1),
+                        "fp64_products": st["gemv64_count"],
+                        "fp64_ms_avg": st["gemv64_ms"] / max(st["gemv64_count"], 1),
+                        "rel_res_fp64": st["rel_res_fp64"], "setup_ms": st["t_assemble_ms"]}
+            print(f"[hmat-300k] {key}: {res[key]}", file=sys.stderr, flush=True)
+        res[f"speedup_{name}"] = res[f"solve_{name}_on_the_fly"]["seconds"] / res[f"solve_{name}_hmat"]["seconds"]
+    return res
+
+
 def run_porous_afs_matrix_free(args, afs, mg, np, torch):
     """The whole pipeline at 300,516 unknowns: adaptive frequency sampling from
     J0 = 8 Chebyshev frequencies (band of Ns = 64: Omega = 0.67 at T = 300,
@@ -588,7 +637,8 @@ def main():
               "porous_matrix_free": lambda: run_porous_matrix_free(args, afs, mg, np, torch),
               "porous_afs_matrix_free": lambda: run_porous_afs_matrix_free(args, afs, mg, np, torch),
               "cavity_L4_afs": lambda: run_cavity_L4_afs(args, afs, mg, np, torch),
-              "cavity_nystrom": lambda: run_cavity_nystrom(args, afs, mg, np, torch)}[args.workload]
+              "cavity_nystrom": lambda: run_cavity_nystrom(args, afs, mg, np, torch),
+              "porous_hmat": lambda: run_porous_hmat(args, afs, mg, np, torch)}[args.workload]
         print(json.dumps(fn()), flush=True)
         return
     mesh = mg.cavity(args.level)

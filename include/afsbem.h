@@ -170,6 +170,19 @@ int afsbem_matvec_free_device(afsbem_problem *p, double s_re, double s_im, int p
  * the dense GEMV (1/4x to 4x of the default) on the live operands with HIP
  * events and keeps the fastest for the rest of the process.  enabled = 0
  * uses the defaults for sizes not yet tuned. */
+/* Hierarchical form of the matrix-free operator at s (the inner operator of
+ * matrix_free = 2; Section 2.1 names an accelerated product, this is the
+ * low-rank one described at afsbem_solve_opts.matrix_free): builds the
+ * frequency's near/self blocks, dense blocks and cross-approximation factors,
+ * then y = A_H(s) x for d_x, d_y (N complex doubles, device).  max_rank,
+ * n_lowrank, n_dense (nullable): the largest rank found, the numbers of
+ * low-rank and dense blocks.  Returns AFSBEM_ENOCONV (y still written, from
+ * the factors as found) when a block did not reach eps within 128 terms.
+ * Flat-element problems only. */
+int afsbem_hmat_matvec_device(afsbem_problem *p, double s_re, double s_im, double eps, double eta, const void *d_x,
+                              void *d_y, int32_t *max_rank, int64_t *n_lowrank, int64_t *n_dense,
+                              void *hip_stream);
+
 int afsbem_autotune_set(int enabled);
 /* Text table of the tuned choices and the measured times; len receives the
  * full length, buf (nullable, cap bytes) a NUL-terminated copy. */
@@ -233,9 +246,20 @@ typedef struct {
     int32_t matrix_free; /* 1: no stored matrix; every product evaluates the far-field rule on the
                             fly (FP64, or FP32 for the inner products of the mixed path) and adds
                             the near/self blocks formed once per frequency in FP64; memory
-                            O(N + near pairs) instead of O(N^2) */
+                            O(N + near pairs) instead of O(N^2).
+                            2: as 1, but the inner products of the mixed path use a hierarchical
+                            form of the same operator built once per frequency (a fast far field
+                            in place of the accelerated product the paper takes, Section 2.1):
+                            admissible cluster pairs as low-rank factors from adaptive cross
+                            approximation to hmat_eps, the rest as dense blocks; the FP64 outer
+                            residual stays the on-the-fly operator.  Needs precision = MIXED;
+                            an admissible block that does not reach hmat_eps within 128 terms
+                            leaves that frequency on the on-the-fly inner operator. */
     int32_t no_graph;    /* batched solve: 1 = launch every kernel directly instead of replaying
                             the captured graphs of four Arnoldi steps (default 0) */
+    double hmat_eps;     /* matrix_free = 2: relative accuracy of each low-rank block (0: 1e-5) */
+    double hmat_eta;     /* matrix_free = 2: admissibility, separation >= hmat_eta x the larger
+                            cluster radius (0: 1.0) */
 } afsbem_solve_opts;
 
 typedef struct {

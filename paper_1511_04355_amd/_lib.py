@@ -42,7 +42,7 @@ class _Opts(ctypes.Structure):
                 ("precision", ctypes.c_int32), ("warm_start", ctypes.c_int32), ("inner_tol", ctypes.c_double),
                 ("batch", ctypes.c_int32), ("fault_inject", ctypes.c_uint32), ("profile", ctypes.c_int32),
                 ("learn_steps", ctypes.c_int32), ("precond", ctypes.c_int32), ("matrix_free", ctypes.c_int32),
-                ("no_graph", ctypes.c_int32)]
+                ("no_graph", ctypes.c_int32), ("hmat_eps", ctypes.c_double), ("hmat_eta", ctypes.c_double)]
 
 
 class _Stats(ctypes.Structure):
@@ -91,6 +91,7 @@ def lib():
         L.afsbem_autotune_set.argtypes = [ctypes.c_int]
         L.afsbem_autotune_report.argtypes = [P, i64, P]
         L.afsbem_matvec_free_device.argtypes = [P, d, d, ctypes.c_int, P, P, P, P, P]
+        L.afsbem_hmat_matvec_device.argtypes = [P, d, d, d, d, P, P, P, P, P, P]
         L.afsbem_solve_opts_default.argtypes = [P]
         L.afsbem_problem_clusters.argtypes = [P, P, P, P]
         L.afsbem_precond_apply_device.argtypes = [P, ctypes.c_int, P, P, P, P, P]
@@ -162,11 +163,13 @@ class SolveOptions:
     precond: int = 0
     matrix_free: int = 0
     no_graph: int = 0
+    hmat_eps: float = 0.0
+    hmat_eta: float = 0.0
 
     def _c(self):
         return _Opts(self.tol, self.restart, self.max_iter, self.precision, self.warm_start, self.inner_tol,
                      self.batch, self.fault_inject, self.profile, self.learn_steps, self.precond, self.matrix_free,
-                     self.no_graph)
+                     self.no_graph, self.hmat_eps, self.hmat_eta)
 
 
 class Problem:
@@ -305,6 +308,21 @@ class Problem:
         _check(lib().afsbem_matvec_free_device(self._h, s.real, s.imag, int(precision), _ptr(bc_val), _ptr(x),
                                                _ptr(y), _ptr(b), _stream()))
         return y, b
+
+    def hmat_matvec(self, s, x, eps=1e-5, eta=1.0):
+        """y = A_H(s) x with the hierarchical (low-rank far field) form of the
+        matrix-free operator.  Returns (y, info) with info = dict(max_rank,
+        n_lowrank, n_dense, converged)."""
+        import torch
+        x = x.contiguous()
+        assert x.dtype == torch.complex128 and x.numel() == self.N and x.is_cuda
+        y = torch.empty(self.N, dtype=torch.complex128, device="cuda")
+        mr, nl, nd = ctypes.c_int32(), ctypes.c_int64(), ctypes.c_int64()
+        s = complex(s)
+        rc = lib().afsbem_hmat_matvec_device(self._h, s.real, s.imag, float(eps), float(eta), _ptr(x), _ptr(y),
+                                             ctypes.byref(mr), ctypes.byref(nl), ctypes.byref(nd), _stream())
+        _check(rc, allow=(ENOCONV,))
+        return y, {"max_rank": mr.value, "n_lowrank": nl.value, "n_dense": nd.value, "converged": rc == 0}
 
     def clusters(self):
         n = ctypes.c_int64()

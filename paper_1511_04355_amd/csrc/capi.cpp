@@ -67,6 +67,8 @@ static void free_problem(afsbem_problem *h) {
     h->p.learn = nullptr;
     delete h->p.barena;
     h->p.barena = nullptr;
+    delete h->p.hmat;
+    h->p.hmat = nullptr;
     if (h->p.st_asm)
         (void)hipStreamDestroy(h->p.st_asm);
     if (h->p.st_sol)
@@ -352,6 +354,41 @@ int afsbem_matvec_free_device(afsbem_problem *p, double s_re, double s_im, int p
     });
 }
 
+int afsbem_hmat_matvec_device(afsbem_problem *p, double s_re, double s_im, double eps, double eta, const void *d_x,
+                              void *d_y, int32_t *max_rank, int64_t *n_lowrank, int64_t *n_dense,
+                              void *hip_stream) {
+    return guarded([&] {
+        AFS_REQUIRE(p && d_x && d_y, AFSBEM_EINVAL, "null pointer argument");
+        AFS_REQUIRE(std::isfinite(s_re) && std::isfinite(s_im), AFSBEM_EINVAL, "non-finite s");
+        AFS_REQUIRE(eps > 0.0 && eps < 1.0 && eta > 0.0 && std::isfinite(eta), AFSBEM_EINVAL,
+                    "eps must be in (0, 1) and eta > 0");
+        AFS_REQUIRE(p->p.dev.disc == 0, AFSBEM_EINVAL, "the hierarchical operator is built for flat-element problems");
+        hipStream_t st = static_cast<hipStream_t>(hip_stream);
+        Problem &P = p->p;
+        const int64_t N = 3 * P.dev.n_tri;
+        Workspace ws;
+        ws.ensure(P, kFmtBlocks, 1, 0);
+        AFS_HIP(hipMemsetAsync(ws.x, 0, (size_t)N * 16, st));  // boundary values: b is not formed here
+        const KernelParams kp = kernel_params(P.mat, s_re, s_im);
+        launch_block_setup(P, kp, ws.x, ws.nearblk, ws.selfblk, ws.precond, ws.asm_scratch, st);
+        hmat_ensure(P, eta);
+        hmat_setup(P, ws, kp, eps, st);
+        AFS_HIP(hipStreamSynchronize(st));
+        const bool ok = hmat_finish(P, ws);
+        hmat_apply(P, ws, static_cast<const double *>(d_x), static_cast<double *>(d_y), st);
+        AFS_HIP(hipStreamSynchronize(st));
+        if (max_rank)
+            *max_rank = ws.hm_max_rank;
+        if (n_lowrank)
+            *n_lowrank = (int64_t)P.hmat->lowrank.size() / 4;
+        if (n_dense)
+            *n_dense = (int64_t)P.hmat->dense.size() / 4;
+        if (!ok)
+            set_error("a low-rank block did not reach eps within the term limit");
+        return ok ? AFSBEM_OK : AFSBEM_ENOCONV;
+    });
+}
+
 int afsbem_autotune_set(int enabled) {
     autotune_set_enabled(enabled != 0);
     return AFSBEM_OK;
@@ -494,7 +531,11 @@ int afsbem_solve_device(afsbem_problem *p, int32_t n_s, const double *s, const v
                         o.warm_start == AFSBEM_WARM_EXTRAP,
                     AFSBEM_EINVAL, "unknown warm start");
         AFS_REQUIRE(o.precond == 0 || o.precond == 1, AFSBEM_EINVAL, "precond must be 0 or 1");
-        AFS_REQUIRE(o.matrix_free == 0 || o.matrix_free == 1, AFSBEM_EINVAL, "matrix_free must be 0 or 1");
+        AFS_REQUIRE(o.matrix_free >= 0 && o.matrix_free <= 2, AFSBEM_EINVAL, "matrix_free must be 0, 1 or 2");
+        AFS_REQUIRE(o.matrix_free != 2 || o.precision == AFSBEM_PREC_MIXED, AFSBEM_EINVAL,
+                    "matrix_free = 2 (hierarchical inner operator) needs the mixed precision path");
+        AFS_REQUIRE(o.hmat_eps >= 0.0 && o.hmat_eps < 1.0 && o.hmat_eta >= 0.0 && std::isfinite(o.hmat_eta),
+                    AFSBEM_EINVAL, "hmat_eps must be in [0, 1) and hmat_eta >= 0");
         AFS_REQUIRE(o.warm_start != AFSBEM_WARM_LEARNED || d_a_out, AFSBEM_EINVAL,
                     "the learned warm start needs the solution output buffer");
         hipStream_t st = static_cast<hipStream_t>(hip_stream);

@@ -1,0 +1,60 @@
+// Hierarchical (H-matrix) form of the matrix-free collocation operator: the
+// inner (FP32-precision) operator of the mixed matrix-free solve.
+//
+// A binary cluster tree over the elements (recursive coordinate bisection of
+// the collocation points, leaves of at most kClusterElems elements) and a
+// block partition of (tree, tree): a pair of clusters whose bounding spheres
+// are separated by at least eta times the larger radius, and between which
+// there is no near pair, is admissible and stored as low-rank factors
+// U V^T found by adaptive cross approximation with partial pivoting on the
+// far rule's entries; every other leaf pair is a dense block of the operator
+// (self block, far rule, near-pair correction: the sum the matrix-free
+// product forms).  Indices of blocks are positions in tree order.  Factors
+// are stored in FP32 (the operator serves FP32 products) in a pool carved as
+// terms are found, so memory follows the ranks reached.
+#pragma once
+#include "internal.hpp"
+
+namespace afsbem {
+
+struct Workspace;
+
+constexpr int kHmatKmax = 128;  // terms per low-rank block at most
+
+struct HmatPlan {
+    double eta = 1.0;
+    int64_t n = 0;
+    std::vector<int32_t> perm;      // tree position -> element
+    std::vector<int64_t> dense;     // [nd][4] a0, a1, b0, b1 (tree positions of elements)
+    std::vector<int64_t> lowrank;   // [nl][4]
+    std::vector<int64_t> dense_off; // [nd+1] offsets (complex entries) of the dense blocks
+    int64_t lr_rows = 0;            // sum over low-rank blocks of R + C (one term's entries)
+    std::vector<int64_t> leaves;    // [nleaf][2] row ranges of the leaves
+    std::vector<int64_t> leaf_ptr;  // [nleaf+1]
+    std::vector<int32_t> leaf_item; // dense block d as d, low-rank block l as -(l + 1)
+    int kmax = 0;
+    // device copies
+    int32_t *d_perm = nullptr;
+    int64_t *d_dense = nullptr, *d_lowrank = nullptr, *d_dense_off = nullptr;
+    int64_t *d_leaves = nullptr, *d_leaf_ptr = nullptr;
+    int32_t *d_leaf_item = nullptr;
+    std::vector<void *> allocs;
+    ~HmatPlan();
+};
+
+// cluster tree and block partition of the problem's elements (host), uploaded
+void hmat_build(const Problem &p, double eta, int kmax, HmatPlan &out);
+// p.hmat built for this eta (rebuilt when eta changed; no work in flight may use the old one)
+void hmat_ensure(Problem &p, double eta);
+
+// per-frequency blocks: dense blocks and ACA factors into the workspace
+// (after the matrix-free block setup: nearblk, selfblk), ranks and status
+// copied to pinned host memory on st.  hmat_finish, once st's work has
+// completed, reads them: false when an admissible block did not reach eps
+// within kmax (the operator then stays the on-the-fly one).
+void hmat_setup(const Problem &p, Workspace &ws, const KernelParams &kp, double eps, hipStream_t st);
+bool hmat_finish(const Problem &p, Workspace &ws);
+// y = A_H x
+void hmat_apply(const Problem &p, const Workspace &ws, const double *x, double *y, hipStream_t st);
+
+}  // namespace afsbem

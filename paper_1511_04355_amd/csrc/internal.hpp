@@ -130,6 +130,7 @@ struct DevicePlan {
 struct Workspace;
 struct LearnState;
 struct BatchArena;
+struct HmatPlan;
 
 struct Problem {
     MaterialDerived mat;
@@ -141,6 +142,7 @@ struct Problem {
     hipStream_t st_asm = nullptr, st_sol = nullptr;  // library streams (default priority)
     LearnState *learn = nullptr;                     // warm-start network (created on first use)
     BatchArena *barena = nullptr;                    // batched-solve memory (created on first use)
+    HmatPlan *hmat = nullptr;                        // hierarchical far field (created on first use)
 };
 
 // ----------------------------------------------------- kernel launchers --

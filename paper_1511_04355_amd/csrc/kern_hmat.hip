@@ -1,0 +1,448 @@
+// Hierarchical far field of the matrix-free operator on gfx950: dense blocks
+// and low-rank factors per frequency, and the product y = A_H x.
+//
+// Low-rank blocks: adaptive cross approximation with partial pivoting on the
+// far rule's entries (FP64 arithmetic, terms stored in FP32 in a pool whose
+// slots a work-group takes with one atomic add per term): at step k the residual row i_k (the block's row
+// minus sum_l U_l[i_k] V_l) is evaluated, its largest entry j_k becomes the
+// pivot, V_k = row / row[j_k], U_k = the residual column j_k, and the next row
+// is the largest entry of U_k outside the rows already used; the block stops
+// when |U_k| |V_k| <= eps |S_k|_F (|S_k|_F^2 accumulated as sum |U_l|^2 |V_l|^2,
+// cross terms neglected) and eight probe rows, one in each eighth of the
+// block's rows in tree order (spatially coherent sub-ranges), have residuals
+// below eps times the mean row norm of S_k; a probe row that fails becomes the
+// next pivot (partial pivoting alone can leave a patch of a block's rows
+// unsampled, e.g. where a cluster spans separate surfaces).  One work-group per block; a row
+// or column costs one element-pair block per source or target element.
+//
+// Product: t_l = V_l^T x per low-rank block (one wavefront per term), then one
+// work-group per leaf row range sums its dense blocks (column-major FP32, read
+// coalesced) and the rows of every low-rank block that covers it, in a fixed
+// order (no atomics).
+#include "hmat.hpp"
+#include "kern_eval.hpp"
+#include "solver.hpp"
+
+namespace afsbem {
+
+namespace {
+
+constexpr int kHmKmax = kHmatKmax;
+
+__device__ __forceinline__ double wave_sum64(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+        v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// 3x3 block (m, n) of the matrix-free operator for m != n (far rule; with
+// near = true also the pair's near correction)
+__device__ void hm_pair_block(const KernelParams &kp, const double *__restrict__ colx,
+                              const double *__restrict__ coly, const double *__restrict__ colz,
+                              const double *__restrict__ src, const double *__restrict__ coef, int64_t m, int64_t n,
+                              cd blk[9]) {
+    const double *rec = src + kSrcStride * n;
+    const double nx = rec[28], ny = rec[29], nz = rec[30];
+    const int kind = (int)rec[31];
+    const cd v0[3] = {cd{0, 0}, cd{0, 0}, cd{0, 0}};
+    cd bdummy[3] = {cd{0, 0}, cd{0, 0}, cd{0, 0}};
+    BlockAcc acc;
+    acc.zero();
+    const double xx = colx[m], xy = coly[m], xz = colz[m];
+#pragma unroll 1
+    for (int q = 0; q < kFarNodes; ++q) {
+        PairEval E;
+        eval_pair(kp, coef, xx, xy, xz, rec[4 * q], rec[4 * q + 1], rec[4 * q + 2], nx, ny, nz, E);
+        const double w = rec[4 * q + 3];
+        if (kind == 0)
+            acc_node<0>(E, kp, nx, ny, nz, w, 0.0, v0, acc, bdummy);
+        else
+            acc_node<1>(E, kp, nx, ny, nz, w, 0.0, v0, acc, bdummy);
+    }
+    expand_block(kind, acc, nx, ny, nz, blk);
+}
+
+// dense block d: (3 na) x (3 nb), column-major, FP32 complex
+__global__ __launch_bounds__(256) void hm_dense_kernel(
+    KernelParams kp, const double *__restrict__ colx, const double *__restrict__ coly, const double *__restrict__ colz,
+    const double *__restrict__ src, const double *__restrict__ coef, const int64_t *__restrict__ near_ptr,
+    const int32_t *__restrict__ near_col, const double *__restrict__ nearblk, const double *__restrict__ selfblk,
+    const int32_t *__restrict__ perm, const int64_t *__restrict__ dense, const int64_t *__restrict__ dense_off,
+    float2 *__restrict__ out) {
+    const int64_t d = blockIdx.x;
+    const int64_t a0 = dense[4 * d], b0 = dense[4 * d + 2];
+    const int na = (int)(dense[4 * d + 1] - a0), nb = (int)(dense[4 * d + 3] - b0);
+    const int64_t R = 3 * (int64_t)na;
+    float2 *blk_out = out + dense_off[d];
+    for (int q = threadIdx.x; q < na * nb; q += 256) {
+        const int r = q % na, k = q / na;
+        const int64_t m = perm[a0 + r], n = perm[b0 + k];
+        cd blk[9];
+        if (m == n) {
+            const double *sb = selfblk + 18 * m;
+#pragma unroll
+            for (int e = 0; e < 9; ++e)
+                blk[e] = cd{sb[2 * e], sb[2 * e + 1]};
+        } else {
+            hm_pair_block(kp, colx, coly, colz, src, coef, m, n, blk);
+            for (int64_t pp = near_ptr[m]; pp < near_ptr[m + 1]; ++pp)
+                if (near_col[pp] == n) {
+                    const double *nb9 = nearblk + 18 * pp;
+#pragma unroll
+                    for (int e = 0; e < 9; ++e)
+                        blk[e] = cadd(blk[e], cd{nb9[2 * e], nb9[2 * e + 1]});
+                    break;
+                }
+        }
+#pragma unroll
+        for (int b = 0; b < 3; ++b)
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+                blk_out[(3 * k + b) * R + 3 * r + a] = make_float2((float)blk[3 * a + b].r, (float)blk[3 * a + b].i);
+    }
+}
+
+struct RedMax {
+    double v;
+    int64_t i;
+};
+
+// work-group (256) reductions through LDS
+__device__ __forceinline__ RedMax group_argmax(double v, int64_t i, double *sv, int64_t *si) {
+    const int t = threadIdx.x;
+    sv[t] = v;
+    si[t] = i;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (t < h) {
+            const double o = sv[t + h];
+            const int64_t oi = si[t + h];
+            if (o > sv[t] || (o == sv[t] && oi < si[t])) {
+                sv[t] = o;
+                si[t] = oi;
+            }
+        }
+        __syncthreads();
+    }
+    RedMax r{sv[0], si[0]};
+    __syncthreads();
+    return r;
+}
+
+__device__ __forceinline__ double group_sum256(double v, double *sv) {
+    const int t = threadIdx.x;
+    sv[t] = v;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (t < h)
+            sv[t] += sv[t + h];
+        __syncthreads();
+    }
+    const double r = sv[0];
+    __syncthreads();
+    return r;
+}
+
+// status: 0 converged, 1 out of terms, 2 pool exhausted
+__global__ __launch_bounds__(256) void hm_aca_kernel(
+    KernelParams kp, const double *__restrict__ colx, const double *__restrict__ coly, const double *__restrict__ colz,
+    const double *__restrict__ src, const double *__restrict__ coef, const int32_t *__restrict__ perm,
+    const int64_t *__restrict__ lowrank, int kmax, double eps, float2 *__restrict__ pool, unsigned long long pool_cap,
+    unsigned long long *__restrict__ ctr, int64_t *__restrict__ offs, int *__restrict__ rank_out,
+    int *__restrict__ status_out) {
+    __shared__ double sv[256];
+    __shared__ int64_t si[256];
+    __shared__ double2 cf[kHmKmax];
+    __shared__ int64_t used[kHmKmax + 1];
+    __shared__ int64_t off_k;
+    const int t = threadIdx.x;
+    const int64_t l = blockIdx.x;
+    const int64_t a0 = lowrank[4 * l], b0 = lowrank[4 * l + 2];
+    const int64_t na = lowrank[4 * l + 1] - a0, nb = lowrank[4 * l + 3] - b0;
+    const int64_t R = 3 * na, C = 3 * nb;
+    int64_t *myoffs = offs + l * kmax;
+    int64_t istar = 0;
+    double S2 = 0.0;
+    int k = 0, status = 1, probes_ok = 0, n_probe = 0;
+    bool probing = false;
+    // probe rows spread over the block's row range in tree order (spatially
+    // coherent sub-ranges): the middle of the j-th eighth, component j % 3,
+    // skipping rows already used (same on every thread)
+    constexpr int kProbes = 8;
+    auto probe_row = [&]() {
+        const int j = (n_probe++) % kProbes;
+        int64_t r = 3 * (((2 * (int64_t)j + 1) * na) / (2 * kProbes)) + j % 3;
+        for (int tries = 0; tries <= k; ++tries) {
+            bool was = false;
+            for (int q = 0; q < k; ++q)
+                was = was || (used[q] == r);
+            if (!was)
+                break;
+            r = (r + 1) % R;
+        }
+        return r;
+    };
+    while (k < kmax) {
+        // ---- the term's slot in the pool (a probe row is evaluated, not stored)
+        if (t == 0 && !probing) {
+            const unsigned long long o = atomicAdd(ctr, (unsigned long long)(R + C));
+            off_k = (o + (unsigned long long)(R + C) <= pool_cap) ? (int64_t)o : -1;
+            if (off_k >= 0)
+                myoffs[k] = off_k;
+        }
+        if (t < k) {
+            const float2 u = pool[myoffs[t] + istar];
+            cf[t] = make_double2(u.x, u.y);
+        }
+        __syncthreads();
+        if (!probing && off_k < 0) {
+            status = 2;
+            break;
+        }
+        float2 *Uk = pool + (probing ? 0 : off_k), *Vk = Uk + R;
+        // ---- residual row istar -> V_k (unnormalised)
+        const int64_t m = perm[a0 + istar / 3];
+        const int al = (int)(istar % 3);
+        double best = -1.0, rn = 0.0;
+        int64_t bi = 0;
+        for (int64_t kk = t; kk < nb; kk += 256) {
+            cd blk[9];
+            hm_pair_block(kp, colx, coly, colz, src, coef, m, perm[b0 + kk], blk);
+#pragma unroll
+            for (int be = 0; be < 3; ++be) {
+                const int64_t c = 3 * kk + be;
+                double vr = blk[3 * al + be].r, vi = blk[3 * al + be].i;
+                for (int q = 0; q < k; ++q) {
+                    const double2 u = cf[q];
+                    const float2 v = pool[myoffs[q] + R + c];
+                    vr -= u.x * v.x - u.y * v.y;
+                    vi -= u.x * v.y + u.y * v.x;
+                }
+                if (!probing)
+                    Vk[c] = make_float2((float)vr, (float)vi);
+                const double a2 = vr * vr + vi * vi;
+                rn += a2;
+                if (a2 > best) {
+                    best = a2;
+                    bi = c;
+                }
+            }
+        }
+        const RedMax pv = group_argmax(best, bi, sv, si);
+        const double rn2 = group_sum256(rn, sv);
+        if (probing) {
+            // after the stopping test: probe rows whose residuals are small
+            // against the mean row norm of S confirm it (all kProbes in a row);
+            // otherwise the probe row becomes the next pivot row
+            if (rn2 <= eps * eps * S2 / (double)R) {
+                if (++probes_ok >= kProbes) {
+                    status = 0;
+                    break;
+                }
+                istar = probe_row();
+                continue;
+            }
+            probing = false;  // the probe row becomes the next pivot row: evaluate and store it
+            probes_ok = 0;
+            continue;
+        }
+        if (!(pv.v > 0.0)) {  // the residual row vanishes: nothing left to approximate
+            status = 0;
+            break;
+        }
+        const int64_t jstar = pv.i;
+        const float2 pf = Vk[jstar];
+        __syncthreads();
+        const double pd = (double)pf.x * pf.x + (double)pf.y * pf.y;
+        const double ir = pf.x / pd, ii = -pf.y / pd;  // 1 / pivot
+        double nv = 0.0;
+        for (int64_t c = t; c < C; c += 256) {
+            const float2 v = Vk[c];
+            const double wr = v.x * ir - v.y * ii, wi = v.x * ii + v.y * ir;
+            Vk[c] = make_float2((float)wr, (float)wi);
+            nv += wr * wr + wi * wi;
+        }
+        // ---- residual column jstar -> U_k
+        if (t < k) {
+            const float2 v = pool[myoffs[t] + R + jstar];
+            cf[t] = make_double2(v.x, v.y);
+        }
+        if (t == 0)
+            used[k] = istar;
+        __syncthreads();
+        const int64_t n = perm[b0 + jstar / 3];
+        const int be = (int)(jstar % 3);
+        double nu = 0.0;
+        best = -1.0;
+        bi = 0;
+        for (int64_t i = t; i < na; i += 256) {
+            cd blk[9];
+            hm_pair_block(kp, colx, coly, colz, src, coef, perm[a0 + i], n, blk);
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const int64_t r = 3 * i + a;
+                double ur = blk[3 * a + be].r, ui = blk[3 * a + be].i;
+                for (int q = 0; q < k; ++q) {
+                    const double2 v = cf[q];
+                    const float2 u = pool[myoffs[q] + r];
+                    ur -= u.x * v.x - u.y * v.y;
+                    ui -= u.x * v.y + u.y * v.x;
+                }
+                Uk[r] = make_float2((float)ur, (float)ui);
+                const double a2 = ur * ur + ui * ui;
+                nu += a2;
+                bool was = false;
+                for (int q = 0; q <= k; ++q)
+                    was = was || (used[q] == r);
+                if (!was && a2 > best) {
+                    best = a2;
+                    bi = r;
+                }
+            }
+        }
+        const double nu2 = group_sum256(nu, sv);
+        const double nv2 = group_sum256(nv, sv);
+        const RedMax nx = group_argmax(best, bi, sv, si);
+        ++k;
+        S2 += nu2 * nv2;
+        // the terms span the block (k = min(R, C): U V^T is then the block itself)
+        if (k >= (R < C ? R : C) || !(nx.v >= 0.0)) {
+            status = 0;
+            break;
+        }
+        if (nu2 * nv2 <= eps * eps * S2) {  // stopping test met: confirm on probe rows
+            probing = true;
+            probes_ok = 0;
+            istar = probe_row();
+            continue;
+        }
+        istar = nx.i;
+    }
+    if (t == 0) {
+        rank_out[l] = k;
+        status_out[l] = status;
+    }
+}
+
+// t[l][q] = V_q^T x on the block's columns, one wavefront per term
+__global__ __launch_bounds__(256) void hm_vt_kernel(const int64_t *__restrict__ lowrank, int kmax,
+                                                    const int *__restrict__ rank, const int64_t *__restrict__ offs,
+                                                    const int32_t *__restrict__ perm, const float2 *__restrict__ pool,
+                                                    const double2 *__restrict__ x, double2 *__restrict__ tv) {
+    const int64_t l = blockIdx.x;
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t a0 = lowrank[4 * l], b0 = lowrank[4 * l + 2];
+    const int64_t R = 3 * (lowrank[4 * l + 1] - a0), C = 3 * (lowrank[4 * l + 3] - b0);
+    const int rk = rank[l];
+    for (int q = w; q < rk; q += 4) {
+        const float2 *V = pool + offs[l * kmax + q] + R;
+        double sr = 0.0, si = 0.0;
+        for (int64_t c = lane; c < C; c += 64) {
+            const float2 v = V[c];
+            const double2 xv = x[3 * (int64_t)perm[b0 + c / 3] + c % 3];
+            sr += v.x * xv.x - v.y * xv.y;
+            si += v.x * xv.y + v.y * xv.x;
+        }
+        sr = wave_sum64(sr);
+        si = wave_sum64(si);
+        if (lane == 0)
+            tv[l * kmax + q] = make_double2(sr, si);
+    }
+}
+
+// one work-group per leaf row range (at most 3 kClusterElems rows)
+__global__ __launch_bounds__(128) void hm_apply_kernel(
+    const int64_t *__restrict__ leaves, const int64_t *__restrict__ leaf_ptr, const int32_t *__restrict__ leaf_item,
+    const int64_t *__restrict__ dense, const int64_t *__restrict__ dense_off, const int64_t *__restrict__ lowrank,
+    int kmax, const int *__restrict__ rank, const int64_t *__restrict__ offs, const int32_t *__restrict__ perm,
+    const float2 *__restrict__ dblk, const float2 *__restrict__ pool, const double2 *__restrict__ tv,
+    const double2 *__restrict__ x, double2 *__restrict__ y) {
+    const int64_t L = blockIdx.x;
+    const int64_t L0 = leaves[2 * L], rows = 3 * (leaves[2 * L + 1] - L0);
+    const int r = threadIdx.x;
+    const bool live = r < rows;
+    double ar = 0.0, ai = 0.0;
+    for (int64_t it = leaf_ptr[L]; it < leaf_ptr[L + 1]; ++it) {
+        const int32_t item = leaf_item[it];
+        if (item >= 0) {
+            const int64_t b0 = dense[4 * item + 2];
+            const int64_t C = 3 * (dense[4 * item + 3] - b0);
+            const float2 *D = dblk + dense_off[item];
+            for (int64_t c = 0; c < C; ++c) {
+                const double2 xv = x[3 * (int64_t)perm[b0 + c / 3] + c % 3];
+                if (live) {
+                    const float2 a = D[c * rows + r];
+                    ar += (double)a.x * xv.x - (double)a.y * xv.y;
+                    ai += (double)a.x * xv.y + (double)a.y * xv.x;
+                }
+            }
+        } else {
+            const int64_t lb = -(int64_t)item - 1;
+            const int64_t rr = 3 * (L0 - lowrank[4 * lb]) + r;
+            const int rk = rank[lb];
+            if (live)
+                for (int q = 0; q < rk; ++q) {
+                    const float2 u = pool[offs[lb * kmax + q] + rr];
+                    const double2 tq = tv[lb * kmax + q];
+                    ar += u.x * tq.x - u.y * tq.y;
+                    ai += u.x * tq.y + u.y * tq.x;
+                }
+        }
+    }
+    if (live)
+        y[3 * (int64_t)perm[L0 + r / 3] + r % 3] = make_double2(ar, ai);
+}
+
+}  // namespace
+
+void hmat_setup(const Problem &p, Workspace &ws, const KernelParams &kp, double eps, hipStream_t st) {
+    const HmatPlan &H = *p.hmat;
+    const DevicePlan &d = p.dev;
+    const int64_t nd = (int64_t)H.dense.size() / 4, nl = (int64_t)H.lowrank.size() / 4;
+    ws.hm_alloc(H);
+    if (nd)
+        hm_dense_kernel<<<(unsigned)nd, 256, 0, st>>>(kp, d.colx, d.coly, d.colz, d.src, d.coef, d.near_ptr,
+                                                       d.near_col, ws.nearblk, ws.selfblk, H.d_perm, H.d_dense,
+                                                       H.d_dense_off, ws.hm_dense);
+    AFS_HIP(hipMemsetAsync(ws.hm_ctr, 0, sizeof(unsigned long long), st));
+    if (nl)
+        hm_aca_kernel<<<(unsigned)nl, 256, 0, st>>>(kp, d.colx, d.coly, d.colz, d.src, d.coef, H.d_perm,
+                                                     H.d_lowrank, H.kmax, eps, ws.hm_pool,
+                                                     (unsigned long long)ws.hm_pool_cap, ws.hm_ctr, ws.hm_offs,
+                                                     ws.hm_rank, ws.hm_status);
+    AFS_HIP(hipGetLastError());
+    if (nl) {
+        AFS_HIP(hipMemcpyAsync(ws.hm_host, ws.hm_rank, nl * sizeof(int), hipMemcpyDeviceToHost, st));
+        AFS_HIP(hipMemcpyAsync(ws.hm_host + nl, ws.hm_status, nl * sizeof(int), hipMemcpyDeviceToHost, st));
+    }
+    ws.hm_ok = false;  // until hmat_finish has read the ranks
+}
+
+bool hmat_finish(const Problem &p, Workspace &ws) {
+    const int64_t nl = (int64_t)p.hmat->lowrank.size() / 4;
+    ws.hm_max_rank = 0;
+    bool ok = true;
+    for (int64_t l = 0; l < nl; ++l) {
+        ws.hm_max_rank = std::max(ws.hm_max_rank, ws.hm_host[l]);
+        ok = ok && ws.hm_host[nl + l] == 0;
+    }
+    ws.hm_ok = ok;
+    return ok;
+}
+
+void hmat_apply(const Problem &p, const Workspace &ws, const double *x, double *y, hipStream_t st) {
+    const HmatPlan &H = *p.hmat;
+    const int64_t nl = (int64_t)H.lowrank.size() / 4, nleaf = (int64_t)H.leaves.size() / 2;
+    const double2 *xv = reinterpret_cast<const double2 *>(x);
+    if (nl)
+        hm_vt_kernel<<<(unsigned)nl, 256, 0, st>>>(H.d_lowrank, H.kmax, ws.hm_rank, ws.hm_offs, H.d_perm, ws.hm_pool,
+                                                    xv, ws.hm_t);
+    hm_apply_kernel<<<(unsigned)nleaf, 128, 0, st>>>(H.d_leaves, H.d_leaf_ptr, H.d_leaf_item, H.d_dense,
+                                                      H.d_dense_off, H.d_lowrank, H.kmax, ws.hm_rank, ws.hm_offs,
+                                                      H.d_perm, ws.hm_dense, ws.hm_pool, ws.hm_t, xv,
+                                                      reinterpret_cast<double2 *>(y));
+    AFS_HIP(hipGetLastError());
+}
+
+}  // namespace afsbem

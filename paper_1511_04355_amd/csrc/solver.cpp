@@ -34,7 +34,51 @@ static void *dalloc(size_t bytes) {
 
 Workspace::~Workspace() { release(); }
 
+void Workspace::hm_release() {
+    for (void *p : {(void *)hm_dense, (void *)hm_pool, (void *)hm_ctr, (void *)hm_offs, (void *)hm_t,
+                    (void *)hm_rank, (void *)hm_status})
+        if (p)
+            (void)hipFree(p);
+    if (hm_host)
+        (void)hipHostFree(hm_host);
+    hm_host = nullptr;
+    hm_dense = hm_pool = nullptr;
+    hm_ctr = nullptr;
+    hm_offs = nullptr;
+    hm_pool_cap = 0;
+    hm_t = nullptr;
+    hm_rank = hm_status = nullptr;
+    hm_cap[0] = hm_cap[1] = hm_cap[2] = 0;
+    hm_ok = false;
+}
+
+void Workspace::hm_alloc(const HmatPlan &H) {
+    const size_t nd = (size_t)H.dense_off.back(), nl = H.lowrank.size() / 4;
+    // pool for an average of 64 terms per block, within half the free memory
+    // (a block that finds the pool spent leaves the frequency on the on-the-fly operator)
+    size_t nf = (size_t)H.lr_rows * 64;
+    if (hm_dense && hm_cap[0] >= nd && hm_cap[1] >= nf && hm_cap[2] >= nl)
+        return;
+    hm_release();
+    size_t free_b = 0, total_b = 0;
+    AFS_HIP(hipMemGetInfo(&free_b, &total_b));
+    nf = std::min(nf, (size_t)(0.5 * (double)(free_b > (size_t)nd * 8 ? free_b - (size_t)nd * 8 : 0)) / 8);
+    hm_dense = (float2 *)dalloc(std::max<size_t>(nd, 1) * 8);
+    hm_pool = (float2 *)dalloc(std::max<size_t>(nf, 1) * 8);
+    hm_pool_cap = nf;
+    hm_ctr = (unsigned long long *)dalloc(sizeof(unsigned long long));
+    hm_offs = (int64_t *)dalloc(std::max<size_t>(nl, 1) * H.kmax * sizeof(int64_t));
+    hm_rank = (int *)dalloc(std::max<size_t>(nl, 1) * 4);
+    hm_status = (int *)dalloc(std::max<size_t>(nl, 1) * 4);
+    hm_t = (double2 *)dalloc(std::max<size_t>(nl, 1) * H.kmax * 16);
+    AFS_HIP(hipHostMalloc((void **)&hm_host, std::max<size_t>(nl, 1) * 2 * sizeof(int), hipHostMallocDefault));
+    hm_cap[0] = nd;
+    hm_cap[1] = nf;
+    hm_cap[2] = nl;
+}
+
 void Workspace::release() {
+    hm_release();
     for (void *p : {(void *)A, (void *)A_lo, (void *)nearblk, (void *)selfblk, (void *)b, (void *)precond, (void *)asm_scratch, (void *)gemv_partial,
                     (void *)V, (void *)w, (void *)z, (void *)x, (void *)r, (void *)tmp, (void *)rin, (void *)xo,
                     (void *)xstart,
@@ -150,7 +194,10 @@ void Operator::apply(const double *xin, double *yout, hipStream_t st) const {
     if (format == kFmtBlocks) {
         if (eb)
             AFS_HIP(hipEventRecord(eb, st));
-        mf_apply(*prob, kp, precision, 0, nearblk, selfblk, xin, yout, partial, st);
+        if (precision == 1 && hm && hm->hm_ok)
+            hmat_apply(*prob, *hm, xin, yout, st);
+        else
+            mf_apply(*prob, kp, precision, 0, nearblk, selfblk, xin, yout, partial, st);
         if (ee)
             AFS_HIP(hipEventRecord(ee, st));
         ++*counter;
@@ -417,6 +464,15 @@ static double elapsed_ms(hipEvent_t a, hipEvent_t b) {
     return (double)ms;
 }
 
+// matrix_free = 2: the inner products of the mixed path through the
+// hierarchical form of the operator (built per frequency in assemble_into)
+static void hm_settings(Workspace &ws, const afsbem_solve_opts &o) {
+    ws.hm_enabled = o.matrix_free == 2;
+    ws.hm_eps = o.hmat_eps > 0.0 ? o.hmat_eps : 1e-5;
+    ws.hm_eta = o.hmat_eta > 0.0 ? o.hmat_eta : 1.0;
+    ws.hm_ok = false;
+}
+
 static void assemble_into(Problem &p, Workspace &ws, int fmt, double s_re, double s_im, const double *d_bc,
                           hipStream_t st, bool profile = false) {
     KernelParams kp = kernel_params(p.mat, s_re, s_im);
@@ -429,6 +485,10 @@ static void assemble_into(Problem &p, Workspace &ws, int fmt, double s_re, doubl
         if (ws.prec_kind == 1) {
             cluster_gather_mf(p, kp, ws.nearblk, ws.selfblk, ws.clgath, st);
             cluster_inverse(p.dev, kFmtBlocks, ws.clgath, nullptr, ws.clinv, st);
+        }
+        if (ws.hm_enabled) {
+            hmat_ensure(p, ws.hm_eta);
+            hmat_setup(p, ws, kp, ws.hm_eps, st);
         }
         return;
     }
@@ -467,8 +527,11 @@ static int krylov_phase(Problem &p, Workspace &ws, const afsbem_solve_opts &o, i
     op64.kp = kp;
     op64.nearblk = ws.nearblk;
     op64.selfblk = ws.selfblk;
+    op64.hm = ws.hm_enabled ? &ws : nullptr;
     const bool mixed = o.precision == AFSBEM_PREC_MIXED;
     const double bnorm = norm2_dev(ws, N, ws.b, st);
+    if (ws.hm_enabled && fmt == kFmtBlocks)
+        hmat_finish(p, ws);  // the frequency's assembly has completed (st waited for it, then synchronised)
     const bool learned = o.warm_start == AFSBEM_WARM_LEARNED;
     const double *x_prev = (d_x0 && o.warm_start != AFSBEM_WARM_NONE) ? d_x0 : nullptr;
     const double *x_net = nullptr;
@@ -624,6 +687,7 @@ int solve_one(Problem &p, const afsbem_solve_opts &o, double s_re, double s_im, 
         p.ws = new Workspace();
     Workspace &ws = *p.ws;
     ws.ensure(p, fmt, o.restart, o.precond);
+    hm_settings(ws, o);
     hipEvent_t e0, e1, e2;
     AFS_HIP(hipEventCreate(&e0));
     AFS_HIP(hipEventCreate(&e1));
@@ -706,6 +770,8 @@ int solve_pipelined(Problem &p, const afsbem_solve_opts &o, int32_t n_s, const d
     Workspace *W[2] = {p.ws, p.ws2};
     W[0]->ensure(p, fmt, o.restart, o.precond);
     W[1]->ensure(p, fmt, o.restart, o.precond);
+    hm_settings(*W[0], o);
+    hm_settings(*W[1], o);
     if (!p.st_asm)
         AFS_HIP(hipStreamCreateWithFlags(&p.st_asm, hipStreamNonBlocking));
     if (!p.st_sol)

@@ -1,6 +1,7 @@
 // Solver internals: device workspace, operator, GMRES.
 #pragma once
 #include "internal.hpp"
+#include "hmat.hpp"
 
 namespace afsbem {
 
@@ -31,6 +32,23 @@ struct Workspace {
     int ev_used = 0;
     hipEvent_t ev_far[2] = {nullptr, nullptr};  // around the far-field kernel (opts.profile)
     bool far_timed = false;
+    // hierarchical far field of the matrix-free operator (solve option matrix_free = 2):
+    // settings, then the frequency's dense blocks, factors, ranks and product scratch
+    int hm_enabled = 0;
+    double hm_eps = 1e-5, hm_eta = 1.0;
+    bool hm_ok = false;
+    int hm_max_rank = 0;
+    float2 *hm_dense = nullptr;
+    float2 *hm_pool = nullptr;             // factor terms: U_q (R entries) then V_q (C entries)
+    size_t hm_pool_cap = 0;                // complex entries
+    unsigned long long *hm_ctr = nullptr;  // pool entries taken
+    int64_t *hm_offs = nullptr;            // [nl][kmax] pool offset of each term
+    double2 *hm_t = nullptr;
+    int *hm_rank = nullptr, *hm_status = nullptr;
+    int *hm_host = nullptr;                // pinned: ranks, then status flags
+    size_t hm_cap[3] = {0, 0, 0};
+    void hm_alloc(const HmatPlan &H);
+    void hm_release();
     void reset_timing() { ev_used = 0; ev_prec.clear(); }
     ~Workspace();
     void release();
@@ -52,6 +70,7 @@ struct Operator {
     const Problem *prob = nullptr;         // matrix-free: plan, frequency, blocks
     KernelParams kp{};
     const double *nearblk = nullptr, *selfblk = nullptr;
+    const Workspace *hm = nullptr;         // FP32 products through the hierarchical form when built
     void apply(const double *x, double *y, hipStream_t st) const;
 };
 

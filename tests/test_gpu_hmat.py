@@ -1,0 +1,101 @@
+"""The hierarchical far field (low-rank cross-approximation blocks + dense
+near blocks) as the inner operator of the mixed matrix-free solve.
+
+It approximates the operator by construction, so the bar is a property: the
+product against the oracle's dense product (or, beyond the oracle's reach, the
+FP64 on-the-fly product) to the requested accuracy, limited by FP32 storage;
+and solves with it reach the FP64 true residual of the exact operator and the
+oracle's LU solution, since the outer residual never uses it.
+"""
+import numpy as np
+import pytest
+
+from synth import meshgen as mg
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _needs_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+
+
+def _x(N, seed):
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal(N) + 1j * rng.standard_normal(N)
+
+
+@pytest.mark.parametrize("name", ["cavity_L3", "block_seed3"])
+def test_hmat_product_against_oracle(name):
+    import paper_1511_04355_amd as afs
+    from oracle import bem
+    mesh = mg.cavity(3) if name == "cavity_L3" else mg.random_block(3)
+    s = 0.25 + 1.3j
+    P = afs.Problem.from_mesh(mesh)
+    x = _x(P.N, 4)
+    print(f"[hmat] {name} N={P.N}", flush=True)
+    A, _ = bem.assemble(mesh, s)
+    yo = A @ x
+    errs = {}
+    for eps in (1e-3, 1e-6):
+        y, info = P.hmat_matvec(s, torch.from_numpy(x).cuda(), eps=eps)
+        assert info["converged"], info
+        errs[eps] = np.linalg.norm(y.cpu().numpy() - yo) / np.linalg.norm(yo)
+        print(f"[hmat] eps {eps}: rel err {errs[eps]:.2e}, {info}", flush=True)
+    assert info["n_lowrank"] > 0 and info["max_rank"] >= 1
+    assert errs[1e-6] < 2e-5          # FP32 storage of the blocks and factors
+    assert errs[1e-3] < 2e-2
+    assert errs[1e-6] < errs[1e-3]
+
+
+def test_hmat_solve_reaches_the_exact_residual():
+    """matrix_free = 2: inner products through the hierarchical operator,
+    outer FP64 residuals on the fly; the solution is the oracle's."""
+    import paper_1511_04355_amd as afs
+    from oracle import bem
+    mesh = mg.cavity(3)
+    s = np.array([0.25 + 0.7j, 0.25 + 2.0j])
+    bc = np.stack([np.asarray(mesh.bc_shape, np.complex128) / sk for sk in s])
+    P = afs.Problem.from_mesh(mesh)
+    tol = 1e-6
+    out = P.solve(s, torch.from_numpy(bc).cuda(),
+                  afs.SolveOptions(tol=tol, precision=afs.PREC_MIXED, matrix_free=2, hmat_eps=1e-5))
+    a = out["a"].cpu().numpy()
+    for k, sk in enumerate(s):
+        st = out["stats"][k]
+        assert st["status"] == 0 and st["rel_res_fp64"] <= tol, st
+        A, b = bem.assemble(mesh, sk)
+        xo = bem.solve_dense(A, b)
+        assert np.linalg.norm(a[k] - xo) / np.linalg.norm(xo) <= 1e-5
+        assert np.linalg.norm(b - A @ a[k]) / np.linalg.norm(b) <= 1.01 * tol
+
+
+def test_hmat_option_checks():
+    import paper_1511_04355_amd as afs
+    mesh = mg.cavity(1)
+    P = afs.Problem.from_mesh(mesh)
+    bc = torch.zeros((1, P.n_tri, 3), dtype=torch.complex128, device="cuda")
+    with pytest.raises(afs.AfsbemError):
+        P.solve([0.3 + 0.5j], bc, afs.SolveOptions(matrix_free=2, precision=afs.PREC_FP64))
+    with pytest.raises(afs.AfsbemError):
+        P.hmat_matvec(0.3 + 0.5j, torch.zeros(P.N, dtype=torch.complex128, device="cuda"), eps=0.0)
+
+
+@pytest.mark.timeout(300)
+def test_hmat_product_full_size_27_voids():
+    """40,320 unknowns (the 27-void block): the hierarchical product against
+    the FP64 on-the-fly product on a random vector at two accuracies."""
+    import paper_1511_04355_amd as afs
+    mesh = mg.lattice_block(3, 20, 2, 1000)
+    P = afs.Problem.from_mesh(mesh)
+    s = complex(3.0 * np.log(10.0) / 300.0, 1.1)
+    x = torch.from_numpy(_x(P.N, 6)).cuda()
+    y_ref, _ = P.matvec_free(s, x, precision=0)
+    for eps, bar in ((1e-4, 1e-3), (1e-6, 2e-5)):
+        y, info = P.hmat_matvec(s, x, eps=eps)
+        err = (torch.linalg.norm(y - y_ref) / torch.linalg.norm(y_ref)).item()
+        print(f"[hmat] 27 voids, eps {eps}: rel err {err:.2e}, {info}", flush=True)
+        assert info["converged"]
+        assert err < bar
