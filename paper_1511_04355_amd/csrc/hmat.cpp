@@ -157,8 +157,19 @@ void hmat_build(const Problem &p, double eta, int kmax, HmatPlan &H) {
         H.dense_off[d + 1] = H.dense_off[d] + 9 * (H.dense[4 * d + 1] - H.dense[4 * d]) *
                                                    (H.dense[4 * d + 3] - H.dense[4 * d + 2]);
     H.lr_rows = 0;
-    for (int64_t l = 0; l < nl; ++l)
-        H.lr_rows += 3 * ((H.lowrank[4 * l + 1] - H.lowrank[4 * l]) + (H.lowrank[4 * l + 3] - H.lowrank[4 * l + 2]));
+    H.lr_order.clear();
+    for (int64_t l = 0; l < nl; ++l) {
+        const int64_t na = H.lowrank[4 * l + 1] - H.lowrank[4 * l], nb = H.lowrank[4 * l + 3] - H.lowrank[4 * l + 2];
+        H.lr_rows += 3 * (na + nb);
+        if (na <= 64 && nb <= 64)
+            H.lr_order.push_back((int32_t)l);
+    }
+    H.n_small = (int64_t)H.lr_order.size();
+    for (int64_t l = 0; l < nl; ++l) {
+        const int64_t na = H.lowrank[4 * l + 1] - H.lowrank[4 * l], nb = H.lowrank[4 * l + 3] - H.lowrank[4 * l + 2];
+        if (!(na <= 64 && nb <= 64))
+            H.lr_order.push_back((int32_t)l);
+    }
 
     // ---- per leaf row range: the dense blocks of its block row and every
     // low-rank block whose row range holds it (fixed order: dense, then low-rank)
@@ -199,6 +210,7 @@ void hmat_build(const Problem &p, double eta, int kmax, HmatPlan &H) {
     H.d_leaves = up(H, H.leaves);
     H.d_leaf_ptr = up(H, H.leaf_ptr);
     H.d_leaf_item = up(H, H.leaf_item);
+    H.d_lr_order = up(H, H.lr_order);
 }
 
 }  // namespace afsbem

@@ -108,13 +108,14 @@ struct RedMax {
     int64_t i;
 };
 
-// work-group (256) reductions through LDS
+// work-group (NT threads) reductions through LDS
+template <int NT>
 __device__ __forceinline__ RedMax group_argmax(double v, int64_t i, double *sv, int64_t *si) {
     const int t = threadIdx.x;
     sv[t] = v;
     si[t] = i;
     __syncthreads();
-    for (int h = 128; h > 0; h >>= 1) {
+    for (int h = NT / 2; h > 0; h >>= 1) {
         if (t < h) {
             const double o = sv[t + h];
             const int64_t oi = si[t + h];
@@ -130,11 +131,12 @@ __device__ __forceinline__ RedMax group_argmax(double v, int64_t i, double *sv, 
     return r;
 }
 
-__device__ __forceinline__ double group_sum256(double v, double *sv) {
+template <int NT>
+__device__ __forceinline__ double group_sum(double v, double *sv) {
     const int t = threadIdx.x;
     sv[t] = v;
     __syncthreads();
-    for (int h = 128; h > 0; h >>= 1) {
+    for (int h = NT / 2; h > 0; h >>= 1) {
         if (t < h)
             sv[t] += sv[t + h];
         __syncthreads();
@@ -144,20 +146,23 @@ __device__ __forceinline__ double group_sum256(double v, double *sv) {
     return r;
 }
 
-// status: 0 converged, 1 out of terms, 2 pool exhausted
-__global__ __launch_bounds__(256) void hm_aca_kernel(
+// status: 0 converged, 1 out of terms, 2 pool exhausted.  NT threads per
+// block: 64 for blocks of at most 64 elements a side (most are leaf pairs of
+// 32), 256 for the larger ones; ids lists the blocks of this launch.
+template <int NT>
+__global__ __launch_bounds__(NT) void hm_aca_kernel(
     KernelParams kp, const double *__restrict__ colx, const double *__restrict__ coly, const double *__restrict__ colz,
     const double *__restrict__ src, const double *__restrict__ coef, const int32_t *__restrict__ perm,
-    const int64_t *__restrict__ lowrank, int kmax, double eps, float2 *__restrict__ pool, unsigned long long pool_cap,
-    unsigned long long *__restrict__ ctr, int64_t *__restrict__ offs, int *__restrict__ rank_out,
-    int *__restrict__ status_out) {
-    __shared__ double sv[256];
-    __shared__ int64_t si[256];
+    const int64_t *__restrict__ lowrank, const int32_t *__restrict__ ids, int kmax, double eps,
+    float2 *__restrict__ pool, unsigned long long pool_cap, unsigned long long *__restrict__ ctr,
+    int64_t *__restrict__ offs, int *__restrict__ rank_out, int *__restrict__ status_out) {
+    __shared__ double sv[NT];
+    __shared__ int64_t si[NT];
     __shared__ double2 cf[kHmKmax];
     __shared__ int64_t used[kHmKmax + 1];
     __shared__ int64_t off_k;
     const int t = threadIdx.x;
-    const int64_t l = blockIdx.x;
+    const int64_t l = ids[blockIdx.x];
     const int64_t a0 = lowrank[4 * l], b0 = lowrank[4 * l + 2];
     const int64_t na = lowrank[4 * l + 1] - a0, nb = lowrank[4 * l + 3] - b0;
     const int64_t R = 3 * na, C = 3 * nb;
@@ -191,9 +196,9 @@ __global__ __launch_bounds__(256) void hm_aca_kernel(
             if (off_k >= 0)
                 myoffs[k] = off_k;
         }
-        if (t < k) {
-            const float2 u = pool[myoffs[t] + istar];
-            cf[t] = make_double2(u.x, u.y);
+        for (int q = t; q < k; q += NT) {
+            const float2 u = pool[myoffs[q] + istar];
+            cf[q] = make_double2(u.x, u.y);
         }
         __syncthreads();
         if (!probing && off_k < 0) {
@@ -206,7 +211,7 @@ __global__ __launch_bounds__(256) void hm_aca_kernel(
         const int al = (int)(istar % 3);
         double best = -1.0, rn = 0.0;
         int64_t bi = 0;
-        for (int64_t kk = t; kk < nb; kk += 256) {
+        for (int64_t kk = t; kk < nb; kk += NT) {
             cd blk[9];
             hm_pair_block(kp, colx, coly, colz, src, coef, m, perm[b0 + kk], blk);
 #pragma unroll
@@ -229,8 +234,8 @@ __global__ __launch_bounds__(256) void hm_aca_kernel(
                 }
             }
         }
-        const RedMax pv = group_argmax(best, bi, sv, si);
-        const double rn2 = group_sum256(rn, sv);
+        const RedMax pv = group_argmax<NT>(best, bi, sv, si);
+        const double rn2 = group_sum<NT>(rn, sv);
         if (probing) {
             // after the stopping test: probe rows whose residuals are small
             // against the mean row norm of S confirm it (all kProbes in a row);
@@ -257,16 +262,16 @@ __global__ __launch_bounds__(256) void hm_aca_kernel(
         const double pd = (double)pf.x * pf.x + (double)pf.y * pf.y;
         const double ir = pf.x / pd, ii = -pf.y / pd;  // 1 / pivot
         double nv = 0.0;
-        for (int64_t c = t; c < C; c += 256) {
+        for (int64_t c = t; c < C; c += NT) {
             const float2 v = Vk[c];
             const double wr = v.x * ir - v.y * ii, wi = v.x * ii + v.y * ir;
             Vk[c] = make_float2((float)wr, (float)wi);
             nv += wr * wr + wi * wi;
         }
         // ---- residual column jstar -> U_k
-        if (t < k) {
-            const float2 v = pool[myoffs[t] + R + jstar];
-            cf[t] = make_double2(v.x, v.y);
+        for (int q = t; q < k; q += NT) {
+            const float2 v = pool[myoffs[q] + R + jstar];
+            cf[q] = make_double2(v.x, v.y);
         }
         if (t == 0)
             used[k] = istar;
@@ -276,7 +281,7 @@ __global__ __launch_bounds__(256) void hm_aca_kernel(
         double nu = 0.0;
         best = -1.0;
         bi = 0;
-        for (int64_t i = t; i < na; i += 256) {
+        for (int64_t i = t; i < na; i += NT) {
             cd blk[9];
             hm_pair_block(kp, colx, coly, colz, src, coef, perm[a0 + i], n, blk);
 #pragma unroll
@@ -301,9 +306,9 @@ __global__ __launch_bounds__(256) void hm_aca_kernel(
                 }
             }
         }
-        const double nu2 = group_sum256(nu, sv);
-        const double nv2 = group_sum256(nv, sv);
-        const RedMax nx = group_argmax(best, bi, sv, si);
+        const double nu2 = group_sum<NT>(nu, sv);
+        const double nv2 = group_sum<NT>(nv, sv);
+        const RedMax nx = group_argmax<NT>(best, bi, sv, si);
         ++k;
         S2 += nu2 * nv2;
         // the terms span the block (k = min(R, C): U V^T is then the block itself)
@@ -369,6 +374,7 @@ __global__ __launch_bounds__(128) void hm_apply_kernel(
             const int64_t b0 = dense[4 * item + 2];
             const int64_t C = 3 * (dense[4 * item + 3] - b0);
             const float2 *D = dblk + dense_off[item];
+#pragma unroll 8
             for (int64_t c = 0; c < C; ++c) {
                 const double2 xv = x[3 * (int64_t)perm[b0 + c / 3] + c % 3];
                 if (live) {
@@ -406,11 +412,17 @@ void hmat_setup(const Problem &p, Workspace &ws, const KernelParams &kp, double 
                                                        d.near_col, ws.nearblk, ws.selfblk, H.d_perm, H.d_dense,
                                                        H.d_dense_off, ws.hm_dense);
     AFS_HIP(hipMemsetAsync(ws.hm_ctr, 0, sizeof(unsigned long long), st));
-    if (nl)
-        hm_aca_kernel<<<(unsigned)nl, 256, 0, st>>>(kp, d.colx, d.coly, d.colz, d.src, d.coef, H.d_perm,
-                                                     H.d_lowrank, H.kmax, eps, ws.hm_pool,
-                                                     (unsigned long long)ws.hm_pool_cap, ws.hm_ctr, ws.hm_offs,
-                                                     ws.hm_rank, ws.hm_status);
+    const int64_t n_small = H.n_small, n_large = nl - H.n_small;
+    if (n_small)
+        hm_aca_kernel<64><<<(unsigned)n_small, 64, 0, st>>>(kp, d.colx, d.coly, d.colz, d.src, d.coef, H.d_perm,
+                                                             H.d_lowrank, H.d_lr_order, H.kmax, eps, ws.hm_pool,
+                                                             (unsigned long long)ws.hm_pool_cap, ws.hm_ctr, ws.hm_offs,
+                                                             ws.hm_rank, ws.hm_status);
+    if (n_large)
+        hm_aca_kernel<256><<<(unsigned)n_large, 256, 0, st>>>(kp, d.colx, d.coly, d.colz, d.src, d.coef, H.d_perm,
+                                                               H.d_lowrank, H.d_lr_order + n_small, H.kmax, eps,
+                                                               ws.hm_pool, (unsigned long long)ws.hm_pool_cap,
+                                                               ws.hm_ctr, ws.hm_offs, ws.hm_rank, ws.hm_status);
     AFS_HIP(hipGetLastError());
     if (nl) {
         AFS_HIP(hipMemcpyAsync(ws.hm_host, ws.hm_rank, nl * sizeof(int), hipMemcpyDeviceToHost, st));
