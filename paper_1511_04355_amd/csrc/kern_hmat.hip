@@ -330,11 +330,19 @@ __global__ __launch_bounds__(NT) void hm_aca_kernel(
     }
 }
 
+// x in tree order: xp[3 q + c] = x[3 perm[q] + c]
+__global__ __launch_bounds__(256) void hm_gather_kernel(int64_t n, const int32_t *__restrict__ perm,
+                                                        const double2 *__restrict__ x, double2 *__restrict__ xp) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < 3 * n)
+        xp[i] = x[3 * (int64_t)perm[i / 3] + i % 3];
+}
+
 // t[l][q] = V_q^T x on the block's columns, one wavefront per term
 __global__ __launch_bounds__(256) void hm_vt_kernel(const int64_t *__restrict__ lowrank, int kmax,
                                                     const int *__restrict__ rank, const int64_t *__restrict__ offs,
-                                                    const int32_t *__restrict__ perm, const float2 *__restrict__ pool,
-                                                    const double2 *__restrict__ x, double2 *__restrict__ tv) {
+                                                    const float2 *__restrict__ pool, const double2 *__restrict__ xp,
+                                                    double2 *__restrict__ tv) {
     const int64_t l = blockIdx.x;
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t a0 = lowrank[4 * l], b0 = lowrank[4 * l + 2];
@@ -343,9 +351,10 @@ __global__ __launch_bounds__(256) void hm_vt_kernel(const int64_t *__restrict__ 
     for (int q = w; q < rk; q += 4) {
         const float2 *V = pool + offs[l * kmax + q] + R;
         double sr = 0.0, si = 0.0;
+        const double2 *xb = xp + 3 * b0;
         for (int64_t c = lane; c < C; c += 64) {
             const float2 v = V[c];
-            const double2 xv = x[3 * (int64_t)perm[b0 + c / 3] + c % 3];
+            const double2 xv = xb[c];
             sr += v.x * xv.x - v.y * xv.y;
             si += v.x * xv.y + v.y * xv.x;
         }
@@ -362,7 +371,9 @@ __global__ __launch_bounds__(128) void hm_apply_kernel(
     const int64_t *__restrict__ dense, const int64_t *__restrict__ dense_off, const int64_t *__restrict__ lowrank,
     int kmax, const int *__restrict__ rank, const int64_t *__restrict__ offs, const int32_t *__restrict__ perm,
     const float2 *__restrict__ dblk, const float2 *__restrict__ pool, const double2 *__restrict__ tv,
-    const double2 *__restrict__ x, double2 *__restrict__ y) {
+    const double2 *__restrict__ xp, double2 *__restrict__ y) {
+    __shared__ int64_t so[kHmKmax];
+    __shared__ double2 stq[kHmKmax];
     const int64_t L = blockIdx.x;
     const int64_t L0 = leaves[2 * L], rows = 3 * (leaves[2 * L + 1] - L0);
     const int r = threadIdx.x;
@@ -374,9 +385,10 @@ __global__ __launch_bounds__(128) void hm_apply_kernel(
             const int64_t b0 = dense[4 * item + 2];
             const int64_t C = 3 * (dense[4 * item + 3] - b0);
             const float2 *D = dblk + dense_off[item];
+            const double2 *xb = xp + 3 * b0;
 #pragma unroll 8
             for (int64_t c = 0; c < C; ++c) {
-                const double2 xv = x[3 * (int64_t)perm[b0 + c / 3] + c % 3];
+                const double2 xv = xb[c];
                 if (live) {
                     const float2 a = D[c * rows + r];
                     ar += (double)a.x * xv.x - (double)a.y * xv.y;
@@ -384,13 +396,20 @@ __global__ __launch_bounds__(128) void hm_apply_kernel(
                 }
             }
         } else {
+            // the block's term offsets and t values staged once (every thread takes this branch)
             const int64_t lb = -(int64_t)item - 1;
             const int64_t rr = 3 * (L0 - lowrank[4 * lb]) + r;
             const int rk = rank[lb];
+            __syncthreads();
+            for (int q = r; q < rk; q += 128) {
+                so[q] = offs[lb * kmax + q];
+                stq[q] = tv[lb * kmax + q];
+            }
+            __syncthreads();
             if (live)
                 for (int q = 0; q < rk; ++q) {
-                    const float2 u = pool[offs[lb * kmax + q] + rr];
-                    const double2 tq = tv[lb * kmax + q];
+                    const float2 u = pool[so[q] + rr];
+                    const double2 tq = stq[q];
                     ar += u.x * tq.x - u.y * tq.y;
                     ai += u.x * tq.y + u.y * tq.x;
                 }
@@ -447,12 +466,13 @@ void hmat_apply(const Problem &p, const Workspace &ws, const double *x, double *
     const HmatPlan &H = *p.hmat;
     const int64_t nl = (int64_t)H.lowrank.size() / 4, nleaf = (int64_t)H.leaves.size() / 2;
     const double2 *xv = reinterpret_cast<const double2 *>(x);
+    hm_gather_kernel<<<(unsigned)((3 * H.n + 255) / 256), 256, 0, st>>>(H.n, H.d_perm, xv, ws.hm_xp);
     if (nl)
-        hm_vt_kernel<<<(unsigned)nl, 256, 0, st>>>(H.d_lowrank, H.kmax, ws.hm_rank, ws.hm_offs, H.d_perm, ws.hm_pool,
-                                                    xv, ws.hm_t);
+        hm_vt_kernel<<<(unsigned)nl, 256, 0, st>>>(H.d_lowrank, H.kmax, ws.hm_rank, ws.hm_offs, ws.hm_pool, ws.hm_xp,
+                                                    ws.hm_t);
     hm_apply_kernel<<<(unsigned)nleaf, 128, 0, st>>>(H.d_leaves, H.d_leaf_ptr, H.d_leaf_item, H.d_dense,
                                                       H.d_dense_off, H.d_lowrank, H.kmax, ws.hm_rank, ws.hm_offs,
-                                                      H.d_perm, ws.hm_dense, ws.hm_pool, ws.hm_t, xv,
+                                                      H.d_perm, ws.hm_dense, ws.hm_pool, ws.hm_t, ws.hm_xp,
                                                       reinterpret_cast<double2 *>(y));
     AFS_HIP(hipGetLastError());
 }

@@ -44,6 +44,7 @@ struct Workspace {
     unsigned long long *hm_ctr = nullptr;  // pool entries taken
     int64_t *hm_offs = nullptr;            // [nl][kmax] pool offset of each term
     double2 *hm_t = nullptr;
+    double2 *hm_xp = nullptr;              // x in tree order (product scratch)
     int *hm_rank = nullptr, *hm_status = nullptr;
     int *hm_host = nullptr;                // pinned: ranks, then status flags
     size_t hm_cap[3] = {0, 0, 0};
