@@ -85,7 +85,10 @@ def parse():
                          "against the closed form beside the flat cavity one level finer), porous_hmat (300,516 "
                          "unknowns: hierarchical vs on-the-fly inner operator of the matrix-free solve)")
     ap.add_argument("--afs-q", type=int, default=4, help="cavity_L4_afs: new frequencies per AFS step")
-    ap.add_argument("--hmat-eps", type=float, default=1e-5, help="porous_hmat: accuracy of the low-rank blocks")
+    ap.add_argument("--hmat-eps", type=float, default=1e-5,
+                    help="porous_hmat, porous_afs_matrix_free: accuracy of the low-rank blocks")
+    ap.add_argument("--matrix-free", type=int, default=1, choices=[1, 2],
+                    help="porous_afs_matrix_free: inner operator, 1 on the fly, 2 hierarchical")
     ap.add_argument("--precond", type=int, default=0,
                     help="blocks_batched, porous_afs_matrix_free: 0 point, 1 cluster block-Jacobi")
     ap.add_argument("--afs-ns", type=int, default=64, help="porous_afs_matrix_free: FSM size Ns of the band")
@@ -446,8 +449,8 @@ def run_porous_afs_matrix_free(args, afs, mg, np, torch):
     loaded = np.nonzero(np.abs(np.asarray(mesh.bc_shape)).sum(1) > 0)[0]
     dofs = np.sort(3 * rng.choice(loaded, 6, replace=False) + 2)
     shape = np.asarray(mesh.bc_shape, np.complex128)
-    base = dict(tol=args.tol, precision=afs.PREC_MIXED, matrix_free=1, restart=100, max_iter=4000, batch=1,
-                precond=args.precond)
+    base = dict(tol=args.tol, precision=afs.PREC_MIXED, matrix_free=args.matrix_free, restart=100, max_iter=4000,
+                batch=1, precond=args.precond, hmat_eps=args.hmat_eps)
     solved, log = {}, []
 
     def response(sv):
@@ -494,7 +497,8 @@ def run_porous_afs_matrix_free(args, afs, mg, np, torch):
     fit_err = float(np.max(np.abs(fit.T - r["F"])) / np.max(np.abs(r["F"])))
     return {"workload": f"porous_afs_matrix_free: 64-void block ({mesh.n_tri} elements, {3 * mesh.n_tri} unknowns), "
                         f"AFS from J0=8, T={T}, eta={eta:.4f}, Ns={Ns} (Omega={np.pi * Ns / T:.3f}), mixed "
-                        f"matrix-free GMRES(100), {'cluster' if args.precond else 'point'} block-Jacobi, "
+                        f"matrix-free GMRES(100) ({'hierarchical' if args.matrix_free == 2 else 'on-the-fly'} inner "
+                        f"operator), {'cluster' if args.precond else 'point'} block-Jacobi, "
                         f"FP64 true rel. residual <= {args.tol}",
             "plan_s": plan_s, "afs_seconds": afs_s, "n_solves": r["Nc"], "fsm_solves_avoided": Ns // 2 + 1 - r["Nc"],
             "converged": bool(r["converged"]), "model_order": len(r["poles"]),
