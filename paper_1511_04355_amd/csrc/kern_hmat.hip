@@ -2,7 +2,8 @@
 // and low-rank factors per frequency, and the product y = A_H x.
 //
 // Low-rank blocks: adaptive cross approximation with partial pivoting on the
-// far rule's entries (FP64 arithmetic, terms stored in FP32 in a pool whose
+// far rule's entries (evaluated in FP32, residual arithmetic in FP64, terms
+// stored in FP32 in a pool whose
 // slots a work-group takes with one atomic add per term): at step k the residual row i_k (the block's row
 // minus sum_l U_l[i_k] V_l) is evaluated, its largest entry j_k becomes the
 // pivot, V_k = row / row[j_k], U_k = the residual column j_k, and the next row
@@ -21,6 +22,7 @@
 // order (no atomics).
 #include "hmat.hpp"
 #include "kern_eval.hpp"
+#include "kern_mfeval.hpp"
 #include "solver.hpp"
 
 namespace afsbem {
@@ -61,6 +63,63 @@ __device__ void hm_pair_block(const KernelParams &kp, const double *__restrict__
             acc_node<1>(E, kp, nx, ny, nz, w, 0.0, v0, acc, bdummy);
     }
     expand_block(kind, acc, nx, ny, nz, blk);
+}
+
+// FP32 evaluation of the cross approximation's entries (the operator it
+// approximates serves FP32 products): s / c_s, beta, lambda/mu, 1/(4 pi mu),
+// 1/|s/c_s|^2
+struct Hm32 {
+    float sr, si, beta, lam, cu, iks2;
+};
+
+// three entries of the far-rule block (m, n): row a (row = true) or column a;
+// T for a kind-0 source, -U for kind 1
+__device__ void hm_entries32(const Hm32 &h, const float *__restrict__ col32, const float *__restrict__ src32,
+                             const float *__restrict__ coef32, int64_t m, int64_t n, bool row, int a, cd out[3]) {
+    const float *rec = src32 + kSrcStride * n;
+    const float nx = rec[28], ny = rec[29], nz = rec[30];
+    const int kind = (int)rec[31];
+    const float px = col32[4 * m], py = col32[4 * m + 1], pz = col32[4 * m + 2];
+    const float nn[3] = {nx, ny, nz};
+    cx<float> acc[3] = {{0.f, 0.f}, {0.f, 0.f}, {0.f, 0.f}};
+#pragma unroll 1
+    for (int q = 0; q < kFarNodes; ++q) {
+        const float dx = rec[4 * q] - px, dy = rec[4 * q + 1] - py, dz = rec[4 * q + 2] - pz;
+        const float r2 = dx * dx + dy * dy + dz * dz;
+        const float ir = inv_sqrt(r2);
+        const float r = r2 * ir;
+        const float rh[3] = {dx * ir, dy * ir, dz * ir};
+        const MfRad<float> Rd = mf_radial<float>(cx<float>{h.sr * r, h.si * r}, h.beta, coef32, ir * ir * h.iks2);
+        if (kind == 0) {
+            const float f = rec[4 * q + 3] * 0.079577471545947667884f * ir * ir;
+            const float rn = rh[0] * nx + rh[1] * ny + rh[2] * nz;
+            const cx<float> t1 = cxsub(Rd.Psd, Rd.X);
+            const cx<float> t0 = cxs(t1, rn);
+            const cx<float> t2 = cxadd(cxs(Rd.X, -2.f), cxs(cxsub(cxsub(Rd.Psd, Rd.Xd), cxs(Rd.X, 2.f)), h.lam));
+            const cx<float> t3 = cxs(cxsub(cxs(Rd.X, 4.f), cxs(Rd.Xd, 2.f)), rn);
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+                const int i = row ? a : b, j = row ? b : a;
+                cx<float> v = cxadd(cxadd(cxs(t1, nn[i] * rh[j]), cxs(t2, rh[i] * nn[j])), cxs(t3, rh[i] * rh[j]));
+                if (i == j)
+                    v = cxadd(v, t0);
+                acc[b] = cxadd(acc[b], cxs(v, f));
+            }
+        } else {
+            const float g = -rec[4 * q + 3] * h.cu * ir;
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+                const int i = row ? a : b, j = row ? b : a;
+                cx<float> v = cxs(Rd.X, -rh[i] * rh[j]);
+                if (i == j)
+                    v = cxadd(v, Rd.Psi);
+                acc[b] = cxadd(acc[b], cxs(v, g));
+            }
+        }
+    }
+#pragma unroll
+    for (int b = 0; b < 3; ++b)
+        out[b] = cd{(double)acc[b].r, (double)acc[b].i};
 }
 
 // dense block d: (3 na) x (3 nb), column-major, FP32 complex
@@ -155,7 +214,11 @@ __global__ __launch_bounds__(NT) void hm_aca_kernel(
     const double *__restrict__ src, const double *__restrict__ coef, const int32_t *__restrict__ perm,
     const int64_t *__restrict__ lowrank, const int32_t *__restrict__ ids, int kmax, double eps,
     float2 *__restrict__ pool, unsigned long long pool_cap, unsigned long long *__restrict__ ctr,
-    int64_t *__restrict__ offs, int *__restrict__ rank_out, int *__restrict__ status_out) {
+    int64_t *__restrict__ offs, int *__restrict__ rank_out, int *__restrict__ status_out, Hm32 h32,
+    const float *__restrict__ col32, const float *__restrict__ src32, const float *__restrict__ coef32_g) {
+    __shared__ float coef32[64];
+    if (threadIdx.x < 64)
+        coef32[threadIdx.x] = coef32_g[threadIdx.x];
     __shared__ double sv[NT];
     __shared__ int64_t si[NT];
     __shared__ double2 cf[kHmKmax];
@@ -212,12 +275,12 @@ __global__ __launch_bounds__(NT) void hm_aca_kernel(
         double best = -1.0, rn = 0.0;
         int64_t bi = 0;
         for (int64_t kk = t; kk < nb; kk += NT) {
-            cd blk[9];
-            hm_pair_block(kp, colx, coly, colz, src, coef, m, perm[b0 + kk], blk);
+            cd ent[3];
+            hm_entries32(h32, col32, src32, coef32, m, perm[b0 + kk], true, al, ent);
 #pragma unroll
             for (int be = 0; be < 3; ++be) {
                 const int64_t c = 3 * kk + be;
-                double vr = blk[3 * al + be].r, vi = blk[3 * al + be].i;
+                double vr = ent[be].r, vi = ent[be].i;
                 for (int q = 0; q < k; ++q) {
                     const double2 u = cf[q];
                     const float2 v = pool[myoffs[q] + R + c];
@@ -282,12 +345,12 @@ __global__ __launch_bounds__(NT) void hm_aca_kernel(
         best = -1.0;
         bi = 0;
         for (int64_t i = t; i < na; i += NT) {
-            cd blk[9];
-            hm_pair_block(kp, colx, coly, colz, src, coef, perm[a0 + i], n, blk);
+            cd ent[3];
+            hm_entries32(h32, col32, src32, coef32, perm[a0 + i], n, false, be, ent);
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
                 const int64_t r = 3 * i + a;
-                double ur = blk[3 * a + be].r, ui = blk[3 * a + be].i;
+                double ur = ent[a].r, ui = ent[a].i;
                 for (int q = 0; q < k; ++q) {
                     const double2 v = cf[q];
                     const float2 u = pool[myoffs[q] + r];
@@ -432,16 +495,23 @@ void hmat_setup(const Problem &p, Workspace &ws, const KernelParams &kp, double 
                                                        H.d_dense_off, ws.hm_dense);
     AFS_HIP(hipMemsetAsync(ws.hm_ctr, 0, sizeof(unsigned long long), st));
     const int64_t n_small = H.n_small, n_large = nl - H.n_small;
+    Hm32 h32;
+    {
+        const double sr = kp.s_re * kp.inv_cs, si = kp.s_im * kp.inv_cs, ks2 = sr * sr + si * si;
+        h32 = Hm32{(float)sr, (float)si, (float)kp.beta, (float)kp.lam_over_mu, (float)kp.c_u,
+                   (float)(ks2 > 0.0 ? 1.0 / ks2 : 0.0)};
+    }
     if (n_small)
         hm_aca_kernel<64><<<(unsigned)n_small, 64, 0, st>>>(kp, d.colx, d.coly, d.colz, d.src, d.coef, H.d_perm,
                                                              H.d_lowrank, H.d_lr_order, H.kmax, eps, ws.hm_pool,
                                                              (unsigned long long)ws.hm_pool_cap, ws.hm_ctr, ws.hm_offs,
-                                                             ws.hm_rank, ws.hm_status);
+                                                             ws.hm_rank, ws.hm_status, h32, d.col32, d.src32, d.coef32);
     if (n_large)
         hm_aca_kernel<256><<<(unsigned)n_large, 256, 0, st>>>(kp, d.colx, d.coly, d.colz, d.src, d.coef, H.d_perm,
                                                                H.d_lowrank, H.d_lr_order + n_small, H.kmax, eps,
                                                                ws.hm_pool, (unsigned long long)ws.hm_pool_cap,
-                                                               ws.hm_ctr, ws.hm_offs, ws.hm_rank, ws.hm_status);
+                                                               ws.hm_ctr, ws.hm_offs, ws.hm_rank, ws.hm_status, h32, d.col32,
+                                                               d.src32, d.coef32);
     AFS_HIP(hipGetLastError());
     if (nl) {
         AFS_HIP(hipMemcpyAsync(ws.hm_host, ws.hm_rank, nl * sizeof(int), hipMemcpyDeviceToHost, st));

@@ -18,104 +18,9 @@
 
 #include "fastmath64.hpp"
 #include "internal.hpp"
+#include "kern_mfeval.hpp"
 
 namespace afsbem {
-
-template <class R>
-struct cx {
-    R r, i;
-};
-template <class R>
-__device__ __forceinline__ cx<R> cxadd(cx<R> a, cx<R> b) {
-    return {a.r + b.r, a.i + b.i};
-}
-template <class R>
-__device__ __forceinline__ cx<R> cxsub(cx<R> a, cx<R> b) {
-    return {a.r - b.r, a.i - b.i};
-}
-template <class R>
-__device__ __forceinline__ cx<R> cxmul(cx<R> a, cx<R> b) {
-    return {a.r * b.r - a.i * b.i, a.r * b.i + a.i * b.r};
-}
-template <class R>
-__device__ __forceinline__ cx<R> cxs(cx<R> a, R s) {
-    return {a.r * s, a.i * s};
-}
-
-__device__ __forceinline__ void exp_sincos(float a, float b, float &e, float &sn, float &cs) {
-    e = __expf(a);
-    __sincosf(b, &sn, &cs);
-}
-__device__ __forceinline__ void exp_sincos(double a, double b, double &e, double &sn, double &cs) {
-    e = exp_cw(a);
-    sincos_cw(b, &sn, &cs);
-}
-__device__ __forceinline__ float inv_sqrt(float a) { return rsqrtf(a); }
-__device__ __forceinline__ double inv_sqrt(double a) { return rsqrt_nr(a); }
-
-// Series about 0 below |x|^2 < thr2, closed form above.  FP32: |x| < 1/2 with
-// 9 terms (truncation ~1e-9; the closed form loses eps32/|x|^2 <= 5e-7 above);
-// FP64: |x| < 1/4 with 16 terms.
-template <class R>
-struct MfTraits;
-template <>
-struct MfTraits<float> {
-    static constexpr float thr2 = 0.25f;
-    static constexpr int nser = 9;
-    static constexpr int unroll = 8;  // the whole Horner loop
-};
-template <>
-struct MfTraits<double> {
-    static constexpr double thr2 = 0.0625;
-    static constexpr int nser = 16;
-    static constexpr int unroll = 4;  // a full unroll keeps all 60 coefficients live (240 VGPRs)
-};
-
-template <class R>
-struct MfRad {
-    cx<R> Psi, X, Psd, Xd;
-};
-
-// inv_ax2 = 1 / |x|^2, supplied by the caller from 1/r (no division)
-template <class R>
-__device__ __forceinline__ MfRad<R> mf_radial(cx<R> x, R beta, const R *__restrict__ coef, R inv_ax2) {
-    MfRad<R> o;
-    const R ax2 = x.r * x.r + x.i * x.i;
-    if (ax2 < MfTraits<R>::thr2) {
-        constexpr int top = MfTraits<R>::nser - 1;
-        cx<R> p0{coef[4 * top], 0}, p1{coef[4 * top + 1], 0}, p2{coef[4 * top + 2], 0}, p3{coef[4 * top + 3], 0};
-#pragma unroll MfTraits<R>::unroll
-        for (int n = top - 1; n >= 0; --n) {
-            p0 = cx<R>{p0.r * x.r - p0.i * x.i + coef[4 * n], p0.r * x.i + p0.i * x.r};
-            p1 = cx<R>{p1.r * x.r - p1.i * x.i + coef[4 * n + 1], p1.r * x.i + p1.i * x.r};
-            p2 = cx<R>{p2.r * x.r - p2.i * x.i + coef[4 * n + 2], p2.r * x.i + p2.i * x.r};
-            p3 = cx<R>{p3.r * x.r - p3.i * x.i + coef[4 * n + 3], p3.r * x.i + p3.i * x.r};
-        }
-        o.Psi = p0;
-        o.X = p1;
-        o.Psd = p2;
-        o.Xd = p3;
-        return o;
-    }
-    R ex, sn, cs, exq, snq, csq;
-    exp_sincos(-x.r, x.i, ex, sn, cs);
-    exp_sincos(-beta * x.r, beta * x.i, exq, snq, csq);
-    const cx<R> e{ex * cs, -ex * sn};      // e^{-x}
-    const cx<R> ep{exq * csq, -exq * snq};  // e^{-beta x}
-    const R inv = inv_ax2;
-    const cx<R> ix{x.r * inv, -x.i * inv};
-    const cx<R> ix2 = cxmul(ix, ix);
-    const R b2 = beta * beta, b3 = b2 * beta;
-    const cx<R> P = cxmul(ep, cx<R>{b2 + R(3) * beta * ix.r + R(3) * ix2.r, R(3) * beta * ix.i + R(3) * ix2.i});
-    o.Psi = cxsub(cxmul(e, cx<R>{R(1) + ix.r + ix2.r, ix.i + ix2.i}),
-                  cxmul(ep, cx<R>{beta * ix.r + ix2.r, beta * ix.i + ix2.i}));
-    o.X = cxsub(cxmul(e, cx<R>{R(1) + R(3) * ix.r + R(3) * ix2.r, R(3) * ix.i + R(3) * ix2.i}), P);
-    o.Psd = cxsub(P, cxmul(e, cx<R>{x.r + R(2) + R(3) * ix.r + R(3) * ix2.r, x.i + R(3) * ix.i + R(3) * ix2.i}));
-    o.Xd = cxsub(cxmul(ep, cx<R>{b3 * x.r + R(4) * b2 + R(9) * beta * ix.r + R(9) * ix2.r,
-                                 b3 * x.i + R(9) * beta * ix.i + R(9) * ix2.i}),
-                 cxmul(e, cx<R>{x.r + R(4) + R(9) * ix.r + R(9) * ix2.r, x.i + R(9) * ix.i + R(9) * ix2.i}));
-    return o;
-}
 
 struct MfArgs {
     double sr, si;  // s / c_s
