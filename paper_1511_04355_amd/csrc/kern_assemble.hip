@@ -585,9 +585,9 @@ void launch_finalize_b(const Problem &p, int S, const double *bpart, const void 
 // staged once, then each lane forms 3-4 of the 216 sums), so no lane carries
 // 216 accumulators.
 // ---------------------------------------------------------------------------
-// rule table in device memory: [0, 12) rule points (xi, eta); [12, 48) the
-// Lagrange basis, L_b = sum_k tab[12 + 6 b + k] m_k, m = 1, xi, eta, xi^2, xi eta, eta^2
-constexpr int kNysTab = 48;
+// rule table in device memory (48 doubles): [0, 12) rule points (xi, eta);
+// [12, 48) the Lagrange basis, L_b = sum_k tab[12 + 6 b + k] m_k,
+// m = 1, xi, eta, xi^2, xi eta, eta^2
 
 struct QGeo {
     double y[3], n[3], J, tx[3], te[3];

@@ -210,8 +210,7 @@ __device__ __forceinline__ double group_sum(double v, double *sv) {
 // 32), 256 for the larger ones; ids lists the blocks of this launch.
 template <int NT>
 __global__ __launch_bounds__(NT) void hm_aca_kernel(
-    KernelParams kp, const double *__restrict__ colx, const double *__restrict__ coly, const double *__restrict__ colz,
-    const double *__restrict__ src, const double *__restrict__ coef, const int32_t *__restrict__ perm,
+    const int32_t *__restrict__ perm,
     const int64_t *__restrict__ lowrank, const int32_t *__restrict__ ids, int kmax, double eps,
     float2 *__restrict__ pool, unsigned long long pool_cap, unsigned long long *__restrict__ ctr,
     int64_t *__restrict__ offs, int *__restrict__ rank_out, int *__restrict__ status_out, Hm32 h32,
@@ -502,12 +501,12 @@ void hmat_setup(const Problem &p, Workspace &ws, const KernelParams &kp, double 
                    (float)(ks2 > 0.0 ? 1.0 / ks2 : 0.0)};
     }
     if (n_small)
-        hm_aca_kernel<64><<<(unsigned)n_small, 64, 0, st>>>(kp, d.colx, d.coly, d.colz, d.src, d.coef, H.d_perm,
+        hm_aca_kernel<64><<<(unsigned)n_small, 64, 0, st>>>(H.d_perm,
                                                              H.d_lowrank, H.d_lr_order, H.kmax, eps, ws.hm_pool,
                                                              (unsigned long long)ws.hm_pool_cap, ws.hm_ctr, ws.hm_offs,
                                                              ws.hm_rank, ws.hm_status, h32, d.col32, d.src32, d.coef32);
     if (n_large)
-        hm_aca_kernel<256><<<(unsigned)n_large, 256, 0, st>>>(kp, d.colx, d.coly, d.colz, d.src, d.coef, H.d_perm,
+        hm_aca_kernel<256><<<(unsigned)n_large, 256, 0, st>>>(H.d_perm,
                                                                H.d_lowrank, H.d_lr_order + n_small, H.kmax, eps,
                                                                ws.hm_pool, (unsigned long long)ws.hm_pool_cap,
                                                                ws.hm_ctr, ws.hm_offs, ws.hm_rank, ws.hm_status, h32, d.col32,
