@@ -99,3 +99,19 @@ def test_hmat_product_full_size_27_voids():
         print(f"[hmat] 27 voids, eps {eps}: rel err {err:.2e}, {info}", flush=True)
         assert info["converged"]
         assert err < bar
+
+
+def test_hmat_without_low_rank_blocks_is_the_exact_operator():
+    """A mesh too small for any admissible block: every block is dense, the
+    product is the operator itself (to FP32 storage)."""
+    import paper_1511_04355_amd as afs
+    from oracle import bem
+    mesh = mg.cavity(1)
+    P = afs.Problem.from_mesh(mesh)
+    s = 0.25 + 0.9j
+    x = _x(P.N, 9)
+    y, info = P.hmat_matvec(s, torch.from_numpy(x).cuda(), eps=1e-6)
+    assert info["n_lowrank"] == 0 and info["converged"]
+    A, _ = bem.assemble(mesh, s)
+    yo = A @ x
+    assert np.linalg.norm(y.cpu().numpy() - yo) / np.linalg.norm(yo) < 1e-6

@@ -240,3 +240,38 @@ def test_afs_driver_on_a_nystrom_problem():
         sk = out["s"][k]
         x = ny.solve(m, sk, shape / sk)
         assert np.max(np.abs(out["F"][k] - x[dofs])) <= 1e-7 * np.max(np.abs(x[dofs]))
+
+
+@pytest.mark.parametrize("n_el", [1, 2])
+def test_assembly_tiny_meshes(n_el):
+    """One element (only the self rule: no near pair, no far pair) and two
+    (near pairs only), against the oracle on every entry."""
+    import paper_1511_04355_amd as afs
+    from oracle import nystrom as ny
+    full = mg.cavity_quadratic(0)
+    used = np.unique(full.tri6[:n_el])
+    remap = -np.ones(full.xyz.shape[0], np.int64)
+    remap[used] = np.arange(len(used))
+    m = mg.QuadMesh(full.xyz[used], remap[full.tri6[:n_el]].astype(np.int32), np.zeros(n_el, np.int8),
+                    np.ones(n_el))
+    s = 0.3 + 0.7j
+    bc = ny.pressure_bc(m, s)
+    P = afs.Problem.from_mesh(m)
+    info = P.info()
+    assert info["n_tri"] == 6 * n_el
+    if n_el == 1:
+        assert info["n_near_pairs"] == 0
+    A, _, b, _ = P.assemble(s, torch.from_numpy(bc).cuda(), fmt=afs.FMT_C128)
+    torch.cuda.synchronize()
+    Ao, bo = ny.assemble(m, s, bc)
+    assert np.max(np.abs(_dense(A, P.N) - Ao)) <= 1e-11 * np.max(np.abs(Ao))
+    assert np.max(np.abs(b.cpu().numpy() - bo)) <= 1e-11 * np.max(np.abs(bo))
+
+
+def test_degenerate_element_is_rejected():
+    import paper_1511_04355_amd as afs
+    xyz = np.array([[0, 0, 0], [1, 0, 0], [2, 0, 0], [0.5, 0, 0], [1.5, 0, 0], [1, 0, 0.0]])
+    m = mg.QuadMesh(xyz, np.array([[0, 1, 2, 3, 4, 5]], np.int32), np.zeros(1, np.int8), np.ones(1))
+    with pytest.raises(afs.AfsbemError) as ei:
+        afs.Problem.from_mesh(m)
+    assert "degenerate" in str(ei.value)
