@@ -635,8 +635,10 @@ __device__ __forceinline__ void lag6(const double *__restrict__ tab, double xi, 
 }
 
 constexpr int kNysOut = 216;    // 6 basis functions x (U, T) x 9 complex
-constexpr int kNysKStride = 37; // LDS row of one point's 36 weighted kernel values (+1 against bank conflicts)
+constexpr int kNysKStride = 19; // LDS row of one point's 18 weighted values of U or T (+1 against bank conflicts)
 
+// U and T are staged and contracted one after the other (half the LDS of
+// staging both: more work-groups resident per CU)
 struct NysLds {
     double K[64 * kNysKStride];
     double L[64 * 6];
@@ -644,9 +646,28 @@ struct NysLds {
     double bv[6 * 6];
 };
 
-// stage one point (or zeros) and add its contribution to the lane's sums
-__device__ __forceinline__ void nys_stage(NysLds &sh, int lane, bool live, const PairEval &E, const KernelParams &kp,
-                                          const double n[3], double w, const double L[6]) {
+// the lane's sums: acc[0..1] for U (outputs o = lane + 64 r < 108, b = o / 18,
+// c = o % 18), acc[2..3] for T; out[36 b + c] (U) and out[36 b + 18 + c] (T)
+__device__ __forceinline__ void nys_contract_half(const NysLds &sh, int lane, int n_live, double acc[2]) {
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+        const int o = lane + 64 * r;
+        if (o < 108) {
+            const int b = o / 18, c = o % 18;
+            double v = acc[r];
+#pragma unroll 4
+            for (int p = 0; p < n_live; ++p)
+                v += sh.L[p * 6 + b] * sh.K[p * kNysKStride + c];
+            acc[r] = v;
+        }
+    }
+}
+
+// stage one point (or zeros), contract U, then T; n_live: points staged in
+// this chunk (wave-uniform, <= 64).  Every lane of the work-group calls it.
+__device__ __forceinline__ void nys_stage_contract(NysLds &sh, int lane, bool live, const PairEval &E,
+                                                   const KernelParams &kp, const double n[3], double w,
+                                                   const double L[6], int n_live, double acc[4]) {
     cd U[9], T[9];
 #pragma unroll
     for (int e = 0; e < 9; ++e)
@@ -660,28 +681,33 @@ __device__ __forceinline__ void nys_stage(NysLds &sh, int lane, bool live, const
     for (int e = 0; e < 9; ++e) {
         k[2 * e] = U[e].r;
         k[2 * e + 1] = U[e].i;
-        k[18 + 2 * e] = T[e].r;
-        k[18 + 2 * e + 1] = T[e].i;
     }
 #pragma unroll
     for (int b = 0; b < 6; ++b)
         sh.L[lane * 6 + b] = live ? L[b] : 0.0;
+    __syncthreads();
+    nys_contract_half(sh, lane, n_live, acc);
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < 9; ++e) {
+        k[2 * e] = T[e].r;
+        k[2 * e + 1] = T[e].i;
+    }
+    __syncthreads();
+    nys_contract_half(sh, lane, n_live, acc + 2);
+    __syncthreads();
 }
 
-// n_live: points staged in this chunk (wave-uniform, <= 64)
-__device__ __forceinline__ void nys_contract(const NysLds &sh, int lane, int n_live, double acc[4]) {
+// the sums into sh.out in the (b, U 9 complex, T 9 complex) layout
+__device__ __forceinline__ void nys_store_sums(NysLds &sh, int lane, const double acc[4]) {
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const int o = lane + 64 * r;
-        if (o < kNysOut) {
-            const int b = o / 36, c = o % 36;
-            double v = acc[r];
-#pragma unroll 4
-            for (int p = 0; p < n_live; ++p)
-                v += sh.L[p * 6 + b] * sh.K[p * kNysKStride + c];
-            acc[r] = v;
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+            const int o = lane + 64 * r;
+            if (o < 108)
+                sh.out[36 * (o / 18) + 18 * h + o % 18] = acc[2 * h + r];
         }
-    }
 }
 
 // near pair p = (target point i, element e): the six corrected column blocks
@@ -724,15 +750,9 @@ __global__ __launch_bounds__(64) void nys_near_kernel(
             eval_pair(kp, coef, xx, xy, xz, g.y[0], g.y[1], g.y[2], g.n[0], g.n[1], g.n[2], E);
             w = rule.w[r] * area * g.J;
         }
-        nys_stage(sh, lane, live, E, kp, g.n, w, L);
-        __syncthreads();
-        nys_contract(sh, lane, (int)(items - c0 < 64 ? items - c0 : 64), acc);
-        __syncthreads();
+        nys_stage_contract(sh, lane, live, E, kp, g.n, w, L, (int)(items - c0 < 64 ? items - c0 : 64), acc);
     }
-#pragma unroll
-    for (int r = 0; r < 4; ++r)
-        if (lane + 64 * r < kNysOut)
-            sh.out[lane + 64 * r] = acc[r];
+    nys_store_sums(sh, lane, acc);
     __syncthreads();
     if (lane < 6) {
         const int64_t j = 6 * e + lane;
@@ -841,18 +861,12 @@ __global__ __launch_bounds__(64) void nys_self_kernel(
             for (int k = 0; k < 3; ++k)
                 sv[k] += f * cx[k];
         }
-        nys_stage(sh, lane, live, E, kp, g.n, w, L);
-        __syncthreads();
-        nys_contract(sh, lane, (int)(items - c0 < 64 ? items - c0 : 64), acc);
-        __syncthreads();
+        nys_stage_contract(sh, lane, live, E, kp, g.n, w, L, (int)(items - c0 < 64 ? items - c0 : 64), acc);
     }
 #pragma unroll
     for (int k = 0; k < 3; ++k)
         sv[k] = wave_sum(sv[k]);
-#pragma unroll
-    for (int r = 0; r < 4; ++r)
-        if (lane + 64 * r < kNysOut)
-            sh.out[lane + 64 * r] = acc[r];
+    nys_store_sums(sh, lane, acc);
     __syncthreads();
     if (lane == 0) {
         // H_b0 += (antisymmetric matrix of sv) + 1/2 I  (real parts)
