@@ -16,10 +16,11 @@
 // unsampled, e.g. where a cluster spans separate surfaces).  One work-group per block; a row
 // or column costs one element-pair block per source or target element.
 //
-// Product: t_l = V_l^T x per low-rank block (one wavefront per term), then one
-// work-group per leaf row range sums its dense blocks (column-major FP32, read
-// coalesced) and the rows of every low-rank block that covers it, in a fixed
-// order (no atomics).
+// Product: x gathered into tree order, t_l = V_l^T x per low-rank block (one
+// wavefront per term), then four work-groups per leaf row range each sum every
+// fourth entry of the leaf's list of dense blocks (column-major FP32, read
+// coalesced) and covering low-rank blocks, and the four partial sums are added
+// in a fixed order (no atomics).
 #include "hmat.hpp"
 #include "kern_eval.hpp"
 #include "kern_mfeval.hpp"
@@ -427,13 +428,17 @@ __global__ __launch_bounds__(256) void hm_vt_kernel(const int64_t *__restrict__ 
     }
 }
 
-// one work-group per leaf row range (at most 3 kClusterElems rows)
+constexpr int kHmSplit = 4;  // work-groups per leaf: each takes every kHmSplit-th block of its list
+
+// work-group (leaf L, part blockIdx.y): rows of leaf L (at most 3 kClusterElems)
+// over the blocks it - leaf_ptr[L] = blockIdx.y (mod kHmSplit) of the leaf's
+// list; partial sums in tree order, yp[part][3 n]
 __global__ __launch_bounds__(128) void hm_apply_kernel(
     const int64_t *__restrict__ leaves, const int64_t *__restrict__ leaf_ptr, const int32_t *__restrict__ leaf_item,
     const int64_t *__restrict__ dense, const int64_t *__restrict__ dense_off, const int64_t *__restrict__ lowrank,
     int kmax, const int *__restrict__ rank, const int64_t *__restrict__ offs, const int32_t *__restrict__ perm,
     const float2 *__restrict__ dblk, const float2 *__restrict__ pool, const double2 *__restrict__ tv,
-    const double2 *__restrict__ xp, double2 *__restrict__ y) {
+    const double2 *__restrict__ xp, int64_t n_el, double2 *__restrict__ yp) {
     __shared__ int64_t so[kHmKmax];
     __shared__ double2 stq[kHmKmax];
     const int64_t L = blockIdx.x;
@@ -441,7 +446,7 @@ __global__ __launch_bounds__(128) void hm_apply_kernel(
     const int r = threadIdx.x;
     const bool live = r < rows;
     double ar = 0.0, ai = 0.0;
-    for (int64_t it = leaf_ptr[L]; it < leaf_ptr[L + 1]; ++it) {
+    for (int64_t it = leaf_ptr[L] + blockIdx.y; it < leaf_ptr[L + 1]; it += kHmSplit) {
         const int32_t item = leaf_item[it];
         if (item >= 0) {
             const int64_t b0 = dense[4 * item + 2];
@@ -478,7 +483,23 @@ __global__ __launch_bounds__(128) void hm_apply_kernel(
         }
     }
     if (live)
-        y[3 * (int64_t)perm[L0 + r / 3] + r % 3] = make_double2(ar, ai);
+        yp[(int64_t)blockIdx.y * 3 * n_el + 3 * L0 + r] = make_double2(ar, ai);
+}
+
+// y = sum of the kHmSplit partial sums, back to element order
+__global__ __launch_bounds__(256) void hm_sum_kernel(int64_t n, const int32_t *__restrict__ perm,
+                                                     const double2 *__restrict__ yp, double2 *__restrict__ y) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= 3 * n)
+        return;
+    double ar = 0.0, ai = 0.0;
+#pragma unroll
+    for (int p = 0; p < kHmSplit; ++p) {
+        const double2 v = yp[(int64_t)p * 3 * n + i];
+        ar += v.x;
+        ai += v.y;
+    }
+    y[3 * (int64_t)perm[i / 3] + i % 3] = make_double2(ar, ai);
 }
 
 }  // namespace
@@ -539,10 +560,11 @@ void hmat_apply(const Problem &p, const Workspace &ws, const double *x, double *
     if (nl)
         hm_vt_kernel<<<(unsigned)nl, 256, 0, st>>>(H.d_lowrank, H.kmax, ws.hm_rank, ws.hm_offs, ws.hm_pool, ws.hm_xp,
                                                     ws.hm_t);
-    hm_apply_kernel<<<(unsigned)nleaf, 128, 0, st>>>(H.d_leaves, H.d_leaf_ptr, H.d_leaf_item, H.d_dense,
-                                                      H.d_dense_off, H.d_lowrank, H.kmax, ws.hm_rank, ws.hm_offs,
-                                                      H.d_perm, ws.hm_dense, ws.hm_pool, ws.hm_t, ws.hm_xp,
-                                                      reinterpret_cast<double2 *>(y));
+    hm_apply_kernel<<<dim3((unsigned)nleaf, kHmSplit), 128, 0, st>>>(
+        H.d_leaves, H.d_leaf_ptr, H.d_leaf_item, H.d_dense, H.d_dense_off, H.d_lowrank, H.kmax, ws.hm_rank, ws.hm_offs,
+        H.d_perm, ws.hm_dense, ws.hm_pool, ws.hm_t, ws.hm_xp, H.n, ws.hm_yp);
+    hm_sum_kernel<<<(unsigned)((3 * H.n + 255) / 256), 256, 0, st>>>(H.n, H.d_perm, ws.hm_yp,
+                                                                      reinterpret_cast<double2 *>(y));
     AFS_HIP(hipGetLastError());
 }
 

@@ -36,7 +36,7 @@ Workspace::~Workspace() { release(); }
 
 void Workspace::hm_release() {
     for (void *p : {(void *)hm_dense, (void *)hm_pool, (void *)hm_ctr, (void *)hm_offs, (void *)hm_t,
-                    (void *)hm_xp, (void *)hm_rank, (void *)hm_status})
+                    (void *)hm_xp, (void *)hm_yp, (void *)hm_rank, (void *)hm_status})
         if (p)
             (void)hipFree(p);
     if (hm_host)
@@ -46,7 +46,7 @@ void Workspace::hm_release() {
     hm_ctr = nullptr;
     hm_offs = nullptr;
     hm_pool_cap = 0;
-    hm_t = hm_xp = nullptr;
+    hm_t = hm_xp = hm_yp = nullptr;
     hm_rank = hm_status = nullptr;
     hm_cap[0] = hm_cap[1] = hm_cap[2] = 0;
     hm_ok = false;
@@ -72,6 +72,7 @@ void Workspace::hm_alloc(const HmatPlan &H) {
     hm_status = (int *)dalloc(std::max<size_t>(nl, 1) * 4);
     hm_t = (double2 *)dalloc(std::max<size_t>(nl, 1) * H.kmax * 16);
     hm_xp = (double2 *)dalloc((size_t)std::max<int64_t>(H.n, 1) * 3 * 16);
+    hm_yp = (double2 *)dalloc((size_t)std::max<int64_t>(H.n, 1) * 3 * 16 * 4);
     AFS_HIP(hipHostMalloc((void **)&hm_host, std::max<size_t>(nl, 1) * 2 * sizeof(int), hipHostMallocDefault));
     hm_cap[0] = nd;
     hm_cap[1] = nf;

@@ -45,6 +45,7 @@ struct Workspace {
     int64_t *hm_offs = nullptr;            // [nl][kmax] pool offset of each term
     double2 *hm_t = nullptr;
     double2 *hm_xp = nullptr;              // x in tree order (product scratch)
+    double2 *hm_yp = nullptr;              // partial sums of the product, [4][3 n] in tree order
     int *hm_rank = nullptr, *hm_status = nullptr;
     int *hm_host = nullptr;                // pinned: ranks, then status flags
     size_t hm_cap[3] = {0, 0, 0};
