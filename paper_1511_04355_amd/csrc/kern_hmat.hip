@@ -163,17 +163,21 @@ __global__ __launch_bounds__(256) void hm_dense_kernel(
     }
 }
 
-struct RedMax {
+// work-group (NT threads) reductions through LDS
+// one pass: argmax of v (index i, smallest index on ties) and the sums of a and b
+struct RedMaxSum {
     double v;
     int64_t i;
+    double a, b;
 };
-
-// work-group (NT threads) reductions through LDS
 template <int NT>
-__device__ __forceinline__ RedMax group_argmax(double v, int64_t i, double *sv, int64_t *si) {
+__device__ __forceinline__ RedMaxSum group_argmax_sums(double v, int64_t i, double a, double b, double *sv,
+                                                       int64_t *si, double *sa, double *sb) {
     const int t = threadIdx.x;
     sv[t] = v;
     si[t] = i;
+    sa[t] = a;
+    sb[t] = b;
     __syncthreads();
     for (int h = NT / 2; h > 0; h >>= 1) {
         if (t < h) {
@@ -183,25 +187,12 @@ __device__ __forceinline__ RedMax group_argmax(double v, int64_t i, double *sv, 
                 sv[t] = o;
                 si[t] = oi;
             }
+            sa[t] += sa[t + h];
+            sb[t] += sb[t + h];
         }
         __syncthreads();
     }
-    RedMax r{sv[0], si[0]};
-    __syncthreads();
-    return r;
-}
-
-template <int NT>
-__device__ __forceinline__ double group_sum(double v, double *sv) {
-    const int t = threadIdx.x;
-    sv[t] = v;
-    __syncthreads();
-    for (int h = NT / 2; h > 0; h >>= 1) {
-        if (t < h)
-            sv[t] += sv[t + h];
-        __syncthreads();
-    }
-    const double r = sv[0];
+    RedMaxSum r{sv[0], si[0], sa[0], sb[0]};
     __syncthreads();
     return r;
 }
@@ -219,7 +210,7 @@ __global__ __launch_bounds__(NT) void hm_aca_kernel(
     __shared__ float coef32[64];
     if (threadIdx.x < 64)
         coef32[threadIdx.x] = coef32_g[threadIdx.x];
-    __shared__ double sv[NT];
+    __shared__ double sv[NT], sa[NT], sb[NT];
     __shared__ int64_t si[NT];
     __shared__ double2 cf[kHmKmax];
     __shared__ int64_t used[kHmKmax + 1];
@@ -297,8 +288,8 @@ __global__ __launch_bounds__(NT) void hm_aca_kernel(
                 }
             }
         }
-        const RedMax pv = group_argmax<NT>(best, bi, sv, si);
-        const double rn2 = group_sum<NT>(rn, sv);
+        const RedMaxSum pv = group_argmax_sums<NT>(best, bi, rn, 0.0, sv, si, sa, sb);
+        const double rn2 = pv.a;
         if (probing) {
             // after the stopping test: probe rows whose residuals are small
             // against the mean row norm of S confirm it (all kProbes in a row);
@@ -369,9 +360,8 @@ __global__ __launch_bounds__(NT) void hm_aca_kernel(
                 }
             }
         }
-        const double nu2 = group_sum<NT>(nu, sv);
-        const double nv2 = group_sum<NT>(nv, sv);
-        const RedMax nx = group_argmax<NT>(best, bi, sv, si);
+        const RedMaxSum nx = group_argmax_sums<NT>(best, bi, nu, nv, sv, si, sa, sb);
+        const double nu2 = nx.a, nv2 = nx.b;
         ++k;
         S2 += nu2 * nv2;
         // the terms span the block (k = min(R, C): U V^T is then the block itself)
