@@ -40,3 +40,22 @@ def test_bench_refuses_several_gpus():
                        text=True, timeout=300)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+
+
+def test_six_node_cavity_mesh():
+    """The six-node sphere: counts, every node on the sphere, each mid-edge node
+    shared by the two elements of its edge (a conforming mesh), and the corner
+    triangles oriented like the flat cavity's."""
+    for L in (0, 1, 2):
+        m = mg.cavity_quadratic(L)
+        assert m.n_tri == 20 * 4 ** L and m.n_nodes == 120 * 4 ** L and m.n_unknowns == 360 * 4 ** L
+        assert np.allclose(np.linalg.norm(m.xyz, axis=1), 1.0, atol=1e-14)
+        owners = {}
+        for e, t in enumerate(m.tri6):
+            for a, mid in ((0, 3), (1, 4), (2, 5)):
+                key = tuple(sorted((t[a], t[(a + 1) % 3])))
+                owners.setdefault(key, set()).add(int(t[mid]))
+        assert all(len(v) == 1 for v in owners.values())          # one mid node per edge
+        assert len(owners) == 30 * 4 ** L                          # every edge of the closed surface
+        flat = mg.cavity(L)
+        assert np.array_equal(m.tri6[:, :3], flat.tri)
