@@ -56,13 +56,16 @@ void Workspace::hm_alloc(const HmatPlan &H) {
     const size_t nd = (size_t)H.dense_off.back(), nl = H.lowrank.size() / 4;
     // pool for an average of 64 terms per block, within half the free memory
     // (a block that finds the pool spent leaves the frequency on the on-the-fly operator)
-    size_t nf = (size_t)H.lr_rows * 64;
-    if (hm_dense && hm_cap[0] >= nd && hm_cap[1] >= nf && hm_cap[2] >= nl)
+    const size_t want = (size_t)H.lr_rows * 64;
+    // hm_cap[1] records the size asked for (the pool itself may have been capped):
+    // the same request reuses the buffers instead of reallocating them per frequency
+    if (hm_dense && hm_cap[0] >= nd && hm_cap[1] >= want && hm_cap[2] >= nl)
         return;
     hm_release();
     size_t free_b = 0, total_b = 0;
     AFS_HIP(hipMemGetInfo(&free_b, &total_b));
-    nf = std::min(nf, (size_t)(0.5 * (double)(free_b > (size_t)nd * 8 ? free_b - (size_t)nd * 8 : 0)) / 8);
+    const size_t nf =
+        std::min(want, (size_t)(0.5 * (double)(free_b > (size_t)nd * 8 ? free_b - (size_t)nd * 8 : 0)) / 8);
     hm_dense = (float2 *)dalloc(std::max<size_t>(nd, 1) * 8);
     hm_pool = (float2 *)dalloc(std::max<size_t>(nf, 1) * 8);
     hm_pool_cap = nf;
@@ -75,7 +78,7 @@ void Workspace::hm_alloc(const HmatPlan &H) {
     hm_yp = (double2 *)dalloc((size_t)std::max<int64_t>(H.n, 1) * 3 * 16 * 4);
     AFS_HIP(hipHostMalloc((void **)&hm_host, std::max<size_t>(nl, 1) * 2 * sizeof(int), hipHostMallocDefault));
     hm_cap[0] = nd;
-    hm_cap[1] = nf;
+    hm_cap[1] = want;
     hm_cap[2] = nl;
 }
 
