@@ -158,17 +158,21 @@ void hmat_build(const Problem &p, double eta, int kmax, HmatPlan &H) {
                                                    (H.dense[4 * d + 3] - H.dense[4 * d + 2]);
     H.lr_rows = 0;
     H.lr_order.clear();
-    for (int64_t l = 0; l < nl; ++l) {
+    auto tier = [&](int64_t l) {
         const int64_t na = H.lowrank[4 * l + 1] - H.lowrank[4 * l], nb = H.lowrank[4 * l + 3] - H.lowrank[4 * l + 2];
-        H.lr_rows += 3 * (na + nb);
-        if (na <= 64 && nb <= 64)
-            H.lr_order.push_back((int32_t)l);
-    }
-    H.n_small = (int64_t)H.lr_order.size();
-    for (int64_t l = 0; l < nl; ++l) {
-        const int64_t na = H.lowrank[4 * l + 1] - H.lowrank[4 * l], nb = H.lowrank[4 * l + 3] - H.lowrank[4 * l + 2];
-        if (!(na <= 64 && nb <= 64))
-            H.lr_order.push_back((int32_t)l);
+        const int64_t big = na > nb ? na : nb;
+        return big <= 64 ? 0 : (big <= 128 ? 1 : 2);
+    };
+    for (int64_t l = 0; l < nl; ++l)
+        H.lr_rows += 3 * ((H.lowrank[4 * l + 1] - H.lowrank[4 * l]) + (H.lowrank[4 * l + 3] - H.lowrank[4 * l + 2]));
+    for (int tr = 0; tr < 3; ++tr) {
+        for (int64_t l = 0; l < nl; ++l)
+            if (tier(l) == tr)
+                H.lr_order.push_back((int32_t)l);
+        if (tr == 0)
+            H.n_small = (int64_t)H.lr_order.size();
+        if (tr == 1)
+            H.n_mid = (int64_t)H.lr_order.size() - H.n_small;
     }
 
     // ---- per leaf row range: the dense blocks of its block row and every

@@ -29,8 +29,8 @@ struct HmatPlan {
     std::vector<int64_t> lowrank;   // [nl][4]
     std::vector<int64_t> dense_off; // [nd+1] offsets (complex entries) of the dense blocks
     int64_t lr_rows = 0;            // sum over low-rank blocks of R + C (one term's entries)
-    std::vector<int32_t> lr_order;  // low-rank blocks: those of at most 64 elements a side first
-    int64_t n_small = 0;
+    std::vector<int32_t> lr_order;  // low-rank blocks by size: at most 64 elements a side, at most 128, larger
+    int64_t n_small = 0, n_mid = 0;
     std::vector<int64_t> leaves;    // [nleaf][2] row ranges of the leaves
     std::vector<int64_t> leaf_ptr;  // [nleaf+1]
     std::vector<int32_t> leaf_item; // dense block d as d, low-rank block l as -(l + 1)

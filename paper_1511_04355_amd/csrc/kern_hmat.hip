@@ -199,7 +199,7 @@ __device__ __forceinline__ RedMaxSum group_argmax_sums(double v, int64_t i, doub
 
 // status: 0 converged, 1 out of terms, 2 pool exhausted.  NT threads per
 // block: 64 for blocks of at most 64 elements a side (most are leaf pairs of
-// 32), 256 for the larger ones; ids lists the blocks of this launch.
+// 32), 128 up to 128, 256 for the larger ones; ids lists the blocks of this launch.
 template <int NT>
 __global__ __launch_bounds__(NT) void hm_aca_kernel(
     const int32_t *__restrict__ perm,
@@ -504,7 +504,7 @@ void hmat_setup(const Problem &p, Workspace &ws, const KernelParams &kp, double 
                                                        d.near_col, ws.nearblk, ws.selfblk, H.d_perm, H.d_dense,
                                                        H.d_dense_off, ws.hm_dense);
     AFS_HIP(hipMemsetAsync(ws.hm_ctr, 0, sizeof(unsigned long long), st));
-    const int64_t n_small = H.n_small, n_large = nl - H.n_small;
+    const int64_t n_small = H.n_small, n_mid = H.n_mid, n_large = nl - H.n_small - H.n_mid;
     Hm32 h32;
     {
         const double sr = kp.s_re * kp.inv_cs, si = kp.s_im * kp.inv_cs, ks2 = sr * sr + si * si;
@@ -516,12 +516,16 @@ void hmat_setup(const Problem &p, Workspace &ws, const KernelParams &kp, double 
                                                              H.d_lowrank, H.d_lr_order, H.kmax, eps, ws.hm_pool,
                                                              (unsigned long long)ws.hm_pool_cap, ws.hm_ctr, ws.hm_offs,
                                                              ws.hm_rank, ws.hm_status, h32, d.col32, d.src32, d.coef32);
+    if (n_mid)
+        hm_aca_kernel<128><<<(unsigned)n_mid, 128, 0, st>>>(H.d_perm, H.d_lowrank, H.d_lr_order + n_small, H.kmax, eps,
+                                                             ws.hm_pool, (unsigned long long)ws.hm_pool_cap, ws.hm_ctr,
+                                                             ws.hm_offs, ws.hm_rank, ws.hm_status, h32, d.col32,
+                                                             d.src32, d.coef32);
     if (n_large)
-        hm_aca_kernel<256><<<(unsigned)n_large, 256, 0, st>>>(H.d_perm,
-                                                               H.d_lowrank, H.d_lr_order + n_small, H.kmax, eps,
-                                                               ws.hm_pool, (unsigned long long)ws.hm_pool_cap,
-                                                               ws.hm_ctr, ws.hm_offs, ws.hm_rank, ws.hm_status, h32, d.col32,
-                                                               d.src32, d.coef32);
+        hm_aca_kernel<256><<<(unsigned)n_large, 256, 0, st>>>(H.d_perm, H.d_lowrank, H.d_lr_order + n_small + n_mid,
+                                                               H.kmax, eps, ws.hm_pool, (unsigned long long)ws.hm_pool_cap,
+                                                               ws.hm_ctr, ws.hm_offs, ws.hm_rank, ws.hm_status, h32,
+                                                               d.col32, d.src32, d.coef32);
     AFS_HIP(hipGetLastError());
     if (nl) {
         AFS_HIP(hipMemcpyAsync(ws.hm_host, ws.hm_rank, nl * sizeof(int), hipMemcpyDeviceToHost, st));
