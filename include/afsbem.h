@@ -179,6 +179,15 @@ int afsbem_matvec_free_device(afsbem_problem *p, double s_re, double s_im, int p
  * low-rank and dense blocks.  Returns AFSBEM_ENOCONV (y still written, from
  * the factors as found) when a block did not reach eps within 128 terms.
  * Flat-element problems only. */
+/* Host-side view of the hierarchical operator's block partition for a flat
+ * mesh (nothing is uploaded; no device needed): out8 = element count n, dense
+ * blocks, low-rank blocks, element pairs covered by all blocks (n^2 for a
+ * partition), near pairs falling in low-rank blocks (0), the largest low-rank
+ * block side (elements), elements covered by the leaves (n), entries of the
+ * per-leaf block lists.  policy nullable (defaults). */
+int afsbem_hmat_partition_info(const afsbem_mesh *mesh, const int8_t *bc_kind, const afsbem_quad_policy *policy,
+                                double eta, int64_t *out8);
+
 int afsbem_hmat_matvec_device(afsbem_problem *p, double s_re, double s_im, double eps, double eta, const void *d_x,
                               void *d_y, int32_t *max_rank, int64_t *n_lowrank, int64_t *n_dense,
                               void *hip_stream);

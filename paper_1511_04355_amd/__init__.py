@@ -20,6 +20,7 @@ from ._lib import (  # noqa: F401
     Problem,
     SolveOptions,
     solve_batched,
+    hmat_partition_info,
     autotune_set,
     autotune_report,
     lib,

@@ -92,6 +92,7 @@ def lib():
         L.afsbem_autotune_report.argtypes = [P, i64, P]
         L.afsbem_matvec_free_device.argtypes = [P, d, d, ctypes.c_int, P, P, P, P, P]
         L.afsbem_hmat_matvec_device.argtypes = [P, d, d, d, d, P, P, P, P, P, P]
+        L.afsbem_hmat_partition_info.argtypes = [P, P, P, d, P]
         L.afsbem_solve_opts_default.argtypes = [P]
         L.afsbem_problem_clusters.argtypes = [P, P, P, P]
         L.afsbem_precond_apply_device.argtypes = [P, ctypes.c_int, P, P, P, P, P]
@@ -362,6 +363,26 @@ class Problem:
         out["status"] = rc
         out["stats"] = [{f: getattr(stats[k], f) for f, _ in _Stats._fields_} for k in range(ns)]
         return out
+
+
+def hmat_partition_info(mesh, eta=1.0, policy=(2.0, 8, 16, 16)):
+    """Block partition of the hierarchical operator for a flat mesh, built on
+    the host (no device): dict of counts (see afsbem_hmat_partition_info)."""
+    L = lib()
+    xyz = np.ascontiguousarray(mesh.xyz, np.float64)
+    tri = np.ascontiguousarray(mesh.tri, np.int32)
+    kind = np.ascontiguousarray(mesh.bc_kind, np.int8)
+    m = ctypes.c_void_p()
+    _check(L.afsbem_mesh_create(xyz.ctypes.data, xyz.shape[0], tri.ctypes.data, tri.shape[0], ctypes.byref(m)))
+    try:
+        out = np.zeros(8, np.int64)
+        pol = _Policy(float(policy[0]), int(policy[1]), int(policy[2]), int(policy[3]))
+        _check(L.afsbem_hmat_partition_info(m, kind.ctypes.data, ctypes.byref(pol), float(eta), out.ctypes.data))
+    finally:
+        L.afsbem_mesh_destroy(m)
+    keys = ["n", "n_dense", "n_lowrank", "pairs_covered", "near_pairs_in_lowrank", "largest_lowrank_side",
+            "leaf_elements", "leaf_list_entries"]
+    return dict(zip(keys, (int(v) for v in out)))
 
 
 def solve_batched(problems, s_lists, bc_vals, opts: SolveOptions | None = None, want_ut=False):

@@ -354,6 +354,55 @@ int afsbem_matvec_free_device(afsbem_problem *p, double s_re, double s_im, int p
     });
 }
 
+int afsbem_hmat_partition_info(const afsbem_mesh *mesh, const int8_t *bc_kind, const afsbem_quad_policy *policy,
+                                double eta, int64_t *out8) {
+    return guarded([&] {
+        AFS_REQUIRE(mesh && bc_kind && out8, AFSBEM_EINVAL, "null pointer argument");
+        AFS_REQUIRE(mesh->order == 1, AFSBEM_EINVAL, "the hierarchical operator is built for flat-element meshes");
+        AFS_REQUIRE(eta > 0.0 && std::isfinite(eta), AFSBEM_EINVAL, "eta must be > 0");
+        for (int64_t e = 0; e < mesh->n_tri; ++e)
+            AFS_REQUIRE(bc_kind[e] == 0 || bc_kind[e] == 1, AFSBEM_EINVAL, "bc_kind must be 0 or 1");
+        Problem P;  // host plan only: nothing is uploaded
+        P.pol = policy ? *policy : afsbem_quad_policy{2.0, 8, 16, 16};
+        P.mat = derive_material(afsbem_material{1.0, 0.25, 1.0});
+        build_plan(mesh->xyz.data(), mesh->n_vert, mesh->tri.data(), mesh->n_tri, bc_kind, P.pol, P.mat, P.host);
+        HmatPlan H;
+        hmat_build(P, eta, kHmatKmax, H, false);
+        const int64_t n = H.n, nd = (int64_t)H.dense.size() / 4, nl = (int64_t)H.lowrank.size() / 4;
+        std::vector<int64_t> pos(n);
+        for (int64_t q = 0; q < n; ++q)
+            pos[H.perm[q]] = q;
+        int64_t covered = 0, near_in_lowrank = 0, largest = 0;
+        for (int64_t d = 0; d < nd; ++d)
+            covered += (H.dense[4 * d + 1] - H.dense[4 * d]) * (H.dense[4 * d + 3] - H.dense[4 * d + 2]);
+        for (int64_t l = 0; l < nl; ++l) {
+            const int64_t a0 = H.lowrank[4 * l], a1 = H.lowrank[4 * l + 1];
+            const int64_t b0 = H.lowrank[4 * l + 2], b1 = H.lowrank[4 * l + 3];
+            covered += (a1 - a0) * (b1 - b0);
+            largest = std::max(largest, std::max(a1 - a0, b1 - b0));
+            for (int64_t q = a0; q < a1; ++q) {
+                const int32_t m = H.perm[q];
+                for (int64_t pp = P.host.near_ptr[m]; pp < P.host.near_ptr[m + 1]; ++pp) {
+                    const int64_t pn = pos[P.host.near_col[pp]];
+                    near_in_lowrank += (pn >= b0 && pn < b1);
+                }
+            }
+        }
+        int64_t leaf_rows = 0;
+        for (size_t L = 0; L + 1 < H.leaves.size(); L += 2)
+            leaf_rows += H.leaves[L + 1] - H.leaves[L];
+        out8[0] = n;
+        out8[1] = nd;
+        out8[2] = nl;
+        out8[3] = covered;
+        out8[4] = near_in_lowrank;
+        out8[5] = largest;
+        out8[6] = leaf_rows;
+        out8[7] = (int64_t)H.leaf_item.size();
+        return AFSBEM_OK;
+    });
+}
+
 int afsbem_hmat_matvec_device(afsbem_problem *p, double s_re, double s_im, double eps, double eta, const void *d_x,
                               void *d_y, int32_t *max_rank, int64_t *n_lowrank, int64_t *n_dense,
                               void *hip_stream) {

@@ -50,7 +50,7 @@ void hmat_ensure(Problem &p, double eta) {
     p.hmat = H;
 }
 
-void hmat_build(const Problem &p, double eta, int kmax, HmatPlan &H) {
+void hmat_build(const Problem &p, double eta, int kmax, HmatPlan &H, bool upload) {
     const HostPlan &P = p.host;
     AFS_REQUIRE(P.disc == 0, AFSBEM_EINVAL, "the hierarchical far field is built for flat-element problems");
     const int64_t n = P.n_tri;
@@ -207,6 +207,8 @@ void hmat_build(const Problem &p, double eta, int kmax, HmatPlan &H) {
     AFS_REQUIRE(nd < ((int64_t)1 << 31) && nl < ((int64_t)1 << 30) && nleaf < ((int64_t)1 << 31), AFSBEM_EINVAL,
                 "hierarchical partition too large");
 
+    if (!upload)
+        return;
     H.d_perm = up(H, H.perm);
     H.d_dense = up(H, H.dense);
     H.d_lowrank = up(H, H.lowrank);

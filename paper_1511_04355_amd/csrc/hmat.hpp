@@ -46,7 +46,8 @@ struct HmatPlan {
 };
 
 // cluster tree and block partition of the problem's elements (host), uploaded
-void hmat_build(const Problem &p, double eta, int kmax, HmatPlan &out);
+// unless upload = false (host-side inspection)
+void hmat_build(const Problem &p, double eta, int kmax, HmatPlan &out, bool upload = true);
 // p.hmat built for this eta (rebuilt when eta changed; no work in flight may use the old one)
 void hmat_ensure(Problem &p, double eta);
 

@@ -76,3 +76,23 @@ def test_quadratic_mesh_validation_errors():
     assert b"out of range" in L.afsbem_last_error()
     rc = L.afsbem_mesh_create_quadratic(xyz.ctypes.data, 5, tri6.ctypes.data, 1, ctypes.byref(out))
     assert rc == afs._lib.EINVAL
+
+
+@pytest.mark.parametrize("name", ["cavity_L4", "block_seed3", "block_27_voids"])
+def test_hmat_partition_covers_every_pair_once(name):
+    """The hierarchical operator's block partition, built on the host: the
+    blocks cover all n^2 element pairs (the recursion splits without overlap,
+    so a full count means each pair once), no near pair falls in a low-rank
+    block, the leaves tile the elements, and larger meshes get low-rank blocks."""
+    import paper_1511_04355_amd as afs
+    from synth import meshgen as mg
+    mesh = {"cavity_L4": lambda: mg.cavity(4), "block_seed3": lambda: mg.random_block(3),
+            "block_27_voids": lambda: mg.lattice_block(3, 20, 2, 1000)}[name]()
+    info = afs.hmat_partition_info(mesh)
+    n = info["n"]
+    assert n == mesh.n_tri
+    assert info["pairs_covered"] == n * n
+    assert info["near_pairs_in_lowrank"] == 0
+    assert info["leaf_elements"] == n
+    assert info["n_lowrank"] > 0 and info["n_dense"] > 0
+    assert info["leaf_list_entries"] >= info["n_dense"] + info["n_lowrank"]
