@@ -179,6 +179,13 @@ int afsbem_matvec_free_device(afsbem_problem *p, double s_re, double s_im, int p
  * low-rank and dense blocks.  Returns AFSBEM_ENOCONV (y still written, from
  * the factors as found) when a block did not reach eps within 128 terms.
  * Flat-element problems only. */
+/* Host-side view of the quadrature plan a problem on this mesh would use
+ * (nothing is uploaded; no device needed): out4 = collocation points (the
+ * n_tri of afsbem_problem_info), near pairs, subdivision leaves, preconditioner
+ * clusters.  Flat or six-node meshes; policy nullable (defaults). */
+int afsbem_plan_info(const afsbem_mesh *mesh, const int8_t *bc_kind, const afsbem_quad_policy *policy,
+                     int64_t *out4);
+
 /* Host-side view of the hierarchical operator's block partition for a flat
  * mesh (nothing is uploaded; no device needed): out8 = element count n, dense
  * blocks, low-rank blocks, element pairs covered by all blocks (n^2 for a

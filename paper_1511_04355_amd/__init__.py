@@ -21,6 +21,7 @@ from ._lib import (  # noqa: F401
     SolveOptions,
     solve_batched,
     hmat_partition_info,
+    plan_info,
     autotune_set,
     autotune_report,
     lib,

@@ -93,6 +93,7 @@ def lib():
         L.afsbem_matvec_free_device.argtypes = [P, d, d, ctypes.c_int, P, P, P, P, P]
         L.afsbem_hmat_matvec_device.argtypes = [P, d, d, d, d, P, P, P, P, P, P]
         L.afsbem_hmat_partition_info.argtypes = [P, P, P, d, P]
+        L.afsbem_plan_info.argtypes = [P, P, P, P]
         L.afsbem_solve_opts_default.argtypes = [P]
         L.afsbem_problem_clusters.argtypes = [P, P, P, P]
         L.afsbem_precond_apply_device.argtypes = [P, ctypes.c_int, P, P, P, P, P]
@@ -363,6 +364,26 @@ class Problem:
         out["status"] = rc
         out["stats"] = [{f: getattr(stats[k], f) for f, _ in _Stats._fields_} for k in range(ns)]
         return out
+
+
+def plan_info(mesh, policy=(2.0, 8, 16, 16)):
+    """Sizes of the quadrature plan for a flat or six-node mesh, built on the
+    host (no device): points, near pairs, subdivision leaves, clusters."""
+    L = lib()
+    xyz = np.ascontiguousarray(mesh.xyz, np.float64)
+    six = hasattr(mesh, "tri6")
+    tri = np.ascontiguousarray(mesh.tri6 if six else mesh.tri, np.int32)
+    kind = np.ascontiguousarray(mesh.bc_kind, np.int8)
+    m = ctypes.c_void_p()
+    create = L.afsbem_mesh_create_quadratic if six else L.afsbem_mesh_create
+    _check(create(xyz.ctypes.data, xyz.shape[0], tri.ctypes.data, tri.shape[0], ctypes.byref(m)))
+    try:
+        out = np.zeros(4, np.int64)
+        pol = _Policy(float(policy[0]), int(policy[1]), int(policy[2]), int(policy[3]))
+        _check(L.afsbem_plan_info(m, kind.ctypes.data, ctypes.byref(pol), out.ctypes.data))
+    finally:
+        L.afsbem_mesh_destroy(m)
+    return dict(zip(["points", "near_pairs", "leaves", "clusters"], (int(v) for v in out)))
 
 
 def hmat_partition_info(mesh, eta=1.0, policy=(2.0, 8, 16, 16)):

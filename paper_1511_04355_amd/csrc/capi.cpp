@@ -354,6 +354,29 @@ int afsbem_matvec_free_device(afsbem_problem *p, double s_re, double s_im, int p
     });
 }
 
+int afsbem_plan_info(const afsbem_mesh *mesh, const int8_t *bc_kind, const afsbem_quad_policy *policy,
+                     int64_t *out4) {
+    return guarded([&] {
+        AFS_REQUIRE(mesh && bc_kind && out4, AFSBEM_EINVAL, "null pointer argument");
+        for (int64_t e = 0; e < mesh->n_tri; ++e)
+            AFS_REQUIRE(bc_kind[e] == 0 || bc_kind[e] == 1, AFSBEM_EINVAL, "bc_kind must be 0 or 1");
+        const afsbem_quad_policy pol = policy ? *policy : afsbem_quad_policy{2.0, 8, 16, 16};
+        HostPlan H;
+        const MaterialDerived mat = derive_material(afsbem_material{1.0, 0.25, 1.0});
+        if (mesh->order == 2) {
+            build_plan_nystrom(mesh->xyz.data(), mesh->n_vert, mesh->tri.data(), mesh->n_tri, bc_kind, pol, mat, H);
+            out4[2] = (int64_t)(H.nys_leaves.size() / 6);
+        } else {
+            build_plan(mesh->xyz.data(), mesh->n_vert, mesh->tri.data(), mesh->n_tri, bc_kind, pol, mat, H);
+            out4[2] = (int64_t)(H.leaves.size() / 10);
+        }
+        out4[0] = H.n_tri;
+        out4[1] = (int64_t)H.near_col.size();
+        out4[3] = (int64_t)H.clus_ptr.size() - 1;
+        return AFSBEM_OK;
+    });
+}
+
 int afsbem_hmat_partition_info(const afsbem_mesh *mesh, const int8_t *bc_kind, const afsbem_quad_policy *policy,
                                 double eta, int64_t *out8) {
     return guarded([&] {
