@@ -12,8 +12,8 @@
  * N x N complex system A(s) a(s) = b(s), N = 3 * n_tri.  Per element either the
  * traction is prescribed (kind 0: the displacement is unknown) or the
  * displacement is prescribed (kind 1: the traction is unknown).
- * The system is solved by right block-Jacobi-preconditioned GMRES (Section 4,
- * "GMRES in conjunction with the block diagonal preconditioner").
+ * The system is solved by GMRES (Section 2.1) with a right block-diagonal
+ * (block-Jacobi) preconditioner (Section 4).
  *
  * Conventions
  *  - Status codes: 0 success, < 0 error (AFSBEM_E*).  On error, outputs are left
@@ -511,6 +511,15 @@ int afsbem_afs_result_info(const afsbem_afs_result *r, int32_t *Nc, int32_t *M, 
                            int32_t *converged);
 /* afsbem_afs_run_problem: total Krylov products of all its solves (0 for afsbem_afs_run). */
 int afsbem_afs_result_work(const afsbem_afs_result *r, int64_t *matvecs);
+/* How the run ended (each pointer nullable).  capped: 1 if the sample cap
+ * max_Nc ended it, also when it cut the Jc validation steps of Eq. 14 short
+ * (converged is then 0: convergence needs all Jc steps to pass).
+ * unconverged_solves (afsbem_afs_run_problem): samples whose solve missed
+ * opts.tol; their best iterate was still sampled, and converged is 0 when any
+ * did.  worst_rel_res: the largest FP64 true relative residual of those solves
+ * (0 for afsbem_afs_run). */
+int afsbem_afs_result_status(const afsbem_afs_result *r, int32_t *capped, int32_t *unconverged_solves,
+                             double *worst_rel_res);
 /* Copies (each pointer nullable): s_out [Nc] complex samples in the order
  * taken, F_out [Nc][Kt] complex responses, poles_out [M] and residues_out
  * [Kt][M] of the final order-M_H model, E1_out and E2_out [n_steps]. */

@@ -18,7 +18,9 @@ Readings of the paper used here:
    Simpson on 4 Ns + 1 points;
  * convergence (Eq. 14): E1 < E1_bar and E2 < E2_bar, then Jc further steps
    that must all pass, otherwise sampling resumes (stage 3 of the Algorithm);
- * safety cap: at most Ns/2 + 1 samples (the cost of the FSM);
+ * safety cap: at most Ns/2 + 1 samples (the cost of the FSM); a run that
+   reaches the cap, also in the middle of the Jc validation steps, is
+   reported as not converged ("capped");
  * multi-point steps (q new frequencies per analysis, an extension the paper
    does not make: it inserts one): the first is the argmax above; each further
    one is the next largest local maximum of the same masked discrepancy that
@@ -81,6 +83,33 @@ def select_new(d, wgrid, taken_w, dw, q):
     return picks
 
 
+def fit_discrepancy(fH, fL):
+    """e_k of Eq. 8 for every function k: the largest |f_kH - f_kL| over the
+    frequency grid divided by the largest |f_kH| over the same grid.
+    fH, fL: [Kt, G] values of the two fits on the grid -> e [Kt]."""
+    fH = np.atleast_2d(fH)
+    fL = np.atleast_2d(fL)
+    return np.abs(fH - fL).max(axis=1) / np.abs(fH).max(axis=1)
+
+
+def stop_E2(e):
+    """E2 of Eq. 13: the largest e_k over the test set."""
+    return float(np.max(e))
+
+
+def stop_E1(td, prev_td, tgrid):
+    """E1 of Eq. 12: for every test function the integral over [0, T] of the
+    squared change of its time response (Eq. 11) between two consecutive steps,
+    divided by the integral of the square of the current response; the largest
+    of these ratios.  td, prev_td: [Kt, len(tgrid)] responses on the uniform
+    grid tgrid (composite Simpson); prev_td None (step 0) gives +infinity."""
+    if prev_td is None:
+        return np.inf
+    num = simpson((td - prev_td) ** 2, tgrid)
+    den = simpson(td ** 2, tgrid)
+    return float(np.max(num / den))
+
+
 def _fit_pair(S, F, K, J, omega, alpha_H, alpha_L, n_iter):
     MH, ML = orders(J, alpha_H, alpha_L)
     out = []
@@ -115,15 +144,10 @@ def run(response, K, Kt, T, eta, Ns, J0=16, alpha_H=2.0, alpha_L=2.3, E1_bar=1e-
         fH = vf.evaluate(sgrid, pH, rH)
         fL = vf.evaluate(sgrid, pL, rL)
         diff = np.abs(fH - fL)
-        e = diff.max(axis=1) / np.abs(fH).max(axis=1)
-        E2 = float(e.max())
+        e = fit_discrepancy(fH, fL)
+        E2 = stop_E2(e)
         td = vf.time_response(tgrid, pH, rH)
-        if prev_td is None:
-            E1 = np.inf
-        else:
-            num = simpson((td - prev_td) ** 2, tgrid)
-            den = simpson(td ** 2, tgrid)
-            E1 = float(np.max(num / den))
+        E1 = stop_E1(td, prev_td, tgrid)
         prev_td = td
         kmax = int(np.argmax(e[:K]))
         s_new = sgrid[select_new(diff[kmax], wgrid, Sa.imag, dw, q)]
@@ -142,25 +166,29 @@ def run(response, K, Kt, T, eta, Ns, J0=16, alpha_H=2.0, alpha_L=2.3, E1_bar=1e-
         F = np.concatenate([F, np.asarray(response(s_new), np.complex128).reshape(len(s_new), Kt)])
 
     E1, E2, s_new, model = analyse()
-    converged = False
+    converged = capped = False
     while True:
         if E1 < E1_bar and E2 < E2_bar:
-            ok = True
-            for _ in range(Jc):
-                if len(S) >= max_Nc:
-                    break
+            # stage 3: Jc further steps, one frequency each, must all pass
+            passed = 0
+            while passed < Jc and len(S) < max_Nc:
                 add(s_new[:1])
                 E1, E2, s_new, model = analyse()
                 if not (E1 < E1_bar and E2 < E2_bar):
-                    ok = False
                     break
-            if ok:
+                passed += 1
+            if passed == Jc:
                 converged = True
+                break
+            if len(S) >= max_Nc:
+                # the cap cut the validation short: not converged (Eq. 14 asks for all Jc steps)
+                capped = True
                 break
             continue
         if len(S) >= max_Nc:
+            capped = True
             break
         add(s_new)
         E1, E2, s_new, model = analyse()
     return {"s": np.array(S), "F": F, "poles": model[0], "residues": model[1], "converged": converged,
-            "Nc": len(S), "history": hist}
+            "capped": capped, "Nc": len(S), "history": hist}

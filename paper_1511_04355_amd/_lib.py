@@ -118,6 +118,7 @@ def lib():
         L.afsbem_afs_result_get.argtypes = [P, P, P, P, P, P, P]
         L.afsbem_afs_result_destroy.argtypes = [P]
         L.afsbem_afs_result_work.argtypes = [P, P]
+        L.afsbem_afs_result_status.argtypes = [P, P, P, P]
         L.afsbem_time_synthesis_device.argtypes = [i32, P, i32, P, i64, P, i32, P, P, P]
         L.afsbem_model_sample_device.argtypes = [i32, P, i32, P, i64, P, i32, P, P, P]
         L.afsbem_fsm_invert_device.argtypes = [d, d, i32, ctypes.c_int, i64, P, P, P]
@@ -582,9 +583,12 @@ def _afs_result(r, Kt):
                                    E1.ctypes.data, E2.ctypes.data))
     mv = ctypes.c_int64()
     _check(L.afsbem_afs_result_work(r, ctypes.byref(mv)))
+    capped, unconv, worst = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
+    _check(L.afsbem_afs_result_status(r, ctypes.byref(capped), ctypes.byref(unconv), ctypes.byref(worst)))
     L.afsbem_afs_result_destroy(r)
     return {"s": s, "F": F, "poles": poles, "residues": res, "E1": E1, "E2": E2, "Nc": nc.value,
-            "converged": bool(conv.value), "matvecs": mv.value}
+            "converged": bool(conv.value), "capped": bool(capped.value), "matvecs": mv.value,
+            "unconverged_solves": unconv.value, "worst_rel_res": worst.value}
 
 
 def afs_run(response, K, Kt, params):

@@ -630,8 +630,11 @@ struct AfsResult {
     std::vector<double> E1, E2;    // per analysis step
     std::vector<int> J, MH, ML;
     int converged = 0;
+    int capped = 0;                // the sample cap ended the run (also inside the Jc validation steps)
     int Kt = 0;
     int64_t matvecs = 0;           // GPU solves (afs_run_problem): Krylov products in all
+    int unconverged = 0;           // GPU solves that missed opts.tol (their iterate was still sampled)
+    double worst_rel_res = 0.0;    // largest FP64 true relative residual over the GPU solves
 };
 
 // responses [n][Kt] at the frequencies asked for; model: the current order-M_H
@@ -820,34 +823,39 @@ static void afs_run_impl(const afsbem_afs_params &P, int K, int Kt, const Respon
     };
     auto pass = [&](std::pair<double, double> e) { return e.first < P.E1_bar && e.second < P.E2_bar; };
     std::pair<double, double> err = analyse();
-    bool converged = false;
+    bool converged = false, capped = false;
     while (true) {
         if (pass(err)) {
-            bool ok = true;
-            for (int v = 0; v < P.Jc; ++v) {
-                if ((int)S.size() >= max_Nc)
-                    break;
-                add(std::vector<cplx>(s_new.begin(), s_new.begin() + 1));  // validation: one at a time
+            // stage 3 (Eq. 14): Jc further steps, one frequency each, must all pass
+            int passed = 0;
+            while (passed < P.Jc && (int)S.size() < max_Nc) {
+                add(std::vector<cplx>(s_new.begin(), s_new.begin() + 1));
                 err = analyse();
-                if (!pass(err)) {
-                    ok = false;
+                if (!pass(err))
                     break;
-                }
+                ++passed;
             }
-            if (ok) {
+            if (passed == P.Jc) {
                 converged = true;
+                break;
+            }
+            if ((int)S.size() >= max_Nc) {
+                capped = true;  // validation cut short by the cap: not converged
                 break;
             }
             continue;
         }
-        if ((int)S.size() >= max_Nc)
+        if ((int)S.size() >= max_Nc) {
+            capped = true;
             break;
+        }
         add(s_new);
         err = analyse();
     }
     R.s = S;
     R.F = Fv;
     R.converged = converged ? 1 : 0;
+    R.capped = capped ? 1 : 0;
 }
 
 }  // namespace afsbem
@@ -1273,8 +1281,15 @@ int afsbem_afs_run_problem(afsbem_problem *p, const afsbem_afs_params *params, c
                                                    st);
                 if (rc != AFSBEM_OK && rc != AFSBEM_ENOCONV)
                     throw Error{rc, std::string("solve failed: ") + afsbem_last_error()};
-                for (const auto &q : stats)
+                for (const auto &q : stats) {
                     res->r.matvecs += q.iters;
+                    // a sample that missed the tolerance is kept (best iterate) but counted: the
+                    // result does not report convergence when any sample missed it
+                    if (!(q.rel_res_fp64 <= o.tol))
+                        ++res->r.unconverged;
+                    if (!(q.rel_res_fp64 <= res->r.worst_rel_res))
+                        res->r.worst_rel_res = q.rel_res_fp64;
+                }
                 std::vector<double> ha(hb.size());
                 AFS_HIP(hipMemcpyAsync(ha.data(), da, ha.size() * 8, hipMemcpyDeviceToHost, st));
                 AFS_HIP(hipStreamSynchronize(st));
@@ -1288,6 +1303,8 @@ int afsbem_afs_run_problem(afsbem_problem *p, const afsbem_afs_params *params, c
                 }
             };
             afs_run_impl(*params, K, Kt, resp, res->r);
+            if (res->r.unconverged > 0)
+                res->r.converged = 0;
         } catch (...) {
             delete res;
             (void)hipStreamSynchronize(st);
@@ -1324,6 +1341,20 @@ int afsbem_afs_result_work(const afsbem_afs_result *r, int64_t *matvecs) {
     return guarded_d([&] {
         AFS_REQUIRE(r && matvecs, AFSBEM_EINVAL, "null argument");
         *matvecs = r->r.matvecs;
+        return AFSBEM_OK;
+    });
+}
+
+int afsbem_afs_result_status(const afsbem_afs_result *r, int32_t *capped, int32_t *unconverged_solves,
+                             double *worst_rel_res) {
+    return guarded_d([&] {
+        AFS_REQUIRE(r, AFSBEM_EINVAL, "null result");
+        if (capped)
+            *capped = r->r.capped;
+        if (unconverged_solves)
+            *unconverged_solves = r->r.unconverged;
+        if (worst_rel_res)
+            *worst_rel_res = r->r.worst_rel_res;
         return AFSBEM_OK;
     });
 }

@@ -208,6 +208,9 @@ def test_afs_library_matches_oracle_on_mock():
     assert np.max(np.abs(p["s"][:30] - o["s"][:30])) < 1e-9
     # the fits at J = 33 (16 poles for 17-pole data) are ill-conditioned: 1e-4
     np.testing.assert_allclose(p["E2"][:20], o["history"]["E2"][:20], rtol=1e-4)
+    assert np.isinf(p["E1"][0]) and np.isinf(o["history"]["E1"][0])
+    np.testing.assert_allclose(p["E1"][1:20], o["history"]["E1"][1:20], rtol=1e-4, atol=1e-8)
+    assert not p["capped"] and p["unconverged_solves"] == 0
     t = np.linspace(0, T, 300)
     ex = vf.time_response(t, poles, res)
     assert np.max(np.abs(afs.vf_eval_time(p["poles"], p["residues"], t) - ex)) < 1e-6 * np.max(np.abs(ex))
@@ -304,3 +307,130 @@ def test_afs_library_reports_callback_failure():
 
     with pytest.raises(ValueError):
         afs.afs_run(bad, 2, 2, afs.afs_params(10.0, 0.5, 64))
+
+
+# ------------------------------------------- pins of Eq. 6 and Eq. 8, 12, 13
+def _contour_residue(H, a, rho=0.1, n=64):
+    """(1 / 2 pi i) of the integral of H over a circle of radius rho about a
+    (trapezoidal rule on the circle: exact up to (rho / d)^n terms, d the
+    distance to the nearest other singularity)."""
+    th = 2 * np.pi * np.arange(n) / n
+    z = rho * np.exp(1j * th)
+    return np.mean(z * np.array([H(a + zz) for zz in z]))
+
+
+def test_time_response_on_the_cavity_partial_fractions():
+    """Eq. 6 read as r e^{+a t}: the cavity wall displacement u_r(1, s) is the
+    rational function (1 + s/sqrt3) / (s (s^2 + 4 s/sqrt3 + 4)) (poles 0 and
+    -2/sqrt3 +- i sqrt(8/3)); its partial fractions, with residues taken by
+    contour integrals of the closed form, must give the closed-form time signal
+    through vf.time_response.  A flipped exponent (e^{-a t}) grows like
+    e^{1.15 t} and fails."""
+    poles = np.array([0.0, complex(-2 / np.sqrt(3), np.sqrt(8 / 3)), complex(-2 / np.sqrt(3), -np.sqrt(8 / 3))])
+    res = np.array([_contour_residue(analytic.cavity_ur, a) for a in poles])
+    # the three terms are the whole function (strictly proper, no other poles)
+    s = np.array([0.3 + 0.1j, 1.0 - 2.0j, 0.05 + 7.0j, 4.0 + 0.0j])
+    assert np.max(np.abs(vf.evaluate(s, poles, res[None])[0] - analytic.cavity_ur(s))) < 1e-12
+    t = np.linspace(0.0, 15.0, 301)
+    h = vf.time_response(t, poles, res[None])[0]
+    assert np.max(np.abs(h - analytic.cavity_ur_time(t))) < 1e-12
+
+
+def test_time_response_against_fsm_inversion_of_the_model():
+    """Eq. 6 against the Fourier-series inversion (Eq. 4, the oracle's direct
+    trapezoidal sum) of the same rational model sampled on a fine FSM grid.
+    Residues chosen so that h(0) = 0 (no jump at t = 0, spectrum ~ 1/w^2);
+    the bound is the FSM's own discretisation error at Ns = 8192, P = 40,
+    kappa = 6 (measured 3e-5 of the signal's peak)."""
+    a1, a2, a3 = complex(-0.5, 1.0), complex(-0.4, 2.5), -1.0
+    r1, r2 = complex(0.7, -0.3), complex(-0.2, 0.9)
+    poles = np.array([a1, np.conj(a1), a2, np.conj(a2), a3])
+    res = np.array([[r1, np.conj(r1), r2, np.conj(r2), -2 * (r1.real + r2.real)]])
+    P, Ns = 40.0, 8192
+    eta = 6 * np.log(10) / P
+    s = fsm.grid(P, eta, Ns)
+    t = np.linspace(0.5, 15.0, 117)
+    h_fsm = fsm.invert_direct(P, eta, Ns, vf.evaluate(s, poles, res), t)[0]
+    h = vf.time_response(t, poles, res)[0]
+    scale = np.max(np.abs(h))
+    assert np.max(np.abs(h - h_fsm)) < 2e-4 * scale
+
+
+def test_fit_discrepancy_and_E2_closed_form():
+    """Eq. 8 and Eq. 13 on one-pole fits: f_H = c/(s + al), f_L = c/(s + be)
+    with real al, be > 0 and |c| = 1 on s = eta + i w, w in [0, Omega] (the
+    grid holds w = 0): |f_H - f_L| = |be - al| / (|s + al||s + be|) and |f_H|
+    both peak at w = 0, so e = |be - al| / (eta + be) exactly.  E2 is the
+    largest e over the functions."""
+    eta, omega = 0.05, 6.0
+    sg = eta + 1j * np.linspace(0.0, omega, 2048)
+    al = np.array([0.3, 1.0, 0.1])
+    be = np.array([0.45, 0.9, 0.4])
+    c = np.exp(1j * np.array([0.2, -1.3, 2.9]))
+    fH = c[:, None] / (sg[None, :] + al[:, None])
+    fL = c[:, None] / (sg[None, :] + be[:, None])
+    e = oafs.fit_discrepancy(fH, fL)
+    want = np.abs(be - al) / (eta + be)
+    assert np.max(np.abs(e - want)) < 1e-14
+    assert abs(oafs.stop_E2(e) - np.max(want)) < 1e-14
+    assert np.argmax(want) == 2 and want[2] > 2 * want[0]  # the max, not a mean, of distinct values
+
+
+def test_E1_closed_form():
+    """Eq. 12 on one-term time responses: current c_k e^{-a_k t}, previous
+    d_k e^{-b_k t}; with I(x) = (1 - e^{-x T}) / x,
+    E1 = max_k [c^2 I(2a) - 2 c d I(a+b) + d^2 I(2b)] / [c^2 I(2a)].
+    Composite Simpson on 4 Ns + 1 points (Ns = 512) is within 1e-9 of it.
+    Step 0 (no previous response) gives +infinity."""
+    T, Ns = 20.0, 512
+    t = np.linspace(0.0, T, 4 * Ns + 1)
+    a = np.array([0.5, 0.2, 0.35])
+    b = np.array([0.45, 0.25, 0.3])
+    c = np.array([1.0, -2.0, 0.7])
+    d = np.array([0.9, -2.1, 0.8])
+    cur = c[:, None] * np.exp(-a[:, None] * t)
+    prev = d[:, None] * np.exp(-b[:, None] * t)
+    integ = lambda x: (1 - np.exp(-x * T)) / x
+    ratio = (c * c * integ(2 * a) - 2 * c * d * integ(a + b) + d * d * integ(2 * b)) / (c * c * integ(2 * a))
+    assert np.argmax(ratio) == 2 and ratio[2] > 1.5 * ratio[0]
+    assert abs(oafs.stop_E1(cur, prev, t) - np.max(ratio)) < 1e-9 * np.max(ratio)
+    assert np.isinf(oafs.stop_E1(cur, None, t))
+    # not symmetric in the two steps: the current response is the denominator
+    swapped = (d * d * integ(2 * b) - 2 * c * d * integ(a + b) + c * c * integ(2 * a)) / (d * d * integ(2 * b))
+    assert abs(np.max(swapped) - np.max(ratio)) > 1e-3 * np.max(ratio)
+
+
+def _few_pole_mock():
+    """A response with 3 poles: every fit of order >= 3 is exact, so E1 and E2
+    pass from the second analysis on."""
+    poles = np.array([complex(-0.1, 1.3), complex(-0.1, -1.3), -0.4])
+    res = np.array([[complex(1.0, 0.5), complex(1.0, -0.5), 0.3], [complex(-0.2, 0.8), complex(-0.2, -0.8), 1.1]])
+    return poles, res
+
+
+@pytest.mark.parametrize("impl", ["oracle", "library"])
+def test_afs_cap_inside_validation_is_not_converged(impl):
+    """Eq. 14 needs all Jc validation steps: a cap that cuts them short ends
+    the run unconverged (and capped); with room for them it converges."""
+    poles, res = _few_pole_mock()
+    T, Ns, J0 = 40.0, 128, 8
+    eta = 3 * np.log(10) / T
+
+    def resp(s):
+        return vf.evaluate(np.asarray(s), poles, res).T
+
+    for cap, want in ((J0 + 1, False), (J0 + 2, False), (J0 + 3, False), (J0 + 30, True)):
+        if impl == "oracle":
+            out = oafs.run(resp, 2, 2, T, eta, Ns, J0=J0, max_Nc=cap)
+            E1, E2 = out["history"]["E1"], out["history"]["E2"]
+        else:
+            out = _lib().afs_run(resp, 2, 2, _lib().afs_params(T, eta, Ns, J0=J0, max_Nc=cap))
+            E1, E2 = out["E1"], out["E2"]
+        assert out["converged"] == want, (cap, out["Nc"])
+        assert out["capped"] == (not want)
+        if want:
+            # the analysis that first passed, then Jc = 3 passing validation steps
+            assert all(e1 < 1e-4 and e2 < 2e-3 for e1, e2 in zip(E1[-4:], E2[-4:]))
+            assert out["Nc"] == J0 + 4
+        else:
+            assert out["Nc"] == cap

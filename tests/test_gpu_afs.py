@@ -132,3 +132,24 @@ def test_afs_model_warm_start_same_samples_fewer_products():
     n_adaptive = z["Nc"] - 16
     for name in ("nearest", "model"):
         assert runs[name]["matvecs"] <= z["matvecs"] + n_adaptive + 16
+
+
+def test_afs_counts_samples_that_missed_the_tolerance():
+    """Solves capped at two products miss tol = 1e-10: their best iterates are
+    still sampled, but the run reports them (every sample, the worst FP64
+    residual) and does not call itself converged."""
+    import paper_1511_04355_amd as afs
+    mesh = mg.cavity(2)
+    T, Ns, eta = 20.0, 64, 0.25
+    rng = np.random.default_rng(5)
+    dofs = np.sort(rng.choice(3 * mesh.n_tri, 6, replace=False))
+    P = afs.Problem.from_mesh(mesh)
+    params = afs.afs_params(T, eta, Ns, max_Nc=20)
+    out = P.afs(params, mesh.bc_shape, dofs, 4, load_kind=0, opts=afs.SolveOptions(tol=1e-10, max_iter=2))
+    print(f"[afs capped solves] Nc={out['Nc']} unconverged={out['unconverged_solves']} "
+          f"worst={out['worst_rel_res']:.2e}", flush=True)
+    assert not out["converged"]
+    assert out["unconverged_solves"] == out["Nc"]
+    assert out["worst_rel_res"] > 1e-10
+    good = P.afs(params, mesh.bc_shape, dofs, 4, load_kind=0, opts=afs.SolveOptions(tol=1e-10))
+    assert good["unconverged_solves"] == 0 and good["worst_rel_res"] <= 1e-10
