@@ -59,7 +59,10 @@ def test_afs_multipoint_on_gpu_matches_oracle_afs(warm):
     """Three new frequencies per analysis step, solved in one call with one
     start per frequency (the nearest sample's solution, or the current model's
     prediction): the same samples as the oracle AFS with q = 3 on the oracle's
-    LU solves, the same time response, and fewer analysis steps than q = 1."""
+    LU solves, the same stopping outcome (on this band q = 3 reaches the
+    Ns/2 + 1 sample cap before its Jc validation steps are complete, Eq. 14:
+    capped, not converged, on both sides), the same time response, and fewer
+    analysis steps than q = 1."""
     import paper_1511_04355_amd as afs
     from oracle import afs as oafs
     from oracle import bem, vf
@@ -77,7 +80,8 @@ def test_afs_multipoint_on_gpu_matches_oracle_afs(warm):
                 opts=afs.SolveOptions(tol=1e-10, warm_start=ws))
     print(f"[afs q=3 {warm}] Nc={out['Nc']} steps={len(out['E1'])} (q=1: Nc={one['Nc']} steps={len(one['E1'])})",
           flush=True)
-    assert out["converged"] and out["Nc"] <= Ns // 2 + 1
+    assert out["Nc"] <= Ns // 2 + 1
+    assert out["converged"] or (out["capped"] and out["Nc"] == Ns // 2 + 1)
     assert len(out["E1"]) < len(one["E1"])
     cache = {}
 
@@ -92,7 +96,7 @@ def test_afs_multipoint_on_gpu_matches_oracle_afs(warm):
         return np.array(rows)
 
     o = oafs.run(resp, K, len(dofs), T, eta, Ns, q=3)
-    assert o["converged"]
+    assert (o["converged"], o["capped"]) == (out["converged"], out["capped"])
     n = min(len(o["s"]), len(out["s"]), 25)
     assert np.max(np.abs(out["s"][:n] - o["s"][:n])) < 1e-9
     assert np.max(np.abs(out["F"][:n] - o["F"][:n])) <= 1e-7 * np.max(np.abs(o["F"][:n]))
