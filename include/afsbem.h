@@ -153,6 +153,7 @@ int afsbem_assemble_device(afsbem_problem *p, double s_re, double s_im, const vo
 int afsbem_matvec_device(afsbem_problem *p, int format, int precision, const void *d_A,
                          const void *d_A_lo, const void *d_x, void *d_y, void *hip_stream);
 
+
 /* Matrix-free product at one s (Eq. 2 without a stored matrix): the far-field
  * rule is evaluated on the fly for every pair m != n (precision 0: FP64;
  * 1: FP32 evaluation with FP64 sums over sources) and the near-pair
@@ -237,11 +238,16 @@ enum { AFSBEM_PREC_FP64 = 0, AFSBEM_PREC_MIXED = 1 };
  * discards every inner correction. */
 enum { AFSBEM_FAULT_NAN_START = 1, AFSBEM_FAULT_STALL_INNER = 2 };
 enum { AFSBEM_WARM_NONE = 0, AFSBEM_WARM_PREV = 1, AFSBEM_WARM_USER = 2, AFSBEM_WARM_LEARNED = 3,
-       AFSBEM_WARM_MODEL = 4 /* afsbem_afs_run_problem only, see there */, AFSBEM_WARM_EXTRAP = 5 };
+       AFSBEM_WARM_MODEL = 4 /* afsbem_afs_run_problem only, see there */, AFSBEM_WARM_EXTRAP = 5,
+       /* zero start; the caller's vector of each frequency (d_x0) augments the search space of the
+          first GMRES cycle, as the network's prediction does with learn_aug = 1 */
+       AFSBEM_WARM_USER_AUG = 6 };
 
 typedef struct {
     double tol;          /* target FP64 true relative residual ||b - A x|| / ||b|| (1e-6) */
-    int32_t restart;     /* GMRES restart length m (50) */
+    int32_t restart;     /* GMRES restart length m (50; afsbem_solve_device and afsbem_solve take up
+                            to 4000, the batched solve 500); the basis holds (m + 1) N complex
+                            doubles of device memory */
     int32_t max_iter;    /* cap on matrix-vector products per frequency (1000) */
     int32_t precision;   /* AFSBEM_PREC_FP64 or AFSBEM_PREC_MIXED */
     int32_t warm_start;  /* AFSBEM_WARM_* */
@@ -276,6 +282,12 @@ typedef struct {
     double hmat_eps;     /* matrix_free = 2: relative accuracy of each low-rank block (0: 1e-5) */
     double hmat_eta;     /* matrix_free = 2: admissibility, separation >= hmat_eta x the larger
                             cluster radius (0: 1.0) */
+    int32_t learn_aug;   /* AFSBEM_WARM_LEARNED: role of the network's prediction.  0: it enters
+                            the starting iterate (residual-minimising combination with the
+                            previous solution); 1: it augments the search space of the first
+                            GMRES cycle instead (flexible form, coefficient from the same
+                            least-squares problem; the start is the previous solution); 2: both */
+    int32_t reserved_;   /* 0 */
 } afsbem_solve_opts;
 
 typedef struct {
@@ -375,6 +387,15 @@ int afsbem_mlp_loss_grad(int32_t d_in, int32_t hidden, int32_t d_out, int32_t n,
 /* One Adam step (step counter t >= 1) in place on d_params with moments d_m, d_v. */
 int afsbem_mlp_adam(int64_t n_params, float *d_params, const float *d_grad, float *d_m, float *d_v, int32_t t,
                     float lr, float beta1, float beta2, float eps, void *hip_stream);
+/* One training step on the matrix cores (mode 1 arithmetic): loss and
+ * gradient of mean((Y - T)^2) over the n rows of d_X / d_T, then the Adam step
+ * t (>= 1) in place on d_params with moments d_m, d_v; the gradient planes of
+ * the batch split are added and applied in one pass (the full gradient is not
+ * stored).  d_loss (nullable): one float, the loss before the step.  Work
+ * memory comes from the stream-ordered allocator. */
+int afsbem_mlp_train_step(int32_t d_in, int32_t hidden, int32_t d_out, int32_t n, float *d_params,
+                          const float *d_X, const float *d_T, float *d_m, float *d_v, int32_t t, float lr,
+                          float beta1, float beta2, float eps, float *d_loss, void *hip_stream);
 
 /* ===================================================================== drivers
  * Host-side frequency-domain drivers on top of the solve.  Complex arrays are

@@ -17,6 +17,7 @@ from ._lib import (  # noqa: F401
     WARM_LEARNED,
     WARM_MODEL,
     WARM_EXTRAP,
+    WARM_USER_AUG,
     Problem,
     SolveOptions,
     solve_batched,

@@ -19,7 +19,7 @@ _lib = None
 OK, EINVAL, ENOMEM, EDEVICE, ENOCONV, EBREAKDOWN, ENAN = 0, -1, -2, -3, -4, -5, -6
 FMT_C128, FMT_SPLIT = 0, 1
 PREC_FP64, PREC_MIXED = 0, 1
-WARM_NONE, WARM_PREV, WARM_USER, WARM_LEARNED, WARM_MODEL, WARM_EXTRAP = 0, 1, 2, 3, 4, 5
+WARM_NONE, WARM_PREV, WARM_USER, WARM_LEARNED, WARM_MODEL, WARM_EXTRAP, WARM_USER_AUG = 0, 1, 2, 3, 4, 5, 6
 
 
 class AfsbemError(RuntimeError):
@@ -42,7 +42,8 @@ class _Opts(ctypes.Structure):
                 ("precision", ctypes.c_int32), ("warm_start", ctypes.c_int32), ("inner_tol", ctypes.c_double),
                 ("batch", ctypes.c_int32), ("fault_inject", ctypes.c_uint32), ("profile", ctypes.c_int32),
                 ("learn_steps", ctypes.c_int32), ("precond", ctypes.c_int32), ("matrix_free", ctypes.c_int32),
-                ("no_graph", ctypes.c_int32), ("hmat_eps", ctypes.c_double), ("hmat_eta", ctypes.c_double)]
+                ("no_graph", ctypes.c_int32), ("hmat_eps", ctypes.c_double), ("hmat_eta", ctypes.c_double),
+                ("learn_aug", ctypes.c_int32), ("reserved_", ctypes.c_int32)]
 
 
 class _Stats(ctypes.Structure):
@@ -105,6 +106,8 @@ def lib():
         L.afsbem_mlp_loss_grad.argtypes = [i32, i32, i32, i32, P, P, P, P, P, ctypes.c_int, P]
         L.afsbem_mlp_adam.argtypes = [i64, P, P, P, P, i32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                       ctypes.c_float, P]
+        L.afsbem_mlp_train_step.argtypes = [i32, i32, i32, i32, P, P, P, P, P, i32, ctypes.c_float,
+                                            ctypes.c_float, ctypes.c_float, ctypes.c_float, P, P]
         L.afsbem_fsm_grid.argtypes = [d, d, i32, P]
         L.afsbem_fsm_invert.argtypes = [d, d, i32, ctypes.c_int, i64, P, P]
         L.afsbem_vf_fit.argtypes = [i32, P, i32, P, i32, P, i32, d, P, P, P]
@@ -168,11 +171,12 @@ class SolveOptions:
     no_graph: int = 0
     hmat_eps: float = 0.0
     hmat_eta: float = 0.0
+    learn_aug: int = 0
 
     def _c(self):
         return _Opts(self.tol, self.restart, self.max_iter, self.precision, self.warm_start, self.inner_tol,
                      self.batch, self.fault_inject, self.profile, self.learn_steps, self.precond, self.matrix_free,
-                     self.no_graph, self.hmat_eps, self.hmat_eta)
+                     self.no_graph, self.hmat_eps, self.hmat_eta, self.learn_aug, 0)
 
 
 class Problem:
@@ -639,6 +643,17 @@ def mlp_loss_grad(params, X, T, d_in, hidden, d_out, mode=1):
     _check(lib().afsbem_mlp_loss_grad(d_in, hidden, d_out, X.shape[0], _ptr(params), _ptr(X), _ptr(T), _ptr(G),
                                       _ptr(loss), int(mode), _stream()))
     return loss, G
+
+
+def mlp_train_step(params, X, T, m, v, t, d_in, hidden, d_out, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+    """One bf16 matrix-core training step (loss, gradient, Adam) in place on
+    params, m, v.  Returns the loss before the step (cuda scalar)."""
+    import torch
+    X, T = X.contiguous(), T.contiguous()
+    loss = torch.empty(1, dtype=torch.float32, device="cuda")
+    _check(lib().afsbem_mlp_train_step(d_in, hidden, d_out, X.shape[0], _ptr(params), _ptr(X), _ptr(T), _ptr(m),
+                                       _ptr(v), int(t), lr, beta1, beta2, eps, _ptr(loss), _stream()))
+    return loss
 
 
 def mlp_adam(params, grad, m, v, t, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):

@@ -532,6 +532,23 @@ int afsbem_mlp_adam(int64_t n_params, float *d_params, const float *d_grad, floa
     });
 }
 
+int afsbem_mlp_train_step(int32_t d_in, int32_t hidden, int32_t d_out, int32_t n, float *d_params, const float *d_X,
+                          const float *d_T, float *d_m, float *d_v, int32_t t, float lr, float beta1, float beta2,
+                          float eps, float *d_loss, void *hip_stream) {
+    return guarded([&] {
+        AFS_REQUIRE(d_in >= 1 && hidden >= 1 && d_out >= 1 && n >= 1, AFSBEM_EINVAL, "bad MLP shape");
+        AFS_REQUIRE(d_params && d_X && d_T && d_m && d_v && t >= 1, AFSBEM_EINVAL, "bad training arguments");
+        hipStream_t st = static_cast<hipStream_t>(hip_stream);
+        MlpShape s(d_in, hidden, d_out);
+        void *work = nullptr;
+        AFS_HIP(hipMallocAsync(&work, mlp_work_floats(s, n) * 4, st));
+        mlp_train_step(s, n, d_params, d_X, d_T, d_m, d_v, t, lr, beta1, beta2, eps, d_loss,
+                       static_cast<float *>(work), st);
+        AFS_HIP(hipFreeAsync(work, st));
+        return AFSBEM_OK;
+    });
+}
+
 int afsbem_problem_clusters(const afsbem_problem *p, int64_t *n_clusters, int64_t *ptr_out, int32_t *elem_out) {
     return guarded([&] {
         AFS_REQUIRE(p && n_clusters, AFSBEM_EINVAL, "null pointer argument");
@@ -594,13 +611,15 @@ int afsbem_solve_device(afsbem_problem *p, int32_t n_s, const double *s, const v
         afsbem_solve_opts_default(&o);
         if (opts)
             o = *opts;
-        AFS_REQUIRE(o.tol > 0 && o.restart >= 1 && o.restart <= 500 && o.max_iter >= 1, AFSBEM_EINVAL,
+        AFS_REQUIRE(o.tol > 0 && o.restart >= 1 && o.restart <= 4000 && o.max_iter >= 1, AFSBEM_EINVAL,
                     "invalid solver options");
+        AFS_REQUIRE(o.learn_aug >= 0 && o.learn_aug <= 2, AFSBEM_EINVAL, "learn_aug must be 0, 1 or 2");
         AFS_REQUIRE(o.precision == AFSBEM_PREC_FP64 || o.precision == AFSBEM_PREC_MIXED, AFSBEM_EINVAL,
                     "unknown precision");
-        AFS_REQUIRE(o.warm_start != AFSBEM_WARM_USER || d_x0, AFSBEM_EINVAL, "user warm start needs x0");
+        AFS_REQUIRE((o.warm_start != AFSBEM_WARM_USER && o.warm_start != AFSBEM_WARM_USER_AUG) || d_x0,
+                    AFSBEM_EINVAL, "user warm start needs x0");
         AFS_REQUIRE((o.warm_start >= AFSBEM_WARM_NONE && o.warm_start <= AFSBEM_WARM_LEARNED) ||
-                        o.warm_start == AFSBEM_WARM_EXTRAP,
+                        o.warm_start == AFSBEM_WARM_EXTRAP || o.warm_start == AFSBEM_WARM_USER_AUG,
                     AFSBEM_EINVAL, "unknown warm start");
         AFS_REQUIRE(o.precond == 0 || o.precond == 1, AFSBEM_EINVAL, "precond must be 0 or 1");
         AFS_REQUIRE(o.matrix_free >= 0 && o.matrix_free <= 2, AFSBEM_EINVAL, "matrix_free must be 0, 1 or 2");

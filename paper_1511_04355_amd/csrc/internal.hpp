@@ -210,8 +210,8 @@ void vec_sub(int64_t N, const double *a, const double *b, double *out, hipStream
 // out = alpha x + beta y (complex scalars passed by value; out may alias)
 void vec_axpby(int64_t N, double ar, double ai, const double *x, double br, double bi, const double *y, double *out,
                hipStream_t st);
-// Multi-dot: out[i] = sum_r conj(V_i[r]) w[r], i < nv <= kMdotMaxVectors; V
-// rows strided by ldv.  partial: mdot_scratch_bytes(N, nv_max) bytes whose
+// Multi-dot: out[i] = sum_r conj(V_i[r]) w[r], i < nv (one launch per
+// kMdotMaxVectors vectors); V rows strided by ldv.  partial: mdot_scratch_bytes(N, nv_max) bytes whose
 // first kMdotCounterBytes are zero when allocated (arrival counters, left
 // zero by every call).
 constexpr int kMdotMaxVectors = 512;

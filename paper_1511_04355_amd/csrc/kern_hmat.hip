@@ -536,12 +536,17 @@ void hmat_setup(const Problem &p, Workspace &ws, const KernelParams &kp, double 
 
 bool hmat_finish(const Problem &p, Workspace &ws) {
     const int64_t nl = (int64_t)p.hmat->lowrank.size() / 4;
+    const std::vector<int64_t> &lr = p.hmat->lowrank;
     ws.hm_max_rank = 0;
     bool ok = true;
+    // bytes one product streams: the dense blocks and every term's U and V (FP32 complex)
+    double entries = (double)p.hmat->dense_off.back();
     for (int64_t l = 0; l < nl; ++l) {
         ws.hm_max_rank = std::max(ws.hm_max_rank, ws.hm_host[l]);
         ok = ok && ws.hm_host[nl + l] == 0;
+        entries += (double)ws.hm_host[l] * 3.0 * (double)((lr[4 * l + 1] - lr[4 * l]) + (lr[4 * l + 3] - lr[4 * l + 2]));
     }
+    ws.hm_bytes = entries * 8.0;
     ws.hm_ok = ok;
     return ok;
 }

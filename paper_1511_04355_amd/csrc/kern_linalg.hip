@@ -394,19 +394,24 @@ __global__ __launch_bounds__(256) void mdot_kernel(int64_t N, const double2 *__r
 }
 
 size_t mdot_scratch_bytes(int64_t N, int nv_max) {
-    return (size_t)kMdotCounterBytes + (size_t)mdot_blocks(N) * nv_max * 16;
+    return (size_t)kMdotCounterBytes + (size_t)mdot_blocks(N) * std::min(nv_max, kMdotMaxVectors) * 16;
 }
 
+// more than kMdotMaxVectors vectors: consecutive launches over groups of them
+// (stream-ordered, so the groups reuse the same partials and counters)
 void vec_mdot(int64_t N, int nv, const double *V, int64_t ldv, const double *w, double *partial, double *out,
               hipStream_t st) {
     const int B = mdot_blocks(N);
-    AFS_REQUIRE(nv >= 1 && nv <= kMdotMaxVectors, AFSBEM_EINVAL, "multi-dot: too many vectors");
+    AFS_REQUIRE(nv >= 1, AFSBEM_EINVAL, "multi-dot: no vectors");
     unsigned *counter = reinterpret_cast<unsigned *>(partial);
     double2 *part = reinterpret_cast<double2 *>(reinterpret_cast<char *>(partial) + kMdotCounterBytes);
-    mdot_kernel<<<dim3(B, nv), 256, 0, st>>>(N, reinterpret_cast<const double2 *>(V), ldv,
-                                             reinterpret_cast<const double2 *>(w), B, part, counter,
-                                             reinterpret_cast<double2 *>(out));
-    AFS_HIP(hipGetLastError());
+    for (int c0 = 0; c0 < nv; c0 += kMdotMaxVectors) {
+        const int nc = std::min(kMdotMaxVectors, nv - c0);
+        mdot_kernel<<<dim3(B, nc), 256, 0, st>>>(N, reinterpret_cast<const double2 *>(V) + (int64_t)c0 * ldv, ldv,
+                                                 reinterpret_cast<const double2 *>(w), B, part, counter,
+                                                 reinterpret_cast<double2 *>(out) + c0);
+        AFS_HIP(hipGetLastError());
+    }
 }
 
 // w -= sum_i h_i V_i   (sign = -1)   or   x += sum_i y_i V_i   (sign = +1)

@@ -156,9 +156,8 @@ void LearnState::train(int steps, hipStream_t st) {
             X = Xb;
             T = Tb;
         }
-        mlp_loss_grad(shape, 1, B, P, X, T, G, loss, work, st);
         ++t;
-        mlp_adam(shape.n_params, P, G, m, v, t, 1e-3f, 0.9f, 0.999f, 1e-8f, st);
+        mlp_train_step(shape, B, P, X, T, m, v, t, 1e-3f, 0.9f, 0.999f, 1e-8f, loss, work, st);
     }
 }
 

@@ -20,6 +20,10 @@ void mlp_loss_grad(const MlpShape &s, int mode, int n, const float *P, const flo
                    float *loss, float *work, hipStream_t st);
 void mlp_adam(int64_t n, float *P, const float *G, float *m, float *v, int t, float lr, float b1, float b2, float eps,
               hipStream_t st);
+// one training step in mode 1: loss gradient and the Adam update of P (m, v
+// its moments, t the step count from 1); the full gradient is never stored
+void mlp_train_step(const MlpShape &s, int n, float *P, const float *X, const float *T, float *m, float *v, int t,
+                    float lr, float b1, float b2, float eps, float *loss, float *work, hipStream_t st);
 
 // ----------------------------------------------------- learned warm start --
 constexpr int kLearnFeatures = 32;

@@ -86,7 +86,7 @@ void Workspace::release() {
     hm_release();
     for (void *p : {(void *)A, (void *)A_lo, (void *)nearblk, (void *)selfblk, (void *)b, (void *)precond, (void *)asm_scratch, (void *)gemv_partial,
                     (void *)V, (void *)w, (void *)z, (void *)x, (void *)r, (void *)tmp, (void *)rin, (void *)xo,
-                    (void *)xstart,
+                    (void *)xstart, (void *)aug,
                     (void *)dots_partial, (void *)small, (void *)one, (void *)clinv, (void *)clgath})
         if (p)
             (void)hipFree(p);
@@ -110,7 +110,7 @@ void Workspace::release() {
     m = 0;
     A = A_lo = asm_scratch = nullptr;
     nearblk = selfblk = nullptr;
-    b = precond = gemv_partial = V = w = z = x = r = tmp = rin = xo = xstart = nullptr;
+    b = precond = gemv_partial = V = w = z = x = r = tmp = rin = xo = xstart = aug = nullptr;
     dots_partial = small = one = host_small = nullptr;
     clinv = clgath = nullptr;
     prec_kind = 0;
@@ -160,7 +160,7 @@ void Workspace::ensure(const Problem &p, int format, int restart_m, int prec) {
     precond = (double *)dalloc((size_t)nt * 9 * 16);
     asm_scratch = dalloc(assembly_scratch_bytes(p));
     gemv_partial = (double *)dalloc((size_t)(format == kFmtBlocks ? mf_chunks(nt) : gemv_chunks(N)) * N * 16);
-    V = (double *)dalloc((size_t)(restart_m + 1) * N * 16);
+    V = (double *)dalloc((size_t)(restart_m + 2) * N * 16);  // [c,] v_0..v_m
     w = (double *)dalloc((size_t)N * 16);
     z = (double *)dalloc((size_t)N * 16);
     x = (double *)dalloc((size_t)N * 16);
@@ -169,6 +169,7 @@ void Workspace::ensure(const Problem &p, int format, int restart_m, int prec) {
     rin = (double *)dalloc((size_t)N * 16);
     xo = (double *)dalloc((size_t)N * 16);
     xstart = (double *)dalloc((size_t)N * 16);
+    aug = (double *)dalloc((size_t)N * 16);
     dots_partial = (double *)dalloc(mdot_scratch_bytes(N, restart_m + 2));
     AFS_HIP(hipMemset(dots_partial, 0, kMdotCounterBytes));  // arrival counters
     small = (double *)dalloc((size_t)(4 * (restart_m + 2)) * 16);
@@ -199,14 +200,16 @@ void Operator::apply(const double *xin, double *yout, hipStream_t st) const {
     if (format == kFmtBlocks) {
         if (eb)
             AFS_HIP(hipEventRecord(eb, st));
-        if (precision == 1 && hm && hm->hm_ok)
+        const bool hier = precision == 1 && hm && hm->hm_ok;
+        if (hier)
             hmat_apply(*prob, *hm, xin, yout, st);
         else
             mf_apply(*prob, kp, precision, 0, nearblk, selfblk, xin, yout, partial, st);
         if (ee)
             AFS_HIP(hipEventRecord(ee, st));
         ++*counter;
-        *bytes += (double)(prob->dev.nnz + prob->dev.n_tri) * 144.0;
+        // stored bytes read: the hierarchical form, or the near and self blocks
+        *bytes += hier ? hm->hm_bytes : (double)(prob->dev.nnz + prob->dev.n_tri) * 144.0;
         return;
     }
     launch_gemv(N, format, precision, A, A_lo, xin, yout, partial, st, eb, ee);
@@ -229,15 +232,20 @@ static void residual(const Operator &op, Workspace &ws, const double *b, const d
 
 GmresResult gmres(const Operator &op, Workspace &ws, int64_t /*n_tri*/, const double *rhs, double rhs_norm,
                   double *x, bool x_is_zero, double tol_abs, int restart, int max_iter, hipStream_t st,
-                  bool verify, const double *r0, double r0_norm) {
+                  bool verify, const double *r0, double r0_norm, const double *aug) {
     const int64_t N = op.N;
     GmresResult res;
-    std::vector<cplx> Hm((size_t)(restart + 1) * restart), g(restart + 1), cs(restart), sn(restart);
-    double *hbuf = ws.small;            // device: h1 [0..j], h2 [restart+2 ..], nrm2
-    double *h2 = ws.small + 2 * (restart + 2);
-    double *nrm = ws.small + 4 * (restart + 2);
+    // Hessenberg columns packed one after another (column j holds rows 0..j+1),
+    // grown as the cycle proceeds: long restarts pay only for the columns used
+    std::vector<cplx> Hm, Bc, g(restart + 1), cs(restart), sn(restart);
+    auto hix = [](int i, int j) { return (size_t)j * (size_t)(j + 3) / 2 + (size_t)i; };
+    // basis slot 0 holds c = A aug / |A aug| in an augmented cycle; the Krylov
+    // vectors v_0, v_1, ... follow it, so that one multi-dot covers [c, V]
+    double *const Cv = ws.V;
+    double *const Vk = ws.V + 2 * N;
+    double *hbuf = ws.small;            // device: first-pass dots, then y
+    double *h2 = ws.small + 2 * (restart + 2);  // second-pass dots, then ||w||^2
     double *host = ws.host_small;
-    (void)nrm;
     // initial residual
     double beta;
     if (x_is_zero) {
@@ -252,6 +260,41 @@ GmresResult gmres(const Operator &op, Workspace &ws, int64_t /*n_tri*/, const do
         beta = norm2_dev(ws, N, ws.r, st);
     }
     res.est = beta;
+    // Augmentation (first cycle): u = aug / gamma with c = A u of unit norm;
+    // the start takes the residual-optimal multiple of u (x += u c^H r,
+    // r -= c c^H r), and the cycle's Arnoldi vectors are kept orthogonal to
+    // c, the projections b_j = c^H A M^-1 v_j recorded, so that the cycle
+    // minimises the residual over x + span{u} + M^-1 K (projected operator);
+    // the update then subtracts u B y.
+    bool augc = false;
+    double gamma = 0.0;
+    if (aug && beta > tol_abs && res.iters < max_iter) {
+        op.apply(aug, ws.w, st);
+        ++res.iters;
+        vec_mdot(N, 1, ws.w, N, ws.w, ws.dots_partial, ws.small, st);
+        vec_mdot(N, 1, ws.w, N, ws.r, ws.dots_partial, ws.small + 2, st);
+        AFS_HIP(hipMemcpyAsync(host, ws.small, 32, hipMemcpyDeviceToHost, st));
+        AFS_HIP(hipStreamSynchronize(st));
+        const double g2 = host[0];
+        const cplx wr(host[2], host[3]);
+        if (g2 > 0.0 && std::isfinite(g2) && std::isfinite(wr.real()) && std::isfinite(wr.imag())) {
+            gamma = std::sqrt(g2);
+            const cplx alpha = wr / g2;  // coefficient of aug
+            vec_normalize(N, ws.small, ws.w, Cv, st);  // c (device ||w||^2 at small[0])
+            if (x_is_zero) {
+                vec_axpby(N, alpha.real(), alpha.imag(), aug, 0.0, 0.0, aug, x, st);
+                x_is_zero = false;
+            } else {
+                vec_axpby(N, 1.0, 0.0, x, alpha.real(), alpha.imag(), aug, x, st);
+            }
+            vec_axpby(N, 1.0, 0.0, ws.r, -alpha.real(), -alpha.imag(), ws.w, ws.r, st);
+            const double b_new = norm2_dev(ws, N, ws.r, st);
+            res.aug_gain = b_new > 0.0 ? beta / b_new : 1e30;
+            beta = b_new;
+            res.est = beta;
+            augc = true;
+        }
+    }
     if (x_is_zero && (!(beta > tol_abs) || res.iters >= max_iter))
         AFS_HIP(hipMemsetAsync(x, 0, (size_t)N * 16, st));  // leave a valid (zero) iterate
     while (true) {
@@ -265,43 +308,51 @@ GmresResult gmres(const Operator &op, Workspace &ws, int64_t /*n_tri*/, const do
         // V_0 = r / beta
         host[0] = beta * beta;
         AFS_HIP(hipMemcpyAsync(ws.small + 4 * (restart + 2) + 2, host, 8, hipMemcpyHostToDevice, st));
-        vec_normalize(N, ws.small + 4 * (restart + 2) + 2, ws.r, ws.V, st);
+        vec_normalize(N, ws.small + 4 * (restart + 2) + 2, ws.r, Vk, st);
         std::fill(g.begin(), g.end(), cplx(0));
         g[0] = beta;
+        Bc.clear();
         int k = 0;
+        const int e = augc ? 1 : 0;          // leading vectors of the multi-dot besides V
+        double *const Vd = augc ? Cv : Vk;   // [c,] v_0, v_1, ...
         for (int j = 0; j < restart; ++j) {
-            double *vj = ws.V + 2 * (int64_t)j * N;
+            double *vj = Vk + 2 * (int64_t)j * N;
             ws.apply_precond(vj, ws.z, st);
             op.apply(ws.z, ws.w, st);
-            // classical Gram-Schmidt, twice
-            vec_mdot(N, j + 1, ws.V, N, ws.w, ws.dots_partial, hbuf, st);
-            vec_mupdate(N, j + 1, ws.V, N, hbuf, ws.w, st);
-            vec_mdot(N, j + 1, ws.V, N, ws.w, ws.dots_partial, h2, st);
-            vec_mupdate(N, j + 1, ws.V, N, h2, ws.w, st);
-            vec_mdot(N, 1, ws.w, N, ws.w, ws.dots_partial, h2 + 2 * (j + 1), st);
-            AFS_HIP(hipMemcpyAsync(host, hbuf, (size_t)(j + 1) * 16, hipMemcpyDeviceToHost, st));
-            AFS_HIP(hipMemcpyAsync(host + 2 * (restart + 2), h2, (size_t)(j + 2) * 16, hipMemcpyDeviceToHost, st));
+            // classical Gram-Schmidt, twice, against [c,] v_0..v_j
+            const int nv = j + 1 + e;
+            vec_mdot(N, nv, Vd, N, ws.w, ws.dots_partial, hbuf, st);
+            vec_mupdate(N, nv, Vd, N, hbuf, ws.w, st);
+            vec_mdot(N, nv, Vd, N, ws.w, ws.dots_partial, h2, st);
+            vec_mupdate(N, nv, Vd, N, h2, ws.w, st);
+            vec_mdot(N, 1, ws.w, N, ws.w, ws.dots_partial, h2 + 2 * nv, st);
+            AFS_HIP(hipMemcpyAsync(host, hbuf, (size_t)nv * 16, hipMemcpyDeviceToHost, st));
+            AFS_HIP(hipMemcpyAsync(host + 2 * (restart + 2), h2, (size_t)(nv + 1) * 16, hipMemcpyDeviceToHost, st));
             AFS_HIP(hipStreamSynchronize(st));
-            const double hn = std::sqrt(std::max(host[2 * (restart + 2) + 2 * (j + 1)], 0.0));
+            const double *hd = host + 2 * (restart + 2);
+            const double hn = std::sqrt(std::max(hd[2 * nv], 0.0));
+            if (Hm.size() < hix(0, j + 1))
+                Hm.resize(hix(0, j + 1));
+            if (augc)
+                Bc.push_back(cplx(host[0] + hd[0], host[1] + hd[1]));
             for (int i = 0; i <= j; ++i)
-                Hm[(size_t)i * restart + j] =
-                    cplx(host[2 * i] + host[2 * (restart + 2) + 2 * i], host[2 * i + 1] + host[2 * (restart + 2) + 2 * i + 1]);
-            Hm[(size_t)(j + 1) * restart + j] = hn;
+                Hm[hix(i, j)] = cplx(host[2 * (i + e)] + hd[2 * (i + e)], host[2 * (i + e) + 1] + hd[2 * (i + e) + 1]);
+            Hm[hix(j + 1, j)] = hn;
             ++res.iters;
             if (!std::isfinite(hn)) {
                 res.nan = true;
                 return res;
             }
             if (hn > 0.0) {
-                // V_{j+1} = w / hn  (device scalar nrm2 at h2 + 2(j+1))
-                vec_normalize(N, h2 + 2 * (j + 1), ws.w, ws.V + 2 * (int64_t)(j + 1) * N, st);
+                // V_{j+1} = w / hn  (device scalar ||w||^2 after the dots)
+                vec_normalize(N, h2 + 2 * nv, ws.w, Vk + 2 * (int64_t)(j + 1) * N, st);
             }
             for (int i = 0; i < j; ++i) {
-                cplx a = Hm[(size_t)i * restart + j], c = Hm[(size_t)(i + 1) * restart + j];
-                Hm[(size_t)i * restart + j] = cs[i] * a + sn[i] * c;
-                Hm[(size_t)(i + 1) * restart + j] = -std::conj(sn[i]) * a + std::conj(cs[i]) * c;
+                cplx a = Hm[hix(i, j)], c = Hm[hix(i + 1, j)];
+                Hm[hix(i, j)] = cs[i] * a + sn[i] * c;
+                Hm[hix(i + 1, j)] = -std::conj(sn[i]) * a + std::conj(cs[i]) * c;
             }
-            cplx a = Hm[(size_t)j * restart + j], c = Hm[(size_t)(j + 1) * restart + j];
+            cplx a = Hm[hix(j, j)], c = Hm[hix(j + 1, j)];
             const double den = std::sqrt(std::norm(a) + std::norm(c));
             if (std::abs(a) == 0.0) {
                 cs[j] = 0.0;
@@ -310,8 +361,8 @@ GmresResult gmres(const Operator &op, Workspace &ws, int64_t /*n_tri*/, const do
                 cs[j] = std::abs(a) / den;
                 sn[j] = (a / std::abs(a)) * std::conj(c) / den;
             }
-            Hm[(size_t)j * restart + j] = cs[j] * a + sn[j] * c;
-            Hm[(size_t)(j + 1) * restart + j] = 0.0;
+            Hm[hix(j, j)] = cs[j] * a + sn[j] * c;
+            Hm[hix(j + 1, j)] = 0.0;
             g[j + 1] = -std::conj(sn[j]) * g[j];
             g[j] = cs[j] * g[j];
             k = j + 1;
@@ -324,17 +375,30 @@ GmresResult gmres(const Operator &op, Workspace &ws, int64_t /*n_tri*/, const do
         for (int i = k - 1; i >= 0; --i) {
             cplx s = g[i];
             for (int l = i + 1; l < k; ++l)
-                s -= Hm[(size_t)i * restart + l] * y[l];
-            y[i] = s / Hm[(size_t)i * restart + i];
+                s -= Hm[hix(i, l)] * y[l];
+            y[i] = s / Hm[hix(i, i)];
         }
         for (int i = 0; i < k; ++i) {
             host[2 * i] = y[i].real();
             host[2 * i + 1] = y[i].imag();
         }
-        AFS_HIP(hipMemcpyAsync(hbuf, host, (size_t)k * 16, hipMemcpyHostToDevice, st));
+        // augmented cycle: the coefficient of aug, -(B y) / gamma, after y
+        cplx du(0.0);
+        if (augc) {
+            for (int i = 0; i < k; ++i)
+                du -= Bc[i] * y[i];
+            du /= gamma;
+            host[2 * k] = du.real();
+            host[2 * k + 1] = du.imag();
+        }
+        AFS_HIP(hipMemcpyAsync(hbuf, host, (size_t)(k + (augc ? 1 : 0)) * 16, hipMemcpyHostToDevice, st));
         AFS_HIP(hipMemsetAsync(ws.tmp, 0, (size_t)N * 16, st));
-        vec_combine(N, k, ws.V, N, hbuf, ws.tmp, st);
+        // x += M^-1 sum_j y_j v_j  (- u B y in the augmented cycle)
+        if (k > 0)
+            vec_combine(N, k, Vk, N, hbuf, ws.tmp, st);
         ws.apply_precond(ws.tmp, ws.z, st);
+        if (augc)
+            vec_combine(N, 1, aug, N, hbuf + 2 * k, ws.z, st);
         if (x_is_zero) {
             AFS_HIP(hipMemcpyAsync(x, ws.z, (size_t)N * 16, hipMemcpyDeviceToDevice, st));
             x_is_zero = false;
@@ -342,6 +406,7 @@ GmresResult gmres(const Operator &op, Workspace &ws, int64_t /*n_tri*/, const do
             vec_combine(N, 1, ws.z, N, ws.one, x, st);  // x += z
         }
         ++res.cycles;
+        augc = false;  // later cycles: plain restarts
         if (!verify && res.est <= 0.5 * tol_abs) {
             // an outer loop judges the iterate with its own residual
             res.converged = true;
@@ -538,7 +603,8 @@ static int krylov_phase(Problem &p, Workspace &ws, const afsbem_solve_opts &o, i
     if (ws.hm_enabled && fmt == kFmtBlocks)
         hmat_finish(p, ws);  // the frequency's assembly has completed (st waited for it, then synchronised)
     const bool learned = o.warm_start == AFSBEM_WARM_LEARNED;
-    const double *x_prev = (d_x0 && o.warm_start != AFSBEM_WARM_NONE) ? d_x0 : nullptr;
+    const bool user_aug = o.warm_start == AFSBEM_WARM_USER_AUG;
+    const double *x_prev = (d_x0 && o.warm_start != AFSBEM_WARM_NONE && !user_aug) ? d_x0 : nullptr;
     const double *x_net = nullptr;
     if (learned) {
         if (!p.learn) {
@@ -547,10 +613,17 @@ static int krylov_phase(Problem &p, Workspace &ws, const afsbem_solve_opts &o, i
             p.learn->init(p);
         }
         if (p.learn->rows > 0 && p.learn->query_now()) {
-            p.learn->predict(p, s_re, s_im, ws.z, st);
-            x_net = ws.z;
+            // the augmentation vector must outlive the preconditioned vectors (ws.z) of GMRES
+            double *dst = o.learn_aug ? ws.aug : ws.z;
+            p.learn->predict(p, s_re, s_im, dst, st);
+            x_net = dst;
         }
     }
+    // the prediction's roles: in the starting iterate (learn_aug 0 or 2) and/or
+    // as a direction of the first GMRES cycle (learn_aug 1 or 2)
+    const double *x_net_start = (x_net && o.learn_aug != 1) ? x_net : nullptr;
+    const double *aug_vec = user_aug ? d_x0 : ((x_net && o.learn_aug != 0) ? x_net : nullptr);
+    double aug_gain = 0.0;
     bool x_zero = true, used_net = false;
     double net_gain = 0.0;
     int status = AFSBEM_OK, refine = 0, fallback = 0;
@@ -565,8 +638,8 @@ static int krylov_phase(Problem &p, Workspace &ws, const afsbem_solve_opts &o, i
         Operator op32 = op64;
         op32.precision = 1;
         double *xs = mixed ? ws.xo : ws.x, *rs = mixed ? ws.rin : ws.r;
-        double r0n = start_iterate(mixed ? op32 : op64, ws, ws.b, bnorm, x_prev, x_net, xs, rs, x_zero, st, &used_net,
-                                   &net_gain);
+        double r0n = start_iterate(mixed ? op32 : op64, ws, ws.b, bnorm, x_prev, x_net_start, xs, rs, x_zero, st,
+                                   &used_net, &net_gain);
         if (!x_zero && (o.fault_inject & AFSBEM_FAULT_NAN_START)) {
             // test hook: the guess turned out non-finite
             AFS_HIP(hipMemsetAsync(xs, 0xff, (size_t)N * 16, st));
@@ -594,8 +667,11 @@ static int krylov_phase(Problem &p, Workspace &ws, const afsbem_solve_opts &o, i
             bool from_zero = false;
             while (true) {
                 const double tol_in = std::max(o.inner_tol * rnorm, 0.5 * o.tol * bnorm);
+                const double *av = refine == 0 ? aug_vec : nullptr;
                 GmresResult g = gmres(op32, ws, nt, ws.rin, rnorm, ws.x, true, tol_in, o.restart,
-                                      std::max(1, o.max_iter - matvecs), st, false, nullptr, 0.0);
+                                      std::max(1, o.max_iter - matvecs), st, false, nullptr, 0.0, av);
+                if (av)
+                    aug_gain = g.aug_gain;
                 if (!(o.fault_inject & AFSBEM_FAULT_STALL_INNER))  // test hook: the correction is lost
                     vec_combine(N, 1, ws.x, N, ws.one, ws.xo, st);  // x_outer += d
                 residual(op64, ws, ws.b, ws.xo, ws.rin, st);         // FP64 judge
@@ -627,8 +703,11 @@ static int krylov_phase(Problem &p, Workspace &ws, const afsbem_solve_opts &o, i
             }
         }
         if (plain) {
+            const double *av = mixed ? nullptr : aug_vec;  // a mixed solve handed over has used it
             GmresResult g = gmres(op64, ws, nt, ws.b, bnorm, ws.x, x_zero, o.tol * bnorm, o.restart,
-                                  std::max(1, o.max_iter - matvecs), st, true, x_zero ? nullptr : ws.r, r0n);
+                                  std::max(1, o.max_iter - matvecs), st, true, x_zero ? nullptr : ws.r, r0n, av);
+            if (av)
+                aug_gain = g.aug_gain;
             // final true FP64 residual (after the last restart gmres already formed r)
             relres = g.est / bnorm;
             if (g.nan)
@@ -642,8 +721,14 @@ static int krylov_phase(Problem &p, Workspace &ws, const afsbem_solve_opts &o, i
         AFS_HIP(hipMemcpyAsync(d_a, ws.x, (size_t)N * 16, hipMemcpyDeviceToDevice, st));
     if (d_u || d_t)
         vec_split_ut(nt, p.dev.kind, ws.x, d_bc, d_u, d_t, st);
-    if (learned && x_net && x_prev)
+    // gate of the network: the residual reduction its prediction brought (the
+    // augmentation direction alone, or the second vector of the start)
+    if (learned && aug_vec && o.learn_aug == 1)
+        p.learn->record_gain(aug_gain);
+    else if (learned && x_net_start && x_prev)
         p.learn->record_gain(net_gain);
+    if (aug_vec && !user_aug)
+        used_net = true;
     if (learned && !p.learn->retired && std::isfinite(relres)) {
         p.learn->add_solution(p, s_re, s_im, ws.x, st);
         p.learn->train(o.learn_steps > 0 ? o.learn_steps : p.learn->steps_per_sample, st);
@@ -734,7 +819,7 @@ bool extrap_coeffs(std::complex<double> s0, std::complex<double> s1, std::comple
 const double *start_guess(const afsbem_solve_opts &o, int32_t k, int64_t N, const double *s, const double *x0_user,
                           const double *a_out, double *xbuf, hipStream_t st) {
     using C = std::complex<double>;
-    if (o.warm_start == AFSBEM_WARM_USER)
+    if (o.warm_start == AFSBEM_WARM_USER || o.warm_start == AFSBEM_WARM_USER_AUG)
         return x0_user + 2 * (size_t)k * N;
     const bool prev_like = o.warm_start == AFSBEM_WARM_PREV || o.warm_start == AFSBEM_WARM_LEARNED ||
                            o.warm_start == AFSBEM_WARM_EXTRAP;

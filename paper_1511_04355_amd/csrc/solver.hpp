@@ -17,6 +17,7 @@ struct Workspace {
     double *V = nullptr, *w = nullptr, *z = nullptr, *x = nullptr, *r = nullptr, *tmp = nullptr;
     double *rin = nullptr, *xo = nullptr;  // mixed: outer residual and outer iterate
     double *xstart = nullptr;              // extrapolated starting guess
+    double *aug = nullptr;                 // augmentation vector of the first GMRES cycle (learned)
     double *dots_partial = nullptr, *small = nullptr;
     double *one = nullptr;                 // device complex 1 + 0i
     // preconditioner: 0 = 3x3 blocks (precond), 1 = element clusters (clinv)
@@ -38,6 +39,7 @@ struct Workspace {
     double hm_eps = 1e-5, hm_eta = 1.0;
     bool hm_ok = false;
     int hm_max_rank = 0;
+    double hm_bytes = 0.0;                 // matrix bytes one hierarchical product streams
     float2 *hm_dense = nullptr;
     float2 *hm_pool = nullptr;             // factor terms: U_q (R entries) then V_q (C entries)
     size_t hm_pool_cap = 0;                // complex entries
@@ -79,6 +81,7 @@ struct Operator {
 struct GmresResult {
     int iters = 0, cycles = 0;
     double est = 0.0;  // last residual norm (true residual of the operator after a restart)
+    double aug_gain = 0.0;  // augmented first cycle: residual reduction by the augmentation direction alone
     bool converged = false, nan = false;
 };
 
@@ -87,10 +90,13 @@ struct GmresResult {
 // holds the iterate.  Stops when the residual norm is <= tol_abs.  With
 // verify = false a cycle whose Arnoldi estimate meets the tolerance returns
 // without forming the true residual of op (an outer loop judges it).  r0
-// (nullable, with x not zero): the residual of x, already formed.
+// (nullable, with x not zero): the residual of x, already formed.  aug
+// (nullable): a vector that joins the search space of the first cycle
+// (flexible GMRES with aug as direction 0 and the preconditioned basis
+// vectors after it), its coefficient found by the same least-squares problem.
 GmresResult gmres(const Operator &op, Workspace &ws, int64_t n_tri, const double *rhs, double rhs_norm, double *x,
                   bool x_is_zero, double tol_abs, int restart, int max_iter, hipStream_t st, bool verify,
-                  const double *r0 = nullptr, double r0_norm = 0.0);
+                  const double *r0 = nullptr, double r0_norm = 0.0, const double *aug = nullptr);
 
 int solve_pipelined(Problem &p, const afsbem_solve_opts &o, int32_t n_s, const double *s, const double *bc,
                     const double *x0_user, double *a_out, double *u_out, double *t_out,

@@ -1,0 +1,101 @@
+"""Augmented GMRES (a vector joins the search space of the first cycle; the
+"preconditioner" use of the learned prediction) against the oracle's LU
+solutions, with vectors whose effect is known: the exact solution ends the
+solve after its own product, a random vector costs its product and a few
+iterations.
+Then the network's prediction in that role on a sequence of frequencies."""
+import numpy as np
+import pytest
+
+from synth import meshgen as mg
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _needs_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+
+
+def _problem(level, ks):
+    import paper_1511_04355_amd as afs
+    from oracle import bem
+    mesh = mg.cavity(level)
+    s = mg.cavity_frequencies(64)[ks]
+    bc = np.stack([np.asarray(mesh.bc_shape, np.complex128) / sk for sk in s])
+    xo = []
+    for k, sk in enumerate(s):
+        A, b = bem.assemble(mesh, sk, bc[k])
+        xo.append(bem.solve_dense(A, b))
+    return afs.Problem.from_mesh(mesh), s, bc, np.array(xo)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_augmentation_with_the_exact_solution(prec):
+    import paper_1511_04355_amd as afs
+    P, s, bc, xo = _problem(2, [3, 40])
+    precision = afs.PREC_FP64 if prec == "fp64" else afs.PREC_MIXED
+    tol, bar = (1e-8, 1e-6) if prec == "fp64" else (1e-6, 1e-5)
+    aug = torch.from_numpy(xo).cuda()
+    out = P.solve(s, torch.from_numpy(bc).cuda(),
+                  afs.SolveOptions(tol=tol, precision=precision, warm_start=afs.WARM_USER_AUG, batch=1), x0=aug)
+    a = out["a"].cpu().numpy()
+    for k in range(len(s)):
+        st = out["stats"][k]
+        err = np.linalg.norm(a[k] - xo[k]) / np.linalg.norm(xo[k])
+        print(f"aug=exact {prec} s={s[k]:.3f}: {st['iters']} products, rel err {err:.1e}", flush=True)
+        # the augmentation direction's product, then the FP64 true residual of the result
+        assert st["iters"] <= 2
+        assert st["rel_res_fp64"] <= tol
+        assert err <= bar
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_augmentation_with_a_random_vector(prec):
+    import paper_1511_04355_amd as afs
+    P, s, bc, xo = _problem(2, [0, 17, 50])
+    precision = afs.PREC_FP64 if prec == "fp64" else afs.PREC_MIXED
+    bar = 1e-6 if prec == "fp64" else 1e-5
+    rng = np.random.default_rng(11)
+    rnd = torch.from_numpy(rng.standard_normal(xo.shape) + 1j * rng.standard_normal(xo.shape)).cuda()
+    bcd = torch.from_numpy(bc).cuda()
+    base = P.solve(s, bcd, afs.SolveOptions(tol=1e-7, precision=precision, batch=1))
+    out = P.solve(s, bcd, afs.SolveOptions(tol=1e-7, precision=precision, warm_start=afs.WARM_USER_AUG, batch=1),
+                  x0=rnd)
+    a = out["a"].cpu().numpy()
+    for k in range(len(s)):
+        st, sb = out["stats"][k], base["stats"][k]
+        err = np.linalg.norm(a[k] - xo[k]) / np.linalg.norm(xo[k])
+        print(f"aug=random {prec} s={s[k]:.3f}: {st['iters']} products (zero start {sb['iters']}), "
+              f"rel err {err:.1e}", flush=True)
+        assert st["rel_res_fp64"] <= 1e-7
+        assert err <= bar
+        # the direction's own product plus a few iterations of the projected
+        # operator (rank-one change of the preconditioned spectrum)
+        assert st["iters"] <= sb["iters"] + 6
+
+
+@pytest.mark.parametrize("learn_aug", [1, 2])
+def test_learned_prediction_as_augmentation(learn_aug):
+    """Cavity (1280 triangles), 24 frequencies, mixed precision: with the
+    network's prediction augmenting the first cycle (alone, or besides its
+    place in the starting iterate) every frequency meets the FP64 residual
+    and matches the oracle."""
+    import paper_1511_04355_amd as afs
+    from oracle import bem
+    mesh = mg.cavity(3)
+    s = mg.cavity_frequencies(24)
+    bc = torch.from_numpy(np.stack([np.asarray(mesh.bc_shape, np.complex128) / sk for sk in s])).cuda()
+    P = afs.Problem.from_mesh(mesh)
+    out = P.solve(s, bc, afs.SolveOptions(tol=1e-6, precision=afs.PREC_MIXED, warm_start=afs.WARM_LEARNED,
+                                          learn_aug=learn_aug))
+    assert max(x["rel_res_fp64"] for x in out["stats"]) <= 1e-6
+    print(f"learn_aug={learn_aug}: products {sum(x['iters'] for x in out['stats'])}, "
+          f"network used {sum(x['used_net'] for x in out['stats'])} times", flush=True)
+    sols = out["a"].cpu().numpy()
+    for k in (5, 17):
+        A, b = bem.assemble(mesh, s[k])
+        xo = bem.solve_dense(A, b)
+        assert np.linalg.norm(sols[k] - xo) / np.linalg.norm(xo) <= 1e-5

@@ -26,9 +26,14 @@ def _setup(n, d_in, H, d_out, seed=0):
     return p, X, T, dev(p), dev(X), dev(T)
 
 
-@pytest.mark.parametrize("shape", [(300, 32, 256, 6), (77, 5, 40, 3), (16, 16, 16, 16)])
-@pytest.mark.parametrize("mode,tol", [(0, 2e-5), (1, 3e-2)])
+@pytest.mark.parametrize("shape", [(8192, 32, 256, 6), (300, 32, 256, 6), (77, 5, 40, 3), (16, 16, 16, 16),
+                                   (1000, 33, 70, 5)])
+@pytest.mark.parametrize("mode,tol", [(0, 1e-5), (1, 2e-2)])
 def test_mlp_forward_and_gradient(shape, mode, tol):
+    """Forward pass, loss and every parameter's gradient against the FP64
+    oracle: the production shape (8192 rows, 32 -> 256 -> 256 -> 6, whose
+    weight gradients split the batch over 32 planes), shapes with ragged tiles
+    in every dimension and leading dimensions that rule out 16-byte loads."""
     import paper_1511_04355_amd as afs
     from oracle import mlp
     n, d_in, H, d_out = shape
@@ -59,6 +64,27 @@ def test_adam_step_matches_oracle():
     assert np.max(np.abs(pd.cpu().numpy() - po)) < 1e-6
     assert np.max(np.abs(md.cpu().numpy() - mo)) < 1e-6
     assert np.max(np.abs(vd.cpu().numpy() - vo)) < 1e-5
+
+
+@pytest.mark.parametrize("shape", [(8192, 32, 256, 6), (77, 5, 40, 3)])
+def test_fused_train_step_equals_gradient_then_adam(shape):
+    """afsbem_mlp_train_step (gradient planes added and applied by Adam in one
+    pass) against afsbem_mlp_loss_grad followed by afsbem_mlp_adam on a copy of
+    the same state (both pinned to the oracle above): same loss, same
+    parameters and moments after three steps."""
+    import paper_1511_04355_amd as afs
+    n, d_in, H, d_out = shape
+    _, _, _, pd, Xd, Td = _setup(n, d_in, H, d_out, seed=7)
+    p1, p2 = pd.clone(), pd.clone()
+    m1, v1 = torch.zeros_like(pd), torch.zeros_like(pd)
+    m2, v2 = torch.zeros_like(pd), torch.zeros_like(pd)
+    for t in range(1, 4):
+        l1 = afs._lib.mlp_train_step(p1, Xd, Td, m1, v1, t, d_in, H, d_out, lr=1e-3)
+        l2, g = afs._lib.mlp_loss_grad(p2, Xd, Td, d_in, H, d_out, 1)
+        afs._lib.mlp_adam(p2, g, m2, v2, t, lr=1e-3)
+        assert abs(l1.item() - l2.item()) <= 1e-6 * abs(l2.item())
+    for a, b in ((p1, p2), (m1, m2), (v1, v2)):
+        assert torch.max(torch.abs(a - b)).item() <= 1e-6 * max(torch.max(torch.abs(b)).item(), 1e-30)
 
 
 def test_training_reduces_loss():
