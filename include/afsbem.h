@@ -153,6 +153,17 @@ int afsbem_assemble_device(afsbem_problem *p, double s_re, double s_im, const vo
 int afsbem_matvec_device(afsbem_problem *p, int format, int precision, const void *d_A,
                          const void *d_A_lo, const void *d_x, void *d_y, void *hip_stream);
 
+/* afsbem_matvec_device for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): same arguments, layouts and result up to the order of the FP64
+ * partial sums.  The partial sums of the column split go to a fixed array of
+ * 16 MiB per device inside the library, held until the process ends; no
+ * hipMalloc, hipFree or allocating library routine is called.  N = 3 n_tri
+ * above 1,048,576 is rejected (AFSBEM_EINVAL).  Every call on a device shares
+ * that device's array: calls that overlap on one device (several streams or
+ * threads) race and must be serialised by the caller. */
+int afsbem_matvec_device_noalloc(afsbem_problem *p, int format, int precision, const void *d_A,
+                                 const void *d_A_lo, const void *d_x, void *d_y, void *hip_stream);
 
 /* Matrix-free product at one s (Eq. 2 without a stored matrix): the far-field
  * rule is evaluated on the fly for every pair m != n (precision 0: FP64;

@@ -89,6 +89,7 @@ def lib():
         L.afsbem_problem_info.argtypes = [P, P, P, P, P]
         L.afsbem_assemble_device.argtypes = [P, d, d, P, ctypes.c_int, P, P, P, P, P]
         L.afsbem_matvec_device.argtypes = [P, ctypes.c_int, ctypes.c_int, P, P, P, P, P]
+        L.afsbem_matvec_device_noalloc.argtypes = [P, ctypes.c_int, ctypes.c_int, P, P, P, P, P]
         L.afsbem_autotune_set.argtypes = [ctypes.c_int]
         L.afsbem_autotune_report.argtypes = [P, i64, P]
         L.afsbem_matvec_free_device.argtypes = [P, d, d, ctypes.c_int, P, P, P, P, P]
@@ -278,6 +279,17 @@ class Problem:
         y = torch.empty(self.N, dtype=torch.complex128, device="cuda")
         _check(lib().afsbem_matvec_device(self._h, int(fmt), int(precision), _ptr(A), _ptr(A_lo), _ptr(x), _ptr(y),
                                           _stream()))
+        return y
+
+    def matvec_noalloc(self, A, A_lo, x, y, fmt=FMT_C128, precision=0):
+        """y = A x through afsbem_matvec_device_noalloc (the library allocates
+        nothing; the caller passes the output buffer y)."""
+        import torch
+        x = x.contiguous()
+        assert x.dtype == torch.complex128 and x.numel() == self.N and x.is_cuda
+        assert y.dtype == torch.complex128 and y.numel() == self.N and y.is_cuda and y.is_contiguous()
+        _check(lib().afsbem_matvec_device_noalloc(self._h, int(fmt), int(precision), _ptr(A), _ptr(A_lo), _ptr(x),
+                                                  _ptr(y), _stream()))
         return y
 
     def solve_host(self, s_list, bc_val, opts: SolveOptions | None = None, x0=None):

@@ -313,6 +313,21 @@ int afsbem_matvec_device(afsbem_problem *p, int format, int precision, const voi
     });
 }
 
+int afsbem_matvec_device_noalloc(afsbem_problem *p, int format, int precision, const void *d_A, const void *d_A_lo,
+                                 const void *d_x, void *d_y, void *hip_stream) {
+    return guarded([&] {
+        AFS_REQUIRE(p && d_A && d_x && d_y, AFSBEM_EINVAL, "null pointer argument");
+        AFS_REQUIRE(format == AFSBEM_FMT_C128 || format == AFSBEM_FMT_SPLIT, AFSBEM_EINVAL, "bad format");
+        AFS_REQUIRE(precision == 0 || (precision == 1 && format == AFSBEM_FMT_SPLIT), AFSBEM_EINVAL,
+                    "FP32 products need the SPLIT format");
+        AFS_REQUIRE(format == AFSBEM_FMT_C128 || precision == 1 || d_A_lo, AFSBEM_EINVAL, "FP64 SPLIT needs lo plane");
+        const int64_t N = 3 * p->p.dev.n_tri;
+        launch_gemv_noalloc(N, format, precision, d_A, d_A_lo, static_cast<const double *>(d_x),
+                            static_cast<double *>(d_y), static_cast<hipStream_t>(hip_stream));
+        return AFSBEM_OK;
+    });
+}
+
 int afsbem_matvec_free_device(afsbem_problem *p, double s_re, double s_im, int precision, const void *d_bc_val,
                               const void *d_x, void *d_y, void *d_b, void *hip_stream) {
     return guarded([&] {

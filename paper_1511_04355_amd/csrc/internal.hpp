@@ -196,6 +196,12 @@ int gemv_chunks(int64_t N);
 void launch_gemv(int64_t N, int format, int precision, const void *A, const void *A_lo,
                  const double *x, double *y, double *partial, hipStream_t st,
                  hipEvent_t ev_begin = nullptr, hipEvent_t ev_end = nullptr);
+// The same product with its partial sums in a fixed per-device array of the
+// library (no allocation; default column split, reduced to fit); N above
+// gemv_noalloc_max_n() is rejected.
+int64_t gemv_noalloc_max_n();
+void launch_gemv_noalloc(int64_t N, int format, int precision, const void *A, const void *A_lo,
+                         const double *x, double *y, hipStream_t st);
 
 // starting guesses of a multi-frequency call (solver.cpp)
 bool extrap_coeffs(std::complex<double> s0, std::complex<double> s1, std::complex<double> s2,

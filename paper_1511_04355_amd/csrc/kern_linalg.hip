@@ -12,6 +12,8 @@
 //               FP32 accumulation within a chunk.
 //   SPLIT FP64: hi + lo planes converted to FP64 per entry, FP64 FMA.
 #include <algorithm>
+#include <mutex>
+#include <string>
 #include <vector>
 
 #include "cplx.hpp"
@@ -285,6 +287,50 @@ void launch_gemv(int64_t N, int format, int precision, const void *A, const void
         [&](int c) { gemv_enqueue(N, format, precision, A, A_lo, x, y, partial, c, st, nullptr, nullptr); },
         gemv_chunks_default(N));
     gemv_enqueue(N, format, precision, A, A_lo, x, y, partial, S, st, ev_begin, ev_end);
+}
+
+// ------------------------------------------- GEMV without allocation --
+// Partial sums of the column split in a file-scope device array instead of
+// caller or allocator memory.  Each device holds its own copy; host code
+// reaches it only through the address hipGetSymbolAddress returns for the
+// current device (resolved once per device and kept), never through the
+// array's name.  Every call on a device shares the array: calls that overlap
+// on one device race.  Nothing in it has to start at zero (the product pass
+// writes every partial sum the summation pass reads).
+constexpr size_t kGemvScratchBytes = (size_t)16 << 20;
+static __device__ __align__(256) unsigned char scratch[kGemvScratchBytes];
+
+namespace {
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[64] = {};
+}  // namespace
+
+static double *gemv_scratch_for_current_device() {
+    int dev = 0;
+    AFS_HIP(hipGetDevice(&dev));
+    AFS_REQUIRE(dev >= 0 && dev < 64, AFSBEM_EDEVICE, "device index out of range");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        AFS_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        AFS_REQUIRE(ptr != nullptr, AFSBEM_EDEVICE, "no device address for the GEMV scratch array");
+        g_scratch_ptr[dev] = ptr;
+    }
+    return static_cast<double *>(g_scratch_ptr[dev]);
+}
+
+int64_t gemv_noalloc_max_n() { return (int64_t)(kGemvScratchBytes / 16); }
+
+void launch_gemv_noalloc(int64_t N, int format, int precision, const void *A, const void *A_lo, const double *x,
+                         double *y, hipStream_t st) {
+    // the default column split, reduced until its partial sums fit the array
+    const int64_t fit = (int64_t)(kGemvScratchBytes / ((size_t)N * 16));
+    AFS_REQUIRE(N >= 1 && fit >= 1, AFSBEM_EINVAL,
+                "N = " + std::to_string(N) + " exceeds the allocation-free GEMV's limit of " +
+                    std::to_string(gemv_noalloc_max_n()) + " unknowns (" +
+                    std::to_string(kGemvScratchBytes >> 20) + " MiB of partial sums per device)");
+    const int S = (int)std::min<int64_t>(gemv_chunks_default(N), fit);
+    gemv_enqueue(N, format, precision, A, A_lo, x, y, gemv_scratch_for_current_device(), S, st, nullptr, nullptr);
 }
 
 // ---------------------------------------------------------- vector kernels --
