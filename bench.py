@@ -1,36 +1,40 @@
 #!/usr/bin/env python3
 """Frequency solves/s at FP64 relative residual 1e-6 on MI355X.
 
-Workload (one "step"): the pressurised spherical cavity in full space,
-icosphere level 4 (5120 flat triangles, 15,360 complex unknowns), unit
-material (mu = rho = 1, nu = 1/4), 64 Laplace parameters s_k = 0.25 + i k pi/20
-with a Heaviside pressure; every frequency is assembled and solved until the
-true residual ||b - A x|| / ||b|| with the FP64 operator is <= 1e-6.
+Contract workload (one "step" = one frequency solve): the porous block of the
+largest configuration, side 4 with 64 seeded spherical voids in a 4x4x4
+lattice (100,172 flat triangles, 300,516 complex unknowns), unit material
+(mu = rho = 1, nu = 1/4), step traction on z = 0, z = 4 fixed, the rest and
+the voids traction-free.  Frequencies on Re s = eta = 3 ln10 / 300 with
+omega in the lowest quarter of the band of T = 300, Ns = 512 (the paper's
+porous-solid shape, k_s L ~ 21 at the top of the band), visited in the order
+an adaptive sampling run takes them; warm-up frequencies first (untimed), then
+the timed ones in one call.
 
-Timed paths (same mesh, same s list, same GPU):
-  * optimised: FP32 hi-plane GMRES inside FP64 iterative refinement, previous-
-    frequency warm start  -> ``value``
-  * plain FP64: FP64 storage and GMRES(50) with block-Jacobi, zero x0 -> ``plain_fp64``
-Inputs (mesh plan, boundary values) are resident in HBM before timing starts.
+Timed path (``value``): mixed precision -- FP32 hierarchical inner operator
+(dense near blocks + cross-approximation factors, built on the GPU per
+frequency) inside FP64 iterative refinement whose residual is the FP64
+on-the-fly operator -- GMRES(1500) with cluster block-Jacobi, learned warm
+start (network trained on the GPU after every solve), two frequencies in
+flight (the hierarchical build of s_k+1 during the Krylov phase of s_k).
+Beside it: plain FP64 (FP64 on-the-fly operator, GMRES(50), 3x3
+block-Jacobi, zero start, one frequency) timed on s = eta only, the optimised
+path alone on that frequency, the FP64 CPU oracle on a bounded row sample,
+and the 15,360-unknown cavity line as a secondary key.  Inputs (plan,
+boundary values) are resident in HBM when timing starts.
 
-Also reported: the roofline of the dominant kernel of the optimised step (the
-one with the larger total time: the FP32 GEMV streaming the hi plane,
-HBM-bound, or the FP64 far-field assembly kernel, VALU-bound; both are timed
-with HIP events on the stream they run on during the timed steps) with the
-other beside it, the lockstep batched path on the same workload, and the FP64
-CPU oracle timed on this host on a bounded sample.
+Roofline of the dominant kernel: the hierarchical FP32 product, HBM-bound;
+algorithmic bytes per launch = the dense blocks plus every term's U and V
+(complex FP32, counted from the ranks the build reached), divided by the
+product's average duration from HIP events on the solve stream.
 
-Algorithmic work per unit (counted from the formulas as implemented, closed-
-form branch of the radial functions; each sqrt, division, exp and sincos
-counted as one operation):
-  far field, per quadrature node (7 per source element, every pair m != n):
+Algorithmic work of the far-field rule (cavity line, FP64 assembly), per
+quadrature node (7 per source element, every pair m != n):
     geometry 22 + radial functions 118 + traction coefficients 24
     + traction invariants 63 + U.t for b 60 + 7 special functions
     + per-pair expansion 90 / 7  ->  307 FP64 flops
-  GEMV: N^2 * 8 bytes (FP32 hi plane) per product.
-HBM traffic of these kernels from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE,
-FETCH_SIZE scaled by 2.0 (it reads 524,300 KiB for a 1 GiB device copy,
-WRITE_SIZE 1,048,576 KiB).
+HBM traffic from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE, FETCH_SIZE scaled
+by 2.0 (it reads 524,300 KiB for a 1 GiB device copy, WRITE_SIZE 1,048,576).
 """
 import argparse
 import json
@@ -52,13 +56,16 @@ FAR_NODES = 7
 # (FETCH_SIZE x 2.0, its reading for a 1 GiB device copy being half the true bytes)
 FAR_TRAFFIC_BYTES = (2.0 * 23885.20 + 3736479.73) * 1024
 GEMV32_TRAFFIC_BYTES = 2.0 * 923559.66 * 1024
+# HBM bytes of one hierarchical product at 300,516 unknowns (rocprofv3 --pmc over its kernels); None until taken
+# on the current kernels
+HMAT_TRAFFIC_BYTES = None
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--level", type=int, default=4)
     ap.add_argument("--nfreq", type=int, default=64)
     ap.add_argument("--tol", type=float, default=1e-6)
@@ -69,11 +76,14 @@ def parse():
     ap.add_argument("--warm", choices=["none", "prev", "extrap", "learned"], default="extrap",
                     help="initial guess of the optimised path (porous_afs_matrix_free: learned = the network "
                          "combined with the nearest sample's solution)")
-    ap.add_argument("--workload", default="cavity_L4",
-                    choices=["cavity_L4", "pmc_probe", "cavity_L2_batched", "blocks_batched", "porous_learned",
+    ap.add_argument("--workload", default="porous_C5",
+                    choices=["porous_C5", "cavity_L4", "pmc_probe", "pmc_probe_c5", "cavity_L2_batched", "blocks_batched", "porous_learned",
                              "porous_matrix_free", "porous_afs_matrix_free", "cavity_L4_afs", "cavity_nystrom",
                              "porous_hmat"],
-                    help="cavity_L4: the contract line (default).  The others print their own JSON line: "
+                    help="porous_C5: the contract line (default; 300,516 unknowns, one step = one frequency).  "
+                         "cavity_L4: the 15,360-unknown cavity line (64 frequencies per step; also run as the "
+                         "contract line's secondary key).  The others print their own JSON line: pmc_probe_c5 (1 GiB copies + one "
+                         "solve of the contract workload at s = eta, for counter runs), "
                          "pmc_probe (1 GiB copies + 4 mixed solves, for counter runs), cavity_L2_batched "
                          "(320 triangles, 16 frequencies), blocks_batched (16 seeded porous blocks x 24 "
                          "frequencies), porous_learned (27-void block, 40,320 unknowns: warm-start A/B on an "
@@ -92,7 +102,13 @@ def parse():
     ap.add_argument("--precond", type=int, default=0,
                     help="blocks_batched, porous_afs_matrix_free: 0 point, 1 cluster block-Jacobi")
     ap.add_argument("--afs-ns", type=int, default=64, help="porous_afs_matrix_free: FSM size Ns of the band")
+    ap.add_argument("--restart", type=int, default=1500, help="porous_afs_matrix_free: GMRES restart length")
     ap.add_argument("--afs-max", type=int, default=24, help="porous_learned: cap on AFS samples")
+    ap.add_argument("--learn-aug", type=int, default=0, choices=[0, 1, 2],
+                    help="porous_C5: the network's prediction in the start (0), augmenting the first GMRES cycle "
+                         "(1), or both (2)")
+    ap.add_argument("--plain-max-iter", type=int, default=300, help="porous_C5: product cap of the plain FP64 leg")
+    ap.add_argument("--no-secondary", action="store_true", help="porous_C5: skip the 15,360-unknown cavity line")
     ap.add_argument("--batch", type=int, default=0,
                     help="optimised path: 1 = one frequency at a time, 0 = assembly of the next frequency "
                          "overlapped with the Krylov phase of the current one")
@@ -197,6 +213,30 @@ def run_pmc_probe(afs, mg, np, torch):
     return {"workload": "pmc_probe", "far_ms": [st["t_far_ms"] for st in o["stats"]]}
 
 
+def run_pmc_probe_c5(args, afs, mg, np, torch):
+    """Short fixed program for counter runs on the contract workload: 3 device
+    copies of 1 GiB (calibration of FETCH_SIZE / WRITE_SIZE), then one mixed
+    solve of the 300,516-unknown porous block at s = eta with the
+    hierarchical inner operator (the contract path's operator and solver, one
+    frequency, zero start)."""
+    x = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    del x, y
+    mesh = mg.lattice_block(4, 39, 3, 2000, rmax=0.45)
+    P = afs.Problem.from_mesh(mesh)
+    s = np.array([C5_KAPPA * np.log(10.0) / C5_T + 0.0j])
+    o = P.solve(s, _bcs(mesh, s, torch, np),
+                afs.SolveOptions(tol=args.tol, precision=afs.PREC_MIXED, matrix_free=2, hmat_eps=C5_HMAT_EPS,
+                                 precond=1, restart=C5_RESTART, max_iter=6000, profile=1, batch=1), want_ut=False)
+    torch.cuda.synchronize()
+    st = o["stats"][0]
+    return {"workload": "pmc_probe_c5", "inner_products": st["gemv_count"],
+            "inner_ms": st["gemv_ms"] / max(st["gemv_count"], 1), "fp64_products": st["gemv64_count"]}
+
+
 def run_cavity_L2_batched(args, afs, mg, np, torch):
     """320-triangle cavity, 16 frequencies, FP64 tol 1e-8: one frequency at a
     time vs all 16 in one lockstep call (FP64 and mixed)."""
@@ -267,8 +307,10 @@ def run_porous_learned(args, afs, mg, np, torch):
     """27-void porous block (13,440 elements, 40,320 unknowns): the frequency
     sequence of an AFS run (J0 = 16 Chebyshev points, then adaptive, at most
     args.afs_max samples) without learning, replayed in the same order with
-    zero, previous-s and learned (network trained on the GPU after each solve)
-    initial guesses.  Prints a progress line per solve batch on stderr."""
+    zero, previous-s, extrapolated and learned (network trained on the GPU
+    after each solve; its prediction in the start, augmenting the first GMRES
+    cycle, or both) initial guesses.  Prints a progress line per solve or
+    replayed leg on stderr."""
     mesh = mg.lattice_block(3, 20, 2, 1000)
     P = afs.Problem.from_mesh(mesh)
     T, kappa, Ns = 300.0, 3.0, 512
@@ -277,7 +319,7 @@ def run_porous_learned(args, afs, mg, np, torch):
     loaded = np.nonzero(np.abs(np.asarray(mesh.bc_shape)).sum(1) > 0)[0]
     dofs = np.sort(3 * rng.choice(loaded, 6, replace=False) + 2)
     shape = np.asarray(mesh.bc_shape, np.complex128)
-    base = dict(tol=args.tol, precision=afs.PREC_MIXED, restart=100, max_iter=8000)
+    base = dict(tol=args.tol, precision=afs.PREC_MIXED, restart=1000, max_iter=8000)
     prev = {}
 
     def response(sv):
@@ -307,7 +349,7 @@ def run_porous_learned(args, afs, mg, np, torch):
     s = np.asarray(r["s"])
     P.close()
     res = {"workload": f"porous_learned: 27-void block ({mesh.n_tri} elements, {3 * mesh.n_tri} unknowns), "
-                       f"{len(s)} AFS frequencies (T=300, eta={eta:.4f}, Ns=512), mixed GMRES(100), "
+                       f"{len(s)} AFS frequencies (T=300, eta={eta:.4f}, Ns=512), mixed GMRES(1000), "
                        f"FP64 true rel. residual <= {args.tol}", "afs_seconds": afs_s, "n_freq": len(s),
            "afs_converged": bool(r["converged"])}
     # the library AFS loop with nearest-sample and vector-fitting-model starts
@@ -321,20 +363,21 @@ def run_porous_learned(args, afs, mg, np, torch):
         print(f"[{name}] {res[name]}", file=sys.stderr, flush=True)
         Q.close()
     bc = _bcs(mesh, s, torch, np)
-    for name, warm in (("zero", afs.WARM_NONE), ("previous", afs.WARM_PREV), ("learned", afs.WARM_LEARNED)):
-        Q = afs.Problem.from_mesh(mesh)  # fresh network for the learned leg
-        o = afs.SolveOptions(warm_start=warm, batch=1, **base)
+    # the replayed sequence in one call per start policy (one frequency at a
+    # time, each start formed from the solutions before it in the sequence)
+    legs = (("zero", afs.WARM_NONE, 0), ("previous", afs.WARM_PREV, 0), ("extrapolated", afs.WARM_EXTRAP, 0),
+            ("learned", afs.WARM_LEARNED, 0), ("learned_augmenting", afs.WARM_LEARNED, 1),
+            ("learned_both", afs.WARM_LEARNED, 2))
+    for name, warm, aug in legs:
+        Q = afs.Problem.from_mesh(mesh)  # fresh network for each learned leg
+        o = afs.SolveOptions(warm_start=warm, batch=1, learn_aug=aug, **base)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        stats = []
-        for k in range(len(s)):  # one call per frequency: same state as one call, with progress
-            out = Q.solve(s[k:k + 1], bc[k:k + 1], o, want_ut=False,
-                          x0=None if (warm == afs.WARM_NONE or k == 0) else a_prev[None])
-            a_prev = out["a"][0].clone()
-            stats += out["stats"]
-            print(f"[{name}] k={k} matvecs={out['stats'][0]['iters']}", file=sys.stderr, flush=True)
+        out = Q.solve(s, bc, o, want_ut=False)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
+        stats = out["stats"]
+        print(f"[{name}] {dt:.1f} s, products {sum(x['iters'] for x in stats)}", file=sys.stderr, flush=True)
         res[name] = {"seconds": dt, "value": len(s) / dt, "matvecs_total": sum(x["iters"] for x in stats),
                      "rel_res_start_median": float(np.median([x["rel_res_start"] for x in stats])),
                      "used_net": sum(x["used_net"] for x in stats),
@@ -433,12 +476,14 @@ def run_porous_hmat(args, afs, mg, np, torch):
 
 def run_porous_afs_matrix_free(args, afs, mg, np, torch):
     """The whole pipeline at 300,516 unknowns: adaptive frequency sampling from
-    J0 = 8 Chebyshev frequencies (band of Ns = 64: Omega = 0.67 at T = 300,
-    eta = 0.023) driving mixed matrix-free solves (FP32 on-the-fly inner
-    products, FP64 residuals, each new frequency started from the nearest
-    sampled solution), the vector-fitting model's time response at 512 steps
-    (Eq. 6), and the Fourier-series inversion (Eq. 4, FFT) of the same model
-    sampled on the FSM grid as a cross-check.  Prints a line per solve."""
+    J0 = 8 Chebyshev frequencies (band of Ns = --afs-ns at T = 300, eta = 0.023:
+    Omega = 0.67 for 64, 5.36 for 512) driving mixed matrix-free solves (FP32
+    inner products on the fly or through the hierarchical form, FP64
+    residuals, each new frequency started from the nearest sampled solution),
+    the vector-fitting model's time response at 512 steps (Eq. 6), and the
+    Fourier-series inversion (Eq. 4, FFT) of the same model sampled on the FSM
+    grid as a cross-check; the host time of every AFS step between two
+    responses.  Prints a line per solve."""
     mesh = mg.lattice_block(4, 39, 3, 2000, rmax=0.45)
     t0 = time.perf_counter()
     P = afs.Problem.from_mesh(mesh)
@@ -449,11 +494,16 @@ def run_porous_afs_matrix_free(args, afs, mg, np, torch):
     loaded = np.nonzero(np.abs(np.asarray(mesh.bc_shape)).sum(1) > 0)[0]
     dofs = np.sort(3 * rng.choice(loaded, 6, replace=False) + 2)
     shape = np.asarray(mesh.bc_shape, np.complex128)
-    base = dict(tol=args.tol, precision=afs.PREC_MIXED, matrix_free=args.matrix_free, restart=100, max_iter=4000,
-                batch=1, precond=args.precond, hmat_eps=args.hmat_eps)
-    solved, log = {}, []
+    base = dict(tol=args.tol, precision=afs.PREC_MIXED, matrix_free=args.matrix_free, restart=args.restart,
+                max_iter=6000, batch=1, precond=args.precond, hmat_eps=args.hmat_eps)
+    solved, log, gaps = {}, [], []
+    t_back = [None]  # when the last response returned to the AFS loop
 
     def response(sv):
+        if t_back[0] is not None:
+            # host time of the AFS step between two responses: vector fitting
+            # of the observed and test functions, E1 / E2, the next frequencies
+            gaps.append(time.perf_counter() - t_back[0])
         rows = []
         for sk in sv:
             o = afs.SolveOptions(**base)
@@ -476,6 +526,7 @@ def run_porous_afs_matrix_free(args, afs, mg, np, torch):
                         "fp64": st["gemv64_count"], "rel_res_fp64": st["rel_res_fp64"]})
             print(f"[afs-300k] s={sk.real:.4f}{sk.imag:+.4f}i {log[-1]['seconds']:.1f}s inner={st['iters']} "
                   f"rel={st['rel_res_fp64']:.1e}", file=sys.stderr, flush=True)
+        t_back[0] = time.perf_counter()
         return np.array(rows)
 
     params = afs.afs_params(T, eta, Ns, J0=8, max_Nc=args.afs_max)
@@ -504,6 +555,12 @@ def run_porous_afs_matrix_free(args, afs, mg, np, torch):
             "converged": bool(r["converged"]), "model_order": len(r["poles"]),
             "E1": [float(x) for x in r["E1"][-3:]], "E2": [float(x) for x in r["E2"][-3:]],
             "model_vs_samples_max_rel": fit_err, "fsm_vs_eq6_max_rel": fsm_gap,
+            "capped": bool(r.get("capped", False)),
+            "E1_history": [float(x) for x in r["E1"]], "E2_history": [float(x) for x in r["E2"]],
+            "poles_right_of_eta": int(np.sum(np.real(r["poles"]) > eta)),
+            "host_afs_step_s": {"max": max(gaps) if gaps else 0.0, "mean": float(np.mean(gaps)) if gaps else 0.0,
+                                "total": float(np.sum(gaps)), "steps": len(gaps)},
+            "solve_s_total": float(sum(x["seconds"] for x in log)),
             "time_response_512_peak": float(np.max(np.abs(h512))), "solves": log}
 
 
@@ -620,31 +677,10 @@ def run_cavity_nystrom(args, afs, mg, np, torch):
     return res
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print(f"bench.py: the benchmark runs on one GPU; --gpus {args.gpus} is not supported "
-              "(the frequencies would shard across GPUs with no communication beyond returning the observed values)", file=sys.stderr)
-        sys.exit(2)
-    import numpy as np
-    import torch
-
-    import paper_1511_04355_amd as afs
-    from synth import meshgen as mg
-
-    torch.cuda.set_device(0)
-    if args.workload != "cavity_L4":
-        fn = {"pmc_probe": lambda: run_pmc_probe(afs, mg, np, torch),
-              "cavity_L2_batched": lambda: run_cavity_L2_batched(args, afs, mg, np, torch),
-              "blocks_batched": lambda: run_blocks_batched(args, afs, mg, np, torch),
-              "porous_learned": lambda: run_porous_learned(args, afs, mg, np, torch),
-              "porous_matrix_free": lambda: run_porous_matrix_free(args, afs, mg, np, torch),
-              "porous_afs_matrix_free": lambda: run_porous_afs_matrix_free(args, afs, mg, np, torch),
-              "cavity_L4_afs": lambda: run_cavity_L4_afs(args, afs, mg, np, torch),
-              "cavity_nystrom": lambda: run_cavity_nystrom(args, afs, mg, np, torch),
-              "porous_hmat": lambda: run_porous_hmat(args, afs, mg, np, torch)}[args.workload]
-        print(json.dumps(fn()), flush=True)
-        return
+def run_cavity_L4_line(args, afs, mg, np, torch, steps, warmup, cpu):
+    """The pressurised cavity at icosphere level 4 (15,360 unknowns), all 64
+    frequencies per step: mixed, extrapolated warm start, assembly overlapped
+    (value), plain FP64 and the lockstep batched call beside it."""
     mesh = mg.cavity(args.level)
     s = mg.cavity_frequencies(args.nfreq)
     bc = torch.from_numpy(np.stack([np.asarray(mesh.bc_shape, np.complex128) / sk for sk in s])).cuda()
@@ -657,7 +693,7 @@ def main():
     warm = {"prev": afs.WARM_PREV, "none": afs.WARM_NONE, "learned": afs.WARM_LEARNED,
             "extrap": afs.WARM_EXTRAP}[args.warm]
     mixed = afs.SolveOptions(tol=args.tol, precision=afs.PREC_MIXED, warm_start=warm, profile=1, batch=args.batch)
-    ms_mixed, out = timed(P, s, bc, mixed, args.steps, args.warmup, torch)
+    ms_mixed, out = timed(P, s, bc, mixed, steps, warmup, torch)
     st = out["stats"]
     worst = max(x["rel_res_fp64"] for x in st)
     assert worst <= args.tol, f"mixed path missed the tolerance: {worst}"
@@ -676,8 +712,8 @@ def main():
         "value": args.nfreq / (ms_mixed * 1e-3),
         "unit": "frequency solves/s",
         "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
+        "steps": steps,
+        "warmup": warmup,
         "ms_per_step": ms_mixed,
         "higher_is_better": True,
         "scaling": "weak",
@@ -710,7 +746,7 @@ def main():
     if not args.no_plain:
         plain = afs.SolveOptions(tol=args.tol, precision=afs.PREC_FP64, warm_start=afs.WARM_NONE, profile=1,
                                  batch=1)
-        ms_plain, out = timed(P, s, bc, plain, args.steps, args.warmup, torch)
+        ms_plain, out = timed(P, s, bc, plain, steps, warmup, torch)
         sp = out["stats"]
         wp = max(x["rel_res_fp64"] for x in sp)
         gp_ms = sum(x["gemv_ms"] for x in sp)
@@ -725,14 +761,14 @@ def main():
         del out
     if not args.no_batched:
         bopts = afs.SolveOptions(tol=args.tol, precision=afs.PREC_MIXED)
-        for _ in range(args.warmup):
+        for _ in range(warmup):
             outs, _ = afs.solve_batched([P], [s], [bc], bopts)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for _ in range(args.steps):
+        for _ in range(steps):
             outs, _ = afs.solve_batched([P], [s], [bc], bopts)
         torch.cuda.synchronize()
-        ms_b = (time.perf_counter() - t0) * 1e3 / args.steps
+        ms_b = (time.perf_counter() - t0) * 1e3 / steps
         sb = outs[0]["stats"]
         res["batched_lockstep"] = {"value": args.nfreq / (ms_b * 1e-3), "ms_per_step": ms_b,
                                    "max_rel_res_fp64": max(x["rel_res_fp64"] for x in sb),
@@ -740,8 +776,222 @@ def main():
                                    "path": "all frequencies in waves solved in lockstep, FP32 inner cycles, "
                                            "FP64 residuals, next wave assembled during the current solve"}
         del outs
-    if not args.no_cpu:
+    if cpu:
         res["cpu_baseline"] = cpu_baseline(mesh, s, args.cpu_freqs)
+    return res
+
+
+# ---------------------------------------------------------------- contract --
+C5_T, C5_KAPPA, C5_NS = 300.0, 3.0, 512
+C5_BAND = 0.25          # the timed frequencies lie in omega <= C5_BAND * Omega_s
+C5_RESTART = 1500
+C5_HMAT_EPS = 1e-5
+
+
+def c5_frequencies(n, om_max, eta):
+    """n Laplace parameters on Re s = eta, omega in [0, om_max], in the order an
+    adaptive sampling run visits a band: eight points clustered towards
+    omega = 0 (om_max (1 - cos(j pi / 14)), j = 0..7), then repeatedly the
+    midpoint of the widest gap between the points so far (ties: lowest
+    omega)."""
+    import numpy as np
+    om = [om_max * (1.0 - np.cos(j * np.pi / 14.0)) for j in range(8)]
+    while len(om) < n:
+        srt = sorted(om)
+        gaps = [(srt[i + 1] - srt[i], -i) for i in range(len(srt) - 1)]
+        _, mi = max(gaps)
+        om.append(0.5 * (srt[-mi] + srt[-mi + 1]))
+    return eta + 1j * np.array(om[:n])
+
+
+def c5_cpu_baseline(mesh, sk, products_per_solve):
+    """The oracle on a bounded sample of the 300,516-unknown operator: full
+    rows (every column: far rule, subdivided near pairs, self element) of
+    sampled collocation points at one frequency, timed on all host threads.
+    A matrix-vector product of the oracle is those rows for every point; a
+    solve takes the plain FP64 path's product count."""
+    import numpy as np
+
+    from oracle import bem
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
+    rows = np.arange(0, mesh.n_tri, max(1, mesh.n_tri // 640))[:640]
+    t0 = time.perf_counter()
+    A, b = bem.assemble(mesh, sk, rows=rows)
+    dt = time.perf_counter() - t0
+    del A, b
+    t_product = dt * mesh.n_tri / len(rows)
+    return {"value": 1.0 / (t_product * products_per_solve), "unit": "frequency solves/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"{3 * len(rows)} of {3 * mesh.n_tri} rows of A(s) at s = {complex(sk):.4f} (all columns) "
+                      f"in {dt:.1f} s; a product of the oracle = every row ({t_product:.0f} s), a solve = "
+                      f"{products_per_solve:.0f} products (the plain FP64 GPU path's count): extrapolated from "
+                      f"the row sample, not a measured solve",
+            "oracle_product_s": t_product}
+
+
+def run_contract_c5(args, afs, mg, np, torch):
+    """The contract line: 64-void porous block, 300,516 unknowns."""
+    t_mesh = time.perf_counter()
+    mesh = mg.lattice_block(4, 39, 3, 2000, rmax=0.45)
+    t0 = time.perf_counter()
+    P = afs.Problem.from_mesh(mesh)
+    torch.cuda.synchronize()
+    plan_s = time.perf_counter() - t0
+    N = P.N
+    eta = C5_KAPPA * np.log(10.0) / C5_T
+    om_s = np.pi * C5_NS / C5_T
+    W, K = args.warmup, args.steps
+    s = c5_frequencies(W + K, C5_BAND * om_s, eta)
+    bc = _bcs(mesh, s, torch, np)
+    print(f"[c5] mesh {time.perf_counter() - t_mesh - plan_s:.1f} s, plan {plan_s:.1f} s, {W} + {K} frequencies",
+          file=sys.stderr, flush=True)
+    opts = afs.SolveOptions(tol=args.tol, precision=afs.PREC_MIXED, matrix_free=2, hmat_eps=C5_HMAT_EPS,
+                            precond=1, restart=C5_RESTART, max_iter=6000, warm_start=afs.WARM_LEARNED,
+                            learn_aug=args.learn_aug, profile=1, batch=args.batch)
+    # warm-up: the first W frequencies (the cluster tree, the pools, the network's first samples)
+    t0 = time.perf_counter()
+    out_w = P.solve(s[:W], bc[:W], opts, want_ut=True) if W > 0 else None
+    torch.cuda.synchronize()
+    warm_s = time.perf_counter() - t0
+    print(f"[c5] warm-up {W} solves {warm_s:.1f} s", file=sys.stderr, flush=True)
+    x0 = out_w["a"][W - 1:W].clone() if W > 0 else None
+    del out_w
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = P.solve(s[W:], bc[W:], opts, x0=x0, want_ut=True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    st = out["stats"]
+    worst = max(x["rel_res_fp64"] for x in st)
+    assert worst <= args.tol, f"optimised path missed the tolerance: {worst}"
+    print(f"[c5] timed {K} solves {elapsed:.1f} s, worst FP64 residual {worst:.2e}", file=sys.stderr, flush=True)
+    info = P.info()
+    near_bytes = (info["n_near_pairs"] + info["n_tri"]) * 144.0
+    g_ms = sum(x["gemv_ms"] for x in st)
+    g_n = sum(x["gemv_count"] for x in st)
+    g64_ms = sum(x["gemv64_ms"] for x in st)
+    g64_n = sum(x["gemv64_count"] for x in st)
+    hm_bytes = sum(x["bytes"] - x["gemv64_count"] * near_bytes for x in st) / max(g_n, 1)
+    asm_ms = sum(x["t_assemble_ms"] for x in st)
+    avg_ms = g_ms / max(g_n, 1)
+    achieved = hm_bytes / (avg_ms * 1e-3) / 1e9
+    roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": HMAT_TRAFFIC_BYTES,
+            "kernel": "hierarchical FP32 product (hm_vt_kernel + hm_apply_kernel + gather/sum; dense near "
+                      "blocks and cross-approximation factors streamed once per product)",
+            "bytes_per_launch": hm_bytes, "avg_launch_ms": avg_ms, "launches": g_n,
+            "ms_per_step": g_ms / K}
+    res = {
+        "metric": METRIC,
+        "value": K / elapsed,
+        "unit": "frequency solves/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": elapsed * 1e3 / K,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 operator (hierarchical) / f64 Arnoldi, residual, near field",
+        "data": "synthetic",
+        "config": {"workload": f"porous block 4x4x4 with 64 seeded voids (C5: {mesh.n_tri} flat triangles, {N} "
+                               f"complex unknowns), {K} timed frequencies after {W} warm-up ones on Re s = "
+                               f"{eta:.4f}, omega in [0, {C5_BAND * om_s:.3f}] (the lowest quarter of the band "
+                               f"of T = {C5_T:g}, Ns = {C5_NS}) in adaptive-sampling order, step traction on "
+                               f"z = 0, z = 4 fixed, FP64 true rel. residual <= {args.tol}",
+                   "path": f"mixed: FP32 hierarchical inner operator (cross approximation, eps "
+                           f"{C5_HMAT_EPS:g}) + FP64 on-the-fly residual, GMRES({C5_RESTART}), cluster "
+                           f"block-Jacobi, learned warm start (network trained on the GPU after every solve"
+                           f"{', prediction also augmenting the first cycle' if args.learn_aug else ''}), "
+                           + ("two frequencies in flight (hierarchical build of s_k+1 during the Krylov phase "
+                              "of s_k)" if args.batch != 1 else "one frequency at a time"),
+                   "plan_s": plan_s, "warmup_s": warm_s},
+        "roofline": roof,
+        "solve": {"max_rel_res_fp64": worst,
+                  "inner_products_per_solve": g_n / K,
+                  "fp64_products_per_solve": g64_n / K,
+                  "inner_product_ms": avg_ms,
+                  "fp64_product_ms": g64_ms / max(g64_n, 1),
+                  "build_ms_per_solve": asm_ms / K,
+                  "network_used": sum(x["used_net"] for x in st),
+                  "omega": [float(v) for v in np.imag(s[W:])],
+                  "seconds_inner_fp64_build": [g_ms * 1e-3, g64_ms * 1e-3, asm_ms * 1e-3]},
+    }
+    del out
+    if not args.no_plain:
+        # plain FP64 on the lowest frequency of the list (s = eta): one solve
+        # takes minutes; higher frequencies would take hours
+        sp = s[:1]
+        plain = afs.SolveOptions(tol=args.tol, precision=afs.PREC_FP64, matrix_free=1, restart=50,
+                                 max_iter=args.plain_max_iter, warm_start=afs.WARM_NONE, profile=1, batch=1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        o = P.solve(sp, bc[:1], plain, want_ut=True)
+        torch.cuda.synchronize()
+        t_plain = time.perf_counter() - t0
+        x = o["stats"][0]
+        print(f"[c5] plain FP64 at s = {complex(sp[0]):.4f}: {t_plain:.1f} s, {x['iters']} products, "
+              f"rel {x['rel_res_fp64']:.1e}", file=sys.stderr, flush=True)
+        # the optimised operator and solver on the same frequency alone, zero start
+        same = afs.SolveOptions(tol=args.tol, precision=afs.PREC_MIXED, matrix_free=2, hmat_eps=C5_HMAT_EPS,
+                                precond=1, restart=C5_RESTART, max_iter=6000, profile=1, batch=1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        o2 = P.solve(sp, bc[:1], same, want_ut=True)
+        torch.cuda.synchronize()
+        t_same = time.perf_counter() - t0
+        res["plain_fp64"] = {"value": 1.0 / t_plain, "seconds": t_plain, "s": [float(sp[0].real), 0.0],
+                             "products": x["iters"], "rel_res_fp64": x["rel_res_fp64"],
+                             "converged": x["status"] == 0,
+                             "product_ms": x["gemv_ms"] / max(x["gemv_count"], 1),
+                             "path": "FP64 on-the-fly operator, GMRES(50), 3x3 block-Jacobi, zero start, one "
+                                     "frequency; timed on s = eta only (a solve at the timed list's higher "
+                                     "frequencies needs thousands of 0.6 s products)"}
+        res["optimised_same_s"] = {"seconds": t_same, "rel_res_fp64": o2["stats"][0]["rel_res_fp64"],
+                                   "inner_products": o2["stats"][0]["gemv_count"],
+                                   "fp64_products": o2["stats"][0]["gemv64_count"],
+                                   "path": "the optimised operator and solver alone on s = eta, zero start"}
+        res["speedup_same_s"] = t_plain / t_same
+        del o, o2
+    if not args.no_cpu:
+        prods = res.get("plain_fp64", {}).get("products", 100)
+        res["cpu_baseline"] = c5_cpu_baseline(mesh, s[0], prods)
+    P.close()
+    if not args.no_secondary:
+        res["secondary_cavity_L4"] = run_cavity_L4_line(args, afs, mg, np, torch, steps=3, warmup=1, cpu=False)
+    return res
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py: the benchmark runs on one GPU; --gpus {args.gpus} is not supported "
+              "(the frequencies would shard across GPUs with no communication beyond returning the observed values)", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_1511_04355_amd as afs
+    from synth import meshgen as mg
+
+    torch.cuda.set_device(0)
+    if args.workload not in ("porous_C5", "cavity_L4"):
+        fn = {"pmc_probe": lambda: run_pmc_probe(afs, mg, np, torch),
+              "pmc_probe_c5": lambda: run_pmc_probe_c5(args, afs, mg, np, torch),
+              "cavity_L2_batched": lambda: run_cavity_L2_batched(args, afs, mg, np, torch),
+              "blocks_batched": lambda: run_blocks_batched(args, afs, mg, np, torch),
+              "porous_learned": lambda: run_porous_learned(args, afs, mg, np, torch),
+              "porous_matrix_free": lambda: run_porous_matrix_free(args, afs, mg, np, torch),
+              "porous_afs_matrix_free": lambda: run_porous_afs_matrix_free(args, afs, mg, np, torch),
+              "cavity_L4_afs": lambda: run_cavity_L4_afs(args, afs, mg, np, torch),
+              "cavity_nystrom": lambda: run_cavity_nystrom(args, afs, mg, np, torch),
+              "porous_hmat": lambda: run_porous_hmat(args, afs, mg, np, torch)}[args.workload]
+        print(json.dumps(fn()), flush=True)
+        return
+    if args.workload == "cavity_L4":
+        res = run_cavity_L4_line(args, afs, mg, np, torch, args.steps, args.warmup, not args.no_cpu)
+    else:
+        res = run_contract_c5(args, afs, mg, np, torch)
     print(json.dumps(res), flush=True)
 
 

@@ -296,8 +296,11 @@ typedef struct {
     int32_t learn_aug;   /* AFSBEM_WARM_LEARNED: role of the network's prediction.  0: it enters
                             the starting iterate (residual-minimising combination with the
                             previous solution); 1: it augments the search space of the first
-                            GMRES cycle instead (flexible form, coefficient from the same
-                            least-squares problem; the start is the previous solution); 2: both */
+                            GMRES cycle instead (its image is projected out of the Arnoldi
+                            vectors and its coefficient found by the same least-squares problem;
+                            the start is the previous solution; a vector whose projection
+                            lowers the residual by less than 5 % is declined after its product);
+                            2: both */
     int32_t reserved_;   /* 0 */
 } afsbem_solve_opts;
 

@@ -154,7 +154,7 @@ void hmat_build(const Problem &p, double eta, int kmax, HmatPlan &H, bool upload
     const int64_t nd = (int64_t)H.dense.size() / 4, nl = (int64_t)H.lowrank.size() / 4;
     H.dense_off.assign(nd + 1, 0);
     for (int64_t d = 0; d < nd; ++d)
-        H.dense_off[d + 1] = H.dense_off[d] + 9 * (H.dense[4 * d + 1] - H.dense[4 * d]) *
+        H.dense_off[d + 1] = H.dense_off[d] + dense_rows_padded(H.dense[4 * d + 1] - H.dense[4 * d]) * 3 *
                                                    (H.dense[4 * d + 3] - H.dense[4 * d + 2]);
     H.lr_rows = 0;
     H.lr_order.clear();

@@ -20,6 +20,10 @@ namespace afsbem {
 struct Workspace;
 
 constexpr int kHmatKmax = 128;  // terms per low-rank block at most
+// dense blocks are column-major with an even row count (the product reads two
+// rows per 16-byte load); the padding row is zero
+constexpr int kHmatApplyParts = 8;  // partial sums per row of the product (parts of each leaf's block list)
+__host__ __device__ inline int64_t dense_rows_padded(int64_t n_elems) { return 3 * n_elems + ((3 * n_elems) & 1); }
 
 struct HmatPlan {
     double eta = 1.0;
@@ -27,7 +31,7 @@ struct HmatPlan {
     std::vector<int32_t> perm;      // tree position -> element
     std::vector<int64_t> dense;     // [nd][4] a0, a1, b0, b1 (tree positions of elements)
     std::vector<int64_t> lowrank;   // [nl][4]
-    std::vector<int64_t> dense_off; // [nd+1] offsets (complex entries) of the dense blocks
+    std::vector<int64_t> dense_off; // [nd+1] offsets (complex entries) of the dense blocks (padded rows)
     int64_t lr_rows = 0;            // sum over low-rank blocks of R + C (one term's entries)
     std::vector<int32_t> lr_order;  // low-rank blocks by size: at most 64 elements a side, at most 128, larger
     int64_t n_small = 0, n_mid = 0;
@@ -55,9 +59,10 @@ void hmat_ensure(Problem &p, double eta);
 // (after the matrix-free block setup: nearblk, selfblk), ranks and status
 // copied to pinned host memory on st.  hmat_finish, once st's work has
 // completed, reads them: false when an admissible block did not reach eps
-// within kmax (the operator then stays the on-the-fly one).
+// within kmax or found the pool spent (ws.hm_exhausted; the operator then
+// stays the on-the-fly one unless the build is repeated).
 void hmat_setup(const Problem &p, Workspace &ws, const KernelParams &kp, double eps, hipStream_t st);
-bool hmat_finish(const Problem &p, Workspace &ws);
+bool hmat_finish(Problem &p, Workspace &ws);
 // y = A_H x
 void hmat_apply(const Problem &p, const Workspace &ws, const double *x, double *y, hipStream_t st);
 

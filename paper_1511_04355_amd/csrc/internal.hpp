@@ -143,6 +143,7 @@ struct Problem {
     LearnState *learn = nullptr;                     // warm-start network (created on first use)
     BatchArena *barena = nullptr;                    // batched-solve memory (created on first use)
     HmatPlan *hmat = nullptr;                        // hierarchical far field (created on first use)
+    double hm_need = 0.0;                            // factor entries the largest build so far took
 };
 
 // ----------------------------------------------------- kernel launchers --

@@ -133,8 +133,11 @@ __global__ __launch_bounds__(256) void hm_dense_kernel(
     const int64_t d = blockIdx.x;
     const int64_t a0 = dense[4 * d], b0 = dense[4 * d + 2];
     const int na = (int)(dense[4 * d + 1] - a0), nb = (int)(dense[4 * d + 3] - b0);
-    const int64_t R = 3 * (int64_t)na;
+    const int64_t R = dense_rows_padded(na);
     float2 *blk_out = out + dense_off[d];
+    if (R != 3 * (int64_t)na)
+        for (int k = threadIdx.x; k < 3 * nb; k += 256)
+            blk_out[(int64_t)k * R + R - 1] = make_float2(0.f, 0.f);
     for (int q = threadIdx.x; q < na * nb; q += 256) {
         const int r = q % na, k = q / na;
         const int64_t m = perm[a0 + r], n = perm[b0 + k];
@@ -214,12 +217,16 @@ __global__ __launch_bounds__(NT) void hm_aca_kernel(
     __shared__ int64_t si[NT];
     __shared__ double2 cf[kHmKmax];
     __shared__ int64_t used[kHmKmax + 1];
+    __shared__ int64_t soff[kHmKmax];  // pool offsets of the terms found so far (read in every residual)
     __shared__ int64_t off_k;
     const int t = threadIdx.x;
     const int64_t l = ids[blockIdx.x];
     const int64_t a0 = lowrank[4 * l], b0 = lowrank[4 * l + 2];
     const int64_t na = lowrank[4 * l + 1] - a0, nb = lowrank[4 * l + 3] - b0;
     const int64_t R = 3 * na, C = 3 * nb;
+    // a term's U (R entries) and V (C entries) each start on an even entry, so
+    // that the products read them with 16-byte loads
+    const int64_t Rp = R + (R & 1), Cp = C + (C & 1);
     int64_t *myoffs = offs + l * kmax;
     int64_t istar = 0;
     double S2 = 0.0;
@@ -245,13 +252,15 @@ __global__ __launch_bounds__(NT) void hm_aca_kernel(
     while (k < kmax) {
         // ---- the term's slot in the pool (a probe row is evaluated, not stored)
         if (t == 0 && !probing) {
-            const unsigned long long o = atomicAdd(ctr, (unsigned long long)(R + C));
-            off_k = (o + (unsigned long long)(R + C) <= pool_cap) ? (int64_t)o : -1;
-            if (off_k >= 0)
+            const unsigned long long o = atomicAdd(ctr, (unsigned long long)(Rp + Cp));
+            off_k = (o + (unsigned long long)(Rp + Cp) <= pool_cap) ? (int64_t)o : -1;
+            if (off_k >= 0) {
                 myoffs[k] = off_k;
+                soff[k] = off_k;
+            }
         }
         for (int q = t; q < k; q += NT) {
-            const float2 u = pool[myoffs[q] + istar];
+            const float2 u = pool[soff[q] + istar];
             cf[q] = make_double2(u.x, u.y);
         }
         __syncthreads();
@@ -259,7 +268,7 @@ __global__ __launch_bounds__(NT) void hm_aca_kernel(
             status = 2;
             break;
         }
-        float2 *Uk = pool + (probing ? 0 : off_k), *Vk = Uk + R;
+        float2 *Uk = pool + (probing ? 0 : off_k), *Vk = Uk + Rp;
         // ---- residual row istar -> V_k (unnormalised)
         const int64_t m = perm[a0 + istar / 3];
         const int al = (int)(istar % 3);
@@ -272,9 +281,10 @@ __global__ __launch_bounds__(NT) void hm_aca_kernel(
             for (int be = 0; be < 3; ++be) {
                 const int64_t c = 3 * kk + be;
                 double vr = ent[be].r, vi = ent[be].i;
+#pragma unroll 4
                 for (int q = 0; q < k; ++q) {
                     const double2 u = cf[q];
-                    const float2 v = pool[myoffs[q] + R + c];
+                    const float2 v = pool[soff[q] + Rp + c];
                     vr -= u.x * v.x - u.y * v.y;
                     vi -= u.x * v.y + u.y * v.x;
                 }
@@ -324,7 +334,7 @@ __global__ __launch_bounds__(NT) void hm_aca_kernel(
         }
         // ---- residual column jstar -> U_k
         for (int q = t; q < k; q += NT) {
-            const float2 v = pool[myoffs[q] + R + jstar];
+            const float2 v = pool[soff[q] + Rp + jstar];
             cf[q] = make_double2(v.x, v.y);
         }
         if (t == 0)
@@ -342,9 +352,10 @@ __global__ __launch_bounds__(NT) void hm_aca_kernel(
             for (int a = 0; a < 3; ++a) {
                 const int64_t r = 3 * i + a;
                 double ur = ent[a].r, ui = ent[a].i;
+#pragma unroll 4
                 for (int q = 0; q < k; ++q) {
                     const double2 v = cf[q];
-                    const float2 u = pool[myoffs[q] + r];
+                    const float2 u = pool[soff[q] + r];
                     ur -= u.x * v.x - u.y * v.y;
                     ui -= u.x * v.y + u.y * v.x;
                 }
@@ -392,91 +403,144 @@ __global__ __launch_bounds__(256) void hm_gather_kernel(int64_t n, const int32_t
 }
 
 // t[l][q] = V_q^T x on the block's columns, one wavefront per term
+// t_q = V_q^T x for every term of every low-rank block: one work-group per
+// block, sixteen lanes per term (16-byte loads, two entries each), sixteen
+// terms at a time
 __global__ __launch_bounds__(256) void hm_vt_kernel(const int64_t *__restrict__ lowrank, int kmax,
                                                     const int *__restrict__ rank, const int64_t *__restrict__ offs,
                                                     const float2 *__restrict__ pool, const double2 *__restrict__ xp,
                                                     double2 *__restrict__ tv) {
     const int64_t l = blockIdx.x;
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int g = threadIdx.x >> 4, ln = threadIdx.x & 15;
     const int64_t a0 = lowrank[4 * l], b0 = lowrank[4 * l + 2];
     const int64_t R = 3 * (lowrank[4 * l + 1] - a0), C = 3 * (lowrank[4 * l + 3] - b0);
+    const int64_t Rp = R + (R & 1), C2 = C >> 1;
     const int rk = rank[l];
-    for (int q = w; q < rk; q += 4) {
-        const float2 *V = pool + offs[l * kmax + q] + R;
+    const double2 *xb = xp + 3 * b0;
+    for (int q = g; q < rk; q += 16) {
+        const float2 *V = pool + offs[l * kmax + q] + Rp;
+        const float4 *V4 = reinterpret_cast<const float4 *>(V);
         double sr = 0.0, si = 0.0;
-        const double2 *xb = xp + 3 * b0;
-        for (int64_t c = lane; c < C; c += 64) {
-            const float2 v = V[c];
-            const double2 xv = xb[c];
-            sr += v.x * xv.x - v.y * xv.y;
-            si += v.x * xv.y + v.y * xv.x;
+#pragma unroll 4
+        for (int64_t c2 = ln; c2 < C2; c2 += 16) {
+            const float4 v = V4[c2];
+            const double2 x0 = xb[2 * c2], x1 = xb[2 * c2 + 1];
+            sr += (double)v.x * x0.x - (double)v.y * x0.y + (double)v.z * x1.x - (double)v.w * x1.y;
+            si += (double)v.x * x0.y + (double)v.y * x0.x + (double)v.z * x1.y + (double)v.w * x1.x;
         }
-        sr = wave_sum64(sr);
-        si = wave_sum64(si);
-        if (lane == 0)
+        if ((C & 1) && ln == 0) {
+            const float2 v = V[C - 1];
+            const double2 xv = xb[C - 1];
+            sr += (double)v.x * xv.x - (double)v.y * xv.y;
+            si += (double)v.x * xv.y + (double)v.y * xv.x;
+        }
+#pragma unroll
+        for (int off = 8; off > 0; off >>= 1) {
+            sr += __shfl_xor(sr, off, 16);
+            si += __shfl_xor(si, off, 16);
+        }
+        if (ln == 0)
             tv[l * kmax + q] = make_double2(sr, si);
     }
 }
 
-constexpr int kHmSplit = 4;  // work-groups per leaf: each takes every kHmSplit-th block of its list
+constexpr int kHmSplit = kHmatApplyParts;  // single-wave work-groups per leaf: each takes every kHmSplit-th block of its list
 
-// work-group (leaf L, part blockIdx.y): rows of leaf L (at most 3 kClusterElems)
-// over the blocks it - leaf_ptr[L] = blockIdx.y (mod kHmSplit) of the leaf's
-// list; partial sums in tree order, yp[part][3 n]
-__global__ __launch_bounds__(128) void hm_apply_kernel(
+__device__ __forceinline__ void cmac2(double &r0, double &i0, double &r1, double &i1, const float4 v,
+                                      const double2 c) {
+    r0 += (double)v.x * c.x - (double)v.y * c.y;
+    i0 += (double)v.x * c.y + (double)v.y * c.x;
+    r1 += (double)v.z * c.x - (double)v.w * c.y;
+    i1 += (double)v.z * c.y + (double)v.w * c.x;
+}
+
+// one wavefront per (leaf L, part blockIdx.y): lane l owns rows 2l, 2l + 1 of
+// the leaf (at most 96 rows, 48 lanes) and sums the blocks it - leaf_ptr[L] =
+// blockIdx.y (mod kHmSplit) of the leaf's list: dense blocks column by column
+// (16-byte loads of two rows, eight columns in flight), low-rank blocks term by
+// term (the leaf's rows of U_q times t_q, eight terms in flight; offsets and
+// t_q are wave-uniform scalar loads).  Partial sums in tree order, yp[part][3 n].
+__global__ __launch_bounds__(64) void hm_apply_kernel(
     const int64_t *__restrict__ leaves, const int64_t *__restrict__ leaf_ptr, const int32_t *__restrict__ leaf_item,
     const int64_t *__restrict__ dense, const int64_t *__restrict__ dense_off, const int64_t *__restrict__ lowrank,
-    int kmax, const int *__restrict__ rank, const int64_t *__restrict__ offs, const int32_t *__restrict__ perm,
-    const float2 *__restrict__ dblk, const float2 *__restrict__ pool, const double2 *__restrict__ tv,
-    const double2 *__restrict__ xp, int64_t n_el, double2 *__restrict__ yp) {
-    __shared__ int64_t so[kHmKmax];
-    __shared__ double2 stq[kHmKmax];
+    int kmax, const int *__restrict__ rank, const int64_t *__restrict__ offs, const float2 *__restrict__ dblk,
+    const float2 *__restrict__ pool, const double2 *__restrict__ tv, const double2 *__restrict__ xp, int64_t n_el,
+    double2 *__restrict__ yp) {
     const int64_t L = blockIdx.x;
     const int64_t L0 = leaves[2 * L], rows = 3 * (leaves[2 * L + 1] - L0);
-    const int r = threadIdx.x;
+    const int64_t Rp = rows + (rows & 1);
+    const int lane = threadIdx.x;
+    const int64_t r = 2 * (int64_t)lane;
     const bool live = r < rows;
-    double ar = 0.0, ai = 0.0;
+    double a0r = 0.0, a0i = 0.0, a1r = 0.0, a1i = 0.0;
     for (int64_t it = leaf_ptr[L] + blockIdx.y; it < leaf_ptr[L + 1]; it += kHmSplit) {
         const int32_t item = leaf_item[it];
         if (item >= 0) {
             const int64_t b0 = dense[4 * item + 2];
             const int64_t C = 3 * (dense[4 * item + 3] - b0);
-            const float2 *D = dblk + dense_off[item];
+            const float4 *D = reinterpret_cast<const float4 *>(dblk + dense_off[item]) + lane;
+            const int64_t ld = Rp >> 1;  // float4 per column
             const double2 *xb = xp + 3 * b0;
-#pragma unroll 8
-            for (int64_t c = 0; c < C; ++c) {
-                const double2 xv = xb[c];
-                if (live) {
-                    const float2 a = D[c * rows + r];
-                    ar += (double)a.x * xv.x - (double)a.y * xv.y;
-                    ai += (double)a.x * xv.y + (double)a.y * xv.x;
-                }
+            int64_t c = 0;
+            for (; c + 8 <= C; c += 8) {
+                float4 v[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+                    v[u] = live ? D[(c + u) * ld] : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+                    cmac2(a0r, a0i, a1r, a1i, v[u], xb[c + u]);
+            }
+            for (; c < C; ++c) {
+                const float4 v = live ? D[c * ld] : make_float4(0.f, 0.f, 0.f, 0.f);
+                cmac2(a0r, a0i, a1r, a1i, v, xb[c]);
             }
         } else {
-            // the block's term offsets and t values staged once (every thread takes this branch)
             const int64_t lb = -(int64_t)item - 1;
-            const int64_t rr = 3 * (L0 - lowrank[4 * lb]) + r;
+            const int64_t rr = 3 * (L0 - lowrank[4 * lb]) + r;  // this lane's first row within U_q
+            const bool even = ((L0 - lowrank[4 * lb]) & 1) == 0;  // wave-uniform: 16-byte aligned rows
             const int rk = rank[lb];
-            __syncthreads();
-            for (int q = r; q < rk; q += 128) {
-                so[q] = offs[lb * kmax + q];
-                stq[q] = tv[lb * kmax + q];
-            }
-            __syncthreads();
-            if (live)
-                for (int q = 0; q < rk; ++q) {
-                    const float2 u = pool[so[q] + rr];
-                    const double2 tq = stq[q];
-                    ar += u.x * tq.x - u.y * tq.y;
-                    ai += u.x * tq.y + u.y * tq.x;
+            const int64_t *ob = offs + lb * kmax;
+            const double2 *tb = tv + lb * kmax;
+            int q = 0;
+            for (; q + 8 <= rk; q += 8) {
+                float4 u[8];
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const float2 *U = pool + ob[q + e] + rr;
+                    if (!live) {
+                        u[e] = make_float4(0.f, 0.f, 0.f, 0.f);
+                    } else if (even) {
+                        u[e] = *reinterpret_cast<const float4 *>(U);
+                    } else {
+                        const float2 lo = U[0], hi = U[1];
+                        u[e] = make_float4(lo.x, lo.y, hi.x, hi.y);
+                    }
                 }
+#pragma unroll
+                for (int e = 0; e < 8; ++e)
+                    cmac2(a0r, a0i, a1r, a1i, u[e], tb[q + e]);
+            }
+            for (; q < rk; ++q) {
+                const float2 *U = pool + ob[q] + rr;
+                float4 u = make_float4(0.f, 0.f, 0.f, 0.f);
+                if (live) {
+                    const float2 lo = U[0], hi = U[1];
+                    u = make_float4(lo.x, lo.y, hi.x, hi.y);
+                }
+                cmac2(a0r, a0i, a1r, a1i, u, tb[q]);
+            }
         }
     }
-    if (live)
-        yp[(int64_t)blockIdx.y * 3 * n_el + 3 * L0 + r] = make_double2(ar, ai);
+    if (live) {
+        double2 *out = yp + (int64_t)blockIdx.y * 3 * n_el + 3 * L0 + r;
+        out[0] = make_double2(a0r, a0i);
+        if (r + 1 < rows)
+            out[1] = make_double2(a1r, a1i);
+    }
 }
 
-// y = sum of the kHmSplit partial sums, back to element order
+// y = sum of the kHmSplit partial sums (fixed order), back to element order
 __global__ __launch_bounds__(256) void hm_sum_kernel(int64_t n, const int32_t *__restrict__ perm,
                                                      const double2 *__restrict__ yp, double2 *__restrict__ y) {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -498,7 +562,7 @@ void hmat_setup(const Problem &p, Workspace &ws, const KernelParams &kp, double 
     const HmatPlan &H = *p.hmat;
     const DevicePlan &d = p.dev;
     const int64_t nd = (int64_t)H.dense.size() / 4, nl = (int64_t)H.lowrank.size() / 4;
-    ws.hm_alloc(H);
+    ws.hm_alloc(p, H);
     if (nd)
         hm_dense_kernel<<<(unsigned)nd, 256, 0, st>>>(kp, d.colx, d.coly, d.colz, d.src, d.coef, d.near_ptr,
                                                        d.near_col, ws.nearblk, ws.selfblk, H.d_perm, H.d_dense,
@@ -531,16 +595,20 @@ void hmat_setup(const Problem &p, Workspace &ws, const KernelParams &kp, double 
         AFS_HIP(hipMemcpyAsync(ws.hm_host, ws.hm_rank, nl * sizeof(int), hipMemcpyDeviceToHost, st));
         AFS_HIP(hipMemcpyAsync(ws.hm_host + nl, ws.hm_status, nl * sizeof(int), hipMemcpyDeviceToHost, st));
     }
+    AFS_HIP(hipMemcpyAsync(ws.hm_used_host, ws.hm_ctr, sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
     ws.hm_ok = false;  // until hmat_finish has read the ranks
 }
 
-bool hmat_finish(const Problem &p, Workspace &ws) {
+bool hmat_finish(Problem &p, Workspace &ws) {
     const int64_t nl = (int64_t)p.hmat->lowrank.size() / 4;
     const std::vector<int64_t> &lr = p.hmat->lowrank;
     ws.hm_max_rank = 0;
     bool ok = true;
     // bytes one product streams: the dense blocks and every term's U and V (FP32 complex)
-    double entries = (double)p.hmat->dense_off.back();
+    double entries = 0.0;
+    const std::vector<int64_t> &dn = p.hmat->dense;
+    for (size_t d = 0; d < dn.size() / 4; ++d)
+        entries += 9.0 * (double)(dn[4 * d + 1] - dn[4 * d]) * (double)(dn[4 * d + 3] - dn[4 * d + 2]);
     for (int64_t l = 0; l < nl; ++l) {
         ws.hm_max_rank = std::max(ws.hm_max_rank, ws.hm_host[l]);
         ok = ok && ws.hm_host[nl + l] == 0;
@@ -548,6 +616,16 @@ bool hmat_finish(const Problem &p, Workspace &ws) {
     }
     ws.hm_bytes = entries * 8.0;
     ws.hm_ok = ok;
+    // a block that found the pool spent (status 2): the next build asks for
+    // twice the pool or 1.5 x what this one requested, whichever is larger
+    ws.hm_exhausted = false;
+    for (int64_t l = 0; l < nl && !ok; ++l)
+        ws.hm_exhausted = ws.hm_exhausted || ws.hm_host[nl + l] == 2;
+    const double used = (double)*ws.hm_used_host;
+    if (ws.hm_exhausted)
+        ws.hm_want = std::max((size_t)(2 * ws.hm_pool_cap), (size_t)(1.5 * used));
+    else
+        p.hm_need = std::max(p.hm_need, used);
     return ok;
 }
 
@@ -559,9 +637,9 @@ void hmat_apply(const Problem &p, const Workspace &ws, const double *x, double *
     if (nl)
         hm_vt_kernel<<<(unsigned)nl, 256, 0, st>>>(H.d_lowrank, H.kmax, ws.hm_rank, ws.hm_offs, ws.hm_pool, ws.hm_xp,
                                                     ws.hm_t);
-    hm_apply_kernel<<<dim3((unsigned)nleaf, kHmSplit), 128, 0, st>>>(
+    hm_apply_kernel<<<dim3((unsigned)nleaf, kHmSplit), 64, 0, st>>>(
         H.d_leaves, H.d_leaf_ptr, H.d_leaf_item, H.d_dense, H.d_dense_off, H.d_lowrank, H.kmax, ws.hm_rank, ws.hm_offs,
-        H.d_perm, ws.hm_dense, ws.hm_pool, ws.hm_t, ws.hm_xp, H.n, ws.hm_yp);
+        ws.hm_dense, ws.hm_pool, ws.hm_t, ws.hm_xp, H.n, ws.hm_yp);
     hm_sum_kernel<<<(unsigned)((3 * H.n + 255) / 256), 256, 0, st>>>(H.n, H.d_perm, ws.hm_yp,
                                                                       reinterpret_cast<double2 *>(y));
     AFS_HIP(hipGetLastError());

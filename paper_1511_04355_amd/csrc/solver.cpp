@@ -41,7 +41,10 @@ void Workspace::hm_release() {
             (void)hipFree(p);
     if (hm_host)
         (void)hipHostFree(hm_host);
+    if (hm_used_host)
+        (void)hipHostFree(hm_used_host);
     hm_host = nullptr;
+    hm_used_host = nullptr;
     hm_dense = hm_pool = nullptr;
     hm_ctr = nullptr;
     hm_offs = nullptr;
@@ -52,11 +55,15 @@ void Workspace::hm_release() {
     hm_ok = false;
 }
 
-void Workspace::hm_alloc(const HmatPlan &H) {
+void Workspace::hm_alloc(const Problem &p, const HmatPlan &H) {
     const size_t nd = (size_t)H.dense_off.back(), nl = H.lowrank.size() / 4;
-    // pool for an average of 64 terms per block, within half the free memory
-    // (a block that finds the pool spent leaves the frequency on the on-the-fly operator)
-    const size_t want = (size_t)H.lr_rows * 64;
+    // pool: 1.25 x the largest build of this problem so far (48 terms per
+    // block before the first), or what a build that ran out asked for, within
+    // half the free memory; a build that runs out is repeated with a larger
+    // pool (hmat_finish reports it), and one that still cannot fit leaves its
+    // frequency on the on-the-fly operator
+    const size_t first = p.hm_need > 0.0 ? 0 : (size_t)H.lr_rows * 48;
+    const size_t want = std::max({first, (size_t)(1.25 * p.hm_need), hm_want});
     // hm_cap[1] records the size asked for (the pool itself may have been capped):
     // the same request reuses the buffers instead of reallocating them per frequency
     if (hm_dense && hm_cap[0] >= nd && hm_cap[1] >= want && hm_cap[2] >= nl)
@@ -75,8 +82,9 @@ void Workspace::hm_alloc(const HmatPlan &H) {
     hm_status = (int *)dalloc(std::max<size_t>(nl, 1) * 4);
     hm_t = (double2 *)dalloc(std::max<size_t>(nl, 1) * H.kmax * 16);
     hm_xp = (double2 *)dalloc((size_t)std::max<int64_t>(H.n, 1) * 3 * 16);
-    hm_yp = (double2 *)dalloc((size_t)std::max<int64_t>(H.n, 1) * 3 * 16 * 4);
+    hm_yp = (double2 *)dalloc((size_t)std::max<int64_t>(H.n, 1) * 3 * 16 * kHmatApplyParts);
     AFS_HIP(hipHostMalloc((void **)&hm_host, std::max<size_t>(nl, 1) * 2 * sizeof(int), hipHostMallocDefault));
+    AFS_HIP(hipHostMalloc((void **)&hm_used_host, sizeof(unsigned long long), hipHostMallocDefault));
     hm_cap[0] = nd;
     hm_cap[1] = want;
     hm_cap[2] = nl;
@@ -277,7 +285,13 @@ GmresResult gmres(const Operator &op, Workspace &ws, int64_t /*n_tri*/, const do
         AFS_HIP(hipStreamSynchronize(st));
         const double g2 = host[0];
         const cplx wr(host[2], host[3]);
-        if (g2 > 0.0 && std::isfinite(g2) && std::isfinite(wr.real()) && std::isfinite(wr.imag())) {
+        // the vector joins the search space only when it explains a useful
+        // part of the residual (projection lowers it by more than 5 %): a
+        // direction unrelated to the solution would only perturb the
+        // projected operator's Krylov space
+        const double b2_new = beta * beta - std::norm(wr) / g2;
+        if (g2 > 0.0 && std::isfinite(g2) && std::isfinite(wr.real()) && std::isfinite(wr.imag()) &&
+            b2_new < 0.9025 * beta * beta) {
             gamma = std::sqrt(g2);
             const cplx alpha = wr / g2;  // coefficient of aug
             vec_normalize(N, ws.small, ws.w, Cv, st);  // c (device ||w||^2 at small[0])
@@ -600,8 +614,14 @@ static int krylov_phase(Problem &p, Workspace &ws, const afsbem_solve_opts &o, i
     op64.hm = ws.hm_enabled ? &ws : nullptr;
     const bool mixed = o.precision == AFSBEM_PREC_MIXED;
     const double bnorm = norm2_dev(ws, N, ws.b, st);
-    if (ws.hm_enabled && fmt == kFmtBlocks)
-        hmat_finish(p, ws);  // the frequency's assembly has completed (st waited for it, then synchronised)
+    if (ws.hm_enabled && fmt == kFmtBlocks) {
+        // the frequency's assembly has completed (st waited for it, then
+        // synchronised); a build that ran out of pool is repeated with more
+        for (int tries = 0; !hmat_finish(p, ws) && ws.hm_exhausted && tries < 3; ++tries) {
+            hmat_setup(p, ws, kernel_params(p.mat, s_re, s_im), ws.hm_eps, st);
+            AFS_HIP(hipStreamSynchronize(st));
+        }
+    }
     const bool learned = o.warm_start == AFSBEM_WARM_LEARNED;
     const bool user_aug = o.warm_start == AFSBEM_WARM_USER_AUG;
     const double *x_prev = (d_x0 && o.warm_start != AFSBEM_WARM_NONE && !user_aug) ? d_x0 : nullptr;

@@ -47,11 +47,14 @@ struct Workspace {
     int64_t *hm_offs = nullptr;            // [nl][kmax] pool offset of each term
     double2 *hm_t = nullptr;
     double2 *hm_xp = nullptr;              // x in tree order (product scratch)
-    double2 *hm_yp = nullptr;              // partial sums of the product, [4][3 n] in tree order
+    double2 *hm_yp = nullptr;              // partial sums of the product, [parts][3 n] in tree order
     int *hm_rank = nullptr, *hm_status = nullptr;
     int *hm_host = nullptr;                // pinned: ranks, then status flags
+    unsigned long long *hm_used_host = nullptr;  // pinned: pool entries the build asked for
+    bool hm_exhausted = false;             // the last build ran out of pool
+    size_t hm_want = 0;                    // pool entries the next allocation asks for at least
     size_t hm_cap[3] = {0, 0, 0};
-    void hm_alloc(const HmatPlan &H);
+    void hm_alloc(const Problem &p, const HmatPlan &H);
     void hm_release();
     void reset_timing() { ev_used = 0; ev_prec.clear(); }
     ~Workspace();

@@ -1,8 +1,7 @@
 """Augmented GMRES (a vector joins the search space of the first cycle; the
 "preconditioner" use of the learned prediction) against the oracle's LU
 solutions, with vectors whose effect is known: the exact solution ends the
-solve after its own product, a random vector costs its product and a few
-iterations.
+solve after its own product, a random vector is declined after its product.
 Then the network's prediction in that role on a sequence of frequencies."""
 import numpy as np
 import pytest
@@ -72,9 +71,9 @@ def test_augmentation_with_a_random_vector(prec):
               f"rel err {err:.1e}", flush=True)
         assert st["rel_res_fp64"] <= 1e-7
         assert err <= bar
-        # the direction's own product plus a few iterations of the projected
-        # operator (rank-one change of the preconditioned spectrum)
-        assert st["iters"] <= sb["iters"] + 6
+        # a direction that explains nothing of the residual is declined after
+        # its own product: the solve is the zero-start one plus that product
+        assert st["iters"] <= sb["iters"] + 1
 
 
 @pytest.mark.parametrize("learn_aug", [1, 2])
@@ -99,3 +98,56 @@ def test_learned_prediction_as_augmentation(learn_aug):
         A, b = bem.assemble(mesh, s[k])
         xo = bem.solve_dense(A, b)
         assert np.linalg.norm(sols[k] - xo) / np.linalg.norm(xo) <= 1e-5
+
+
+def test_learned_start_against_the_cheap_starts():
+    """Porous block (5,280 unknowns), 12 frequencies of the lightly damped band
+    (T = 300, eta = 0.023) in the order an adaptive sampling run visits them,
+    mixed precision, one frequency at a time: zero, previous-solution and
+    extrapolated starts against the learned start (prediction in the start,
+    augmenting the first cycle, or both).  Every leg meets the FP64 residual
+    and matches the oracle; the gate keeps a network that does not help within
+    the products its queries cost (at most three per frequency: the start's
+    two images and the augmentation direction) of the best cheap start.  The
+    products and seconds of every leg are printed: on this band neighbouring
+    solutions carry little information, which is what the comparison shows."""
+    import paper_1511_04355_amd as afs
+    from oracle import bem
+    mesh = mg.random_block(0)
+    eta = 3.0 * np.log(10.0) / 300.0
+    om_max = 0.25 * np.pi * 512 / 300.0
+    om = [om_max * (1.0 - np.cos(j * np.pi / 14.0)) for j in range(8)]
+    while len(om) < 12:
+        srt = sorted(om)
+        i = max(range(len(srt) - 1), key=lambda q: (srt[q + 1] - srt[q], -q))
+        om.append(0.5 * (srt[i] + srt[i + 1]))
+    s = eta + 1j * np.array(om)
+    bc = torch.from_numpy(np.stack([np.asarray(mesh.bc_shape, np.complex128) / sk for sk in s])).cuda()
+    legs = {"zero": (afs.WARM_NONE, 0), "previous": (afs.WARM_PREV, 0), "extrapolated": (afs.WARM_EXTRAP, 0),
+            "learned": (afs.WARM_LEARNED, 0), "learned_augmenting": (afs.WARM_LEARNED, 1),
+            "learned_both": (afs.WARM_LEARNED, 2)}
+    prods, secs, sols = {}, {}, {}
+    import time
+    for name, (warm, aug) in legs.items():
+        P = afs.Problem.from_mesh(mesh)
+        o = afs.SolveOptions(tol=1e-6, precision=afs.PREC_MIXED, restart=300, max_iter=6000, warm_start=warm,
+                             learn_aug=aug, batch=1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = P.solve(s, bc, o, want_ut=False)
+        torch.cuda.synchronize()
+        secs[name] = time.perf_counter() - t0
+        assert max(x["rel_res_fp64"] for x in out["stats"]) <= 1e-6
+        prods[name] = sum(x["iters"] for x in out["stats"])
+        sols[name] = out["a"].cpu().numpy()
+        P.close()
+    print("products:", prods, flush=True)
+    print("seconds:", {k: round(v, 3) for k, v in secs.items()}, flush=True)
+    best_cheap = min(prods["zero"], prods["previous"], prods["extrapolated"])
+    for name in ("learned", "learned_augmenting", "learned_both"):
+        assert prods[name] <= best_cheap + 3 * len(s)
+    for k in (2, 9):
+        A, b = bem.assemble(mesh, s[k])
+        xo = bem.solve_dense(A, b)
+        for name in legs:
+            assert np.linalg.norm(sols[name][k] - xo) / np.linalg.norm(xo) <= 1e-5
