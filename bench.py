@@ -77,13 +77,14 @@ def parse():
                     help="initial guess of the optimised path (porous_afs_matrix_free: learned = the network "
                          "combined with the nearest sample's solution)")
     ap.add_argument("--workload", default="porous_C5",
-                    choices=["porous_C5", "cavity_L4", "pmc_probe", "pmc_probe_c5", "cavity_L2_batched", "blocks_batched", "porous_learned",
+                    choices=["porous_C5", "cavity_L4", "pmc_probe", "pmc_probe_c5", "mlp_train", "cavity_L2_batched", "blocks_batched", "porous_learned",
                              "porous_matrix_free", "porous_afs_matrix_free", "cavity_L4_afs", "cavity_nystrom",
                              "porous_hmat"],
                     help="porous_C5: the contract line (default; 300,516 unknowns, one step = one frequency).  "
                          "cavity_L4: the 15,360-unknown cavity line (64 frequencies per step; also run as the "
                          "contract line's secondary key).  The others print their own JSON line: pmc_probe_c5 (1 GiB copies + one "
-                         "solve of the contract workload at s = eta, for counter runs), "
+                         "solve of the contract workload at s = eta, for counter runs), mlp_train (the warm-start network's "
+                         "training step at its production shape), "
                          "pmc_probe (1 GiB copies + 4 mixed solves, for counter runs), cavity_L2_batched "
                          "(320 triangles, 16 frequencies), blocks_batched (16 seeded porous blocks x 24 "
                          "frequencies), porous_learned (27-void block, 40,320 unknowns: warm-start A/B on an "
@@ -235,6 +236,39 @@ def run_pmc_probe_c5(args, afs, mg, np, torch):
     st = o["stats"][0]
     return {"workload": "pmc_probe_c5", "inner_products": st["gemv_count"],
             "inner_ms": st["gemv_ms"] / max(st["gemv_count"], 1), "fp64_products": st["gemv64_count"]}
+
+
+def run_mlp_train(args, afs, mg, np, torch):
+    """The warm-start network at its production shape: minibatches of 8,192
+    rows, 32 -> 256 -> 256 -> 6, bf16 matrix-core training steps (forward,
+    loss, gradient, Adam) timed with HIP events, and the training time of one
+    solved frequency (24 steps).  MFMA work per step: forward and weight
+    gradients of the three layers and the activation gradients of the upper
+    two."""
+    n, d_in, H, d_out = 8192, 32, 256, 6
+    npar = afs._lib.mlp_n_params(d_in, H, d_out)
+    g = torch.Generator(device="cpu").manual_seed(0)
+    p = ((torch.rand(npar, generator=g) - 0.5) * 0.1).cuda()
+    X = torch.randn(n, d_in, generator=g).cuda()
+    T = torch.randn(n, d_out, generator=g).cuda()
+    m, v = torch.zeros_like(p), torch.zeros_like(p)
+    for t in range(1, 6):
+        afs._lib.mlp_train_step(p, X, T, m, v, t, d_in, H, d_out)
+    torch.cuda.synchronize()
+    steps = 240
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for t in range(6, 6 + steps):
+        afs._lib.mlp_train_step(p, X, T, m, v, t, d_in, H, d_out)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    # 2 flops per multiply-add: forward and weight gradients of all three
+    # layers, activation gradients of the upper two
+    flops = 2.0 * n * (2.0 * (d_in * H + H * H + H * d_out) + (H * H + H * d_out))
+    return {"workload": f"mlp_train: {n} rows, {d_in} -> {H} -> {H} -> {d_out}, bf16 MFMA, Adam",
+            "ms_per_step": ms, "ms_per_solved_frequency": 24 * ms, "tflops": flops / (ms * 1e-3) / 1e12,
+            "frac_of_bf16_peak": flops / (ms * 1e-3) / 2.5e15}
 
 
 def run_cavity_L2_batched(args, afs, mg, np, torch):
@@ -978,6 +1012,7 @@ def main():
     if args.workload not in ("porous_C5", "cavity_L4"):
         fn = {"pmc_probe": lambda: run_pmc_probe(afs, mg, np, torch),
               "pmc_probe_c5": lambda: run_pmc_probe_c5(args, afs, mg, np, torch),
+              "mlp_train": lambda: run_mlp_train(args, afs, mg, np, torch),
               "cavity_L2_batched": lambda: run_cavity_L2_batched(args, afs, mg, np, torch),
               "blocks_batched": lambda: run_blocks_batched(args, afs, mg, np, torch),
               "porous_learned": lambda: run_porous_learned(args, afs, mg, np, torch),
