@@ -56,9 +56,9 @@ FAR_NODES = 7
 # (FETCH_SIZE x 2.0, its reading for a 1 GiB device copy being half the true bytes)
 FAR_TRAFFIC_BYTES = (2.0 * 23885.20 + 3736479.73) * 1024
 GEMV32_TRAFFIC_BYTES = 2.0 * 923559.66 * 1024
-# HBM bytes of one hierarchical product at 300,516 unknowns (rocprofv3 --pmc over its kernels); None until taken
-# on the current kernels
-HMAT_TRAFFIC_BYTES = None
+# HBM bytes of one hierarchical product at 300,516 unknowns: rocprofv3 --pmc FETCH_SIZE (x 2.0) and WRITE_SIZE
+# per dispatch of its four kernels over --workload pmc_probe_c5 (gather, V^T x, apply, sum)
+HMAT_TRAFFIC_BYTES = (2.0 * (4006.2 + 16543798.0 + 28502385.5 + 19334.3) + (4695.6 + 256856.5 + 38076.5 + 5089.2)) * 1024
 
 
 def parse():
