@@ -529,7 +529,7 @@ def run_porous_afs_matrix_free(args, afs, mg, np, torch):
     dofs = np.sort(3 * rng.choice(loaded, 6, replace=False) + 2)
     shape = np.asarray(mesh.bc_shape, np.complex128)
     base = dict(tol=args.tol, precision=afs.PREC_MIXED, matrix_free=args.matrix_free, restart=args.restart,
-                max_iter=6000, batch=1, precond=args.precond, hmat_eps=args.hmat_eps)
+                max_iter=6000, batch=1, precond=args.precond, hmat_eps=args.hmat_eps, profile=1)
     solved, log, gaps = {}, [], []
     t_back = [None]  # when the last response returned to the AFS loop
 
@@ -582,7 +582,7 @@ def run_porous_afs_matrix_free(args, afs, mg, np, torch):
     fit_err = float(np.max(np.abs(fit.T - r["F"])) / np.max(np.abs(r["F"])))
     return {"workload": f"porous_afs_matrix_free: 64-void block ({mesh.n_tri} elements, {3 * mesh.n_tri} unknowns), "
                         f"AFS from J0=8, T={T}, eta={eta:.4f}, Ns={Ns} (Omega={np.pi * Ns / T:.3f}), mixed "
-                        f"matrix-free GMRES(100) ({'hierarchical' if args.matrix_free == 2 else 'on-the-fly'} inner "
+                        f"matrix-free GMRES({args.restart}) ({'hierarchical' if args.matrix_free == 2 else 'on-the-fly'} inner "
                         f"operator), {'cluster' if args.precond else 'point'} block-Jacobi, "
                         f"FP64 true rel. residual <= {args.tol}",
             "plan_s": plan_s, "afs_seconds": afs_s, "n_solves": r["Nc"], "fsm_solves_avoided": Ns // 2 + 1 - r["Nc"],

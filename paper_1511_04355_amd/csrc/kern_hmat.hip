@@ -218,6 +218,7 @@ __global__ __launch_bounds__(NT) void hm_aca_kernel(
     __shared__ double2 cf[kHmKmax];
     __shared__ int64_t used[kHmKmax + 1];
     __shared__ int64_t soff[kHmKmax];  // pool offsets of the terms found so far (read in every residual)
+    __shared__ double2 sent[3 * NT];   // one chunk of NT element pairs' entries (3 per pair)
     __shared__ int64_t off_k;
     const int t = threadIdx.x;
     const int64_t l = ids[blockIdx.x];
@@ -274,13 +275,22 @@ __global__ __launch_bounds__(NT) void hm_aca_kernel(
         const int al = (int)(istar % 3);
         double best = -1.0, rn = 0.0;
         int64_t bi = 0;
-        for (int64_t kk = t; kk < nb; kk += NT) {
-            cd ent[3];
-            hm_entries32(h32, col32, src32, coef32, m, perm[b0 + kk], true, al, ent);
+        // chunks of NT element pairs: each thread evaluates one pair's three
+        // entries into LDS, then the chunk's entries are taken in order by
+        // consecutive threads, so that the earlier terms are read coalesced
+        for (int64_t base = 0; base < nb; base += NT) {
+            if (base + t < nb) {
+                cd ent[3];
+                hm_entries32(h32, col32, src32, coef32, m, perm[b0 + base + t], true, al, ent);
 #pragma unroll
-            for (int be = 0; be < 3; ++be) {
-                const int64_t c = 3 * kk + be;
-                double vr = ent[be].r, vi = ent[be].i;
+                for (int be = 0; be < 3; ++be)
+                    sent[3 * t + be] = make_double2(ent[be].r, ent[be].i);
+            }
+            __syncthreads();
+            const int64_t ce = (3 * (nb - base) < 3 * NT) ? 3 * (nb - base) : 3 * NT;
+            for (int64_t e = t; e < ce; e += NT) {
+                const int64_t c = 3 * base + e;
+                double vr = sent[e].x, vi = sent[e].y;
 #pragma unroll 4
                 for (int q = 0; q < k; ++q) {
                     const double2 u = cf[q];
@@ -297,6 +307,7 @@ __global__ __launch_bounds__(NT) void hm_aca_kernel(
                     bi = c;
                 }
             }
+            __syncthreads();
         }
         const RedMaxSum pv = group_argmax_sums<NT>(best, bi, rn, 0.0, sv, si, sa, sb);
         const double rn2 = pv.a;
@@ -345,13 +356,19 @@ __global__ __launch_bounds__(NT) void hm_aca_kernel(
         double nu = 0.0;
         best = -1.0;
         bi = 0;
-        for (int64_t i = t; i < na; i += NT) {
-            cd ent[3];
-            hm_entries32(h32, col32, src32, coef32, perm[a0 + i], n, false, be, ent);
+        for (int64_t base = 0; base < na; base += NT) {
+            if (base + t < na) {
+                cd ent[3];
+                hm_entries32(h32, col32, src32, coef32, perm[a0 + base + t], n, false, be, ent);
 #pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                const int64_t r = 3 * i + a;
-                double ur = ent[a].r, ui = ent[a].i;
+                for (int a = 0; a < 3; ++a)
+                    sent[3 * t + a] = make_double2(ent[a].r, ent[a].i);
+            }
+            __syncthreads();
+            const int64_t ce = (3 * (na - base) < 3 * NT) ? 3 * (na - base) : 3 * NT;
+            for (int64_t e = t; e < ce; e += NT) {
+                const int64_t r = 3 * base + e;
+                double ur = sent[e].x, ui = sent[e].y;
 #pragma unroll 4
                 for (int q = 0; q < k; ++q) {
                     const double2 v = cf[q];
@@ -370,6 +387,7 @@ __global__ __launch_bounds__(NT) void hm_aca_kernel(
                     bi = r;
                 }
             }
+            __syncthreads();
         }
         const RedMaxSum nx = group_argmax_sums<NT>(best, bi, nu, nv, sv, si, sa, sb);
         const double nu2 = nx.a, nv2 = nx.b;
