@@ -331,7 +331,10 @@ int afsbem_solve_opts_default(afsbem_solve_opts *opts);
  * d_bc_val: [n_s][n_tri][3] complex<double> prescribed values at each s.
  * d_x0: nullable [n_s][N] complex<double> initial guesses (used with
  *       AFSBEM_WARM_USER; with PREV or LEARNED its first N entries stand for
- *       the solution preceding the first frequency).
+ *       the solution preceding the first frequency).  With PREV or LEARNED the
+ *       start of frequency k > 0 is the solution of the nearest frequency
+ *       (in |s - s_k|) among those before it in the call: the previous one
+ *       for an ordered list; EXTRAP uses the two previous ones.
  * Outputs (each nullable): d_a_out [n_s][N] solution vector, d_u_out and
  * d_t_out [n_s][n_tri][3] displacement and traction per element.
  * stats: nullable host array of n_s entries.

@@ -850,6 +850,22 @@ const double *start_guess(const afsbem_solve_opts &o, int32_t k, int64_t N, cons
     if (!a_out)
         return nullptr;
     const double *a1 = a_out + 2 * (size_t)(k - 1) * N;
+    if (o.warm_start != AFSBEM_WARM_EXTRAP) {
+        // the solution of the nearest frequency solved before in this call
+        // (the previous one for an ordered list; an adaptive sampling order
+        // visits the band out of order)
+        const C sk(s[2 * k], s[2 * k + 1]);
+        int32_t best = k - 1;
+        double bd = std::abs(sk - C(s[2 * best], s[2 * best + 1]));
+        for (int32_t j = k - 2; j >= 0; --j) {
+            const double d = std::abs(sk - C(s[2 * j], s[2 * j + 1]));
+            if (d < bd) {
+                bd = d;
+                best = j;
+            }
+        }
+        return a_out + 2 * (size_t)best * N;
+    }
     C c1, c2;
     if (o.warm_start == AFSBEM_WARM_EXTRAP && k >= 2 && xbuf &&
         extrap_coeffs(C(s[2 * (k - 2)], s[2 * (k - 2) + 1]), C(s[2 * (k - 1)], s[2 * (k - 1) + 1]),

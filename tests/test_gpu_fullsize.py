@@ -125,3 +125,42 @@ def test_porous_64_voids_matrix_free_solve_sampled_rows():
     x = out["a"][0].cpu().numpy()
     r = _check_rows(afs, bem, P, mesh, sk, bc[0], x, tol, 4, 11, check_A=False)
     print(f"[full] 64 voids: {st['iters']} products, sampled-row residual {r:.2e} of ||b||", flush=True)
+
+
+@pytest.mark.timeout(300)
+def test_porous_64_voids_contract_configuration_sampled_rows():
+    """The contract line's launch configuration on the 64-void block (300,516
+    unknowns): hierarchical FP32 inner operator (eps 1e-5), FP64 on-the-fly
+    residual, GMRES(1500), cluster block-Jacobi, learned warm start, two
+    frequencies in flight, three frequencies of its band in one call (the
+    lowest, a middle one and the top, omega <= 1.34): every frequency meets the
+    FP64 residual, and on sampled rows of the oracle's operator b matches and
+    the residual bound holds."""
+    import paper_1511_04355_amd as afs
+    from oracle import bem
+    mesh = mg.lattice_block(4, 39, 3, 2000, rmax=0.45)
+    P = afs.Problem.from_mesh(mesh)
+    eta = 3.0 * np.log(10.0) / 300.0
+    s = eta + 1j * np.array([0.0, 0.7588, 1.3404])
+    bc = _bcs(mesh, s)
+    tol = 1e-6
+    print(f"[full] 64-void block, N = {3 * mesh.n_tri}, contract configuration", flush=True)
+    out = P.solve(s, torch.from_numpy(bc).cuda(),
+                  afs.SolveOptions(tol=tol, precision=afs.PREC_MIXED, matrix_free=2, hmat_eps=1e-5, precond=1,
+                                   restart=1500, max_iter=6000, warm_start=afs.WARM_LEARNED, batch=0),
+                  want_ut=True)
+    for k, sk in enumerate(s):
+        st = out["stats"][k]
+        assert st["status"] == 0 and st["rel_res_fp64"] <= tol, (k, st)
+        x = out["a"][k].cpu().numpy()
+        r = _check_rows(afs, bem, P, mesh, sk, bc[k], x, tol, 3, 20 + k, check_A=False)
+        print(f"[full] contract s={sk:.4f}: {st['iters']} products, sampled-row residual {r:.2e} of ||b||",
+              flush=True)
+    # the u / t split of the last frequency: traction where prescribed, the solution elsewhere
+    u = out["u"][2].cpu().numpy().reshape(-1)
+    t = out["t"][2].cpu().numpy().reshape(-1)
+    a = out["a"][2].cpu().numpy()
+    kind = np.repeat(np.asarray(mesh.bc_kind), 3)
+    assert np.array_equal(t[kind == 0], bc[2].reshape(-1)[kind == 0])
+    assert np.array_equal(u[kind == 0], a[kind == 0])
+    assert np.array_equal(t[kind == 1], a[kind == 1])
