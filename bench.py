@@ -96,8 +96,8 @@ def parse():
                          "against the closed form beside the flat cavity one level finer), porous_hmat (300,516 "
                          "unknowns: hierarchical vs on-the-fly inner operator of the matrix-free solve)")
     ap.add_argument("--afs-q", type=int, default=4, help="cavity_L4_afs: new frequencies per AFS step")
-    ap.add_argument("--hmat-eps", type=float, default=1e-5,
-                    help="porous_hmat, porous_afs_matrix_free: accuracy of the low-rank blocks")
+    ap.add_argument("--hmat-eps", type=float, default=C5_HMAT_EPS,
+                    help="porous_C5, porous_hmat, porous_afs_matrix_free: accuracy of the low-rank blocks")
     ap.add_argument("--matrix-free", type=int, default=1, choices=[1, 2],
                     help="porous_afs_matrix_free: inner operator, 1 on the fly, 2 hierarchical")
     ap.add_argument("--precond", type=int, default=0,
@@ -879,7 +879,7 @@ def run_contract_c5(args, afs, mg, np, torch):
     bc = _bcs(mesh, s, torch, np)
     print(f"[c5] mesh {time.perf_counter() - t_mesh - plan_s:.1f} s, plan {plan_s:.1f} s, {W} + {K} frequencies",
           file=sys.stderr, flush=True)
-    opts = afs.SolveOptions(tol=args.tol, precision=afs.PREC_MIXED, matrix_free=2, hmat_eps=C5_HMAT_EPS,
+    opts = afs.SolveOptions(tol=args.tol, precision=afs.PREC_MIXED, matrix_free=2, hmat_eps=args.hmat_eps,
                             precond=1, restart=C5_RESTART, max_iter=6000, warm_start=afs.WARM_LEARNED,
                             learn_aug=args.learn_aug, profile=1, batch=args.batch)
     # warm-up: the first W frequencies (the cluster tree, the pools, the network's first samples)
@@ -934,7 +934,7 @@ def run_contract_c5(args, afs, mg, np, torch):
                                f"of T = {C5_T:g}, Ns = {C5_NS}) in adaptive-sampling order, step traction on "
                                f"z = 0, z = 4 fixed, FP64 true rel. residual <= {args.tol}",
                    "path": f"mixed: FP32 hierarchical inner operator (cross approximation, eps "
-                           f"{C5_HMAT_EPS:g}) + FP64 on-the-fly residual, GMRES({C5_RESTART}), cluster "
+                           f"{args.hmat_eps:g}) + FP64 on-the-fly residual, GMRES({C5_RESTART}), cluster "
                            f"block-Jacobi, learned warm start (network trained on the GPU after every solve"
                            f"{', prediction also augmenting the first cycle' if args.learn_aug else ''}), "
                            + ("two frequencies in flight (hierarchical build of s_k+1 during the Krylov phase "
@@ -967,7 +967,7 @@ def run_contract_c5(args, afs, mg, np, torch):
         print(f"[c5] plain FP64 at s = {complex(sp[0]):.4f}: {t_plain:.1f} s, {x['iters']} products, "
               f"rel {x['rel_res_fp64']:.1e}", file=sys.stderr, flush=True)
         # the optimised operator and solver on the same frequency alone, zero start
-        same = afs.SolveOptions(tol=args.tol, precision=afs.PREC_MIXED, matrix_free=2, hmat_eps=C5_HMAT_EPS,
+        same = afs.SolveOptions(tol=args.tol, precision=afs.PREC_MIXED, matrix_free=2, hmat_eps=args.hmat_eps,
                                 precond=1, restart=C5_RESTART, max_iter=6000, profile=1, batch=1)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
