@@ -22,7 +22,8 @@ struct Radial {
     cd Psi, X, Psd, Xd;
 };
 
-// inv_ax2 = 1 / |x|^2, supplied by the caller (from 1/r, without a division)
+// inv_ax2 = 1 / |x|^2, supplied by the caller (from 1/r, without a division);
+// coef: the plan's 64 series coefficients, then the kFmTabLen table entries
 __device__ __forceinline__ Radial radial64(cd x, double beta, const double *__restrict__ coef, double inv_ax2) {
     Radial R;
     const double ax2 = x.r * x.r + x.i * x.i;
@@ -43,12 +44,13 @@ __device__ __forceinline__ Radial radial64(cd x, double beta, const double *__re
         R.Xd = p3;
         return R;
     }
+    // coef + 64: the tables of the FP64 exp and sincos
     double sn, cs;
-    sincos_cw(x.i, &sn, &cs);
-    const double ex = exp_cw(-x.r);
+    sincos_tab(x.i, coef + 64, &sn, &cs);
+    const double ex = exp_tab(-x.r, coef + 64);
     const cd e = cd{ex * cs, -ex * sn};
-    sincos_cw(beta * x.i, &sn, &cs);
-    const double exp_ = exp_cw(-beta * x.r);
+    sincos_tab(beta * x.i, coef + 64, &sn, &cs);
+    const double exp_ = exp_tab(-beta * x.r, coef + 64);
     const cd ep = cd{exp_ * cs, -exp_ * sn};
     const double inv = inv_ax2;
     const cd ix = cd{x.r * inv, -x.i * inv};

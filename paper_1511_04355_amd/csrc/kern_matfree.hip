@@ -36,9 +36,11 @@ __global__ __launch_bounds__(256) void mf_far_kernel(int64_t nt, MfArgs a, const
                                                      const R *__restrict__ src, const R *__restrict__ coef_g,
                                                      const double *__restrict__ x, int64_t chunk_len,
                                                      double2 *__restrict__ partial) {
-    __shared__ R coef[64];
-    if (threadIdx.x < 64)
-        coef[threadIdx.x] = coef_g[threadIdx.x];
+    // series coefficients (and in FP64 the exp / sincos tables after them)
+    constexpr int NC = sizeof(R) == 8 ? 64 + kFmTabLen : 64;
+    __shared__ R coef[NC];
+    for (int q = threadIdx.x; q < NC; q += 256)
+        coef[q] = coef_g[q];
     __syncthreads();
     const int64_t N = 3 * nt;
     const int64_t m = (int64_t)blockIdx.x * 256 + threadIdx.x;

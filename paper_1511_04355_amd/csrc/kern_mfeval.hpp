@@ -30,13 +30,17 @@ __device__ __forceinline__ cx<R> cxs(cx<R> a, R s) {
     return {a.r * s, a.i * s};
 }
 
-__device__ __forceinline__ void exp_sincos(float a, float b, float &e, float &sn, float &cs) {
+// e^a, sin b, cos b: the hardware's FP32 approximations, or the FP64 table
+// functions on tab (the kFmTabLen entries after the series coefficients)
+__device__ __forceinline__ void exp_sincos(float a, float b, float &e, float &sn, float &cs,
+                                           const float * /*tab*/) {
     e = __expf(a);
     __sincosf(b, &sn, &cs);
 }
-__device__ __forceinline__ void exp_sincos(double a, double b, double &e, double &sn, double &cs) {
-    e = exp_cw(a);
-    sincos_cw(b, &sn, &cs);
+__device__ __forceinline__ void exp_sincos(double a, double b, double &e, double &sn, double &cs,
+                                           const double *__restrict__ tab) {
+    e = exp_tab(a, tab);
+    sincos_tab(b, tab, &sn, &cs);
 }
 __device__ __forceinline__ float inv_sqrt(float a) { return rsqrtf(a); }
 __device__ __forceinline__ double inv_sqrt(double a) { return rsqrt_nr(a); }
@@ -64,7 +68,8 @@ struct MfRad {
     cx<R> Psi, X, Psd, Xd;
 };
 
-// inv_ax2 = 1 / |x|^2, supplied by the caller from 1/r (no division)
+// inv_ax2 = 1 / |x|^2, supplied by the caller from 1/r (no division); coef:
+// the 64 series coefficients, in FP64 followed by the kFmTabLen table entries
 template <class R>
 __device__ __forceinline__ MfRad<R> mf_radial(cx<R> x, R beta, const R *__restrict__ coef, R inv_ax2) {
     MfRad<R> o;
@@ -86,8 +91,8 @@ __device__ __forceinline__ MfRad<R> mf_radial(cx<R> x, R beta, const R *__restri
         return o;
     }
     R ex, sn, cs, exq, snq, csq;
-    exp_sincos(-x.r, x.i, ex, sn, cs);
-    exp_sincos(-beta * x.r, beta * x.i, exq, snq, csq);
+    exp_sincos(-x.r, x.i, ex, sn, cs, coef + 64);
+    exp_sincos(-beta * x.r, beta * x.i, exq, snq, csq, coef + 64);
     const cx<R> e{ex * cs, -ex * sn};      // e^{-x}
     const cx<R> ep{exq * csq, -exq * snq};  // e^{-beta x}
     const R inv = inv_ax2;

@@ -16,6 +16,7 @@
 #include <cmath>
 #include <unordered_map>
 
+#include "fastmath64.hpp"
 #include "internal.hpp"
 
 namespace afsbem {
@@ -185,7 +186,7 @@ void plan_clusters(HostPlan &P) {
 //   r psi: (-1)^n [(n+1)^2 + (n+1) beta^(n+2)] / (n+2)!
 //   r chi: (-1)^n (n^2 - 1)(1 - beta^(n+2)) / (n+2)!
 void plan_series(const MaterialDerived &mat, HostPlan &P) {
-    P.coef.assign(64, 0.0);
+    P.coef.assign(64 + kFmTabLen, 0.0);
     for (int n = 0; n < 16; ++n) {
         double inv_fact = 1.0;
         for (int k = 2; k <= n + 2; ++k)
@@ -198,6 +199,19 @@ void plan_series(const MaterialDerived &mat, HostPlan &P) {
         P.coef[4 * n + 1] = b;
         P.coef[4 * n + 2] = (n - 1.0) * a;
         P.coef[4 * n + 3] = (n - 1.0) * b;
+    }
+    // tables of the FP64 exp and sincos (after the series): 2^(j/64), and
+    // cos, sin of j pi/32 from the first quadrant by exact quarter turns
+    double *tab = P.coef.data() + 64;
+    const long double pi_l = 3.141592653589793238462643383279502884L;
+    for (int j = 0; j < 64; ++j) {
+        tab[j] = (double)std::exp2((long double)j / 64.0L);
+        const int q = j / 16, m = j % 16;
+        const long double th = pi_l * m / 32.0L;
+        const double c = m ? (double)std::cos(th) : 1.0, s = m ? (double)std::sin(th) : 0.0;
+        const double cq[4] = {c, -s, -c, s}, sq[4] = {s, c, -s, -c};
+        tab[64 + 2 * j] = cq[q];
+        tab[65 + 2 * j] = sq[q];
     }
 }
 
