@@ -301,7 +301,10 @@ typedef struct {
                             the start is the previous solution; a vector whose projection
                             lowers the residual by less than 5 % is declined after its product);
                             2: both */
-    int32_t reserved_;   /* 0 */
+    int32_t no_recycle;  /* mixed path: 0 (default) = the correction of every refinement step after
+                            the first is sought in the first inner solve's Krylov subspace (same
+                            FP32 operator) augmented by new Arnoldi vectors of the part of the
+                            residual outside it; 1 = each inner solve builds a fresh Krylov space */
 } afsbem_solve_opts;
 
 typedef struct {

@@ -43,7 +43,7 @@ class _Opts(ctypes.Structure):
                 ("batch", ctypes.c_int32), ("fault_inject", ctypes.c_uint32), ("profile", ctypes.c_int32),
                 ("learn_steps", ctypes.c_int32), ("precond", ctypes.c_int32), ("matrix_free", ctypes.c_int32),
                 ("no_graph", ctypes.c_int32), ("hmat_eps", ctypes.c_double), ("hmat_eta", ctypes.c_double),
-                ("learn_aug", ctypes.c_int32), ("reserved_", ctypes.c_int32)]
+                ("learn_aug", ctypes.c_int32), ("no_recycle", ctypes.c_int32)]
 
 
 class _Stats(ctypes.Structure):
@@ -173,11 +173,12 @@ class SolveOptions:
     hmat_eps: float = 0.0
     hmat_eta: float = 0.0
     learn_aug: int = 0
+    no_recycle: int = 0
 
     def _c(self):
         return _Opts(self.tol, self.restart, self.max_iter, self.precision, self.warm_start, self.inner_tol,
                      self.batch, self.fault_inject, self.profile, self.learn_steps, self.precond, self.matrix_free,
-                     self.no_graph, self.hmat_eps, self.hmat_eta, self.learn_aug, 0)
+                     self.no_graph, self.hmat_eps, self.hmat_eta, self.learn_aug, self.no_recycle)
 
 
 class Problem:

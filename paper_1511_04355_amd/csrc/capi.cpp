@@ -634,6 +634,7 @@ int afsbem_solve_device(afsbem_problem *p, int32_t n_s, const double *s, const v
         AFS_REQUIRE(o.tol > 0 && o.restart >= 1 && o.restart <= 4000 && o.max_iter >= 1, AFSBEM_EINVAL,
                     "invalid solver options");
         AFS_REQUIRE(o.learn_aug >= 0 && o.learn_aug <= 2, AFSBEM_EINVAL, "learn_aug must be 0, 1 or 2");
+        AFS_REQUIRE(o.no_recycle == 0 || o.no_recycle == 1, AFSBEM_EINVAL, "no_recycle must be 0 or 1");
         AFS_REQUIRE(o.precision == AFSBEM_PREC_FP64 || o.precision == AFSBEM_PREC_MIXED, AFSBEM_EINVAL,
                     "unknown precision");
         AFS_REQUIRE((o.warm_start != AFSBEM_WARM_USER && o.warm_start != AFSBEM_WARM_USER_AUG) || d_x0,

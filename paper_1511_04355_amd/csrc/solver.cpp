@@ -238,9 +238,29 @@ static void residual(const Operator &op, Workspace &ws, const double *b, const d
     vec_sub(op.N, b, ws.tmp, r, st);
 }
 
+// Givens rotation (c real, s) with c a + s b = r, -conj(s) a + c b = 0,
+// applied to the pair (a, b) in place
+static void givens_make(cplx &a, cplx &b, cplx &c, cplx &s) {
+    const double den = std::sqrt(std::norm(a) + std::norm(b));
+    if (std::abs(a) == 0.0) {
+        c = 0.0;
+        s = 1.0;
+    } else {
+        c = std::abs(a) / den;
+        s = (a / std::abs(a)) * std::conj(b) / den;
+    }
+    a = c * a + s * b;
+    b = 0.0;
+}
+static void givens_apply(cplx c, cplx s, cplx &a, cplx &b) {
+    const cplx a0 = a;
+    a = c * a0 + s * b;
+    b = -std::conj(s) * a0 + std::conj(c) * b;
+}
+
 GmresResult gmres(const Operator &op, Workspace &ws, int64_t /*n_tri*/, const double *rhs, double rhs_norm,
                   double *x, bool x_is_zero, double tol_abs, int restart, int max_iter, hipStream_t st,
-                  bool verify, const double *r0, double r0_norm, const double *aug) {
+                  bool verify, const double *r0, double r0_norm, const double *aug, int recycle) {
     const int64_t N = op.N;
     GmresResult res;
     // Hessenberg columns packed one after another (column j holds rows 0..j+1),
@@ -268,6 +288,144 @@ GmresResult gmres(const Operator &op, Workspace &ws, int64_t /*n_tri*/, const do
         beta = norm2_dev(ws, N, ws.r, st);
     }
     res.est = beta;
+    const bool use_kept = recycle == 2 && ws.rc_valid && !aug && x_is_zero && ws.rc_k >= 1 &&
+                          ws.rc_k + 2 <= restart;
+    if (!use_kept)
+        ws.rc_valid = false;  // the cycles below overwrite the basis
+    if (use_kept && beta > tol_abs && res.iters < max_iter) {
+        // Recycled first cycle (GCRO with the kept subspace).  The kept cycle
+        // gives A M^-1 V_K = W H_K with W = V_{K+1} (Krylov slots 0..K) and
+        // rotations Q with Q H_K = [R_K; 0], so C = W Q^H[:, 0..K-1] is an
+        // orthonormal basis of the image A U of U = M^-1 V_K R_K^-1.  The
+        // residual's part in C is removed at once (coefficients c = C^H r);
+        // the new Arnoldi vectors (slots K+1, ...) start from the rest and are
+        // kept orthogonal to C (not to the last direction of W), the
+        // projections B = C^H A M^-1 V_new recorded; the cycle then minimises
+        // over the new vectors and the update is M^-1 (V_K R_K^-1 (c - B y)
+        // + V_new y).  Projections onto C are formed through W: the W
+        // coordinates rotated by Q, their last entry dropped, rotated back.
+        const int K = ws.rc_k, nw = K + 1;
+        double *const Vn = Vk + 2 * (int64_t)nw * N;
+        std::vector<cplx> coef;
+        // one classical Gram-Schmidt pass of v against C and the first nn new
+        // vectors; adds the C coordinates to bacc and the new ones to hacc
+        auto pass = [&](double *v, int nn, cplx *bacc, cplx *hacc) {
+            const int nv = nw + nn;
+            vec_mdot(N, nv, Vk, N, v, ws.dots_partial, hbuf, st);
+            AFS_HIP(hipMemcpyAsync(host, hbuf, (size_t)nv * 16, hipMemcpyDeviceToHost, st));
+            AFS_HIP(hipStreamSynchronize(st));
+            coef.assign(nv, cplx(0));
+            for (int i = 0; i < nv; ++i)
+                coef[i] = cplx(host[2 * i], host[2 * i + 1]);
+            for (int i = 0; i < K; ++i)
+                givens_apply(ws.rc_cs[i], ws.rc_sn[i], coef[i], coef[i + 1]);
+            coef[K] = 0.0;  // the direction of W outside C stays
+            for (int i = 0; i < K; ++i)
+                bacc[i] += coef[i];
+            for (int i = K - 1; i >= 0; --i) {  // back to W coordinates: Q^H
+                const cplx a = coef[i], b = coef[i + 1], c = ws.rc_cs[i], s = ws.rc_sn[i];
+                coef[i] = std::conj(c) * a - s * b;
+                coef[i + 1] = std::conj(s) * a + c * b;
+            }
+            for (int i = 0; i < nn; ++i)
+                hacc[i] += coef[nw + i];
+            for (int i = 0; i < nv; ++i) {
+                host[2 * i] = coef[i].real();
+                host[2 * i + 1] = coef[i].imag();
+            }
+            AFS_HIP(hipMemcpyAsync(hbuf, host, (size_t)nv * 16, hipMemcpyHostToDevice, st));
+            vec_mupdate(N, nv, Vk, N, hbuf, v, st);
+        };
+        auto sqnorm = [&](const double *v) {
+            vec_mdot(N, 1, v, N, v, ws.dots_partial, h2, st);
+            AFS_HIP(hipMemcpyAsync(host, h2, 16, hipMemcpyDeviceToHost, st));
+            AFS_HIP(hipStreamSynchronize(st));
+            return std::max(host[0], 0.0);
+        };
+        std::vector<cplx> cc(K, cplx(0));
+        pass(ws.r, 0, cc.data(), nullptr);
+        pass(ws.r, 0, cc.data(), nullptr);
+        const double bp2 = sqnorm(ws.r);
+        const double bp = std::sqrt(bp2);
+        const int mmax = std::min(restart - nw, max_iter - res.iters);
+        std::vector<cplx> Bn, gq(mmax + 1, cplx(0)), c2(mmax), s2(mmax);
+        gq[0] = bp;
+        double est = bp;
+        int kn = 0;
+        if (bp > 0.0 && std::isfinite(bp) && est > 0.5 * tol_abs) {
+            vec_normalize(N, h2, ws.r, Vn, st);  // h2[0] = ||r||^2 on the device
+            std::vector<cplx> bcol(K), hcol;
+            for (int j = 0; j < mmax; ++j) {
+                ws.apply_precond(Vn + 2 * (int64_t)j * N, ws.z, st);
+                op.apply(ws.z, ws.w, st);
+                std::fill(bcol.begin(), bcol.end(), cplx(0));
+                hcol.assign(j + 2, cplx(0));
+                pass(ws.w, j + 1, bcol.data(), hcol.data());
+                pass(ws.w, j + 1, bcol.data(), hcol.data());
+                const double hn2 = sqnorm(ws.w);
+                const double hn = std::sqrt(hn2);
+                ++res.iters;
+                if (!std::isfinite(hn)) {
+                    res.nan = true;
+                    return res;
+                }
+                if (hn > 0.0)
+                    vec_normalize(N, h2, ws.w, Vn + 2 * (int64_t)(j + 1) * N, st);
+                Bn.insert(Bn.end(), bcol.begin(), bcol.end());
+                hcol[j + 1] = hn;
+                if (Hm.size() < hix(0, j + 1))
+                    Hm.resize(hix(0, j + 1));
+                for (int i = 0; i < j; ++i)
+                    givens_apply(c2[i], s2[i], hcol[i], hcol[i + 1]);
+                givens_make(hcol[j], hcol[j + 1], c2[j], s2[j]);
+                for (int i = 0; i <= j; ++i)
+                    Hm[hix(i, j)] = hcol[i];
+                givens_apply(c2[j], s2[j], gq[j], gq[j + 1]);
+                kn = j + 1;
+                est = std::abs(gq[j + 1]);
+                if (est <= 0.5 * tol_abs || res.iters >= max_iter || hn == 0.0)
+                    break;
+            }
+        }
+        // y for the new vectors, then the kept ones: z = R_K^-1 (c - B y)
+        std::vector<cplx> yn(kn), z(K);
+        for (int i = kn - 1; i >= 0; --i) {
+            cplx s = gq[i];
+            for (int l = i + 1; l < kn; ++l)
+                s -= Hm[hix(i, l)] * yn[l];
+            yn[i] = s / Hm[hix(i, i)];
+        }
+        for (int i = K - 1; i >= 0; --i) {
+            cplx s = cc[i];
+            for (int l = 0; l < kn; ++l)
+                s -= Bn[(size_t)l * K + i] * yn[l];
+            for (int l = i + 1; l < K; ++l)
+                s -= ws.rc_R[hix(i, l)] * z[l];
+            z[i] = s / ws.rc_R[hix(i, i)];
+        }
+        // coefficients over Krylov slots 0..K+kn (slot K, outside the kept domain: 0)
+        const int nc = nw + kn;
+        for (int i = 0; i < nc; ++i) {
+            const cplx v = i < K ? z[i] : (i == K ? cplx(0) : yn[i - nw]);
+            host[2 * i] = v.real();
+            host[2 * i + 1] = v.imag();
+        }
+        AFS_HIP(hipMemcpyAsync(hbuf, host, (size_t)nc * 16, hipMemcpyHostToDevice, st));
+        AFS_HIP(hipMemsetAsync(ws.tmp, 0, (size_t)N * 16, st));
+        vec_combine(N, nc, Vk, N, hbuf, ws.tmp, st);
+        ws.apply_precond(ws.tmp, x, st);  // x was zero: x = M^-1 (...)
+        x_is_zero = false;
+        ++res.cycles;
+        res.est = est;
+        if (!verify && est <= 0.5 * tol_abs) {
+            res.converged = true;  // the kept subspace stays valid for a further step
+            return res;
+        }
+        ws.rc_valid = false;
+        residual(op, ws, rhs, x, ws.r, st);
+        beta = norm2_dev(ws, N, ws.r, st);
+        res.est = beta;
+    }
     // Augmentation (first cycle): u = aug / gamma with c = A u of unit norm;
     // the start takes the residual-optimal multiple of u (x += u c^H r,
     // r -= c c^H r), and the cycle's Arnoldi vectors are kept orthogonal to
@@ -395,6 +553,16 @@ GmresResult gmres(const Operator &op, Workspace &ws, int64_t /*n_tri*/, const do
         for (int i = 0; i < k; ++i) {
             host[2 * i] = y[i].real();
             host[2 * i + 1] = y[i].imag();
+        }
+        if (recycle == 1) {
+            // keep this cycle for later corrections with the same operator
+            ws.rc_valid = !augc && k >= 1;
+            if (ws.rc_valid) {
+                ws.rc_k = k;
+                ws.rc_R.assign(Hm.begin(), Hm.begin() + hix(0, k));
+                ws.rc_cs.assign(cs.begin(), cs.begin() + k);
+                ws.rc_sn.assign(sn.begin(), sn.begin() + k);
+            }
         }
         // augmented cycle: the coefficient of aug, -(B y) / gamma, after y
         cplx du(0.0);
@@ -688,8 +856,10 @@ static int krylov_phase(Problem &p, Workspace &ws, const afsbem_solve_opts &o, i
             while (true) {
                 const double tol_in = std::max(o.inner_tol * rnorm, 0.5 * o.tol * bnorm);
                 const double *av = refine == 0 ? aug_vec : nullptr;
+                // later steps search the first inner solve's Krylov subspace first
+                const int rcy = o.no_recycle ? 0 : (refine == 0 ? 1 : 2);
                 GmresResult g = gmres(op32, ws, nt, ws.rin, rnorm, ws.x, true, tol_in, o.restart,
-                                      std::max(1, o.max_iter - matvecs), st, false, nullptr, 0.0, av);
+                                      std::max(1, o.max_iter - matvecs), st, false, nullptr, 0.0, av, rcy);
                 if (av)
                     aug_gain = g.aug_gain;
                 if (!(o.fault_inject & AFSBEM_FAULT_STALL_INNER))  // test hook: the correction is lost

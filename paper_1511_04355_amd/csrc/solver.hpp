@@ -1,5 +1,8 @@
 // Solver internals: device workspace, operator, GMRES.
 #pragma once
+#include <complex>
+#include <vector>
+
 #include "internal.hpp"
 #include "hmat.hpp"
 
@@ -18,6 +21,13 @@ struct Workspace {
     double *rin = nullptr, *xo = nullptr;  // mixed: outer residual and outer iterate
     double *xstart = nullptr;              // extrapolated starting guess
     double *aug = nullptr;                 // augmentation vector of the first GMRES cycle (learned)
+    // Krylov subspace kept from the last cycle of a mixed solve's first inner
+    // GMRES, for the corrections of its later refinement steps (same FP32
+    // operator): Krylov vectors 0..rc_k of V, the cycle's triangular factor
+    // (columns packed as the Hessenberg) and its Givens rotations
+    bool rc_valid = false;
+    int rc_k = 0;
+    std::vector<std::complex<double>> rc_R, rc_cs, rc_sn;
     double *dots_partial = nullptr, *small = nullptr;
     double *one = nullptr;                 // device complex 1 + 0i
     // preconditioner: 0 = 3x3 blocks (precond), 1 = element clusters (clinv)
@@ -97,9 +107,14 @@ struct GmresResult {
 // (nullable): a vector that joins the search space of the first cycle
 // (flexible GMRES with aug as direction 0 and the preconditioned basis
 // vectors after it), its coefficient found by the same least-squares problem.
+//
+// recycle: 0 = none; 1 = keep the last cycle's subspace in ws (rc_*); 2 = the
+// first cycle (x zero, no aug) starts from the kept subspace of the same
+// operator: the solution is sought in M^-1 span(kept V_K) plus the Krylov
+// space of the residual's part outside span(V_{K+1}).
 GmresResult gmres(const Operator &op, Workspace &ws, int64_t n_tri, const double *rhs, double rhs_norm, double *x,
                   bool x_is_zero, double tol_abs, int restart, int max_iter, hipStream_t st, bool verify,
-                  const double *r0 = nullptr, double r0_norm = 0.0, const double *aug = nullptr);
+                  const double *r0 = nullptr, double r0_norm = 0.0, const double *aug = nullptr, int recycle = 0);
 
 int solve_pipelined(Problem &p, const afsbem_solve_opts &o, int32_t n_s, const double *s, const double *bc,
                     const double *x0_user, double *a_out, double *u_out, double *t_out,

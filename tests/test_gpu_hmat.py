@@ -72,6 +72,42 @@ def test_hmat_solve_reaches_the_exact_residual():
         assert np.linalg.norm(b - A @ a[k]) / np.linalg.norm(b) <= 1.01 * tol
 
 
+@pytest.mark.parametrize("tol", [1e-6, 1e-9])
+def test_recycled_refinement_steps(tol):
+    """Refinement steps after the first search the first inner solve's
+    Krylov subspace plus new Arnoldi vectors (no_recycle = 0) or a fresh
+    Krylov space (no_recycle = 1).  Both reach the FP64 residual of the exact
+    operator and the oracle's LU solution; a coarse low-rank accuracy (1e-4)
+    forces several steps, and the kept subspace needs fewer inner products."""
+    import paper_1511_04355_amd as afs
+    from oracle import bem
+    mesh = mg.random_block(3)
+    s = np.array([0.25 + 0.7j, 0.25 + 2.0j])
+    bc = np.stack([np.asarray(mesh.bc_shape, np.complex128) / sk for sk in s])
+    P = afs.Problem.from_mesh(mesh)
+    outs = {}
+    for nr in (0, 1):
+        print(f"[hmat] recycle tol={tol} no_recycle={nr}", flush=True)
+        outs[nr] = P.solve(s, torch.from_numpy(bc).cuda(),
+                           afs.SolveOptions(tol=tol, precision=afs.PREC_MIXED, matrix_free=2, hmat_eps=1e-4,
+                                            precond=1, restart=400, max_iter=4000, batch=1, no_recycle=nr))
+    bar = 1e-5 if tol >= 1e-6 else 1e-7
+    for k, sk in enumerate(s):
+        A, b = bem.assemble(mesh, sk)
+        xo = bem.solve_dense(A, b)
+        for nr in (0, 1):
+            st = outs[nr]["stats"][k]
+            a = outs[nr]["a"][k].cpu().numpy()
+            assert st["status"] == 0 and st["rel_res_fp64"] <= tol, (nr, st)
+            assert st["refine_steps"] >= 2, (nr, st)
+            assert np.linalg.norm(b - A @ a) / np.linalg.norm(b) <= 1.01 * tol
+            assert np.linalg.norm(a - xo) / np.linalg.norm(xo) <= bar
+    # products of the FP32 operator: all products less one FP64 residual per step
+    inner = {nr: sum(st["iters"] - st["refine_steps"] for st in outs[nr]["stats"]) for nr in (0, 1)}
+    print(f"[hmat] inner products: kept subspace {inner[0]}, fresh {inner[1]}", flush=True)
+    assert inner[0] < inner[1]
+
+
 def test_hmat_option_checks():
     import paper_1511_04355_amd as afs
     mesh = mg.cavity(1)
