@@ -110,9 +110,11 @@ def parse():
                          "(1), or both (2)")
     ap.add_argument("--plain-max-iter", type=int, default=300, help="porous_C5: product cap of the plain FP64 leg")
     ap.add_argument("--no-secondary", action="store_true", help="porous_C5: skip the 15,360-unknown cavity line")
-    ap.add_argument("--batch", type=int, default=0,
+    ap.add_argument("--batch", type=int, default=None,
                     help="optimised path: 1 = one frequency at a time, 0 = assembly of the next frequency "
-                         "overlapped with the Krylov phase of the current one")
+                         "overlapped with the Krylov phase of the current one (default: 1 on the 300,516-unknown "
+                         "contract line, where the overlapped build slows the products more than it hides; 0 "
+                         "on the cavity line)")
     return ap.parse_args()
 
 
@@ -726,7 +728,8 @@ def run_cavity_L4_line(args, afs, mg, np, torch, steps, warmup, cpu):
 
     warm = {"prev": afs.WARM_PREV, "none": afs.WARM_NONE, "learned": afs.WARM_LEARNED,
             "extrap": afs.WARM_EXTRAP}[args.warm]
-    mixed = afs.SolveOptions(tol=args.tol, precision=afs.PREC_MIXED, warm_start=warm, profile=1, batch=args.batch)
+    batch = 0 if args.batch is None else args.batch
+    mixed = afs.SolveOptions(tol=args.tol, precision=afs.PREC_MIXED, warm_start=warm, profile=1, batch=batch)
     ms_mixed, out = timed(P, s, bc, mixed, steps, warmup, torch)
     st = out["stats"]
     worst = max(x["rel_res_fp64"] for x in st)
@@ -761,7 +764,7 @@ def run_cavity_L4_line(args, afs, mg, np, torch, steps, warmup, cpu):
                            + {"prev": "previous-s warm start", "none": "zero start",
                               "learned": "learned + previous-s warm start",
                               "extrap": "warm start extrapolated linearly in s from the two previous s"}[args.warm]
-                           + (", assembly of s_k+1 overlapped with GMRES of s_k" if args.batch != 1 else ""),
+                           + (", assembly of s_k+1 overlapped with GMRES of s_k" if batch != 1 else ""),
                    "plan_s": plan_s},
         # the dominant kernel (largest share of GPU time in the timed step) is
         # reported as "roofline", the other as "roofline_other"
@@ -879,9 +882,10 @@ def run_contract_c5(args, afs, mg, np, torch):
     bc = _bcs(mesh, s, torch, np)
     print(f"[c5] mesh {time.perf_counter() - t_mesh - plan_s:.1f} s, plan {plan_s:.1f} s, {W} + {K} frequencies",
           file=sys.stderr, flush=True)
+    batch = 1 if args.batch is None else args.batch
     opts = afs.SolveOptions(tol=args.tol, precision=afs.PREC_MIXED, matrix_free=2, hmat_eps=args.hmat_eps,
                             precond=1, restart=C5_RESTART, max_iter=6000, warm_start=afs.WARM_LEARNED,
-                            learn_aug=args.learn_aug, profile=1, batch=args.batch)
+                            learn_aug=args.learn_aug, profile=1, batch=batch)
     # warm-up: the first W frequencies (the cluster tree, the pools, the network's first samples)
     t0 = time.perf_counter()
     out_w = P.solve(s[:W], bc[:W], opts, want_ut=True) if W > 0 else None
@@ -938,7 +942,7 @@ def run_contract_c5(args, afs, mg, np, torch):
                            f"block-Jacobi, learned warm start (network trained on the GPU after every solve"
                            f"{', prediction also augmenting the first cycle' if args.learn_aug else ''}), "
                            + ("two frequencies in flight (hierarchical build of s_k+1 during the Krylov phase "
-                              "of s_k)" if args.batch != 1 else "one frequency at a time"),
+                              "of s_k)" if batch != 1 else "one frequency at a time"),
                    "plan_s": plan_s, "warmup_s": warm_s},
         "roofline": roof,
         "solve": {"max_rel_res_fp64": worst,

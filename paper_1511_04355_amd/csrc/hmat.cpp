@@ -156,15 +156,12 @@ void hmat_build(const Problem &p, double eta, int kmax, HmatPlan &H, bool upload
     for (int64_t d = 0; d < nd; ++d)
         H.dense_off[d + 1] = H.dense_off[d] + dense_rows_padded(H.dense[4 * d + 1] - H.dense[4 * d]) * 3 *
                                                    (H.dense[4 * d + 3] - H.dense[4 * d + 2]);
-    H.lr_rows = 0;
     H.lr_order.clear();
     auto tier = [&](int64_t l) {
         const int64_t na = H.lowrank[4 * l + 1] - H.lowrank[4 * l], nb = H.lowrank[4 * l + 3] - H.lowrank[4 * l + 2];
         const int64_t big = na > nb ? na : nb;
         return big <= 64 ? 0 : (big <= 128 ? 1 : 2);
     };
-    for (int64_t l = 0; l < nl; ++l)
-        H.lr_rows += 3 * ((H.lowrank[4 * l + 1] - H.lowrank[4 * l]) + (H.lowrank[4 * l + 3] - H.lowrank[4 * l + 2]));
     for (int tr = 0; tr < 3; ++tr) {
         for (int64_t l = 0; l < nl; ++l)
             if (tier(l) == tr)
@@ -186,6 +183,27 @@ void hmat_build(const Problem &p, double eta, int kmax, HmatPlan &H, bool upload
         }
     // leaves were pushed in tree (DFS) order, i.e. by increasing start
     const int64_t nleaf = (int64_t)H.leaves.size() / 2;
+    // pool slot geometry: each leaf's padded rows, and per low-rank block
+    // the place of its row cluster's first leaf and its padded row count
+    H.leaf_of.assign(n, -1);
+    H.leaf_prow.assign(nleaf + 1, 0);
+    for (int64_t L = 0; L < nleaf; ++L) {
+        for (int64_t q = H.leaves[2 * L]; q < H.leaves[2 * L + 1]; ++q)
+            H.leaf_of[q] = (int32_t)L;
+        H.leaf_prow[L + 1] = H.leaf_prow[L] + dense_rows_padded(H.leaves[2 * L + 1] - H.leaves[2 * L]);
+    }
+    H.lr_rp.assign(2 * nl, 0);
+    H.lr_rows = 0;
+    for (int64_t l = 0; l < nl; ++l) {
+        const int32_t La = H.leaf_of[H.lowrank[4 * l]], Lb = H.leaf_of[H.lowrank[4 * l + 1] - 1];
+        AFS_REQUIRE(La >= 0 && Lb >= La && H.leaves[2 * La] == H.lowrank[4 * l] &&
+                        H.leaves[2 * Lb + 1] == H.lowrank[4 * l + 1],
+                    AFSBEM_EINVAL, "internal: low-rank row cluster not a union of leaves");
+        H.lr_rp[2 * l] = H.leaf_prow[La];
+        H.lr_rp[2 * l + 1] = H.leaf_prow[Lb + 1] - H.leaf_prow[La];
+        const int64_t C = 3 * (H.lowrank[4 * l + 3] - H.lowrank[4 * l + 2]);
+        H.lr_rows += H.lr_rp[2 * l + 1] + C + (C & 1);
+    }
     std::vector<std::vector<int32_t>> items(nleaf);
     for (int64_t d = 0; d < nd; ++d) {
         const int64_t L = leaf_of_start[H.dense[4 * d]];
@@ -217,6 +235,9 @@ void hmat_build(const Problem &p, double eta, int kmax, HmatPlan &H, bool upload
     H.d_leaf_ptr = up(H, H.leaf_ptr);
     H.d_leaf_item = up(H, H.leaf_item);
     H.d_lr_order = up(H, H.lr_order);
+    H.d_leaf_of = up(H, H.leaf_of);
+    H.d_leaf_prow = up(H, H.leaf_prow);
+    H.d_lr_rp = up(H, H.lr_rp);
 }
 
 }  // namespace afsbem

@@ -11,7 +11,11 @@
 // (self block, far rule, near-pair correction: the sum the matrix-free
 // product forms).  Indices of blocks are positions in tree order.  Factors
 // are stored in FP32 (the operator serves FP32 products) in a pool carved as
-// terms are found, so memory follows the ranks reached.
+// terms are found, kHmatGroup terms per slot, so memory follows the ranks
+// reached.  A slot holds, for each leaf of the block's row cluster in tree
+// order, the group's rows of that leaf term after term (the leaf's padded row
+// count each), then the group's V terms (padded column count each): the
+// product reads a leaf's rows of a whole group as one contiguous range.
 #pragma once
 #include "internal.hpp"
 
@@ -20,10 +24,17 @@ namespace afsbem {
 struct Workspace;
 
 constexpr int kHmatKmax = 128;  // terms per low-rank block at most
+constexpr int kHmatGroup = 8;   // terms per pool slot
 // dense blocks are column-major with an even row count (the product reads two
 // rows per 16-byte load); the padding row is zero
 constexpr int kHmatApplyParts = 8;  // partial sums per row of the product (parts of each leaf's block list)
 __host__ __device__ inline int64_t dense_rows_padded(int64_t n_elems) { return 3 * n_elems + ((3 * n_elems) & 1); }
+// entries of one pool slot of a low-rank block with RL padded rows (summed
+// over its leaves) and Cp padded columns, rounded to 128 bytes
+__host__ __device__ inline int64_t hm_slot_entries(int64_t RL, int64_t Cp) {
+    return (kHmatGroup * (RL + Cp) + 15) & ~(int64_t)15;
+}
+__host__ __device__ inline int hm_slots(int kmax) { return (kmax + kHmatGroup - 1) / kHmatGroup; }
 
 struct HmatPlan {
     double eta = 1.0;
@@ -32,12 +43,15 @@ struct HmatPlan {
     std::vector<int64_t> dense;     // [nd][4] a0, a1, b0, b1 (tree positions of elements)
     std::vector<int64_t> lowrank;   // [nl][4]
     std::vector<int64_t> dense_off; // [nd+1] offsets (complex entries) of the dense blocks (padded rows)
-    int64_t lr_rows = 0;            // sum over low-rank blocks of R + C (one term's entries)
+    int64_t lr_rows = 0;            // sum over low-rank blocks of RL + Cp (one term's padded entries)
     std::vector<int32_t> lr_order;  // low-rank blocks by size: at most 64 elements a side, at most 128, larger
     int64_t n_small = 0, n_mid = 0;
     std::vector<int64_t> leaves;    // [nleaf][2] row ranges of the leaves
     std::vector<int64_t> leaf_ptr;  // [nleaf+1]
     std::vector<int32_t> leaf_item; // dense block d as d, low-rank block l as -(l + 1)
+    std::vector<int32_t> leaf_of;   // [n] leaf of each tree position
+    std::vector<int64_t> leaf_prow; // [nleaf+1] prefix sums of the leaves' padded row counts
+    std::vector<int64_t> lr_rp;     // [nl][2] leaf_prow at the row cluster's first leaf, padded rows RL
     int kmax = 0;
     // device copies
     int32_t *d_perm = nullptr;
@@ -45,6 +59,8 @@ struct HmatPlan {
     int64_t *d_leaves = nullptr, *d_leaf_ptr = nullptr;
     int32_t *d_leaf_item = nullptr;
     int32_t *d_lr_order = nullptr;
+    int32_t *d_leaf_of = nullptr;
+    int64_t *d_leaf_prow = nullptr, *d_lr_rp = nullptr;
     std::vector<void *> allocs;
     ~HmatPlan();
 };

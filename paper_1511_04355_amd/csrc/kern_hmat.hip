@@ -3,8 +3,8 @@
 //
 // Low-rank blocks: adaptive cross approximation with partial pivoting on the
 // far rule's entries (evaluated in FP32, residual arithmetic in FP64, terms
-// stored in FP32 in a pool whose
-// slots a work-group takes with one atomic add per term): at step k the residual row i_k (the block's row
+// stored in FP32 in a pool whose slots of kHmatGroup terms a work-group takes
+// with one atomic add per slot): at step k the residual row i_k (the block's row
 // minus sum_l U_l[i_k] V_l) is evaluated, its largest entry j_k becomes the
 // pivot, V_k = row / row[j_k], U_k = the residual column j_k, and the next row
 // is the largest entry of U_k outside the rows already used; the block stops
@@ -16,11 +16,12 @@
 // unsampled, e.g. where a cluster spans separate surfaces).  One work-group per block; a row
 // or column costs one element-pair block per source or target element.
 //
-// Product: x gathered into tree order, t_l = V_l^T x per low-rank block (one
-// wavefront per term), then four work-groups per leaf row range each sum every
-// fourth entry of the leaf's list of dense blocks (column-major FP32, read
-// coalesced) and covering low-rank blocks, and the four partial sums are added
-// in a fixed order (no atomics).
+// Product: x gathered into tree order, t_l = V_l^T x per low-rank block
+// (sixteen lanes per term), then kHmatApplyParts single-wave work-groups per
+// leaf row range each sum every kHmatApplyParts-th entry of the leaf's list of
+// dense blocks (column-major FP32, read coalesced) and covering low-rank blocks
+// (the leaf's rows of a slot's terms, contiguous), and the partial sums are
+// added in a fixed order (no atomics).
 #include "hmat.hpp"
 #include "kern_eval.hpp"
 #include "kern_mfeval.hpp"
@@ -203,13 +204,35 @@ __device__ __forceinline__ RedMaxSum group_argmax_sums(double v, int64_t i, doub
 // status: 0 converged, 1 out of terms, 2 pool exhausted.  NT threads per
 // block: 64 for blocks of at most 64 elements a side (most are leaf pairs of
 // 32), 128 up to 128, 256 for the larger ones; ids lists the blocks of this launch.
+// Place of row r of a low-rank block in its pool slots (layout in hmat.hpp):
+// the row's leaf's offset within a slot, the leaf's padded row count, and the
+// row's index within the leaf.
+struct HmRowPos {
+    int64_t lo, rp, rl;
+};
+__device__ __forceinline__ HmRowPos hm_row_pos(int64_t a0, int64_t rowbase, int64_t r,
+                                               const int32_t *__restrict__ leaf_of,
+                                               const int64_t *__restrict__ leaves,
+                                               const int64_t *__restrict__ leaf_prow) {
+    const int64_t el = a0 + r / 3;
+    const int32_t L = leaf_of[el];
+    const int64_t L0 = leaves[2 * L];
+    HmRowPos o;
+    o.rp = dense_rows_padded(leaves[2 * L + 1] - L0);
+    o.lo = (leaf_prow[L] - rowbase) * kHmatGroup;
+    o.rl = 3 * (el - L0) + r % 3;
+    return o;
+}
+
 template <int NT>
 __global__ __launch_bounds__(NT) void hm_aca_kernel(
     const int32_t *__restrict__ perm,
     const int64_t *__restrict__ lowrank, const int32_t *__restrict__ ids, int kmax, double eps,
     float2 *__restrict__ pool, unsigned long long pool_cap, unsigned long long *__restrict__ ctr,
     int64_t *__restrict__ offs, int *__restrict__ rank_out, int *__restrict__ status_out, Hm32 h32,
-    const float *__restrict__ col32, const float *__restrict__ src32, const float *__restrict__ coef32_g) {
+    const float *__restrict__ col32, const float *__restrict__ src32, const float *__restrict__ coef32_g,
+    const int32_t *__restrict__ leaf_of, const int64_t *__restrict__ leaves, const int64_t *__restrict__ leaf_prow,
+    const int64_t *__restrict__ lr_rp) {
     __shared__ float coef32[64];
     if (threadIdx.x < 64)
         coef32[threadIdx.x] = coef32_g[threadIdx.x];
@@ -217,18 +240,26 @@ __global__ __launch_bounds__(NT) void hm_aca_kernel(
     __shared__ int64_t si[NT];
     __shared__ double2 cf[kHmKmax];
     __shared__ int64_t used[kHmKmax + 1];
-    __shared__ int64_t soff[kHmKmax];  // pool offsets of the terms found so far (read in every residual)
+    __shared__ int64_t sgoff[kHmKmax / kHmatGroup];  // pool offsets of the slots taken so far
     __shared__ double2 sent[3 * NT];   // one chunk of NT element pairs' entries (3 per pair)
-    __shared__ int64_t off_k;
     const int t = threadIdx.x;
     const int64_t l = ids[blockIdx.x];
     const int64_t a0 = lowrank[4 * l], b0 = lowrank[4 * l + 2];
     const int64_t na = lowrank[4 * l + 1] - a0, nb = lowrank[4 * l + 3] - b0;
     const int64_t R = 3 * na, C = 3 * nb;
-    // a term's U (R entries) and V (C entries) each start on an even entry, so
-    // that the products read them with 16-byte loads
-    const int64_t Rp = R + (R & 1), Cp = C + (C & 1);
-    int64_t *myoffs = offs + l * kmax;
+    // rows padded per leaf and columns padded to even counts, so that the
+    // products read two entries per 16-byte load
+    const int64_t rowbase = lr_rp[2 * l], RL = lr_rp[2 * l + 1], Cp = C + (C & 1);
+    const int64_t slot = hm_slot_entries(RL, Cp);
+    int64_t *myoffs = offs + l * hm_slots(kmax);
+    // pool index of row (at p) of U_q, and of column c of V_q
+    auto upos = [&](int q, const HmRowPos &p) {
+        return sgoff[q / kHmatGroup] + p.lo + (int64_t)(q % kHmatGroup) * p.rp + p.rl;
+    };
+    auto vpos = [&](int q, int64_t c) {
+        return sgoff[q / kHmatGroup] + kHmatGroup * RL + (int64_t)(q % kHmatGroup) * Cp + c;
+    };
+    auto rowpos = [&](int64_t r) { return hm_row_pos(a0, rowbase, r, leaf_of, leaves, leaf_prow); };
     int64_t istar = 0;
     double S2 = 0.0;
     int k = 0, status = 1, probes_ok = 0, n_probe = 0;
@@ -251,25 +282,27 @@ __global__ __launch_bounds__(NT) void hm_aca_kernel(
         return r;
     };
     while (k < kmax) {
-        // ---- the term's slot in the pool (a probe row is evaluated, not stored)
-        if (t == 0 && !probing) {
-            const unsigned long long o = atomicAdd(ctr, (unsigned long long)(Rp + Cp));
-            off_k = (o + (unsigned long long)(Rp + Cp) <= pool_cap) ? (int64_t)o : -1;
-            if (off_k >= 0) {
-                myoffs[k] = off_k;
-                soff[k] = off_k;
+        // ---- a new slot for every kHmatGroup terms (a probe row is evaluated, not stored)
+        const bool new_slot = !probing && (k % kHmatGroup) == 0;
+        if (t == 0 && new_slot) {
+            const unsigned long long o = atomicAdd(ctr, (unsigned long long)slot);
+            const bool fits = o + (unsigned long long)slot <= pool_cap;
+            sgoff[k / kHmatGroup] = fits ? (int64_t)o : -1;
+            if (fits)
+                myoffs[k / kHmatGroup] = (int64_t)o;
+        }
+        {
+            const HmRowPos pi = rowpos(istar);
+            for (int q = t; q < k; q += NT) {
+                const float2 u = pool[upos(q, pi)];
+                cf[q] = make_double2(u.x, u.y);
             }
         }
-        for (int q = t; q < k; q += NT) {
-            const float2 u = pool[soff[q] + istar];
-            cf[q] = make_double2(u.x, u.y);
-        }
         __syncthreads();
-        if (!probing && off_k < 0) {
+        if (new_slot && sgoff[k / kHmatGroup] < 0) {
             status = 2;
             break;
         }
-        float2 *Uk = pool + (probing ? 0 : off_k), *Vk = Uk + Rp;
         // ---- residual row istar -> V_k (unnormalised)
         const int64_t m = perm[a0 + istar / 3];
         const int al = (int)(istar % 3);
@@ -294,12 +327,12 @@ __global__ __launch_bounds__(NT) void hm_aca_kernel(
 #pragma unroll 4
                 for (int q = 0; q < k; ++q) {
                     const double2 u = cf[q];
-                    const float2 v = pool[soff[q] + Rp + c];
+                    const float2 v = pool[vpos(q, c)];
                     vr -= u.x * v.x - u.y * v.y;
                     vi -= u.x * v.y + u.y * v.x;
                 }
                 if (!probing)
-                    Vk[c] = make_float2((float)vr, (float)vi);
+                    pool[vpos(k, c)] = make_float2((float)vr, (float)vi);
                 const double a2 = vr * vr + vi * vi;
                 rn += a2;
                 if (a2 > best) {
@@ -332,6 +365,7 @@ __global__ __launch_bounds__(NT) void hm_aca_kernel(
             break;
         }
         const int64_t jstar = pv.i;
+        float2 *Vk = pool + vpos(k, 0);
         const float2 pf = Vk[jstar];
         __syncthreads();
         const double pd = (double)pf.x * pf.x + (double)pf.y * pf.y;
@@ -345,7 +379,7 @@ __global__ __launch_bounds__(NT) void hm_aca_kernel(
         }
         // ---- residual column jstar -> U_k
         for (int q = t; q < k; q += NT) {
-            const float2 v = pool[soff[q] + Rp + jstar];
+            const float2 v = pool[vpos(q, jstar)];
             cf[q] = make_double2(v.x, v.y);
         }
         if (t == 0)
@@ -368,15 +402,16 @@ __global__ __launch_bounds__(NT) void hm_aca_kernel(
             const int64_t ce = (3 * (na - base) < 3 * NT) ? 3 * (na - base) : 3 * NT;
             for (int64_t e = t; e < ce; e += NT) {
                 const int64_t r = 3 * base + e;
+                const HmRowPos pr = rowpos(r);
                 double ur = sent[e].x, ui = sent[e].y;
 #pragma unroll 4
                 for (int q = 0; q < k; ++q) {
                     const double2 v = cf[q];
-                    const float2 u = pool[soff[q] + r];
+                    const float2 u = pool[upos(q, pr)];
                     ur -= u.x * v.x - u.y * v.y;
                     ui -= u.x * v.y + u.y * v.x;
                 }
-                Uk[r] = make_float2((float)ur, (float)ui);
+                pool[upos(k, pr)] = make_float2((float)ur, (float)ui);
                 const double a2 = ur * ur + ui * ui;
                 nu += a2;
                 bool was = false;
@@ -426,17 +461,20 @@ __global__ __launch_bounds__(256) void hm_gather_kernel(int64_t n, const int32_t
 // terms at a time
 __global__ __launch_bounds__(256) void hm_vt_kernel(const int64_t *__restrict__ lowrank, int kmax,
                                                     const int *__restrict__ rank, const int64_t *__restrict__ offs,
+                                                    const int64_t *__restrict__ lr_rp,
                                                     const float2 *__restrict__ pool, const double2 *__restrict__ xp,
                                                     double2 *__restrict__ tv) {
     const int64_t l = blockIdx.x;
     const int g = threadIdx.x >> 4, ln = threadIdx.x & 15;
-    const int64_t a0 = lowrank[4 * l], b0 = lowrank[4 * l + 2];
-    const int64_t R = 3 * (lowrank[4 * l + 1] - a0), C = 3 * (lowrank[4 * l + 3] - b0);
-    const int64_t Rp = R + (R & 1), C2 = C >> 1;
+    const int64_t b0 = lowrank[4 * l + 2];
+    const int64_t C = 3 * (lowrank[4 * l + 3] - b0);
+    const int64_t Cp = C + (C & 1), C2 = C >> 1;
+    const int64_t vbase = kHmatGroup * lr_rp[2 * l + 1];  // V terms after the slot's rows
+    const int64_t *so = offs + l * hm_slots(kmax);
     const int rk = rank[l];
     const double2 *xb = xp + 3 * b0;
     for (int q = g; q < rk; q += 16) {
-        const float2 *V = pool + offs[l * kmax + q] + Rp;
+        const float2 *V = pool + so[q / kHmatGroup] + vbase + (int64_t)(q % kHmatGroup) * Cp;
         const float4 *V4 = reinterpret_cast<const float4 *>(V);
         double sr = 0.0, si = 0.0;
 #pragma unroll 4
@@ -475,28 +513,36 @@ __device__ __forceinline__ void cmac2(double &r0, double &i0, double &r1, double
 // one wavefront per (leaf L, part blockIdx.y): lane l owns rows 2l, 2l + 1 of
 // the leaf (at most 96 rows, 48 lanes) and sums the blocks it - leaf_ptr[L] =
 // blockIdx.y (mod kHmSplit) of the leaf's list: dense blocks column by column
-// (16-byte loads of two rows, eight columns in flight), low-rank blocks term by
-// term (the leaf's rows of U_q times t_q, eight terms in flight; offsets and
-// t_q are wave-uniform scalar loads).  Partial sums in tree order, yp[part][3 n].
+// (16-byte loads of two rows, eight columns in flight), low-rank blocks a slot
+// of kHmatGroup terms at a time (the leaf's rows of those terms are one
+// contiguous range of the slot, eight terms in flight; slot offsets and t_q
+// are wave-uniform scalar loads).  Partial sums in tree order, yp[part][3 n].
 __global__ __launch_bounds__(64) void hm_apply_kernel(
     const int64_t *__restrict__ leaves, const int64_t *__restrict__ leaf_ptr, const int32_t *__restrict__ leaf_item,
-    const int64_t *__restrict__ dense, const int64_t *__restrict__ dense_off, const int64_t *__restrict__ lowrank,
-    int kmax, const int *__restrict__ rank, const int64_t *__restrict__ offs, const float2 *__restrict__ dblk,
-    const float2 *__restrict__ pool, const double2 *__restrict__ tv, const double2 *__restrict__ xp, int64_t n_el,
-    double2 *__restrict__ yp) {
+    const int64_t *__restrict__ dense, const int64_t *__restrict__ dense_off, const int64_t *__restrict__ leaf_prow,
+    const int64_t *__restrict__ lr_rp, int kmax, const int *__restrict__ rank, const int64_t *__restrict__ offs,
+    const float2 *__restrict__ dblk, const float2 *__restrict__ pool, const double2 *__restrict__ tv,
+    const double2 *__restrict__ xp, int64_t n_el, double2 *__restrict__ yp) {
+    static_assert(kHmatGroup == 8, "the low-rank loop keeps one slot's eight terms in flight");
     const int64_t L = blockIdx.x;
     const int64_t L0 = leaves[2 * L], rows = 3 * (leaves[2 * L + 1] - L0);
     const int64_t Rp = rows + (rows & 1);
+    const int64_t prow = leaf_prow[L];
     const int lane = threadIdx.x;
     const int64_t r = 2 * (int64_t)lane;
     const bool live = r < rows;
+    // lanes past the leaf's rows load a live lane's entries (in bounds) and
+    // drop them, so that every load of a batch is issued without a branch and
+    // the batch is in flight together
+    const int64_t lc = live ? lane : (Rp >> 1) - 1;
+    const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
     double a0r = 0.0, a0i = 0.0, a1r = 0.0, a1i = 0.0;
     for (int64_t it = leaf_ptr[L] + blockIdx.y; it < leaf_ptr[L + 1]; it += kHmSplit) {
         const int32_t item = leaf_item[it];
         if (item >= 0) {
             const int64_t b0 = dense[4 * item + 2];
             const int64_t C = 3 * (dense[4 * item + 3] - b0);
-            const float4 *D = reinterpret_cast<const float4 *>(dblk + dense_off[item]) + lane;
+            const float4 *D = reinterpret_cast<const float4 *>(dblk + dense_off[item]) + lc;
             const int64_t ld = Rp >> 1;  // float4 per column
             const double2 *xb = xp + 3 * b0;
             int64_t c = 0;
@@ -504,49 +550,36 @@ __global__ __launch_bounds__(64) void hm_apply_kernel(
                 float4 v[8];
 #pragma unroll
                 for (int u = 0; u < 8; ++u)
-                    v[u] = live ? D[(c + u) * ld] : make_float4(0.f, 0.f, 0.f, 0.f);
+                    v[u] = D[(c + u) * ld];
 #pragma unroll
                 for (int u = 0; u < 8; ++u)
-                    cmac2(a0r, a0i, a1r, a1i, v[u], xb[c + u]);
+                    cmac2(a0r, a0i, a1r, a1i, live ? v[u] : z4, xb[c + u]);
             }
             for (; c < C; ++c) {
-                const float4 v = live ? D[c * ld] : make_float4(0.f, 0.f, 0.f, 0.f);
-                cmac2(a0r, a0i, a1r, a1i, v, xb[c]);
+                const float4 v = D[c * ld];
+                cmac2(a0r, a0i, a1r, a1i, live ? v : z4, xb[c]);
             }
         } else {
             const int64_t lb = -(int64_t)item - 1;
-            const int64_t rr = 3 * (L0 - lowrank[4 * lb]) + r;  // this lane's first row within U_q
-            const bool even = ((L0 - lowrank[4 * lb]) & 1) == 0;  // wave-uniform: 16-byte aligned rows
             const int rk = rank[lb];
-            const int64_t *ob = offs + lb * kmax;
+            // this leaf's rows in every slot of the block: kHmatGroup terms of Rp
+            // entries each (every offset even: 16-byte loads)
+            const int64_t lo = (prow - lr_rp[2 * lb]) * kHmatGroup + 2 * lc;
+            const int64_t *ob = offs + lb * hm_slots(kmax);
             const double2 *tb = tv + lb * kmax;
-            int q = 0;
-            for (; q + 8 <= rk; q += 8) {
+            const int64_t st4 = Rp >> 1;  // float4 per term of the leaf
+            // a slot at a time; in the last one the terms past the rank load
+            // the last term's rows again (in bounds) and take a zero coefficient
+            for (int q = 0; q < rk; q += 8) {
+                const float4 *U = reinterpret_cast<const float4 *>(pool + ob[q / 8] + lo);
+                const int last = rk - q - 1;
                 float4 u[8];
 #pragma unroll
-                for (int e = 0; e < 8; ++e) {
-                    const float2 *U = pool + ob[q + e] + rr;
-                    if (!live) {
-                        u[e] = make_float4(0.f, 0.f, 0.f, 0.f);
-                    } else if (even) {
-                        u[e] = *reinterpret_cast<const float4 *>(U);
-                    } else {
-                        const float2 lo = U[0], hi = U[1];
-                        u[e] = make_float4(lo.x, lo.y, hi.x, hi.y);
-                    }
-                }
+                for (int e = 0; e < 8; ++e)
+                    u[e] = U[(e < last ? e : last) * st4];
 #pragma unroll
                 for (int e = 0; e < 8; ++e)
-                    cmac2(a0r, a0i, a1r, a1i, u[e], tb[q + e]);
-            }
-            for (; q < rk; ++q) {
-                const float2 *U = pool + ob[q] + rr;
-                float4 u = make_float4(0.f, 0.f, 0.f, 0.f);
-                if (live) {
-                    const float2 lo = U[0], hi = U[1];
-                    u = make_float4(lo.x, lo.y, hi.x, hi.y);
-                }
-                cmac2(a0r, a0i, a1r, a1i, u, tb[q]);
+                    cmac2(a0r, a0i, a1r, a1i, live ? u[e] : z4, e <= last ? tb[q + e] : make_double2(0.0, 0.0));
             }
         }
     }
@@ -597,17 +630,20 @@ void hmat_setup(const Problem &p, Workspace &ws, const KernelParams &kp, double 
         hm_aca_kernel<64><<<(unsigned)n_small, 64, 0, st>>>(H.d_perm,
                                                              H.d_lowrank, H.d_lr_order, H.kmax, eps, ws.hm_pool,
                                                              (unsigned long long)ws.hm_pool_cap, ws.hm_ctr, ws.hm_offs,
-                                                             ws.hm_rank, ws.hm_status, h32, d.col32, d.src32, d.coef32);
+                                                             ws.hm_rank, ws.hm_status, h32, d.col32, d.src32, d.coef32, H.d_leaf_of, H.d_leaves,
+                                                             H.d_leaf_prow, H.d_lr_rp);
     if (n_mid)
         hm_aca_kernel<128><<<(unsigned)n_mid, 128, 0, st>>>(H.d_perm, H.d_lowrank, H.d_lr_order + n_small, H.kmax, eps,
                                                              ws.hm_pool, (unsigned long long)ws.hm_pool_cap, ws.hm_ctr,
                                                              ws.hm_offs, ws.hm_rank, ws.hm_status, h32, d.col32,
-                                                             d.src32, d.coef32);
+                                                             d.src32, d.coef32, H.d_leaf_of, H.d_leaves, H.d_leaf_prow,
+                                                             H.d_lr_rp);
     if (n_large)
         hm_aca_kernel<256><<<(unsigned)n_large, 256, 0, st>>>(H.d_perm, H.d_lowrank, H.d_lr_order + n_small + n_mid,
                                                                H.kmax, eps, ws.hm_pool, (unsigned long long)ws.hm_pool_cap,
                                                                ws.hm_ctr, ws.hm_offs, ws.hm_rank, ws.hm_status, h32,
-                                                               d.col32, d.src32, d.coef32);
+                                                               d.col32, d.src32, d.coef32, H.d_leaf_of, H.d_leaves,
+                                                               H.d_leaf_prow, H.d_lr_rp);
     AFS_HIP(hipGetLastError());
     if (nl) {
         AFS_HIP(hipMemcpyAsync(ws.hm_host, ws.hm_rank, nl * sizeof(int), hipMemcpyDeviceToHost, st));
@@ -653,11 +689,11 @@ void hmat_apply(const Problem &p, const Workspace &ws, const double *x, double *
     const double2 *xv = reinterpret_cast<const double2 *>(x);
     hm_gather_kernel<<<(unsigned)((3 * H.n + 255) / 256), 256, 0, st>>>(H.n, H.d_perm, xv, ws.hm_xp);
     if (nl)
-        hm_vt_kernel<<<(unsigned)nl, 256, 0, st>>>(H.d_lowrank, H.kmax, ws.hm_rank, ws.hm_offs, ws.hm_pool, ws.hm_xp,
-                                                    ws.hm_t);
+        hm_vt_kernel<<<(unsigned)nl, 256, 0, st>>>(H.d_lowrank, H.kmax, ws.hm_rank, ws.hm_offs, H.d_lr_rp, ws.hm_pool,
+                                                    ws.hm_xp, ws.hm_t);
     hm_apply_kernel<<<dim3((unsigned)nleaf, kHmSplit), 64, 0, st>>>(
-        H.d_leaves, H.d_leaf_ptr, H.d_leaf_item, H.d_dense, H.d_dense_off, H.d_lowrank, H.kmax, ws.hm_rank, ws.hm_offs,
-        ws.hm_dense, ws.hm_pool, ws.hm_t, ws.hm_xp, H.n, ws.hm_yp);
+        H.d_leaves, H.d_leaf_ptr, H.d_leaf_item, H.d_dense, H.d_dense_off, H.d_leaf_prow, H.d_lr_rp, H.kmax, ws.hm_rank,
+        ws.hm_offs, ws.hm_dense, ws.hm_pool, ws.hm_t, ws.hm_xp, H.n, ws.hm_yp);
     hm_sum_kernel<<<(unsigned)((3 * H.n + 255) / 256), 256, 0, st>>>(H.n, H.d_perm, ws.hm_yp,
                                                                       reinterpret_cast<double2 *>(y));
     AFS_HIP(hipGetLastError());

@@ -77,7 +77,7 @@ void Workspace::hm_alloc(const Problem &p, const HmatPlan &H) {
     hm_pool = (float2 *)dalloc(std::max<size_t>(nf, 1) * 8);
     hm_pool_cap = nf;
     hm_ctr = (unsigned long long *)dalloc(sizeof(unsigned long long));
-    hm_offs = (int64_t *)dalloc(std::max<size_t>(nl, 1) * H.kmax * sizeof(int64_t));
+    hm_offs = (int64_t *)dalloc(std::max<size_t>(nl, 1) * hm_slots(H.kmax) * sizeof(int64_t));
     hm_rank = (int *)dalloc(std::max<size_t>(nl, 1) * 4);
     hm_status = (int *)dalloc(std::max<size_t>(nl, 1) * 4);
     hm_t = (double2 *)dalloc(std::max<size_t>(nl, 1) * H.kmax * 16);

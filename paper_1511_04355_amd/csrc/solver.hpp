@@ -51,10 +51,10 @@ struct Workspace {
     int hm_max_rank = 0;
     double hm_bytes = 0.0;                 // matrix bytes one hierarchical product streams
     float2 *hm_dense = nullptr;
-    float2 *hm_pool = nullptr;             // factor terms: U_q (R entries) then V_q (C entries)
+    float2 *hm_pool = nullptr;             // factor terms in slots of kHmatGroup (layout in hmat.hpp)
     size_t hm_pool_cap = 0;                // complex entries
     unsigned long long *hm_ctr = nullptr;  // pool entries taken
-    int64_t *hm_offs = nullptr;            // [nl][kmax] pool offset of each term
+    int64_t *hm_offs = nullptr;            // [nl][hm_slots(kmax)] pool offset of each slot of terms
     double2 *hm_t = nullptr;
     double2 *hm_xp = nullptr;              // x in tree order (product scratch)
     double2 *hm_yp = nullptr;              // partial sums of the product, [parts][3 n] in tree order
