@@ -455,45 +455,75 @@ __global__ __launch_bounds__(256) void hm_gather_kernel(int64_t n, const int32_t
         xp[i] = x[3 * (int64_t)perm[i / 3] + i % 3];
 }
 
-// t[l][q] = V_q^T x on the block's columns, one wavefront per term
 // t_q = V_q^T x for every term of every low-rank block: one work-group per
-// block, sixteen lanes per term (16-byte loads, two entries each), sixteen
-// terms at a time
+// block, a slot of kHmatGroup terms (contiguous) per pass, 32 lanes per term
+// (16-byte loads of two entries; each lane's two loads of a 64-wide stripe
+// issued unconditionally from clamped indices, so that the whole slot is in
+// flight at once).  The block's x segment, which every term reads, is staged
+// in LDS once when it fits (up to kVtLds entries).
+constexpr int kVtLds = 1536;
+
+// one lane's share of t_q (32 lanes per term) with x read from xr (LDS or global)
+__device__ __forceinline__ void vt_term(const float2 *__restrict__ V, const double2 *__restrict__ xr, int64_t C,
+                                        int ln, double &sr, double &si) {
+    const int64_t C2 = C >> 1;
+    const float4 *V4 = reinterpret_cast<const float4 *>(V);
+    const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
+    for (int64_t s0 = 0; s0 < C2; s0 += 64) {
+        const int64_t ca = s0 + ln, cb = s0 + 32 + ln;
+        const int64_t ia = ca < C2 ? ca : C2 - 1, ib = cb < C2 ? cb : C2 - 1;
+        const float4 va0 = V4[ia], vb0 = V4[ib];
+        const double2 xa0 = xr[2 * ia], xa1 = xr[2 * ia + 1], xb0 = xr[2 * ib], xb1 = xr[2 * ib + 1];
+        const float4 va = ca < C2 ? va0 : z4, vb = cb < C2 ? vb0 : z4;
+        sr += (double)va.x * xa0.x - (double)va.y * xa0.y + (double)va.z * xa1.x - (double)va.w * xa1.y;
+        si += (double)va.x * xa0.y + (double)va.y * xa0.x + (double)va.z * xa1.y + (double)va.w * xa1.x;
+        sr += (double)vb.x * xb0.x - (double)vb.y * xb0.y + (double)vb.z * xb1.x - (double)vb.w * xb1.y;
+        si += (double)vb.x * xb0.y + (double)vb.y * xb0.x + (double)vb.z * xb1.y + (double)vb.w * xb1.x;
+    }
+    if ((C & 1) && ln == 0) {
+        const float2 v = V[C - 1];
+        const double2 xv = xr[C - 1];
+        sr += (double)v.x * xv.x - (double)v.y * xv.y;
+        si += (double)v.x * xv.y + (double)v.y * xv.x;
+    }
+}
+
 __global__ __launch_bounds__(256) void hm_vt_kernel(const int64_t *__restrict__ lowrank, int kmax,
                                                     const int *__restrict__ rank, const int64_t *__restrict__ offs,
                                                     const int64_t *__restrict__ lr_rp,
                                                     const float2 *__restrict__ pool, const double2 *__restrict__ xp,
                                                     double2 *__restrict__ tv) {
+    static_assert(kHmatGroup * 32 == 256, "one slot per pass of the work-group");
+    __shared__ double2 xs[kVtLds];
     const int64_t l = blockIdx.x;
-    const int g = threadIdx.x >> 4, ln = threadIdx.x & 15;
+    const int g = threadIdx.x >> 5, ln = threadIdx.x & 31;
     const int64_t b0 = lowrank[4 * l + 2];
     const int64_t C = 3 * (lowrank[4 * l + 3] - b0);
-    const int64_t Cp = C + (C & 1), C2 = C >> 1;
-    const int64_t vbase = kHmatGroup * lr_rp[2 * l + 1];  // V terms after the slot's rows
+    const int64_t Cp = C + (C & 1);
+    const int64_t vbase = kHmatGroup * lr_rp[2 * l + 1] + (int64_t)g * Cp;  // this term's V within a slot
     const int64_t *so = offs + l * hm_slots(kmax);
     const int rk = rank[l];
+    const bool staged = C <= kVtLds;  // block-uniform
     const double2 *xb = xp + 3 * b0;
-    for (int q = g; q < rk; q += 16) {
-        const float2 *V = pool + so[q / kHmatGroup] + vbase + (int64_t)(q % kHmatGroup) * Cp;
-        const float4 *V4 = reinterpret_cast<const float4 *>(V);
+    if (staged) {
+        for (int64_t c = threadIdx.x; c < C; c += 256)
+            xs[c] = xb[c];
+        __syncthreads();
+    }
+    for (int q0 = 0; q0 < rk; q0 += kHmatGroup) {
+        const int q = q0 + g;
+        if (q >= rk)
+            continue;
+        const float2 *V = pool + so[q0 / kHmatGroup] + vbase;
         double sr = 0.0, si = 0.0;
-#pragma unroll 4
-        for (int64_t c2 = ln; c2 < C2; c2 += 16) {
-            const float4 v = V4[c2];
-            const double2 x0 = xb[2 * c2], x1 = xb[2 * c2 + 1];
-            sr += (double)v.x * x0.x - (double)v.y * x0.y + (double)v.z * x1.x - (double)v.w * x1.y;
-            si += (double)v.x * x0.y + (double)v.y * x0.x + (double)v.z * x1.y + (double)v.w * x1.x;
-        }
-        if ((C & 1) && ln == 0) {
-            const float2 v = V[C - 1];
-            const double2 xv = xb[C - 1];
-            sr += (double)v.x * xv.x - (double)v.y * xv.y;
-            si += (double)v.x * xv.y + (double)v.y * xv.x;
-        }
+        if (staged)
+            vt_term(V, xs, C, ln, sr, si);
+        else
+            vt_term(V, xb, C, ln, sr, si);
 #pragma unroll
-        for (int off = 8; off > 0; off >>= 1) {
-            sr += __shfl_xor(sr, off, 16);
-            si += __shfl_xor(si, off, 16);
+        for (int off = 16; off > 0; off >>= 1) {
+            sr += __shfl_xor(sr, off, 32);
+            si += __shfl_xor(si, off, 32);
         }
         if (ln == 0)
             tv[l * kmax + q] = make_double2(sr, si);
