@@ -58,7 +58,7 @@ FAR_TRAFFIC_BYTES = (2.0 * 23885.20 + 3736479.73) * 1024
 GEMV32_TRAFFIC_BYTES = 2.0 * 923559.66 * 1024
 # HBM bytes of one hierarchical product at 300,516 unknowns: rocprofv3 --pmc FETCH_SIZE (x 2.0) and WRITE_SIZE
 # per dispatch of its four kernels over --workload pmc_probe_c5 (gather, V^T x, apply, sum)
-HMAT_TRAFFIC_BYTES = (2.0 * (4006.2 + 16543798.0 + 28502385.5 + 19334.3) + (4695.6 + 256856.5 + 38076.5 + 5089.2)) * 1024
+HMAT_TRAFFIC_BYTES = (2.0 * (4004.2 + 15906131.5 + 25485994.5 + 19334.3) + (4695.6 + 254775.4 + 38080.4 + 5089.6)) * 1024
 
 
 def parse():

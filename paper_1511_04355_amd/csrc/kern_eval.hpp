@@ -22,17 +22,22 @@ struct Radial {
     cd Psi, X, Psd, Xd;
 };
 
+constexpr int kSer64 = 13;  // FP64 series terms used (of the 16 stored)
+
 // inv_ax2 = 1 / |x|^2, supplied by the caller (from 1/r, without a division);
 // coef: the plan's 64 series coefficients, then the kFmTabLen table entries
 __device__ __forceinline__ Radial radial64(cd x, double beta, const double *__restrict__ coef, double inv_ax2) {
     Radial R;
     const double ax2 = x.r * x.r + x.i * x.i;
     if (ax2 < 0.0625) {
-        // coef: [16][4] = a_n, b_n, (n-1) a_n, (n-1) b_n ; Horner from the top
-        cd p0 = cd{coef[4 * 15 + 0], 0.0}, p1 = cd{coef[4 * 15 + 1], 0.0};
-        cd p2 = cd{coef[4 * 15 + 2], 0.0}, p3 = cd{coef[4 * 15 + 3], 0.0};
+        // coef: [16][4] = a_n, b_n, (n-1) a_n, (n-1) b_n ; Horner from the top.
+        // Terms n <= kSer64 - 1 only: at |x| <= 1/4 the rest sum to below
+        // 7e-17 of the leading ones (the coefficients fall as (n+1)^2/(n+2)!)
+        constexpr int top = kSer64 - 1;
+        cd p0 = cd{coef[4 * top + 0], 0.0}, p1 = cd{coef[4 * top + 1], 0.0};
+        cd p2 = cd{coef[4 * top + 2], 0.0}, p3 = cd{coef[4 * top + 3], 0.0};
 #pragma unroll
-        for (int n = 14; n >= 0; --n) {
+        for (int n = top - 1; n >= 0; --n) {
             p0 = cfma_real(p0, x, coef[4 * n + 0]);
             p1 = cfma_real(p1, x, coef[4 * n + 1]);
             p2 = cfma_real(p2, x, coef[4 * n + 2]);
