@@ -5,6 +5,7 @@
 #include "cplx.hpp"
 #include "fastmath64.hpp"
 #include "internal.hpp"
+#include "kern_mfeval.hpp"
 
 namespace afsbem {
 
@@ -30,23 +31,15 @@ __device__ __forceinline__ Radial radial64(cd x, double beta, const double *__re
     Radial R;
     const double ax2 = x.r * x.r + x.i * x.i;
     if (ax2 < 0.0625) {
-        // coef: [16][4] = a_n, b_n, (n-1) a_n, (n-1) b_n ; Horner from the top.
+        // coef: [16][4] = a_n, b_n, (n-1) a_n, (n-1) b_n, summed from the top.
         // Terms n <= kSer64 - 1 only: at |x| <= 1/4 the rest sum to below
         // 7e-17 of the leading ones (the coefficients fall as (n+1)^2/(n+2)!)
-        constexpr int top = kSer64 - 1;
-        cd p0 = cd{coef[4 * top + 0], 0.0}, p1 = cd{coef[4 * top + 1], 0.0};
-        cd p2 = cd{coef[4 * top + 2], 0.0}, p3 = cd{coef[4 * top + 3], 0.0};
-#pragma unroll
-        for (int n = top - 1; n >= 0; --n) {
-            p0 = cfma_real(p0, x, coef[4 * n + 0]);
-            p1 = cfma_real(p1, x, coef[4 * n + 1]);
-            p2 = cfma_real(p2, x, coef[4 * n + 2]);
-            p3 = cfma_real(p3, x, coef[4 * n + 3]);
-        }
-        R.Psi = p0;
-        R.X = p1;
-        R.Psd = p2;
-        R.Xd = p3;
+        double pr[4], pi[4];
+        series4<double, kSer64, kSer64>(coef, x.r, x.i, ax2, pr, pi);
+        R.Psi = cd{pr[0], pi[0]};
+        R.X = cd{pr[1], pi[1]};
+        R.Psd = cd{pr[2], pi[2]};
+        R.Xd = cd{pr[3], pi[3]};
         return R;
     }
     // coef + 64: the tables of the FP64 exp and sincos
