@@ -54,8 +54,8 @@ FAR_FLOPS_PER_NODE = 307.0
 FAR_NODES = 7
 # HBM bytes per launch from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE over --workload pmc_probe
 # (FETCH_SIZE x 2.0, its reading for a 1 GiB device copy being half the true bytes)
-FAR_TRAFFIC_BYTES = (2.0 * 23885.20 + 3736479.73) * 1024
-GEMV32_TRAFFIC_BYTES = 2.0 * 923559.66 * 1024
+FAR_TRAFFIC_BYTES = (2.0 * 18252.0 + 3736124.9) * 1024
+GEMV32_TRAFFIC_BYTES = (2.0 * 923552.1 + 14831.3) * 1024
 # HBM bytes of one hierarchical product at 300,516 unknowns: rocprofv3 --pmc FETCH_SIZE (x 2.0) and WRITE_SIZE
 # per dispatch of its four kernels over --workload pmc_probe_c5 (gather, V^T x, apply, sum)
 HMAT_TRAFFIC_BYTES = (2.0 * (4004.2 + 15906131.5 + 25485994.5 + 19334.3) + (4695.6 + 254775.4 + 38080.4 + 5089.6)) * 1024
