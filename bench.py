@@ -822,7 +822,8 @@ def run_cavity_L4_line(args, afs, mg, np, torch, steps, warmup, cpu):
 C5_T, C5_KAPPA, C5_NS = 300.0, 3.0, 512
 C5_BAND = 0.25          # the timed frequencies lie in omega <= C5_BAND * Omega_s
 C5_RESTART = 1500
-C5_HMAT_EPS = 1e-5
+C5_HMAT_EPS = 5e-4  # low-rank accuracy of the inner operator: with recycled refinement steps a coarser
+                    # operator is cheaper per product and to build while two FP64 residuals still suffice
 
 
 def c5_frequencies(n, om_max, eta):
