@@ -54,11 +54,11 @@ FAR_FLOPS_PER_NODE = 307.0
 FAR_NODES = 7
 # HBM bytes per launch from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE over --workload pmc_probe
 # (FETCH_SIZE x 2.0, its reading for a 1 GiB device copy being half the true bytes)
-FAR_TRAFFIC_BYTES = (2.0 * 18252.0 + 3736124.9) * 1024
+FAR_TRAFFIC_BYTES = (2.0 * 18304.0 + 3736640.9) * 1024
 GEMV32_TRAFFIC_BYTES = (2.0 * 923552.1 + 14831.3) * 1024
 # HBM bytes of one hierarchical product at 300,516 unknowns: rocprofv3 --pmc FETCH_SIZE (x 2.0) and WRITE_SIZE
 # per dispatch of its four kernels over --workload pmc_probe_c5 (gather, V^T x, apply, sum)
-HMAT_TRAFFIC_BYTES = (2.0 * (4004.2 + 15906131.5 + 25485994.5 + 19334.3) + (4695.6 + 254775.4 + 38080.4 + 5089.6)) * 1024
+HMAT_TRAFFIC_BYTES = (2.0 * (4006.2 + 9547493.7 + 19037592.4 + 19330.8) + (4695.6 + 158170.9 + 38079.8 + 5089.3)) * 1024
 
 
 def parse():
@@ -112,9 +112,10 @@ def parse():
     ap.add_argument("--no-secondary", action="store_true", help="porous_C5: skip the 15,360-unknown cavity line")
     ap.add_argument("--batch", type=int, default=None,
                     help="optimised path: 1 = one frequency at a time, 0 = assembly of the next frequency "
-                         "overlapped with the Krylov phase of the current one (default: 1 on the 300,516-unknown "
-                         "contract line, where the overlapped build slows the products more than it hides; 0 "
-                         "on the cavity line)")
+                         "overlapped with the Krylov phase of the current one, 2 = the next frequency's assembly "
+                         "started with the current one's first FP64 residual (default: 2 on the 300,516-unknown "
+                         "contract line, whose hierarchical build would slow the HBM-bound inner products it "
+                         "overlaps; 0 on the cavity line)")
     return ap.parse_args()
 
 
@@ -883,7 +884,7 @@ def run_contract_c5(args, afs, mg, np, torch):
     bc = _bcs(mesh, s, torch, np)
     print(f"[c5] mesh {time.perf_counter() - t_mesh - plan_s:.1f} s, plan {plan_s:.1f} s, {W} + {K} frequencies",
           file=sys.stderr, flush=True)
-    batch = 1 if args.batch is None else args.batch
+    batch = 2 if args.batch is None else args.batch
     opts = afs.SolveOptions(tol=args.tol, precision=afs.PREC_MIXED, matrix_free=2, hmat_eps=args.hmat_eps,
                             precond=1, restart=C5_RESTART, max_iter=6000, warm_start=afs.WARM_LEARNED,
                             learn_aug=args.learn_aug, profile=1, batch=batch)
@@ -942,8 +943,10 @@ def run_contract_c5(args, afs, mg, np, torch):
                            f"{args.hmat_eps:g}) + FP64 on-the-fly residual, GMRES({C5_RESTART}), cluster "
                            f"block-Jacobi, learned warm start (network trained on the GPU after every solve"
                            f"{', prediction also augmenting the first cycle' if args.learn_aug else ''}), "
-                           + ("two frequencies in flight (hierarchical build of s_k+1 during the Krylov phase "
-                              "of s_k)" if batch != 1 else "one frequency at a time"),
+                           + ({0: "two frequencies in flight (hierarchical build of s_k+1 during the Krylov "
+                                  "phase of s_k)",
+                               2: "two frequencies in flight (hierarchical build of s_k+1 from the first FP64 "
+                                  "residual of s_k on)"}.get(batch, "one frequency at a time")),
                    "plan_s": plan_s, "warmup_s": warm_s},
         "roofline": roof,
         "solve": {"max_rel_res_fp64": worst,
@@ -982,7 +985,7 @@ def run_contract_c5(args, afs, mg, np, torch):
         res["plain_fp64"] = {"value": 1.0 / t_plain, "seconds": t_plain, "s": [float(sp[0].real), 0.0],
                              "products": x["iters"], "rel_res_fp64": x["rel_res_fp64"],
                              "converged": x["status"] == 0,
-                             "product_ms": x["gemv_ms"] / max(x["gemv_count"], 1),
+                             "product_ms": x["gemv64_ms"] / max(x["gemv64_count"], 1),  # FP64 products
                              "path": "FP64 on-the-fly operator, GMRES(50), 3x3 block-Jacobi, zero start, one "
                                      "frequency; timed on s = eta only (a solve at the timed list's higher "
                                      "frequencies needs thousands of 0.6 s products)"}

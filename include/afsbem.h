@@ -265,10 +265,12 @@ typedef struct {
     double inner_tol;    /* mixed: relative reduction asked of each FP32 inner solve; the target
                             is max(inner_tol * ||r||, tol * ||b|| / 2) (default 0: aim at tol) */
     int32_t batch;       /* afsbem_solve_device: 1 = one frequency at a time on the caller's
-                            stream; otherwise (default 0) two in flight, the assembly of
-                            frequency k+1 on one library stream overlapping the Krylov phase of
-                            frequency k on another.  afsbem_solve_batched_device: >= 1 caps the
-                            systems of a wave (default 0: memory-bound, at most 64) */
+                            stream; 2 = two in flight, the assembly of frequency k+1 on one
+                            library stream starting with the first FP64 residual of frequency k
+                            (mixed path) on another; otherwise (default 0) two in flight, the
+                            assembly of frequency k+1 overlapping the whole Krylov phase of
+                            frequency k.  afsbem_solve_batched_device: >= 1 caps the systems of
+                            a wave (default 0: memory-bound, at most 64) */
     uint32_t fault_inject; /* test hooks (AFSBEM_FAULT_* bits), 0 in production */
     int32_t profile;     /* 1: time every matrix-vector kernel with HIP events (stats.gemv_*) */
     int32_t learn_steps; /* AFSBEM_WARM_LEARNED: Adam steps after each solved frequency (0: 24) */

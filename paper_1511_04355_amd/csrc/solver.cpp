@@ -13,6 +13,7 @@
 #include <cmath>
 #include <complex>
 #include <cstring>
+#include <functional>
 
 #include "internal.hpp"
 #include "solver.hpp"
@@ -758,9 +759,19 @@ static void assemble_into(Problem &p, Workspace &ws, int fmt, double s_re, doubl
 // Krylov phase of one frequency on an assembled workspace (stream st); the
 // timing events bracket the assembly (ea0, ea1, possibly on another stream)
 // and this phase.
+// on_residual (nullable): called once, right after the first FP64 residual
+// of the mixed refinement is enqueued (or at the end of a phase without one)
 static int krylov_phase(Problem &p, Workspace &ws, const afsbem_solve_opts &o, int fmt, double s_re, double s_im,
                         const double *d_bc, const double *d_x0, double *d_a, double *d_u, double *d_t,
-                        afsbem_solve_stats *stats, hipStream_t st, hipEvent_t ea0, hipEvent_t ea1, hipEvent_t e2) {
+                        afsbem_solve_stats *stats, hipStream_t st, hipEvent_t ea0, hipEvent_t ea1, hipEvent_t e2,
+                        const std::function<void()> &on_residual = {}) {
+    bool residual_called = false;
+    auto residual_hook = [&]() {
+        if (on_residual && !residual_called) {
+            residual_called = true;
+            on_residual();
+        }
+    };
     const int64_t nt = p.dev.n_tri, N = 3 * nt;
     hipEvent_t ek;  // start of this phase on st
     AFS_HIP(hipEventCreate(&ek));
@@ -865,6 +876,7 @@ static int krylov_phase(Problem &p, Workspace &ws, const afsbem_solve_opts &o, i
                 if (!(o.fault_inject & AFSBEM_FAULT_STALL_INNER))  // test hook: the correction is lost
                     vec_combine(N, 1, ws.x, N, ws.one, ws.xo, st);  // x_outer += d
                 residual(op64, ws, ws.b, ws.xo, ws.rin, st);         // FP64 judge
+                residual_hook();
                 const double rn = norm2_dev(ws, N, ws.rin, st);
                 ++refine;
                 if (!std::isfinite(rn) || g.nan) {
@@ -906,6 +918,7 @@ static int krylov_phase(Problem &p, Workspace &ws, const afsbem_solve_opts &o, i
         if (!std::isfinite(relres))
             status = AFSBEM_ENAN;
     }
+    residual_hook();
     AFS_HIP(hipEventRecord(e2, st));
     if (d_a)
         AFS_HIP(hipMemcpyAsync(d_a, ws.x, (size_t)N * 16, hipMemcpyDeviceToDevice, st));
@@ -1101,10 +1114,17 @@ int solve_pipelined(Problem &p, const afsbem_solve_opts &o, int32_t n_s, const d
             assemble_into(p, w, fmt, s[2 * k], s[2 * k + 1], bc + 2 * (size_t)k * N, SA, o.profile != 0);
             AFS_HIP(hipEventRecord(a1[k], SA));
         };
+        // batch 2: the build of frequency k+1 starts with the first FP64
+        // residual of frequency k (VALU-bound) instead of beside its inner
+        // products (HBM-bound, like the hierarchical build)
+        const bool at_residual = o.batch == 2;
         enqueue_asm(0);
         for (int32_t k = 0; k < n_s; ++k) {
-            if (k + 1 < n_s)
+            if (k + 1 < n_s && !at_residual)
                 enqueue_asm(k + 1);
+            std::function<void()> hook;
+            if (k + 1 < n_s && at_residual)
+                hook = [&enqueue_asm, k]() { enqueue_asm(k + 1); };
             AFS_HIP(hipStreamWaitEvent(SS, a1[k], 0));
             const double *x0 = start_guess(o, k, N, s, x0_user, a_out, W[k % 2]->xstart, SS);
             afsbem_solve_opts ok = o;
@@ -1115,7 +1135,7 @@ int solve_pipelined(Problem &p, const afsbem_solve_opts &o, int32_t n_s, const d
             int r = krylov_phase(p, *W[k % 2], ok, fmt, s[2 * k], s[2 * k + 1], bc + 2 * (size_t)k * N, x0,
                                  a_out ? a_out + 2 * (size_t)k * N : nullptr, u_out ? u_out + 2 * (size_t)k * N : nullptr,
                                  t_out ? t_out + 2 * (size_t)k * N : nullptr, stats ? &stats[k] : nullptr, SS, a0[k],
-                                 a1[k], e2[k]);
+                                 a1[k], e2[k], hook);
             AFS_HIP(hipEventRecord(sdone[k], SS));
             if (r != AFSBEM_OK && rc == AFSBEM_OK)
                 rc = r;

@@ -108,6 +108,36 @@ def test_recycled_refinement_steps(tol):
     assert inner[0] < inner[1]
 
 
+def test_pipelined_schedules_give_the_same_solutions():
+    """Frequencies one at a time (batch 1), two in flight with the next build
+    beside the whole Krylov phase (0) or starting with the first FP64
+    residual (2): the same kernels on the same inputs, so the same solutions
+    (to rounding), each meeting the exact operator's FP64 residual; one
+    frequency against the oracle's LU solution."""
+    import paper_1511_04355_amd as afs
+    from oracle import bem
+    mesh = mg.random_block(3)
+    s = np.array([0.25 + 0.4j, 0.25 + 0.9j, 0.25 + 1.5j, 0.25 + 2.2j])
+    bc = np.stack([np.asarray(mesh.bc_shape, np.complex128) / sk for sk in s])
+    P = afs.Problem.from_mesh(mesh)
+    tol = 1e-6
+    sols = {}
+    for batch in (1, 0, 2):
+        print(f"[hmat] schedule batch={batch}", flush=True)
+        out = P.solve(s, torch.from_numpy(bc).cuda(),
+                      afs.SolveOptions(tol=tol, precision=afs.PREC_MIXED, matrix_free=2, hmat_eps=1e-4, precond=1,
+                                       restart=400, max_iter=4000, warm_start=afs.WARM_PREV, batch=batch))
+        for st in out["stats"]:
+            assert st["status"] == 0 and st["rel_res_fp64"] <= tol, (batch, st)
+        sols[batch] = out["a"].cpu().numpy()
+    for batch in (0, 2):
+        d = np.linalg.norm(sols[batch] - sols[1], axis=1) / np.linalg.norm(sols[1], axis=1)
+        assert np.all(d <= 1e-10), (batch, d)
+    A, b = bem.assemble(mesh, s[2])
+    xo = bem.solve_dense(A, b)
+    assert np.linalg.norm(sols[2][2] - xo) / np.linalg.norm(xo) <= 1e-5
+
+
 def test_hmat_option_checks():
     import paper_1511_04355_amd as afs
     mesh = mg.cavity(1)
