@@ -27,7 +27,7 @@ constexpr int kHmatKmax = 128;  // terms per low-rank block at most
 constexpr int kHmatGroup = 8;   // terms per pool slot
 // dense blocks are column-major with an even row count (the product reads two
 // rows per 16-byte load); the padding row is zero
-constexpr int kHmatApplyParts = 8;  // partial sums per row of the product (parts of each leaf's block list)
+constexpr int kHmatApplyParts = 32;  // partial sums per row of the product (parts of each leaf's block list)
 __host__ __device__ inline int64_t dense_rows_padded(int64_t n_elems) { return 3 * n_elems + ((3 * n_elems) & 1); }
 // entries of one pool slot of a low-rank block with RL padded rows (summed
 // over its leaves) and Cp padded columns, rounded to 128 bytes
