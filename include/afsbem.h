@@ -266,8 +266,9 @@ typedef struct {
                             is max(inner_tol * ||r||, tol * ||b|| / 2) (default 0: aim at tol) */
     int32_t batch;       /* afsbem_solve_device: 1 = one frequency at a time on the caller's
                             stream; 2 = two in flight, the assembly of frequency k+1 on one
-                            library stream starting with the first FP64 residual of frequency k
-                            (mixed path) on another; otherwise (default 0) two in flight, the
+                            library stream starting when frequency k's first inner solve (mixed
+                            path, on another stream) is within 50x of its target, or with its
+                            first FP64 residual; otherwise (default 0) two in flight, the
                             assembly of frequency k+1 overlapping the whole Krylov phase of
                             frequency k.  afsbem_solve_batched_device: >= 1 caps the systems of
                             a wave (default 0: memory-bound, at most 64) */

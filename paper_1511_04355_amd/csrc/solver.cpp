@@ -261,7 +261,8 @@ static void givens_apply(cplx c, cplx s, cplx &a, cplx &b) {
 
 GmresResult gmres(const Operator &op, Workspace &ws, int64_t /*n_tri*/, const double *rhs, double rhs_norm,
                   double *x, bool x_is_zero, double tol_abs, int restart, int max_iter, hipStream_t st,
-                  bool verify, const double *r0, double r0_norm, const double *aug, int recycle) {
+                  bool verify, const double *r0, double r0_norm, const double *aug, int recycle,
+                  const std::function<void(double)> &progress) {
     const int64_t N = op.N;
     GmresResult res;
     // Hessenberg columns packed one after another (column j holds rows 0..j+1),
@@ -540,6 +541,8 @@ GmresResult gmres(const Operator &op, Workspace &ws, int64_t /*n_tri*/, const do
             g[j] = cs[j] * g[j];
             k = j + 1;
             res.est = std::abs(g[j + 1]);
+            if (progress)
+                progress(res.est);
             if (res.est <= 0.5 * tol_abs || res.iters >= max_iter || hn == 0.0)
                 break;
         }
@@ -759,8 +762,9 @@ static void assemble_into(Problem &p, Workspace &ws, int fmt, double s_re, doubl
 // Krylov phase of one frequency on an assembled workspace (stream st); the
 // timing events bracket the assembly (ea0, ea1, possibly on another stream)
 // and this phase.
-// on_residual (nullable): called once, right after the first FP64 residual
-// of the mixed refinement is enqueued (or at the end of a phase without one)
+// on_residual (nullable): called once, when the first inner solve of the
+// mixed refinement comes within 50x of its target, else right after the first
+// FP64 residual is enqueued, else at the end of the phase
 static int krylov_phase(Problem &p, Workspace &ws, const afsbem_solve_opts &o, int fmt, double s_re, double s_im,
                         const double *d_bc, const double *d_x0, double *d_a, double *d_u, double *d_t,
                         afsbem_solve_stats *stats, hipStream_t st, hipEvent_t ea0, hipEvent_t ea1, hipEvent_t e2,
@@ -869,8 +873,16 @@ static int krylov_phase(Problem &p, Workspace &ws, const afsbem_solve_opts &o, i
                 const double *av = refine == 0 ? aug_vec : nullptr;
                 // later steps search the first inner solve's Krylov subspace first
                 const int rcy = o.no_recycle ? 0 : (refine == 0 ? 1 : 2);
+                // the caller's hook (the next frequency's build) also fires once the
+                // first inner solve is within 50x of its target, its last ~20 products
+                std::function<void(double)> progress;
+                if (on_residual && refine == 0)
+                    progress = [&, tol_in](double est) {
+                        if (est <= 50.0 * tol_in)
+                            residual_hook();
+                    };
                 GmresResult g = gmres(op32, ws, nt, ws.rin, rnorm, ws.x, true, tol_in, o.restart,
-                                      std::max(1, o.max_iter - matvecs), st, false, nullptr, 0.0, av, rcy);
+                                      std::max(1, o.max_iter - matvecs), st, false, nullptr, 0.0, av, rcy, progress);
                 if (av)
                     aug_gain = g.aug_gain;
                 if (!(o.fault_inject & AFSBEM_FAULT_STALL_INNER))  // test hook: the correction is lost
@@ -1114,9 +1126,10 @@ int solve_pipelined(Problem &p, const afsbem_solve_opts &o, int32_t n_s, const d
             assemble_into(p, w, fmt, s[2 * k], s[2 * k + 1], bc + 2 * (size_t)k * N, SA, o.profile != 0);
             AFS_HIP(hipEventRecord(a1[k], SA));
         };
-        // batch 2: the build of frequency k+1 starts with the first FP64
-        // residual of frequency k (VALU-bound) instead of beside its inner
-        // products (HBM-bound, like the hierarchical build)
+        // batch 2: the build of frequency k+1 starts near the end of frequency
+        // k's first inner solve (see krylov_phase), so that it overlaps the
+        // VALU-bound FP64 residual rather than the HBM-bound inner products
+        // (the hierarchical build is HBM-bound too)
         const bool at_residual = o.batch == 2;
         enqueue_asm(0);
         for (int32_t k = 0; k < n_s; ++k) {

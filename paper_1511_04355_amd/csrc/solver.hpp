@@ -1,6 +1,7 @@
 // Solver internals: device workspace, operator, GMRES.
 #pragma once
 #include <complex>
+#include <functional>
 #include <vector>
 
 #include "internal.hpp"
@@ -108,13 +109,16 @@ struct GmresResult {
 // (flexible GMRES with aug as direction 0 and the preconditioned basis
 // vectors after it), its coefficient found by the same least-squares problem.
 //
+// progress (nullable): called with the residual estimate after every Arnoldi
+// step of the ordinary cycles.
 // recycle: 0 = none; 1 = keep the last cycle's subspace in ws (rc_*); 2 = the
 // first cycle (x zero, no aug) starts from the kept subspace of the same
 // operator: the solution is sought in M^-1 span(kept V_K) plus the Krylov
 // space of the residual's part outside span(V_{K+1}).
 GmresResult gmres(const Operator &op, Workspace &ws, int64_t n_tri, const double *rhs, double rhs_norm, double *x,
                   bool x_is_zero, double tol_abs, int restart, int max_iter, hipStream_t st, bool verify,
-                  const double *r0 = nullptr, double r0_norm = 0.0, const double *aug = nullptr, int recycle = 0);
+                  const double *r0 = nullptr, double r0_norm = 0.0, const double *aug = nullptr, int recycle = 0,
+                  const std::function<void(double)> &progress = {});
 
 int solve_pipelined(Problem &p, const afsbem_solve_opts &o, int32_t n_s, const double *s, const double *bc,
                     const double *x0_user, double *a_out, double *u_out, double *t_out,
