@@ -276,7 +276,7 @@ typedef struct {
     int32_t profile;     /* 1: time every matrix-vector kernel with HIP events (stats.gemv_*) */
     int32_t learn_steps; /* AFSBEM_WARM_LEARNED: Adam steps after each solved frequency (0: 24) */
     int32_t precond;     /* block-diagonal preconditioner: 0 = one 3x3 block per collocation point;
-                            1 = blocks over spatial clusters of up to 32 elements (recursive
+                            1 = blocks over spatial clusters of up to 49 elements (recursive
                             coordinate bisection), inverted in FP32 on the device (with
                             matrix_free: the blocks are evaluated, far rule + near/self blocks) */
     int32_t matrix_free; /* 1: no stored matrix; every product evaluates the far-field rule on the

@@ -212,10 +212,11 @@ size_t layout(Wave &W, const std::vector<SysRef> &all, Problem *const *probs, in
 
 size_t system_bytes(const SysRef &r, int m, int prec) {
     // matrix (16 B per entry in both formats), vectors and basis, blocks, and
-    // the cluster inverses (kClusterDim^2 complex64 per cluster; clusters hold at least
-    // kClusterElems/2 >= 12 elements, so nt/12 + 2 bounds their count)
+    // the cluster inverses (kClusterDim^2 complex64 per cluster; a split cell
+    // leaves clusters of more than kClusterElems / 2 >= 24 elements, so
+    // nt/24 + 2 bounds their count)
     return (size_t)r.N * r.lda * 16 + (size_t)r.N * (m + 8) * 16 + (size_t)r.nt * 144 +
-           (prec == 1 ? (size_t)(r.nt / 12 + 2) * kClusterDim * kClusterDim * 8 : 0);
+           (prec == 1 ? (size_t)(r.nt / 24 + 2) * kClusterDim * kClusterDim * 8 : 0);
 }
 
 template <class T>

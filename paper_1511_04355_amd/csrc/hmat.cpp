@@ -90,7 +90,7 @@ void hmat_build(const Problem &p, double eta, int kmax, HmatPlan &H, bool upload
         }
         const int me = (int)nodes.size();
         nodes.push_back(t);
-        if (e - b <= kClusterElems)
+        if (e - b <= kLeafElems)
             return me;
         int ax = 0;
         for (int d = 1; d < 3; ++d)

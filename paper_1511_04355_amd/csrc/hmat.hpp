@@ -2,7 +2,7 @@
 // inner (FP32-precision) operator of the mixed matrix-free solve.
 //
 // A binary cluster tree over the elements (recursive coordinate bisection of
-// the collocation points, leaves of at most kClusterElems elements) and a
+// the collocation points, leaves of at most kLeafElems elements) and a
 // block partition of (tree, tree): a pair of clusters whose bounding spheres
 // are separated by at least eta times the larger radius, and between which
 // there is no near pair, is admissible and stored as low-rank factors

@@ -45,8 +45,9 @@ MaterialDerived derive_material(const afsbem_material &m);
 // Per-element source record read with wave-uniform (scalar) loads by the far
 // field kernel: 7 quadrature nodes (x, y, z, weight*area), unit normal, kind.
 constexpr int kFarNodes = 7;
-constexpr int kClusterElems = 32;                  // elements per preconditioner cluster (at most)
+constexpr int kClusterElems = 49;                  // elements per preconditioner cluster (at most)
 constexpr int kClusterDim = 3 * kClusterElems;      // unknowns per cluster block (at most)
+constexpr int kLeafElems = 32;                     // elements per leaf of the hierarchical operator (at most)
 constexpr int kSrcStride = 32;  // doubles per element record
 
 struct HostPlan {

@@ -262,15 +262,16 @@ def test_solve_cluster_preconditioner(prec, mesh_name):
 
 
 def test_cluster_preconditioner_blocks():
-    """The clusters partition the elements (at most 24 each) and M^-1 v equals
-    the block-diagonal inverse over them (FP32 inverses: 1e-5)."""
+    """The clusters partition the elements (at most 49 each, the preconditioner
+    cluster size) and M^-1 v equals the block-diagonal inverse over them (FP32
+    inverses: 1e-5)."""
     afs, bem = _afs(), _oracle()
     mesh = mg.cavity(2)
     s = 0.25 + 1.5j
     P = afs.Problem.from_mesh(mesh)
     ptr, elem = P.clusters()
     assert np.array_equal(np.sort(elem), np.arange(mesh.n_tri))
-    assert np.all(np.diff(ptr) >= 1) and np.all(np.diff(ptr) <= 24)
+    assert np.all(np.diff(ptr) >= 1) and np.all(np.diff(ptr) <= 49)
     A, _, _, _ = P.assemble(s, _bc_dev(mesh, s), fmt=afs.FMT_C128)
     Ao = _dense_from_colmajor(A, P.N)
     rng = np.random.default_rng(1)
