@@ -58,7 +58,7 @@ FAR_TRAFFIC_BYTES = (2.0 * 18304.0 + 3736640.9) * 1024
 GEMV32_TRAFFIC_BYTES = (2.0 * 923552.1 + 14831.3) * 1024
 # HBM bytes of one hierarchical product at 300,516 unknowns: rocprofv3 --pmc FETCH_SIZE (x 2.0) and WRITE_SIZE
 # per dispatch of its four kernels over --workload pmc_probe_c5 (gather, V^T x, apply, sum)
-HMAT_TRAFFIC_BYTES = (2.0 * (4006.2 + 9549049.9 + 19045590.2 + 76580.7) + (4695.6 + 158173.6 + 152324.2 + 5097.3)) * 1024
+HMAT_TRAFFIC_BYTES = (2.0 * (4004.2 + 10904917.6 + 19176654.4 + 76577.0) + (4695.6 + 157952.8 + 152310.3 + 5098.2)) * 1024
 
 
 def parse():

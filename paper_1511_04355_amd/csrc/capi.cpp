@@ -461,11 +461,11 @@ int afsbem_hmat_matvec_device(afsbem_problem *p, double s_re, double s_im, doubl
         hmat_ensure(P, eta);
         hmat_setup(P, ws, kp, eps, st);
         AFS_HIP(hipStreamSynchronize(st));
-        bool ok = hmat_finish(P, ws);
+        bool ok = hmat_finish(P, ws, st);
         for (int tries = 0; !ok && ws.hm_exhausted && tries < 3; ++tries) {
             hmat_setup(P, ws, kp, eps, st);  // a larger pool
             AFS_HIP(hipStreamSynchronize(st));
-            ok = hmat_finish(P, ws);
+            ok = hmat_finish(P, ws, st);
         }
         hmat_apply(P, ws, static_cast<const double *>(d_x), static_cast<double *>(d_y), st);
         AFS_HIP(hipStreamSynchronize(st));

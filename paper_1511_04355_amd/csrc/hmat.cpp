@@ -172,6 +172,23 @@ void hmat_build(const Problem &p, double eta, int kmax, HmatPlan &H, bool upload
             H.n_mid = (int64_t)H.lr_order.size() - H.n_small;
     }
 
+    H.vt_order.resize(nl);
+    for (int64_t l = 0; l < nl; ++l)
+        H.vt_order[l] = (int32_t)l;
+    // width classes widest first (their long streams start early), within a
+    // class by column range, so that the items in flight at a time read
+    // neighbouring parts of x (from L2 rather than memory)
+    auto wclass = [&](int32_t u) {
+        const int64_t nb = H.lowrank[4 * (int64_t)u + 3] - H.lowrank[4 * (int64_t)u + 2];
+        return nb > 256 ? 3 : (nb > 64 ? 2 : (nb > kLeafElems ? 1 : 0));
+    };
+    std::stable_sort(H.vt_order.begin(), H.vt_order.end(), [&](int32_t u, int32_t w) {
+        const int cu = wclass(u), cw = wclass(w);
+        if (cu != cw)
+            return cu > cw;
+        return H.lowrank[4 * (int64_t)u + 2] < H.lowrank[4 * (int64_t)w + 2];
+    });
+
     // ---- per leaf row range: the dense blocks of its block row and every
     // low-rank block whose row range holds it (fixed order: dense, then low-rank)
     H.leaves.clear();
@@ -222,7 +239,7 @@ void hmat_build(const Problem &p, double eta, int kmax, HmatPlan &H, bool upload
         H.leaf_item.insert(H.leaf_item.end(), items[L].begin(), items[L].end());
         H.leaf_ptr[L + 1] = (int64_t)H.leaf_item.size();
     }
-    AFS_REQUIRE(nd < ((int64_t)1 << 31) && nl < ((int64_t)1 << 30) && nleaf < ((int64_t)1 << 31), AFSBEM_EINVAL,
+    AFS_REQUIRE(nd < ((int64_t)1 << 31) && nl < ((int64_t)1 << 25) && nleaf < ((int64_t)1 << 31), AFSBEM_EINVAL,
                 "hierarchical partition too large");
 
     if (!upload)

@@ -25,6 +25,7 @@ struct Workspace;
 
 constexpr int kHmatKmax = 128;  // terms per low-rank block at most
 constexpr int kHmatGroup = 8;   // terms per pool slot
+static_assert(kHmatKmax / kHmatGroup <= 16, "a V^T x item packs its first slot in four bits");
 // dense blocks are column-major with an even row count (the product reads two
 // rows per 16-byte load); the padding row is zero
 constexpr int kHmatApplyParts = 32;  // partial sums per row of the product (parts of each leaf's block list)
@@ -45,6 +46,7 @@ struct HmatPlan {
     std::vector<int64_t> dense_off; // [nd+1] offsets (complex entries) of the dense blocks (padded rows)
     int64_t lr_rows = 0;            // sum over low-rank blocks of RL + Cp (one term's padded entries)
     std::vector<int32_t> lr_order;  // low-rank blocks by size: at most 64 elements a side, at most 128, larger
+    std::vector<int32_t> vt_order;  // low-rank blocks in the order of the V^T x work (width classes, then columns)
     int64_t n_small = 0, n_mid = 0;
     std::vector<int64_t> leaves;    // [nleaf][2] row ranges of the leaves
     std::vector<int64_t> leaf_ptr;  // [nleaf+1]
@@ -76,9 +78,12 @@ void hmat_ensure(Problem &p, double eta);
 // copied to pinned host memory on st.  hmat_finish, once st's work has
 // completed, reads them: false when an admissible block did not reach eps
 // within kmax or found the pool spent (ws.hm_exhausted; the operator then
-// stays the on-the-fly one unless the build is repeated).
+// stays the on-the-fly one unless the build is repeated).  It also lists the
+// work items of the product's V^T x pass (runs of a block's slots) for the
+// ranks reached, widest blocks first, and copies them to the device on st (from pinned
+// memory that the next call overwrites: st must have finished the copy by then).
 void hmat_setup(const Problem &p, Workspace &ws, const KernelParams &kp, double eps, hipStream_t st);
-bool hmat_finish(Problem &p, Workspace &ws);
+bool hmat_finish(Problem &p, Workspace &ws, hipStream_t st);
 // y = A_H x
 void hmat_apply(const Problem &p, const Workspace &ws, const double *x, double *y, hipStream_t st);
 

@@ -455,79 +455,170 @@ __global__ __launch_bounds__(256) void hm_gather_kernel(int64_t n, const int32_t
         xp[i] = x[3 * (int64_t)perm[i / 3] + i % 3];
 }
 
-// t_q = V_q^T x for every term of every low-rank block: one work-group per
-// block, a slot of kHmatGroup terms (contiguous) per pass, 32 lanes per term
-// (16-byte loads of two entries; each lane's two loads of a 64-wide stripe
-// issued unconditionally from clamped indices, so that the whole slot is in
-// flight at once).  The block's x segment, which every term reads, is staged
-// in LDS once when it fits (up to kVtLds entries).
-constexpr int kVtLds = 1536;
+// t_q = V_q^T x for every term of every low-rank block, as a list of items
+// of up to four slots of one block (widest blocks first, then by column
+// range: the items in flight share their x), taken by a grid of single-wave
+// work-groups in turn (item i by wave i mod the grid).  Lane j takes the
+// column pairs j, j + 64, ... of all kHmatGroup terms of the slot: x is read
+// once per pair for the eight terms and eight 16-byte loads of V are in
+// flight per lane, issued unconditionally from clamped indices (the terms
+// past the rank read the last term again and are not written).  The next
+// item's description is loaded while the first loads of the current one are
+// in flight.  The 16 sums (term, real / imaginary) are reduced over the wave
+// by a butterfly that halves the set each lane keeps at every step: 17
+// exchanges, after which lanes 4k .. 4k + 3 hold sum k.
+constexpr int kVtWaves = 256 * 20;  // waves of the V^T x pass (20 per compute unit: the occupancy its registers allow)
 
-// one lane's share of t_q (32 lanes per term) with x read from xr (LDS or global)
-__device__ __forceinline__ void vt_term(const float2 *__restrict__ V, const double2 *__restrict__ xr, int64_t C,
-                                        int ln, double &sr, double &si) {
-    const int64_t C2 = C >> 1;
-    const float4 *V4 = reinterpret_cast<const float4 *>(V);
-    const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
-    for (int64_t s0 = 0; s0 < C2; s0 += 64) {
-        const int64_t ca = s0 + ln, cb = s0 + 32 + ln;
-        const int64_t ia = ca < C2 ? ca : C2 - 1, ib = cb < C2 ? cb : C2 - 1;
-        const float4 va0 = V4[ia], vb0 = V4[ib];
-        const double2 xa0 = xr[2 * ia], xa1 = xr[2 * ia + 1], xb0 = xr[2 * ib], xb1 = xr[2 * ib + 1];
-        const float4 va = ca < C2 ? va0 : z4, vb = cb < C2 ? vb0 : z4;
-        sr += (double)va.x * xa0.x - (double)va.y * xa0.y + (double)va.z * xa1.x - (double)va.w * xa1.y;
-        si += (double)va.x * xa0.y + (double)va.y * xa0.x + (double)va.z * xa1.y + (double)va.w * xa1.x;
-        sr += (double)vb.x * xb0.x - (double)vb.y * xb0.y + (double)vb.z * xb1.x - (double)vb.w * xb1.y;
-        si += (double)vb.x * xb0.y + (double)vb.y * xb0.x + (double)vb.z * xb1.y + (double)vb.w * xb1.x;
-    }
-    if ((C & 1) && ln == 0) {
-        const float2 v = V[C - 1];
-        const double2 xv = xr[C - 1];
-        sr += (double)v.x * xv.x - (double)v.y * xv.y;
-        si += (double)v.x * xv.y + (double)v.y * xv.x;
+struct VtItem {
+    const float4 *V;    // the current slot's first term (V part), 16-byte units
+    const float2 *P;    // the block's V parts: pool + kHmatGroup * (padded rows of the block)
+    const int64_t *so;  // the block's slot offsets
+    const double2 *x;   // the block's column range of x (tree order)
+    int64_t C, st4;     // columns; float4 per term
+    int64_t t0;         // index of the current slot's first t_q
+    int s, send, rk;    // current slot, end of the item's slots, rank
+    int last;           // terms in the current slot less one
+};
+
+// item code: block << 6 | first slot << 2 | (slots - 1)
+__device__ __forceinline__ VtItem vt_item(int32_t code, const int64_t *__restrict__ lowrank, int kmax,
+                                          const int *__restrict__ rank, const int64_t *__restrict__ offs,
+                                          const int64_t *__restrict__ lr_rp, const float2 *__restrict__ pool,
+                                          const double2 *__restrict__ xp) {
+    const int64_t l = code >> 6;
+    VtItem m;
+    m.s = (code >> 2) & 15;
+    m.send = m.s + (code & 3) + 1;
+    const int64_t b0 = lowrank[4 * l + 2];
+    m.C = 3 * (lowrank[4 * l + 3] - b0);
+    m.st4 = (m.C + (m.C & 1)) >> 1;
+    m.rk = rank[l];
+    const int nq = m.rk - m.s * kHmatGroup;  // >= 1: items hold live slots only
+    m.last = (nq < kHmatGroup ? nq : kHmatGroup) - 1;
+    m.P = pool + kHmatGroup * lr_rp[2 * l + 1];
+    m.so = offs + l * hm_slots(kmax);
+    m.V = reinterpret_cast<const float4 *>(m.P + m.so[m.s]);
+    m.x = xp + 3 * b0;
+    m.t0 = l * kmax + m.s * kHmatGroup;
+    return m;
+}
+
+// the item's next slot
+__device__ __forceinline__ VtItem vt_next_slot(VtItem m) {
+    m.s += 1;
+    const int nq = m.rk - m.s * kHmatGroup;
+    m.last = (nq < kHmatGroup ? nq : kHmatGroup) - 1;
+    m.V = reinterpret_cast<const float4 *>(m.P + m.so[m.s]);
+    m.t0 += kHmatGroup;
+    return m;
+}
+
+// one butterfly step: lanes whose bit log2(4 H) is clear keep sums 0 .. H-1
+// of their set, the others sums H .. 2H-1, each added to its partner's copy
+template <int H>
+__device__ __forceinline__ void vt_halve(double (&s)[16], int lane) {
+    const bool hi = (lane & (4 * H)) != 0;
+#pragma unroll
+    for (int k = 0; k < H; ++k) {
+        const double send = hi ? s[k] : s[k + H];
+        const double keep = hi ? s[k + H] : s[k];
+        s[k] = keep + __shfl_xor(send, 4 * H, 64);
     }
 }
 
-__global__ __launch_bounds__(256) void hm_vt_kernel(const int64_t *__restrict__ lowrank, int kmax,
-                                                    const int *__restrict__ rank, const int64_t *__restrict__ offs,
-                                                    const int64_t *__restrict__ lr_rp,
-                                                    const float2 *__restrict__ pool, const double2 *__restrict__ xp,
-                                                    double2 *__restrict__ tv) {
-    static_assert(kHmatGroup * 32 == 256, "one slot per pass of the work-group");
-    __shared__ double2 xs[kVtLds];
-    const int64_t l = blockIdx.x;
-    const int g = threadIdx.x >> 5, ln = threadIdx.x & 31;
-    const int64_t b0 = lowrank[4 * l + 2];
-    const int64_t C = 3 * (lowrank[4 * l + 3] - b0);
-    const int64_t Cp = C + (C & 1);
-    const int64_t vbase = kHmatGroup * lr_rp[2 * l + 1] + (int64_t)g * Cp;  // this term's V within a slot
-    const int64_t *so = offs + l * hm_slots(kmax);
-    const int rk = rank[l];
-    const bool staged = C <= kVtLds;  // block-uniform
-    const double2 *xb = xp + 3 * b0;
-    if (staged) {
-        for (int64_t c = threadIdx.x; c < C; c += 256)
-            xs[c] = xb[c];
-        __syncthreads();
-    }
-    for (int q0 = 0; q0 < rk; q0 += kHmatGroup) {
-        const int q = q0 + g;
-        if (q >= rk)
-            continue;
-        const float2 *V = pool + so[q0 / kHmatGroup] + vbase;
-        double sr = 0.0, si = 0.0;
-        if (staged)
-            vt_term(V, xs, C, ln, sr, si);
-        else
-            vt_term(V, xb, C, ln, sr, si);
+__global__ __launch_bounds__(64) void hm_vt_kernel(const int32_t *__restrict__ items, int64_t n_items,
+                                                   const int64_t *__restrict__ lowrank, int kmax,
+                                                   const int *__restrict__ rank, const int64_t *__restrict__ offs,
+                                                   const int64_t *__restrict__ lr_rp, const float2 *__restrict__ pool,
+                                                   const double2 *__restrict__ xp, double2 *__restrict__ tv) {
+    static_assert(kHmatGroup == 8, "eight terms per item");
+    int64_t it = blockIdx.x;
+    if (it >= n_items)
+        return;
+    const int lane = threadIdx.x;
+    const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
+    VtItem m = vt_item(items[it], lowrank, kmax, rank, offs, lr_rp, pool, xp);
+    for (;;) {
+        const int64_t nx = it + gridDim.x;
+        const int64_t C2 = m.C >> 1;  // >= 1
+        double sr[8], si[8];
+        {
+            const int64_t pc = lane < C2 ? lane : C2 - 1;
+            float4 va[8];
 #pragma unroll
-        for (int off = 16; off > 0; off >>= 1) {
-            sr += __shfl_xor(sr, off, 32);
-            si += __shfl_xor(si, off, 32);
+            for (int e = 0; e < 8; ++e)
+                va[e] = m.V[(int64_t)(e < m.last ? e : m.last) * m.st4 + pc];
+            const double2 x0 = m.x[2 * pc], x1 = m.x[2 * pc + 1];
+            const bool same = m.s + 1 < m.send;
+            VtItem mn = m;
+            if (same)
+                mn = vt_next_slot(m);
+            else if (nx < n_items)
+                mn = vt_item(items[nx], lowrank, kmax, rank, offs, lr_rp, pool, xp);
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const float4 v = lane < C2 ? va[e] : z4;
+                sr[e] = (double)v.x * x0.x - (double)v.y * x0.y + (double)v.z * x1.x - (double)v.w * x1.y;
+                si[e] = (double)v.x * x0.y + (double)v.y * x0.x + (double)v.z * x1.y + (double)v.w * x1.x;
+            }
+            for (int64_t p0 = 64; p0 < C2; p0 += 64) {
+                const int64_t pa = p0 + lane;
+                const int64_t pq = pa < C2 ? pa : C2 - 1;
+#pragma unroll
+                for (int e = 0; e < 8; ++e)
+                    va[e] = m.V[(int64_t)(e < m.last ? e : m.last) * m.st4 + pq];
+                const double2 y0 = m.x[2 * pq], y1 = m.x[2 * pq + 1];
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const float4 v = pa < C2 ? va[e] : z4;
+                    sr[e] += (double)v.x * y0.x - (double)v.y * y0.y + (double)v.z * y1.x - (double)v.w * y1.y;
+                    si[e] += (double)v.x * y0.y + (double)v.y * y0.x + (double)v.z * y1.y + (double)v.w * y1.x;
+                }
+            }
+            if ((m.C & 1) && lane == 0) {  // the odd last column
+                const double2 xv = m.x[m.C - 1];
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const float2 v =
+                        reinterpret_cast<const float2 *>(m.V + (int64_t)(e < m.last ? e : m.last) * m.st4)[m.C - 1];
+                    sr[e] += (double)v.x * xv.x - (double)v.y * xv.y;
+                    si[e] += (double)v.x * xv.y + (double)v.y * xv.x;
+                }
+            }
+            // sums k = 2 e + {0: real, 1: imaginary}
+            double s[16];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                s[2 * e] = sr[e];
+                s[2 * e + 1] = si[e];
+            }
+            vt_halve<8>(s, lane);
+            vt_halve<4>(s, lane);
+            vt_halve<2>(s, lane);
+            vt_halve<1>(s, lane);
+            s[0] += __shfl_xor(s[0], 2, 64);
+            s[0] += __shfl_xor(s[0], 1, 64);
+            const int k = lane >> 2, e = k >> 1;
+            if ((lane & 3) == 0 && e <= m.last)
+                reinterpret_cast<double *>(tv)[2 * (m.t0 + e) + (k & 1)] = s[0];
+            if (!same) {
+                if (nx >= n_items)
+                    break;
+                it = nx;
+            }
+            m = mn;
         }
-        if (ln == 0)
-            tv[l * kmax + q] = make_double2(sr, si);
     }
+}
+
+// a 16-byte load marked non-temporal: the product's matrix entries are read
+// once per product, and keeping them out of the way of x and t in the caches
+// measured faster for the dense blocks and U (6.46 -> 5.84 ms per product
+// pass at 300,516 unknowns), slower for V in the V^T x pass (4.04 -> 5.01 ms)
+typedef float hm_v4f __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ float4 ld_nt(const float4 *p) {
+    const hm_v4f v = __builtin_nontemporal_load(reinterpret_cast<const hm_v4f *>(p));
+    return make_float4(v.x, v.y, v.z, v.w);
 }
 
 constexpr int kHmSplit = kHmatApplyParts;  // single-wave work-groups per leaf: each takes every kHmSplit-th block of its list
@@ -580,13 +671,13 @@ __global__ __launch_bounds__(64) void hm_apply_kernel(
                 float4 v[8];
 #pragma unroll
                 for (int u = 0; u < 8; ++u)
-                    v[u] = D[(c + u) * ld];
+                    v[u] = ld_nt(&D[(c + u) * ld]);
 #pragma unroll
                 for (int u = 0; u < 8; ++u)
                     cmac2(a0r, a0i, a1r, a1i, live ? v[u] : z4, xb[c + u]);
             }
             for (; c < C; ++c) {
-                const float4 v = D[c * ld];
+                const float4 v = ld_nt(&D[c * ld]);
                 cmac2(a0r, a0i, a1r, a1i, live ? v : z4, xb[c]);
             }
         } else {
@@ -606,7 +697,7 @@ __global__ __launch_bounds__(64) void hm_apply_kernel(
                 float4 u[8];
 #pragma unroll
                 for (int e = 0; e < 8; ++e)
-                    u[e] = U[(e < last ? e : last) * st4];
+                    u[e] = ld_nt(&U[(e < last ? e : last) * st4]);
 #pragma unroll
                 for (int e = 0; e < 8; ++e)
                     cmac2(a0r, a0i, a1r, a1i, live ? u[e] : z4, e <= last ? tb[q + e] : make_double2(0.0, 0.0));
@@ -683,7 +774,7 @@ void hmat_setup(const Problem &p, Workspace &ws, const KernelParams &kp, double 
     ws.hm_ok = false;  // until hmat_finish has read the ranks
 }
 
-bool hmat_finish(Problem &p, Workspace &ws) {
+bool hmat_finish(Problem &p, Workspace &ws, hipStream_t st) {
     const int64_t nl = (int64_t)p.hmat->lowrank.size() / 4;
     const std::vector<int64_t> &lr = p.hmat->lowrank;
     ws.hm_max_rank = 0;
@@ -700,6 +791,19 @@ bool hmat_finish(Problem &p, Workspace &ws) {
     }
     ws.hm_bytes = entries * 8.0;
     ws.hm_ok = ok;
+    // the V^T x items of this build's ranks
+    // up to four slots of a block per item (two for blocks wider than 1,536
+    // columns): the slots of an item share one read of the block's x
+    int64_t k = 0;
+    for (const int32_t l : p.hmat->vt_order) {
+        const int ns = hm_slots(std::min(ws.hm_host[l], p.hmat->kmax));
+        const int per = 3 * (lr[4 * (int64_t)l + 3] - lr[4 * (int64_t)l + 2]) <= 1536 ? 4 : 2;
+        for (int j = 0; j < ns; j += per)
+            ws.hm_items_host[k++] = (l << 6) | (j << 2) | (std::min(per, ns - j) - 1);
+    }
+    ws.hm_n_items = k;
+    if (k)
+        AFS_HIP(hipMemcpyAsync(ws.hm_items, ws.hm_items_host, (size_t)k * sizeof(int32_t), hipMemcpyHostToDevice, st));
     // a block that found the pool spent (status 2): the next build asks for
     // twice the pool or 1.5 x what this one requested, whichever is larger
     ws.hm_exhausted = false;
@@ -718,9 +822,10 @@ void hmat_apply(const Problem &p, const Workspace &ws, const double *x, double *
     const int64_t nl = (int64_t)H.lowrank.size() / 4, nleaf = (int64_t)H.leaves.size() / 2;
     const double2 *xv = reinterpret_cast<const double2 *>(x);
     hm_gather_kernel<<<(unsigned)((3 * H.n + 255) / 256), 256, 0, st>>>(H.n, H.d_perm, xv, ws.hm_xp);
-    if (nl)
-        hm_vt_kernel<<<(unsigned)nl, 256, 0, st>>>(H.d_lowrank, H.kmax, ws.hm_rank, ws.hm_offs, H.d_lr_rp, ws.hm_pool,
-                                                    ws.hm_xp, ws.hm_t);
+    if (ws.hm_n_items)
+        hm_vt_kernel<<<(unsigned)std::min<int64_t>(ws.hm_n_items, kVtWaves), 64, 0, st>>>(
+            ws.hm_items, ws.hm_n_items, H.d_lowrank, H.kmax, ws.hm_rank, ws.hm_offs, H.d_lr_rp, ws.hm_pool, ws.hm_xp,
+            ws.hm_t);
     hm_apply_kernel<<<dim3((unsigned)nleaf, kHmSplit), 64, 0, st>>>(
         H.d_leaves, H.d_leaf_ptr, H.d_leaf_item, H.d_dense, H.d_dense_off, H.d_leaf_prow, H.d_lr_rp, H.kmax, ws.hm_rank,
         ws.hm_offs, ws.hm_dense, ws.hm_pool, ws.hm_t, ws.hm_xp, H.n, ws.hm_yp);

@@ -37,11 +37,15 @@ Workspace::~Workspace() { release(); }
 
 void Workspace::hm_release() {
     for (void *p : {(void *)hm_dense, (void *)hm_pool, (void *)hm_ctr, (void *)hm_offs, (void *)hm_t,
-                    (void *)hm_xp, (void *)hm_yp, (void *)hm_rank, (void *)hm_status})
+                    (void *)hm_xp, (void *)hm_yp, (void *)hm_rank, (void *)hm_status, (void *)hm_items})
         if (p)
             (void)hipFree(p);
     if (hm_host)
         (void)hipHostFree(hm_host);
+    if (hm_items_host)
+        (void)hipHostFree(hm_items_host);
+    hm_items = hm_items_host = nullptr;
+    hm_n_items = 0;
     if (hm_used_host)
         (void)hipHostFree(hm_used_host);
     hm_host = nullptr;
@@ -84,7 +88,10 @@ void Workspace::hm_alloc(const Problem &p, const HmatPlan &H) {
     hm_t = (double2 *)dalloc(std::max<size_t>(nl, 1) * H.kmax * 16);
     hm_xp = (double2 *)dalloc((size_t)std::max<int64_t>(H.n, 1) * 3 * 16);
     hm_yp = (double2 *)dalloc((size_t)std::max<int64_t>(H.n, 1) * 3 * 16 * kHmatApplyParts);
+    hm_items = (int32_t *)dalloc(std::max<size_t>(nl, 1) * hm_slots(H.kmax) * sizeof(int32_t));
     AFS_HIP(hipHostMalloc((void **)&hm_host, std::max<size_t>(nl, 1) * 2 * sizeof(int), hipHostMallocDefault));
+    AFS_HIP(hipHostMalloc((void **)&hm_items_host, std::max<size_t>(nl, 1) * hm_slots(H.kmax) * sizeof(int32_t),
+                          hipHostMallocDefault));
     AFS_HIP(hipHostMalloc((void **)&hm_used_host, sizeof(unsigned long long), hipHostMallocDefault));
     hm_cap[0] = nd;
     hm_cap[1] = want;
@@ -800,7 +807,7 @@ static int krylov_phase(Problem &p, Workspace &ws, const afsbem_solve_opts &o, i
     if (ws.hm_enabled && fmt == kFmtBlocks) {
         // the frequency's assembly has completed (st waited for it, then
         // synchronised); a build that ran out of pool is repeated with more
-        for (int tries = 0; !hmat_finish(p, ws) && ws.hm_exhausted && tries < 3; ++tries) {
+        for (int tries = 0; !hmat_finish(p, ws, st) && ws.hm_exhausted && tries < 3; ++tries) {
             hmat_setup(p, ws, kernel_params(p.mat, s_re, s_im), ws.hm_eps, st);
             AFS_HIP(hipStreamSynchronize(st));
         }

@@ -61,6 +61,9 @@ struct Workspace {
     double2 *hm_yp = nullptr;              // partial sums of the product, [parts][3 n] in tree order
     int *hm_rank = nullptr, *hm_status = nullptr;
     int *hm_host = nullptr;                // pinned: ranks, then status flags
+    int32_t *hm_items = nullptr;           // V^T x work items: block << 6 | first slot << 2 | (slots - 1)
+    int32_t *hm_items_host = nullptr;      // pinned staging of hm_items
+    int64_t hm_n_items = 0;
     unsigned long long *hm_used_host = nullptr;  // pinned: pool entries the build asked for
     bool hm_exhausted = false;             // the last build ran out of pool
     size_t hm_want = 0;                    // pool entries the next allocation asks for at least
