@@ -17,7 +17,8 @@
 // or column costs one element-pair block per source or target element.
 //
 // Product: x gathered into tree order, t_l = V_l^T x per low-rank block
-// (32 lanes per term), then kHmatApplyParts single-wave work-groups per
+// (persistent single waves over runs of a block's slots, a lane per column
+// pair of the slot's eight terms), then kHmatApplyParts single-wave work-groups per
 // leaf row range each sum every kHmatApplyParts-th entry of the leaf's list of
 // dense blocks (column-major FP32, read coalesced) and covering low-rank blocks
 // (the leaf's rows of a slot's terms, contiguous), and the partial sums are
