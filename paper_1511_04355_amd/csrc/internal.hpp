@@ -218,11 +218,11 @@ void vec_sub(int64_t N, const double *a, const double *b, double *out, hipStream
 // out = alpha x + beta y (complex scalars passed by value; out may alias)
 void vec_axpby(int64_t N, double ar, double ai, const double *x, double br, double bi, const double *y, double *out,
                hipStream_t st);
-// Multi-dot: out[i] = sum_r conj(V_i[r]) w[r], i < nv (one launch per
-// kMdotMaxVectors vectors); V rows strided by ldv.  partial: mdot_scratch_bytes(N, nv_max) bytes whose
-// first kMdotCounterBytes are zero when allocated (arrival counters, left
-// zero by every call).
+// Multi-dot: out[i] = sum_r conj(V_i[r]) w[r], i < nv (two launches per
+// kMdotMaxVectors vectors); V rows strided by ldv.  partial: mdot_scratch_bytes(N, nv_max) bytes
+// (a reserved head of kMdotCounterBytes, then the per-block partial sums).
 constexpr int kMdotMaxVectors = 512;
+constexpr int kMdotMaxBlocks = 1024;
 constexpr int kMdotCounterBytes = kMdotMaxVectors * 4;
 size_t mdot_scratch_bytes(int64_t N, int nv_max);
 void vec_mdot(int64_t N, int nv, const double *V, int64_t ldv, const double *w, double *partial,

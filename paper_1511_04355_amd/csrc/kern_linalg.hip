@@ -371,21 +371,23 @@ void vec_sub(int64_t N, const double *a, const double *b, double *out, hipStream
     AFS_HIP(hipGetLastError());
 }
 
+// Multi-dot in two launches.  mdot_kernel: block b takes rows
+// [b R, (b + 1) R) and, eight vectors at a time, forms each thread's partial
+// conj(V_i) . w over its rows (w read once per eight vectors, the eight
+// vectors' loads in flight together), reduces the 16 sums (vector, real /
+// imaginary) over each wave by a butterfly that halves the set each lane
+// keeps at every step (17 exchanges), then over the four waves through LDS,
+// and stores partial[i][b].  mdot_final_kernel: one wave per vector adds its
+// B partials in block order.  Every V_i is read once per call.
 int mdot_blocks(int64_t N) {
-    int64_t b = (N + 1023) / 1024;
-    if (b > 256)
-        b = 256;
+    int64_t b = (N + 511) / 512;
+    if (b > kMdotMaxBlocks)
+        b = kMdotMaxBlocks;
     if (b < 1)
         b = 1;
     return (int)b;
 }
 
-// Multi-dot in one launch, grid (B, nv): block (b, i) reduces conj(V_i) . w
-// over its rows (wave shuffles, then the four waves through LDS) and stores
-// its partial; the last block to finish vector i (a per-vector arrival
-// counter) adds the B partials in block order, writes out[i] and re-arms the
-// counter.  The counters live at the head of the partial buffer (zeroed when
-// the buffer is allocated).
 __device__ __forceinline__ double wave_sum64(double v) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1)
@@ -393,38 +395,69 @@ __device__ __forceinline__ double wave_sum64(double v) {
     return v;
 }
 
-__global__ __launch_bounds__(256) void mdot_kernel(int64_t N, const double2 *__restrict__ V, int64_t ldv,
-                                                   const double2 *__restrict__ w, int B,
-                                                   double2 *__restrict__ partial, unsigned *__restrict__ counter,
-                                                   double2 *__restrict__ out) {
-    __shared__ double sr[4], si[4];
-    __shared__ bool last;
-    const int i = blockIdx.y;
+// one butterfly step: lanes whose bit log2(4 H) is clear keep sums 0 .. H-1
+// of their set, the others sums H .. 2H-1, each added to its partner's copy
+template <int H>
+__device__ __forceinline__ void md_halve(double (&s)[16], int lane) {
+    const bool hi = (lane & (4 * H)) != 0;
+#pragma unroll
+    for (int k = 0; k < H; ++k) {
+        const double send = hi ? s[k] : s[k + H];
+        const double keep = hi ? s[k + H] : s[k];
+        s[k] = keep + __shfl_xor(send, 4 * H, 64);
+    }
+}
+
+__global__ __launch_bounds__(256) void mdot_kernel(int64_t N, int nv, const double2 *__restrict__ V, int64_t ldv,
+                                                   const double2 *__restrict__ w, int64_t R,
+                                                   double2 *__restrict__ partial) {
+    __shared__ double red[4][16];
+    const int b = blockIdx.x, B = gridDim.x;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const double2 *v = V + (int64_t)i * ldv;
-    double ar = 0, ai = 0;
-    for (int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x; r < N; r += (int64_t)B * 256) {
-        const double2 a = v[r], b = w[r];
-        ar += a.x * b.x + a.y * b.y;  // conj(a) * b
-        ai += a.x * b.y - a.y * b.x;
+    const int64_t r0 = (int64_t)b * R, r1 = (r0 + R < N) ? r0 + R : N;
+    for (int g = 0; g < nv; g += 8) {
+        const int ng = (nv - g < 8) ? nv - g : 8;
+        const double2 *Vg = V + (int64_t)g * ldv;
+        double s[16];
+#pragma unroll
+        for (int k = 0; k < 16; ++k)
+            s[k] = 0.0;
+        for (int64_t r = r0 + threadIdx.x; r < r1; r += 256) {
+            // vectors past the group's last read the last one again (in
+            // bounds) and are not stored
+            double2 a[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e)
+                a[e] = Vg[(int64_t)(e < ng ? e : ng - 1) * ldv + r];
+            const double2 x = w[r];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                s[2 * e] += a[e].x * x.x + a[e].y * x.y;  // conj(a) * x
+                s[2 * e + 1] += a[e].x * x.y - a[e].y * x.x;
+            }
+        }
+        md_halve<8>(s, lane);
+        md_halve<4>(s, lane);
+        md_halve<2>(s, lane);
+        md_halve<1>(s, lane);
+        s[0] += __shfl_xor(s[0], 2, 64);
+        s[0] += __shfl_xor(s[0], 1, 64);
+        if ((lane & 3) == 0)
+            red[wv][lane >> 2] = s[0];
+        __syncthreads();
+        if (threadIdx.x < 16) {
+            const int k = threadIdx.x, e = k >> 1;
+            if (e < ng)
+                reinterpret_cast<double *>(partial)[2 * ((int64_t)(g + e) * B + b) + (k & 1)] =
+                    (red[0][k] + red[1][k]) + (red[2][k] + red[3][k]);
+        }
+        __syncthreads();
     }
-    ar = wave_sum64(ar);
-    ai = wave_sum64(ai);
-    if (lane == 0) {
-        sr[wv] = ar;
-        si[wv] = ai;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        partial[(int64_t)i * B + blockIdx.x] = make_double2((sr[0] + sr[1]) + (sr[2] + sr[3]),
-                                                            (si[0] + si[1]) + (si[2] + si[3]));
-        __threadfence();
-        last = atomicAdd(&counter[i], 1u) == (unsigned)(B - 1);
-    }
-    __syncthreads();
-    if (!last || wv != 0)
-        return;
-    __threadfence();
+}
+
+__global__ __launch_bounds__(64) void mdot_final_kernel(int B, const double2 *__restrict__ partial,
+                                                        double2 *__restrict__ out) {
+    const int i = blockIdx.x, lane = threadIdx.x;
     double br = 0, bi = 0;
     for (int b = lane; b < B; b += 64) {
         const double2 q = partial[(int64_t)i * B + b];
@@ -433,10 +466,8 @@ __global__ __launch_bounds__(256) void mdot_kernel(int64_t N, const double2 *__r
     }
     br = wave_sum64(br);
     bi = wave_sum64(bi);
-    if (lane == 0) {
+    if (lane == 0)
         out[i] = make_double2(br, bi);
-        counter[i] = 0u;
-    }
 }
 
 size_t mdot_scratch_bytes(int64_t N, int nv_max) {
@@ -444,18 +475,18 @@ size_t mdot_scratch_bytes(int64_t N, int nv_max) {
 }
 
 // more than kMdotMaxVectors vectors: consecutive launches over groups of them
-// (stream-ordered, so the groups reuse the same partials and counters)
+// (stream-ordered, so the groups reuse the same partials)
 void vec_mdot(int64_t N, int nv, const double *V, int64_t ldv, const double *w, double *partial, double *out,
               hipStream_t st) {
     const int B = mdot_blocks(N);
+    const int64_t R = (N + B - 1) / B;
     AFS_REQUIRE(nv >= 1, AFSBEM_EINVAL, "multi-dot: no vectors");
-    unsigned *counter = reinterpret_cast<unsigned *>(partial);
     double2 *part = reinterpret_cast<double2 *>(reinterpret_cast<char *>(partial) + kMdotCounterBytes);
     for (int c0 = 0; c0 < nv; c0 += kMdotMaxVectors) {
         const int nc = std::min(kMdotMaxVectors, nv - c0);
-        mdot_kernel<<<dim3(B, nc), 256, 0, st>>>(N, reinterpret_cast<const double2 *>(V) + (int64_t)c0 * ldv, ldv,
-                                                 reinterpret_cast<const double2 *>(w), B, part, counter,
-                                                 reinterpret_cast<double2 *>(out) + c0);
+        mdot_kernel<<<(unsigned)B, 256, 0, st>>>(N, nc, reinterpret_cast<const double2 *>(V) + (int64_t)c0 * ldv, ldv,
+                                                 reinterpret_cast<const double2 *>(w), R, part);
+        mdot_final_kernel<<<(unsigned)nc, 64, 0, st>>>(B, part, reinterpret_cast<double2 *>(out) + c0);
         AFS_HIP(hipGetLastError());
     }
 }

@@ -187,7 +187,6 @@ void Workspace::ensure(const Problem &p, int format, int restart_m, int prec) {
     xstart = (double *)dalloc((size_t)N * 16);
     aug = (double *)dalloc((size_t)N * 16);
     dots_partial = (double *)dalloc(mdot_scratch_bytes(N, restart_m + 2));
-    AFS_HIP(hipMemset(dots_partial, 0, kMdotCounterBytes));  // arrival counters
     small = (double *)dalloc((size_t)(4 * (restart_m + 2)) * 16);
     AFS_HIP(hipHostMalloc((void **)&host_small, (size_t)(4 * (restart_m + 2)) * 16, hipHostMallocDefault));
     one = (double *)dalloc(16);
